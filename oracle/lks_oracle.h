@@ -1,0 +1,113 @@
+/*
+ * lks_oracle.h -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, double-precision CPU reference of the Lattice Kinetic Scheme
+ * (LKS) time march with a rigidly moving Brinkman body, the objective J1, and
+ * the exact discrete adjoint of that march (shape and motion sensitivities).
+ * It exists to check the GPU library; only the test suite, the smoke check and
+ * the benchmark's CPU-baseline leg may load it.  It shares no source with the
+ * GPU library.
+ *
+ * Paper: Tanabe, Yaji, Ushijima, "4D topology optimization of moving rigid
+ * bodies in fluid flows".  Sections cited: 2.2 (LKS), 2.3 (grid separation),
+ * 2.4 (motion representation), 2.5 (sensitivities), 2.6 (objective J1).
+ *
+ * Conventions (lattice units, dx = dt = 1):
+ *   - analysis fields are stored as planes [d+1][N]: plane 0 is the pressure p
+ *     itself, planes 1..d the velocity components; x is fastest, then y, z.
+ *   - motion table per time step n = 1..nt (row n-1): xg[3], ug[3], theta, omega.
+ *   - design grid (incl. margin) is [Dz][Dy][Dx], Dx = m[0] + 2*margin, ...;
+ *     gamma covers only the inner m[0] x m[1] x m[2] block, margin gamma = 0.
+ * All functions return 0 on success and a negative value on bad arguments.
+ */
+#ifndef LKS_ORACLE_H
+#define LKS_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_problem {
+  int32_t d;               /* 2 -> D2Q9, 3 -> D3Q15 */
+  int32_t n[3];            /* analysis nodes per axis (n[2] = 1 when d = 2) */
+  int32_t bc[3];           /* per axis: 0 periodic, 1 wall nodes at both ends */
+  double u_wall[3][2][3];  /* wall velocity [axis][lo, hi][component] */
+  double dp_seam[3];       /* pressure drop across a periodic axis (test mode) */
+  double nu;               /* lattice kinematic viscosity */
+  double kappa_max, q;     /* Brinkman interpolation parameters (lattice units) */
+  int32_t m[3];            /* design points per axis, margin excluded */
+  int32_t margin;          /* margin width in design points */
+  double xg_min[3], xg_max[3]; /* admissible centre range per axis */
+  double th_min, th_max;   /* admissible rotation range (about z) */
+  int32_t nt, r_t, r_w;    /* time steps, temporal filter radii (steps) */
+  int32_t tgt_lo[3], tgt_hi[3]; /* objective target box [lo, hi) */
+  double ndir[3];          /* flow direction n */
+  double phi;              /* J1 = E - phi * V */
+} orc_problem;
+
+/* Motion prelude (Sec. 2.4): chi [nt][3], psi [nt] -> motion [nt][8]. */
+int orc_motion(const orc_problem* p, const double* chi, const double* psi, double* motion);
+
+/* Brinkman coefficient on the design grid incl. margin (Eq. kappa_ref). */
+int orc_kappa_ref(const orc_problem* p, const double* gamma, double* kappa_ref);
+
+/* Design -> analysis transfer for one time step (Eqs. kappa, u_s, rigid motion):
+ * kappa [N], us [d][N].  Wall nodes receive 0. */
+int orc_map(const orc_problem* p, const double* kappa_ref, const double* motion8,
+            double* kappa, double* us);
+
+/* Transpose of orc_map at one step: given dJ/dkappa [N] and dJ/dus [d][N],
+ * ADD dJ/dkappa_ref into kref_bar [Mtot] and WRITE the step's motion partials
+ * motion_bar8 = (xg_bar[3], ug_bar[3], theta_bar, omega_bar). */
+int orc_map_adjoint(const orc_problem* p, const double* kappa_ref, const double* motion8,
+                    const double* kbar, const double* usbar, double* kref_bar,
+                    double* motion_bar8);
+
+/* One LKS step (Sec. 2.2) from state_in to state_out with given body fields. */
+int orc_step(const orc_problem* p, const double* state_in, const double* kappa,
+             const double* us, double* state_out);
+
+/* Transpose of orc_step.  lam = dJ/d(state_out) (total), state_in/state_out as
+ * in orc_step.  Writes lam_prev = dJ/d(state_in) through this step,
+ * kbar = dJ/dkappa, usbar = dJ/dus. */
+int orc_step_adjoint(const orc_problem* p, const double* state_in, const double* state_out,
+                     const double* kappa, const double* us, const double* lam,
+                     double* lam_prev, double* kbar, double* usbar);
+
+/* Full forward march.  state0 nullable (p = 1/3, u = 0); state_final, traj
+ * nullable; traj receives [(nt+1)][d+1][N].  J_out = (J, E, V). */
+int orc_forward(const orc_problem* p, const double* gamma, const double* chi,
+                const double* psi, const double* state0, double* state_final,
+                double* J_out, double* traj);
+
+/* Full discrete adjoint.  dJ = seed scalar; adj_terminal nullable ([d+1][N],
+ * added to dJ/d(state at nt)); adj_initial nullable (receives dJ/d(state0)).
+ * kref_bar [Mtot] and motion_bar [nt][8] nullable (raw accumulators). */
+int orc_adjoint(const orc_problem* p, const double* gamma, const double* chi,
+                const double* psi, const double* state0, double dJ,
+                const double* adj_terminal, double* adj_initial, double* dJ_dgamma,
+                double* dJ_dchi, double* dJ_dpsi, double* kref_bar, double* motion_bar);
+
+/* Sensitivity epilogue alone: raw accumulators -> dJ/dgamma, dJ/dchi, dJ/dpsi. */
+int orc_sensitivities(const orc_problem* p, const double* gamma, const double* kref_bar,
+                      const double* motion_bar, const double* motion, double* dJ_dgamma,
+                      double* dJ_dchi, double* dJ_dpsi);
+
+/* Complex-step variants (re, im pairs) used to pin the adjoint.  Null imaginary
+ * parts mean zero. */
+int orc_forward_cs(const orc_problem* p, const double* gamma_re, const double* gamma_im,
+                   const double* chi_re, const double* chi_im, const double* psi_re,
+                   const double* psi_im, const double* state0_re, const double* state0_im,
+                   double* J_re, double* J_im);
+int orc_step_cs(const orc_problem* p, const double* s_re, const double* s_im,
+                const double* k_re, const double* k_im, const double* us_re,
+                const double* us_im, double* out_re, double* out_im);
+int orc_map_cs(const orc_problem* p, const double* kref_re, const double* kref_im,
+               const double* mot_re, const double* mot_im, double* k_re, double* k_im,
+               double* us_re, double* us_im);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
