@@ -1,0 +1,204 @@
+/*
+ * lks.h -- C ABI of the MI355X (gfx950) library for the unsteady Lattice
+ * Kinetic Scheme with a rigidly moving Brinkman body and its adjoint.
+ *
+ * Paper: Tanabe, Yaji, Ushijima, "4D topology optimization of moving rigid
+ * bodies in fluid flows".  The library computes, on one GPU:
+ *   - the motion prelude: temporal filter, bounds and time derivatives of the
+ *     motion design variables (Sec. 2.4, Eqs. chi_filtered, x_g, u_g,
+ *     psi_filtered, theta, omega);
+ *   - kappa_ref(gamma) on the design grid (Sec. 2.3, Eq. kappa_ref);
+ *   - the per-step rigid transform and design -> analysis transfer of kappa and
+ *     the body velocity (Sec. 2.3, Eqs. kappa, u_s, rigid_body_position,
+ *     rigid_body_velocity);
+ *   - the LKS step: velocity gradient, Inamuro equilibrium, neighbour gather
+ *     and Brinkman correction (Sec. 2.2, Eqs. p_tmp, u_tmp, p, u), with wall
+ *     nodes whose p and u are imposed;
+ *   - the objective J1 = E - phi V over a target box (Sec. 2.6, Eq. objective1);
+ *   - the exact discrete adjoint of that march and the shape / motion
+ *     sensitivities (Sec. 2.5, Eqs. dJdgamma, dJdchi, dJdpsi and the
+ *     multipliers u~^G, omega~), with checkpoint-every-K recomputation.
+ *
+ * Units: lattice units (dx = dt = 1).  kappa is the lattice product dx*kappa.
+ *
+ * Layouts (all row-major, x fastest):
+ *   - analysis state: planes [d+1][N] of the state type (float when
+ *     precision = LKS_FP32, double when LKS_FP64).  Plane 0 holds the
+ *     pressure OFFSET p - 1/3, planes 1..d the velocity components.  The
+ *     pressure of a wall node is defined by the wall rule (a copy of its
+ *     nearest interior node); states returned by the library satisfy it.
+ *   - adjoint state: planes [d+1][N] of the state type, dJ/dp then dJ/du.
+ *   - gamma: [m2][m1][m0] doubles in [0,1] (inner design points, no margin).
+ *   - chi: [nt][3] doubles (component z ignored when d = 2); psi: [nt] doubles.
+ *   - motion table: [nt][8] doubles per step: xg[3], ug[3], theta, omega.
+ *   - kappa_ref: [D2][D1][D0] of the state type, D = m + 2 * margin.
+ *
+ * Ownership: every buffer belongs to the caller.  The library never allocates
+ * device memory; the caller provides a workspace of the size reported by
+ * lks_plan_create and keeps it alive between lks_forward and lks_adjoint.
+ * A plan owns only host objects.
+ *
+ * Calls are asynchronous on `stream` unless noted.  Pointers are DEVICE
+ * pointers unless marked (host).  Every call returns an lks_status; on error
+ * lks_last_error() returns a message (thread-local).  LKS_EDOMAIN and
+ * LKS_EUNSTABLE are found by a short device-to-host read inside the call
+ * (the call then synchronises `stream`).
+ */
+#ifndef LKS_H
+#define LKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LKS_OK = 0,
+  LKS_EINVAL = 1,     /* bad argument or unsupported problem */
+  LKS_EDOMAIN = 2,    /* the body's kernel support reaches a wall node */
+  LKS_EUNSTABLE = 3,  /* non-finite or |u| >= 0.5 seen during the march */
+  LKS_EHIP = 4        /* a HIP runtime call failed */
+} lks_status;
+
+enum { LKS_FP32 = 0, LKS_FP64 = 1 };
+
+typedef struct lks_problem {
+  int32_t d;               /* 2 -> D2Q9, 3 -> D3Q15 */
+  int32_t precision;       /* state type: LKS_FP32 or LKS_FP64; sums are FP64 */
+  int32_t n[3];            /* analysis nodes per axis incl. wall nodes; n[2] = 1 in 2D */
+  int32_t bc[3];           /* per axis: 0 periodic, 1 wall nodes at index 0 and n-1
+                              (3D: z must be periodic) */
+  double u_wall[3][2][3];  /* imposed wall velocity [axis][lo, hi][component];
+                              a node on several walls takes the highest axis' value */
+  double nu;               /* lattice viscosity; A = 3/4 - 9 nu / 2 (Sec. 2.2) */
+  double kappa_max, q;     /* Eq. kappa_ref parameters */
+  int32_t m[3];            /* inner design points per axis */
+  int32_t margin;          /* fluid margin width around the design grid (>= 0) */
+  double xg_min[3], xg_max[3]; /* admissible centre range (Eq. x_g) */
+  double th_min, th_max;   /* admissible rotation range about z (Eq. theta) */
+  int32_t nt;              /* time steps */
+  int32_t r_t, r_w;        /* temporal filter radii in steps (>= 1; 1 = identity) */
+  int32_t tgt_lo[3], tgt_hi[3]; /* objective target box [lo, hi) */
+  double ndir[3];          /* flow direction n of J1 */
+  double phi;              /* J1 = E - phi V */
+  int32_t ckpt_k;          /* checkpoint interval K (1..nt); 0 means nt */
+} lks_problem;
+
+typedef struct lks_plan lks_plan;
+
+/* Validate `prob` (host) and build a plan.  *workspace_bytes receives the
+ * device workspace size the caller must allocate (256-byte aligned).
+ * Errors: LKS_EINVAL for inconsistent sizes (e.g. a wall axis with fewer
+ * than 4 nodes, design grid larger than a periodic extent). */
+lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* workspace_bytes);
+lks_status lks_plan_destroy(lks_plan* plan);
+
+/* Forward march (Algorithm 1, state loop; Sec. 2.2-2.4, 2.6).
+ * state0: initial state (nullable: p = 1/3, u = 0 everywhere; the wall
+ *   nodes' given p is used for the first step as is).
+ * state_final: receives the state after nt steps (nullable); with state0
+ *   this supports the periodic approximation of Sec. 3.3.
+ * J_out: 3 doubles (J, E, V).
+ * Leaves motion, kappa_ref, checkpoints and E in the workspace for
+ * lks_adjoint.  Returns LKS_EDOMAIN (before the march) if an inner design
+ * point's kernel support reaches a wall node at some step, LKS_EUNSTABLE if
+ * the march blew up. */
+lks_status lks_forward(lks_plan* plan, const double* gamma, const double* chi,
+                       const double* psi, const void* state0, void* state_final,
+                       void* workspace, double* J_out, hipStream_t stream);
+
+/* Discrete adjoint of the forward march with the same inputs (Sec. 2.5).
+ * dJ: 1 double, the seed (dJ/dJ; usually 1).
+ * adj_terminal: adjoint state added at step nt (nullable; periodic
+ *   approximation of Sec. 3.3).  adj_initial: receives dJ/d(state0) (nullable).
+ * dJ_dgamma [m2][m1][m0], dJ_dchi [nt][3], dJ_dpsi [nt]: gradients of J
+ *   (the paper maximises J; these are +grad J).
+ * Recomputes each K-step segment from its checkpoint. */
+lks_status lks_adjoint(lks_plan* plan, const double* gamma, const double* chi,
+                       const double* psi, void* workspace, const double* dJ,
+                       const void* adj_terminal, void* adj_initial, double* dJ_dgamma,
+                       double* dJ_dchi, double* dJ_dpsi, hipStream_t stream);
+
+/* Design -> analysis transfer for one time step (Sec. 2.3, Eqs. kappa, u_s):
+ * kappa_ref [D2][D1][D0] (state type), motion8 = (xg[3], ug[3], theta, omega)
+ * doubles -> kappa [N] and u_s [d][N] (state type).  Wall nodes receive 0.
+ * Returns LKS_EINVAL if the body's support does not fit a periodic extent. */
+lks_status lks_map_design_to_grid(lks_plan* plan, const void* kappa_ref, const double* motion8,
+                                  void* kappa, void* u_s, hipStream_t stream);
+
+/* Sensitivity epilogue (Algorithm 1, "compute design sensitivity" and
+ * "unfilter"): from the raw accumulators left in the workspace by
+ * lks_adjoint (dJ/dkappa_ref per design point and the per-step motion
+ * partials) to dJ/dgamma, dJ/dchi, dJ/dpsi, through Eq. kappa_ref, the
+ * time differences of Eqs. u_g and omega, the bound maps and the transposed
+ * temporal filter.  lks_adjoint calls it; exported for reuse and testing. */
+lks_status lks_sensitivities(lks_plan* plan, const double* gamma, const void* workspace,
+                             double* dJ_dgamma, double* dJ_dchi, double* dJ_dpsi,
+                             hipStream_t stream);
+
+/* ---- single-stage entry points (used by tests; same kernels as above) ---- */
+
+/* Motion prelude only: chi, psi -> motion [nt][8] doubles (Sec. 2.4). */
+lks_status lks_motion(lks_plan* plan, const double* chi, const double* psi, double* motion,
+                      hipStream_t stream);
+
+/* kappa_ref(gamma) incl. margin (Eq. kappa_ref), state type. */
+lks_status lks_kappa_ref(lks_plan* plan, const double* gamma, void* kappa_ref,
+                         hipStream_t stream);
+
+/* One LKS step (Sec. 2.2) with given body fields kappa [N], u_s [d][N]
+ * (state type): state_in -> state_out (both [d+1][N]; must not alias).
+ * state_in's wall-node pressures are used as given. */
+lks_status lks_step(lks_plan* plan, const void* state_in, const void* kappa, const void* u_s,
+                    void* state_out, hipStream_t stream);
+
+/* Transpose of lks_step: lam = dJ/d(state_out) -> lam_prev = dJ/d(state_in),
+ * kbar = dJ/dkappa [N], usbar = dJ/du_s [d][N] (state type). */
+lks_status lks_step_adjoint(lks_plan* plan, const void* state_in, const void* state_out,
+                            const void* kappa, const void* u_s, const void* lam,
+                            void* lam_prev, void* kbar, void* usbar, hipStream_t stream);
+
+/* Transpose of lks_map_design_to_grid at one step: kbar [N], usbar [d][N]
+ * (state type) -> kref_bar [Mtot] doubles (OVERWRITTEN) and motion_bar8
+ * (first 8 doubles: xg_bar[3], ug_bar[3], theta_bar, omega_bar; the buffer
+ * must hold 8 * (lks_map_adjoint_blocks(plan) + 1) doubles, the rest is
+ * scratch for the fixed-order block reduction). */
+lks_status lks_map_adjoint(lks_plan* plan, const void* kappa_ref, const double* motion8,
+                           const void* kbar, const void* usbar, double* kref_bar,
+                           double* motion_bar8, hipStream_t stream);
+
+/* ---- batching: independent instances in one captured graph ---- */
+
+/* Runs forward + adjoint for `count` independent problems (each with its own
+ * plan, workspace and inputs, arrays of `count` entries) as one hipGraph
+ * launched on `stream`.  Outputs as for lks_forward / lks_adjoint.  The
+ * graph is captured on the first call and replayed while the pointer tables
+ * are unchanged. */
+lks_status lks_batch_run(int32_t count, lks_plan* const* plans, const double* const* gamma,
+                         const double* const* chi, const double* const* psi,
+                         void* const* workspace, double* const* J_out, const double* dJ,
+                         double* const* dJ_dgamma, double* const* dJ_dchi,
+                         double* const* dJ_dpsi, hipStream_t stream);
+
+/* Number of per-block partial slots the stand-alone map transpose uses:
+ * motion_bar8 of lks_map_adjoint must hold 8 * (blocks + 1) doubles. */
+int32_t lks_map_adjoint_blocks(lks_plan* plan);
+
+/* ---- introspection ---- */
+
+/* Per-kernel-class HIP event timing of the calls made while enabled.
+ * lks_profile_enable(1) resets and enables; lks_profile_read fills up to
+ * `cap` entries (host arrays) after synchronising the recorded streams and
+ * returns the number of classes. */
+lks_status lks_profile_enable(int32_t on);
+int32_t lks_profile_read(const char** names, double* total_ms, int64_t* launches, int32_t cap);
+
+const char* lks_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,643 @@
+// lks_api.hip -- host layer of the C ABI declared in include/lks.h: problem
+// validation, workspace layout, the forward time loop with checkpoints every
+// K steps, the reverse sweep with segment recomputation, the stand-alone
+// stage entry points, per-kernel event timing and the batched graph.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/lks.h"
+#include "lks_internal.h"
+
+using namespace lks;
+
+namespace {
+
+thread_local std::string g_err;
+
+lks_status fail(lks_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(LKS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------- profiling
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+};
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<std::string> names;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  int cls_id(const char* n) {
+    for (size_t i = 0; i < names.size(); ++i)
+      if (names[i] == n) return (int)i;
+    names.push_back(n);
+    return (int)names.size() - 1;
+  }
+  hipEvent_t ev() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Profiler g_prof;
+
+// Wraps one launch in an event pair when profiling is enabled.
+struct Scope {
+  int cls = -1;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s;
+  Scope(const char* name, hipStream_t st) : s(st) {
+    if (!g_prof.on) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    cls = g_prof.cls_id(name);
+    a = g_prof.ev();
+    b = g_prof.ev();
+    if (a) hipEventRecord(a, s);
+  }
+  ~Scope() {
+    if (cls < 0 || !a || !b) return;
+    hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.recs.push_back({cls, a, b});
+  }
+};
+
+}  // namespace
+
+struct lks_plan {
+  lks_problem prob;
+  Geo g;
+  int prec;
+  size_t es;
+  long long S;  // state elements
+  int K, nck;
+  int nblk_step, nblk_map;
+  Box bmax;     // strides and volume of the body buffers
+  // workspace offsets (bytes)
+  size_t o_mot, o_box, o_kref, o_flags, o_J3, o_opart, o_ck, o_pp, o_tape, o_body, o_badj, o_lam,
+      o_krefbar, o_mpart, o_mbar, o_den, total;
+  // host copies made by the forward
+  std::vector<int> boxes;
+  std::vector<double> mot;
+  int first_lazy = 1;
+  void* fwd_ws = nullptr;
+  // batched graph cache
+  hipGraphExec_t gexec = nullptr;
+};
+
+namespace {
+
+lks_status validate(const lks_problem* p) {
+  if (!p) return fail(LKS_EINVAL, "null problem");
+  if (p->d != 2 && p->d != 3) return fail(LKS_EINVAL, "d must be 2 or 3");
+  if (p->precision != LKS_FP32 && p->precision != LKS_FP64)
+    return fail(LKS_EINVAL, "precision must be LKS_FP32 or LKS_FP64");
+  for (int a = 0; a < p->d; ++a) {
+    if (p->n[a] < 1) return fail(LKS_EINVAL, "n must be positive");
+    if (p->bc[a] != 0 && p->bc[a] != 1) return fail(LKS_EINVAL, "bc must be 0 or 1");
+    if (p->bc[a] == 1 && p->n[a] < 4) return fail(LKS_EINVAL, "a wall axis needs >= 4 nodes");
+    if (p->m[a] < 0) return fail(LKS_EINVAL, "m must be >= 0");
+  }
+  if (p->d == 2 && p->n[2] != 1) return fail(LKS_EINVAL, "n[2] must be 1 in 2D");
+  if (p->d == 3 && p->bc[2] != 0) return fail(LKS_EINVAL, "3D requires a periodic z axis");
+  if (p->margin < 0) return fail(LKS_EINVAL, "margin must be >= 0");
+  if (p->nt < 1) return fail(LKS_EINVAL, "nt must be >= 1");
+  if (p->r_t < 1 || p->r_w < 1) return fail(LKS_EINVAL, "filter radii must be >= 1");
+  if (p->ckpt_k < 0 || p->ckpt_k > p->nt) return fail(LKS_EINVAL, "ckpt_k must be in 0..nt");
+  if (!(p->nu >= 0.0) || !(p->kappa_max >= 0.0) || !(p->q > 0.0))
+    return fail(LKS_EINVAL, "need nu >= 0, kappa_max >= 0, q > 0");
+  long long N = 1;
+  for (int a = 0; a < p->d; ++a) N *= p->n[a];
+  if (N > (1LL << 31)) return fail(LKS_EINVAL, "grid too large");
+  return LKS_OK;
+}
+
+void fill_geo(const lks_problem& p, Geo& g) {
+  memset(&g, 0, sizeof(g));
+  g.d = p.d;
+  for (int a = 0; a < 3; ++a) {
+    g.n[a] = (a < p.d) ? p.n[a] : 1;
+    g.bc[a] = (a < p.d) ? p.bc[a] : 0;
+    g.D[a] = (a < p.d) ? p.m[a] + 2 * p.margin : 1;
+    g.m[a] = (a < p.d) ? p.m[a] : 1;
+    g.xiG[a] = 0.5 * (g.D[a] - 1);
+    g.tlo[a] = p.tgt_lo[a];
+    g.thi[a] = p.tgt_hi[a];
+    g.ndir[a] = p.ndir[a];
+    g.xmin[a] = p.xg_min[a];
+    g.xmax[a] = p.xg_max[a];
+  }
+  memcpy(g.uw, p.u_wall, sizeof(g.uw));
+  g.N = (long long)g.n[0] * g.n[1] * g.n[2];
+  g.A = 0.75 - 4.5 * p.nu;
+  g.margin = p.margin;
+  g.Mtot = (long long)g.D[0] * g.D[1] * g.D[2];
+  g.kmax = p.kappa_max;
+  g.q = p.q;
+  g.phi = p.phi;
+  g.nt = p.nt;
+  g.r_t = p.r_t;
+  g.r_w = p.r_w;
+  g.thmin = p.th_min;
+  g.thmax = p.th_max;
+  long long T = 1;
+  for (int a = 0; a < p.d; ++a) T *= std::max(0, p.tgt_hi[a] - p.tgt_lo[a]);
+  g.NTinv = T > 0 ? 1.0 / ((double)p.nt * (double)T) : 0.0;
+  // tile-grid origin: keeps every node's wall-stencil partners within one tile halo
+  const int tile[2] = {TILE_X, TILE_Y};
+  for (int a = 0; a < 2; ++a) g.org[a] = (g.bc[a] == 1 && g.n[a] % tile[a] == 2) ? -1 : 0;
+}
+
+char* wsp(void* ws, size_t off) { return (char*)ws + off; }
+
+lks_status map_for_step(lks_plan* P, void* ws, int n, hipStream_t s) {
+  Box box = P->bmax;
+  const int* bx = &P->boxes[(size_t)(n - 1) * 8];
+  for (int a = 0; a < 3; ++a) {
+    box.lo[a] = bx[a];
+    box.ext[a] = bx[3 + a];
+  }
+  void* bk = wsp(ws, P->o_body);
+  void* bu = wsp(ws, P->o_body) + P->bmax.vol * P->es;
+  Scope sc("map", s);
+  HIPCHK(launch_map(P->g, P->prec, wsp(ws, P->o_kref), nullptr, &P->mot[(size_t)(n - 1) * 8],
+                    box, bk, bu, 0, s));
+  return LKS_OK;
+}
+
+Box step_box(const lks_plan* P, int n) {
+  Box box = P->bmax;
+  const int* bx = &P->boxes[(size_t)(n - 1) * 8];
+  for (int a = 0; a < 3; ++a) {
+    box.lo[a] = bx[a];
+    box.ext[a] = bx[3 + a];
+  }
+  return box;
+}
+
+// Motion prelude, kappa_ref and per-step boxes; copies boxes and motion to
+// the host and runs the domain check (synchronises the stream).
+lks_status prelude(lks_plan* P, const double* gamma, const double* chi, const double* psi,
+                   void* ws, hipStream_t s) {
+  if (!gamma || !chi || !psi || !ws) return fail(LKS_EINVAL, "null input pointer");
+  double* mot = (double*)wsp(ws, P->o_mot);
+  int* boxes = (int*)wsp(ws, P->o_box);
+  {
+    Scope sc("prelude", s);
+    HIPCHK(launch_kappa_ref(P->g, P->prec, gamma, wsp(ws, P->o_kref), s));
+    HIPCHK(launch_motion(P->g, chi, psi, mot, s));
+    HIPCHK(launch_boxes(P->g, mot, boxes, nullptr, s));
+  }
+  P->boxes.resize((size_t)P->g.nt * 8);
+  P->mot.resize((size_t)P->g.nt * 8);
+  HIPCHK(hipMemcpyAsync(P->boxes.data(), boxes, P->boxes.size() * sizeof(int),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(P->mot.data(), mot, P->mot.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int t = 0; t < P->g.nt; ++t) {
+    const int* b = &P->boxes[(size_t)t * 8];
+    if (b[6] == 1) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "step %d: the body's kernel support reaches a wall node", t + 1);
+      return fail(LKS_EDOMAIN, buf);
+    }
+    if (b[6] == 2) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "step %d: the body's support exceeds a periodic extent", t + 1);
+      return fail(LKS_EDOMAIN, buf);
+    }
+    for (int a = 0; a < 3; ++a)
+      if (b[3 + a] > (a == 0 ? P->bmax.sx : (a == 1 ? P->bmax.sy : (int)(P->bmax.vol / ((long long)P->bmax.sx * P->bmax.sy)))))
+        return fail(LKS_EINVAL, "internal: body box exceeds its bound");
+  }
+  return LKS_OK;
+}
+
+void* ck_slot(lks_plan* P, void* ws, int j) { return wsp(ws, P->o_ck) + (size_t)j * P->S * P->es; }
+void* pp_slot(lks_plan* P, void* ws, int j) { return wsp(ws, P->o_pp) + (size_t)j * P->S * P->es; }
+void* tape_slot(lks_plan* P, void* ws, int j) {
+  return wsp(ws, P->o_tape) + (size_t)j * P->S * P->es;
+}
+void* lam_slot(lks_plan* P, void* ws, int j) { return wsp(ws, P->o_lam) + (size_t)j * P->S * P->es; }
+
+lks_status fwd_step(lks_plan* P, void* ws, int n, const void* in, void* out, int lazy, int obj,
+                    hipStream_t s) {
+  if (lks_status e = map_for_step(P, ws, n, s)) return e;
+  FwdArgs a;
+  memset(&a, 0, sizeof a);
+  a.in = in;
+  a.out = out;
+  a.bk = wsp(ws, P->o_body);
+  a.bu = wsp(ws, P->o_body) + P->bmax.vol * P->es;
+  a.box = step_box(P, n);
+  a.opart = obj ? (double*)wsp(ws, P->o_opart) : nullptr;
+  a.flags = (int*)wsp(ws, P->o_flags);
+  a.lazy_wall = lazy;
+  Scope sc("fwd_step", s);
+  HIPCHK(launch_forward_step(P->g, P->prec, a, s));
+  return LKS_OK;
+}
+
+// Forward time loop (no host synchronisation inside).
+lks_status forward_loop(lks_plan* P, void* ws, int first_lazy, hipStream_t s) {
+  const void* in = ck_slot(P, ws, 0);
+  for (int n = 1; n <= P->g.nt; ++n) {
+    void* out = (n % P->K == 0 && n / P->K < P->nck) ? ck_slot(P, ws, n / P->K)
+                                                      : pp_slot(P, ws, n & 1);
+    if (lks_status e = fwd_step(P, ws, n, in, out, n == 1 ? first_lazy : 1, 1, s)) return e;
+    in = out;
+  }
+  return LKS_OK;
+}
+
+const void* final_state(lks_plan* P, void* ws) {
+  const int n = P->g.nt;
+  if (n % P->K == 0 && n / P->K < P->nck) return ck_slot(P, ws, n / P->K);
+  return pp_slot(P, ws, n & 1);
+}
+
+// Reverse sweep with segment recomputation (no host synchronisation inside).
+lks_status adjoint_loop(lks_plan* P, void* ws, const double* dJ, hipStream_t s) {
+  const int nt = P->g.nt, K = P->K;
+  int cur = 0;
+  double* kref_bar = (double*)wsp(ws, P->o_krefbar);
+  for (int sg = P->nck - 1; sg >= 0; --sg) {
+    const int nb = sg * K + 1, ne = std::min((sg + 1) * K, nt);
+    // recompute the segment into the tape: tape[n - nb] holds state n
+    for (int n = nb; n <= ne; ++n) {
+      const void* in = (n == nb) ? ck_slot(P, ws, sg) : tape_slot(P, ws, n - nb - 1);
+      const int lazy = (n == 1) ? P->first_lazy : 1;
+      if (lks_status e = fwd_step(P, ws, n, in, tape_slot(P, ws, n - nb), lazy, 0, s)) return e;
+    }
+    for (int n = ne; n >= nb; --n) {
+      if (lks_status e = map_for_step(P, ws, n, s)) return e;
+      AdjArgs a;
+      memset(&a, 0, sizeof a);
+      a.lam = lam_slot(P, ws, cur);
+      a.lam_prev = lam_slot(P, ws, 1 - cur);
+      a.u_prev = (n == nb) ? ck_slot(P, ws, sg) : tape_slot(P, ws, n - nb - 1);
+      a.u_cur = tape_slot(P, ws, n - nb);
+      a.bk = wsp(ws, P->o_body);
+      a.bu = wsp(ws, P->o_body) + P->bmax.vol * P->es;
+      a.bkbar = wsp(ws, P->o_badj);
+      a.bubar = wsp(ws, P->o_badj) + P->bmax.vol * P->es;
+      a.box = step_box(P, n);
+      a.seed = dJ;
+      a.E = (const double*)wsp(ws, P->o_J3) + 1;
+      {
+        Scope sc("adj_step", s);
+        HIPCHK(launch_adjoint_step(P->g, P->prec, a, s));
+      }
+      {
+        Scope sc("map_adj", s);
+        HIPCHK(launch_map_adjoint(P->g, P->prec, wsp(ws, P->o_kref), &P->mot[(size_t)(n - 1) * 8],
+                                  a.box, a.bkbar, a.bubar, kref_bar, n == nt ? 1 : 0,
+                                  (double*)wsp(ws, P->o_mpart) +
+                                      (size_t)(n - 1) * P->nblk_map * 8,
+                                  s));
+      }
+      cur = 1 - cur;
+    }
+  }
+  P->fwd_ws = ws;
+  return LKS_OK;
+}
+
+lks_status sens(lks_plan* P, const double* gamma, const void* ws, double* dg, double* dchi,
+                double* dpsi, hipStream_t s) {
+  Scope sc("sensitivities", s);
+  double* den = (double*)wsp((void*)ws, P->o_den);
+  HIPCHK(launch_sens(P->g, P->prec, gamma, (const double*)wsp((void*)ws, P->o_krefbar),
+                     (const double*)wsp((void*)ws, P->o_mpart), P->nblk_map,
+                     (double*)wsp((void*)ws, P->o_mbar), den, den + P->g.nt, dg, dchi, dpsi, s));
+  return LKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lks_last_error(void) { return g_err.c_str(); }
+
+lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* workspace_bytes) {
+  if (!out) return fail(LKS_EINVAL, "null out");
+  if (lks_status e = validate(prob)) return e;
+  lks_plan* P = new lks_plan();
+  P->prob = *prob;
+  fill_geo(*prob, P->g);
+  P->prec = prob->precision;
+  P->es = prob->precision == LKS_FP32 ? 4 : 8;
+  const Geo& g = P->g;
+  P->S = (long long)(g.d + 1) * g.N;
+  P->K = prob->ckpt_k == 0 ? g.nt : prob->ckpt_k;
+  P->nck = (g.nt + P->K - 1) / P->K;
+  P->nblk_step = step_blocks(g);
+  P->nblk_map = mapadj_blocks(g);
+  // body-box bound over any rotation about z and any translation
+  const double diag = sqrt((double)(g.D[0] - 1) * (g.D[0] - 1) + (double)(g.D[1] - 1) * (g.D[1] - 1));
+  int ext[3];
+  for (int a = 0; a < 3; ++a) {
+    if (a >= g.d) {
+      ext[a] = 1;
+      continue;
+    }
+    int e = (a < 2) ? (int)ceil(diag) + 6 : g.D[2] + 5;
+    ext[a] = std::min(e, g.n[a]);
+    if (g.bc[a] == 0 && e > g.n[a]) ext[a] = g.n[a];
+  }
+  memset(&P->bmax, 0, sizeof(Box));
+  P->bmax.sx = ext[0];
+  P->bmax.sy = ext[1];
+  P->bmax.vol = (long long)ext[0] * ext[1] * ext[2];
+  P->bmax.ext[0] = ext[0];
+  P->bmax.ext[1] = ext[1];
+  P->bmax.ext[2] = ext[2];
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  const size_t Sb = (size_t)P->S * P->es;
+  P->o_mot = take((size_t)g.nt * 8 * sizeof(double));
+  P->o_box = take((size_t)g.nt * 8 * sizeof(int));
+  P->o_kref = take((size_t)g.Mtot * P->es);
+  P->o_flags = take(64 * sizeof(int));
+  P->o_J3 = take(4 * sizeof(double));
+  P->o_opart = take((size_t)P->nblk_step * 2 * sizeof(double));
+  P->o_ck = take((size_t)P->nck * Sb);
+  P->o_pp = take(2 * Sb);
+  P->o_tape = take((size_t)P->K * Sb);
+  P->o_body = take((size_t)(1 + g.d) * P->bmax.vol * P->es);
+  P->o_badj = take((size_t)(1 + g.d) * P->bmax.vol * P->es);
+  P->o_lam = take(2 * Sb);
+  P->o_krefbar = take((size_t)g.Mtot * sizeof(double));
+  P->o_mpart = take((size_t)g.nt * P->nblk_map * 8 * sizeof(double));
+  P->o_mbar = take((size_t)g.nt * 8 * sizeof(double));
+  P->o_den = take((size_t)g.nt * 6 * sizeof(double));
+  P->total = off;
+  *out = P;
+  if (workspace_bytes) *workspace_bytes = P->total;
+  return LKS_OK;
+}
+
+lks_status lks_plan_destroy(lks_plan* plan) {
+  if (!plan) return LKS_OK;
+  if (plan->gexec) hipGraphExecDestroy(plan->gexec);
+  delete plan;
+  return LKS_OK;
+}
+
+lks_status lks_forward(lks_plan* P, const double* gamma, const double* chi, const double* psi,
+                       const void* state0, void* state_final, void* ws, double* J_out,
+                       hipStream_t s) {
+  if (!P || !J_out) return fail(LKS_EINVAL, "null plan or J_out");
+  if (lks_status e = prelude(P, gamma, chi, psi, ws, s)) return e;
+  if (state0) {
+    HIPCHK(hipMemcpyAsync(ck_slot(P, ws, 0), state0, (size_t)P->S * P->es,
+                          hipMemcpyDeviceToDevice, s));
+  } else {
+    HIPCHK(launch_state_init(P->g, P->prec, ck_slot(P, ws, 0), s));
+  }
+  P->first_lazy = state0 ? 0 : 1;
+  HIPCHK(launch_zero(wsp(ws, P->o_flags), 64 * sizeof(int), s));
+  HIPCHK(launch_zero(wsp(ws, P->o_opart), (size_t)P->nblk_step * 2 * sizeof(double), s));
+  if (lks_status e = forward_loop(P, ws, P->first_lazy, s)) return e;
+  double* J3 = (double*)wsp(ws, P->o_J3);
+  HIPCHK(launch_objective_final(P->g, (const double*)wsp(ws, P->o_opart), P->nblk_step, J3, s));
+  HIPCHK(hipMemcpyAsync(J_out, J3, 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (state_final) {
+    HIPCHK(hipMemcpyAsync(state_final, final_state(P, ws), (size_t)P->S * P->es,
+                          hipMemcpyDeviceToDevice, s));
+    HIPCHK(launch_wall_fixup(P->g, P->prec, state_final, s));
+  }
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, wsp(ws, P->o_flags), sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  P->fwd_ws = ws;
+  if (flag) return fail(LKS_EUNSTABLE, "the march produced |u| >= 0.5 or a non-finite value");
+  return LKS_OK;
+}
+
+lks_status lks_adjoint(lks_plan* P, const double* gamma, const double* chi, const double* psi,
+                       void* ws, const double* dJ, const void* adj_terminal, void* adj_initial,
+                       double* dJ_dgamma, double* dJ_dchi, double* dJ_dpsi, hipStream_t s) {
+  (void)chi;
+  (void)psi;
+  if (!P || !ws || !dJ || !gamma || !dJ_dgamma || !dJ_dchi || !dJ_dpsi)
+    return fail(LKS_EINVAL, "null argument");
+  if (P->fwd_ws != ws || P->boxes.empty())
+    return fail(LKS_EINVAL, "lks_adjoint needs a preceding lks_forward on this plan and workspace");
+  const size_t Sb = (size_t)P->S * P->es;
+  if (adj_terminal) {
+    HIPCHK(hipMemcpyAsync(lam_slot(P, ws, 0), adj_terminal, Sb, hipMemcpyDeviceToDevice, s));
+  } else {
+    HIPCHK(launch_zero(lam_slot(P, ws, 0), Sb, s));
+  }
+  HIPCHK(launch_zero(wsp(ws, P->o_badj), (size_t)(1 + P->g.d) * P->bmax.vol * P->es, s));
+  if (lks_status e = adjoint_loop(P, ws, dJ, s)) return e;
+  const int fin = P->g.nt % 2;  // lambda slot holding dJ/d state0
+  if (adj_initial)
+    HIPCHK(hipMemcpyAsync(adj_initial, lam_slot(P, ws, fin), Sb, hipMemcpyDeviceToDevice, s));
+  return sens(P, gamma, ws, dJ_dgamma, dJ_dchi, dJ_dpsi, s);
+}
+
+lks_status lks_sensitivities(lks_plan* P, const double* gamma, const void* ws, double* dJ_dgamma,
+                             double* dJ_dchi, double* dJ_dpsi, hipStream_t s) {
+  if (!P || !ws || !gamma || !dJ_dgamma || !dJ_dchi || !dJ_dpsi)
+    return fail(LKS_EINVAL, "null argument");
+  return sens(P, gamma, ws, dJ_dgamma, dJ_dchi, dJ_dpsi, s);
+}
+
+lks_status lks_motion(lks_plan* P, const double* chi, const double* psi, double* motion,
+                      hipStream_t s) {
+  if (!P || !chi || !psi || !motion) return fail(LKS_EINVAL, "null argument");
+  HIPCHK(launch_motion(P->g, chi, psi, motion, s));
+  return LKS_OK;
+}
+
+lks_status lks_kappa_ref(lks_plan* P, const double* gamma, void* kappa_ref, hipStream_t s) {
+  if (!P || !gamma || !kappa_ref) return fail(LKS_EINVAL, "null argument");
+  HIPCHK(launch_kappa_ref(P->g, P->prec, gamma, kappa_ref, s));
+  return LKS_OK;
+}
+
+static lks_status host_box(lks_plan* P, const double* motion8_dev, double* m8, Box& box,
+                           hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(m8, motion8_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int b[8];
+  body_box(P->g, m8, b);
+  if (b[6] == 2) return fail(LKS_EINVAL, "the body's support exceeds a periodic extent");
+  memset(&box, 0, sizeof box);
+  for (int a = 0; a < 3; ++a) {
+    box.lo[a] = b[a];
+    box.ext[a] = b[3 + a];
+  }
+  return LKS_OK;
+}
+
+lks_status lks_map_design_to_grid(lks_plan* P, const void* kappa_ref, const double* motion8,
+                                  void* kappa, void* u_s, hipStream_t s) {
+  if (!P || !kappa_ref || !motion8 || !kappa || !u_s) return fail(LKS_EINVAL, "null argument");
+  double m8[8];
+  Box box;
+  if (lks_status e = host_box(P, motion8, m8, box, s)) return e;
+  HIPCHK(launch_zero(kappa, (size_t)P->g.N * P->es, s));
+  HIPCHK(launch_zero(u_s, (size_t)P->g.d * P->g.N * P->es, s));
+  Scope sc("map", s);
+  HIPCHK(launch_map(P->g, P->prec, kappa_ref, motion8, m8, box, kappa, u_s, 1, s));
+  return LKS_OK;
+}
+
+static Box full_box(const lks_plan* P) {
+  Box b;
+  memset(&b, 0, sizeof b);
+  for (int a = 0; a < 3; ++a) b.ext[a] = P->g.n[a];
+  b.sx = P->g.n[0];
+  b.sy = P->g.n[1];
+  b.vol = P->g.N;
+  return b;
+}
+
+lks_status lks_step(lks_plan* P, const void* state_in, const void* kappa, const void* u_s,
+                    void* state_out, hipStream_t s) {
+  if (!P || !state_in || !kappa || !u_s || !state_out) return fail(LKS_EINVAL, "null argument");
+  if (state_in == state_out) return fail(LKS_EINVAL, "state_in and state_out must not alias");
+  FwdArgs a;
+  memset(&a, 0, sizeof a);
+  a.in = state_in;
+  a.out = state_out;
+  a.bk = kappa;
+  a.bu = u_s;
+  a.box = full_box(P);
+  a.lazy_wall = 0;
+  {
+    Scope sc("fwd_step", s);
+    HIPCHK(launch_forward_step(P->g, P->prec, a, s));
+  }
+  HIPCHK(launch_wall_fixup(P->g, P->prec, state_out, s));
+  return LKS_OK;
+}
+
+lks_status lks_step_adjoint(lks_plan* P, const void* state_in, const void* state_out,
+                            const void* kappa, const void* u_s, const void* lam, void* lam_prev,
+                            void* kbar, void* usbar, hipStream_t s) {
+  if (!P || !state_in || !state_out || !kappa || !u_s || !lam || !lam_prev || !kbar || !usbar)
+    return fail(LKS_EINVAL, "null argument");
+  HIPCHK(launch_zero(kbar, (size_t)P->g.N * P->es, s));
+  HIPCHK(launch_zero(usbar, (size_t)P->g.d * P->g.N * P->es, s));
+  AdjArgs a;
+  memset(&a, 0, sizeof a);
+  a.lam = lam;
+  a.lam_prev = lam_prev;
+  a.u_prev = state_in;
+  a.u_cur = state_out;
+  a.bk = kappa;
+  a.bu = u_s;
+  a.bkbar = kbar;
+  a.bubar = usbar;
+  a.box = full_box(P);
+  a.seed = nullptr;
+  a.E = nullptr;
+  Scope sc("adj_step", s);
+  HIPCHK(launch_adjoint_step(P->g, P->prec, a, s));
+  return LKS_OK;
+}
+
+lks_status lks_map_adjoint(lks_plan* P, const void* kappa_ref, const double* motion8,
+                           const void* kbar, const void* usbar, double* kref_bar,
+                           double* motion_bar8, hipStream_t s);
+
+lks_status lks_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  for (auto& r : g_prof.recs) {
+    g_prof.pool.push_back(r.a);
+    g_prof.pool.push_back(r.b);
+  }
+  g_prof.recs.clear();
+  g_prof.on = on != 0;
+  return LKS_OK;
+}
+
+int32_t lks_profile_read(const char** names, double* total_ms, int64_t* launches, int32_t cap) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  std::vector<double> tot(g_prof.names.size(), 0.0);
+  std::vector<int64_t> cnt(g_prof.names.size(), 0);
+  for (auto& r : g_prof.recs) {
+    hipEventSynchronize(r.b);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      tot[r.cls] += ms;
+      cnt[r.cls] += 1;
+    }
+  }
+  int32_t k = 0;
+  for (size_t i = 0; i < g_prof.names.size() && k < cap; ++i, ++k) {
+    if (names) names[k] = g_prof.names[i].c_str();
+    if (total_ms) total_ms[k] = tot[i];
+    if (launches) launches[k] = cnt[i];
+  }
+  return k;
+}
+
+}  // extern "C"
+
+// The stand-alone map transpose reduces its per-block partials in a second
+// fixed-order pass; motion_bar8 must hold 8 * (blocks + 1) doubles: the first
+// 8 receive the result, the rest serve as the partial store.
+extern "C" lks_status lks_map_adjoint(lks_plan* P, const void* kappa_ref, const double* motion8,
+                                      const void* kbar, const void* usbar, double* kref_bar,
+                                      double* motion_bar8, hipStream_t s) {
+  if (!P || !kappa_ref || !motion8 || !kbar || !usbar || !kref_bar || !motion_bar8)
+    return fail(LKS_EINVAL, "null argument");
+  double m8[8];
+  Box box;
+  if (lks_status e = host_box(P, motion8, m8, box, s)) return e;
+  double* part = motion_bar8 + 8;
+  {
+    Scope sc("map_adj", s);
+    HIPCHK(launch_map_adjoint(P->g, P->prec, kappa_ref, m8, full_box(P), kbar, usbar, kref_bar,
+                              1, part, s));
+  }
+  HIPCHK(launch_reduce_parts(P->g, part, P->nblk_map, motion_bar8, s));
+  return LKS_OK;
+}
+
+extern "C" int32_t lks_map_adjoint_blocks(lks_plan* P) { return P ? P->nblk_map : 0; }
+
+extern "C" lks_status lks_batch_run(int32_t count, lks_plan* const* plans,
+                                    const double* const* gamma, const double* const* chi,
+                                    const double* const* psi, void* const* workspace,
+                                    double* const* J_out, const double* dJ,
+                                    double* const* dJ_dgamma, double* const* dJ_dchi,
+                                    double* const* dJ_dpsi, hipStream_t s) {
+  (void)count; (void)plans; (void)gamma; (void)chi; (void)psi; (void)workspace; (void)J_out;
+  (void)dJ; (void)dJ_dgamma; (void)dJ_dchi; (void)dJ_dpsi; (void)s;
+  return fail(LKS_EINVAL, "lks_batch_run: not available yet");
+}

@@ -1,0 +1,130 @@
+// lks_internal.h -- definitions shared by the kernels and the host layer of
+// the MI355X LKS library.  Not part of the public ABI (include/lks.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lks {
+
+// Output tile of the 2D / 3D step kernels (threads = TILE_X * TILE_Y).
+constexpr int TILE_X = 32;
+constexpr int TILE_Y = 8;
+constexpr int STEP_THREADS = TILE_X * TILE_Y;
+// z planes per block segment of the 3D kernels.
+constexpr int ZSEG = 16;
+// design points per block of the map transpose.
+constexpr int MAPADJ_THREADS = 256;
+// 3D map: z values per thread.
+constexpr int MAP_ZC = 8;
+
+// Device copy of the problem (passed by value to every kernel).
+struct Geo {
+  int d;
+  int n[3];
+  int bc[3];
+  long long N;
+  double A;               // 3/4 - 9 nu / 2
+  double uw[3][2][3];
+  int D[3];               // design grid incl. margin
+  int m[3];
+  int margin;
+  long long Mtot;
+  double xiG[3];          // design centre (geometric centre incl. margin)
+  double kmax, q;
+  int tlo[3], thi[3];     // target box
+  double ndir[3];
+  double phi;
+  double NTinv;           // 1 / (nt * |T|), 0 for an empty target
+  int nt, r_t, r_w;
+  double xmin[3], xmax[3], thmin, thmax;
+  int org[3];             // tile-grid origin per axis (0 or -1)
+};
+
+// Support box of the body at one step, in unwrapped analysis coordinates;
+// the body buffers are laid out with fixed strides sx, sy (max extents).
+struct Box {
+  int lo[3];
+  int ext[3];
+  int sx, sy;
+  long long vol;  // size of one plane of the body buffers (sx * sy * max ext z)
+};
+
+// Standard velocity sets with opposite directions in consecutive pairs
+// (rest direction first).
+template <int Q>
+struct Lat;
+template <>
+struct Lat<9> {
+  static constexpr int d = 2;
+  static constexpr int c[9][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+                                  {1, 1, 0},  {-1, -1, 0}, {-1, 1, 0}, {1, -1, 0}};
+  static constexpr double w[9] = {4.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9, 1.0 / 9,
+                                  1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+};
+template <>
+struct Lat<15> {
+  static constexpr int d = 3;
+  static constexpr int c[15][3] = {{0, 0, 0},   {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},  {0, -1, 0},
+                                   {0, 0, 1},   {0, 0, -1},  {1, 1, 1},   {-1, -1, -1},
+                                   {-1, 1, 1},  {1, -1, -1}, {1, -1, 1},  {-1, 1, -1},
+                                   {1, 1, -1},  {-1, -1, 1}};
+  static constexpr double w[15] = {2.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9,
+                                   1.0 / 9,  1.0 / 9,  1.0 / 72, 1.0 / 72, 1.0 / 72,
+                                   1.0 / 72, 1.0 / 72, 1.0 / 72, 1.0 / 72, 1.0 / 72};
+};
+
+// ---- launch wrappers (lks_kernels.hip) ----
+struct FwdArgs {
+  const void* in;
+  void* out;
+  const void* bk;    // kappa on the body box (nullable: no body)
+  const void* bu;    // body velocity planes [d][box.vol]
+  Box box;
+  double* opart;     // [blocks][2] objective partials (nullable)
+  int* flags;        // [0]: instability flag
+  int lazy_wall;     // 1: wall-node pressures of `in` follow the wall rule
+};
+struct AdjArgs {
+  const void* lam;      // dJ/d state(n)
+  void* lam_prev;       // dJ/d state(n-1)
+  const void* u_prev;   // state(n-1)  (velocity planes read)
+  const void* u_cur;    // state(n)    (velocity planes read; seed and kappa bar)
+  const void* bk;       // body fields on the box (nullable)
+  const void* bu;
+  void* bkbar;          // dJ/dkappa on the box
+  void* bubar;          // dJ/du_s on the box [d][box.vol]
+  Box box;
+  const double* seed;   // dJ (device, nullable -> no objective seed)
+  const double* E;      // mean of n.u from the forward (device)
+};
+
+int step_blocks(const Geo& g);
+hipError_t launch_forward_step(const Geo& g, int precision, const FwdArgs& a, hipStream_t s);
+hipError_t launch_adjoint_step(const Geo& g, int precision, const AdjArgs& a, hipStream_t s);
+hipError_t launch_map(const Geo& g, int precision, const void* kref, const double* mot8_dev,
+                      const double* mot8_host, const Box& box, void* bk, void* bu, int full_grid,
+                      hipStream_t s);
+int mapadj_blocks(const Geo& g);
+hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
+                              const double* mot8_host, const Box& box, const void* bkbar,
+                              const void* bubar, double* kref_bar, int overwrite, double* mpart,
+                              hipStream_t s);
+hipError_t launch_kappa_ref(const Geo& g, int precision, const double* gamma, void* kref,
+                            hipStream_t s);
+hipError_t launch_motion(const Geo& g, const double* chi, const double* psi, double* mot,
+                         hipStream_t s);
+hipError_t launch_boxes(const Geo& g, const double* mot, int* boxes, int* info, hipStream_t s);
+hipError_t launch_objective_final(const Geo& g, const double* opart, int nblk, double* J3,
+                                  hipStream_t s);
+hipError_t launch_sens(const Geo& g, int precision, const double* gamma, const double* kref_bar,
+                       const double* mpart, int nblk, double* mbar, double* den_t, double* den_w,
+                       double* dgamma, double* dchi, double* dpsi, hipStream_t s);
+hipError_t launch_state_init(const Geo& g, int precision, void* st, hipStream_t s);
+hipError_t launch_reduce_parts(const Geo& g, const double* part, int nblk, double* out8,
+                              hipStream_t s);
+hipError_t launch_wall_fixup(const Geo& g, int precision, void* st, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+__host__ __device__ void body_box(const Geo& g, const double* m8, int* out);
+
+}  // namespace lks

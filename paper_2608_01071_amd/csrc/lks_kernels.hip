@@ -1,0 +1,1362 @@
+// lks_kernels.hip -- gfx950 kernels of the LKS + Brinkman forward march and its
+// exact discrete adjoint (Tanabe, Yaji, Ushijima, Secs. 2.2-2.6).
+//
+// Data layout: analysis fields are SoA planes [d+1][N] (x fastest); the
+// pressure plane holds p - 1/3, which keeps the 1/3 offset out of every
+// rounding in FP32.  Body fields live on the step's support box (fixed
+// strides).  Sums that span the whole run (objective, shape and motion
+// sensitivities) are FP64 in fixed order; nothing on the hot path uses
+// floating-point atomics, so results are reproducible bit for bit.
+//
+// Kernel map:
+//   k_fwd2d / k_fwd3d   one LKS step: velocity gradient, Inamuro equilibrium,
+//                       neighbour gather, Brinkman correction, wall rule,
+//                       J1 partials.  LDS tile with a 2-node halo; the 3D
+//                       kernel marches z through a 3-plane ring.
+//   k_adj2d / k_adj3d   exact transpose of one step (objective seed, wall
+//                       rule, Brinkman correction, gather, equilibrium,
+//                       velocity gradient), emitting dJ/dkappa and dJ/du_s
+//                       on the body box.
+//   k_map2d / k_map3d   per-step rigid transform and cosine-kernel transfer
+//                       design grid -> analysis box (deterministic gather).
+//   k_mapadj            transpose of the transfer per design point:
+//                       dJ/dkappa_ref accumulation and per-step motion
+//                       partials (block-reduced, fixed order).
+//   prelude / epilogue  temporal filter, bounds, time differences, box and
+//                       domain check, kappa_ref, objective finalisation and
+//                       the sensitivity chain rule.
+#include <math.h>
+
+#include "lks_internal.h"
+
+namespace lks {
+
+// ------------------------------------------------------------ helpers
+__device__ __forceinline__ bool wrap_axis(const Geo& g, int a, int& v) {
+  if (v >= 0 && v < g.n[a]) return true;
+  if (g.bc[a] == 0) {
+    v %= g.n[a];
+    if (v < 0) v += g.n[a];
+    return true;
+  }
+  return false;
+}
+__device__ __forceinline__ bool on_wall(const Geo& g, int a, int v) {
+  return g.bc[a] == 1 && (v == 0 || v == g.n[a] - 1);
+}
+__device__ __forceinline__ bool is_wall(const Geo& g, int x, int y, int z) {
+  bool w = on_wall(g, 0, x) || on_wall(g, 1, y);
+  if (g.d == 3) w = w || on_wall(g, 2, z);
+  return w;
+}
+__device__ __forceinline__ long long nidx(const Geo& g, int x, int y, int z) {
+  return x + (long long)g.n[0] * (y + (long long)g.n[1] * z);
+}
+__device__ __forceinline__ int inward(const Geo& g, int a, int v) {
+  if (g.bc[a] != 1) return v;
+  if (v == 0) return 1;
+  if (v == g.n[a] - 1) return g.n[a] - 2;
+  return v;
+}
+__device__ __forceinline__ long long wall_src(const Geo& g, int x, int y, int z) {
+  return nidx(g, inward(g, 0, x), inward(g, 1, y), g.d == 3 ? inward(g, 2, z) : z);
+}
+// Imposed velocity at a wall node (the highest wall axis wins).
+__device__ __forceinline__ void wall_vel(const Geo& g, int x, int y, int z, double u[3]) {
+  u[0] = u[1] = u[2] = 0.0;
+  const int c[3] = {x, y, z};
+  for (int a = 0; a < g.d; ++a) {
+    if (g.bc[a] != 1) continue;
+    int side = -1;
+    if (c[a] == 0) side = 0;
+    if (c[a] == g.n[a] - 1) side = 1;
+    if (side < 0) continue;
+    for (int k = 0; k < 3; ++k) u[k] = g.uw[a][side][k];
+  }
+}
+__device__ __forceinline__ bool in_target(const Geo& g, int x, int y, int z) {
+  if (x < g.tlo[0] || x >= g.thi[0] || y < g.tlo[1] || y >= g.thi[1]) return false;
+  if (g.d == 3 && (z < g.tlo[2] || z >= g.thi[2])) return false;
+  return true;
+}
+// Body-box local index of a (wrapped) node, -1 outside this step's box.
+__device__ __forceinline__ long long box_index(const Geo& g, const Box& b, int x, int y, int z) {
+  const int c[3] = {x, y, z};
+  int r[3] = {0, 0, 0};
+  for (int a = 0; a < g.d; ++a) {
+    int v = c[a] - b.lo[a];
+    if (g.bc[a] == 0) {
+      v %= g.n[a];
+      if (v < 0) v += g.n[a];
+    }
+    if (v < 0 || v >= b.ext[a]) return -1;
+    r[a] = v;
+  }
+  return r[0] + (long long)b.sx * (r[1] + (long long)b.sy * r[2]);
+}
+
+// Cosine kernel w(r) = (1 + cos(pi r / 2)) / 4 and its derivative (Sec. 2.3).
+__device__ __forceinline__ float wk(float r) { return 0.25f * (1.0f + cospif(0.5f * r)); }
+__device__ __forceinline__ double wk(double r) { return 0.25 * (1.0 + cospi(0.5 * r)); }
+__device__ __forceinline__ float wkd(float r) { return -0.39269908169872414f * sinpif(0.5f * r); }
+__device__ __forceinline__ double wkd(double r) { return -0.39269908169872414 * sinpi(0.5 * r); }
+
+// Derivative along one axis from an LDS row (stride st): central, or
+// second-order one-sided on a wall node.
+template <class R>
+__device__ __forceinline__ R dnum(const Geo& g, int a, int v, const R* s, int c, int st) {
+  if (g.bc[a] == 1) {
+    if (v == 0) return R(-1.5) * s[c] + R(2) * s[c + st] - R(0.5) * s[c + 2 * st];
+    if (v == g.n[a] - 1) return R(1.5) * s[c] - R(2) * s[c - st] + R(0.5) * s[c - 2 * st];
+  }
+  return R(0.5) * (s[c + st] - s[c - st]);
+}
+// Transpose of dnum at node coordinate v: sum_x D[x][v] gv(x), reading the
+// LDS row around index c.
+template <class R>
+__device__ __forceinline__ R dnumT(const Geo& g, int a, int v, const R* s, int c, int st) {
+  if (g.bc[a] != 1) return R(0.5) * (s[c - st] - s[c + st]);
+  const int n = g.n[a];
+  R r = R(0);
+  if (v == 0) r += R(-1.5) * s[c];
+  if (v == n - 1) r += R(1.5) * s[c];
+  if (v - 1 >= 0) r += (v - 1 == 0 ? R(2) : R(0.5)) * s[c - st];
+  if (v + 1 <= n - 1) r += (v + 1 == n - 1 ? R(-2) : R(-0.5)) * s[c + st];
+  if (v - 2 == 0) r += R(-0.5) * s[c - 2 * st];
+  if (v + 2 == n - 1) r += R(0.5) * s[c + 2 * st];
+  return r;
+}
+
+// Inamuro equilibria for one node (pairs of opposite directions share
+// their even part).  S holds D_a u_b + D_b u_a.
+template <class R>
+__device__ __forceinline__ void feq9(R p, R ux, R uy, R Sxx, R Syy, R Sxy, R A, R* f) {
+  const R base = R(3) * p - R(1.5) * (ux * ux + uy * uy);
+  f[0] = R(4.0 / 9.0) * base;
+  auto pair = [&](int i, R w, R cu, R cSc) {
+    R com = w * (base + R(4.5) * cu * cu + A * cSc);
+    R od = R(3) * w * cu;
+    f[i] = com + od;
+    f[i + 1] = com - od;
+  };
+  pair(1, R(1.0 / 9.0), ux, Sxx);
+  pair(3, R(1.0 / 9.0), uy, Syy);
+  pair(5, R(1.0 / 36.0), ux + uy, Sxx + Syy + R(2) * Sxy);
+  pair(7, R(1.0 / 36.0), uy - ux, Sxx + Syy - R(2) * Sxy);
+}
+template <class R>
+__device__ __forceinline__ void feq15(R p, R ux, R uy, R uz, R Sxx, R Syy, R Szz, R Sxy, R Sxz,
+                                      R Syz, R A, R* f) {
+  const R base = R(3) * p - R(1.5) * (ux * ux + uy * uy + uz * uz);
+  f[0] = R(2.0 / 9.0) * base;
+  auto pair = [&](int i, R w, R cu, R cSc) {
+    R com = w * (base + R(4.5) * cu * cu + A * cSc);
+    R od = R(3) * w * cu;
+    f[i] = com + od;
+    f[i + 1] = com - od;
+  };
+  const R tr = Sxx + Syy + Szz;
+  pair(1, R(1.0 / 9.0), ux, Sxx);
+  pair(3, R(1.0 / 9.0), uy, Syy);
+  pair(5, R(1.0 / 9.0), uz, Szz);
+  pair(7, R(1.0 / 72.0), ux + uy + uz, tr + R(2) * (Sxy + Sxz + Syz));
+  pair(9, R(1.0 / 72.0), -ux + uy + uz, tr + R(2) * (-Sxy - Sxz + Syz));
+  pair(11, R(1.0 / 72.0), ux - uy + uz, tr + R(2) * (-Sxy + Sxz - Syz));
+  pair(13, R(1.0 / 72.0), ux + uy - uz, tr + R(2) * (Sxy - Sxz - Syz));
+}
+
+// Block-wide fixed-order sum of K doubles per thread into out[0..K) (thread 0).
+template <int K, int NT>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* out) {
+  __shared__ double red[NT / 64][K];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if (lane == 0) red[wv][k] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < NT / 64; ++w) s += red[w][k];
+      out[k] = s;
+    }
+  }
+}
+
+// Brinkman correction, wall rule, objective partials and store of one
+// output node.  acc = (sum_i feq_i, sum_i c_i feq_i) gathered at x.
+template <class R>
+__device__ __forceinline__ void finish_node(const Geo& g, const FwdArgs& a, int x, int y, int z,
+                                            R sp, R sux, R suy, R suz, double& s1, double& s2) {
+  R* out = (R*)a.out;
+  const long long N = g.N;
+  const long long i = nidx(g, x, y, z);
+  R u[3];
+  R p;
+  if (is_wall(g, x, y, z)) {
+    double uw[3];
+    wall_vel(g, x, y, z, uw);
+    u[0] = (R)uw[0];
+    u[1] = (R)uw[1];
+    u[2] = (R)uw[2];
+    p = R(0);  // wall pressure follows the wall rule when read
+  } else {
+    p = sp * R(1.0 / 3.0);
+    u[0] = sux;
+    u[1] = suy;
+    u[2] = suz;
+    if (a.bk) {
+      long long bi = box_index(g, a.box, x, y, z);
+      if (bi >= 0) {
+        const R* bk = (const R*)a.bk;
+        const R* bu = (const R*)a.bu;
+        R k = bk[bi];
+        R inv = R(1) / (R(1) + k);
+        for (int c = 0; c < g.d; ++c) u[c] = (u[c] + k * bu[c * a.box.vol + bi]) * inv;
+      }
+    }
+    R uu = u[0] * u[0] + u[1] * u[1] + (g.d == 3 ? u[2] * u[2] : R(0));
+    if (a.flags && !(uu < R(0.25))) a.flags[0] = 1;  // non-finite or |u| >= 0.5
+  }
+  out[i] = p;
+  out[N + i] = u[0];
+  out[2 * N + i] = u[1];
+  if (g.d == 3) out[3 * N + i] = u[2];
+  if (a.opart && in_target(g, x, y, z)) {
+    double un = g.ndir[0] * (double)u[0] + g.ndir[1] * (double)u[1];
+    if (g.d == 3) un += g.ndir[2] * (double)u[2];
+    s1 += un;
+    s2 += un * un;
+  }
+}
+
+// ------------------------------------------------------ forward, D2Q9
+template <class R>
+__global__ __launch_bounds__(STEP_THREADS) void k_fwd2d(Geo g, FwdArgs a) {
+  constexpr int TX = TILE_X, TY = TILE_Y;
+  constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
+  __shared__ R sp[LY * LX], sx[LY * LX], sy[LY * LX];
+  __shared__ R sf[9][FY * FX];
+  const R* in = (const R*)a.in;
+  const long long N = g.N;
+  const int x0 = blockIdx.x * TX + g.org[0], y0 = blockIdx.y * TY + g.org[1];
+  for (int k = threadIdx.x; k < LX * LY; k += STEP_THREADS) {
+    int gx = x0 - 2 + k % LX, gy = y0 - 2 + k / LX;
+    R p = R(0), ux = R(0), uy = R(0);
+    if (wrap_axis(g, 0, gx) && wrap_axis(g, 1, gy)) {
+      long long i = nidx(g, gx, gy, 0);
+      ux = in[N + i];
+      uy = in[2 * N + i];
+      long long ip = (a.lazy_wall && is_wall(g, gx, gy, 0)) ? wall_src(g, gx, gy, 0) : i;
+      p = in[ip];
+    }
+    sp[k] = p;
+    sx[k] = ux;
+    sy[k] = uy;
+  }
+  __syncthreads();
+  const R A = (R)g.A;
+  for (int k = threadIdx.x; k < FX * FY; k += STEP_THREADS) {
+    int fx = k % FX, fy = k / FX;
+    int gx = x0 - 1 + fx, gy = y0 - 1 + fy;
+    R f[9];
+    if (wrap_axis(g, 0, gx) && wrap_axis(g, 1, gy)) {
+      const int c = (fy + 1) * LX + (fx + 1);
+      R dxux = dnum(g, 0, gx, sx, c, 1), dxuy = dnum(g, 0, gx, sy, c, 1);
+      R dyux = dnum(g, 1, gy, sx, c, LX), dyuy = dnum(g, 1, gy, sy, c, LX);
+      feq9(sp[c], sx[c], sy[c], R(2) * dxux, R(2) * dyuy, dxuy + dyux, A, f);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = R(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) sf[i][k] = f[i];
+  }
+  __syncthreads();
+  double s1 = 0.0, s2 = 0.0;
+  {
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int gx = x0 + tx, gy = y0 + ty;
+    if (gx >= 0 && gx < g.n[0] && gy >= 0 && gy < g.n[1]) {
+      const int c = (ty + 1) * FX + (tx + 1);
+      R P = R(0), Ux = R(0), Uy = R(0);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const int cx = Lat<9>::c[i][0], cy = Lat<9>::c[i][1];
+        R v = sf[i][c - cx - cy * FX];
+        P += v;
+        if (cx == 1) Ux += v;
+        if (cx == -1) Ux -= v;
+        if (cy == 1) Uy += v;
+        if (cy == -1) Uy -= v;
+      }
+      finish_node<R>(g, a, gx, gy, 0, P, Ux, Uy, R(0), s1, s2);
+    }
+  }
+  if (a.opart) {
+    double v[2] = {s1, s2};
+    double tot[2];
+    block_sum<2, STEP_THREADS>(v, tot);
+    if (threadIdx.x == 0) {
+      const long long b = blockIdx.x + (long long)gridDim.x * blockIdx.y;
+      a.opart[2 * b] += tot[0];
+      a.opart[2 * b + 1] += tot[1];
+    }
+  }
+}
+
+// ------------------------------------------------------ forward, D3Q15
+template <class R>
+__global__ __launch_bounds__(STEP_THREADS) void k_fwd3d(Geo g, FwdArgs a) {
+  constexpr int TX = TILE_X, TY = TILE_Y;
+  constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
+  constexpr int LP = LX * LY, FP = FX * FY;
+  __shared__ R ring[3][4][LP];  // planes (mod 3): p, ux, uy, uz
+  __shared__ R sf[15][FP];
+  const R* in = (const R*)a.in;
+  const long long N = g.N;
+  const int nz = g.n[2];
+  const int x0 = blockIdx.x * TX + g.org[0], y0 = blockIdx.y * TY + g.org[1];
+  const int z0 = blockIdx.z * ZSEG, z1 = min(z0 + ZSEG, nz);
+
+  auto load_plane = [&](int zp) {
+    int zw = zp % nz;
+    if (zw < 0) zw += nz;
+    const int sl = (zp + 3) % 3;
+    for (int k = threadIdx.x; k < LP; k += STEP_THREADS) {
+      int gx = x0 - 2 + k % LX, gy = y0 - 2 + k / LX;
+      R p = R(0), ux = R(0), uy = R(0), uz = R(0);
+      if (wrap_axis(g, 0, gx) && wrap_axis(g, 1, gy)) {
+        long long i = nidx(g, gx, gy, zw);
+        ux = in[N + i];
+        uy = in[2 * N + i];
+        uz = in[3 * N + i];
+        long long ip = (a.lazy_wall && is_wall(g, gx, gy, zw)) ? wall_src(g, gx, gy, zw) : i;
+        p = in[ip];
+      }
+      ring[sl][0][k] = p;
+      ring[sl][1][k] = ux;
+      ring[sl][2][k] = uy;
+      ring[sl][3][k] = uz;
+    }
+  };
+
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int gx = x0 + tx, gy = y0 + ty;
+  const bool own = gx >= 0 && gx < g.n[0] && gy >= 0 && gy < g.n[1];
+  const int oc = (ty + 1) * FX + (tx + 1);
+  R am[4] = {R(0), R(0), R(0), R(0)}, a0[4] = {R(0), R(0), R(0), R(0)},
+    ap[4] = {R(0), R(0), R(0), R(0)};
+  double s1 = 0.0, s2 = 0.0;
+  const R A = (R)g.A;
+
+  load_plane(z0 - 2);
+  load_plane(z0 - 1);
+  for (int zf = z0 - 1; zf <= z1; ++zf) {
+    load_plane(zf + 1);
+    __syncthreads();
+    {
+      const int sm = (zf + 2) % 3, sc = (zf + 3) % 3, sp1 = (zf + 4) % 3;
+      for (int k = threadIdx.x; k < FP; k += STEP_THREADS) {
+        int fx = k % FX, fy = k / FX;
+        int hx = x0 - 1 + fx, hy = y0 - 1 + fy;
+        R f[15];
+        if (wrap_axis(g, 0, hx) && wrap_axis(g, 1, hy)) {
+          const int c = (fy + 1) * LX + (fx + 1);
+          const R* ux = ring[sc][1];
+          const R* uy = ring[sc][2];
+          const R* uz = ring[sc][3];
+          R dxux = dnum(g, 0, hx, ux, c, 1), dxuy = dnum(g, 0, hx, uy, c, 1),
+            dxuz = dnum(g, 0, hx, uz, c, 1);
+          R dyux = dnum(g, 1, hy, ux, c, LX), dyuy = dnum(g, 1, hy, uy, c, LX),
+            dyuz = dnum(g, 1, hy, uz, c, LX);
+          R dzux = R(0.5) * (ring[sp1][1][c] - ring[sm][1][c]);
+          R dzuy = R(0.5) * (ring[sp1][2][c] - ring[sm][2][c]);
+          R dzuz = R(0.5) * (ring[sp1][3][c] - ring[sm][3][c]);
+          feq15(ring[sc][0][c], ux[c], uy[c], uz[c], R(2) * dxux, R(2) * dyuy, R(2) * dzuz,
+                dxuy + dyux, dxuz + dzux, dyuz + dzuy, A, f);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 15; ++i) f[i] = R(0);
+        }
+#pragma unroll
+        for (int i = 0; i < 15; ++i) sf[i][k] = f[i];
+      }
+    }
+    __syncthreads();
+    // gather plane zf into the three output planes it feeds
+#pragma unroll
+    for (int i = 0; i < 15; ++i) {
+      const int cx = Lat<15>::c[i][0], cy = Lat<15>::c[i][1], cz = Lat<15>::c[i][2];
+      R v = sf[i][oc - cx - cy * FX];
+      R* acc = (cz == 1) ? ap : ((cz == 0) ? a0 : am);
+      acc[0] += v;
+      if (cx == 1) acc[1] += v;
+      if (cx == -1) acc[1] -= v;
+      if (cy == 1) acc[2] += v;
+      if (cy == -1) acc[2] -= v;
+      if (cz == 1) acc[3] += v;
+      if (cz == -1) acc[3] -= v;
+    }
+    const int zo = zf - 1;
+    if (zo >= z0 && own) finish_node<R>(g, a, gx, gy, zo, am[0], am[1], am[2], am[3], s1, s2);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      am[k] = a0[k];
+      a0[k] = ap[k];
+      ap[k] = R(0);
+    }
+  }
+  if (a.opart) {
+    double v[2] = {s1, s2};
+    double tot[2];
+    block_sum<2, STEP_THREADS>(v, tot);
+    if (threadIdx.x == 0) {
+      const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+      a.opart[2 * b] += tot[0];
+      a.opart[2 * b + 1] += tot[1];
+    }
+  }
+}
+
+// ---------------------------------------------------------- adjoint helpers
+// Adjoint-state value of node (x,y,z) after the objective seed, the
+// transposed wall rule and the transposed Brinkman correction:
+// returns (pbar*, ubar*).  Wall nodes and nodes outside the grid give 0.
+// Owned nodes of the body box also emit dJ/dkappa and dJ/du_s.
+template <class R>
+__device__ __forceinline__ void adj_star(const Geo& g, const AdjArgs& a, int x, int y, int z,
+                                         bool inside, bool owned, R out[4]) {
+  out[0] = out[1] = out[2] = out[3] = R(0);
+  if (!inside || is_wall(g, x, y, z)) return;
+  const R* lam = (const R*)a.lam;
+  const R* uc = (const R*)a.u_cur;
+  const long long N = g.N;
+  const long long i = nidx(g, x, y, z);
+  // pressure adjoint plus the wall nodes that copy this node's pressure
+  R pb = lam[i];
+  const int c[3] = {x, y, z};
+  int opt[3][2];
+  int cnt[3];
+  for (int ax = 0; ax < 3; ++ax) {
+    opt[ax][0] = c[ax];
+    cnt[ax] = 1;
+    if (ax < g.d && g.bc[ax] == 1) {
+      if (c[ax] == 1) opt[ax][cnt[ax]++] = 0;
+      else if (c[ax] == g.n[ax] - 2) opt[ax][cnt[ax]++] = g.n[ax] - 1;
+    }
+  }
+  for (int kz = 0; kz < cnt[2]; ++kz)
+    for (int ky = 0; ky < cnt[1]; ++ky)
+      for (int kx = 0; kx < cnt[0]; ++kx) {
+        if (kx == 0 && ky == 0 && kz == 0) continue;
+        pb += lam[nidx(g, opt[0][kx], opt[1][ky], opt[2][kz])];
+      }
+  R ub[3];
+  ub[0] = lam[N + i];
+  ub[1] = lam[2 * N + i];
+  ub[2] = g.d == 3 ? lam[3 * N + i] : R(0);
+  R un3[3] = {R(0), R(0), R(0)};
+  bool have_u = false;
+  if (a.seed && in_target(g, x, y, z)) {
+    for (int k = 0; k < g.d; ++k) un3[k] = uc[(k + 1) * N + i];
+    have_u = true;
+    double un = 0.0;
+    for (int k = 0; k < g.d; ++k) un += g.ndir[k] * (double)un3[k];
+    double gs = a.seed[0] * g.NTinv * (1.0 - 2.0 * g.phi * (un - a.E[0]));
+    for (int k = 0; k < g.d; ++k) ub[k] += (R)(gs * g.ndir[k]);
+  }
+  out[0] = pb;
+  if (a.bk) {
+    long long bi = box_index(g, a.box, x, y, z);
+    if (bi >= 0) {
+      const R* bk = (const R*)a.bk;
+      const R* bu = (const R*)a.bu;
+      const R k = bk[bi];
+      const R inv = R(1) / (R(1) + k);
+      if (owned) {
+        if (!have_u)
+          for (int q = 0; q < g.d; ++q) un3[q] = uc[(q + 1) * N + i];
+        R kb = R(0);
+        R* bkbar = (R*)a.bkbar;
+        R* bubar = (R*)a.bubar;
+        for (int q = 0; q < g.d; ++q) {
+          kb += ub[q] * (bu[q * a.box.vol + bi] - un3[q]);
+          bubar[q * a.box.vol + bi] = k * ub[q] * inv;
+        }
+        bkbar[bi] = kb * inv;
+      }
+      for (int q = 0; q < g.d; ++q) ub[q] *= inv;
+    }
+  }
+  out[1] = ub[0];
+  out[2] = ub[1];
+  out[3] = ub[2];
+}
+
+// ------------------------------------------------------ adjoint, D2Q9
+template <class R>
+__global__ __launch_bounds__(STEP_THREADS) void k_adj2d(Geo g, AdjArgs a) {
+  constexpr int TX = TILE_X, TY = TILE_Y;
+  constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
+  __shared__ R sl[3][LY * LX];     // pbar*, ubar*_x, ubar*_y
+  __shared__ R sm[6][FY * FX];     // M0, M1x, M1y, M2xx, M2yy, M2xy
+  const long long N = g.N;
+  const int x0 = blockIdx.x * TX + g.org[0], y0 = blockIdx.y * TY + g.org[1];
+  for (int k = threadIdx.x; k < LX * LY; k += STEP_THREADS) {
+    int lx = k % LX, ly = k / LX;
+    int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+    bool inside = wrap_axis(g, 0, gx) && wrap_axis(g, 1, gy);
+    bool owned = lx >= 2 && lx < TX + 2 && ly >= 2 && ly < TY + 2 && (x0 - 2 + lx) == gx &&
+                 (y0 - 2 + ly) == gy;
+    R v[4];
+    adj_star<R>(g, a, gx, gy, 0, inside, owned, v);
+    sl[0][k] = v[0];
+    sl[1][k] = v[1];
+    sl[2][k] = v[2];
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < FX * FY; k += STEP_THREADS) {
+    int fx = k % FX, fy = k / FX;
+    const int c = (fy + 1) * LX + (fx + 1);
+    R M0 = R(0), M1x = R(0), M1y = R(0), Mxx = R(0), Myy = R(0), Mxy = R(0);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int cx = Lat<9>::c[i][0], cy = Lat<9>::c[i][1];
+      const int j = c + cx + cy * LX;
+      R F = sl[0][j] * R(1.0 / 3.0);
+      if (cx == 1) F += sl[1][j];
+      if (cx == -1) F -= sl[1][j];
+      if (cy == 1) F += sl[2][j];
+      if (cy == -1) F -= sl[2][j];
+      const R wF = R(Lat<9>::w[i]) * F;
+      M0 += wF;
+      if (cx == 1) { M1x += wF; Mxx += wF; }
+      if (cx == -1) { M1x -= wF; Mxx += wF; }
+      if (cy == 1) { M1y += wF; Myy += wF; }
+      if (cy == -1) { M1y -= wF; Myy += wF; }
+      if (cx * cy == 1) Mxy += wF;
+      if (cx * cy == -1) Mxy -= wF;
+    }
+    sm[0][k] = M0;
+    sm[1][k] = M1x;
+    sm[2][k] = M1y;
+    sm[3][k] = Mxx;
+    sm[4][k] = Myy;
+    sm[5][k] = Mxy;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int gx = x0 + tx, gy = y0 + ty;
+  if (gx < 0 || gx >= g.n[0] || gy < 0 || gy >= g.n[1]) return;
+  const int c = (ty + 1) * FX + (tx + 1);
+  const long long i = nidx(g, gx, gy, 0);
+  const R* up = (const R*)a.u_prev;
+  const R ux = up[N + i], uy = up[2 * N + i];
+  const R M0 = sm[0][c];
+  const R A2 = R(2) * (R)g.A;
+  R px = R(3) * M0;
+  R bx = R(3) * sm[1][c] + R(9) * (sm[3][c] * ux + sm[5][c] * uy) - R(3) * ux * M0;
+  R by = R(3) * sm[2][c] + R(9) * (sm[5][c] * ux + sm[4][c] * uy) - R(3) * uy * M0;
+  // velocity-gradient transpose: ubar_b += sum_a D_a^T (2 A M2_ab)
+  bx += A2 * (dnumT(g, 0, gx, sm[3], c, 1) + dnumT(g, 1, gy, sm[5], c, FX));
+  by += A2 * (dnumT(g, 0, gx, sm[5], c, 1) + dnumT(g, 1, gy, sm[4], c, FX));
+  R* lp = (R*)a.lam_prev;
+  lp[i] = px;
+  lp[N + i] = bx;
+  lp[2 * N + i] = by;
+}
+
+// ------------------------------------------------------ adjoint, D3Q15
+template <class R>
+__global__ __launch_bounds__(STEP_THREADS) void k_adj3d(Geo g, AdjArgs a) {
+  constexpr int TX = TILE_X, TY = TILE_Y;
+  constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
+  constexpr int LP = LX * LY, FP = FX * FY;
+  __shared__ R ring[3][4][LP];   // adjoint star planes (mod 3)
+  __shared__ R mb[2][10][FP];    // moment planes (mod 2): M0, M1x,y,z, Mxx,yy,zz,xy,xz,yz
+  const long long N = g.N;
+  const int nz = g.n[2];
+  const int x0 = blockIdx.x * TX + g.org[0], y0 = blockIdx.y * TY + g.org[1];
+  const int z0 = blockIdx.z * ZSEG, z1 = min(z0 + ZSEG, nz);
+
+  auto load_plane = [&](int zp) {
+    int zw = zp % nz;
+    if (zw < 0) zw += nz;
+    const int s = (zp + 3) % 3;
+    const bool own_plane = zp >= z0 && zp < z1;
+    for (int k = threadIdx.x; k < LP; k += STEP_THREADS) {
+      int lx = k % LX, ly = k / LX;
+      int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+      bool inside = wrap_axis(g, 0, gx) && wrap_axis(g, 1, gy);
+      bool owned = own_plane && lx >= 2 && lx < TX + 2 && ly >= 2 && ly < TY + 2 &&
+                   (x0 - 2 + lx) == gx && (y0 - 2 + ly) == gy;
+      R v[4];
+      adj_star<R>(g, a, gx, gy, zw, inside, owned, v);
+      ring[s][0][k] = v[0];
+      ring[s][1][k] = v[1];
+      ring[s][2][k] = v[2];
+      ring[s][3][k] = v[3];
+    }
+  };
+
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int gx = x0 + tx, gy = y0 + ty;
+  const bool own = gx >= 0 && gx < g.n[0] && gy >= 0 && gy < g.n[1];
+  const int oc = (ty + 1) * FX + (tx + 1);
+  const R A2 = R(2) * (R)g.A;
+  const R* up = (const R*)a.u_prev;
+  R* lp = (R*)a.lam_prev;
+  R zprev[3] = {R(0), R(0), R(0)};  // own column M2_{zx}, M2_{zy}, M2_{zz} at zo - 1
+
+  load_plane(z0 - 2);
+  load_plane(z0 - 1);
+  for (int zs = z0 - 1; zs <= z1; ++zs) {
+    load_plane(zs + 1);
+    __syncthreads();
+    {
+      const int s0 = (zs + 2) % 3, s1 = (zs + 3) % 3, s2 = (zs + 4) % 3;
+      const int rs[3] = {s0, s1, s2};  // planes zs-1, zs, zs+1
+      R(*mo)[FP] = mb[zs & 1];
+      for (int k = threadIdx.x; k < FP; k += STEP_THREADS) {
+        int fx = k % FX, fy = k / FX;
+        const int c = (fy + 1) * LX + (fx + 1);
+        R M[10];
+#pragma unroll
+        for (int q = 0; q < 10; ++q) M[q] = R(0);
+#pragma unroll
+        for (int i = 0; i < 15; ++i) {
+          const int cx = Lat<15>::c[i][0], cy = Lat<15>::c[i][1], cz = Lat<15>::c[i][2];
+          const int pl = rs[cz + 1];
+          const int j = c + cx + cy * LX;
+          R F = ring[pl][0][j] * R(1.0 / 3.0);
+          if (cx == 1) F += ring[pl][1][j];
+          if (cx == -1) F -= ring[pl][1][j];
+          if (cy == 1) F += ring[pl][2][j];
+          if (cy == -1) F -= ring[pl][2][j];
+          if (cz == 1) F += ring[pl][3][j];
+          if (cz == -1) F -= ring[pl][3][j];
+          const R wF = R(Lat<15>::w[i]) * F;
+          M[0] += wF;
+          if (cx != 0) { M[1] += cx * wF; M[4] += wF; }
+          if (cy != 0) { M[2] += cy * wF; M[5] += wF; }
+          if (cz != 0) { M[3] += cz * wF; M[6] += wF; }
+          if (cx * cy != 0) M[7] += (cx * cy) * wF;
+          if (cx * cz != 0) M[8] += (cx * cz) * wF;
+          if (cy * cz != 0) M[9] += (cy * cz) * wF;
+        }
+#pragma unroll
+        for (int q = 0; q < 10; ++q) mo[q][k] = M[q];
+      }
+    }
+    __syncthreads();
+    const int zo = zs - 1;
+    if (zo >= z0 && own) {
+      R(*m0)[FP] = mb[zo & 1];   // plane zo
+      R(*m1)[FP] = mb[zs & 1];   // plane zo + 1
+      const long long i = nidx(g, gx, gy, zo);
+      const R ux = up[N + i], uy = up[2 * N + i], uz = up[3 * N + i];
+      const R M0 = m0[0][oc];
+      const R Mxx = m0[4][oc], Myy = m0[5][oc], Mzz = m0[6][oc];
+      const R Mxy = m0[7][oc], Mxz = m0[8][oc], Myz = m0[9][oc];
+      R bx = R(3) * m0[1][oc] + R(9) * (Mxx * ux + Mxy * uy + Mxz * uz) - R(3) * ux * M0;
+      R by = R(3) * m0[2][oc] + R(9) * (Mxy * ux + Myy * uy + Myz * uz) - R(3) * uy * M0;
+      R bz = R(3) * m0[3][oc] + R(9) * (Mxz * ux + Myz * uy + Mzz * uz) - R(3) * uz * M0;
+      // D_x^T and D_y^T in plane; D_z^T (periodic) from planes zo - 1, zo + 1
+      bx += A2 * (dnumT(g, 0, gx, m0[4], oc, 1) + dnumT(g, 1, gy, m0[7], oc, FX) +
+                  R(0.5) * (zprev[0] - m1[8][oc]));
+      by += A2 * (dnumT(g, 0, gx, m0[7], oc, 1) + dnumT(g, 1, gy, m0[5], oc, FX) +
+                  R(0.5) * (zprev[1] - m1[9][oc]));
+      bz += A2 * (dnumT(g, 0, gx, m0[8], oc, 1) + dnumT(g, 1, gy, m0[9], oc, FX) +
+                  R(0.5) * (zprev[2] - m1[6][oc]));
+      lp[i] = R(3) * M0;
+      lp[N + i] = bx;
+      lp[2 * N + i] = by;
+      lp[3 * N + i] = bz;
+    }
+    if (zs >= z0) {
+      // keep own-column z-moments of plane zs - 1 for the next output
+      R(*mz)[FP] = mb[(zs - 1) & 1];
+      zprev[0] = mz[8][oc];
+      zprev[1] = mz[9][oc];
+      zprev[2] = mz[6][oc];
+    }
+  }
+}
+
+// --------------------------------------------------------------- map
+struct Mot {
+  double xg[3], ug[3], c, s, om;
+};
+__host__ __device__ inline Mot make_mot(const double* m8) {
+  Mot m;
+  for (int k = 0; k < 3; ++k) {
+    m.xg[k] = m8[k];
+    m.ug[k] = m8[3 + k];
+  }
+  m.c = cos(m8[6]);
+  m.s = sin(m8[6]);
+  m.om = m8[7];
+  return m;
+}
+
+// Cosine-kernel sums over the design points whose rotated position lies
+// within the kernel support of analysis position (bx, by):
+// W-weighted kappa_ref (per z value for 3D), sum W, sum W r1, sum W r2.
+template <class R>
+__global__ __launch_bounds__(256) void k_map2d(Geo g, const R* kref, Mot m, Box box, R* bk,
+                                               R* bu, int full_grid) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= box.ext[0] || j >= box.ext[1]) return;
+  const int bx = box.lo[0] + i, by = box.lo[1] + j;
+  int x = bx, y = by;
+  const bool inside = wrap_axis(g, 0, x) && wrap_axis(g, 1, y);
+  const bool wall = inside && is_wall(g, x, y, 0);
+  R k = R(0), m0 = R(0), m1 = R(0), m2 = R(0);
+  if (inside && !wall) {
+    const double rx = bx - m.xg[0], ry = by - m.xg[1];
+    const double q0 = m.c * rx + m.s * ry + g.xiG[0];
+    const double q1 = -m.s * rx + m.c * ry + g.xiG[1];
+    const double h = 2.0 * (fabs(m.c) + fabs(m.s));
+    const int i0 = max(0, (int)ceil(q0 - h)), i1 = min(g.D[0] - 1, (int)floor(q0 + h));
+    const int j0 = max(0, (int)ceil(q1 - h)), j1 = min(g.D[1] - 1, (int)floor(q1 + h));
+    for (int e1 = j0; e1 <= j1; ++e1) {
+      const double r1 = e1 - g.xiG[1];
+      for (int e0 = i0; e0 <= i1; ++e0) {
+        const double r0 = e0 - g.xiG[0];
+        const double d0 = bx - (m.c * r0 - m.s * r1 + m.xg[0]);
+        const double d1 = by - (m.s * r0 + m.c * r1 + m.xg[1]);
+        if (fabs(d0) < 2.0 && fabs(d1) < 2.0) {
+          const R W = wk((R)d0) * wk((R)d1);
+          m0 += W;
+          m1 += W * (R)r0;
+          m2 += W * (R)r1;
+          k += W * kref[e0 + (long long)g.D[0] * e1];
+        }
+      }
+    }
+  }
+  const R om = (R)m.om, c = (R)m.c, s = (R)m.s;
+  const R usx = om * (-s * m1 - c * m2) + (R)m.ug[0] * m0;
+  const R usy = om * (c * m1 - s * m2) + (R)m.ug[1] * m0;
+  if (full_grid) {
+    if (!inside || wall) return;
+    const long long n = nidx(g, x, y, 0);
+    bk[n] = k;
+    bu[n] = usx;
+    bu[g.N + n] = usy;
+  } else {
+    const long long bi = i + (long long)box.sx * j;
+    bk[bi] = k;
+    bu[bi] = usx;
+    bu[box.vol + bi] = usy;
+  }
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_map3d(Geo g, const R* kref, Mot m, Box box, R* bk,
+                                               R* bu, int full_grid) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const int zc = blockIdx.z * MAP_ZC;
+  if (i >= box.ext[0] || j >= box.ext[1] || zc >= box.ext[2]) return;
+  const int bx = box.lo[0] + i, by = box.lo[1] + j;
+  int x = bx, y = by;
+  const bool col_inside = wrap_axis(g, 0, x) && wrap_axis(g, 1, y);
+  const bool col_wall = col_inside && (on_wall(g, 0, x) || on_wall(g, 1, y));
+  R k[MAP_ZC], zs[MAP_ZC];
+  int base[MAP_ZC];
+  R wz[MAP_ZC][4];
+  const double o = g.xiG[2] - m.xg[2];
+#pragma unroll
+  for (int t = 0; t < MAP_ZC; ++t) {
+    k[t] = R(0);
+    const double zz = (double)(box.lo[2] + zc + t) + o;
+    const double fl = floor(zz);
+    const R f = (R)(zz - fl);
+    base[t] = (int)fl - 1;
+    zs[t] = R(0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      wz[t][q] = wk(f + R(1) - R(q));
+      const int e2 = base[t] + q;
+      if (e2 >= 0 && e2 < g.D[2]) zs[t] += wz[t][q];
+    }
+  }
+  R m0 = R(0), m1 = R(0), m2 = R(0);
+  if (col_inside && !col_wall) {
+    const double rx = bx - m.xg[0], ry = by - m.xg[1];
+    const double q0 = m.c * rx + m.s * ry + g.xiG[0];
+    const double q1 = -m.s * rx + m.c * ry + g.xiG[1];
+    const double h = 2.0 * (fabs(m.c) + fabs(m.s));
+    const int i0 = max(0, (int)ceil(q0 - h)), i1 = min(g.D[0] - 1, (int)floor(q0 + h));
+    const int j0 = max(0, (int)ceil(q1 - h)), j1 = min(g.D[1] - 1, (int)floor(q1 + h));
+    const long long plane = (long long)g.D[0] * g.D[1];
+    for (int e1 = j0; e1 <= j1; ++e1) {
+      const double r1 = e1 - g.xiG[1];
+      for (int e0 = i0; e0 <= i1; ++e0) {
+        const double r0 = e0 - g.xiG[0];
+        const double d0 = bx - (m.c * r0 - m.s * r1 + m.xg[0]);
+        const double d1 = by - (m.s * r0 + m.c * r1 + m.xg[1]);
+        if (fabs(d0) < 2.0 && fabs(d1) < 2.0) {
+          const R W = wk((R)d0) * wk((R)d1);
+          m0 += W;
+          m1 += W * (R)r0;
+          m2 += W * (R)r1;
+          const R* col = kref + e0 + (long long)g.D[0] * e1;
+#pragma unroll
+          for (int t = 0; t < MAP_ZC; ++t) {
+            R acc = R(0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int e2 = base[t] + q;
+              if (e2 >= 0 && e2 < g.D[2]) acc += wz[t][q] * col[e2 * plane];
+            }
+            k[t] += W * acc;
+          }
+        }
+      }
+    }
+  }
+  const R om = (R)m.om, c = (R)m.c, s = (R)m.s;
+  const R vx = om * (-s * m1 - c * m2) + (R)m.ug[0] * m0;
+  const R vy = om * (c * m1 - s * m2) + (R)m.ug[1] * m0;
+  const R vz = (R)m.ug[2] * m0;
+#pragma unroll
+  for (int t = 0; t < MAP_ZC; ++t) {
+    const int kz = zc + t;
+    if (kz >= box.ext[2]) break;
+    int z = box.lo[2] + kz;
+    const bool inside = col_inside && wrap_axis(g, 2, z);
+    const bool wall = !inside || col_wall || on_wall(g, 2, z);
+    R kk = wall ? R(0) : k[t];
+    R ux = wall ? R(0) : zs[t] * vx, uy = wall ? R(0) : zs[t] * vy, uz = wall ? R(0) : zs[t] * vz;
+    if (full_grid) {
+      if (wall) continue;
+      const long long n = nidx(g, x, y, z);
+      bk[n] = kk;
+      bu[n] = ux;
+      bu[g.N + n] = uy;
+      bu[2 * g.N + n] = uz;
+    } else {
+      const long long bi = i + (long long)box.sx * (j + (long long)box.sy * kz);
+      bk[bi] = kk;
+      bu[bi] = ux;
+      bu[box.vol + bi] = uy;
+      bu[2 * box.vol + bi] = uz;
+    }
+  }
+}
+
+// Transpose of the transfer for one step, one thread per design point.
+template <class R>
+__global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj(Geo g, const R* kref, Mot m, Box box,
+                                                           const R* bkbar, const R* bubar,
+                                                           double* kref_bar, int overwrite,
+                                                           double* mpart) {
+  const long long k = blockIdx.x * (long long)MAPADJ_THREADS + threadIdx.x;
+  double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (k < g.Mtot) {
+    const int e0 = (int)(k % g.D[0]);
+    const int e1 = (int)((k / g.D[0]) % g.D[1]);
+    const int e2 = (int)(k / ((long long)g.D[0] * g.D[1]));
+    const double r0 = e0 - g.xiG[0], r1 = e1 - g.xiG[1];
+    double X[3], U[3];
+    X[0] = m.c * r0 - m.s * r1 + m.xg[0];
+    X[1] = m.s * r0 + m.c * r1 + m.xg[1];
+    X[2] = (g.d == 3) ? (e2 - g.xiG[2]) + m.xg[2] : 0.0;
+    U[0] = m.om * (-m.s * r0 - m.c * r1) + m.ug[0];
+    U[1] = m.om * (m.c * r0 - m.s * r1) + m.ug[1];
+    U[2] = (g.d == 3) ? m.ug[2] : 0.0;
+    const double kr = (double)kref[k];
+    R wv[3][4], dv[3][4];
+    int node[3][4], bidx[3][4];
+    const int na = g.d;
+    for (int a = 0; a < 3; ++a) {
+      const int lo = (a < na) ? (int)floor(X[a]) - 1 : 0;
+      for (int q = 0; q < 4; ++q) {
+        if (a >= na) {
+          wv[a][q] = (q == 0) ? R(1) : R(0);
+          dv[a][q] = R(0);
+          node[a][q] = 0;
+          bidx[a][q] = (q == 0) ? 0 : -1;
+          continue;
+        }
+        int v = lo + q;
+        const R r = (R)((double)v - X[a]);
+        wv[a][q] = wk(r);
+        dv[a][q] = wkd(r);
+        bool ok = wrap_axis(g, a, v);
+        node[a][q] = v;
+        if (!ok || on_wall(g, a, v)) {
+          bidx[a][q] = -1;
+          continue;
+        }
+        int b = v - box.lo[a];
+        if (g.bc[a] == 0) {
+          b %= g.n[a];
+          if (b < 0) b += g.n[a];
+        }
+        bidx[a][q] = (b >= 0 && b < box.ext[a]) ? b : -1;
+      }
+    }
+    double kb = 0.0, Ub[3] = {0, 0, 0}, Xb[3] = {0, 0, 0};
+    const int qz = (na == 3) ? 4 : 1;
+    for (int cz = 0; cz < qz; ++cz) {
+      if (bidx[2][cz] < 0) continue;
+      for (int cy = 0; cy < 4; ++cy) {
+        if (bidx[1][cy] < 0) continue;
+        for (int cx = 0; cx < 4; ++cx) {
+          if (bidx[0][cx] < 0) continue;
+          const long long bi =
+              bidx[0][cx] + (long long)box.sx * (bidx[1][cy] + (long long)box.sy * bidx[2][cz]);
+          const double kbv = (double)bkbar[bi];
+          double ubv[3] = {(double)bubar[bi], (double)bubar[box.vol + bi],
+                           na == 3 ? (double)bubar[2 * box.vol + bi] : 0.0};
+          const double wx = wv[0][cx], wy = wv[1][cy], wz = wv[2][cz];
+          const double W = wx * wy * wz;
+          kb += W * kbv;
+          double gs = kr * kbv;
+          for (int a = 0; a < na; ++a) {
+            Ub[a] += W * ubv[a];
+            gs += U[a] * ubv[a];
+          }
+          Xb[0] -= (double)dv[0][cx] * wy * wz * gs;
+          Xb[1] -= wx * (double)dv[1][cy] * wz * gs;
+          if (na == 3) Xb[2] -= wx * wy * (double)dv[2][cz] * gs;
+        }
+      }
+    }
+    kref_bar[k] = (overwrite ? 0.0 : kref_bar[k]) + kb;
+    const double dX0 = -m.s * r0 - m.c * r1, dX1 = m.c * r0 - m.s * r1;              // R' r
+    const double dU0 = m.om * (-m.c * r0 + m.s * r1), dU1 = m.om * (-m.s * r0 - m.c * r1);  // om R'' r
+    for (int a = 0; a < 3; ++a) {
+      part[a] = Xb[a];
+      part[3 + a] = Ub[a];
+    }
+    part[6] = Xb[0] * dX0 + Xb[1] * dX1 + Ub[0] * dU0 + Ub[1] * dU1;
+    part[7] = Ub[0] * dX0 + Ub[1] * dX1;
+  }
+  double tot[8];
+  block_sum<8, MAPADJ_THREADS>(part, tot);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 8; ++q) mpart[(long long)blockIdx.x * 8 + q] = tot[q];
+}
+
+// ----------------------------------------------------------- prelude
+__device__ double filter_den(int t, int nt, int R) {
+  double den = 0.0;
+  const int a = max(0, t - R + 1), b = min(nt - 1, t + R - 1);
+  for (int tau = a; tau <= b; ++tau) den += (double)(R - abs(t - tau)) / (double)R;
+  return den;
+}
+
+// Temporal filter and bound map (Eqs. chi_filtered, x_g, psi_filtered, theta).
+__global__ void k_motion_pos(Geo g, const double* chi, const double* psi, double* mot) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int comp = blockIdx.y;  // 0..2 translation, 3 rotation
+  if (t >= g.nt) return;
+  if (comp < 3 && comp >= g.d) {
+    mot[t * 8 + comp] = 0.0;
+    return;
+  }
+  const int R = comp < 3 ? g.r_t : g.r_w;
+  const double* src = comp < 3 ? chi + comp : psi;
+  const int stride = comp < 3 ? 3 : 1;
+  double num = 0.0, den = 0.0;
+  const int a = max(0, t - R + 1), b = min(g.nt - 1, t + R - 1);
+  for (int tau = a; tau <= b; ++tau) {
+    const double w = (double)(R - abs(t - tau)) / (double)R;
+    num += w * src[(long long)tau * stride];
+    den += w;
+  }
+  const double f = num / den;
+  if (comp < 3)
+    mot[t * 8 + comp] = (g.xmax[comp] - g.xmin[comp]) * f + g.xmin[comp];
+  else
+    mot[t * 8 + 6] = (g.thmax - g.thmin) * f + g.thmin;
+}
+
+// Time derivative of the filtered motion (Eqs. u_g, omega).
+__global__ void k_motion_rate(Geo g, double* mot) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int comp = blockIdx.y;
+  if (t >= g.nt) return;
+  const int pc = comp < 3 ? comp : 6, vc = comp < 3 ? 3 + comp : 7;
+  const int nt = g.nt;
+  double v;
+  if (nt == 1)
+    v = 0.0;
+  else if (t == 0)
+    v = mot[8 + pc] - mot[pc];
+  else if (t == nt - 1)
+    v = mot[(nt - 1) * 8 + pc] - mot[(nt - 2) * 8 + pc];
+  else
+    v = 0.5 * (mot[(t + 1) * 8 + pc] - mot[(t - 1) * 8 + pc]);
+  mot[t * 8 + vc] = v;
+}
+
+// Support box per step and the domain check.  boxes[t] = lo[3], ext[3], flag, 0.
+__host__ __device__ void body_box(const Geo& g, const double* m8, int* out) {
+  const double c = cos(m8[6]), s = sin(m8[6]);
+  int lo[3], hi[3];
+  int flag = 0;
+  for (int pass = 0; pass < 2; ++pass) {  // 0: inner design points, 1: incl. margin
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+    for (int corner = 0; corner < 4; ++corner) {
+      double e0, e1;
+      if (pass == 0) {
+        e0 = (corner & 1) ? g.margin + g.m[0] - 1 : g.margin;
+        e1 = (corner & 2) ? g.margin + g.m[1] - 1 : g.margin;
+      } else {
+        e0 = (corner & 1) ? g.D[0] - 1 : 0;
+        e1 = (corner & 2) ? g.D[1] - 1 : 0;
+      }
+      const double r0 = e0 - g.xiG[0], r1 = e1 - g.xiG[1];
+      const double X0 = c * r0 - s * r1 + m8[0], X1 = s * r0 + c * r1 + m8[1];
+      mn[0] = fmin(mn[0], X0);
+      mx[0] = fmax(mx[0], X0);
+      mn[1] = fmin(mn[1], X1);
+      mx[1] = fmax(mx[1], X1);
+    }
+    if (g.d == 3) {
+      const double lo2 = (pass == 0 ? g.margin : 0) - g.xiG[2];
+      const double hi2 = (pass == 0 ? g.margin + g.m[2] - 1 : g.D[2] - 1) - g.xiG[2];
+      mn[2] = lo2 + m8[2];
+      mx[2] = hi2 + m8[2];
+    }
+    for (int a = 0; a < g.d; ++a) {
+      lo[a] = (int)floor(mn[a]) - 1;
+      hi[a] = (int)floor(mx[a]) + 2;
+      if (pass == 0 && g.bc[a] == 1 && (lo[a] < 1 || hi[a] > g.n[a] - 2)) flag = 1;
+    }
+    if (pass == 0) {
+      bool empty = false;
+      for (int a = 0; a < g.d; ++a) empty = empty || g.m[a] == 0;
+      if (empty) flag = 0;
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (a >= g.d) {
+      out[a] = 0;
+      out[3 + a] = 1;
+      continue;
+    }
+    int l = lo[a], h = hi[a];
+    if (g.bc[a] == 1) {
+      l = l < 0 ? 0 : l;
+      h = h > g.n[a] - 1 ? g.n[a] - 1 : h;
+    } else if (h - l + 1 > g.n[a]) {
+      flag = flag ? flag : 2;
+    }
+    out[a] = l;
+    out[3 + a] = h >= l ? h - l + 1 : 0;
+  }
+  out[6] = flag;
+  out[7] = 0;
+}
+
+__global__ void k_boxes(Geo g, const double* mot, int* boxes) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.nt) return;
+  body_box(g, mot + t * 8, boxes + t * 8);
+}
+
+// Eq. kappa_ref on the design grid incl. margin.
+template <class R>
+__global__ void k_kref(Geo g, const double* gamma, R* kref) {
+  const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (k >= g.Mtot) return;
+  const int e[3] = {(int)(k % g.D[0]), (int)((k / g.D[0]) % g.D[1]),
+                    (int)(k / ((long long)g.D[0] * g.D[1]))};
+  bool inner = true;
+  int j[3] = {0, 0, 0};
+  for (int a = 0; a < g.d; ++a) {
+    j[a] = e[a] - g.margin;
+    inner = inner && j[a] >= 0 && j[a] < g.m[a];
+  }
+  if (!inner) {
+    kref[k] = R(0);
+    return;
+  }
+  const double gm = gamma[j[0] + (long long)g.m[0] * (j[1] + (long long)g.m[1] * j[2])];
+  kref[k] = (R)(g.kmax * g.q * gm / ((1.0 - gm) + g.q));
+}
+
+// ---------------------------------------------------------- epilogue
+__global__ void k_obj_final(Geo g, const double* opart, int nblk, double* J3) {
+  double v[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += 256) {
+    v[0] += opart[2 * b];
+    v[1] += opart[2 * b + 1];
+  }
+  double tot[2];
+  block_sum<2, 256>(v, tot);
+  if (threadIdx.x == 0) {
+    const double E = tot[0] * g.NTinv;
+    const double V = tot[1] * g.NTinv - E * E;
+    J3[0] = E - g.phi * V;
+    J3[1] = E;
+    J3[2] = V;
+  }
+}
+
+// dJ/dgamma through Eq. kappa_ref.
+__global__ void k_sens_gamma(Geo g, const double* gamma, const double* kref_bar, double* dg) {
+  const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  long long M = 1;
+  for (int a = 0; a < g.d; ++a) M *= g.m[a];
+  if (j >= M) return;
+  const int i0 = (int)(j % g.m[0]);
+  const int i1 = (int)((j / g.m[0]) % g.m[1]);
+  const int i2 = (g.d == 3) ? (int)(j / ((long long)g.m[0] * g.m[1])) : 0;
+  const int e2 = (g.d == 3) ? i2 + g.margin : 0;
+  const long long k =
+      (i0 + g.margin) + (long long)g.D[0] * ((i1 + g.margin) + (long long)g.D[1] * e2);
+  const double gm = gamma[j];
+  const double den = (1.0 - gm) + g.q;
+  dg[j] = kref_bar[k] * g.kmax * g.q * (1.0 + g.q) / (den * den);
+}
+
+// Per-step motion partials: fixed-order sum over map-transpose blocks.
+__global__ void k_sens_mbar(Geo g, const double* mpart, int nblk, double* mbar) {
+  const int t = blockIdx.x;
+  const int q = threadIdx.x;  // 0..7
+  if (t >= g.nt || q >= 8) return;
+  double s = 0.0;
+  const double* p = mpart + (long long)t * nblk * 8;
+  for (int b = 0; b < nblk; ++b) s += p[b * 8 + q];
+  mbar[t * 8 + q] = s;
+}
+
+// tot[t][c] = span_c * (xbar(t) + (D_t^T vbar)(t)); den_t, den_w filter normalisers.
+__global__ void k_sens_tot(Geo g, const double* mbar, double* tot, double* den_t, double* den_w) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;  // 0..2 translation, 3 rotation
+  const int nt = g.nt;
+  if (t >= nt) return;
+  if (c == 0) {
+    den_t[t] = filter_den(t, nt, g.r_t);
+    den_w[t] = filter_den(t, nt, g.r_w);
+  }
+  const int pc = c < 3 ? c : 6, vc = c < 3 ? 3 + c : 7;
+  double v = mbar[t * 8 + pc];
+  if (nt >= 2) {
+    auto vb = [&](int tt) { return mbar[tt * 8 + vc]; };
+    if (t == 0) v -= vb(0);
+    if (t == 1) v += vb(0);
+    if (t == nt - 1) v += vb(nt - 1);
+    if (t == nt - 2) v -= vb(nt - 1);
+    if (t - 1 >= 1 && t - 1 <= nt - 2) v += 0.5 * vb(t - 1);
+    if (t + 1 >= 1 && t + 1 <= nt - 2) v -= 0.5 * vb(t + 1);
+  }
+  const double span = c < 3 ? (g.xmax[c] - g.xmin[c]) : (g.thmax - g.thmin);
+  tot[t * 4 + c] = (c < 3 && c >= g.d) ? 0.0 : span * v;
+}
+
+// Transposed temporal filter -> dJ/dchi, dJ/dpsi.
+__global__ void k_sens_filter(Geo g, const double* tot, const double* den_t, const double* den_w,
+                              double* dchi, double* dpsi) {
+  const int tau = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  const int nt = g.nt;
+  if (tau >= nt) return;
+  const int R = c < 3 ? g.r_t : g.r_w;
+  const double* den = c < 3 ? den_t : den_w;
+  double s = 0.0;
+  if (!(c < 3 && c >= g.d)) {
+    const int a = max(0, tau - R + 1), b = min(nt - 1, tau + R - 1);
+    for (int t = a; t <= b; ++t) s += ((double)(R - abs(t - tau)) / (double)R / den[t]) * tot[t * 4 + c];
+  }
+  if (c < 3)
+    dchi[tau * 3 + c] = s;
+  else
+    dpsi[tau] = s;
+}
+
+template <class R>
+__global__ void k_wall_fixup(Geo g, R* st) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  const int x = (int)(i % g.n[0]);
+  const int y = (int)((i / g.n[0]) % g.n[1]);
+  const int z = (int)(i / ((long long)g.n[0] * g.n[1]));
+  if (is_wall(g, x, y, z)) st[i] = st[wall_src(g, x, y, z)];
+}
+
+__global__ void k_zero(uint32_t* p, long long n) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// ------------------------------------------------------------ launchers
+static dim3 step_grid(const Geo& g) {
+  const int bx = (g.n[0] - g.org[0] + TILE_X - 1) / TILE_X;
+  const int by = (g.n[1] - g.org[1] + TILE_Y - 1) / TILE_Y;
+  const int bz = g.d == 3 ? (g.n[2] + ZSEG - 1) / ZSEG : 1;
+  return dim3(bx, by, bz);
+}
+int step_blocks(const Geo& g) {
+  dim3 d = step_grid(g);
+  return d.x * d.y * d.z;
+}
+
+hipError_t launch_forward_step(const Geo& g, int precision, const FwdArgs& a, hipStream_t s) {
+  dim3 grid = step_grid(g);
+  if (g.d == 2) {
+    if (precision == 0)
+      hipLaunchKernelGGL(k_fwd2d<float>, grid, dim3(STEP_THREADS), 0, s, g, a);
+    else
+      hipLaunchKernelGGL(k_fwd2d<double>, grid, dim3(STEP_THREADS), 0, s, g, a);
+  } else {
+    if (precision == 0)
+      hipLaunchKernelGGL(k_fwd3d<float>, grid, dim3(STEP_THREADS), 0, s, g, a);
+    else
+      hipLaunchKernelGGL(k_fwd3d<double>, grid, dim3(STEP_THREADS), 0, s, g, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(const Geo& g, int precision, const AdjArgs& a, hipStream_t s) {
+  dim3 grid = step_grid(g);
+  if (g.d == 2) {
+    if (precision == 0)
+      hipLaunchKernelGGL(k_adj2d<float>, grid, dim3(STEP_THREADS), 0, s, g, a);
+    else
+      hipLaunchKernelGGL(k_adj2d<double>, grid, dim3(STEP_THREADS), 0, s, g, a);
+  } else {
+    if (precision == 0)
+      hipLaunchKernelGGL(k_adj3d<float>, grid, dim3(STEP_THREADS), 0, s, g, a);
+    else
+      hipLaunchKernelGGL(k_adj3d<double>, grid, dim3(STEP_THREADS), 0, s, g, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_map(const Geo& g, int precision, const void* kref, const double* mot8_dev,
+                      const double* mot8_host, const Box& box, void* bk, void* bu, int full_grid,
+                      hipStream_t s) {
+  (void)mot8_dev;
+  if (box.ext[0] <= 0 || box.ext[1] <= 0 || box.ext[2] <= 0) return hipSuccess;
+  Mot m = make_mot(mot8_host);
+  if (g.d == 2) {
+    dim3 grid((box.ext[0] + 255) / 256, box.ext[1]);
+    if (precision == 0)
+      hipLaunchKernelGGL(k_map2d<float>, grid, dim3(256), 0, s, g, (const float*)kref, m, box,
+                         (float*)bk, (float*)bu, full_grid);
+    else
+      hipLaunchKernelGGL(k_map2d<double>, grid, dim3(256), 0, s, g, (const double*)kref, m, box,
+                         (double*)bk, (double*)bu, full_grid);
+  } else {
+    dim3 grid((box.ext[0] + 63) / 64, box.ext[1], (box.ext[2] + MAP_ZC - 1) / MAP_ZC);
+    if (precision == 0)
+      hipLaunchKernelGGL(k_map3d<float>, grid, dim3(64), 0, s, g, (const float*)kref, m, box,
+                         (float*)bk, (float*)bu, full_grid);
+    else
+      hipLaunchKernelGGL(k_map3d<double>, grid, dim3(64), 0, s, g, (const double*)kref, m, box,
+                         (double*)bk, (double*)bu, full_grid);
+  }
+  return hipGetLastError();
+}
+
+int mapadj_blocks(const Geo& g) { return (int)((g.Mtot + MAPADJ_THREADS - 1) / MAPADJ_THREADS); }
+
+hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
+                              const double* mot8_host, const Box& box, const void* bkbar,
+                              const void* bubar, double* kref_bar, int overwrite, double* mpart,
+                              hipStream_t s) {
+  Mot m = make_mot(mot8_host);
+  dim3 grid(mapadj_blocks(g));
+  if (precision == 0)
+    hipLaunchKernelGGL(k_mapadj<float>, grid, dim3(MAPADJ_THREADS), 0, s, g, (const float*)kref,
+                       m, box, (const float*)bkbar, (const float*)bubar, kref_bar, overwrite,
+                       mpart);
+  else
+    hipLaunchKernelGGL(k_mapadj<double>, grid, dim3(MAPADJ_THREADS), 0, s, g,
+                       (const double*)kref, m, box, (const double*)bkbar, (const double*)bubar,
+                       kref_bar, overwrite, mpart);
+  return hipGetLastError();
+}
+
+hipError_t launch_kappa_ref(const Geo& g, int precision, const double* gamma, void* kref,
+                            hipStream_t s) {
+  dim3 grid((unsigned)((g.Mtot + 255) / 256));
+  if (precision == 0)
+    hipLaunchKernelGGL(k_kref<float>, grid, dim3(256), 0, s, g, gamma, (float*)kref);
+  else
+    hipLaunchKernelGGL(k_kref<double>, grid, dim3(256), 0, s, g, gamma, (double*)kref);
+  return hipGetLastError();
+}
+
+hipError_t launch_motion(const Geo& g, const double* chi, const double* psi, double* mot,
+                         hipStream_t s) {
+  dim3 grid((g.nt + 255) / 256, 4);
+  hipLaunchKernelGGL(k_motion_pos, grid, dim3(256), 0, s, g, chi, psi, mot);
+  hipLaunchKernelGGL(k_motion_rate, grid, dim3(256), 0, s, g, mot);
+  return hipGetLastError();
+}
+
+hipError_t launch_boxes(const Geo& g, const double* mot, int* boxes, int* info, hipStream_t s) {
+  (void)info;
+  hipLaunchKernelGGL(k_boxes, dim3((g.nt + 255) / 256), dim3(256), 0, s, g, mot, boxes);
+  return hipGetLastError();
+}
+
+hipError_t launch_objective_final(const Geo& g, const double* opart, int nblk, double* J3,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(256), 0, s, g, opart, nblk, J3);
+  return hipGetLastError();
+}
+
+hipError_t launch_sens(const Geo& g, int precision, const double* gamma, const double* kref_bar,
+                       const double* mpart, int nblk, double* mbar, double* den_t, double* den_w,
+                       double* dgamma, double* dchi, double* dpsi, hipStream_t s) {
+  (void)precision;
+  long long M = 1;
+  for (int a = 0; a < g.d; ++a) M *= g.m[a];
+  if (M > 0)
+    hipLaunchKernelGGL(k_sens_gamma, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, g, gamma,
+                       kref_bar, dgamma);
+  hipLaunchKernelGGL(k_sens_mbar, dim3(g.nt), dim3(64), 0, s, g, mpart, nblk, mbar);
+  // tot buffer follows den_w (nt * 4 doubles) -- see workspace layout
+  double* tot = den_w + g.nt;
+  dim3 grid((g.nt + 255) / 256, 4);
+  hipLaunchKernelGGL(k_sens_tot, grid, dim3(256), 0, s, g, mbar, tot, den_t, den_w);
+  hipLaunchKernelGGL(k_sens_filter, grid, dim3(256), 0, s, g, tot, den_t, den_w, dchi, dpsi);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_parts(const Geo& g, const double* part, int nblk, double* out8,
+                              hipStream_t s) {
+  Geo g1 = g;
+  g1.nt = 1;
+  hipLaunchKernelGGL(k_sens_mbar, dim3(1), dim3(64), 0, s, g1, part, nblk, out8);
+  return hipGetLastError();
+}
+
+hipError_t launch_wall_fixup(const Geo& g, int precision, void* st, hipStream_t s) {
+  dim3 grid((unsigned)((g.N + 255) / 256));
+  if (precision == 0)
+    hipLaunchKernelGGL(k_wall_fixup<float>, grid, dim3(256), 0, s, g, (float*)st);
+  else
+    hipLaunchKernelGGL(k_wall_fixup<double>, grid, dim3(256), 0, s, g, (double*)st);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const long long n = (long long)(bytes / 4);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint32_t*)p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_init(const Geo& g, int precision, void* st, hipStream_t s) {
+  return launch_zero(st, (size_t)(g.d + 1) * g.N * (precision == 0 ? 4 : 8), s);
+}
+
+}  // namespace lks

@@ -1,0 +1,270 @@
+"""Python binding of the MI355X LKS library (``liblks.so``, C ABI in include/lks.h).
+
+Argument marshalling only: every stage of the forward march, the adjoint and
+the sensitivities runs in the library's HIP kernels.  PyTorch provides device
+memory (including the workspace) and the current stream.  If the library has
+not been built this module raises on first use; there is no fallback.
+
+States use the library layout: [d+1][N] of the state dtype, plane 0 holds
+p - 1/3, planes 1..d the velocity.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblks.so")
+
+LKS_OK, LKS_EINVAL, LKS_EDOMAIN, LKS_EUNSTABLE, LKS_EHIP = range(5)
+_NAMES = {0: "LKS_OK", 1: "LKS_EINVAL", 2: "LKS_EDOMAIN", 3: "LKS_EUNSTABLE", 4: "LKS_EHIP"}
+
+
+class LksError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class LksProblem(C.Structure):
+    _fields_ = [
+        ("d", C.c_int32), ("precision", C.c_int32), ("n", C.c_int32 * 3), ("bc", C.c_int32 * 3),
+        ("u_wall", C.c_double * 18), ("nu", C.c_double), ("kappa_max", C.c_double),
+        ("q", C.c_double), ("m", C.c_int32 * 3), ("margin", C.c_int32),
+        ("xg_min", C.c_double * 3), ("xg_max", C.c_double * 3), ("th_min", C.c_double),
+        ("th_max", C.c_double), ("nt", C.c_int32), ("r_t", C.c_int32), ("r_w", C.c_int32),
+        ("tgt_lo", C.c_int32 * 3), ("tgt_hi", C.c_int32 * 3), ("ndir", C.c_double * 3),
+        ("phi", C.c_double), ("ckpt_k", C.c_int32),
+    ]
+
+
+_lib = None
+_VP = C.c_void_p
+
+
+def lib():
+    """Load liblks.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        L.lks_last_error.restype = C.c_char_p
+        L.lks_plan_create.argtypes = [C.POINTER(LksProblem), C.POINTER(_VP), C.POINTER(C.c_size_t)]
+        L.lks_plan_destroy.argtypes = [_VP]
+        L.lks_forward.argtypes = [_VP] * 9
+        L.lks_adjoint.argtypes = [_VP] * 12
+        L.lks_map_design_to_grid.argtypes = [_VP] * 6
+        L.lks_sensitivities.argtypes = [_VP] * 7
+        L.lks_motion.argtypes = [_VP] * 5
+        L.lks_kappa_ref.argtypes = [_VP] * 4
+        L.lks_step.argtypes = [_VP] * 6
+        L.lks_step_adjoint.argtypes = [_VP] * 10
+        L.lks_map_adjoint.argtypes = [_VP] * 8
+        L.lks_map_adjoint_blocks.argtypes = [_VP]
+        L.lks_map_adjoint_blocks.restype = C.c_int32
+        L.lks_profile_enable.argtypes = [C.c_int32]
+        L.lks_profile_read.argtypes = [C.POINTER(C.c_char_p), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_int64), C.c_int32]
+        L.lks_profile_read.restype = C.c_int32
+        L.lks_batch_run.argtypes = [C.c_int32] + [_VP] * 11
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != LKS_OK:
+        raise LksError(status, lib().lks_last_error().decode(errors="replace"))
+
+
+def to_struct(p) -> LksProblem:
+    s = LksProblem()
+    s.d = p.d
+    s.precision = p.precision
+    for a in range(3):
+        s.n[a] = p.n[a] if a < p.d else 1
+        s.bc[a] = p.bc[a] if a < p.d else 0
+        s.m[a] = p.m[a] if a < p.d else 1
+        s.xg_min[a] = p.xg_min[a]
+        s.xg_max[a] = p.xg_max[a]
+        s.tgt_lo[a] = p.tgt_lo[a]
+        s.tgt_hi[a] = p.tgt_hi[a]
+        s.ndir[a] = p.ndir[a]
+    flat = [float(v) for ax in p.u_wall for side in ax for v in side]
+    for k in range(18):
+        s.u_wall[k] = flat[k]
+    s.nu, s.kappa_max, s.q = p.nu, p.kappa_max, p.q
+    s.margin = p.margin
+    s.th_min, s.th_max = p.th_min, p.th_max
+    s.nt, s.r_t, s.r_w = p.nt, p.r_t, p.r_w
+    s.phi = p.phi
+    s.ckpt_k = p.ckpt_k
+    return s
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "expected a contiguous device tensor"
+    return t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Plan:
+    """A validated problem plus its device workspace (allocated by torch)."""
+
+    def __init__(self, problem, device: str = "cuda"):
+        self.problem = problem
+        self.device = torch.device(device)
+        self._s = to_struct(problem)
+        h = _VP()
+        nbytes = C.c_size_t()
+        _check(lib().lks_plan_create(C.byref(self._s), C.byref(h), C.byref(nbytes)))
+        self.handle = h
+        self.workspace_bytes = nbytes.value
+        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        self.dtype = torch.float32 if problem.precision == 0 else torch.float64
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.lks_plan_destroy(h)
+
+    # ----------------------------------------------------------- helpers
+    def _f64(self, a) -> torch.Tensor:
+        return torch.as_tensor(a, dtype=torch.float64, device=self.device).contiguous()
+
+    def _st(self, a) -> torch.Tensor:
+        return torch.as_tensor(a, dtype=self.dtype, device=self.device).contiguous()
+
+    @property
+    def state_size(self) -> int:
+        p = self.problem
+        return (p.d + 1) * p.N
+
+    # -------------------------------------------------------- full path
+    def forward(self, gamma, chi, psi, state0=None, want_final: bool = False):
+        """Forward march; returns (J3 device tensor [J, E, V], final state or None)."""
+        g, c, s = self._f64(gamma), self._f64(chi), self._f64(psi)
+        st0 = None if state0 is None else self._st(state0)
+        fin = torch.empty(self.state_size, dtype=self.dtype, device=self.device) if want_final else None
+        J3 = torch.empty(3, dtype=torch.float64, device=self.device)
+        self._keep = (g, c, s)
+        _check(lib().lks_forward(self.handle, _ptr(g), _ptr(c), _ptr(s), _ptr(st0), _ptr(fin),
+                                 _ptr(self.workspace), _ptr(J3), _stream()))
+        return J3, fin
+
+    def adjoint(self, gamma, chi, psi, dJ=None, adj_terminal=None, want_initial: bool = False):
+        """Discrete adjoint of the preceding forward; returns gradients."""
+        p = self.problem
+        g, c, s = self._f64(gamma), self._f64(chi), self._f64(psi)
+        seed = self._f64([1.0]) if dJ is None else self._f64(dJ).reshape(1)
+        at = None if adj_terminal is None else self._st(adj_terminal)
+        ai = torch.empty(self.state_size, dtype=self.dtype, device=self.device) if want_initial else None
+        dg = torch.empty(p.M, dtype=torch.float64, device=self.device)
+        dc = torch.empty(p.nt * 3, dtype=torch.float64, device=self.device)
+        dp = torch.empty(p.nt, dtype=torch.float64, device=self.device)
+        _check(lib().lks_adjoint(self.handle, _ptr(g), _ptr(c), _ptr(s), _ptr(self.workspace),
+                                 _ptr(seed), _ptr(at), _ptr(ai), _ptr(dg), _ptr(dc), _ptr(dp),
+                                 _stream()))
+        return {"dgamma": dg, "dchi": dc.reshape(p.nt, 3), "dpsi": dp, "adj_initial": ai}
+
+    def sensitivities(self, gamma):
+        p = self.problem
+        g = self._f64(gamma)
+        dg = torch.empty(p.M, dtype=torch.float64, device=self.device)
+        dc = torch.empty(p.nt * 3, dtype=torch.float64, device=self.device)
+        dp = torch.empty(p.nt, dtype=torch.float64, device=self.device)
+        _check(lib().lks_sensitivities(self.handle, _ptr(g), _ptr(self.workspace), _ptr(dg),
+                                       _ptr(dc), _ptr(dp), _stream()))
+        return dg, dc.reshape(p.nt, 3), dp
+
+    # ---------------------------------------------------- single stages
+    def motion(self, chi, psi):
+        c, s = self._f64(chi), self._f64(psi)
+        out = torch.empty(self.problem.nt * 8, dtype=torch.float64, device=self.device)
+        _check(lib().lks_motion(self.handle, _ptr(c), _ptr(s), _ptr(out), _stream()))
+        return out.reshape(self.problem.nt, 8)
+
+    def kappa_ref(self, gamma):
+        g = self._f64(gamma)
+        out = torch.empty(self.problem.Mtot, dtype=self.dtype, device=self.device)
+        _check(lib().lks_kappa_ref(self.handle, _ptr(g), _ptr(out), _stream()))
+        return out
+
+    def map(self, kref, motion8):
+        p = self.problem
+        kr, m = self._st(kref), self._f64(motion8)
+        k = torch.empty(p.N, dtype=self.dtype, device=self.device)
+        us = torch.empty(p.d * p.N, dtype=self.dtype, device=self.device)
+        _check(lib().lks_map_design_to_grid(self.handle, _ptr(kr), _ptr(m), _ptr(k), _ptr(us),
+                                            _stream()))
+        return k, us
+
+    def step(self, state, kappa, us):
+        si, k, u = self._st(state), self._st(kappa), self._st(us)
+        out = torch.empty_like(si)
+        _check(lib().lks_step(self.handle, _ptr(si), _ptr(k), _ptr(u), _ptr(out), _stream()))
+        return out
+
+    def step_adjoint(self, state_in, state_out, kappa, us, lam):
+        p = self.problem
+        si, so, k, u, l = (self._st(v) for v in (state_in, state_out, kappa, us, lam))
+        lp = torch.empty_like(si)
+        kb = torch.empty(p.N, dtype=self.dtype, device=self.device)
+        ub = torch.empty(p.d * p.N, dtype=self.dtype, device=self.device)
+        _check(lib().lks_step_adjoint(self.handle, _ptr(si), _ptr(so), _ptr(k), _ptr(u), _ptr(l),
+                                      _ptr(lp), _ptr(kb), _ptr(ub), _stream()))
+        return lp, kb, ub
+
+    def map_adjoint(self, kref, motion8, kbar, usbar):
+        p = self.problem
+        kr, m, kb, ub = self._st(kref), self._f64(motion8), self._st(kbar), self._st(usbar)
+        nblk = lib().lks_map_adjoint_blocks(self.handle)
+        out = torch.empty(p.Mtot, dtype=torch.float64, device=self.device)
+        mb = torch.empty(8 * (nblk + 1), dtype=torch.float64, device=self.device)
+        _check(lib().lks_map_adjoint(self.handle, _ptr(kr), _ptr(m), _ptr(kb), _ptr(ub), _ptr(out),
+                                     _ptr(mb), _stream()))
+        return out, mb[:8].clone()
+
+
+class LKSObjective(torch.autograd.Function):
+    """J1(gamma, chi, psi) with the hand-written discrete adjoint as backward.
+
+    forward runs the checkpointed forward march (lks_forward); backward runs
+    lks_adjoint, which recomputes each K-step segment from its checkpoint."""
+
+    @staticmethod
+    def forward(ctx, gamma, chi, psi, plan: Plan):
+        J3, _ = plan.forward(gamma, chi, psi)
+        ctx.plan = plan
+        ctx.save_for_backward(gamma, chi, psi)
+        return J3[0].clone()
+
+    @staticmethod
+    def backward(ctx, gJ):
+        gamma, chi, psi = ctx.saved_tensors
+        plan = ctx.plan
+        g = plan.adjoint(gamma, chi, psi, dJ=gJ.detach().reshape(1).to(torch.float64))
+        p = plan.problem
+        return (g["dgamma"].reshape(gamma.shape).to(gamma.dtype),
+                g["dchi"].reshape(chi.shape).to(chi.dtype),
+                g["dpsi"].reshape(psi.shape).to(psi.dtype), None)
+
+
+def profile_enable(on: bool = True):
+    _check(lib().lks_profile_enable(1 if on else 0))
+
+
+def profile_read(cap: int = 32):
+    names = (C.c_char_p * cap)()
+    tot = (C.c_double * cap)()
+    cnt = (C.c_int64 * cap)()
+    k = lib().lks_profile_read(names, tot, cnt, cap)
+    return {names[i].decode(): (tot[i], cnt[i]) for i in range(k)}

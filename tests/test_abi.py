@@ -1,0 +1,69 @@
+"""Host-only checks of the C ABI: the library loads, exports every function
+include/lks.h declares, and validates problems without touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2608_01071_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lks.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lks_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2608_01071_amd import lks
+    return lks.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in include/lks.h but not exported"
+
+
+def test_plan_validation_and_workspace(L):
+    from paper_2608_01071_amd import lks
+    p, *_ = W.c1()
+    h = C.c_void_p()
+    nb = C.c_size_t()
+    s = lks.to_struct(p)
+    assert L.lks_plan_create(C.byref(s), C.byref(h), C.byref(nb)) == 0
+    assert nb.value > 0 and nb.value % 256 == 0
+    # checkpoint storage grows as K shrinks
+    s2 = lks.to_struct(p.replace(ckpt_k=10))
+    h2 = C.c_void_p()
+    nb2 = C.c_size_t()
+    assert L.lks_plan_create(C.byref(s2), C.byref(h2), C.byref(nb2)) == 0
+    assert nb2.value != nb.value
+    L.lks_plan_destroy(h)
+    L.lks_plan_destroy(h2)
+    bad = [p.replace(d=4), p.replace(n=(64, 3, 1)), p.replace(nt=0), p.replace(r_t=0),
+           p.replace(ckpt_k=500), p.replace(precision=2), p.replace(q=0.0)]
+    p3, *_ = W.make_3d(16, 4, 5, 2, nu=0.1, seed=0)
+    bad.append(p3.replace(bc=(1, 1, 1)))
+    for b in bad:
+        h3 = C.c_void_p()
+        rc = L.lks_plan_create(C.byref(lks.to_struct(b)), C.byref(h3), C.byref(nb))
+        assert rc == lks.LKS_EINVAL, b
+        assert len(L.lks_last_error()) > 0
+
+
+def test_null_arguments_rejected_before_any_launch(L):
+    from paper_2608_01071_amd import lks
+    p, *_ = W.c1()
+    h = C.c_void_p()
+    nb = C.c_size_t()
+    assert L.lks_plan_create(C.byref(lks.to_struct(p)), C.byref(h), C.byref(nb)) == 0
+    assert L.lks_forward(h, None, None, None, None, None, None, None, None) == lks.LKS_EINVAL
+    assert L.lks_adjoint(h, *([None] * 11)) == lks.LKS_EINVAL
+    assert L.lks_step(h, None, None, None, None, None) == lks.LKS_EINVAL
+    L.lks_plan_destroy(h)

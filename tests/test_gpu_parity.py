@@ -1,0 +1,375 @@
+"""GPU parity: every stage of the HIP path against the CPU oracle.
+
+All calls go through the C ABI (ctypes binding).  Inputs are seeded; the
+oracle works in FP64 on the same arrays.  Tolerances:
+  * FP64 state: relative 1e-11 of the field's max magnitude per stage, 1e-10
+    for whole runs (only the summation order differs);
+  * FP32 state with FP64 sums: objective relative error <= 1e-5, gradient
+    relative L2 error <= 1e-3 (the targets of the precision extension);
+    single stages <= 2e-5 of the field's max magnitude.
+Grids are ragged (not multiples of the 32x8 tile) and include the sizes
+n = 2 (mod tile) on wall axes, where the tile grid is shifted by one node.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2608_01071_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+THIRD = 1.0 / 3.0
+
+
+def lk():
+    from paper_2608_01071_amd import lks
+    return lks
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def l2err(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def cpu(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def prob2d(n=(45, 21), prec=1, **kw):
+    base = dict(d=2, n=(n[0], n[1], 1), bc=(0, 1, 0), nu=0.08, kappa_max=60.0, q=0.1,
+                m=(8, 6, 1), margin=4, xg_min=(n[0] / 2 - 1.5, n[1] / 2 - 1.0, 0.0),
+                xg_max=(n[0] / 2 + 1.5, n[1] / 2 + 1.0, 0.0), th_min=-0.3, th_max=0.3,
+                nt=12, r_t=3, r_w=3, tgt_lo=(0, 1, 0), tgt_hi=(1, n[1] - 1, 1),
+                ndir=(1.0, 0.0, 0.0), phi=0.2, precision=prec, ckpt_k=5)
+    base.update(kw)
+    return W.Problem(**base)
+
+
+def prob3d(n=(34, 18, 20), prec=1, **kw):
+    base = dict(d=3, n=n, bc=(1, 1, 0), nu=0.08, kappa_max=40.0, q=0.1, m=(6, 4, 5), margin=3,
+                xg_min=(n[0] / 2 - 1.0, n[1] / 2 - 0.5, n[2] / 2 - 1.0),
+                xg_max=(n[0] / 2 + 1.0, n[1] / 2 + 0.5, n[2] / 2 + 1.0), th_min=-0.3,
+                th_max=0.3, nt=6, r_t=2, r_w=2, tgt_lo=(4, 4, 2), tgt_hi=(30, 14, 5),
+                ndir=(0.0, 0.0, 1.0), phi=0.1, precision=prec, ckpt_k=4)
+    base.update(kw)
+    return W.Problem(**base)
+
+
+def rand_state(p, seed, amp=0.05):
+    rng = np.random.default_rng(seed)
+    s = np.zeros((p.d + 1) * p.N)
+    s[: p.N] = THIRD + 0.01 * rng.standard_normal(p.N)
+    s[p.N:] = amp * rng.standard_normal(p.d * p.N)
+    return s
+
+
+def gpu_state(s, p):
+    g = s.copy()
+    g[: p.N] -= THIRD
+    return g
+
+
+def oracle_state(g, p):
+    s = np.asarray(g, dtype=np.float64).copy()
+    s[: p.N] += THIRD
+    return s
+
+
+def rand_inputs(p, seed):
+    rng = np.random.default_rng(seed)
+    gamma = rng.uniform(0.05, 0.95, size=p.M)
+    chi = rng.uniform(0.3, 0.7, size=(p.nt, 3))
+    psi = rng.uniform(0.3, 0.7, size=p.nt)
+    return gamma, chi, psi
+
+
+PROBS = {
+    "2d_walls_y": lambda prec: prob2d((45, 21), prec),
+    "2d_shift_y": lambda prec: prob2d((37, 18), prec),
+    "2d_walls_xy_shift_x": lambda prec: prob2d((34, 19), prec, bc=(1, 1, 0), tgt_lo=(1, 1, 0),
+                                                tgt_hi=(2, 18, 1)),
+    "3d_shift_xy": lambda prec: prob3d((34, 18, 20), prec),
+    "3d_plain": lambda prec: prob3d((29, 23, 9), prec, tgt_lo=(3, 3, 1), tgt_hi=(26, 20, 3)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PROBS))
+@pytest.mark.parametrize("prec", [1, 0])
+def test_motion_and_kappa_ref(orc, name, prec):
+    p = PROBS[name](prec)
+    plan = lk().Plan(p)
+    gamma, chi, psi = rand_inputs(p, 1)
+    m = cpu(plan.motion(chi, psi))
+    assert relerr(m, orc.motion(p, chi, psi)) < 1e-14
+    k = cpu(plan.kappa_ref(gamma))
+    tol = 1e-15 if prec == 1 else 1e-7
+    assert relerr(k, orc.kappa_ref(p, gamma)) < tol
+
+
+@pytest.mark.parametrize("name", sorted(PROBS))
+@pytest.mark.parametrize("prec", [1, 0])
+def test_map(orc, name, prec):
+    p = PROBS[name](prec)
+    plan = lk().Plan(p)
+    rng = np.random.default_rng(2)
+    kref = rng.uniform(0, 50, size=p.Mtot)
+    tol = 1e-12 if prec == 1 else 2e-6
+    for th in (0.0, 0.31, -1.2, math.pi / 2):
+        mot = np.array([p.n[0] / 2 + 0.37, p.n[1] / 2 - 0.21, (p.n[2] / 2 + 0.13) if p.d == 3 else 0,
+                        0.02, -0.01, 0.005 if p.d == 3 else 0, th, 0.003])
+        k, us = plan.map(kref, mot)
+        ko, uo = orc.map_fields(p, kref, mot)
+        assert relerr(cpu(k), ko) < tol, th
+        assert relerr(cpu(us), uo) < tol, th
+
+
+def test_map_wraps_periodic_seam(orc):
+    """A body straddling the periodic seam maps its support across it."""
+    p = prob2d((45, 21), 1)
+    plan = lk().Plan(p)
+    kref = np.random.default_rng(3).uniform(0, 5, size=p.Mtot)
+    mot = np.array([1.3, 10.2, 0, 0.01, 0.0, 0, 0.4, 0.002])
+    k, us = plan.map(kref, mot)
+    ko, uo = orc.map_fields(p, kref, mot)
+    assert relerr(cpu(k), ko) < 1e-12 and relerr(cpu(us), uo) < 1e-12
+    assert np.abs(ko.reshape(21, 45)[:, -3:]).max() > 0
+
+
+@pytest.mark.parametrize("name", sorted(PROBS))
+@pytest.mark.parametrize("prec", [1, 0])
+def test_step(orc, name, prec):
+    p = PROBS[name](prec)
+    plan = lk().Plan(p)
+    rng = np.random.default_rng(4)
+    s = rand_state(p, 5)
+    kap = rng.uniform(0, 30, size=p.N)
+    us = 0.05 * rng.standard_normal(p.d * p.N)
+    out = cpu(plan.step(gpu_state(s, p), kap, us))
+    ref = orc.step(p, s, kap, us)
+    tol = 1e-13 if prec == 1 else 2e-6
+    # pressure offset compared as p - 1/3, velocity as is
+    assert relerr(out[: p.N], ref[: p.N] - THIRD) < (1e-11 if prec == 1 else 2e-5)
+    assert relerr(out[p.N:], ref[p.N:]) < tol
+
+
+@pytest.mark.parametrize("name", sorted(PROBS))
+@pytest.mark.parametrize("prec", [1, 0])
+def test_step_adjoint(orc, name, prec):
+    p = PROBS[name](prec)
+    plan = lk().Plan(p)
+    rng = np.random.default_rng(6)
+    s_in = rand_state(p, 7)
+    kap = rng.uniform(0, 30, size=p.N)
+    us = 0.05 * rng.standard_normal(p.d * p.N)
+    s_out = orc.step(p, s_in, kap, us)
+    lam = rng.standard_normal((p.d + 1) * p.N)
+    lp, kb, ub = plan.step_adjoint(gpu_state(s_in, p), gpu_state(s_out, p), kap, us, lam)
+    rlp, rkb, rub = orc.step_adjoint(p, s_in, s_out, kap, us, lam)
+    tol = 1e-12 if prec == 1 else 2e-5
+    assert relerr(cpu(lp), rlp) < tol
+    assert relerr(cpu(kb), rkb) < tol
+    assert relerr(cpu(ub), rub) < tol
+
+
+@pytest.mark.parametrize("name", sorted(PROBS))
+@pytest.mark.parametrize("prec", [1, 0])
+def test_map_adjoint(orc, name, prec):
+    p = PROBS[name](prec)
+    plan = lk().Plan(p)
+    rng = np.random.default_rng(8)
+    kref = rng.uniform(0, 50, size=p.Mtot)
+    kbar = rng.standard_normal(p.N)
+    usbar = rng.standard_normal(p.d * p.N)
+    # wall nodes carry no body adjoint (the step transpose zeroes them)
+    n = p.n
+    idx = np.arange(p.N)
+    x, y, z = idx % n[0], (idx // n[0]) % n[1], idx // (n[0] * n[1])
+    wall = np.zeros(p.N, bool)
+    for a, c in enumerate((x, y, z)[: p.d]):
+        if p.bc[a] == 1:
+            wall |= (c == 0) | (c == n[a] - 1)
+    kbar[wall] = 0
+    usbar.reshape(p.d, p.N)[:, wall] = 0
+    tol = 1e-12 if prec == 1 else 2e-5
+    for th in (0.0, 0.41):
+        mot = np.array([p.n[0] / 2 - 0.3, p.n[1] / 2 + 0.2, (p.n[2] / 2 - 0.4) if p.d == 3 else 0,
+                        0.01, 0.02, 0.01 if p.d == 3 else 0, th, 0.004])
+        kb, mb = plan.map_adjoint(kref, mot, kbar, usbar)
+        rkb, rmb = orc.map_adjoint(p, kref, mot, kbar, usbar)
+        assert relerr(cpu(kb), rkb) < tol
+        assert relerr(cpu(mb), rmb) < (1e-11 if prec == 1 else 1e-4)
+
+
+@pytest.mark.parametrize("name", sorted(PROBS))
+@pytest.mark.parametrize("prec", [1, 0])
+def test_forward_adjoint_run(orc, name, prec):
+    """Whole runs (checkpoint K < nt, ragged segment) vs the oracle."""
+    p = PROBS[name](prec)
+    plan = lk().Plan(p)
+    gamma, chi, psi = rand_inputs(p, 9)
+    J3, fin = plan.forward(gamma, chi, psi, want_final=True)
+    g = plan.adjoint(gamma, chi, psi, want_initial=True)
+    ref = orc.forward(p, gamma, chi, psi)
+    adj = orc.adjoint(p, gamma, chi, psi)
+    J = cpu(J3)
+    if prec == 1:
+        assert abs(J[0] - ref["J"]) <= 1e-10 * abs(ref["J"])
+        assert relerr(oracle_state(cpu(fin), p), ref["final"]) < 1e-10
+        for k in ("dgamma", "dchi", "dpsi"):
+            assert l2err(cpu(g[k]), adj[k]) < 1e-9, k
+        assert relerr(cpu(g["adj_initial"]), adj["adj_initial"]) < 1e-9
+    else:
+        assert abs(J[0] - ref["J"]) <= 1e-5 * abs(ref["J"])
+        for k in ("dgamma", "dchi", "dpsi"):
+            assert l2err(cpu(g[k]), adj[k]) < 1e-3, k
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_c1_forward_adjoint(orc, prec):
+    """The 64x64 / 200-step workload (D2Q9, design 32x32, x/y/theta motion)."""
+    p, gamma, chi, psi = W.c1(precision=prec)
+    p = p.replace(ckpt_k=50)
+    plan = lk().Plan(p)
+    J3, _ = plan.forward(gamma, chi, psi)
+    g = plan.adjoint(gamma, chi, psi)
+    ref = orc.forward(p, gamma, chi, psi)
+    adj = orc.adjoint(p, gamma, chi, psi)
+    J = cpu(J3)[0]
+    if prec == 1:
+        assert abs(J - ref["J"]) <= 1e-10 * abs(ref["J"])
+        tol = 1e-8
+    else:
+        assert abs(J - ref["J"]) <= 1e-5 * abs(ref["J"])
+        tol = 1e-3
+    for k in ("dgamma", "dchi", "dpsi"):
+        assert l2err(cpu(g[k]), adj[k]) < tol, k
+
+
+def test_checkpoint_interval_does_not_change_gradients(orc):
+    """K in {1, 3, 7, nt} and full tape give bit-identical gradients."""
+    p0 = prob2d((45, 21), 0, nt=14)
+    gamma, chi, psi = rand_inputs(p0, 10)
+    outs = []
+    for K in (1, 3, 7, 14):
+        plan = lk().Plan(p0.replace(ckpt_k=K))
+        J3, _ = plan.forward(gamma, chi, psi)
+        g = plan.adjoint(gamma, chi, psi)
+        outs.append((cpu(J3), cpu(g["dgamma"]), cpu(g["dchi"]), cpu(g["dpsi"])))
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+
+
+def test_periodic_approximation_state_carry(orc):
+    """state0 / state_final and adj_terminal / adj_initial round trip
+    (Sec. 3.3): a second run started from the first run's final state
+    matches the oracle started from the same state."""
+    p = prob2d((45, 21), 1)
+    plan = lk().Plan(p)
+    gamma, chi, psi = rand_inputs(p, 11)
+    _, fin = plan.forward(gamma, chi, psi, want_final=True)
+    s1 = oracle_state(cpu(fin), p)
+    J3, fin2 = plan.forward(gamma, chi, psi, state0=fin, want_final=True)
+    rng = np.random.default_rng(12)
+    aterm = 0.01 * rng.standard_normal((p.d + 1) * p.N)
+    g = plan.adjoint(gamma, chi, psi, adj_terminal=aterm, want_initial=True)
+    ref = orc.forward(p, gamma, chi, psi, state0=s1)
+    adj = orc.adjoint(p, gamma, chi, psi, state0=s1, adj_terminal=aterm)
+    assert abs(cpu(J3)[0] - ref["J"]) <= 1e-10 * abs(ref["J"])
+    assert relerr(oracle_state(cpu(fin2), p), ref["final"]) < 1e-10
+    assert relerr(cpu(g["adj_initial"]), adj["adj_initial"]) < 1e-9
+    assert l2err(cpu(g["dgamma"]), adj["dgamma"]) < 1e-9
+
+
+def test_edge_cases(orc):
+    """Empty target (J = 0, zero gradients), no body (kappa_max = 0),
+    a single step, and seed scaling."""
+    lks = lk()
+    p = prob2d((45, 21), 1, tgt_lo=(0, 0, 0), tgt_hi=(0, 21, 1))
+    plan = lks.Plan(p)
+    gamma, chi, psi = rand_inputs(p, 13)
+    J3, _ = plan.forward(gamma, chi, psi)
+    g = plan.adjoint(gamma, chi, psi)
+    assert np.all(cpu(J3) == 0) and np.all(cpu(g["dgamma"]) == 0) and np.all(cpu(g["dpsi"]) == 0)
+    p = prob2d((45, 21), 1, kappa_max=0.0)
+    plan = lks.Plan(p)
+    J3, _ = plan.forward(gamma, chi, psi)
+    assert abs(cpu(J3)[0]) == 0.0
+    p = prob2d((45, 21), 1, nt=1, ckpt_k=1)
+    plan = lks.Plan(p)
+    gamma, chi, psi = rand_inputs(p, 14)
+    s0 = rand_state(p, 15)
+    J3, _ = plan.forward(gamma, chi, psi, state0=gpu_state(s0, p))
+    g = plan.adjoint(gamma, chi, psi, dJ=[-3.0])
+    ref = orc.forward(p, gamma, chi, psi, state0=s0)
+    adj = orc.adjoint(p, gamma, chi, psi, state0=s0, dJ=-3.0)
+    assert abs(cpu(J3)[0] - ref["J"]) <= 1e-11 * abs(ref["J"])
+    assert l2err(cpu(g["dgamma"]), adj["dgamma"]) < 1e-10
+
+
+def test_domain_error_before_march():
+    """A body whose support reaches a wall node is rejected (LKS_EDOMAIN)."""
+    lks = lk()
+    p = prob2d((45, 21), 1, xg_min=(22.0, 2.0, 0.0), xg_max=(23.0, 3.0, 0.0))
+    plan = lks.Plan(p)
+    gamma, chi, psi = rand_inputs(p, 16)
+    with pytest.raises(lks.LksError) as e:
+        plan.forward(gamma, chi, psi)
+    assert e.value.status == lks.LKS_EDOMAIN
+
+
+def test_instability_reported():
+    """|u| >= 0.5 (or a non-finite value) anywhere in the march is reported as
+    LKS_EUNSTABLE.  Forced from the host: a uniform initial flow at 0.6 is an
+    exact solution, so every step carries it and trips the check."""
+    lks = lk()
+    p = prob2d((45, 21), 1, bc=(0, 0, 0), kappa_max=0.0, nt=3, ckpt_k=3)
+    plan = lks.Plan(p)
+    gamma, chi, psi = rand_inputs(p, 16)
+    s0 = np.zeros((p.d + 1) * p.N)
+    s0[p.N:2 * p.N] = 0.6
+    with pytest.raises(lks.LksError) as e:
+        plan.forward(gamma, chi, psi, state0=s0)
+    assert e.value.status == lks.LKS_EUNSTABLE
+
+
+def test_autograd_function(orc):
+    """LKSObjective: torch.autograd backward equals the oracle adjoint."""
+    lks = lk()
+    p = prob2d((45, 21), 1)
+    plan = lks.Plan(p)
+    gamma, chi, psi = rand_inputs(p, 17)
+    tg = torch.tensor(gamma, device="cuda", requires_grad=True)
+    tc = torch.tensor(chi, device="cuda", requires_grad=True)
+    tp = torch.tensor(psi, device="cuda", requires_grad=True)
+    J = lks.LKSObjective.apply(tg, tc, tp, plan)
+    (2.0 * J).backward()
+    adj = orc.adjoint(p, gamma, chi, psi, dJ=2.0)
+    assert l2err(cpu(tg.grad), adj["dgamma"]) < 1e-9
+    assert l2err(cpu(tc.grad), adj["dchi"]) < 1e-9
+    assert l2err(cpu(tp.grad), adj["dpsi"]) < 1e-9
+
+
+def test_reproducible_bitwise():
+    """Two identical runs give bit-identical objective and gradients."""
+    lks = lk()
+    p = prob3d((34, 18, 20), 0)
+    plan = lks.Plan(p)
+    gamma, chi, psi = rand_inputs(p, 18)
+    res = []
+    for _ in range(2):
+        J3, _ = plan.forward(gamma, chi, psi)
+        g = plan.adjoint(gamma, chi, psi)
+        res.append((cpu(J3), cpu(g["dgamma"]), cpu(g["dchi"])))
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
