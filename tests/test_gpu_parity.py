@@ -99,7 +99,7 @@ PROBS = {
     "2d_walls_xy_shift_x": lambda prec: prob2d((34, 19), prec, bc=(1, 1, 0), tgt_lo=(1, 1, 0),
                                                 tgt_hi=(2, 18, 1)),
     "3d_shift_xy": lambda prec: prob3d((34, 18, 20), prec),
-    "3d_plain": lambda prec: prob3d((29, 23, 9), prec, tgt_lo=(3, 3, 1), tgt_hi=(26, 20, 3)),
+    "3d_plain": lambda prec: prob3d((29, 23, 17), prec, tgt_lo=(3, 3, 1), tgt_hi=(26, 20, 3)),
 }
 
 
