@@ -49,7 +49,8 @@ def prob2d(n=(45, 21), prec=1, **kw):
     base = dict(d=2, n=(n[0], n[1], 1), bc=(0, 1, 0), nu=0.08, kappa_max=60.0, q=0.1,
                 m=(8, 6, 1), margin=4, xg_min=(n[0] / 2 - 1.5, n[1] / 2 - 1.0, 0.0),
                 xg_max=(n[0] / 2 + 1.5, n[1] / 2 + 1.0, 0.0), th_min=-0.3, th_max=0.3,
-                nt=12, r_t=3, r_w=3, tgt_lo=(0, 1, 0), tgt_hi=(1, n[1] - 1, 1),
+                nt=12, r_t=3, r_w=3, tgt_lo=(n[0] // 2 - 2, 1, 0),
+                tgt_hi=(n[0] // 2 + 2, n[1] - 1, 1),
                 ndir=(1.0, 0.0, 0.0), phi=0.2, precision=prec, ckpt_k=5)
     base.update(kw)
     return W.Problem(**base)
@@ -96,8 +97,8 @@ def rand_inputs(p, seed):
 PROBS = {
     "2d_walls_y": lambda prec: prob2d((45, 21), prec),
     "2d_shift_y": lambda prec: prob2d((37, 18), prec),
-    "2d_walls_xy_shift_x": lambda prec: prob2d((34, 19), prec, bc=(1, 1, 0), tgt_lo=(1, 1, 0),
-                                                tgt_hi=(2, 18, 1)),
+    "2d_walls_xy_shift_x": lambda prec: prob2d((34, 19), prec, bc=(1, 1, 0), tgt_lo=(14, 0, 0),
+                                                tgt_hi=(20, 19, 1)),
     "3d_shift_xy": lambda prec: prob3d((34, 18, 20), prec),
     "3d_plain": lambda prec: prob3d((29, 23, 17), prec, tgt_lo=(3, 3, 1), tgt_hi=(26, 20, 3)),
 }
