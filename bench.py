@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark of the LKS + Brinkman forward + adjoint hot path on one MI355X.
+
+Workload: D3Q15, 128^3 analysis grid, 64^3 design grid (+4 margin), 5000 time
+steps, body rotating about z (one revolution) with a small translation,
+FP32 state with FP64 objective / sensitivity sums, checkpoint every 100 steps.
+One benchmark "step" is a whole optimisation-iteration pass: lks_forward
+(5000 steps) followed by lks_adjoint (segment recomputation + 5000 reverse
+steps + sensitivities), on synthetic seeded inputs resident in HBM.
+
+value = forward+adjoint MLUPS = N * nt / (time per pass) / 1e6.
+
+Also reported: forward-only MLUPS, the roofline object of the dominant kernel
+(per-kernel HIP event timing of one extra pass), the FP64 "plain form" run of
+the same workload (speedup and the FP32 path's errors against it), and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("forward+adjoint MLUPS & HBM GB/s fraction, D3Q15 128^3, "
+          "FP32 vs FP64 at stated grad err")
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_per_node(kind: str, d: int, s: int) -> float:
+    """Bytes per node one launch of the kernel must move (body fields and
+    target-box reads excluded; they touch a fraction of the nodes).
+    fwd_step: read (p, u) + write (p, u) = 2 (d+1) s.
+    adj_step: read lambda + write lambda + read u^(n-1) = (2 (d+1) + d) s."""
+    if kind == "fwd_step":
+        return 2 * (d + 1) * s
+    if kind == "adj_step":
+        return (2 * (d + 1) + d) * s
+    raise ValueError(kind)
+
+
+def run_pass(plan, g, c, s, seed):
+    import torch
+    t0 = time.perf_counter()
+    J3, _ = plan.forward(g, c, s)          # synchronises at its end (instability check)
+    t1 = time.perf_counter()
+    grads = plan.adjoint(g, c, s, dJ=seed)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return J3, grads, t1 - t0, t2 - t1
+
+
+def cpu_baseline(nt_sample: int):
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2608_01071_amd import workloads as W
+    p, gamma, chi, psi = W.c4(nt=nt_sample)
+    O.lib()
+    t0 = time.perf_counter()
+    O.adjoint(p, gamma, chi, psi)           # includes its own forward march
+    dt = time.perf_counter() - t0
+    return {"value": p.N * nt_sample / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"D3Q15 128^3, 64^3 design, first {nt_sample} of 5000 steps, "
+                      f"forward + discrete adjoint + sensitivities, FP64, single thread "
+                      f"({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nt", type=int, default=5000, help="time steps (the workload uses 5000)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain-form run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU; multi-GPU sharding is not "
+              "implemented (see the sharding design notes).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2608_01071_amd import lks, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    p, gamma, chi, psi = W.c4(precision=0, nt=args.nt)
+    plan = lks.Plan(p)
+    dev = torch.device("cuda")
+    g = torch.tensor(gamma, dtype=torch.float64, device=dev).contiguous()
+    c = torch.tensor(chi, dtype=torch.float64, device=dev).contiguous()
+    s = torch.tensor(psi, dtype=torch.float64, device=dev).contiguous()
+    seed = torch.ones(1, dtype=torch.float64, device=dev)
+    print(f"[bench] workload D3Q15 {p.n} design {p.m} nt={p.nt} K={p.ckpt_k} "
+          f"workspace {plan.workspace_bytes / 2**30:.2f} GiB", file=sys.stderr, flush=True)
+
+    for w in range(args.warmup):
+        _, _, tf, ta = run_pass(plan, g, c, s, seed)
+        print(f"[bench] warmup {w}: fwd {tf:.3f}s adj {ta:.3f}s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    tf_sum = ta_sum = 0.0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        J3, grads, tf, ta = run_pass(plan, g, c, s, seed)
+        tf_sum += tf
+        ta_sum += ta
+        print(f"[bench] step {k}: fwd {tf:.3f}s adj {ta:.3f}s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    N, nt = p.N, p.nt
+    value = N * nt / (elapsed / args.steps) / 1e6
+    fwd_mlups = N * nt / (tf_sum / args.steps) / 1e6
+    J32 = J3.cpu().numpy().copy()
+    g32 = {k: v.cpu().numpy().copy() for k, v in grads.items() if v is not None}
+
+    # per-kernel event timing of one more pass (the dominant kernel's roofline)
+    roofline = None
+    kernels = {}
+    if not args.no_profile:
+        lks.profile_enable(True)
+        run_pass(plan, g, c, s, seed)
+        torch.cuda.synchronize()
+        prof = lks.profile_read()
+        lks.profile_enable(False)
+        kernels = {k: {"total_ms": v[0], "launches": v[1], "avg_us": 1e3 * v[0] / max(v[1], 1)}
+                   for k, v in prof.items()}
+        dom = max(("fwd_step", "adj_step"), key=lambda k: prof.get(k, (0, 0))[0])
+        tot_ms, cnt = prof[dom]
+        avg_s = tot_ms / 1e3 / cnt
+        bpn = algorithmic_bytes_per_node(dom, p.d, 4)
+        achieved = N * bpn / avg_s / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None, "bytes_per_node": bpn, "avg_launch_us": round(avg_s * 1e6, 2)}
+
+    fp64 = None
+    if not args.no_fp64:
+        p64 = p.replace(precision=1)
+        plan64 = lks.Plan(p64)
+        run_pass(plan64, g, c, s, seed)  # warm-up
+        J3d, gd, tf64, ta64 = run_pass(plan64, g, c, s, seed)
+        J64 = J3d.cpu().numpy()
+        rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+        fp64 = {"ms_per_step": round((tf64 + ta64) * 1e3, 2),
+                "value": round(N * nt / (tf64 + ta64) / 1e6, 2),
+                "speedup_fp32": round((tf64 + ta64) / (elapsed / args.steps), 3),
+                "fp32_err": {"J": float(abs(J32[0] - J64[0]) / max(abs(J64[0]), 1e-300)),
+                             "dgamma": rel(g32["dgamma"], gd["dgamma"].cpu().numpy()),
+                             "dchi": rel(g32["dchi"], gd["dchi"].cpu().numpy()),
+                             "dpsi": rel(g32["dpsi"], gd["dpsi"].cpu().numpy())}}
+        del plan64
+        torch.cuda.empty_cache()
+
+    cpu = None if args.no_cpu else cpu_baseline(args.cpu_steps)
+
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "D3Q15 LKS 128^3, 64^3 design, 5000 steps, z-rotation, "
+                               "FP32 state / FP64 sums, forward+adjoint, checkpoint K=100",
+                   "nt": nt, "nodes": N, "ckpt_k": p.ckpt_k},
+        "forward_mlups": round(fwd_mlups, 2),
+        "J": float(J32[0]),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp64_plain": fp64,
+        "kernels": kernels,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
