@@ -99,7 +99,7 @@ struct lks_plan {
   Box bmax;     // strides and volume of the body buffers
   // workspace offsets (bytes)
   size_t o_mot, o_box, o_kref, o_flags, o_J3, o_opart, o_ck, o_pp, o_tape, o_body, o_badj, o_lam,
-      o_krefbar, o_mpart, o_mbar, o_den, total;
+      o_krefbar, o_mpart, o_mbar, o_den, o_kz, total;
   // host copies made by the forward
   std::vector<int> boxes;
   std::vector<double> mot;
@@ -184,8 +184,8 @@ lks_status map_for_step(lks_plan* P, void* ws, int n, hipStream_t s) {
   void* bk = wsp(ws, P->o_body);
   void* bu = wsp(ws, P->o_body) + P->bmax.vol * P->es;
   Scope sc("map", s);
-  HIPCHK(launch_map(P->g, P->prec, wsp(ws, P->o_kref), nullptr, &P->mot[(size_t)(n - 1) * 8],
-                    box, bk, bu, 0, s));
+  HIPCHK(launch_map(P->g, P->prec, wsp(ws, P->o_kref), wsp(ws, P->o_kz), P->bmax.ext[2],
+                    &P->mot[(size_t)(n - 1) * 8], box, bk, bu, 0, s));
   return LKS_OK;
 }
 
@@ -400,6 +400,7 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   P->o_mpart = take((size_t)g.nt * P->nblk_map * 8 * sizeof(double));
   P->o_mbar = take((size_t)g.nt * 8 * sizeof(double));
   P->o_den = take((size_t)g.nt * 6 * sizeof(double));
+  P->o_kz = take(kz_bytes(g, P->bmax.ext[2], P->prec));
   P->total = off;
   *out = P;
   if (workspace_bytes) *workspace_bytes = P->total;
@@ -503,15 +504,17 @@ static lks_status host_box(lks_plan* P, const double* motion8_dev, double* m8, B
 }
 
 lks_status lks_map_design_to_grid(lks_plan* P, const void* kappa_ref, const double* motion8,
-                                  void* kappa, void* u_s, hipStream_t s) {
-  if (!P || !kappa_ref || !motion8 || !kappa || !u_s) return fail(LKS_EINVAL, "null argument");
+                                  void* kappa, void* u_s, void* ws, hipStream_t s) {
+  if (!P || !kappa_ref || !motion8 || !kappa || !u_s || !ws)
+    return fail(LKS_EINVAL, "null argument");
   double m8[8];
   Box box;
   if (lks_status e = host_box(P, motion8, m8, box, s)) return e;
   HIPCHK(launch_zero(kappa, (size_t)P->g.N * P->es, s));
   HIPCHK(launch_zero(u_s, (size_t)P->g.d * P->g.N * P->es, s));
   Scope sc("map", s);
-  HIPCHK(launch_map(P->g, P->prec, kappa_ref, motion8, m8, box, kappa, u_s, 1, s));
+  HIPCHK(launch_map(P->g, P->prec, kappa_ref, wsp(ws, P->o_kz), P->bmax.ext[2], m8, box, kappa,
+                    u_s, 1, s));
   return LKS_OK;
 }
 

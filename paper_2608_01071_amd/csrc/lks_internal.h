@@ -11,12 +11,16 @@ namespace lks {
 constexpr int TILE_X = 32;
 constexpr int TILE_Y = 8;
 constexpr int STEP_THREADS = TILE_X * TILE_Y;
+// 3D step kernels: enough threads for the whole 1-node halo region (34 x 10).
+constexpr int THREADS3D = 384;
 // z planes per block segment of the 3D kernels.
 constexpr int ZSEG = 16;
 // design points per block of the map transpose.
 constexpr int MAPADJ_THREADS = 256;
 // 3D map: z values per thread.
-constexpr int MAP_ZC = 8;
+constexpr int MAP_ZC = 16;
+// 3D map transpose: design levels per thread.
+constexpr int MAPADJ_LCH = 8;
 
 // Device copy of the problem (passed by value to every kernel).
 struct Geo {
@@ -102,7 +106,8 @@ struct AdjArgs {
 int step_blocks(const Geo& g);
 hipError_t launch_forward_step(const Geo& g, int precision, const FwdArgs& a, hipStream_t s);
 hipError_t launch_adjoint_step(const Geo& g, int precision, const AdjArgs& a, hipStream_t s);
-hipError_t launch_map(const Geo& g, int precision, const void* kref, const double* mot8_dev,
+size_t kz_bytes(const Geo& g, int ext2max, int precision);
+hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf, int ext2max,
                       const double* mot8_host, const Box& box, void* bk, void* bu, int full_grid,
                       hipStream_t s);
 int mapadj_blocks(const Geo& g);

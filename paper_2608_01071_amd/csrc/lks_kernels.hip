@@ -310,11 +310,19 @@ __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d(Geo g, FwdArgs a) {
 }
 
 // ------------------------------------------------------ forward, D3Q15
+// Block = one 32x8 column tile marching z over a ZSEG segment.  Per plane:
+// (1) the (p, u) plane with a 2-node halo enters a 3-plane LDS ring from
+// registers fetched one iteration earlier (the global loads of the next
+// plane overlap this plane's arithmetic); (2) the 15 equilibria of the
+// plane are formed on the 1-node halo region; (3) each output column adds
+// them into the accumulators of the three output planes they feed; the
+// plane below is then complete and is finished (Brinkman, walls, J1).
 template <class R>
-__global__ __launch_bounds__(STEP_THREADS) void k_fwd3d(Geo g, FwdArgs a) {
+__global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
   constexpr int TX = TILE_X, TY = TILE_Y;
   constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
   constexpr int LP = LX * LY, FP = FX * FY;
+  constexpr int NLD = (LP + THREADS3D - 1) / THREADS3D;
   __shared__ R ring[3][4][LP];  // planes (mod 3): p, ux, uy, uz
   __shared__ R sf[15][FP];
   const R* in = (const R*)a.in;
@@ -323,98 +331,132 @@ __global__ __launch_bounds__(STEP_THREADS) void k_fwd3d(Geo g, FwdArgs a) {
   const int x0 = blockIdx.x * TX + g.org[0], y0 = blockIdx.y * TY + g.org[1];
   const int z0 = blockIdx.z * ZSEG, z1 = min(z0 + ZSEG, nz);
 
-  auto load_plane = [&](int zp) {
+  // per-thread load slots of the halo plane (fixed over the march)
+  long long lofs[NLD];
+  long long lpofs[NLD];
+  bool lok[NLD];
+#pragma unroll
+  for (int j = 0; j < NLD; ++j) {
+    const int k = threadIdx.x + j * THREADS3D;
+    int gx = x0 - 2 + k % LX, gy = y0 - 2 + k / LX;
+    lok[j] = k < LP && wrap_axis(g, 0, gx) && wrap_axis(g, 1, gy);
+    lofs[j] = lok[j] ? gx + (long long)g.n[0] * gy : 0;
+    lpofs[j] = (lok[j] && a.lazy_wall && is_wall(g, gx, gy, 0))
+                   ? inward(g, 0, gx) + (long long)g.n[0] * inward(g, 1, gy)
+                   : lofs[j];
+  }
+  R pf[NLD][4];
+  auto fetch = [&](int zp) {
     int zw = zp % nz;
     if (zw < 0) zw += nz;
-    const int sl = (zp + 3) % 3;
-    for (int k = threadIdx.x; k < LP; k += STEP_THREADS) {
-      int gx = x0 - 2 + k % LX, gy = y0 - 2 + k / LX;
-      R p = R(0), ux = R(0), uy = R(0), uz = R(0);
-      if (wrap_axis(g, 0, gx) && wrap_axis(g, 1, gy)) {
-        long long i = nidx(g, gx, gy, zw);
-        ux = in[N + i];
-        uy = in[2 * N + i];
-        uz = in[3 * N + i];
-        long long ip = (a.lazy_wall && is_wall(g, gx, gy, zw)) ? wall_src(g, gx, gy, zw) : i;
-        p = in[ip];
+    const long long pl = (long long)g.n[0] * g.n[1] * zw;
+#pragma unroll
+    for (int j = 0; j < NLD; ++j) {
+      if (lok[j]) {
+        pf[j][0] = in[pl + lpofs[j]];
+        pf[j][1] = in[N + pl + lofs[j]];
+        pf[j][2] = in[2 * N + pl + lofs[j]];
+        pf[j][3] = in[3 * N + pl + lofs[j]];
+      } else {
+        pf[j][0] = pf[j][1] = pf[j][2] = pf[j][3] = R(0);
       }
-      ring[sl][0][k] = p;
-      ring[sl][1][k] = ux;
-      ring[sl][2][k] = uy;
-      ring[sl][3][k] = uz;
+    }
+  };
+  auto commit = [&](int zp) {
+    const int sl = (zp + 3) % 3;
+#pragma unroll
+    for (int j = 0; j < NLD; ++j) {
+      const int k = threadIdx.x + j * THREADS3D;
+      if (k < LP) {
+        ring[sl][0][k] = pf[j][0];
+        ring[sl][1][k] = pf[j][1];
+        ring[sl][2][k] = pf[j][2];
+        ring[sl][3][k] = pf[j][3];
+      }
     }
   };
 
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int tid = threadIdx.x;
+  const bool outer = tid < TX * TY;
+  const int tx = tid % TX, ty = tid / TX;
   const int gx = x0 + tx, gy = y0 + ty;
-  const bool own = gx >= 0 && gx < g.n[0] && gy >= 0 && gy < g.n[1];
+  const bool own = outer && gx >= 0 && gx < g.n[0] && gy >= 0 && gy < g.n[1];
   const int oc = (ty + 1) * FX + (tx + 1);
   R am[4] = {R(0), R(0), R(0), R(0)}, a0[4] = {R(0), R(0), R(0), R(0)},
     ap[4] = {R(0), R(0), R(0), R(0)};
   double s1 = 0.0, s2 = 0.0;
   const R A = (R)g.A;
 
-  load_plane(z0 - 2);
-  load_plane(z0 - 1);
+  // equilibrium slot of this thread (one position of the 1-node halo region)
+  const int fk = tid;
+  const bool fok = fk < FP;
+  int hx = x0 - 1 + fk % FX, hy = y0 - 1 + fk / FX;
+  const bool fin = fok && wrap_axis(g, 0, hx) && wrap_axis(g, 1, hy);
+  const int fc = (fk / FX + 1) * LX + (fk % FX + 1);
+
+  fetch(z0 - 2);
+  commit(z0 - 2);
+  fetch(z0 - 1);
+  commit(z0 - 1);
+  fetch(z0);
   for (int zf = z0 - 1; zf <= z1; ++zf) {
-    load_plane(zf + 1);
+    commit(zf + 1);
     __syncthreads();
-    {
-      const int sm = (zf + 2) % 3, sc = (zf + 3) % 3, sp1 = (zf + 4) % 3;
-      for (int k = threadIdx.x; k < FP; k += STEP_THREADS) {
-        int fx = k % FX, fy = k / FX;
-        int hx = x0 - 1 + fx, hy = y0 - 1 + fy;
-        R f[15];
-        if (wrap_axis(g, 0, hx) && wrap_axis(g, 1, hy)) {
-          const int c = (fy + 1) * LX + (fx + 1);
-          const R* ux = ring[sc][1];
-          const R* uy = ring[sc][2];
-          const R* uz = ring[sc][3];
-          R dxux = dnum(g, 0, hx, ux, c, 1), dxuy = dnum(g, 0, hx, uy, c, 1),
-            dxuz = dnum(g, 0, hx, uz, c, 1);
-          R dyux = dnum(g, 1, hy, ux, c, LX), dyuy = dnum(g, 1, hy, uy, c, LX),
-            dyuz = dnum(g, 1, hy, uz, c, LX);
-          R dzux = R(0.5) * (ring[sp1][1][c] - ring[sm][1][c]);
-          R dzuy = R(0.5) * (ring[sp1][2][c] - ring[sm][2][c]);
-          R dzuz = R(0.5) * (ring[sp1][3][c] - ring[sm][3][c]);
-          feq15(ring[sc][0][c], ux[c], uy[c], uz[c], R(2) * dxux, R(2) * dyuy, R(2) * dzuz,
-                dxuy + dyux, dxuz + dzux, dyuz + dzuy, A, f);
-        } else {
+    if (zf + 2 <= z1 + 1) fetch(zf + 2);
+    if (fok) {
+      R f[15];
+      if (fin) {
+        const int sm = (zf + 2) % 3, sc = (zf + 3) % 3, sp1 = (zf + 4) % 3;
+        const R* ux = ring[sc][1];
+        const R* uy = ring[sc][2];
+        const R* uz = ring[sc][3];
+        const int c = fc;
+        R dxux = dnum(g, 0, hx, ux, c, 1), dxuy = dnum(g, 0, hx, uy, c, 1),
+          dxuz = dnum(g, 0, hx, uz, c, 1);
+        R dyux = dnum(g, 1, hy, ux, c, LX), dyuy = dnum(g, 1, hy, uy, c, LX),
+          dyuz = dnum(g, 1, hy, uz, c, LX);
+        R dzux = R(0.5) * (ring[sp1][1][c] - ring[sm][1][c]);
+        R dzuy = R(0.5) * (ring[sp1][2][c] - ring[sm][2][c]);
+        R dzuz = R(0.5) * (ring[sp1][3][c] - ring[sm][3][c]);
+        feq15(ring[sc][0][c], ux[c], uy[c], uz[c], R(2) * dxux, R(2) * dyuy, R(2) * dzuz,
+              dxuy + dyux, dxuz + dzux, dyuz + dzuy, A, f);
+      } else {
 #pragma unroll
-          for (int i = 0; i < 15; ++i) f[i] = R(0);
-        }
-#pragma unroll
-        for (int i = 0; i < 15; ++i) sf[i][k] = f[i];
+        for (int i = 0; i < 15; ++i) f[i] = R(0);
       }
+#pragma unroll
+      for (int i = 0; i < 15; ++i) sf[i][fk] = f[i];
     }
     __syncthreads();
-    // gather plane zf into the three output planes it feeds
+    if (outer) {
+      // gather plane zf into the three output planes it feeds
 #pragma unroll
-    for (int i = 0; i < 15; ++i) {
-      const int cx = Lat<15>::c[i][0], cy = Lat<15>::c[i][1], cz = Lat<15>::c[i][2];
-      R v = sf[i][oc - cx - cy * FX];
-      R* acc = (cz == 1) ? ap : ((cz == 0) ? a0 : am);
-      acc[0] += v;
-      if (cx == 1) acc[1] += v;
-      if (cx == -1) acc[1] -= v;
-      if (cy == 1) acc[2] += v;
-      if (cy == -1) acc[2] -= v;
-      if (cz == 1) acc[3] += v;
-      if (cz == -1) acc[3] -= v;
-    }
-    const int zo = zf - 1;
-    if (zo >= z0 && own) finish_node<R>(g, a, gx, gy, zo, am[0], am[1], am[2], am[3], s1, s2);
+      for (int i = 0; i < 15; ++i) {
+        const int cx = Lat<15>::c[i][0], cy = Lat<15>::c[i][1], cz = Lat<15>::c[i][2];
+        R v = sf[i][oc - cx - cy * FX];
+        R* acc = (cz == 1) ? ap : ((cz == 0) ? a0 : am);
+        acc[0] += v;
+        if (cx == 1) acc[1] += v;
+        if (cx == -1) acc[1] -= v;
+        if (cy == 1) acc[2] += v;
+        if (cy == -1) acc[2] -= v;
+        if (cz == 1) acc[3] += v;
+        if (cz == -1) acc[3] -= v;
+      }
+      const int zo = zf - 1;
+      if (zo >= z0 && own) finish_node<R>(g, a, gx, gy, zo, am[0], am[1], am[2], am[3], s1, s2);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      am[k] = a0[k];
-      a0[k] = ap[k];
-      ap[k] = R(0);
+      for (int k = 0; k < 4; ++k) {
+        am[k] = a0[k];
+        a0[k] = ap[k];
+        ap[k] = R(0);
+      }
     }
   }
   if (a.opart) {
     double v[2] = {s1, s2};
     double tot[2];
-    block_sum<2, STEP_THREADS>(v, tot);
+    block_sum<2, THREADS3D>(v, tot);
     if (threadIdx.x == 0) {
       const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
       a.opart[2 * b] += tot[0];
@@ -572,86 +614,222 @@ __global__ __launch_bounds__(STEP_THREADS) void k_adj2d(Geo g, AdjArgs a) {
 }
 
 // ------------------------------------------------------ adjoint, D3Q15
+// Same column-tile march as the forward kernel, run on the adjoint state.
+// Per plane: the adjoint state of plane z+1 (after objective seed, the
+// transposed wall rule and the transposed Brinkman correction; raw loads
+// fetched one iteration ahead) enters a 3-plane ring; the gather transpose
+// F_i and its moments M0, M1, M2 are formed for plane z on the 1-node halo;
+// plane z-1 is then finished: equilibrium transpose plus the transposed
+// velocity gradient (in-plane from the moment plane, along z from the
+// neighbouring planes' moments of the own column).
 template <class R>
-__global__ __launch_bounds__(STEP_THREADS) void k_adj3d(Geo g, AdjArgs a) {
+__global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
   constexpr int TX = TILE_X, TY = TILE_Y;
   constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
   constexpr int LP = LX * LY, FP = FX * FY;
+  constexpr int NLD = (LP + THREADS3D - 1) / THREADS3D;
   __shared__ R ring[3][4][LP];   // adjoint star planes (mod 3)
   __shared__ R mb[2][10][FP];    // moment planes (mod 2): M0, M1x,y,z, Mxx,yy,zz,xy,xz,yz
+  const R* lam = (const R*)a.lam;
+  const R* uc = (const R*)a.u_cur;
+  const R* bk = (const R*)a.bk;
+  const R* bu = (const R*)a.bu;
   const long long N = g.N;
   const int nz = g.n[2];
+  const long long NP = (long long)g.n[0] * g.n[1];
   const int x0 = blockIdx.x * TX + g.org[0], y0 = blockIdx.y * TY + g.org[1];
   const int z0 = blockIdx.z * ZSEG, z1 = min(z0 + ZSEG, nz);
+  const double seed = a.seed ? a.seed[0] : 0.0;
+  const double Ebar = a.seed ? a.E[0] : 0.0;
 
-  auto load_plane = [&](int zp) {
+  // per-thread load slots (fixed over the march)
+  int lgx[NLD], lgy[NLD];
+  long long lofs[NLD];
+  long long bxy[NLD];
+  bool lok[NLD], ltg[NLD], lown[NLD];
+#pragma unroll
+  for (int j = 0; j < NLD; ++j) {
+    const int k = threadIdx.x + j * THREADS3D;
+    const int lx = k % LX, ly = k / LX;
+    int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+    bool ok = k < LP && wrap_axis(g, 0, gx) && wrap_axis(g, 1, gy);
+    lown[j] = ok && lx >= 2 && lx < TX + 2 && ly >= 2 && ly < TY + 2 && (x0 - 2 + lx) == gx &&
+              (y0 - 2 + ly) == gy;
+    ok = ok && !(on_wall(g, 0, gx) || on_wall(g, 1, gy));
+    lok[j] = ok;
+    lgx[j] = gx;
+    lgy[j] = gy;
+    lofs[j] = ok ? gx + (long long)g.n[0] * gy : 0;
+    ltg[j] = ok && a.seed && gx >= g.tlo[0] && gx < g.thi[0] && gy >= g.tlo[1] && gy < g.thi[1];
+    long long b = -1;
+    if (ok && a.bk) {
+      int r0 = gx - a.box.lo[0], r1 = gy - a.box.lo[1];
+      if (g.bc[0] == 0) { r0 %= g.n[0]; if (r0 < 0) r0 += g.n[0]; }
+      if (g.bc[1] == 0) { r1 %= g.n[1]; if (r1 < 0) r1 += g.n[1]; }
+      if (r0 >= 0 && r0 < a.box.ext[0] && r1 >= 0 && r1 < a.box.ext[1])
+        b = r0 + (long long)a.box.sx * r1;
+    }
+    bxy[j] = b;
+  }
+  // raw values of the next plane, fetched one iteration ahead
+  R rl[NLD][4], run[NLD][3], rbk[NLD], rbu[NLD][3];
+  long long rbi[NLD];
+  bool rtg[NLD];
+  auto fetch = [&](int zp) {
     int zw = zp % nz;
     if (zw < 0) zw += nz;
-    const int s = (zp + 3) % 3;
+    const long long pl = NP * zw;
+    int r2 = zw - a.box.lo[2];
+    r2 %= nz;
+    if (r2 < 0) r2 += nz;
+    const bool zbox = r2 < a.box.ext[2];
+    const bool ztg = zw >= g.tlo[2] && zw < g.thi[2];
     const bool own_plane = zp >= z0 && zp < z1;
-    for (int k = threadIdx.x; k < LP; k += STEP_THREADS) {
-      int lx = k % LX, ly = k / LX;
-      int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
-      bool inside = wrap_axis(g, 0, gx) && wrap_axis(g, 1, gy);
-      bool owned = own_plane && lx >= 2 && lx < TX + 2 && ly >= 2 && ly < TY + 2 &&
-                   (x0 - 2 + lx) == gx && (y0 - 2 + ly) == gy;
-      R v[4];
-      adj_star<R>(g, a, gx, gy, zw, inside, owned, v);
-      ring[s][0][k] = v[0];
-      ring[s][1][k] = v[1];
-      ring[s][2][k] = v[2];
-      ring[s][3][k] = v[3];
+#pragma unroll
+    for (int j = 0; j < NLD; ++j) {
+      rtg[j] = false;
+      rbi[j] = -1;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rl[j][q] = R(0);
+      if (!lok[j]) continue;
+      const long long i = pl + lofs[j];
+      rl[j][0] = lam[i];
+      rl[j][1] = lam[N + i];
+      rl[j][2] = lam[2 * N + i];
+      rl[j][3] = lam[3 * N + i];
+      rtg[j] = ltg[j] && ztg;
+      const long long bi = (bxy[j] >= 0 && zbox) ? bxy[j] + (long long)a.box.sx * a.box.sy * r2 : -1;
+      rbi[j] = bi;
+      if (rtg[j] || (bi >= 0 && lown[j] && own_plane)) {
+        run[j][0] = uc[N + i];
+        run[j][1] = uc[2 * N + i];
+        run[j][2] = uc[3 * N + i];
+      }
+      if (bi >= 0) {
+        rbk[j] = bk[bi];
+        rbu[j][0] = bu[bi];
+        rbu[j][1] = bu[a.box.vol + bi];
+        rbu[j][2] = bu[2 * a.box.vol + bi];
+      }
+    }
+  };
+  auto commit = [&](int zp) {
+    int zw = zp % nz;
+    if (zw < 0) zw += nz;
+    const int sl = (zp + 3) % 3;
+    const bool own_plane = zp >= z0 && zp < z1;
+#pragma unroll
+    for (int j = 0; j < NLD; ++j) {
+      const int k = threadIdx.x + j * THREADS3D;
+      if (k >= LP) continue;
+      R v0 = R(0), v1 = R(0), v2 = R(0), v3 = R(0);
+      if (lok[j]) {
+        const int gx = lgx[j], gy = lgy[j];
+        R pb = rl[j][0];
+        // wall nodes that copy this node's pressure hand their adjoint back
+        int ox[2] = {gx, gx}, oy[2] = {gy, gy};
+        int cx = 1, cy = 1;
+        if (g.bc[0] == 1) {
+          if (gx == 1) ox[cx++] = 0;
+          else if (gx == g.n[0] - 2) ox[cx++] = g.n[0] - 1;
+        }
+        if (g.bc[1] == 1) {
+          if (gy == 1) oy[cy++] = 0;
+          else if (gy == g.n[1] - 2) oy[cy++] = g.n[1] - 1;
+        }
+        if (cx > 1 || cy > 1) {
+          for (int ky = 0; ky < cy; ++ky)
+            for (int kx = 0; kx < cx; ++kx)
+              if (kx || ky) pb += lam[nidx(g, ox[kx], oy[ky], zw)];
+        }
+        R ub[3] = {rl[j][1], rl[j][2], rl[j][3]};
+        if (rtg[j]) {
+          double un = g.ndir[0] * (double)run[j][0] + g.ndir[1] * (double)run[j][1] +
+                      g.ndir[2] * (double)run[j][2];
+          double gs = seed * g.NTinv * (1.0 - 2.0 * g.phi * (un - Ebar));
+          for (int q = 0; q < 3; ++q) ub[q] += (R)(gs * g.ndir[q]);
+        }
+        const long long bi = rbi[j];
+        if (bi >= 0) {
+          const R kk = rbk[j];
+          const R inv = R(1) / (R(1) + kk);
+          if (lown[j] && own_plane) {
+            R* bkbar = (R*)a.bkbar;
+            R* bubar = (R*)a.bubar;
+            R kb = R(0);
+            for (int q = 0; q < 3; ++q) {
+              kb += ub[q] * (rbu[j][q] - run[j][q]);
+              bubar[q * a.box.vol + bi] = kk * ub[q] * inv;
+            }
+            bkbar[bi] = kb * inv;
+          }
+          for (int q = 0; q < 3; ++q) ub[q] *= inv;
+        }
+        v0 = pb;
+        v1 = ub[0];
+        v2 = ub[1];
+        v3 = ub[2];
+      }
+      ring[sl][0][k] = v0;
+      ring[sl][1][k] = v1;
+      ring[sl][2][k] = v2;
+      ring[sl][3][k] = v3;
     }
   };
 
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int tid = threadIdx.x;
+  const bool outer = tid < TX * TY;
+  const int tx = tid % TX, ty = tid / TX;
   const int gx = x0 + tx, gy = y0 + ty;
-  const bool own = gx >= 0 && gx < g.n[0] && gy >= 0 && gy < g.n[1];
+  const bool own = outer && gx >= 0 && gx < g.n[0] && gy >= 0 && gy < g.n[1];
   const int oc = (ty + 1) * FX + (tx + 1);
   const R A2 = R(2) * (R)g.A;
   const R* up = (const R*)a.u_prev;
   R* lp = (R*)a.lam_prev;
   R zprev[3] = {R(0), R(0), R(0)};  // own column M2_{zx}, M2_{zy}, M2_{zz} at zo - 1
+  const int fk = tid;
+  const bool fok = fk < FP;
+  const int fc = (fk / FX + 1) * LX + (fk % FX + 1);
 
-  load_plane(z0 - 2);
-  load_plane(z0 - 1);
+  fetch(z0 - 2);
+  commit(z0 - 2);
+  fetch(z0 - 1);
+  commit(z0 - 1);
+  fetch(z0);
   for (int zs = z0 - 1; zs <= z1; ++zs) {
-    load_plane(zs + 1);
+    commit(zs + 1);
     __syncthreads();
-    {
+    if (zs + 2 <= z1 + 1) fetch(zs + 2);
+    if (fok) {
       const int s0 = (zs + 2) % 3, s1 = (zs + 3) % 3, s2 = (zs + 4) % 3;
       const int rs[3] = {s0, s1, s2};  // planes zs-1, zs, zs+1
-      R(*mo)[FP] = mb[zs & 1];
-      for (int k = threadIdx.x; k < FP; k += STEP_THREADS) {
-        int fx = k % FX, fy = k / FX;
-        const int c = (fy + 1) * LX + (fx + 1);
-        R M[10];
+      R M[10];
 #pragma unroll
-        for (int q = 0; q < 10; ++q) M[q] = R(0);
+      for (int q = 0; q < 10; ++q) M[q] = R(0);
 #pragma unroll
-        for (int i = 0; i < 15; ++i) {
-          const int cx = Lat<15>::c[i][0], cy = Lat<15>::c[i][1], cz = Lat<15>::c[i][2];
-          const int pl = rs[cz + 1];
-          const int j = c + cx + cy * LX;
-          R F = ring[pl][0][j] * R(1.0 / 3.0);
-          if (cx == 1) F += ring[pl][1][j];
-          if (cx == -1) F -= ring[pl][1][j];
-          if (cy == 1) F += ring[pl][2][j];
-          if (cy == -1) F -= ring[pl][2][j];
-          if (cz == 1) F += ring[pl][3][j];
-          if (cz == -1) F -= ring[pl][3][j];
-          const R wF = R(Lat<15>::w[i]) * F;
-          M[0] += wF;
-          if (cx != 0) { M[1] += cx * wF; M[4] += wF; }
-          if (cy != 0) { M[2] += cy * wF; M[5] += wF; }
-          if (cz != 0) { M[3] += cz * wF; M[6] += wF; }
-          if (cx * cy != 0) M[7] += (cx * cy) * wF;
-          if (cx * cz != 0) M[8] += (cx * cz) * wF;
-          if (cy * cz != 0) M[9] += (cy * cz) * wF;
-        }
-#pragma unroll
-        for (int q = 0; q < 10; ++q) mo[q][k] = M[q];
+      for (int i = 0; i < 15; ++i) {
+        const int cx = Lat<15>::c[i][0], cy = Lat<15>::c[i][1], cz = Lat<15>::c[i][2];
+        const int pl = rs[cz + 1];
+        const int j = fc + cx + cy * LX;
+        R F = ring[pl][0][j] * R(1.0 / 3.0);
+        if (cx == 1) F += ring[pl][1][j];
+        if (cx == -1) F -= ring[pl][1][j];
+        if (cy == 1) F += ring[pl][2][j];
+        if (cy == -1) F -= ring[pl][2][j];
+        if (cz == 1) F += ring[pl][3][j];
+        if (cz == -1) F -= ring[pl][3][j];
+        const R wF = R(Lat<15>::w[i]) * F;
+        M[0] += wF;
+        if (cx != 0) { M[1] += cx * wF; M[4] += wF; }
+        if (cy != 0) { M[2] += cy * wF; M[5] += wF; }
+        if (cz != 0) { M[3] += cz * wF; M[6] += wF; }
+        if (cx * cy != 0) M[7] += (cx * cy) * wF;
+        if (cx * cz != 0) M[8] += (cx * cz) * wF;
+        if (cy * cz != 0) M[9] += (cy * cz) * wF;
       }
+      R(*mo)[FP] = mb[zs & 1];
+#pragma unroll
+      for (int q = 0; q < 10; ++q) mo[q][fk] = M[q];
     }
     __syncthreads();
     const int zo = zs - 1;
@@ -678,7 +856,7 @@ __global__ __launch_bounds__(STEP_THREADS) void k_adj3d(Geo g, AdjArgs a) {
       lp[2 * N + i] = by;
       lp[3 * N + i] = bz;
     }
-    if (zs >= z0) {
+    if (zs >= z0 && outer) {
       // keep own-column z-moments of plane zs - 1 for the next output
       R(*mz)[FP] = mb[(zs - 1) & 1];
       zprev[0] = mz[8][oc];
@@ -758,9 +936,40 @@ __global__ __launch_bounds__(256) void k_map2d(Geo g, const R* kref, Mot m, Box 
   }
 }
 
+// 3D transfer, stage 1: the z factor of the kernel is axis aligned and the
+// same for every design column, so kappa_ref is first resampled onto the
+// analysis z values of the step's box: kz[column][zz] =
+// sum_{xi3} w(z - X3(xi3)) kappa_ref(column, xi3); the tail row holds
+// sum_{xi3} w(z - X3(xi3)) (the z weight sum used by the body velocity).
 template <class R>
-__global__ __launch_bounds__(256) void k_map3d(Geo g, const R* kref, Mot m, Box box, R* bk,
-                                               R* bu, int full_grid) {
+__global__ __launch_bounds__(256) void k_kz(Geo g, const R* kref, Mot m, Box box, R* kz, int ezp) {
+  const long long cols = (long long)g.D[0] * g.D[1];
+  const long long idx = blockIdx.x * 256LL + threadIdx.x;
+  if (idx >= (cols + 1) * ezp) return;
+  const long long col = idx / ezp;
+  const int zz = (int)(idx % ezp);
+  R v = R(0);
+  if (zz < box.ext[2]) {
+    const double t = (double)(box.lo[2] + zz) + (g.xiG[2] - m.xg[2]);
+    const double fl = floor(t);
+    const R f = (R)(t - fl);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e2 = (int)fl - 1 + q;
+      if (e2 >= 0 && e2 < g.D[2]) {
+        const R w = wk(f + R(1) - R(q));
+        v += (col < cols) ? w * kref[col + cols * e2] : w;
+      }
+    }
+  }
+  kz[idx] = v;
+}
+
+// 3D transfer, stage 2: one thread per analysis column and MAP_ZC z values;
+// the rotated xy candidates and their weights are formed once per column.
+template <class R>
+__global__ __launch_bounds__(64) void k_map3d(Geo g, const R* kz, int ezp, Mot m, Box box, R* bk,
+                                              R* bu, int full_grid) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const int zc = blockIdx.z * MAP_ZC;
@@ -769,25 +978,9 @@ __global__ __launch_bounds__(256) void k_map3d(Geo g, const R* kref, Mot m, Box 
   int x = bx, y = by;
   const bool col_inside = wrap_axis(g, 0, x) && wrap_axis(g, 1, y);
   const bool col_wall = col_inside && (on_wall(g, 0, x) || on_wall(g, 1, y));
-  R k[MAP_ZC], zs[MAP_ZC];
-  int base[MAP_ZC];
-  R wz[MAP_ZC][4];
-  const double o = g.xiG[2] - m.xg[2];
+  R k[MAP_ZC];
 #pragma unroll
-  for (int t = 0; t < MAP_ZC; ++t) {
-    k[t] = R(0);
-    const double zz = (double)(box.lo[2] + zc + t) + o;
-    const double fl = floor(zz);
-    const R f = (R)(zz - fl);
-    base[t] = (int)fl - 1;
-    zs[t] = R(0);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      wz[t][q] = wk(f + R(1) - R(q));
-      const int e2 = base[t] + q;
-      if (e2 >= 0 && e2 < g.D[2]) zs[t] += wz[t][q];
-    }
-  }
+  for (int t = 0; t < MAP_ZC; ++t) k[t] = R(0);
   R m0 = R(0), m1 = R(0), m2 = R(0);
   if (col_inside && !col_wall) {
     const double rx = bx - m.xg[0], ry = by - m.xg[1];
@@ -796,7 +989,6 @@ __global__ __launch_bounds__(256) void k_map3d(Geo g, const R* kref, Mot m, Box 
     const double h = 2.0 * (fabs(m.c) + fabs(m.s));
     const int i0 = max(0, (int)ceil(q0 - h)), i1 = min(g.D[0] - 1, (int)floor(q0 + h));
     const int j0 = max(0, (int)ceil(q1 - h)), j1 = min(g.D[1] - 1, (int)floor(q1 + h));
-    const long long plane = (long long)g.D[0] * g.D[1];
     for (int e1 = j0; e1 <= j1; ++e1) {
       const double r1 = e1 - g.xiG[1];
       for (int e0 = i0; e0 <= i1; ++e0) {
@@ -808,17 +1000,9 @@ __global__ __launch_bounds__(256) void k_map3d(Geo g, const R* kref, Mot m, Box 
           m0 += W;
           m1 += W * (R)r0;
           m2 += W * (R)r1;
-          const R* col = kref + e0 + (long long)g.D[0] * e1;
+          const R* col = kz + (e0 + (long long)g.D[0] * e1) * ezp + zc;
 #pragma unroll
-          for (int t = 0; t < MAP_ZC; ++t) {
-            R acc = R(0);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int e2 = base[t] + q;
-              if (e2 >= 0 && e2 < g.D[2]) acc += wz[t][q] * col[e2 * plane];
-            }
-            k[t] += W * acc;
-          }
+          for (int t = 0; t < MAP_ZC; ++t) k[t] += W * col[t];
         }
       }
     }
@@ -827,30 +1011,189 @@ __global__ __launch_bounds__(256) void k_map3d(Geo g, const R* kref, Mot m, Box 
   const R vx = om * (-s * m1 - c * m2) + (R)m.ug[0] * m0;
   const R vy = om * (c * m1 - s * m2) + (R)m.ug[1] * m0;
   const R vz = (R)m.ug[2] * m0;
+  const R* zsum = kz + (long long)g.D[0] * g.D[1] * ezp + zc;
 #pragma unroll
   for (int t = 0; t < MAP_ZC; ++t) {
-    const int kz = zc + t;
-    if (kz >= box.ext[2]) break;
-    int z = box.lo[2] + kz;
+    const int kk = zc + t;
+    if (kk >= box.ext[2]) break;
+    int z = box.lo[2] + kk;
     const bool inside = col_inside && wrap_axis(g, 2, z);
     const bool wall = !inside || col_wall || on_wall(g, 2, z);
-    R kk = wall ? R(0) : k[t];
-    R ux = wall ? R(0) : zs[t] * vx, uy = wall ? R(0) : zs[t] * vy, uz = wall ? R(0) : zs[t] * vz;
+    const R zs = zsum[t];
+    const R kv = wall ? R(0) : k[t];
+    const R ux = wall ? R(0) : zs * vx, uy = wall ? R(0) : zs * vy, uz = wall ? R(0) : zs * vz;
     if (full_grid) {
       if (wall) continue;
       const long long n = nidx(g, x, y, z);
-      bk[n] = kk;
+      bk[n] = kv;
       bu[n] = ux;
       bu[g.N + n] = uy;
       bu[2 * g.N + n] = uz;
     } else {
-      const long long bi = i + (long long)box.sx * (j + (long long)box.sy * kz);
-      bk[bi] = kk;
+      const long long bi = i + (long long)box.sx * (j + (long long)box.sy * kk);
+      bk[bi] = kv;
       bu[bi] = ux;
       bu[box.vol + bi] = uy;
       bu[2 * box.vol + bi] = uz;
     }
   }
+}
+
+// 3D transfer transpose: one thread per design column and MAPADJ_LCH design
+// levels.  The z factor is the same 4-tap kernel for every level and
+// consecutive levels are one node apart, so the thread marches the analysis
+// planes once: each plane's 16 xy taps are reduced to 12 plane sums, which
+// feed the (up to 4) levels in flight; a level is complete after its 4th
+// plane.  Finishing a level adds dJ/dkappa_ref and the motion partials.
+template <class R>
+__global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kref, Mot m, Box box,
+                                                             const R* bkbar, const R* bubar,
+                                                             double* kref_bar, int overwrite,
+                                                             double* mpart) {
+  const long long cols = (long long)g.D[0] * g.D[1];
+  const int nch = (g.D[2] + MAPADJ_LCH - 1) / MAPADJ_LCH;
+  const long long idx = blockIdx.x * (long long)MAPADJ_THREADS + threadIdx.x;
+  double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (idx < cols * nch) {
+    const long long col = idx % cols;
+    const int ch = (int)(idx / cols);
+    const int l0 = ch * MAPADJ_LCH, l1 = min(l0 + MAPADJ_LCH, g.D[2]);
+    const int e0 = (int)(col % g.D[0]), e1 = (int)(col / g.D[0]);
+    const double r0 = e0 - g.xiG[0], r1 = e1 - g.xiG[1];
+    const double X0 = m.c * r0 - m.s * r1 + m.xg[0];
+    const double X1 = m.s * r0 + m.c * r1 + m.xg[1];
+    const double U0 = m.om * (-m.s * r0 - m.c * r1) + m.ug[0];
+    const double U1 = m.om * (m.c * r0 - m.s * r1) + m.ug[1];
+    const double U2 = m.ug[2];
+    const double dX0 = -m.s * r0 - m.c * r1, dX1 = m.c * r0 - m.s * r1;                      // R' r
+    const double dU0 = m.om * (-m.c * r0 + m.s * r1), dU1 = m.om * (-m.s * r0 - m.c * r1);  // om R'' r
+    R wx[4], dx[4], wy[4], dy[4];
+    int bix[4], biy[4];
+    {
+      const int lx = (int)floor(X0) - 1, ly = (int)floor(X1) - 1;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int vx = lx + q, vy = ly + q;
+        const R rx = (R)((double)vx - X0), ry = (R)((double)vy - X1);
+        wx[q] = wk(rx);
+        dx[q] = wkd(rx);
+        wy[q] = wk(ry);
+        dy[q] = wkd(ry);
+        int b = -1;
+        if (wrap_axis(g, 0, vx) && !on_wall(g, 0, vx)) {
+          b = vx - box.lo[0];
+          if (g.bc[0] == 0) { b %= g.n[0]; if (b < 0) b += g.n[0]; }
+          if (b < 0 || b >= box.ext[0]) b = -1;
+        }
+        bix[q] = b;
+        b = -1;
+        if (wrap_axis(g, 1, vy) && !on_wall(g, 1, vy)) {
+          b = vy - box.lo[1];
+          if (g.bc[1] == 0) { b %= g.n[1]; if (b < 0) b += g.n[1]; }
+          if (b < 0 || b >= box.ext[1]) b = -1;
+        }
+        biy[q] = b;
+      }
+    }
+    const double o2 = m.xg[2] - g.xiG[2];
+    const double fo = floor(o2);
+    const R f = (R)(o2 - fo);
+    R wz[4], dz[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      wz[q] = wk(R(q) - R(1) - f);
+      dz[q] = wkd(R(q) - R(1) - f);
+    }
+    const int zb = l0 + (int)fo - 1;       // first plane
+    const int npl = (l1 - l0) + 3;
+    R acc[4][16];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[a][q] = R(0);
+    const long long sxy = (long long)box.sx * box.sy;
+    for (int p0 = 0; p0 < npl; p0 += 4) {
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int pz = p0 + rr;
+        if (pz >= npl) break;
+        // plane sums over the 16 xy taps of plane z
+        R P[12];
+#pragma unroll
+        for (int q = 0; q < 12; ++q) P[q] = R(0);
+        int z = zb + pz;
+        bool zok = wrap_axis(g, 2, z);
+        int r2 = z - box.lo[2];
+        if (g.bc[2] == 0) { r2 %= g.n[2]; if (r2 < 0) r2 += g.n[2]; }
+        zok = zok && r2 >= 0 && r2 < box.ext[2];
+        if (zok) {
+#pragma unroll
+          for (int cy = 0; cy < 4; ++cy) {
+            if (biy[cy] < 0) continue;
+#pragma unroll
+            for (int cx = 0; cx < 4; ++cx) {
+              if (bix[cx] < 0) continue;
+              const long long bi = bix[cx] + (long long)box.sx * biy[cy] + sxy * r2;
+              const R kb = bkbar[bi];
+              const R u0 = bubar[bi], u1 = bubar[box.vol + bi], u2 = bubar[2 * box.vol + bi];
+              const R w = wx[cx] * wy[cy], wxd = dx[cx] * wy[cy], wyd = wx[cx] * dy[cy];
+              P[0] += w * kb;
+              P[1] += w * u0;
+              P[2] += w * u1;
+              P[3] += w * u2;
+              P[4] += wxd * kb;
+              P[5] += wxd * u0;
+              P[6] += wxd * u1;
+              P[7] += wxd * u2;
+              P[8] += wyd * kb;
+              P[9] += wyd * u0;
+              P[10] += wyd * u1;
+              P[11] += wyd * u2;
+            }
+          }
+        }
+        // feed the levels in flight: level L = l0 + pz - q uses tap q
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int L = l0 + pz - q;
+          if (L < l0 || L >= l1) continue;
+          R* A = acc[(rr - q) & 3];
+          const R w = wz[q], d = dz[q];
+#pragma unroll
+          for (int t = 0; t < 12; ++t) A[t] += w * P[t];
+          A[12] += d * P[0];
+          A[13] += d * P[1];
+          A[14] += d * P[2];
+          A[15] += d * P[3];
+          if (q == 3) {
+            // level L complete
+            const long long k = col + cols * L;
+            const double kr = (double)kref[k];
+            const double kb = A[0];
+            const double Ub[3] = {A[1], A[2], A[3]};
+            const double Xb0 = -(kr * A[4] + U0 * A[5] + U1 * A[6] + U2 * A[7]);
+            const double Xb1 = -(kr * A[8] + U0 * A[9] + U1 * A[10] + U2 * A[11]);
+            const double Xb2 = -(kr * A[12] + U0 * A[13] + U1 * A[14] + U2 * A[15]);
+            kref_bar[k] = (overwrite ? 0.0 : kref_bar[k]) + kb;
+            part[0] += Xb0;
+            part[1] += Xb1;
+            part[2] += Xb2;
+            part[3] += Ub[0];
+            part[4] += Ub[1];
+            part[5] += Ub[2];
+            part[6] += Xb0 * dX0 + Xb1 * dX1 + Ub[0] * dU0 + Ub[1] * dU1;
+            part[7] += Ub[0] * dX0 + Ub[1] * dX1;
+#pragma unroll
+            for (int t = 0; t < 16; ++t) A[t] = R(0);
+          }
+        }
+      }
+    }
+  }
+  double tot[8];
+  block_sum<8, MAPADJ_THREADS>(part, tot);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 8; ++q) mpart[(long long)blockIdx.x * 8 + q] = tot[q];
 }
 
 // Transpose of the transfer for one step, one thread per design point.
@@ -1215,9 +1558,9 @@ hipError_t launch_forward_step(const Geo& g, int precision, const FwdArgs& a, hi
       hipLaunchKernelGGL(k_fwd2d<double>, grid, dim3(STEP_THREADS), 0, s, g, a);
   } else {
     if (precision == 0)
-      hipLaunchKernelGGL(k_fwd3d<float>, grid, dim3(STEP_THREADS), 0, s, g, a);
+      hipLaunchKernelGGL(k_fwd3d<float>, grid, dim3(THREADS3D), 0, s, g, a);
     else
-      hipLaunchKernelGGL(k_fwd3d<double>, grid, dim3(STEP_THREADS), 0, s, g, a);
+      hipLaunchKernelGGL(k_fwd3d<double>, grid, dim3(THREADS3D), 0, s, g, a);
   }
   return hipGetLastError();
 }
@@ -1231,17 +1574,25 @@ hipError_t launch_adjoint_step(const Geo& g, int precision, const AdjArgs& a, hi
       hipLaunchKernelGGL(k_adj2d<double>, grid, dim3(STEP_THREADS), 0, s, g, a);
   } else {
     if (precision == 0)
-      hipLaunchKernelGGL(k_adj3d<float>, grid, dim3(STEP_THREADS), 0, s, g, a);
+      hipLaunchKernelGGL(k_adj3d<float>, grid, dim3(THREADS3D), 0, s, g, a);
     else
-      hipLaunchKernelGGL(k_adj3d<double>, grid, dim3(STEP_THREADS), 0, s, g, a);
+      hipLaunchKernelGGL(k_adj3d<double>, grid, dim3(THREADS3D), 0, s, g, a);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_map(const Geo& g, int precision, const void* kref, const double* mot8_dev,
+int kz_rows(const Geo& g, int ext2max) {
+  (void)g;
+  return ((ext2max + MAP_ZC - 1) / MAP_ZC) * MAP_ZC;
+}
+size_t kz_bytes(const Geo& g, int ext2max, int precision) {
+  if (g.d != 3) return 0;
+  return (size_t)(g.D[0] * (long long)g.D[1] + 1) * kz_rows(g, ext2max) * (precision == 0 ? 4 : 8);
+}
+
+hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf, int ext2max,
                       const double* mot8_host, const Box& box, void* bk, void* bu, int full_grid,
                       hipStream_t s) {
-  (void)mot8_dev;
   if (box.ext[0] <= 0 || box.ext[1] <= 0 || box.ext[2] <= 0) return hipSuccess;
   Mot m = make_mot(mot8_host);
   if (g.d == 2) {
@@ -1253,18 +1604,32 @@ hipError_t launch_map(const Geo& g, int precision, const void* kref, const doubl
       hipLaunchKernelGGL(k_map2d<double>, grid, dim3(256), 0, s, g, (const double*)kref, m, box,
                          (double*)bk, (double*)bu, full_grid);
   } else {
+    const int ezp = kz_rows(g, ext2max);
+    const long long nkz = ((long long)g.D[0] * g.D[1] + 1) * ezp;
+    dim3 g1((unsigned)((nkz + 255) / 256));
     dim3 grid((box.ext[0] + 63) / 64, box.ext[1], (box.ext[2] + MAP_ZC - 1) / MAP_ZC);
-    if (precision == 0)
-      hipLaunchKernelGGL(k_map3d<float>, grid, dim3(64), 0, s, g, (const float*)kref, m, box,
-                         (float*)bk, (float*)bu, full_grid);
-    else
-      hipLaunchKernelGGL(k_map3d<double>, grid, dim3(64), 0, s, g, (const double*)kref, m, box,
-                         (double*)bk, (double*)bu, full_grid);
+    if (precision == 0) {
+      hipLaunchKernelGGL(k_kz<float>, g1, dim3(256), 0, s, g, (const float*)kref, m, box,
+                         (float*)kzbuf, ezp);
+      hipLaunchKernelGGL(k_map3d<float>, grid, dim3(64), 0, s, g, (const float*)kzbuf, ezp, m,
+                         box, (float*)bk, (float*)bu, full_grid);
+    } else {
+      hipLaunchKernelGGL(k_kz<double>, g1, dim3(256), 0, s, g, (const double*)kref, m, box,
+                         (double*)kzbuf, ezp);
+      hipLaunchKernelGGL(k_map3d<double>, grid, dim3(64), 0, s, g, (const double*)kzbuf, ezp, m,
+                         box, (double*)bk, (double*)bu, full_grid);
+    }
   }
   return hipGetLastError();
 }
 
-int mapadj_blocks(const Geo& g) { return (int)((g.Mtot + MAPADJ_THREADS - 1) / MAPADJ_THREADS); }
+int mapadj_blocks(const Geo& g) {
+  if (g.d == 3) {
+    const long long n = (long long)g.D[0] * g.D[1] * ((g.D[2] + MAPADJ_LCH - 1) / MAPADJ_LCH);
+    return (int)((n + MAPADJ_THREADS - 1) / MAPADJ_THREADS);
+  }
+  return (int)((g.Mtot + MAPADJ_THREADS - 1) / MAPADJ_THREADS);
+}
 
 hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
                               const double* mot8_host, const Box& box, const void* bkbar,
@@ -1272,6 +1637,17 @@ hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
                               hipStream_t s) {
   Mot m = make_mot(mot8_host);
   dim3 grid(mapadj_blocks(g));
+  if (g.d == 3) {
+    if (precision == 0)
+      hipLaunchKernelGGL(k_mapadj3d<float>, grid, dim3(MAPADJ_THREADS), 0, s, g,
+                         (const float*)kref, m, box, (const float*)bkbar, (const float*)bubar,
+                         kref_bar, overwrite, mpart);
+    else
+      hipLaunchKernelGGL(k_mapadj3d<double>, grid, dim3(MAPADJ_THREADS), 0, s, g,
+                         (const double*)kref, m, box, (const double*)bkbar, (const double*)bubar,
+                         kref_bar, overwrite, mpart);
+    return hipGetLastError();
+  }
   if (precision == 0)
     hipLaunchKernelGGL(k_mapadj<float>, grid, dim3(MAPADJ_THREADS), 0, s, g, (const float*)kref,
                        m, box, (const float*)bkbar, (const float*)bubar, kref_bar, overwrite,

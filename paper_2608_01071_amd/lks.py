@@ -57,7 +57,7 @@ def lib():
         L.lks_plan_destroy.argtypes = [_VP]
         L.lks_forward.argtypes = [_VP] * 9
         L.lks_adjoint.argtypes = [_VP] * 12
-        L.lks_map_design_to_grid.argtypes = [_VP] * 6
+        L.lks_map_design_to_grid.argtypes = [_VP] * 7
         L.lks_sensitivities.argtypes = [_VP] * 7
         L.lks_motion.argtypes = [_VP] * 5
         L.lks_kappa_ref.argtypes = [_VP] * 4
@@ -204,7 +204,7 @@ class Plan:
         k = torch.empty(p.N, dtype=self.dtype, device=self.device)
         us = torch.empty(p.d * p.N, dtype=self.dtype, device=self.device)
         _check(lib().lks_map_design_to_grid(self.handle, _ptr(kr), _ptr(m), _ptr(k), _ptr(us),
-                                            _stream()))
+                                            _ptr(self.workspace), _stream()))
         return k, us
 
     def step(self, state, kappa, us):
