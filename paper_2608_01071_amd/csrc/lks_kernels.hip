@@ -386,6 +386,31 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
     ap[4] = {R(0), R(0), R(0), R(0)};
   double s1 = 0.0, s2 = 0.0;
   const R A = (R)g.A;
+  // column-constant data of the output node
+  const bool cwall = own && (on_wall(g, 0, gx) || on_wall(g, 1, gy));
+  const bool ctgt = own && a.opart && gx >= g.tlo[0] && gx < g.thi[0] && gy >= g.tlo[1] &&
+                    gy < g.thi[1];
+  long long cbxy = -1;
+  if (own && !cwall && a.bk) {
+    int r0 = gx - a.box.lo[0], r1 = gy - a.box.lo[1];
+    if (g.bc[0] == 0) { r0 %= g.n[0]; if (r0 < 0) r0 += g.n[0]; }
+    if (g.bc[1] == 0) { r1 %= g.n[1]; if (r1 < 0) r1 += g.n[1]; }
+    if (r0 >= 0 && r0 < a.box.ext[0] && r1 >= 0 && r1 < a.box.ext[1])
+      cbxy = r0 + (long long)a.box.sx * r1;
+  }
+  R cw[3] = {R(0), R(0), R(0)};
+  if (cwall) {
+    double uw[3];
+    wall_vel(g, gx, gy, 0, uw);
+    cw[0] = (R)uw[0];
+    cw[1] = (R)uw[1];
+    cw[2] = (R)uw[2];
+  }
+  const R* bkp = (const R*)a.bk;
+  const R* bup = (const R*)a.bu;
+  R* outp = (R*)a.out;
+  R bkv = R(0), buv[3] = {R(0), R(0), R(0)};
+  bool binb = false;
 
   // equilibrium slot of this thread (one position of the 1-node halo region)
   const int fk = tid;
@@ -403,6 +428,20 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
     commit(zf + 1);
     __syncthreads();
     if (zf + 2 <= z1 + 1) fetch(zf + 2);
+    // body fields of the plane finished in this iteration
+    binb = false;
+    if (cbxy >= 0 && zf - 1 >= z0) {
+      int r2 = (zf - 1 - a.box.lo[2]) % nz;
+      if (r2 < 0) r2 += nz;
+      if (r2 < a.box.ext[2]) {
+        const long long bi = cbxy + (long long)a.box.sx * a.box.sy * r2;
+        binb = true;
+        bkv = bkp[bi];
+        buv[0] = bup[bi];
+        buv[1] = bup[a.box.vol + bi];
+        buv[2] = bup[2 * a.box.vol + bi];
+      }
+    }
     if (fok) {
       R f[15];
       if (fin) {
@@ -444,7 +483,38 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
         if (cz == -1) acc[3] -= v;
       }
       const int zo = zf - 1;
-      if (zo >= z0 && own) finish_node<R>(g, a, gx, gy, zo, am[0], am[1], am[2], am[3], s1, s2);
+      if (zo >= z0 && own) {
+        const long long i = nidx(g, gx, gy, zo);
+        R u0, u1, u2, p;
+        if (cwall) {
+          u0 = cw[0];
+          u1 = cw[1];
+          u2 = cw[2];
+          p = R(0);  // wall pressure follows the wall rule when read
+        } else {
+          p = am[0] * R(1.0 / 3.0);
+          u0 = am[1];
+          u1 = am[2];
+          u2 = am[3];
+          if (binb) {
+            const R inv = R(1) / (R(1) + bkv);
+            u0 = (u0 + bkv * buv[0]) * inv;
+            u1 = (u1 + bkv * buv[1]) * inv;
+            u2 = (u2 + bkv * buv[2]) * inv;
+          }
+          const R uu = u0 * u0 + u1 * u1 + u2 * u2;
+          if (a.flags && !(uu < R(0.25))) a.flags[0] = 1;  // non-finite or |u| >= 0.5
+        }
+        outp[i] = p;
+        outp[N + i] = u0;
+        outp[2 * N + i] = u1;
+        outp[3 * N + i] = u2;
+        if (ctgt && zo >= g.tlo[2] && zo < g.thi[2]) {
+          const double un = g.ndir[0] * (double)u0 + g.ndir[1] * (double)u1 + g.ndir[2] * (double)u2;
+          s1 += un;
+          s2 += un * un;
+        }
+      }
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         am[k] = a0[k];
@@ -800,6 +870,13 @@ __global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
     commit(zs + 1);
     __syncthreads();
     if (zs + 2 <= z1 + 1) fetch(zs + 2);
+    R upx = R(0), upy = R(0), upz = R(0);
+    if (zs - 1 >= z0 && own) {
+      const long long i = nidx(g, gx, gy, zs - 1);
+      upx = up[N + i];
+      upy = up[2 * N + i];
+      upz = up[3 * N + i];
+    }
     if (fok) {
       const int s0 = (zs + 2) % 3, s1 = (zs + 3) % 3, s2 = (zs + 4) % 3;
       const int rs[3] = {s0, s1, s2};  // planes zs-1, zs, zs+1
@@ -837,7 +914,7 @@ __global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
       R(*m0)[FP] = mb[zo & 1];   // plane zo
       R(*m1)[FP] = mb[zs & 1];   // plane zo + 1
       const long long i = nidx(g, gx, gy, zo);
-      const R ux = up[N + i], uy = up[2 * N + i], uz = up[3 * N + i];
+      const R ux = upx, uy = upy, uz = upz;
       const R M0 = m0[0][oc];
       const R Mxx = m0[4][oc], Myy = m0[5][oc], Mzz = m0[6][oc];
       const R Mxy = m0[7][oc], Mxz = m0[8][oc], Myz = m0[9][oc];
@@ -1104,89 +1181,75 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
       wz[q] = wk(R(q) - R(1) - f);
       dz[q] = wkd(R(q) - R(1) - f);
     }
-    const int zb = l0 + (int)fo - 1;       // first plane
-    const int npl = (l1 - l0) + 3;
-    R acc[4][16];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) acc[a][q] = R(0);
+    const int zb = l0 + (int)fo - 1;       // first plane of level l0
     const long long sxy = (long long)box.sx * box.sy;
-    for (int p0 = 0; p0 < npl; p0 += 4) {
+    // plane sums over the 16 xy taps of analysis plane z:
+    // (w, w'_x w_y, w_x w'_y) times (kbar, ubar_x, ubar_y, ubar_z)
+    auto plane_sums = [&](int z, R* P) {
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int pz = p0 + rr;
-        if (pz >= npl) break;
-        // plane sums over the 16 xy taps of plane z
-        R P[12];
+      for (int q = 0; q < 12; ++q) P[q] = R(0);
+      bool zok = wrap_axis(g, 2, z);
+      int r2 = z - box.lo[2];
+      if (g.bc[2] == 0) { r2 %= g.n[2]; if (r2 < 0) r2 += g.n[2]; }
+      if (!zok || r2 < 0 || r2 >= box.ext[2]) return;
 #pragma unroll
-        for (int q = 0; q < 12; ++q) P[q] = R(0);
-        int z = zb + pz;
-        bool zok = wrap_axis(g, 2, z);
-        int r2 = z - box.lo[2];
-        if (g.bc[2] == 0) { r2 %= g.n[2]; if (r2 < 0) r2 += g.n[2]; }
-        zok = zok && r2 >= 0 && r2 < box.ext[2];
-        if (zok) {
+      for (int cy = 0; cy < 4; ++cy) {
+        if (biy[cy] < 0) continue;
 #pragma unroll
-          for (int cy = 0; cy < 4; ++cy) {
-            if (biy[cy] < 0) continue;
-#pragma unroll
-            for (int cx = 0; cx < 4; ++cx) {
-              if (bix[cx] < 0) continue;
-              const long long bi = bix[cx] + (long long)box.sx * biy[cy] + sxy * r2;
-              const R kb = bkbar[bi];
-              const R u0 = bubar[bi], u1 = bubar[box.vol + bi], u2 = bubar[2 * box.vol + bi];
-              const R w = wx[cx] * wy[cy], wxd = dx[cx] * wy[cy], wyd = wx[cx] * dy[cy];
-              P[0] += w * kb;
-              P[1] += w * u0;
-              P[2] += w * u1;
-              P[3] += w * u2;
-              P[4] += wxd * kb;
-              P[5] += wxd * u0;
-              P[6] += wxd * u1;
-              P[7] += wxd * u2;
-              P[8] += wyd * kb;
-              P[9] += wyd * u0;
-              P[10] += wyd * u1;
-              P[11] += wyd * u2;
-            }
-          }
+        for (int cx = 0; cx < 4; ++cx) {
+          if (bix[cx] < 0) continue;
+          const long long bi = bix[cx] + (long long)box.sx * biy[cy] + sxy * r2;
+          const R kb = bkbar[bi];
+          const R u0 = bubar[bi], u1 = bubar[box.vol + bi], u2 = bubar[2 * box.vol + bi];
+          const R w = wx[cx] * wy[cy], wxd = dx[cx] * wy[cy], wyd = wx[cx] * dy[cy];
+          P[0] += w * kb;
+          P[1] += w * u0;
+          P[2] += w * u1;
+          P[3] += w * u2;
+          P[4] += wxd * kb;
+          P[5] += wxd * u0;
+          P[6] += wxd * u1;
+          P[7] += wxd * u2;
+          P[8] += wyd * kb;
+          P[9] += wyd * u0;
+          P[10] += wyd * u1;
+          P[11] += wyd * u2;
         }
-        // feed the levels in flight: level L = l0 + pz - q uses tap q
+      }
+    };
+    // window of the 4 planes feeding the current level
+    R W0[12], W1[12], W2[12], W3[12];
+    plane_sums(zb, W0);
+    plane_sums(zb + 1, W1);
+    plane_sums(zb + 2, W2);
+    for (int L = l0; L < l1; ++L) {
+      plane_sums(L + (int)fo + 2, W3);
+      R A[16];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int L = l0 + pz - q;
-          if (L < l0 || L >= l1) continue;
-          R* A = acc[(rr - q) & 3];
-          const R w = wz[q], d = dz[q];
+      for (int t = 0; t < 12; ++t)
+        A[t] = wz[0] * W0[t] + wz[1] * W1[t] + wz[2] * W2[t] + wz[3] * W3[t];
 #pragma unroll
-          for (int t = 0; t < 12; ++t) A[t] += w * P[t];
-          A[12] += d * P[0];
-          A[13] += d * P[1];
-          A[14] += d * P[2];
-          A[15] += d * P[3];
-          if (q == 3) {
-            // level L complete
-            const long long k = col + cols * L;
-            const double kr = (double)kref[k];
-            const double kb = A[0];
-            const double Ub[3] = {A[1], A[2], A[3]};
-            const double Xb0 = -(kr * A[4] + U0 * A[5] + U1 * A[6] + U2 * A[7]);
-            const double Xb1 = -(kr * A[8] + U0 * A[9] + U1 * A[10] + U2 * A[11]);
-            const double Xb2 = -(kr * A[12] + U0 * A[13] + U1 * A[14] + U2 * A[15]);
-            kref_bar[k] = (overwrite ? 0.0 : kref_bar[k]) + kb;
-            part[0] += Xb0;
-            part[1] += Xb1;
-            part[2] += Xb2;
-            part[3] += Ub[0];
-            part[4] += Ub[1];
-            part[5] += Ub[2];
-            part[6] += Xb0 * dX0 + Xb1 * dX1 + Ub[0] * dU0 + Ub[1] * dU1;
-            part[7] += Ub[0] * dX0 + Ub[1] * dX1;
+      for (int t = 0; t < 4; ++t)
+        A[12 + t] = dz[0] * W0[t] + dz[1] * W1[t] + dz[2] * W2[t] + dz[3] * W3[t];
+      const long long k = col + cols * L;
+      const double kr = (double)kref[k];
+      const double Xb0 = -(kr * A[4] + U0 * A[5] + U1 * A[6] + U2 * A[7]);
+      const double Xb1 = -(kr * A[8] + U0 * A[9] + U1 * A[10] + U2 * A[11]);
+      const double Xb2 = -(kr * A[12] + U0 * A[13] + U1 * A[14] + U2 * A[15]);
+      kref_bar[k] = (overwrite ? 0.0 : kref_bar[k]) + (double)A[0];
+      part[0] += Xb0;
+      part[1] += Xb1;
+      part[2] += Xb2;
+      part[3] += A[1];
+      part[4] += A[2];
+      part[5] += A[3];
+      part[6] += Xb0 * dX0 + Xb1 * dX1 + (double)A[1] * dU0 + (double)A[2] * dU1;
+      part[7] += (double)A[1] * dX0 + (double)A[2] * dX1;
 #pragma unroll
-            for (int t = 0; t < 16; ++t) A[t] = R(0);
-          }
-        }
+      for (int t = 0; t < 12; ++t) {
+        W0[t] = W1[t];
+        W1[t] = W2[t];
+        W2[t] = W3[t];
       }
     }
   }
