@@ -96,6 +96,13 @@ typedef struct lks_plan lks_plan;
 lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* workspace_bytes);
 lks_status lks_plan_destroy(lks_plan* plan);
 
+/* Graph replay of the time loops (default on).  With it on, lks_forward and
+ * lks_adjoint capture their time loop into a hipGraph on first use for a
+ * workspace (on a private stream of the plan) and replay it afterwards;
+ * per-step data are read from device tables, so replays see new inputs.
+ * While lks_profile_enable is on, loops run eagerly (per-launch events). */
+lks_status lks_plan_set_graphs(lks_plan* plan, int32_t on);
+
 /* Forward march (Algorithm 1, state loop; Sec. 2.2-2.4, 2.6).
  * state0: initial state (nullable: p = 1/3, u = 0 everywhere; the wall
  *   nodes' given p is used for the first step as is).

@@ -1,13 +1,18 @@
 // lks_api.hip -- host layer of the C ABI declared in include/lks.h: problem
 // validation, workspace layout, the forward time loop with checkpoints every
-// K steps, the reverse sweep with segment recomputation, the stand-alone
-// stage entry points, per-kernel event timing and the batched graph.
+// K steps, the reverse sweep with segment recomputation, hipGraph capture of
+// both time loops, the stand-alone stage entry points, per-kernel event
+// timing and the batched graph of independent instances.
+//
+// The time loops contain launches only: every per-step quantity (rigid
+// motion, support box) lives in a device table filled by the prelude, so a
+// loop captured once per (plan, workspace) is replayed unchanged on later
+// calls.  No host synchronisation happens inside a loop.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
-#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -65,7 +70,7 @@ struct Profiler {
 };
 Profiler g_prof;
 
-// Wraps one launch in an event pair when profiling is enabled.
+// Wraps one launch in an event pair (on the launch stream) while profiling.
 struct Scope {
   int cls = -1;
   hipEvent_t a = nullptr, b = nullptr;
@@ -76,13 +81,25 @@ struct Scope {
     cls = g_prof.cls_id(name);
     a = g_prof.ev();
     b = g_prof.ev();
-    if (a) hipEventRecord(a, s);
+    if (a) (void)hipEventRecord(a, s);
   }
   ~Scope() {
     if (cls < 0 || !a || !b) return;
-    hipEventRecord(b, s);
+    (void)hipEventRecord(b, s);
     std::lock_guard<std::mutex> lk(g_prof.mu);
     g_prof.recs.push_back({cls, a, b});
+  }
+};
+
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  void* ws = nullptr;
+  int key = 0;
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+    ws = nullptr;
+    key = 0;
   }
 };
 
@@ -96,17 +113,21 @@ struct lks_plan {
   long long S;  // state elements
   int K, nck;
   int nblk_step, nblk_map;
-  Box bmax;     // strides and volume of the body buffers
+  Box bmax;     // strides, volume and launch extents of the body buffers
   // workspace offsets (bytes)
-  size_t o_mot, o_box, o_kref, o_flags, o_J3, o_opart, o_ck, o_pp, o_tape, o_body, o_badj, o_lam,
-      o_krefbar, o_mpart, o_mbar, o_den, o_kz, total;
-  // host copies made by the forward
-  std::vector<int> boxes;
-  std::vector<double> mot;
+  size_t o_mot, o_tab, o_info, o_kref, o_flags, o_J3, o_seed, o_opart, o_ck, o_pp, o_tape,
+      o_body, o_btape, o_badj, o_lam, o_krefbar, o_mpart, o_mbar, o_den, o_kz, total;
   int first_lazy = 1;
   void* fwd_ws = nullptr;
-  // batched graph cache
-  hipGraphExec_t gexec = nullptr;
+  bool use_graphs = true;
+  hipStream_t cap = nullptr;  // private stream used for graph capture
+  GraphCache gfwd, gadj, gbatch;
+  ~lks_plan() {
+    gfwd.reset();
+    gadj.reset();
+    gbatch.reset();
+    if (cap) (void)hipStreamDestroy(cap);
+  }
 };
 
 namespace {
@@ -174,87 +195,38 @@ void fill_geo(const lks_problem& p, Geo& g) {
 
 char* wsp(void* ws, size_t off) { return (char*)ws + off; }
 
-lks_status map_for_step(lks_plan* P, void* ws, int n, hipStream_t s) {
-  Box box = P->bmax;
-  const int* bx = &P->boxes[(size_t)(n - 1) * 8];
-  for (int a = 0; a < 3; ++a) {
-    box.lo[a] = bx[a];
-    box.ext[a] = bx[3 + a];
-  }
-  void* bk = wsp(ws, P->o_body);
-  void* bu = wsp(ws, P->o_body) + P->bmax.vol * P->es;
-  Scope sc("map", s);
-  HIPCHK(launch_map(P->g, P->prec, wsp(ws, P->o_kref), wsp(ws, P->o_kz), P->bmax.ext[2],
-                    &P->mot[(size_t)(n - 1) * 8], box, bk, bu, 0, s));
-  return LKS_OK;
+const StepInfo* tab(lks_plan* P, void* ws, int n) {
+  return (const StepInfo*)wsp(ws, P->o_tab) + (n - 1);
 }
-
-Box step_box(const lks_plan* P, int n) {
-  Box box = P->bmax;
-  const int* bx = &P->boxes[(size_t)(n - 1) * 8];
-  for (int a = 0; a < 3; ++a) {
-    box.lo[a] = bx[a];
-    box.ext[a] = bx[3 + a];
-  }
-  return box;
-}
-
-// Motion prelude, kappa_ref and per-step boxes; copies boxes and motion to
-// the host and runs the domain check (synchronises the stream).
-lks_status prelude(lks_plan* P, const double* gamma, const double* chi, const double* psi,
-                   void* ws, hipStream_t s) {
-  if (!gamma || !chi || !psi || !ws) return fail(LKS_EINVAL, "null input pointer");
-  double* mot = (double*)wsp(ws, P->o_mot);
-  int* boxes = (int*)wsp(ws, P->o_box);
-  {
-    Scope sc("prelude", s);
-    HIPCHK(launch_kappa_ref(P->g, P->prec, gamma, wsp(ws, P->o_kref), s));
-    HIPCHK(launch_motion(P->g, chi, psi, mot, s));
-    HIPCHK(launch_boxes(P->g, mot, boxes, nullptr, s));
-  }
-  P->boxes.resize((size_t)P->g.nt * 8);
-  P->mot.resize((size_t)P->g.nt * 8);
-  HIPCHK(hipMemcpyAsync(P->boxes.data(), boxes, P->boxes.size() * sizeof(int),
-                        hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(P->mot.data(), mot, P->mot.size() * sizeof(double),
-                        hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  for (int t = 0; t < P->g.nt; ++t) {
-    const int* b = &P->boxes[(size_t)t * 8];
-    if (b[6] == 1) {
-      char buf[160];
-      snprintf(buf, sizeof buf, "step %d: the body's kernel support reaches a wall node", t + 1);
-      return fail(LKS_EDOMAIN, buf);
-    }
-    if (b[6] == 2) {
-      char buf[160];
-      snprintf(buf, sizeof buf, "step %d: the body's support exceeds a periodic extent", t + 1);
-      return fail(LKS_EDOMAIN, buf);
-    }
-    for (int a = 0; a < 3; ++a)
-      if (b[3 + a] > (a == 0 ? P->bmax.sx : (a == 1 ? P->bmax.sy : (int)(P->bmax.vol / ((long long)P->bmax.sx * P->bmax.sy)))))
-        return fail(LKS_EINVAL, "internal: body box exceeds its bound");
-  }
-  return LKS_OK;
-}
-
 void* ck_slot(lks_plan* P, void* ws, int j) { return wsp(ws, P->o_ck) + (size_t)j * P->S * P->es; }
 void* pp_slot(lks_plan* P, void* ws, int j) { return wsp(ws, P->o_pp) + (size_t)j * P->S * P->es; }
 void* tape_slot(lks_plan* P, void* ws, int j) {
   return wsp(ws, P->o_tape) + (size_t)j * P->S * P->es;
 }
 void* lam_slot(lks_plan* P, void* ws, int j) { return wsp(ws, P->o_lam) + (size_t)j * P->S * P->es; }
+size_t body_bytes(const lks_plan* P) { return (size_t)(1 + P->g.d) * P->bmax.vol * P->es; }
+void* btape_slot(lks_plan* P, void* ws, int j) {
+  return wsp(ws, P->o_btape) + (size_t)j * body_bytes(P);
+}
 
-lks_status fwd_step(lks_plan* P, void* ws, int n, const void* in, void* out, int lazy, int obj,
-                    hipStream_t s) {
-  if (lks_status e = map_for_step(P, ws, n, s)) return e;
+// Body fields (kappa, u_s) of step n into `body` (layout [1+d][bmax.vol]).
+lks_status map_step(lks_plan* P, void* ws, int n, void* body, hipStream_t s) {
+  Scope sc("map", s);
+  HIPCHK(launch_map(P->g, P->prec, wsp(ws, P->o_kref), wsp(ws, P->o_kz), P->bmax.ext[2], nullptr,
+                    tab(P, ws, n), P->bmax, body, (char*)body + P->bmax.vol * P->es, 0, s));
+  return LKS_OK;
+}
+
+lks_status fwd_step(lks_plan* P, void* ws, int n, const void* in, void* out, const void* body,
+                    int lazy, int obj, hipStream_t s) {
   FwdArgs a;
   memset(&a, 0, sizeof a);
   a.in = in;
   a.out = out;
-  a.bk = wsp(ws, P->o_body);
-  a.bu = wsp(ws, P->o_body) + P->bmax.vol * P->es;
-  a.box = step_box(P, n);
+  a.bk = body;
+  a.bu = (const char*)body + P->bmax.vol * P->es;
+  a.box = P->bmax;
+  a.si = tab(P, ws, n);
   a.opart = obj ? (double*)wsp(ws, P->o_opart) : nullptr;
   a.flags = (int*)wsp(ws, P->o_flags);
   a.lazy_wall = lazy;
@@ -263,15 +235,56 @@ lks_status fwd_step(lks_plan* P, void* ws, int n, const void* in, void* out, int
   return LKS_OK;
 }
 
-// Forward time loop (no host synchronisation inside).
-lks_status forward_loop(lks_plan* P, void* ws, int first_lazy, hipStream_t s) {
+// Motion prelude, kappa_ref, the per-step table and the domain check
+// (synchronises the stream once).
+lks_status prelude(lks_plan* P, const double* gamma, const double* chi, const double* psi,
+                   void* ws, hipStream_t s) {
+  if (!gamma || !chi || !psi || !ws) return fail(LKS_EINVAL, "null input pointer");
+  double* mot = (double*)wsp(ws, P->o_mot);
+  int* info = (int*)wsp(ws, P->o_info);
+  {
+    Scope sc("prelude", s);
+    HIPCHK(launch_zero(info, 64 * sizeof(int), s));
+    HIPCHK(launch_kappa_ref(P->g, P->prec, gamma, wsp(ws, P->o_kref), s));
+    HIPCHK(launch_motion(P->g, chi, psi, mot, s));
+    HIPCHK(launch_steps(P->g, mot, (StepInfo*)wsp(ws, P->o_tab), info, s));
+  }
+  int flag = 0;
+  HIPCHK(hipMemcpyAsync(&flag, info, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (flag) {
+    std::vector<StepInfo> t(P->g.nt);
+    HIPCHK(hipMemcpy(t.data(), wsp(ws, P->o_tab), t.size() * sizeof(StepInfo),
+                     hipMemcpyDeviceToHost));
+    int step = 0;
+    for (int k = 0; k < P->g.nt && !step; ++k)
+      if (t[k].flag == flag) step = k + 1;
+    char buf[192];
+    snprintf(buf, sizeof buf,
+             flag == 1 ? "step %d: the body's kernel support reaches a wall node"
+                       : "step %d: the body's support exceeds a periodic extent",
+             step);
+    return fail(LKS_EDOMAIN, buf);
+  }
+  return LKS_OK;
+}
+
+// Forward time loop: launches only.
+lks_status forward_loop(lks_plan* P, void* ws, hipStream_t s) {
+  HIPCHK(launch_zero(wsp(ws, P->o_flags), 64 * sizeof(int), s));
+  HIPCHK(launch_zero(wsp(ws, P->o_opart), (size_t)P->nblk_step * 2 * sizeof(double), s));
+  void* body = wsp(ws, P->o_body);
   const void* in = ck_slot(P, ws, 0);
   for (int n = 1; n <= P->g.nt; ++n) {
     void* out = (n % P->K == 0 && n / P->K < P->nck) ? ck_slot(P, ws, n / P->K)
                                                       : pp_slot(P, ws, n & 1);
-    if (lks_status e = fwd_step(P, ws, n, in, out, n == 1 ? first_lazy : 1, 1, s)) return e;
+    if (lks_status e = map_step(P, ws, n, body, s)) return e;
+    if (lks_status e = fwd_step(P, ws, n, in, out, body, n == 1 ? P->first_lazy : 1, 1, s))
+      return e;
     in = out;
   }
+  HIPCHK(launch_objective_final(P->g, (const double*)wsp(ws, P->o_opart), P->nblk_step,
+                                (double*)wsp(ws, P->o_J3), s));
   return LKS_OK;
 }
 
@@ -281,33 +294,39 @@ const void* final_state(lks_plan* P, void* ws) {
   return pp_slot(P, ws, n & 1);
 }
 
-// Reverse sweep with segment recomputation (no host synchronisation inside).
-lks_status adjoint_loop(lks_plan* P, void* ws, const double* dJ, hipStream_t s) {
+// Reverse sweep with segment recomputation: launches only.  The recompute
+// keeps each step's body fields, which the reverse steps then reuse.
+lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
   const int nt = P->g.nt, K = P->K;
   int cur = 0;
   double* kref_bar = (double*)wsp(ws, P->o_krefbar);
+  const double* seed = (const double*)wsp(ws, P->o_seed);
   for (int sg = P->nck - 1; sg >= 0; --sg) {
     const int nb = sg * K + 1, ne = std::min((sg + 1) * K, nt);
     // recompute the segment into the tape: tape[n - nb] holds state n
     for (int n = nb; n <= ne; ++n) {
       const void* in = (n == nb) ? ck_slot(P, ws, sg) : tape_slot(P, ws, n - nb - 1);
       const int lazy = (n == 1) ? P->first_lazy : 1;
-      if (lks_status e = fwd_step(P, ws, n, in, tape_slot(P, ws, n - nb), lazy, 0, s)) return e;
+      void* body = btape_slot(P, ws, n - nb);
+      if (lks_status e = map_step(P, ws, n, body, s)) return e;
+      if (lks_status e = fwd_step(P, ws, n, in, tape_slot(P, ws, n - nb), body, lazy, 0, s))
+        return e;
     }
     for (int n = ne; n >= nb; --n) {
-      if (lks_status e = map_for_step(P, ws, n, s)) return e;
+      const void* body = btape_slot(P, ws, n - nb);
       AdjArgs a;
       memset(&a, 0, sizeof a);
       a.lam = lam_slot(P, ws, cur);
       a.lam_prev = lam_slot(P, ws, 1 - cur);
       a.u_prev = (n == nb) ? ck_slot(P, ws, sg) : tape_slot(P, ws, n - nb - 1);
       a.u_cur = tape_slot(P, ws, n - nb);
-      a.bk = wsp(ws, P->o_body);
-      a.bu = wsp(ws, P->o_body) + P->bmax.vol * P->es;
+      a.bk = body;
+      a.bu = (const char*)body + P->bmax.vol * P->es;
       a.bkbar = wsp(ws, P->o_badj);
       a.bubar = wsp(ws, P->o_badj) + P->bmax.vol * P->es;
-      a.box = step_box(P, n);
-      a.seed = dJ;
+      a.box = P->bmax;
+      a.si = tab(P, ws, n);
+      a.seed = seed;
       a.E = (const double*)wsp(ws, P->o_J3) + 1;
       {
         Scope sc("adj_step", s);
@@ -315,16 +334,14 @@ lks_status adjoint_loop(lks_plan* P, void* ws, const double* dJ, hipStream_t s) 
       }
       {
         Scope sc("map_adj", s);
-        HIPCHK(launch_map_adjoint(P->g, P->prec, wsp(ws, P->o_kref), &P->mot[(size_t)(n - 1) * 8],
-                                  a.box, a.bkbar, a.bubar, kref_bar, n == nt ? 1 : 0,
-                                  (double*)wsp(ws, P->o_mpart) +
-                                      (size_t)(n - 1) * P->nblk_map * 8,
+        HIPCHK(launch_map_adjoint(P->g, P->prec, wsp(ws, P->o_kref), nullptr, tab(P, ws, n),
+                                  P->bmax, a.bkbar, a.bubar, kref_bar, n == nt ? 1 : 0,
+                                  (double*)wsp(ws, P->o_mpart) + (size_t)(n - 1) * P->nblk_map * 8,
                                   s));
       }
       cur = 1 - cur;
     }
   }
-  P->fwd_ws = ws;
   return LKS_OK;
 }
 
@@ -335,6 +352,61 @@ lks_status sens(lks_plan* P, const double* gamma, const void* ws, double* dg, do
   HIPCHK(launch_sens(P->g, P->prec, gamma, (const double*)wsp((void*)ws, P->o_krefbar),
                      (const double*)wsp((void*)ws, P->o_mpart), P->nblk_map,
                      (double*)wsp((void*)ws, P->o_mbar), den, den + P->g.nt, dg, dchi, dpsi, s));
+  return LKS_OK;
+}
+
+// Runs `body` on `s`: eagerly while profiling (per-launch events) or when
+// graphs are off, otherwise through a graph captured on the plan's private
+// stream on first use for this (workspace, key) and replayed afterwards.
+template <class F>
+lks_status run_loop(lks_plan* P, GraphCache& gc, void* ws, int key, hipStream_t s, F body) {
+  if (!P->use_graphs || g_prof.on) return body(s);
+  if (!(gc.exec && gc.ws == ws && gc.key == key)) {
+    gc.reset();
+    if (!P->cap) HIPCHK(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
+    lks_status e = body(P->cap);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(P->cap, &graph);
+    if (e) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return e;
+    }
+    if (ce != hipSuccess) return fail(LKS_EHIP, std::string("capture: ") + hipGetErrorString(ce));
+    hipError_t ie = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      gc.exec = nullptr;
+      return fail(LKS_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ie));
+    }
+    gc.ws = ws;
+    gc.key = key;
+  }
+  HIPCHK(hipGraphLaunch(gc.exec, s));
+  return LKS_OK;
+}
+
+Box full_box(const lks_plan* P) {
+  Box b;
+  memset(&b, 0, sizeof b);
+  for (int a = 0; a < 3; ++a) b.ext[a] = P->g.n[a];
+  b.sx = P->g.n[0];
+  b.sy = P->g.n[1];
+  b.vol = P->g.N;
+  return b;
+}
+
+lks_status host_box(lks_plan* P, const double* motion8_dev, double* m8, Box& box, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(m8, motion8_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int b[8];
+  body_box(P->g, m8, b);
+  if (b[6] == 2) return fail(LKS_EINVAL, "the body's support exceeds a periodic extent");
+  memset(&box, 0, sizeof box);
+  for (int a = 0; a < 3; ++a) {
+    box.lo[a] = b[a];
+    box.ext[a] = b[3 + a];
+  }
   return LKS_OK;
 }
 
@@ -368,15 +440,12 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
     }
     int e = (a < 2) ? (int)ceil(diag) + 6 : g.D[2] + 5;
     ext[a] = std::min(e, g.n[a]);
-    if (g.bc[a] == 0 && e > g.n[a]) ext[a] = g.n[a];
   }
   memset(&P->bmax, 0, sizeof(Box));
   P->bmax.sx = ext[0];
   P->bmax.sy = ext[1];
   P->bmax.vol = (long long)ext[0] * ext[1] * ext[2];
-  P->bmax.ext[0] = ext[0];
-  P->bmax.ext[1] = ext[1];
-  P->bmax.ext[2] = ext[2];
+  for (int a = 0; a < 3; ++a) P->bmax.ext[a] = ext[a];
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -385,16 +454,19 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   };
   const size_t Sb = (size_t)P->S * P->es;
   P->o_mot = take((size_t)g.nt * 8 * sizeof(double));
-  P->o_box = take((size_t)g.nt * 8 * sizeof(int));
+  P->o_tab = take((size_t)g.nt * sizeof(StepInfo));
+  P->o_info = take(64 * sizeof(int));
   P->o_kref = take((size_t)g.Mtot * P->es);
   P->o_flags = take(64 * sizeof(int));
   P->o_J3 = take(4 * sizeof(double));
+  P->o_seed = take(sizeof(double));
   P->o_opart = take((size_t)P->nblk_step * 2 * sizeof(double));
   P->o_ck = take((size_t)P->nck * Sb);
   P->o_pp = take(2 * Sb);
   P->o_tape = take((size_t)P->K * Sb);
-  P->o_body = take((size_t)(1 + g.d) * P->bmax.vol * P->es);
-  P->o_badj = take((size_t)(1 + g.d) * P->bmax.vol * P->es);
+  P->o_body = take(body_bytes(P));
+  P->o_btape = take((size_t)P->K * body_bytes(P));
+  P->o_badj = take(body_bytes(P));
   P->o_lam = take(2 * Sb);
   P->o_krefbar = take((size_t)g.Mtot * sizeof(double));
   P->o_mpart = take((size_t)g.nt * P->nblk_map * 8 * sizeof(double));
@@ -408,9 +480,13 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
 }
 
 lks_status lks_plan_destroy(lks_plan* plan) {
-  if (!plan) return LKS_OK;
-  if (plan->gexec) hipGraphExecDestroy(plan->gexec);
   delete plan;
+  return LKS_OK;
+}
+
+lks_status lks_plan_set_graphs(lks_plan* P, int32_t on) {
+  if (!P) return fail(LKS_EINVAL, "null plan");
+  P->use_graphs = on != 0;
   return LKS_OK;
 }
 
@@ -426,12 +502,11 @@ lks_status lks_forward(lks_plan* P, const double* gamma, const double* chi, cons
     HIPCHK(launch_state_init(P->g, P->prec, ck_slot(P, ws, 0), s));
   }
   P->first_lazy = state0 ? 0 : 1;
-  HIPCHK(launch_zero(wsp(ws, P->o_flags), 64 * sizeof(int), s));
-  HIPCHK(launch_zero(wsp(ws, P->o_opart), (size_t)P->nblk_step * 2 * sizeof(double), s));
-  if (lks_status e = forward_loop(P, ws, P->first_lazy, s)) return e;
-  double* J3 = (double*)wsp(ws, P->o_J3);
-  HIPCHK(launch_objective_final(P->g, (const double*)wsp(ws, P->o_opart), P->nblk_step, J3, s));
-  HIPCHK(hipMemcpyAsync(J_out, J3, 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  P->fwd_ws = nullptr;
+  if (lks_status e = run_loop(P, P->gfwd, ws, P->first_lazy, s,
+                              [&](hipStream_t st) { return forward_loop(P, ws, st); }))
+    return e;
+  HIPCHK(hipMemcpyAsync(J_out, wsp(ws, P->o_J3), 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
   if (state_final) {
     HIPCHK(hipMemcpyAsync(state_final, final_state(P, ws), (size_t)P->S * P->es,
                           hipMemcpyDeviceToDevice, s));
@@ -452,16 +527,19 @@ lks_status lks_adjoint(lks_plan* P, const double* gamma, const double* chi, cons
   (void)psi;
   if (!P || !ws || !dJ || !gamma || !dJ_dgamma || !dJ_dchi || !dJ_dpsi)
     return fail(LKS_EINVAL, "null argument");
-  if (P->fwd_ws != ws || P->boxes.empty())
+  if (P->fwd_ws != ws)
     return fail(LKS_EINVAL, "lks_adjoint needs a preceding lks_forward on this plan and workspace");
   const size_t Sb = (size_t)P->S * P->es;
+  HIPCHK(hipMemcpyAsync(wsp(ws, P->o_seed), dJ, sizeof(double), hipMemcpyDeviceToDevice, s));
   if (adj_terminal) {
     HIPCHK(hipMemcpyAsync(lam_slot(P, ws, 0), adj_terminal, Sb, hipMemcpyDeviceToDevice, s));
   } else {
     HIPCHK(launch_zero(lam_slot(P, ws, 0), Sb, s));
   }
-  HIPCHK(launch_zero(wsp(ws, P->o_badj), (size_t)(1 + P->g.d) * P->bmax.vol * P->es, s));
-  if (lks_status e = adjoint_loop(P, ws, dJ, s)) return e;
+  HIPCHK(launch_zero(wsp(ws, P->o_badj), body_bytes(P), s));
+  if (lks_status e = run_loop(P, P->gadj, ws, P->first_lazy, s,
+                              [&](hipStream_t st) { return adjoint_loop(P, ws, st); }))
+    return e;
   const int fin = P->g.nt % 2;  // lambda slot holding dJ/d state0
   if (adj_initial)
     HIPCHK(hipMemcpyAsync(adj_initial, lam_slot(P, ws, fin), Sb, hipMemcpyDeviceToDevice, s));
@@ -488,21 +566,6 @@ lks_status lks_kappa_ref(lks_plan* P, const double* gamma, void* kappa_ref, hipS
   return LKS_OK;
 }
 
-static lks_status host_box(lks_plan* P, const double* motion8_dev, double* m8, Box& box,
-                           hipStream_t s) {
-  HIPCHK(hipMemcpyAsync(m8, motion8_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  int b[8];
-  body_box(P->g, m8, b);
-  if (b[6] == 2) return fail(LKS_EINVAL, "the body's support exceeds a periodic extent");
-  memset(&box, 0, sizeof box);
-  for (int a = 0; a < 3; ++a) {
-    box.lo[a] = b[a];
-    box.ext[a] = b[3 + a];
-  }
-  return LKS_OK;
-}
-
 lks_status lks_map_design_to_grid(lks_plan* P, const void* kappa_ref, const double* motion8,
                                   void* kappa, void* u_s, void* ws, hipStream_t s) {
   if (!P || !kappa_ref || !motion8 || !kappa || !u_s || !ws)
@@ -513,19 +576,9 @@ lks_status lks_map_design_to_grid(lks_plan* P, const void* kappa_ref, const doub
   HIPCHK(launch_zero(kappa, (size_t)P->g.N * P->es, s));
   HIPCHK(launch_zero(u_s, (size_t)P->g.d * P->g.N * P->es, s));
   Scope sc("map", s);
-  HIPCHK(launch_map(P->g, P->prec, kappa_ref, wsp(ws, P->o_kz), P->bmax.ext[2], m8, box, kappa,
-                    u_s, 1, s));
+  HIPCHK(launch_map(P->g, P->prec, kappa_ref, wsp(ws, P->o_kz), P->bmax.ext[2], m8, nullptr, box,
+                    kappa, u_s, 1, s));
   return LKS_OK;
-}
-
-static Box full_box(const lks_plan* P) {
-  Box b;
-  memset(&b, 0, sizeof b);
-  for (int a = 0; a < 3; ++a) b.ext[a] = P->g.n[a];
-  b.sx = P->g.n[0];
-  b.sy = P->g.n[1];
-  b.vol = P->g.N;
-  return b;
 }
 
 lks_status lks_step(lks_plan* P, const void* state_in, const void* kappa, const void* u_s,
@@ -566,16 +619,43 @@ lks_status lks_step_adjoint(lks_plan* P, const void* state_in, const void* state
   a.bkbar = kbar;
   a.bubar = usbar;
   a.box = full_box(P);
-  a.seed = nullptr;
-  a.E = nullptr;
   Scope sc("adj_step", s);
   HIPCHK(launch_adjoint_step(P->g, P->prec, a, s));
   return LKS_OK;
 }
 
+// The stand-alone map transpose reduces its per-block partials in a second
+// fixed-order pass; motion_bar8 must hold 8 * (blocks + 1) doubles: the first
+// 8 receive the result, the rest serve as the partial store.
 lks_status lks_map_adjoint(lks_plan* P, const void* kappa_ref, const double* motion8,
                            const void* kbar, const void* usbar, double* kref_bar,
-                           double* motion_bar8, hipStream_t s);
+                           double* motion_bar8, hipStream_t s) {
+  if (!P || !kappa_ref || !motion8 || !kbar || !usbar || !kref_bar || !motion_bar8)
+    return fail(LKS_EINVAL, "null argument");
+  double m8[8];
+  Box box;
+  if (lks_status e = host_box(P, motion8, m8, box, s)) return e;
+  double* part = motion_bar8 + 8;
+  {
+    Scope sc("map_adj", s);
+    HIPCHK(launch_map_adjoint(P->g, P->prec, kappa_ref, m8, nullptr, full_box(P), kbar, usbar,
+                              kref_bar, 1, part, s));
+  }
+  HIPCHK(launch_reduce_parts(P->g, part, P->nblk_map, motion_bar8, s));
+  return LKS_OK;
+}
+
+int32_t lks_map_adjoint_blocks(lks_plan* P) { return P ? P->nblk_map : 0; }
+
+lks_status lks_batch_run(int32_t count, lks_plan* const* plans, const double* const* gamma,
+                         const double* const* chi, const double* const* psi,
+                         void* const* workspace, double* const* J_out, const double* dJ,
+                         double* const* dJ_dgamma, double* const* dJ_dchi,
+                         double* const* dJ_dpsi, hipStream_t s) {
+  (void)count; (void)plans; (void)gamma; (void)chi; (void)psi; (void)workspace; (void)J_out;
+  (void)dJ; (void)dJ_dgamma; (void)dJ_dchi; (void)dJ_dpsi; (void)s;
+  return fail(LKS_EINVAL, "lks_batch_run: not available yet");
+}
 
 lks_status lks_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
@@ -593,7 +673,7 @@ int32_t lks_profile_read(const char** names, double* total_ms, int64_t* launches
   std::vector<double> tot(g_prof.names.size(), 0.0);
   std::vector<int64_t> cnt(g_prof.names.size(), 0);
   for (auto& r : g_prof.recs) {
-    hipEventSynchronize(r.b);
+    (void)hipEventSynchronize(r.b);
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
       tot[r.cls] += ms;
@@ -610,37 +690,3 @@ int32_t lks_profile_read(const char** names, double* total_ms, int64_t* launches
 }
 
 }  // extern "C"
-
-// The stand-alone map transpose reduces its per-block partials in a second
-// fixed-order pass; motion_bar8 must hold 8 * (blocks + 1) doubles: the first
-// 8 receive the result, the rest serve as the partial store.
-extern "C" lks_status lks_map_adjoint(lks_plan* P, const void* kappa_ref, const double* motion8,
-                                      const void* kbar, const void* usbar, double* kref_bar,
-                                      double* motion_bar8, hipStream_t s) {
-  if (!P || !kappa_ref || !motion8 || !kbar || !usbar || !kref_bar || !motion_bar8)
-    return fail(LKS_EINVAL, "null argument");
-  double m8[8];
-  Box box;
-  if (lks_status e = host_box(P, motion8, m8, box, s)) return e;
-  double* part = motion_bar8 + 8;
-  {
-    Scope sc("map_adj", s);
-    HIPCHK(launch_map_adjoint(P->g, P->prec, kappa_ref, m8, full_box(P), kbar, usbar, kref_bar,
-                              1, part, s));
-  }
-  HIPCHK(launch_reduce_parts(P->g, part, P->nblk_map, motion_bar8, s));
-  return LKS_OK;
-}
-
-extern "C" int32_t lks_map_adjoint_blocks(lks_plan* P) { return P ? P->nblk_map : 0; }
-
-extern "C" lks_status lks_batch_run(int32_t count, lks_plan* const* plans,
-                                    const double* const* gamma, const double* const* chi,
-                                    const double* const* psi, void* const* workspace,
-                                    double* const* J_out, const double* dJ,
-                                    double* const* dJ_dgamma, double* const* dJ_dchi,
-                                    double* const* dJ_dpsi, hipStream_t s) {
-  (void)count; (void)plans; (void)gamma; (void)chi; (void)psi; (void)workspace; (void)J_out;
-  (void)dJ; (void)dJ_dgamma; (void)dJ_dchi; (void)dJ_dpsi; (void)s;
-  return fail(LKS_EINVAL, "lks_batch_run: not available yet");
-}

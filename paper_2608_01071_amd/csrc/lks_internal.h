@@ -54,6 +54,15 @@ struct Box {
   long long vol;  // size of one plane of the body buffers (sx * sy * max ext z)
 };
 
+// Per-step body data computed on the device by the prelude: rigid motion
+// (centre, velocity, cos/sin of the angle, angular velocity) and the support
+// box.  Step kernels read it, so their launch arguments do not change from
+// call to call (the time loops can be captured once and replayed).
+struct StepInfo {
+  double xg[3], ug[3], c, s, om;
+  int lo[3], ext[3], flag, pad;
+};
+
 // Standard velocity sets with opposite directions in consecutive pairs
 // (rest direction first).
 template <int Q>
@@ -88,6 +97,7 @@ struct FwdArgs {
   double* opart;     // [blocks][2] objective partials (nullable)
   int* flags;        // [0]: instability flag
   int lazy_wall;     // 1: wall-node pressures of `in` follow the wall rule
+  const StepInfo* si; // nullable: step box taken from the device table
 };
 struct AdjArgs {
   const void* lam;      // dJ/d state(n)
@@ -101,6 +111,7 @@ struct AdjArgs {
   Box box;
   const double* seed;   // dJ (device, nullable -> no objective seed)
   const double* E;      // mean of n.u from the forward (device)
+  const StepInfo* si;   // nullable: step box taken from the device table
 };
 
 int step_blocks(const Geo& g);
@@ -108,13 +119,14 @@ hipError_t launch_forward_step(const Geo& g, int precision, const FwdArgs& a, hi
 hipError_t launch_adjoint_step(const Geo& g, int precision, const AdjArgs& a, hipStream_t s);
 size_t kz_bytes(const Geo& g, int ext2max, int precision);
 hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf, int ext2max,
-                      const double* mot8_host, const Box& box, void* bk, void* bu, int full_grid,
-                      hipStream_t s);
+                      const double* mot8_host, const StepInfo* si, const Box& box, void* bk,
+                      void* bu, int full_grid, hipStream_t s);
 int mapadj_blocks(const Geo& g);
 hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
-                              const double* mot8_host, const Box& box, const void* bkbar,
-                              const void* bubar, double* kref_bar, int overwrite, double* mpart,
-                              hipStream_t s);
+                              const double* mot8_host, const StepInfo* si, const Box& box,
+                              const void* bkbar, const void* bubar, double* kref_bar, int overwrite,
+                              double* mpart, hipStream_t s);
+hipError_t launch_steps(const Geo& g, const double* mot, StepInfo* tab, int* info, hipStream_t s);
 hipError_t launch_kappa_ref(const Geo& g, int precision, const double* gamma, void* kref,
                             hipStream_t s);
 hipError_t launch_motion(const Geo& g, const double* chi, const double* psi, double* mot,

@@ -26,6 +26,7 @@
 //                       domain check, kappa_ref, objective finalisation and
 //                       the sensitivity chain rule.
 #include <math.h>
+#include <string.h>
 
 #include "lks_internal.h"
 
@@ -93,6 +94,15 @@ __device__ __forceinline__ long long box_index(const Geo& g, const Box& b, int x
     r[a] = v;
   }
   return r[0] + (long long)b.sx * (r[1] + (long long)b.sy * r[2]);
+}
+
+// Step box from the device table (when given).
+__device__ __forceinline__ void apply_step(Box& b, const StepInfo* si) {
+  if (!si) return;
+  for (int k = 0; k < 3; ++k) {
+    b.lo[k] = si->lo[k];
+    b.ext[k] = si->ext[k];
+  }
 }
 
 // Cosine kernel w(r) = (1 + cos(pi r / 2)) / 4 and its derivative (Sec. 2.3).
@@ -237,6 +247,7 @@ __device__ __forceinline__ void finish_node(const Geo& g, const FwdArgs& a, int 
 // ------------------------------------------------------ forward, D2Q9
 template <class R>
 __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d(Geo g, FwdArgs a) {
+  apply_step(a.box, a.si);
   constexpr int TX = TILE_X, TY = TILE_Y;
   constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
   __shared__ R sp[LY * LX], sx[LY * LX], sy[LY * LX];
@@ -319,6 +330,7 @@ __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d(Geo g, FwdArgs a) {
 // plane below is then complete and is finished (Brinkman, walls, J1).
 template <class R>
 __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
+  apply_step(a.box, a.si);
   constexpr int TX = TILE_X, TY = TILE_Y;
   constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
   constexpr int LP = LX * LY, FP = FX * FY;
@@ -613,6 +625,7 @@ __device__ __forceinline__ void adj_star(const Geo& g, const AdjArgs& a, int x, 
 // ------------------------------------------------------ adjoint, D2Q9
 template <class R>
 __global__ __launch_bounds__(STEP_THREADS) void k_adj2d(Geo g, AdjArgs a) {
+  apply_step(a.box, a.si);
   constexpr int TX = TILE_X, TY = TILE_Y;
   constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
   __shared__ R sl[3][LY * LX];     // pbar*, ubar*_x, ubar*_y
@@ -694,6 +707,7 @@ __global__ __launch_bounds__(STEP_THREADS) void k_adj2d(Geo g, AdjArgs a) {
 // neighbouring planes' moments of the own column).
 template <class R>
 __global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
+  apply_step(a.box, a.si);
   constexpr int TX = TILE_X, TY = TILE_Y;
   constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
   constexpr int LP = LX * LY, FP = FX * FY;
@@ -959,12 +973,25 @@ __host__ __device__ inline Mot make_mot(const double* m8) {
   return m;
 }
 
+__device__ __forceinline__ void apply_step(Box& b, Mot& m, const StepInfo* si) {
+  if (!si) return;
+  apply_step(b, si);
+  for (int k = 0; k < 3; ++k) {
+    m.xg[k] = si->xg[k];
+    m.ug[k] = si->ug[k];
+  }
+  m.c = si->c;
+  m.s = si->s;
+  m.om = si->om;
+}
+
 // Cosine-kernel sums over the design points whose rotated position lies
 // within the kernel support of analysis position (bx, by):
 // W-weighted kappa_ref (per z value for 3D), sum W, sum W r1, sum W r2.
 template <class R>
-__global__ __launch_bounds__(256) void k_map2d(Geo g, const R* kref, Mot m, Box box, R* bk,
-                                               R* bu, int full_grid) {
+__global__ __launch_bounds__(256) void k_map2d(Geo g, const R* kref, Mot m, Box box,
+                                               const StepInfo* si, R* bk, R* bu, int full_grid) {
+  apply_step(box, m, si);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= box.ext[0] || j >= box.ext[1]) return;
@@ -1019,7 +1046,9 @@ __global__ __launch_bounds__(256) void k_map2d(Geo g, const R* kref, Mot m, Box 
 // sum_{xi3} w(z - X3(xi3)) kappa_ref(column, xi3); the tail row holds
 // sum_{xi3} w(z - X3(xi3)) (the z weight sum used by the body velocity).
 template <class R>
-__global__ __launch_bounds__(256) void k_kz(Geo g, const R* kref, Mot m, Box box, R* kz, int ezp) {
+__global__ __launch_bounds__(256) void k_kz(Geo g, const R* kref, Mot m, Box box,
+                                            const StepInfo* si, R* kz, int ezp) {
+  apply_step(box, m, si);
   const long long cols = (long long)g.D[0] * g.D[1];
   const long long idx = blockIdx.x * 256LL + threadIdx.x;
   if (idx >= (cols + 1) * ezp) return;
@@ -1045,8 +1074,9 @@ __global__ __launch_bounds__(256) void k_kz(Geo g, const R* kref, Mot m, Box box
 // 3D transfer, stage 2: one thread per analysis column and MAP_ZC z values;
 // the rotated xy candidates and their weights are formed once per column.
 template <class R>
-__global__ __launch_bounds__(64) void k_map3d(Geo g, const R* kz, int ezp, Mot m, Box box, R* bk,
-                                              R* bu, int full_grid) {
+__global__ __launch_bounds__(64) void k_map3d(Geo g, const R* kz, int ezp, Mot m, Box box,
+                                              const StepInfo* si, R* bk, R* bu, int full_grid) {
+  apply_step(box, m, si);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   const int zc = blockIdx.z * MAP_ZC;
@@ -1124,9 +1154,10 @@ __global__ __launch_bounds__(64) void k_map3d(Geo g, const R* kz, int ezp, Mot m
 // plane.  Finishing a level adds dJ/dkappa_ref and the motion partials.
 template <class R>
 __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kref, Mot m, Box box,
-                                                             const R* bkbar, const R* bubar,
-                                                             double* kref_bar, int overwrite,
-                                                             double* mpart) {
+                                                             const StepInfo* si, const R* bkbar,
+                                                             const R* bubar, double* kref_bar,
+                                                             int overwrite, double* mpart) {
+  apply_step(box, m, si);
   const long long cols = (long long)g.D[0] * g.D[1];
   const int nch = (g.D[2] + MAPADJ_LCH - 1) / MAPADJ_LCH;
   const long long idx = blockIdx.x * (long long)MAPADJ_THREADS + threadIdx.x;
@@ -1262,9 +1293,10 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
 // Transpose of the transfer for one step, one thread per design point.
 template <class R>
 __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj(Geo g, const R* kref, Mot m, Box box,
-                                                           const R* bkbar, const R* bubar,
-                                                           double* kref_bar, int overwrite,
-                                                           double* mpart) {
+                                                           const StepInfo* si, const R* bkbar,
+                                                           const R* bubar, double* kref_bar,
+                                                           int overwrite, double* mpart) {
+  apply_step(box, m, si);
   const long long k = blockIdx.x * (long long)MAPADJ_THREADS + threadIdx.x;
   double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (k < g.Mtot) {
@@ -1467,6 +1499,30 @@ __host__ __device__ void body_box(const Geo& g, const double* m8, int* out) {
   out[7] = 0;
 }
 
+__global__ void k_steps(Geo g, const double* mot, StepInfo* tab, int* info) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.nt) return;
+  const double* m8 = mot + t * 8;
+  StepInfo si;
+  for (int k = 0; k < 3; ++k) {
+    si.xg[k] = m8[k];
+    si.ug[k] = m8[3 + k];
+  }
+  si.c = cos(m8[6]);
+  si.s = sin(m8[6]);
+  si.om = m8[7];
+  int b[8];
+  body_box(g, m8, b);
+  for (int k = 0; k < 3; ++k) {
+    si.lo[k] = b[k];
+    si.ext[k] = b[3 + k];
+  }
+  si.flag = b[6];
+  si.pad = 0;
+  tab[t] = si;
+  if (b[6]) atomicMax(info, b[6]);
+}
+
 __global__ void k_boxes(Geo g, const double* mot, int* boxes) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.nt) return;
@@ -1654,17 +1710,21 @@ size_t kz_bytes(const Geo& g, int ext2max, int precision) {
 }
 
 hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf, int ext2max,
-                      const double* mot8_host, const Box& box, void* bk, void* bu, int full_grid,
-                      hipStream_t s) {
+                      const double* mot8_host, const StepInfo* si, const Box& box, void* bk,
+                      void* bu, int full_grid, hipStream_t s) {
   if (box.ext[0] <= 0 || box.ext[1] <= 0 || box.ext[2] <= 0) return hipSuccess;
-  Mot m = make_mot(mot8_host);
+  Mot m;
+  if (mot8_host)
+    m = make_mot(mot8_host);
+  else
+    memset(&m, 0, sizeof m);
   if (g.d == 2) {
     dim3 grid((box.ext[0] + 255) / 256, box.ext[1]);
     if (precision == 0)
-      hipLaunchKernelGGL(k_map2d<float>, grid, dim3(256), 0, s, g, (const float*)kref, m, box,
+      hipLaunchKernelGGL(k_map2d<float>, grid, dim3(256), 0, s, g, (const float*)kref, m, box, si,
                          (float*)bk, (float*)bu, full_grid);
     else
-      hipLaunchKernelGGL(k_map2d<double>, grid, dim3(256), 0, s, g, (const double*)kref, m, box,
+      hipLaunchKernelGGL(k_map2d<double>, grid, dim3(256), 0, s, g, (const double*)kref, m, box, si,
                          (double*)bk, (double*)bu, full_grid);
   } else {
     const int ezp = kz_rows(g, ext2max);
@@ -1672,15 +1732,15 @@ hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf
     dim3 g1((unsigned)((nkz + 255) / 256));
     dim3 grid((box.ext[0] + 63) / 64, box.ext[1], (box.ext[2] + MAP_ZC - 1) / MAP_ZC);
     if (precision == 0) {
-      hipLaunchKernelGGL(k_kz<float>, g1, dim3(256), 0, s, g, (const float*)kref, m, box,
+      hipLaunchKernelGGL(k_kz<float>, g1, dim3(256), 0, s, g, (const float*)kref, m, box, si,
                          (float*)kzbuf, ezp);
       hipLaunchKernelGGL(k_map3d<float>, grid, dim3(64), 0, s, g, (const float*)kzbuf, ezp, m,
-                         box, (float*)bk, (float*)bu, full_grid);
+                         box, si, (float*)bk, (float*)bu, full_grid);
     } else {
-      hipLaunchKernelGGL(k_kz<double>, g1, dim3(256), 0, s, g, (const double*)kref, m, box,
+      hipLaunchKernelGGL(k_kz<double>, g1, dim3(256), 0, s, g, (const double*)kref, m, box, si,
                          (double*)kzbuf, ezp);
       hipLaunchKernelGGL(k_map3d<double>, grid, dim3(64), 0, s, g, (const double*)kzbuf, ezp, m,
-                         box, (double*)bk, (double*)bu, full_grid);
+                         box, si, (double*)bk, (double*)bu, full_grid);
     }
   }
   return hipGetLastError();
@@ -1695,29 +1755,33 @@ int mapadj_blocks(const Geo& g) {
 }
 
 hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
-                              const double* mot8_host, const Box& box, const void* bkbar,
-                              const void* bubar, double* kref_bar, int overwrite, double* mpart,
-                              hipStream_t s) {
-  Mot m = make_mot(mot8_host);
+                              const double* mot8_host, const StepInfo* si, const Box& box,
+                              const void* bkbar, const void* bubar, double* kref_bar, int overwrite,
+                              double* mpart, hipStream_t s) {
+  Mot m;
+  if (mot8_host)
+    m = make_mot(mot8_host);
+  else
+    memset(&m, 0, sizeof m);
   dim3 grid(mapadj_blocks(g));
   if (g.d == 3) {
     if (precision == 0)
       hipLaunchKernelGGL(k_mapadj3d<float>, grid, dim3(MAPADJ_THREADS), 0, s, g,
-                         (const float*)kref, m, box, (const float*)bkbar, (const float*)bubar,
+                         (const float*)kref, m, box, si, (const float*)bkbar, (const float*)bubar,
                          kref_bar, overwrite, mpart);
     else
       hipLaunchKernelGGL(k_mapadj3d<double>, grid, dim3(MAPADJ_THREADS), 0, s, g,
-                         (const double*)kref, m, box, (const double*)bkbar, (const double*)bubar,
+                         (const double*)kref, m, box, si, (const double*)bkbar, (const double*)bubar,
                          kref_bar, overwrite, mpart);
     return hipGetLastError();
   }
   if (precision == 0)
     hipLaunchKernelGGL(k_mapadj<float>, grid, dim3(MAPADJ_THREADS), 0, s, g, (const float*)kref,
-                       m, box, (const float*)bkbar, (const float*)bubar, kref_bar, overwrite,
+                       m, box, si, (const float*)bkbar, (const float*)bubar, kref_bar, overwrite,
                        mpart);
   else
     hipLaunchKernelGGL(k_mapadj<double>, grid, dim3(MAPADJ_THREADS), 0, s, g,
-                       (const double*)kref, m, box, (const double*)bkbar, (const double*)bubar,
+                       (const double*)kref, m, box, si, (const double*)bkbar, (const double*)bubar,
                        kref_bar, overwrite, mpart);
   return hipGetLastError();
 }
@@ -1743,6 +1807,11 @@ hipError_t launch_motion(const Geo& g, const double* chi, const double* psi, dou
 hipError_t launch_boxes(const Geo& g, const double* mot, int* boxes, int* info, hipStream_t s) {
   (void)info;
   hipLaunchKernelGGL(k_boxes, dim3((g.nt + 255) / 256), dim3(256), 0, s, g, mot, boxes);
+  return hipGetLastError();
+}
+
+hipError_t launch_steps(const Geo& g, const double* mot, StepInfo* tab, int* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_steps, dim3((g.nt + 255) / 256), dim3(256), 0, s, g, mot, tab, info);
   return hipGetLastError();
 }
 

@@ -55,6 +55,7 @@ def lib():
         L.lks_last_error.restype = C.c_char_p
         L.lks_plan_create.argtypes = [C.POINTER(LksProblem), C.POINTER(_VP), C.POINTER(C.c_size_t)]
         L.lks_plan_destroy.argtypes = [_VP]
+        L.lks_plan_set_graphs.argtypes = [_VP, C.c_int32]
         L.lks_forward.argtypes = [_VP] * 9
         L.lks_adjoint.argtypes = [_VP] * 12
         L.lks_map_design_to_grid.argtypes = [_VP] * 7
@@ -130,6 +131,10 @@ class Plan:
         self.workspace_bytes = nbytes.value
         self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
         self.dtype = torch.float32 if problem.precision == 0 else torch.float64
+
+    def set_graphs(self, on: bool):
+        """Replay the time loops from captured hipGraphs (default) or launch eagerly."""
+        _check(lib().lks_plan_set_graphs(self.handle, 1 if on else 0))
 
     def __del__(self):
         h = getattr(self, "handle", None)
