@@ -191,6 +191,17 @@ void fill_geo(const lks_problem& p, Geo& g) {
   // tile-grid origin: keeps every node's wall-stencil partners within one tile halo
   const int tile[2] = {TILE_X, TILE_Y};
   for (int a = 0; a < 2; ++a) g.org[a] = (g.bc[a] == 1 && g.n[a] % tile[a] == 2) ? -1 : 0;
+  // z segments: enough blocks to fill every CU with STEP_RESIDENT blocks, but
+  // no segment shorter than 4 planes (each segment re-reads 2 halo planes)
+  g.zseg = 1;
+  if (g.d == 3) {
+    const long long tiles = (long long)((g.n[0] - g.org[0] + TILE_X - 1) / TILE_X) *
+                            ((g.n[1] - g.org[1] + TILE_Y - 1) / TILE_Y);
+    const long long want = (long long)STEP_RESIDENT * CU_COUNT;
+    long long nseg = std::max(1LL, (want + tiles - 1) / tiles);
+    int zs = (int)((g.n[2] + nseg - 1) / nseg);
+    g.zseg = std::max(std::min(zs, g.n[2]), std::min(4, g.n[2]));
+  }
 }
 
 char* wsp(void* ws, size_t off) { return (char*)ws + off; }

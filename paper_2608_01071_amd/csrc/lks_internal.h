@@ -13,14 +13,17 @@ constexpr int TILE_Y = 8;
 constexpr int STEP_THREADS = TILE_X * TILE_Y;
 // 3D step kernels: enough threads for the whole 1-node halo region (34 x 10).
 constexpr int THREADS3D = 384;
-// z planes per block segment of the 3D kernels.
-constexpr int ZSEG = 16;
+// Resident blocks per CU the 3D step kernels are sized for (LDS-limited) and
+// the CU count of the target; the z-segment length is chosen so the grid is
+// about STEP_RESIDENT * CU_COUNT blocks.
+constexpr int STEP_RESIDENT = 3;
+constexpr int CU_COUNT = 256;
 // design points per block of the map transpose.
 constexpr int MAPADJ_THREADS = 256;
 // 3D map: z values per thread.
 constexpr int MAP_ZC = 16;
 // 3D map transpose: design levels per thread.
-constexpr int MAPADJ_LCH = 8;
+constexpr int MAPADJ_LCH = 4;
 
 // Device copy of the problem (passed by value to every kernel).
 struct Geo {
@@ -43,6 +46,7 @@ struct Geo {
   int nt, r_t, r_w;
   double xmin[3], xmax[3], thmin, thmax;
   int org[3];             // tile-grid origin per axis (0 or -1)
+  int zseg;               // z planes per block segment (3D step kernels)
 };
 
 // Support box of the body at one step, in unwrapped analysis coordinates;

@@ -321,7 +321,7 @@ __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d(Geo g, FwdArgs a) {
 }
 
 // ------------------------------------------------------ forward, D3Q15
-// Block = one 32x8 column tile marching z over a ZSEG segment.  Per plane:
+// Block = one 32x8 column tile marching z over a g.zseg segment.  Per plane:
 // (1) the (p, u) plane with a 2-node halo enters a 3-plane LDS ring from
 // registers fetched one iteration earlier (the global loads of the next
 // plane overlap this plane's arithmetic); (2) the 15 equilibria of the
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
   const long long N = g.N;
   const int nz = g.n[2];
   const int x0 = blockIdx.x * TX + g.org[0], y0 = blockIdx.y * TY + g.org[1];
-  const int z0 = blockIdx.z * ZSEG, z1 = min(z0 + ZSEG, nz);
+  const int z0 = blockIdx.z * g.zseg, z1 = min(z0 + g.zseg, nz);
 
   // per-thread load slots of the halo plane (fixed over the march)
   long long lofs[NLD];
@@ -722,7 +722,7 @@ __global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
   const int nz = g.n[2];
   const long long NP = (long long)g.n[0] * g.n[1];
   const int x0 = blockIdx.x * TX + g.org[0], y0 = blockIdx.y * TY + g.org[1];
-  const int z0 = blockIdx.z * ZSEG, z1 = min(z0 + ZSEG, nz);
+  const int z0 = blockIdx.z * g.zseg, z1 = min(z0 + g.zseg, nz);
   const double seed = a.seed ? a.seed[0] : 0.0;
   const double Ebar = a.seed ? a.E[0] : 0.0;
 
@@ -1660,7 +1660,7 @@ __global__ void k_zero(uint32_t* p, long long n) {
 static dim3 step_grid(const Geo& g) {
   const int bx = (g.n[0] - g.org[0] + TILE_X - 1) / TILE_X;
   const int by = (g.n[1] - g.org[1] + TILE_Y - 1) / TILE_Y;
-  const int bz = g.d == 3 ? (g.n[2] + ZSEG - 1) / ZSEG : 1;
+  const int bz = g.d == 3 ? (g.n[2] + g.zseg - 1) / g.zseg : 1;
   return dim3(bx, by, bz);
 }
 int step_blocks(const Geo& g) {
