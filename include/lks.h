@@ -103,6 +103,11 @@ lks_status lks_plan_destroy(lks_plan* plan);
  * While lks_profile_enable is on, loops run eagerly (per-launch events). */
 lks_status lks_plan_set_graphs(lks_plan* plan, int32_t on);
 
+/* Tuning: z planes per block segment of the 3D step kernels (0 = automatic,
+ * sized to fill every CU).  Smaller values mean more blocks and more halo
+ * planes re-read per segment.  Ignored in 2D. */
+lks_status lks_plan_set_zseg(lks_plan* plan, int32_t zseg);
+
 /* Forward march (Algorithm 1, state loop; Sec. 2.2-2.4, 2.6).
  * state0: initial state (nullable: p = 1/3, u = 0 everywhere; the wall
  *   nodes' given p is used for the first step as is).

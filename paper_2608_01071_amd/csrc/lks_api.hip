@@ -294,7 +294,7 @@ lks_status forward_loop(lks_plan* P, void* ws, hipStream_t s) {
       return e;
     in = out;
   }
-  HIPCHK(launch_objective_final(P->g, (const double*)wsp(ws, P->o_opart), P->nblk_step,
+  HIPCHK(launch_objective_final(P->g, (const double*)wsp(ws, P->o_opart), step_blocks(P->g),
                                 (double*)wsp(ws, P->o_J3), s));
   return LKS_OK;
 }
@@ -440,6 +440,11 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   P->K = prob->ckpt_k == 0 ? g.nt : prob->ckpt_k;
   P->nck = (g.nt + P->K - 1) / P->K;
   P->nblk_step = step_blocks(g);
+  if (g.d == 3) {
+    Geo g4 = g;
+    g4.zseg = std::min(4, g.n[2]);
+    P->nblk_step = std::max(P->nblk_step, step_blocks(g4));
+  }
   P->nblk_map = mapadj_blocks(g);
   // body-box bound over any rotation about z and any translation
   const double diag = sqrt((double)(g.D[0] - 1) * (g.D[0] - 1) + (double)(g.D[1] - 1) * (g.D[1] - 1));
@@ -498,6 +503,28 @@ lks_status lks_plan_destroy(lks_plan* plan) {
 lks_status lks_plan_set_graphs(lks_plan* P, int32_t on) {
   if (!P) return fail(LKS_EINVAL, "null plan");
   P->use_graphs = on != 0;
+  return LKS_OK;
+}
+
+lks_status lks_plan_set_zseg(lks_plan* P, int32_t zseg) {
+  if (!P) return fail(LKS_EINVAL, "null plan");
+  if (P->g.d != 3) return LKS_OK;
+  if (zseg < 0) return fail(LKS_EINVAL, "zseg must be >= 0");
+  if (zseg == 0) {
+    Geo g2;
+    fill_geo(P->prob, g2);
+    zseg = g2.zseg;
+  }
+  zseg = std::min(zseg, P->g.n[2]);
+  if (zseg != P->g.zseg) {
+    // the step grid (and with it the objective partial slots) changes
+    Geo g2 = P->g;
+    g2.zseg = zseg;
+    if (step_blocks(g2) > P->nblk_step) return fail(LKS_EINVAL, "zseg too small for this plan");
+    P->g.zseg = zseg;
+    P->gfwd.reset();
+    P->gadj.reset();
+  }
   return LKS_OK;
 }
 

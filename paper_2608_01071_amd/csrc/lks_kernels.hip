@@ -137,6 +137,26 @@ __device__ __forceinline__ R dnumT(const Geo& g, int a, int v, const R* s, int c
   return r;
 }
 
+// XCD-aware tile order.  Workgroups are dealt to the 8 XCDs round robin by
+// their linear id, and each XCD has its own L2; this remap gives every XCD a
+// contiguous run of tiles (x fastest, then y, then z segment), so tiles that
+// share halo nodes run on the same XCD and hit the same L2.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_tile(int nbx, int nby, int nbz, int& bx, int& by, int& bz) {
+  const int total = nbx * nby * nbz;
+  const int b = blockIdx.x;
+  const int xcd = b % NUM_XCD, slot = b / NUM_XCD;
+  const int q = total / NUM_XCD, r = total % NUM_XCD;
+  const int t = (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+  bx = t % nbx;
+  by = (t / nbx) % nby;
+  bz = t / (nbx * nby);
+  return t;
+}
+__device__ __forceinline__ int tiles_x(const Geo& g) { return (g.n[0] - g.org[0] + TILE_X - 1) / TILE_X; }
+__device__ __forceinline__ int tiles_y(const Geo& g) { return (g.n[1] - g.org[1] + TILE_Y - 1) / TILE_Y; }
+__device__ __forceinline__ int tiles_z(const Geo& g) { return g.d == 3 ? (g.n[2] + g.zseg - 1) / g.zseg : 1; }
+
 // Inamuro equilibria for one node (pairs of opposite directions share
 // their even part).  S holds D_a u_b + D_b u_a.
 template <class R>
@@ -254,7 +274,9 @@ __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d(Geo g, FwdArgs a) {
   __shared__ R sf[9][FY * FX];
   const R* in = (const R*)a.in;
   const long long N = g.N;
-  const int x0 = blockIdx.x * TX + g.org[0], y0 = blockIdx.y * TY + g.org[1];
+  int tbx, tby, tbz;
+  const int tlin = xcd_tile(tiles_x(g), tiles_y(g), 1, tbx, tby, tbz);
+  const int x0 = tbx * TX + g.org[0], y0 = tby * TY + g.org[1];
   for (int k = threadIdx.x; k < LX * LY; k += STEP_THREADS) {
     int gx = x0 - 2 + k % LX, gy = y0 - 2 + k / LX;
     R p = R(0), ux = R(0), uy = R(0);
@@ -313,9 +335,8 @@ __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d(Geo g, FwdArgs a) {
     double tot[2];
     block_sum<2, STEP_THREADS>(v, tot);
     if (threadIdx.x == 0) {
-      const long long b = blockIdx.x + (long long)gridDim.x * blockIdx.y;
-      a.opart[2 * b] += tot[0];
-      a.opart[2 * b + 1] += tot[1];
+      a.opart[2 * tlin] += tot[0];
+      a.opart[2 * tlin + 1] += tot[1];
     }
   }
 }
@@ -340,8 +361,10 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
   const R* in = (const R*)a.in;
   const long long N = g.N;
   const int nz = g.n[2];
-  const int x0 = blockIdx.x * TX + g.org[0], y0 = blockIdx.y * TY + g.org[1];
-  const int z0 = blockIdx.z * g.zseg, z1 = min(z0 + g.zseg, nz);
+  int tbx, tby, tbz;
+  const int tlin = xcd_tile(tiles_x(g), tiles_y(g), tiles_z(g), tbx, tby, tbz);
+  const int x0 = tbx * TX + g.org[0], y0 = tby * TY + g.org[1];
+  const int z0 = tbz * g.zseg, z1 = min(z0 + g.zseg, nz);
 
   // per-thread load slots of the halo plane (fixed over the march)
   long long lofs[NLD];
@@ -540,9 +563,8 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
     double tot[2];
     block_sum<2, THREADS3D>(v, tot);
     if (threadIdx.x == 0) {
-      const long long b = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
-      a.opart[2 * b] += tot[0];
-      a.opart[2 * b + 1] += tot[1];
+      a.opart[2 * tlin] += tot[0];
+      a.opart[2 * tlin + 1] += tot[1];
     }
   }
 }
@@ -631,7 +653,9 @@ __global__ __launch_bounds__(STEP_THREADS) void k_adj2d(Geo g, AdjArgs a) {
   __shared__ R sl[3][LY * LX];     // pbar*, ubar*_x, ubar*_y
   __shared__ R sm[6][FY * FX];     // M0, M1x, M1y, M2xx, M2yy, M2xy
   const long long N = g.N;
-  const int x0 = blockIdx.x * TX + g.org[0], y0 = blockIdx.y * TY + g.org[1];
+  int tbx, tby, tbz;
+  xcd_tile(tiles_x(g), tiles_y(g), 1, tbx, tby, tbz);
+  const int x0 = tbx * TX + g.org[0], y0 = tby * TY + g.org[1];
   for (int k = threadIdx.x; k < LX * LY; k += STEP_THREADS) {
     int lx = k % LX, ly = k / LX;
     int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
@@ -721,8 +745,10 @@ __global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
   const long long N = g.N;
   const int nz = g.n[2];
   const long long NP = (long long)g.n[0] * g.n[1];
-  const int x0 = blockIdx.x * TX + g.org[0], y0 = blockIdx.y * TY + g.org[1];
-  const int z0 = blockIdx.z * g.zseg, z1 = min(z0 + g.zseg, nz);
+  int tbx, tby, tbz;
+  xcd_tile(tiles_x(g), tiles_y(g), tiles_z(g), tbx, tby, tbz);
+  const int x0 = tbx * TX + g.org[0], y0 = tby * TY + g.org[1];
+  const int z0 = tbz * g.zseg, z1 = min(z0 + g.zseg, nz);
   const double seed = a.seed ? a.seed[0] : 0.0;
   const double Ebar = a.seed ? a.E[0] : 0.0;
 
@@ -1661,7 +1687,7 @@ static dim3 step_grid(const Geo& g) {
   const int bx = (g.n[0] - g.org[0] + TILE_X - 1) / TILE_X;
   const int by = (g.n[1] - g.org[1] + TILE_Y - 1) / TILE_Y;
   const int bz = g.d == 3 ? (g.n[2] + g.zseg - 1) / g.zseg : 1;
-  return dim3(bx, by, bz);
+  return dim3(bx * by * bz);
 }
 int step_blocks(const Geo& g) {
   dim3 d = step_grid(g);

@@ -56,6 +56,7 @@ def lib():
         L.lks_plan_create.argtypes = [C.POINTER(LksProblem), C.POINTER(_VP), C.POINTER(C.c_size_t)]
         L.lks_plan_destroy.argtypes = [_VP]
         L.lks_plan_set_graphs.argtypes = [_VP, C.c_int32]
+        L.lks_plan_set_zseg.argtypes = [_VP, C.c_int32]
         L.lks_forward.argtypes = [_VP] * 9
         L.lks_adjoint.argtypes = [_VP] * 12
         L.lks_map_design_to_grid.argtypes = [_VP] * 7
@@ -135,6 +136,10 @@ class Plan:
     def set_graphs(self, on: bool):
         """Replay the time loops from captured hipGraphs (default) or launch eagerly."""
         _check(lib().lks_plan_set_graphs(self.handle, 1 if on else 0))
+
+    def set_zseg(self, zseg: int):
+        """3D step kernels: z planes per block segment (0 = automatic)."""
+        _check(lib().lks_plan_set_zseg(self.handle, int(zseg)))
 
     def __del__(self):
         h = getattr(self, "handle", None)
