@@ -153,7 +153,8 @@ lks_status validate(const lks_problem* p) {
     return fail(LKS_EINVAL, "need nu >= 0, kappa_max >= 0, q > 0");
   long long N = 1;
   for (int a = 0; a < p->d; ++a) N *= p->n[a];
-  if (N > (1LL << 31)) return fail(LKS_EINVAL, "grid too large");
+  // node offsets inside the (d+1)-plane state are 32-bit in the kernels
+  if (N > (1LL << 29)) return fail(LKS_EINVAL, "grid too large (at most 2^29 nodes)");
   return LKS_OK;
 }
 

@@ -349,6 +349,7 @@ __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d(Geo g, FwdArgs a) {
 // plane are formed on the 1-node halo region; (3) each output column adds
 // them into the accumulators of the three output planes they feed; the
 // plane below is then complete and is finished (Brinkman, walls, J1).
+// Node offsets within a plane set are 32-bit (plan validation bounds N).
 template <class R>
 __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
   apply_step(a.box, a.si);
@@ -358,40 +359,43 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
   constexpr int NLD = (LP + THREADS3D - 1) / THREADS3D;
   __shared__ R ring[3][4][LP];  // planes (mod 3): p, ux, uy, uz
   __shared__ R sf[15][FP];
-  const R* in = (const R*)a.in;
-  const long long N = g.N;
+  const int N = (int)g.N;
+  const R* in_p = (const R*)a.in;
+  const R* in_x = in_p + N;
+  const R* in_y = in_p + 2 * N;
+  const R* in_z = in_p + 3 * N;
   const int nz = g.n[2];
+  const int NP = g.n[0] * g.n[1];
   int tbx, tby, tbz;
   const int tlin = xcd_tile(tiles_x(g), tiles_y(g), tiles_z(g), tbx, tby, tbz);
   const int x0 = tbx * TX + g.org[0], y0 = tby * TY + g.org[1];
   const int z0 = tbz * g.zseg, z1 = min(z0 + g.zseg, nz);
 
   // per-thread load slots of the halo plane (fixed over the march)
-  long long lofs[NLD];
-  long long lpofs[NLD];
+  int lofs[NLD], lpofs[NLD];
   bool lok[NLD];
 #pragma unroll
   for (int j = 0; j < NLD; ++j) {
     const int k = threadIdx.x + j * THREADS3D;
     int gx = x0 - 2 + k % LX, gy = y0 - 2 + k / LX;
     lok[j] = k < LP && wrap_axis(g, 0, gx) && wrap_axis(g, 1, gy);
-    lofs[j] = lok[j] ? gx + (long long)g.n[0] * gy : 0;
+    lofs[j] = lok[j] ? gx + g.n[0] * gy : 0;
     lpofs[j] = (lok[j] && a.lazy_wall && is_wall(g, gx, gy, 0))
-                   ? inward(g, 0, gx) + (long long)g.n[0] * inward(g, 1, gy)
+                   ? inward(g, 0, gx) + g.n[0] * inward(g, 1, gy)
                    : lofs[j];
   }
   R pf[NLD][4];
   auto fetch = [&](int zp) {
     int zw = zp % nz;
     if (zw < 0) zw += nz;
-    const long long pl = (long long)g.n[0] * g.n[1] * zw;
+    const int pl = NP * zw;
 #pragma unroll
     for (int j = 0; j < NLD; ++j) {
       if (lok[j]) {
-        pf[j][0] = in[pl + lpofs[j]];
-        pf[j][1] = in[N + pl + lofs[j]];
-        pf[j][2] = in[2 * N + pl + lofs[j]];
-        pf[j][3] = in[3 * N + pl + lofs[j]];
+        pf[j][0] = in_p[pl + lpofs[j]];
+        pf[j][1] = in_x[pl + lofs[j]];
+        pf[j][2] = in_y[pl + lofs[j]];
+        pf[j][3] = in_z[pl + lofs[j]];
       } else {
         pf[j][0] = pf[j][1] = pf[j][2] = pf[j][3] = R(0);
       }
@@ -425,13 +429,12 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
   const bool cwall = own && (on_wall(g, 0, gx) || on_wall(g, 1, gy));
   const bool ctgt = own && a.opart && gx >= g.tlo[0] && gx < g.thi[0] && gy >= g.tlo[1] &&
                     gy < g.thi[1];
-  long long cbxy = -1;
+  int cbxy = -1;
   if (own && !cwall && a.bk) {
     int r0 = gx - a.box.lo[0], r1 = gy - a.box.lo[1];
     if (g.bc[0] == 0) { r0 %= g.n[0]; if (r0 < 0) r0 += g.n[0]; }
     if (g.bc[1] == 0) { r1 %= g.n[1]; if (r1 < 0) r1 += g.n[1]; }
-    if (r0 >= 0 && r0 < a.box.ext[0] && r1 >= 0 && r1 < a.box.ext[1])
-      cbxy = r0 + (long long)a.box.sx * r1;
+    if (r0 >= 0 && r0 < a.box.ext[0] && r1 >= 0 && r1 < a.box.ext[1]) cbxy = r0 + a.box.sx * r1;
   }
   R cw[3] = {R(0), R(0), R(0)};
   if (cwall) {
@@ -441,9 +444,15 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
     cw[1] = (R)uw[1];
     cw[2] = (R)uw[2];
   }
+  const int bvol = (int)a.box.vol, bplane = a.box.sx * a.box.sy;
   const R* bkp = (const R*)a.bk;
-  const R* bup = (const R*)a.bu;
-  R* outp = (R*)a.out;
+  const R* bux = (const R*)a.bu;
+  const R* buy = bux + bvol;
+  const R* buz = bux + 2 * bvol;
+  R* out_p = (R*)a.out;
+  R* out_x = out_p + N;
+  R* out_y = out_p + 2 * N;
+  R* out_z = out_p + 3 * N;
   R bkv = R(0), buv[3] = {R(0), R(0), R(0)};
   bool binb = false;
 
@@ -453,6 +462,8 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
   int hx = x0 - 1 + fk % FX, hy = y0 - 1 + fk / FX;
   const bool fin = fok && wrap_axis(g, 0, hx) && wrap_axis(g, 1, hy);
   const int fc = (fk / FX + 1) * LX + (fk % FX + 1);
+  // wall positions take one-sided derivatives (rare: handled after the central ones)
+  const bool fwx = fin && on_wall(g, 0, hx), fwy = fin && on_wall(g, 1, hy);
 
   fetch(z0 - 2);
   commit(z0 - 2);
@@ -469,32 +480,43 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
       int r2 = (zf - 1 - a.box.lo[2]) % nz;
       if (r2 < 0) r2 += nz;
       if (r2 < a.box.ext[2]) {
-        const long long bi = cbxy + (long long)a.box.sx * a.box.sy * r2;
+        const int bi = cbxy + bplane * r2;
         binb = true;
         bkv = bkp[bi];
-        buv[0] = bup[bi];
-        buv[1] = bup[a.box.vol + bi];
-        buv[2] = bup[2 * a.box.vol + bi];
+        buv[0] = bux[bi];
+        buv[1] = buy[bi];
+        buv[2] = buz[bi];
       }
     }
     if (fok) {
+      const int sm = (zf + 2) % 3, sc = (zf + 3) % 3, sp1 = (zf + 4) % 3;
+      const R* ux = ring[sc][1];
+      const R* uy = ring[sc][2];
+      const R* uz = ring[sc][3];
+      const int c = fc;
+      R dxux = R(0.5) * (ux[c + 1] - ux[c - 1]);
+      R dxuy = R(0.5) * (uy[c + 1] - uy[c - 1]);
+      R dxuz = R(0.5) * (uz[c + 1] - uz[c - 1]);
+      R dyux = R(0.5) * (ux[c + LX] - ux[c - LX]);
+      R dyuy = R(0.5) * (uy[c + LX] - uy[c - LX]);
+      R dyuz = R(0.5) * (uz[c + LX] - uz[c - LX]);
+      if (fwx) {
+        dxux = dnum(g, 0, hx, ux, c, 1);
+        dxuy = dnum(g, 0, hx, uy, c, 1);
+        dxuz = dnum(g, 0, hx, uz, c, 1);
+      }
+      if (fwy) {
+        dyux = dnum(g, 1, hy, ux, c, LX);
+        dyuy = dnum(g, 1, hy, uy, c, LX);
+        dyuz = dnum(g, 1, hy, uz, c, LX);
+      }
+      const R dzux = R(0.5) * (ring[sp1][1][c] - ring[sm][1][c]);
+      const R dzuy = R(0.5) * (ring[sp1][2][c] - ring[sm][2][c]);
+      const R dzuz = R(0.5) * (ring[sp1][3][c] - ring[sm][3][c]);
       R f[15];
-      if (fin) {
-        const int sm = (zf + 2) % 3, sc = (zf + 3) % 3, sp1 = (zf + 4) % 3;
-        const R* ux = ring[sc][1];
-        const R* uy = ring[sc][2];
-        const R* uz = ring[sc][3];
-        const int c = fc;
-        R dxux = dnum(g, 0, hx, ux, c, 1), dxuy = dnum(g, 0, hx, uy, c, 1),
-          dxuz = dnum(g, 0, hx, uz, c, 1);
-        R dyux = dnum(g, 1, hy, ux, c, LX), dyuy = dnum(g, 1, hy, uy, c, LX),
-          dyuz = dnum(g, 1, hy, uz, c, LX);
-        R dzux = R(0.5) * (ring[sp1][1][c] - ring[sm][1][c]);
-        R dzuy = R(0.5) * (ring[sp1][2][c] - ring[sm][2][c]);
-        R dzuz = R(0.5) * (ring[sp1][3][c] - ring[sm][3][c]);
-        feq15(ring[sc][0][c], ux[c], uy[c], uz[c], R(2) * dxux, R(2) * dyuy, R(2) * dzuz,
-              dxuy + dyux, dxuz + dzux, dyuz + dzuy, A, f);
-      } else {
+      feq15(ring[sc][0][c], ux[c], uy[c], uz[c], R(2) * dxux, R(2) * dyuy, R(2) * dzuz,
+            dxuy + dyux, dxuz + dzux, dyuz + dzuy, A, f);
+      if (!fin) {
 #pragma unroll
         for (int i = 0; i < 15; ++i) f[i] = R(0);
       }
@@ -519,7 +541,7 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
       }
       const int zo = zf - 1;
       if (zo >= z0 && own) {
-        const long long i = nidx(g, gx, gy, zo);
+        const int i = gx + g.n[0] * gy + NP * zo;
         R u0, u1, u2, p;
         if (cwall) {
           u0 = cw[0];
@@ -540,10 +562,10 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
           const R uu = u0 * u0 + u1 * u1 + u2 * u2;
           if (a.flags && !(uu < R(0.25))) a.flags[0] = 1;  // non-finite or |u| >= 0.5
         }
-        outp[i] = p;
-        outp[N + i] = u0;
-        outp[2 * N + i] = u1;
-        outp[3 * N + i] = u2;
+        out_p[i] = p;
+        out_x[i] = u0;
+        out_y[i] = u1;
+        out_z[i] = u2;
         if (ctgt && zo >= g.tlo[2] && zo < g.thi[2]) {
           const double un = g.ndir[0] * (double)u0 + g.ndir[1] * (double)u1 + g.ndir[2] * (double)u2;
           s1 += un;
@@ -738,25 +760,36 @@ __global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
   constexpr int NLD = (LP + THREADS3D - 1) / THREADS3D;
   __shared__ R ring[3][4][LP];   // adjoint star planes (mod 3)
   __shared__ R mb[2][10][FP];    // moment planes (mod 2): M0, M1x,y,z, Mxx,yy,zz,xy,xz,yz
-  const R* lam = (const R*)a.lam;
-  const R* uc = (const R*)a.u_cur;
-  const R* bk = (const R*)a.bk;
-  const R* bu = (const R*)a.bu;
-  const long long N = g.N;
+  const int N = (int)g.N;
+  const R* lam_p = (const R*)a.lam;
+  const R* lam_x = lam_p + N;
+  const R* lam_y = lam_p + 2 * N;
+  const R* lam_z = lam_p + 3 * N;
+  const R* uc_x = (const R*)a.u_cur + N;
+  const R* uc_y = uc_x + N;
+  const R* uc_z = uc_x + 2 * N;
+  const int bvol = (int)a.box.vol, bplane = a.box.sx * a.box.sy;
+  const R* bkp = (const R*)a.bk;
+  const R* bux = (const R*)a.bu;
+  const R* buy = bux + bvol;
+  const R* buz = bux + 2 * bvol;
+  R* bkbar = (R*)a.bkbar;
+  R* bubar_x = (R*)a.bubar;
+  R* bubar_y = bubar_x + bvol;
+  R* bubar_z = bubar_x + 2 * bvol;
   const int nz = g.n[2];
-  const long long NP = (long long)g.n[0] * g.n[1];
+  const int NP = g.n[0] * g.n[1];
   int tbx, tby, tbz;
   xcd_tile(tiles_x(g), tiles_y(g), tiles_z(g), tbx, tby, tbz);
   const int x0 = tbx * TX + g.org[0], y0 = tby * TY + g.org[1];
   const int z0 = tbz * g.zseg, z1 = min(z0 + g.zseg, nz);
   const double seed = a.seed ? a.seed[0] : 0.0;
   const double Ebar = a.seed ? a.E[0] : 0.0;
+  const R nd0 = (R)g.ndir[0], nd1 = (R)g.ndir[1], nd2 = (R)g.ndir[2];
 
   // per-thread load slots (fixed over the march)
-  int lgx[NLD], lgy[NLD];
-  long long lofs[NLD];
-  long long bxy[NLD];
-  bool lok[NLD], ltg[NLD], lown[NLD];
+  int lgx[NLD], lgy[NLD], lofs[NLD], bxy[NLD];
+  bool lok[NLD], ltg[NLD], lown[NLD], lwn[NLD];
 #pragma unroll
   for (int j = 0; j < NLD; ++j) {
     const int k = threadIdx.x + j * THREADS3D;
@@ -769,28 +802,29 @@ __global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
     lok[j] = ok;
     lgx[j] = gx;
     lgy[j] = gy;
-    lofs[j] = ok ? gx + (long long)g.n[0] * gy : 0;
+    lofs[j] = ok ? gx + g.n[0] * gy : 0;
     ltg[j] = ok && a.seed && gx >= g.tlo[0] && gx < g.thi[0] && gy >= g.tlo[1] && gy < g.thi[1];
-    long long b = -1;
+    // next to a wall whose nodes copy this node's pressure
+    lwn[j] = ok && ((g.bc[0] == 1 && (gx == 1 || gx == g.n[0] - 2)) ||
+                    (g.bc[1] == 1 && (gy == 1 || gy == g.n[1] - 2)));
+    int b = -1;
     if (ok && a.bk) {
       int r0 = gx - a.box.lo[0], r1 = gy - a.box.lo[1];
       if (g.bc[0] == 0) { r0 %= g.n[0]; if (r0 < 0) r0 += g.n[0]; }
       if (g.bc[1] == 0) { r1 %= g.n[1]; if (r1 < 0) r1 += g.n[1]; }
-      if (r0 >= 0 && r0 < a.box.ext[0] && r1 >= 0 && r1 < a.box.ext[1])
-        b = r0 + (long long)a.box.sx * r1;
+      if (r0 >= 0 && r0 < a.box.ext[0] && r1 >= 0 && r1 < a.box.ext[1]) b = r0 + a.box.sx * r1;
     }
     bxy[j] = b;
   }
   // raw values of the next plane, fetched one iteration ahead
   R rl[NLD][4], run[NLD][3], rbk[NLD], rbu[NLD][3];
-  long long rbi[NLD];
+  int rbi[NLD];
   bool rtg[NLD];
   auto fetch = [&](int zp) {
     int zw = zp % nz;
     if (zw < 0) zw += nz;
-    const long long pl = NP * zw;
-    int r2 = zw - a.box.lo[2];
-    r2 %= nz;
+    const int pl = NP * zw;
+    int r2 = (zw - a.box.lo[2]) % nz;
     if (r2 < 0) r2 += nz;
     const bool zbox = r2 < a.box.ext[2];
     const bool ztg = zw >= g.tlo[2] && zw < g.thi[2];
@@ -802,24 +836,24 @@ __global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) rl[j][q] = R(0);
       if (!lok[j]) continue;
-      const long long i = pl + lofs[j];
-      rl[j][0] = lam[i];
-      rl[j][1] = lam[N + i];
-      rl[j][2] = lam[2 * N + i];
-      rl[j][3] = lam[3 * N + i];
+      const int i = pl + lofs[j];
+      rl[j][0] = lam_p[i];
+      rl[j][1] = lam_x[i];
+      rl[j][2] = lam_y[i];
+      rl[j][3] = lam_z[i];
       rtg[j] = ltg[j] && ztg;
-      const long long bi = (bxy[j] >= 0 && zbox) ? bxy[j] + (long long)a.box.sx * a.box.sy * r2 : -1;
+      const int bi = (bxy[j] >= 0 && zbox) ? bxy[j] + bplane * r2 : -1;
       rbi[j] = bi;
       if (rtg[j] || (bi >= 0 && lown[j] && own_plane)) {
-        run[j][0] = uc[N + i];
-        run[j][1] = uc[2 * N + i];
-        run[j][2] = uc[3 * N + i];
+        run[j][0] = uc_x[i];
+        run[j][1] = uc_y[i];
+        run[j][2] = uc_z[i];
       }
       if (bi >= 0) {
-        rbk[j] = bk[bi];
-        rbu[j][0] = bu[bi];
-        rbu[j][1] = bu[a.box.vol + bi];
-        rbu[j][2] = bu[2 * a.box.vol + bi];
+        rbk[j] = bkp[bi];
+        rbu[j][0] = bux[bi];
+        rbu[j][1] = buy[bi];
+        rbu[j][2] = buz[bi];
       }
     }
   };
@@ -834,51 +868,53 @@ __global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
       if (k >= LP) continue;
       R v0 = R(0), v1 = R(0), v2 = R(0), v3 = R(0);
       if (lok[j]) {
-        const int gx = lgx[j], gy = lgy[j];
         R pb = rl[j][0];
-        // wall nodes that copy this node's pressure hand their adjoint back
-        int ox[2] = {gx, gx}, oy[2] = {gy, gy};
-        int cx = 1, cy = 1;
-        if (g.bc[0] == 1) {
-          if (gx == 1) ox[cx++] = 0;
-          else if (gx == g.n[0] - 2) ox[cx++] = g.n[0] - 1;
-        }
-        if (g.bc[1] == 1) {
-          if (gy == 1) oy[cy++] = 0;
-          else if (gy == g.n[1] - 2) oy[cy++] = g.n[1] - 1;
-        }
-        if (cx > 1 || cy > 1) {
+        if (lwn[j]) {
+          // wall nodes that copy this node's pressure hand their adjoint back
+          const int gx = lgx[j], gy = lgy[j];
+          int ox[2] = {gx, gx}, oy[2] = {gy, gy};
+          int cx = 1, cy = 1;
+          if (g.bc[0] == 1) {
+            if (gx == 1) ox[cx++] = 0;
+            else if (gx == g.n[0] - 2) ox[cx++] = g.n[0] - 1;
+          }
+          if (g.bc[1] == 1) {
+            if (gy == 1) oy[cy++] = 0;
+            else if (gy == g.n[1] - 2) oy[cy++] = g.n[1] - 1;
+          }
           for (int ky = 0; ky < cy; ++ky)
             for (int kx = 0; kx < cx; ++kx)
-              if (kx || ky) pb += lam[nidx(g, ox[kx], oy[ky], zw)];
+              if (kx || ky) pb += lam_p[ox[kx] + g.n[0] * oy[ky] + NP * zw];
         }
-        R ub[3] = {rl[j][1], rl[j][2], rl[j][3]};
+        R ub0 = rl[j][1], ub1 = rl[j][2], ub2 = rl[j][3];
         if (rtg[j]) {
-          double un = g.ndir[0] * (double)run[j][0] + g.ndir[1] * (double)run[j][1] +
-                      g.ndir[2] * (double)run[j][2];
-          double gs = seed * g.NTinv * (1.0 - 2.0 * g.phi * (un - Ebar));
-          for (int q = 0; q < 3; ++q) ub[q] += (R)(gs * g.ndir[q]);
+          const double un = g.ndir[0] * (double)run[j][0] + g.ndir[1] * (double)run[j][1] +
+                            g.ndir[2] * (double)run[j][2];
+          const R gs = (R)(seed * g.NTinv * (1.0 - 2.0 * g.phi * (un - Ebar)));
+          ub0 += gs * nd0;
+          ub1 += gs * nd1;
+          ub2 += gs * nd2;
         }
-        const long long bi = rbi[j];
+        const int bi = rbi[j];
         if (bi >= 0) {
           const R kk = rbk[j];
           const R inv = R(1) / (R(1) + kk);
           if (lown[j] && own_plane) {
-            R* bkbar = (R*)a.bkbar;
-            R* bubar = (R*)a.bubar;
-            R kb = R(0);
-            for (int q = 0; q < 3; ++q) {
-              kb += ub[q] * (rbu[j][q] - run[j][q]);
-              bubar[q * a.box.vol + bi] = kk * ub[q] * inv;
-            }
+            const R kb = ub0 * (rbu[j][0] - run[j][0]) + ub1 * (rbu[j][1] - run[j][1]) +
+                         ub2 * (rbu[j][2] - run[j][2]);
             bkbar[bi] = kb * inv;
+            bubar_x[bi] = kk * ub0 * inv;
+            bubar_y[bi] = kk * ub1 * inv;
+            bubar_z[bi] = kk * ub2 * inv;
           }
-          for (int q = 0; q < 3; ++q) ub[q] *= inv;
+          ub0 *= inv;
+          ub1 *= inv;
+          ub2 *= inv;
         }
         v0 = pb;
-        v1 = ub[0];
-        v2 = ub[1];
-        v3 = ub[2];
+        v1 = ub0;
+        v2 = ub1;
+        v3 = ub2;
       }
       ring[sl][0][k] = v0;
       ring[sl][1][k] = v1;
@@ -893,13 +929,22 @@ __global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
   const int gx = x0 + tx, gy = y0 + ty;
   const bool own = outer && gx >= 0 && gx < g.n[0] && gy >= 0 && gy < g.n[1];
   const int oc = (ty + 1) * FX + (tx + 1);
+  // own nodes within two nodes of a wall take the one-sided stencil transposes
+  const bool owx = own && g.bc[0] == 1 && (gx <= 2 || gx >= g.n[0] - 3);
+  const bool owy = own && g.bc[1] == 1 && (gy <= 2 || gy >= g.n[1] - 3);
   const R A2 = R(2) * (R)g.A;
-  const R* up = (const R*)a.u_prev;
-  R* lp = (R*)a.lam_prev;
+  const R* up_x = (const R*)a.u_prev + N;
+  const R* up_y = up_x + N;
+  const R* up_z = up_x + 2 * N;
+  R* lp_p = (R*)a.lam_prev;
+  R* lp_x = lp_p + N;
+  R* lp_y = lp_p + 2 * N;
+  R* lp_z = lp_p + 3 * N;
   R zprev[3] = {R(0), R(0), R(0)};  // own column M2_{zx}, M2_{zy}, M2_{zz} at zo - 1
   const int fk = tid;
   const bool fok = fk < FP;
   const int fc = (fk / FX + 1) * LX + (fk % FX + 1);
+  const int ocol = gx + g.n[0] * gy;
 
   fetch(z0 - 2);
   commit(z0 - 2);
@@ -912,10 +957,10 @@ __global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
     if (zs + 2 <= z1 + 1) fetch(zs + 2);
     R upx = R(0), upy = R(0), upz = R(0);
     if (zs - 1 >= z0 && own) {
-      const long long i = nidx(g, gx, gy, zs - 1);
-      upx = up[N + i];
-      upy = up[2 * N + i];
-      upz = up[3 * N + i];
+      const int i = ocol + NP * (zs - 1);
+      upx = up_x[i];
+      upy = up_y[i];
+      upz = up_z[i];
     }
     if (fok) {
       const int s0 = (zs + 2) % 3, s1 = (zs + 3) % 3, s2 = (zs + 4) % 3;
@@ -953,7 +998,7 @@ __global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
     if (zo >= z0 && own) {
       R(*m0)[FP] = mb[zo & 1];   // plane zo
       R(*m1)[FP] = mb[zs & 1];   // plane zo + 1
-      const long long i = nidx(g, gx, gy, zo);
+      const int i = ocol + NP * zo;
       const R ux = upx, uy = upy, uz = upz;
       const R M0 = m0[0][oc];
       const R Mxx = m0[4][oc], Myy = m0[5][oc], Mzz = m0[6][oc];
@@ -961,17 +1006,31 @@ __global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
       R bx = R(3) * m0[1][oc] + R(9) * (Mxx * ux + Mxy * uy + Mxz * uz) - R(3) * ux * M0;
       R by = R(3) * m0[2][oc] + R(9) * (Mxy * ux + Myy * uy + Myz * uz) - R(3) * uy * M0;
       R bz = R(3) * m0[3][oc] + R(9) * (Mxz * ux + Myz * uy + Mzz * uz) - R(3) * uz * M0;
-      // D_x^T and D_y^T in plane; D_z^T (periodic) from planes zo - 1, zo + 1
-      bx += A2 * (dnumT(g, 0, gx, m0[4], oc, 1) + dnumT(g, 1, gy, m0[7], oc, FX) +
-                  R(0.5) * (zprev[0] - m1[8][oc]));
-      by += A2 * (dnumT(g, 0, gx, m0[7], oc, 1) + dnumT(g, 1, gy, m0[5], oc, FX) +
-                  R(0.5) * (zprev[1] - m1[9][oc]));
-      bz += A2 * (dnumT(g, 0, gx, m0[8], oc, 1) + dnumT(g, 1, gy, m0[9], oc, FX) +
-                  R(0.5) * (zprev[2] - m1[6][oc]));
-      lp[i] = R(3) * M0;
-      lp[N + i] = bx;
-      lp[2 * N + i] = by;
-      lp[3 * N + i] = bz;
+      // velocity-gradient transpose: D_x^T, D_y^T in plane (central, then the
+      // one-sided transposes next to walls); D_z^T (periodic) from zo -+ 1
+      R tx0 = R(0.5) * (m0[4][oc - 1] - m0[4][oc + 1]);
+      R tx1 = R(0.5) * (m0[7][oc - 1] - m0[7][oc + 1]);
+      R tx2 = R(0.5) * (m0[8][oc - 1] - m0[8][oc + 1]);
+      R ty0 = R(0.5) * (m0[7][oc - FX] - m0[7][oc + FX]);
+      R ty1 = R(0.5) * (m0[5][oc - FX] - m0[5][oc + FX]);
+      R ty2 = R(0.5) * (m0[9][oc - FX] - m0[9][oc + FX]);
+      if (owx) {
+        tx0 = dnumT(g, 0, gx, m0[4], oc, 1);
+        tx1 = dnumT(g, 0, gx, m0[7], oc, 1);
+        tx2 = dnumT(g, 0, gx, m0[8], oc, 1);
+      }
+      if (owy) {
+        ty0 = dnumT(g, 1, gy, m0[7], oc, FX);
+        ty1 = dnumT(g, 1, gy, m0[5], oc, FX);
+        ty2 = dnumT(g, 1, gy, m0[9], oc, FX);
+      }
+      bx += A2 * (tx0 + ty0 + R(0.5) * (zprev[0] - m1[8][oc]));
+      by += A2 * (tx1 + ty1 + R(0.5) * (zprev[1] - m1[9][oc]));
+      bz += A2 * (tx2 + ty2 + R(0.5) * (zprev[2] - m1[6][oc]));
+      lp_p[i] = R(3) * M0;
+      lp_x[i] = bx;
+      lp_y[i] = by;
+      lp_z[i] = bz;
     }
     if (zs >= z0 && outer) {
       // keep own-column z-moments of plane zs - 1 for the next output
