@@ -137,8 +137,9 @@ lks_status lks_adjoint(lks_plan* plan, const double* gamma, const double* chi,
 /* Design -> analysis transfer for one time step (Sec. 2.3, Eqs. kappa, u_s):
  * kappa_ref [D2][D1][D0] (state type), motion8 = (xg[3], ug[3], theta, omega)
  * doubles -> kappa [N] and u_s [d][N] (state type).  Wall nodes receive 0.
- * workspace: the plan's workspace (3D uses its z-resampling scratch; the
- * checkpoints left by lks_forward are not touched).  Reads motion8 back to
+ * workspace: the plan's workspace (3D keeps a z-fastest copy of kappa_ref
+ * there; the checkpoints left by lks_forward are not touched and a later
+ * lks_adjoint rebuilds its copy).  Reads motion8 back to
  * the host (synchronises `stream`).  Returns LKS_EINVAL if the body's
  * support does not fit a periodic extent. */
 lks_status lks_map_design_to_grid(lks_plan* plan, const void* kappa_ref, const double* motion8,

@@ -258,6 +258,7 @@ lks_status prelude(lks_plan* P, const double* gamma, const double* chi, const do
     Scope sc("prelude", s);
     HIPCHK(launch_zero(info, 64 * sizeof(int), s));
     HIPCHK(launch_kappa_ref(P->g, P->prec, gamma, wsp(ws, P->o_kref), s));
+    HIPCHK(launch_kref_t(P->g, P->prec, wsp(ws, P->o_kref), wsp(ws, P->o_kz), s));
     HIPCHK(launch_motion(P->g, chi, psi, mot, s));
     HIPCHK(launch_steps(P->g, mot, (StepInfo*)wsp(ws, P->o_tab), info, s));
   }
@@ -576,6 +577,8 @@ lks_status lks_adjoint(lks_plan* P, const double* gamma, const double* chi, cons
     HIPCHK(launch_zero(lam_slot(P, ws, 0), Sb, s));
   }
   HIPCHK(launch_zero(wsp(ws, P->o_badj), body_bytes(P), s));
+  // the z-fastest kappa_ref copy may have been reused by a stand-alone map call
+  HIPCHK(launch_kref_t(P->g, P->prec, wsp(ws, P->o_kref), wsp(ws, P->o_kz), s));
   if (lks_status e = run_loop(P, P->gadj, ws, P->first_lazy, s,
                               [&](hipStream_t st) { return adjoint_loop(P, ws, st); }))
     return e;
@@ -614,6 +617,7 @@ lks_status lks_map_design_to_grid(lks_plan* P, const void* kappa_ref, const doub
   if (lks_status e = host_box(P, motion8, m8, box, s)) return e;
   HIPCHK(launch_zero(kappa, (size_t)P->g.N * P->es, s));
   HIPCHK(launch_zero(u_s, (size_t)P->g.d * P->g.N * P->es, s));
+  HIPCHK(launch_kref_t(P->g, P->prec, kappa_ref, wsp(ws, P->o_kz), s));
   Scope sc("map", s);
   HIPCHK(launch_map(P->g, P->prec, kappa_ref, wsp(ws, P->o_kz), P->bmax.ext[2], m8, nullptr, box,
                     kappa, u_s, 1, s));

@@ -16,14 +16,18 @@ constexpr int THREADS3D = 384;
 // Resident blocks per CU the 3D step kernels are sized for (LDS-limited) and
 // the CU count of the target; the z-segment length is chosen so the grid is
 // about STEP_RESIDENT * CU_COUNT blocks.
-constexpr int STEP_RESIDENT = 3;
+constexpr int STEP_RESIDENT = 2;
 constexpr int CU_COUNT = 256;
 // design points per block of the map transpose.
 constexpr int MAPADJ_THREADS = 256;
 // 3D map: z values per thread.
 constexpr int MAP_ZC = 16;
+// 3D map: zero padding (design levels) of the z-fastest kappa_ref copy.
+constexpr int KZ_PAD = 8;
 // 3D map transpose: design levels per thread.
-constexpr int MAPADJ_LCH = 4;
+constexpr int MAPADJ_LCH = 8;
+// 3D map transpose: lanes per (design column, level chunk), one per xy tap row.
+constexpr int MAPADJ_TPC = 4;
 
 // Device copy of the problem (passed by value to every kernel).
 struct Geo {
@@ -122,6 +126,7 @@ int step_blocks(const Geo& g);
 hipError_t launch_forward_step(const Geo& g, int precision, const FwdArgs& a, hipStream_t s);
 hipError_t launch_adjoint_step(const Geo& g, int precision, const AdjArgs& a, hipStream_t s);
 size_t kz_bytes(const Geo& g, int ext2max, int precision);
+hipError_t launch_kref_t(const Geo& g, int precision, const void* kref, void* kt, hipStream_t s);
 hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf, int ext2max,
                       const double* mot8_host, const StepInfo* si, const Box& box, void* bk,
                       void* bu, int full_grid, hipStream_t s);

@@ -1125,41 +1125,25 @@ __global__ __launch_bounds__(256) void k_map2d(Geo g, const R* kref, Mot m, Box 
   }
 }
 
-// 3D transfer, stage 1: the z factor of the kernel is axis aligned and the
-// same for every design column, so kappa_ref is first resampled onto the
-// analysis z values of the step's box: kz[column][zz] =
-// sum_{xi3} w(z - X3(xi3)) kappa_ref(column, xi3); the tail row holds
-// sum_{xi3} w(z - X3(xi3)) (the z weight sum used by the body velocity).
+// 3D transfer.  The z factor of the kernel is axis aligned and its 4 weights
+// are the same for every design column and every analysis z (design levels
+// and analysis planes are one node apart), so with kappa_ref stored z-fastest
+// (krefT, built once per run, zero-padded by KZ_PAD levels below and
+// MAP_ZC + KZ_PAD above) a thread first sums the W_xy-weighted columns of its
+// rotated xy candidates over MAP_ZC + 3 consecutive levels and then applies
+// the z filter once.  One thread per analysis column and MAP_ZC z values.
 template <class R>
-__global__ __launch_bounds__(256) void k_kz(Geo g, const R* kref, Mot m, Box box,
-                                            const StepInfo* si, R* kz, int ezp) {
-  apply_step(box, m, si);
+__global__ __launch_bounds__(256) void k_kref_t(Geo g, const R* kref, R* kt, int lz) {
   const long long cols = (long long)g.D[0] * g.D[1];
   const long long idx = blockIdx.x * 256LL + threadIdx.x;
-  if (idx >= (cols + 1) * ezp) return;
-  const long long col = idx / ezp;
-  const int zz = (int)(idx % ezp);
-  R v = R(0);
-  if (zz < box.ext[2]) {
-    const double t = (double)(box.lo[2] + zz) + (g.xiG[2] - m.xg[2]);
-    const double fl = floor(t);
-    const R f = (R)(t - fl);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e2 = (int)fl - 1 + q;
-      if (e2 >= 0 && e2 < g.D[2]) {
-        const R w = wk(f + R(1) - R(q));
-        v += (col < cols) ? w * kref[col + cols * e2] : w;
-      }
-    }
-  }
-  kz[idx] = v;
+  if (idx >= cols * lz) return;
+  const long long col = idx / lz;
+  const int e2 = (int)(idx % lz) - KZ_PAD;
+  kt[idx] = (e2 >= 0 && e2 < g.D[2]) ? kref[col + cols * e2] : R(0);
 }
 
-// 3D transfer, stage 2: one thread per analysis column and MAP_ZC z values;
-// the rotated xy candidates and their weights are formed once per column.
 template <class R>
-__global__ __launch_bounds__(64) void k_map3d(Geo g, const R* kz, int ezp, Mot m, Box box,
+__global__ __launch_bounds__(64) void k_map3d(Geo g, const R* kt, int lz, Mot m, Box box,
                                               const StepInfo* si, R* bk, R* bu, int full_grid) {
   apply_step(box, m, si);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1170,9 +1154,15 @@ __global__ __launch_bounds__(64) void k_map3d(Geo g, const R* kz, int ezp, Mot m
   int x = bx, y = by;
   const bool col_inside = wrap_axis(g, 0, x) && wrap_axis(g, 1, y);
   const bool col_wall = col_inside && (on_wall(g, 0, x) || on_wall(g, 1, y));
-  R k[MAP_ZC];
+  // analysis z = lo2 + zc + t uses design levels L0 + t + q (q = 0..3),
+  // L0 = lo2 + zc + floor(xiG2 - xg2) - 1, with weights w(f + 1 - q)
+  const double o = g.xiG[2] - m.xg[2];
+  const int fo = (int)floor(o);
+  const R f = (R)(o - fo);
+  const int L0 = box.lo[2] + zc + fo - 1;
+  R G[MAP_ZC + 3];
 #pragma unroll
-  for (int t = 0; t < MAP_ZC; ++t) k[t] = R(0);
+  for (int t = 0; t < MAP_ZC + 3; ++t) G[t] = R(0);
   R m0 = R(0), m1 = R(0), m2 = R(0);
   if (col_inside && !col_wall) {
     const double rx = bx - m.xg[0], ry = by - m.xg[1];
@@ -1181,6 +1171,7 @@ __global__ __launch_bounds__(64) void k_map3d(Geo g, const R* kz, int ezp, Mot m
     const double h = 2.0 * (fabs(m.c) + fabs(m.s));
     const int i0 = max(0, (int)ceil(q0 - h)), i1 = min(g.D[0] - 1, (int)floor(q0 + h));
     const int j0 = max(0, (int)ceil(q1 - h)), j1 = min(g.D[1] - 1, (int)floor(q1 + h));
+    const int zoff = L0 + KZ_PAD;
     for (int e1 = j0; e1 <= j1; ++e1) {
       const double r1 = e1 - g.xiG[1];
       for (int e0 = i0; e0 <= i1; ++e0) {
@@ -1192,18 +1183,20 @@ __global__ __launch_bounds__(64) void k_map3d(Geo g, const R* kz, int ezp, Mot m
           m0 += W;
           m1 += W * (R)r0;
           m2 += W * (R)r1;
-          const R* col = kz + (e0 + (long long)g.D[0] * e1) * ezp + zc;
+          const R* col = kt + (long long)(e0 + g.D[0] * e1) * lz + zoff;
 #pragma unroll
-          for (int t = 0; t < MAP_ZC; ++t) k[t] += W * col[t];
+          for (int t = 0; t < MAP_ZC + 3; ++t) G[t] += W * col[t];
         }
       }
     }
   }
+  R wz[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) wz[q] = wk(f + R(1) - R(q));
   const R om = (R)m.om, c = (R)m.c, s = (R)m.s;
   const R vx = om * (-s * m1 - c * m2) + (R)m.ug[0] * m0;
   const R vy = om * (c * m1 - s * m2) + (R)m.ug[1] * m0;
   const R vz = (R)m.ug[2] * m0;
-  const R* zsum = kz + (long long)g.D[0] * g.D[1] * ezp + zc;
 #pragma unroll
   for (int t = 0; t < MAP_ZC; ++t) {
     const int kk = zc + t;
@@ -1211,8 +1204,15 @@ __global__ __launch_bounds__(64) void k_map3d(Geo g, const R* kz, int ezp, Mot m
     int z = box.lo[2] + kk;
     const bool inside = col_inside && wrap_axis(g, 2, z);
     const bool wall = !inside || col_wall || on_wall(g, 2, z);
-    const R zs = zsum[t];
-    const R kv = wall ? R(0) : k[t];
+    // z weight sum over the design levels that exist
+    R zs = R(0), kv = R(0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e2 = L0 + t + q;
+      if (e2 >= 0 && e2 < g.D[2]) zs += wz[q];
+      kv += wz[q] * G[t + q];
+    }
+    if (wall) kv = R(0);
     const R ux = wall ? R(0) : zs * vx, uy = wall ? R(0) : zs * vy, uz = wall ? R(0) : zs * vz;
     if (full_grid) {
       if (wall) continue;
@@ -1231,115 +1231,129 @@ __global__ __launch_bounds__(64) void k_map3d(Geo g, const R* kz, int ezp, Mot m
   }
 }
 
-// 3D transfer transpose: one thread per design column and MAPADJ_LCH design
-// levels.  The z factor is the same 4-tap kernel for every level and
-// consecutive levels are one node apart, so the thread marches the analysis
-// planes once: each plane's 16 xy taps are reduced to 12 plane sums, which
-// feed the (up to 4) levels in flight; a level is complete after its 4th
-// plane.  Finishing a level adds dJ/dkappa_ref and the motion partials.
+// 3D transfer transpose: MAPADJ_TPC consecutive lanes per (design column,
+// chunk of MAPADJ_LCH design levels), lane r owning the r-th row of the 4x4
+// xy taps.  The z factor is the same 4-tap kernel for every level and
+// consecutive levels are one node apart, so the lanes march the analysis
+// planes once: each plane's xy taps are reduced to 12 plane sums (a 4-lane
+// butterfly joins the rows); a window of the last 4 planes' sums gives each
+// level its z-weighted sums.  Finishing a level adds dJ/dkappa_ref and the
+// level's motion partials.
 template <class R>
 __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kref, Mot m, Box box,
                                                              const StepInfo* si, const R* bkbar,
                                                              const R* bubar, double* kref_bar,
                                                              int overwrite, double* mpart) {
   apply_step(box, m, si);
-  const long long cols = (long long)g.D[0] * g.D[1];
+  const int cols = g.D[0] * g.D[1];
   const int nch = (g.D[2] + MAPADJ_LCH - 1) / MAPADJ_LCH;
-  const long long idx = blockIdx.x * (long long)MAPADJ_THREADS + threadIdx.x;
+  const int gid = blockIdx.x * MAPADJ_THREADS + threadIdx.x;
+  const int item = gid / MAPADJ_TPC, row = gid % MAPADJ_TPC;
+  const bool active = item < cols * nch;
   double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (idx < cols * nch) {
-    const long long col = idx % cols;
-    const int ch = (int)(idx / cols);
-    const int l0 = ch * MAPADJ_LCH, l1 = min(l0 + MAPADJ_LCH, g.D[2]);
-    const int e0 = (int)(col % g.D[0]), e1 = (int)(col / g.D[0]);
-    const double r0 = e0 - g.xiG[0], r1 = e1 - g.xiG[1];
-    const double X0 = m.c * r0 - m.s * r1 + m.xg[0];
-    const double X1 = m.s * r0 + m.c * r1 + m.xg[1];
-    const double U0 = m.om * (-m.s * r0 - m.c * r1) + m.ug[0];
-    const double U1 = m.om * (m.c * r0 - m.s * r1) + m.ug[1];
-    const double U2 = m.ug[2];
-    const double dX0 = -m.s * r0 - m.c * r1, dX1 = m.c * r0 - m.s * r1;                      // R' r
-    const double dU0 = m.om * (-m.c * r0 + m.s * r1), dU1 = m.om * (-m.s * r0 - m.c * r1);  // om R'' r
-    R wx[4], dx[4], wy[4], dy[4];
-    int bix[4], biy[4];
-    {
-      const int lx = (int)floor(X0) - 1, ly = (int)floor(X1) - 1;
+  // all lanes of a group take the same trip counts (the butterfly needs them)
+  const int col = active ? item % cols : 0;
+  const int ch = active ? item / cols : 0;
+  const int l0 = ch * MAPADJ_LCH, l1 = active ? min(l0 + MAPADJ_LCH, g.D[2]) : l0;
+  const int e0 = col % g.D[0], e1 = col / g.D[0];
+  const double r0 = e0 - g.xiG[0], r1 = e1 - g.xiG[1];
+  const double X0 = m.c * r0 - m.s * r1 + m.xg[0];
+  const double X1 = m.s * r0 + m.c * r1 + m.xg[1];
+  R wx[4], dx[4];
+  int bix[4];
+  const int lx = (int)floor(X0) - 1;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        int vx = lx + q, vy = ly + q;
-        const R rx = (R)((double)vx - X0), ry = (R)((double)vy - X1);
-        wx[q] = wk(rx);
-        dx[q] = wkd(rx);
-        wy[q] = wk(ry);
-        dy[q] = wkd(ry);
-        int b = -1;
-        if (wrap_axis(g, 0, vx) && !on_wall(g, 0, vx)) {
-          b = vx - box.lo[0];
-          if (g.bc[0] == 0) { b %= g.n[0]; if (b < 0) b += g.n[0]; }
-          if (b < 0 || b >= box.ext[0]) b = -1;
-        }
-        bix[q] = b;
-        b = -1;
-        if (wrap_axis(g, 1, vy) && !on_wall(g, 1, vy)) {
-          b = vy - box.lo[1];
-          if (g.bc[1] == 0) { b %= g.n[1]; if (b < 0) b += g.n[1]; }
-          if (b < 0 || b >= box.ext[1]) b = -1;
-        }
-        biy[q] = b;
+  for (int q = 0; q < 4; ++q) {
+    int vx = lx + q;
+    const R rx = (R)((double)vx - X0);
+    wx[q] = wk(rx);
+    dx[q] = wkd(rx);
+    int b = -1;
+    if (wrap_axis(g, 0, vx) && !on_wall(g, 0, vx)) {
+      b = vx - box.lo[0];
+      if (g.bc[0] == 0) { b %= g.n[0]; if (b < 0) b += g.n[0]; }
+      if (b < 0 || b >= box.ext[0]) b = -1;
+    }
+    bix[q] = b;
+  }
+  R wy, dy;
+  int biy;
+  {
+    int vy = (int)floor(X1) - 1 + row;
+    const R ry = (R)((double)vy - X1);
+    wy = wk(ry);
+    dy = wkd(ry);
+    int b = -1;
+    if (wrap_axis(g, 1, vy) && !on_wall(g, 1, vy)) {
+      b = vy - box.lo[1];
+      if (g.bc[1] == 0) { b %= g.n[1]; if (b < 0) b += g.n[1]; }
+      if (b < 0 || b >= box.ext[1]) b = -1;
+    }
+    biy = b;
+  }
+  const double o2 = m.xg[2] - g.xiG[2];
+  const int fo = (int)floor(o2);
+  const R f = (R)(o2 - fo);
+  R wz[4], dz[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    wz[q] = wk(R(q) - R(1) - f);
+    dz[q] = wkd(R(q) - R(1) - f);
+  }
+  const int bvol = (int)box.vol, bplane = box.sx * box.sy;
+  const R* bux = bubar;
+  const R* buy = bubar + bvol;
+  const R* buz = bubar + 2 * bvol;
+  // this lane's share of the plane sums of analysis plane z, then the
+  // butterfly over the group's 4 lanes
+  auto plane_sums = [&](int z, R* P) {
+#pragma unroll
+    for (int q = 0; q < 12; ++q) P[q] = R(0);
+    bool zok = wrap_axis(g, 2, z);
+    int r2 = z - box.lo[2];
+    if (g.bc[2] == 0) { r2 %= g.n[2]; if (r2 < 0) r2 += g.n[2]; }
+    if (zok && r2 >= 0 && r2 < box.ext[2] && biy >= 0) {
+      const int rowb = box.sx * biy + bplane * r2;
+#pragma unroll
+      for (int cx = 0; cx < 4; ++cx) {
+        if (bix[cx] < 0) continue;
+        const int bi = bix[cx] + rowb;
+        const R kb = bkbar[bi];
+        const R u0 = bux[bi], u1 = buy[bi], u2 = buz[bi];
+        const R w = wx[cx] * wy, wxd = dx[cx] * wy, wyd = wx[cx] * dy;
+        P[0] += w * kb;
+        P[1] += w * u0;
+        P[2] += w * u1;
+        P[3] += w * u2;
+        P[4] += wxd * kb;
+        P[5] += wxd * u0;
+        P[6] += wxd * u1;
+        P[7] += wxd * u2;
+        P[8] += wyd * kb;
+        P[9] += wyd * u0;
+        P[10] += wyd * u1;
+        P[11] += wyd * u2;
       }
     }
-    const double o2 = m.xg[2] - g.xiG[2];
-    const double fo = floor(o2);
-    const R f = (R)(o2 - fo);
-    R wz[4], dz[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      wz[q] = wk(R(q) - R(1) - f);
-      dz[q] = wkd(R(q) - R(1) - f);
+    for (int q = 0; q < 12; ++q) {
+      P[q] += __shfl_xor(P[q], 1, MAPADJ_TPC);
+      P[q] += __shfl_xor(P[q], 2, MAPADJ_TPC);
     }
-    const int zb = l0 + (int)fo - 1;       // first plane of level l0
-    const long long sxy = (long long)box.sx * box.sy;
-    // plane sums over the 16 xy taps of analysis plane z:
-    // (w, w'_x w_y, w_x w'_y) times (kbar, ubar_x, ubar_y, ubar_z)
-    auto plane_sums = [&](int z, R* P) {
-#pragma unroll
-      for (int q = 0; q < 12; ++q) P[q] = R(0);
-      bool zok = wrap_axis(g, 2, z);
-      int r2 = z - box.lo[2];
-      if (g.bc[2] == 0) { r2 %= g.n[2]; if (r2 < 0) r2 += g.n[2]; }
-      if (!zok || r2 < 0 || r2 >= box.ext[2]) return;
-#pragma unroll
-      for (int cy = 0; cy < 4; ++cy) {
-        if (biy[cy] < 0) continue;
-#pragma unroll
-        for (int cx = 0; cx < 4; ++cx) {
-          if (bix[cx] < 0) continue;
-          const long long bi = bix[cx] + (long long)box.sx * biy[cy] + sxy * r2;
-          const R kb = bkbar[bi];
-          const R u0 = bubar[bi], u1 = bubar[box.vol + bi], u2 = bubar[2 * box.vol + bi];
-          const R w = wx[cx] * wy[cy], wxd = dx[cx] * wy[cy], wyd = wx[cx] * dy[cy];
-          P[0] += w * kb;
-          P[1] += w * u0;
-          P[2] += w * u1;
-          P[3] += w * u2;
-          P[4] += wxd * kb;
-          P[5] += wxd * u0;
-          P[6] += wxd * u1;
-          P[7] += wxd * u2;
-          P[8] += wyd * kb;
-          P[9] += wyd * u0;
-          P[10] += wyd * u1;
-          P[11] += wyd * u2;
-        }
-      }
-    };
-    // window of the 4 planes feeding the current level
-    R W0[12], W1[12], W2[12], W3[12];
-    plane_sums(zb, W0);
-    plane_sums(zb + 1, W1);
-    plane_sums(zb + 2, W2);
-    for (int L = l0; L < l1; ++L) {
-      plane_sums(L + (int)fo + 2, W3);
+  };
+  const int zb = l0 + fo - 1;  // first plane of level l0
+  R W0[12], W1[12], W2[12], W3[12];
+  plane_sums(zb, W0);
+  plane_sums(zb + 1, W1);
+  plane_sums(zb + 2, W2);
+  const double U0 = m.om * (-m.s * r0 - m.c * r1) + m.ug[0];
+  const double U1 = m.om * (m.c * r0 - m.s * r1) + m.ug[1];
+  const double U2 = m.ug[2];
+  const double dX0 = -m.s * r0 - m.c * r1, dX1 = m.c * r0 - m.s * r1;                      // R' r
+  const double dU0 = m.om * (-m.c * r0 + m.s * r1), dU1 = m.om * (-m.s * r0 - m.c * r1);  // om R'' r
+  for (int L = l0; L < l1; ++L) {
+    plane_sums(L + fo + 2, W3);
+    if (row == 0) {
       R A[16];
 #pragma unroll
       for (int t = 0; t < 12; ++t)
@@ -1347,7 +1361,7 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
 #pragma unroll
       for (int t = 0; t < 4; ++t)
         A[12 + t] = dz[0] * W0[t] + dz[1] * W1[t] + dz[2] * W2[t] + dz[3] * W3[t];
-      const long long k = col + cols * L;
+      const long long k = col + (long long)cols * L;
       const double kr = (double)kref[k];
       const double Xb0 = -(kr * A[4] + U0 * A[5] + U1 * A[6] + U2 * A[7]);
       const double Xb1 = -(kr * A[8] + U0 * A[9] + U1 * A[10] + U2 * A[11]);
@@ -1361,12 +1375,12 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
       part[5] += A[3];
       part[6] += Xb0 * dX0 + Xb1 * dX1 + (double)A[1] * dU0 + (double)A[2] * dU1;
       part[7] += (double)A[1] * dX0 + (double)A[2] * dX1;
+    }
 #pragma unroll
-      for (int t = 0; t < 12; ++t) {
-        W0[t] = W1[t];
-        W1[t] = W2[t];
-        W2[t] = W3[t];
-      }
+    for (int t = 0; t < 12; ++t) {
+      W0[t] = W1[t];
+      W1[t] = W2[t];
+      W2[t] = W3[t];
     }
   }
   double tot[8];
@@ -1785,18 +1799,30 @@ hipError_t launch_adjoint_step(const Geo& g, int precision, const AdjArgs& a, hi
   return hipGetLastError();
 }
 
-int kz_rows(const Geo& g, int ext2max) {
-  (void)g;
-  return ((ext2max + MAP_ZC - 1) / MAP_ZC) * MAP_ZC;
-}
+int kz_levels(const Geo& g) { return g.D[2] + MAP_ZC + 2 * KZ_PAD; }
 size_t kz_bytes(const Geo& g, int ext2max, int precision) {
+  (void)ext2max;
   if (g.d != 3) return 0;
-  return (size_t)(g.D[0] * (long long)g.D[1] + 1) * kz_rows(g, ext2max) * (precision == 0 ? 4 : 8);
+  return (size_t)g.D[0] * g.D[1] * kz_levels(g) * (precision == 0 ? 4 : 8);
+}
+
+hipError_t launch_kref_t(const Geo& g, int precision, const void* kref, void* kt, hipStream_t s) {
+  if (g.d != 3) return hipSuccess;
+  const int lz = kz_levels(g);
+  const long long n = (long long)g.D[0] * g.D[1] * lz;
+  dim3 grid((unsigned)((n + 255) / 256));
+  if (precision == 0)
+    hipLaunchKernelGGL(k_kref_t<float>, grid, dim3(256), 0, s, g, (const float*)kref, (float*)kt, lz);
+  else
+    hipLaunchKernelGGL(k_kref_t<double>, grid, dim3(256), 0, s, g, (const double*)kref,
+                       (double*)kt, lz);
+  return hipGetLastError();
 }
 
 hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf, int ext2max,
                       const double* mot8_host, const StepInfo* si, const Box& box, void* bk,
                       void* bu, int full_grid, hipStream_t s) {
+  (void)ext2max;
   if (box.ext[0] <= 0 || box.ext[1] <= 0 || box.ext[2] <= 0) return hipSuccess;
   Mot m;
   if (mot8_host)
@@ -1812,28 +1838,22 @@ hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf
       hipLaunchKernelGGL(k_map2d<double>, grid, dim3(256), 0, s, g, (const double*)kref, m, box, si,
                          (double*)bk, (double*)bu, full_grid);
   } else {
-    const int ezp = kz_rows(g, ext2max);
-    const long long nkz = ((long long)g.D[0] * g.D[1] + 1) * ezp;
-    dim3 g1((unsigned)((nkz + 255) / 256));
+    const int lz = kz_levels(g);
     dim3 grid((box.ext[0] + 63) / 64, box.ext[1], (box.ext[2] + MAP_ZC - 1) / MAP_ZC);
-    if (precision == 0) {
-      hipLaunchKernelGGL(k_kz<float>, g1, dim3(256), 0, s, g, (const float*)kref, m, box, si,
-                         (float*)kzbuf, ezp);
-      hipLaunchKernelGGL(k_map3d<float>, grid, dim3(64), 0, s, g, (const float*)kzbuf, ezp, m,
-                         box, si, (float*)bk, (float*)bu, full_grid);
-    } else {
-      hipLaunchKernelGGL(k_kz<double>, g1, dim3(256), 0, s, g, (const double*)kref, m, box, si,
-                         (double*)kzbuf, ezp);
-      hipLaunchKernelGGL(k_map3d<double>, grid, dim3(64), 0, s, g, (const double*)kzbuf, ezp, m,
+    if (precision == 0)
+      hipLaunchKernelGGL(k_map3d<float>, grid, dim3(64), 0, s, g, (const float*)kzbuf, lz, m, box,
+                         si, (float*)bk, (float*)bu, full_grid);
+    else
+      hipLaunchKernelGGL(k_map3d<double>, grid, dim3(64), 0, s, g, (const double*)kzbuf, lz, m,
                          box, si, (double*)bk, (double*)bu, full_grid);
-    }
   }
   return hipGetLastError();
 }
 
 int mapadj_blocks(const Geo& g) {
   if (g.d == 3) {
-    const long long n = (long long)g.D[0] * g.D[1] * ((g.D[2] + MAPADJ_LCH - 1) / MAPADJ_LCH);
+    const long long n = (long long)g.D[0] * g.D[1] * ((g.D[2] + MAPADJ_LCH - 1) / MAPADJ_LCH) *
+                        MAPADJ_TPC;
     return (int)((n + MAPADJ_THREADS - 1) / MAPADJ_THREADS);
   }
   return (int)((g.Mtot + MAPADJ_THREADS - 1) / MAPADJ_THREADS);
