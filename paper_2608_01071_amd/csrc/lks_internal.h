@@ -20,8 +20,10 @@ constexpr int STEP_RESIDENT = 2;
 constexpr int CU_COUNT = 256;
 // design points per block of the map transpose.
 constexpr int MAPADJ_THREADS = 256;
-// 3D map: z values per thread.
+// 3D map: most z values per thread the kappa_ref copy is padded for, and the
+// value the launches use (smaller = more threads, more candidate searches).
 constexpr int MAP_ZC = 16;
+constexpr int MAP_ZC_RUN = 4;
 // 3D map: zero padding (design levels) of the z-fastest kappa_ref copy.
 constexpr int KZ_PAD = 8;
 // 3D map transpose: design levels per thread.

@@ -1142,13 +1142,14 @@ __global__ __launch_bounds__(256) void k_kref_t(Geo g, const R* kref, R* kt, int
   kt[idx] = (e2 >= 0 && e2 < g.D[2]) ? kref[col + cols * e2] : R(0);
 }
 
-template <class R>
+template <class R, int ZC>
 __global__ __launch_bounds__(64) void k_map3d(Geo g, const R* kt, int lz, Mot m, Box box,
                                               const StepInfo* si, R* bk, R* bu, int full_grid) {
+  static_assert(ZC <= MAP_ZC, "the z-fastest copy is padded for ZC values per thread");
   apply_step(box, m, si);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
-  const int zc = blockIdx.z * MAP_ZC;
+  const int zc = blockIdx.z * ZC;
   if (i >= box.ext[0] || j >= box.ext[1] || zc >= box.ext[2]) return;
   const int bx = box.lo[0] + i, by = box.lo[1] + j;
   int x = bx, y = by;
@@ -1160,9 +1161,9 @@ __global__ __launch_bounds__(64) void k_map3d(Geo g, const R* kt, int lz, Mot m,
   const int fo = (int)floor(o);
   const R f = (R)(o - fo);
   const int L0 = box.lo[2] + zc + fo - 1;
-  R G[MAP_ZC + 3];
+  R G[ZC + 3];
 #pragma unroll
-  for (int t = 0; t < MAP_ZC + 3; ++t) G[t] = R(0);
+  for (int t = 0; t < ZC + 3; ++t) G[t] = R(0);
   R m0 = R(0), m1 = R(0), m2 = R(0);
   if (col_inside && !col_wall) {
     const double rx = bx - m.xg[0], ry = by - m.xg[1];
@@ -1185,7 +1186,7 @@ __global__ __launch_bounds__(64) void k_map3d(Geo g, const R* kt, int lz, Mot m,
           m2 += W * (R)r1;
           const R* col = kt + (long long)(e0 + g.D[0] * e1) * lz + zoff;
 #pragma unroll
-          for (int t = 0; t < MAP_ZC + 3; ++t) G[t] += W * col[t];
+          for (int t = 0; t < ZC + 3; ++t) G[t] += W * col[t];
         }
       }
     }
@@ -1198,7 +1199,7 @@ __global__ __launch_bounds__(64) void k_map3d(Geo g, const R* kt, int lz, Mot m,
   const R vy = om * (c * m1 - s * m2) + (R)m.ug[1] * m0;
   const R vz = (R)m.ug[2] * m0;
 #pragma unroll
-  for (int t = 0; t < MAP_ZC; ++t) {
+  for (int t = 0; t < ZC; ++t) {
     const int kk = zc + t;
     if (kk >= box.ext[2]) break;
     int z = box.lo[2] + kk;
@@ -1839,13 +1840,14 @@ hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf
                          (double*)bk, (double*)bu, full_grid);
   } else {
     const int lz = kz_levels(g);
-    dim3 grid((box.ext[0] + 63) / 64, box.ext[1], (box.ext[2] + MAP_ZC - 1) / MAP_ZC);
+    constexpr int ZC = MAP_ZC_RUN;
+    dim3 grid((box.ext[0] + 63) / 64, box.ext[1], (box.ext[2] + ZC - 1) / ZC);
     if (precision == 0)
-      hipLaunchKernelGGL(k_map3d<float>, grid, dim3(64), 0, s, g, (const float*)kzbuf, lz, m, box,
-                         si, (float*)bk, (float*)bu, full_grid);
+      hipLaunchKernelGGL((k_map3d<float, ZC>), grid, dim3(64), 0, s, g, (const float*)kzbuf, lz, m,
+                         box, si, (float*)bk, (float*)bu, full_grid);
     else
-      hipLaunchKernelGGL(k_map3d<double>, grid, dim3(64), 0, s, g, (const double*)kzbuf, lz, m,
-                         box, si, (double*)bk, (double*)bu, full_grid);
+      hipLaunchKernelGGL((k_map3d<double, ZC>), grid, dim3(64), 0, s, g, (const double*)kzbuf, lz,
+                         m, box, si, (double*)bk, (double*)bu, full_grid);
   }
   return hipGetLastError();
 }
