@@ -11,13 +11,19 @@ namespace lks {
 constexpr int TILE_X = 32;
 constexpr int TILE_Y = 8;
 constexpr int STEP_THREADS = TILE_X * TILE_Y;
-// 3D step kernels: enough threads for the whole 1-node halo region (34 x 10).
-constexpr int THREADS3D = 384;
+// 3D step kernels: one thread per node of the 2-node halo plane (36 x 12).
+constexpr int THREADS3D = 448;
 // Resident blocks per CU the 3D step kernels are sized for (LDS-limited) and
 // the CU count of the target; the z-segment length is chosen so the grid is
 // about STEP_RESIDENT * CU_COUNT blocks.
 constexpr int STEP_RESIDENT = 2;
 constexpr int CU_COUNT = 256;
+// 3D adjoint step: planes of its LDS ring (3: two barriers per plane and
+// about 34 KB of LDS in FP32; 4: one barrier and about 41 KB).
+#ifndef LKS_ADJ_RING
+#define LKS_ADJ_RING 3
+#endif
+constexpr int ADJ_RING = LKS_ADJ_RING;
 // design points per block of the map transpose.
 constexpr int MAPADJ_THREADS = 256;
 // 3D map: most z values per thread the kappa_ref copy is padded for, and the

@@ -346,9 +346,11 @@ __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d(Geo g, FwdArgs a) {
 // (1) the (p, u) plane with a 2-node halo enters a 3-plane LDS ring from
 // registers fetched one iteration earlier (the global loads of the next
 // plane overlap this plane's arithmetic); (2) the 15 equilibria of the
-// plane are formed on the 1-node halo region; (3) each output column adds
-// them into the accumulators of the three output planes they feed; the
-// plane below is then complete and is finished (Brinkman, walls, J1).
+// plane are formed on the 1-node halo region, the 12 that move within the
+// plane go through LDS; (3) each output column adds them into the
+// accumulators of the three output planes they feed; the plane below is
+// then complete and is finished (Brinkman, walls, J1).  About 37 KB of LDS
+// (FP32) keeps four blocks resident per CU.
 // Node offsets within a plane set are 32-bit (plan validation bounds N).
 template <class R>
 __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
@@ -356,9 +358,10 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
   constexpr int TX = TILE_X, TY = TILE_Y;
   constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
   constexpr int LP = LX * LY, FP = FX * FY;
-  constexpr int NLD = (LP + THREADS3D - 1) / THREADS3D;
-  __shared__ R ring[3][4][LP];  // planes (mod 3): p, ux, uy, uz
-  __shared__ R sf[15][FP];
+  static_assert(THREADS3D >= LP && THREADS3D >= FP, "one load and one equilibrium slot per thread");
+  // planes (mod 3): p, ux, uy, uz; entries LP.. take the commits of idle slots
+  __shared__ R ring[3][4][THREADS3D];
+  __shared__ R sf[12][FP];  // the 12 equilibria that move within the plane
   const int N = (int)g.N;
   const R* in_p = (const R*)a.in;
   const R* in_x = in_p + N;
@@ -371,60 +374,12 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
   const int x0 = tbx * TX + g.org[0], y0 = tby * TY + g.org[1];
   const int z0 = tbz * g.zseg, z1 = min(z0 + g.zseg, nz);
 
-  // per-thread load slots of the halo plane (fixed over the march)
-  int lofs[NLD], lpofs[NLD];
-  bool lok[NLD];
-#pragma unroll
-  for (int j = 0; j < NLD; ++j) {
-    const int k = threadIdx.x + j * THREADS3D;
-    int gx = x0 - 2 + k % LX, gy = y0 - 2 + k / LX;
-    lok[j] = k < LP && wrap_axis(g, 0, gx) && wrap_axis(g, 1, gy);
-    lofs[j] = lok[j] ? gx + g.n[0] * gy : 0;
-    lpofs[j] = (lok[j] && a.lazy_wall && is_wall(g, gx, gy, 0))
-                   ? inward(g, 0, gx) + g.n[0] * inward(g, 1, gy)
-                   : lofs[j];
-  }
-  R pf[NLD][4];
-  auto fetch = [&](int zp) {
-    int zw = zp % nz;
-    if (zw < 0) zw += nz;
-    const int pl = NP * zw;
-#pragma unroll
-    for (int j = 0; j < NLD; ++j) {
-      if (lok[j]) {
-        pf[j][0] = in_p[pl + lpofs[j]];
-        pf[j][1] = in_x[pl + lofs[j]];
-        pf[j][2] = in_y[pl + lofs[j]];
-        pf[j][3] = in_z[pl + lofs[j]];
-      } else {
-        pf[j][0] = pf[j][1] = pf[j][2] = pf[j][3] = R(0);
-      }
-    }
-  };
-  auto commit = [&](int zp) {
-    const int sl = (zp + 3) % 3;
-#pragma unroll
-    for (int j = 0; j < NLD; ++j) {
-      const int k = threadIdx.x + j * THREADS3D;
-      if (k < LP) {
-        ring[sl][0][k] = pf[j][0];
-        ring[sl][1][k] = pf[j][1];
-        ring[sl][2][k] = pf[j][2];
-        ring[sl][3][k] = pf[j][3];
-      }
-    }
-  };
-
   const int tid = threadIdx.x;
   const bool outer = tid < TX * TY;
   const int tx = tid % TX, ty = tid / TX;
   const int gx = x0 + tx, gy = y0 + ty;
   const bool own = outer && gx >= 0 && gx < g.n[0] && gy >= 0 && gy < g.n[1];
   const int oc = (ty + 1) * FX + (tx + 1);
-  R am[4] = {R(0), R(0), R(0), R(0)}, a0[4] = {R(0), R(0), R(0), R(0)},
-    ap[4] = {R(0), R(0), R(0), R(0)};
-  double s1 = 0.0, s2 = 0.0;
-  const R A = (R)g.A;
   // column-constant data of the output node
   const bool cwall = own && (on_wall(g, 0, gx) || on_wall(g, 1, gy));
   const bool ctgt = own && a.opart && gx >= g.tlo[0] && gx < g.thi[0] && gy >= g.tlo[1] &&
@@ -445,6 +400,7 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
     cw[2] = (R)uw[2];
   }
   const int bvol = (int)a.box.vol, bplane = a.box.sx * a.box.sy;
+  const bool body = a.bk && bvol > 0;
   const R* bkp = (const R*)a.bk;
   const R* bux = (const R*)a.bu;
   const R* buy = bux + bvol;
@@ -453,41 +409,97 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
   R* out_x = out_p + N;
   R* out_y = out_p + 2 * N;
   R* out_z = out_p + 3 * N;
-  R bkv = R(0), buv[3] = {R(0), R(0), R(0)};
-  bool binb = false;
 
-  // equilibrium slot of this thread (one position of the 1-node halo region)
-  const int fk = tid;
-  const bool fok = fk < FP;
-  int hx = x0 - 1 + fk % FX, hy = y0 - 1 + fk / FX;
+  // load slot of the halo plane (fixed over the march); slots outside the
+  // grid or the halo read node 0 of the plane and commit zeros
+  int lofs, lpofs;
+  bool lok;
+  {
+    int hx2 = x0 - 2 + tid % LX, hy2 = y0 - 2 + tid / LX;
+    lok = tid < LP && wrap_axis(g, 0, hx2) && wrap_axis(g, 1, hy2);
+    lofs = lok ? hx2 + g.n[0] * hy2 : 0;
+    lpofs = (lok && a.lazy_wall && is_wall(g, hx2, hy2, 0))
+                ? inward(g, 0, hx2) + g.n[0] * inward(g, 1, hy2)
+                : lofs;
+  }
+  // Register buffers of two planes in flight.  Every load and every commit
+  // is unconditional (clamped plane and node), so the wait before a commit
+  // counts only the loads issued after it, never the output stores.
+  struct Buf {
+    R v[4];
+    R bk, bu[3];  // body fields of output plane zp - 2
+    bool bin;
+  };
+  auto fetch = [&](int zp, Buf& B) {
+    B.bin = false;
+    if (body) {
+      int r2 = (zp - 2 - a.box.lo[2]) % nz;
+      if (r2 < 0) r2 += nz;
+      B.bin = cbxy >= 0 && r2 < a.box.ext[2] && zp - 2 >= z0 && zp - 2 < z1;
+      const int bi = B.bin ? cbxy + bplane * r2 : 0;
+      B.bk = bkp[bi];
+      B.bu[0] = bux[bi];
+      B.bu[1] = buy[bi];
+      B.bu[2] = buz[bi];
+    }
+    int zw = min(zp, z1 + 1) % nz;
+    if (zw < 0) zw += nz;
+    const int pl = NP * zw;
+    B.v[0] = in_p[pl + lpofs];
+    B.v[1] = in_x[pl + lofs];
+    B.v[2] = in_y[pl + lofs];
+    B.v[3] = in_z[pl + lofs];
+  };
+  auto commit = [&](int zp, const Buf& B) {
+    const int sl = (zp + 3) % 3;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ring[sl][q][tid] = lok ? B.v[q] : R(0);
+  };
+
+  // equilibrium slot: threads 0..255 take their own output position (the
+  // three equilibria that stay in the column, 0 and +-z, never leave
+  // registers), threads 256..339 the positions of the 1-node halo ring
+  const bool fok = tid < FP;
+  int fx, fy;
+  if (outer) {
+    fx = tx + 1;
+    fy = ty + 1;
+  } else {
+    const int r = tid - TX * TY;
+    if (r < FX) {
+      fx = r;
+      fy = 0;
+    } else if (r < 2 * FX) {
+      fx = r - FX;
+      fy = FY - 1;
+    } else {
+      const int q = r - 2 * FX;  // 0 .. 2 (FY - 2) - 1
+      fx = (q & 1) ? FX - 1 : 0;
+      fy = 1 + (q >> 1);
+    }
+  }
+  const int fpos = fx + FX * fy;
+  int hx = x0 - 1 + fx, hy = y0 - 1 + fy;
   const bool fin = fok && wrap_axis(g, 0, hx) && wrap_axis(g, 1, hy);
-  const int fc = (fk / FX + 1) * LX + (fk % FX + 1);
+  const int fc = (fy + 1) * LX + (fx + 1);
   // wall positions take one-sided derivatives (rare: handled after the central ones)
   const bool fwx = fin && on_wall(g, 0, hx), fwy = fin && on_wall(g, 1, hy);
 
-  fetch(z0 - 2);
-  commit(z0 - 2);
-  fetch(z0 - 1);
-  commit(z0 - 1);
-  fetch(z0);
-  for (int zf = z0 - 1; zf <= z1; ++zf) {
-    commit(zf + 1);
+  R am[4] = {R(0), R(0), R(0), R(0)}, a0[4] = {R(0), R(0), R(0), R(0)},
+    ap[4] = {R(0), R(0), R(0), R(0)};
+  double s1 = 0.0, s2 = 0.0;
+  const R A = (R)g.A;
+
+  // Iteration zf: commit plane zf+1 (buffer X) | barrier | fetch plane zf+3
+  // into X | equilibria of plane zf | barrier | gather of plane zf, finish
+  // of plane zf-1.
+  auto iter = [&](int zf, Buf& X) {
+    commit(zf + 1, X);
+    const bool binb = X.bin;
+    const R bkv = X.bk, bu0 = X.bu[0], bu1 = X.bu[1], bu2 = X.bu[2];
     __syncthreads();
-    if (zf + 2 <= z1 + 1) fetch(zf + 2);
-    // body fields of the plane finished in this iteration
-    binb = false;
-    if (cbxy >= 0 && zf - 1 >= z0) {
-      int r2 = (zf - 1 - a.box.lo[2]) % nz;
-      if (r2 < 0) r2 += nz;
-      if (r2 < a.box.ext[2]) {
-        const int bi = cbxy + bplane * r2;
-        binb = true;
-        bkv = bkp[bi];
-        buv[0] = bux[bi];
-        buv[1] = buy[bi];
-        buv[2] = buz[bi];
-      }
-    }
+    fetch(zf + 3, X);
+    R f0 = R(0), fzp = R(0), fzm = R(0);
     if (fok) {
       const int sm = (zf + 2) % 3, sc = (zf + 3) % 3, sp1 = (zf + 4) % 3;
       const R* ux = ring[sc][1];
@@ -520,16 +532,26 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
 #pragma unroll
         for (int i = 0; i < 15; ++i) f[i] = R(0);
       }
+      f0 = f[0];
+      fzp = f[5];
+      fzm = f[6];
 #pragma unroll
-      for (int i = 0; i < 15; ++i) sf[i][fk] = f[i];
+      for (int i = 1; i < 15; ++i)
+        if (i != 5 && i != 6) sf[i < 5 ? i - 1 : i - 3][fpos] = f[i];
     }
     __syncthreads();
     if (outer) {
       // gather plane zf into the three output planes it feeds
+      a0[0] += f0;
+      ap[0] += fzp;
+      ap[3] += fzp;
+      am[0] += fzm;
+      am[3] -= fzm;
 #pragma unroll
-      for (int i = 0; i < 15; ++i) {
+      for (int i = 1; i < 15; ++i) {
+        if (i == 5 || i == 6) continue;
         const int cx = Lat<15>::c[i][0], cy = Lat<15>::c[i][1], cz = Lat<15>::c[i][2];
-        R v = sf[i][oc - cx - cy * FX];
+        R v = sf[i < 5 ? i - 1 : i - 3][oc - cx - cy * FX];
         R* acc = (cz == 1) ? ap : ((cz == 0) ? a0 : am);
         acc[0] += v;
         if (cx == 1) acc[1] += v;
@@ -555,9 +577,9 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
           u2 = am[3];
           if (binb) {
             const R inv = R(1) / (R(1) + bkv);
-            u0 = (u0 + bkv * buv[0]) * inv;
-            u1 = (u1 + bkv * buv[1]) * inv;
-            u2 = (u2 + bkv * buv[2]) * inv;
+            u0 = (u0 + bkv * bu0) * inv;
+            u1 = (u1 + bkv * bu1) * inv;
+            u2 = (u2 + bkv * bu2) * inv;
           }
           const R uu = u0 * u0 + u1 * u1 + u2 * u2;
           if (a.flags && !(uu < R(0.25))) a.flags[0] = 1;  // non-finite or |u| >= 0.5
@@ -579,7 +601,23 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
         ap[k] = R(0);
       }
     }
+  };
+
+  Buf bA, bB;
+  fetch(z0 - 2, bA);
+  commit(z0 - 2, bA);
+  fetch(z0 - 1, bA);
+  commit(z0 - 1, bA);
+  fetch(z0, bA);
+  fetch(z0 + 1, bB);
+  // iterations z0-1 .. z1, two per trip so each buffer stays in fixed
+  // registers (and every trip ends with the loads of the other buffer)
+  int zf = z0 - 1;
+  for (; zf + 1 <= z1; zf += 2) {
+    iter(zf, bA);
+    iter(zf + 1, bB);
   }
+  if (zf <= z1) iter(zf, bA);
   if (a.opart) {
     double v[2] = {s1, s2};
     double tot[2];
@@ -752,14 +790,16 @@ __global__ __launch_bounds__(STEP_THREADS) void k_adj2d(Geo g, AdjArgs a) {
 // velocity gradient (in-plane from the moment plane, along z from the
 // neighbouring planes' moments of the own column).
 template <class R>
-__global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
+__global__ __launch_bounds__(THREADS3D, sizeof(R) == 4 ? 4 : 2) void k_adj3d(Geo g, AdjArgs a) {
   apply_step(a.box, a.si);
   constexpr int TX = TILE_X, TY = TILE_Y;
   constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
   constexpr int LP = LX * LY, FP = FX * FY;
-  constexpr int NLD = (LP + THREADS3D - 1) / THREADS3D;
-  __shared__ R ring[3][4][LP];   // adjoint star planes (mod 3)
-  __shared__ R mb[2][10][FP];    // moment planes (mod 2): M0, M1x,y,z, Mxx,yy,zz,xy,xz,yz
+  static_assert(THREADS3D >= LP && THREADS3D >= FP, "one load and one moment slot per thread");
+  constexpr int NR = ADJ_RING;  // 3: two barriers per plane, 4: one
+  // adjoint star planes (mod NR); entries LP.. take the commits of idle slots
+  __shared__ R ring[NR][4][THREADS3D];
+  __shared__ R mb[2][5][FP];  // in-plane second moments (mod 2): Mxx, Myy, Mxy, Mxz, Myz
   const int N = (int)g.N;
   const R* lam_p = (const R*)a.lam;
   const R* lam_x = lam_p + N;
@@ -769,6 +809,7 @@ __global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
   const R* uc_y = uc_x + N;
   const R* uc_z = uc_x + 2 * N;
   const int bvol = (int)a.box.vol, bplane = a.box.sx * a.box.sy;
+  const bool body = a.bk && bvol > 0;
   const R* bkp = (const R*)a.bk;
   const R* bux = (const R*)a.bu;
   const R* buy = bux + bvol;
@@ -786,42 +827,72 @@ __global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
   const double seed = a.seed ? a.seed[0] : 0.0;
   const double Ebar = a.seed ? a.E[0] : 0.0;
   const R nd0 = (R)g.ndir[0], nd1 = (R)g.ndir[1], nd2 = (R)g.ndir[2];
+  const int tid = threadIdx.x;
 
-  // per-thread load slots (fixed over the march)
-  int lgx[NLD], lgy[NLD], lofs[NLD], bxy[NLD];
-  bool lok[NLD], ltg[NLD], lown[NLD], lwn[NLD];
-#pragma unroll
-  for (int j = 0; j < NLD; ++j) {
-    const int k = threadIdx.x + j * THREADS3D;
-    const int lx = k % LX, ly = k / LX;
-    int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
-    bool ok = k < LP && wrap_axis(g, 0, gx) && wrap_axis(g, 1, gy);
-    lown[j] = ok && lx >= 2 && lx < TX + 2 && ly >= 2 && ly < TY + 2 && (x0 - 2 + lx) == gx &&
-              (y0 - 2 + ly) == gy;
-    ok = ok && !(on_wall(g, 0, gx) || on_wall(g, 1, gy));
-    lok[j] = ok;
-    lgx[j] = gx;
-    lgy[j] = gy;
-    lofs[j] = ok ? gx + g.n[0] * gy : 0;
-    ltg[j] = ok && a.seed && gx >= g.tlo[0] && gx < g.thi[0] && gy >= g.tlo[1] && gy < g.thi[1];
-    // next to a wall whose nodes copy this node's pressure
-    lwn[j] = ok && ((g.bc[0] == 1 && (gx == 1 || gx == g.n[0] - 2)) ||
-                    (g.bc[1] == 1 && (gy == 1 || gy == g.n[1] - 2)));
-    int b = -1;
-    if (ok && a.bk) {
-      int r0 = gx - a.box.lo[0], r1 = gy - a.box.lo[1];
+  // load slot of the halo plane (fixed over the march)
+  int lofs, bxy;
+  bool lok, ltg, lown;
+  int nwn = 0, wofs[3] = {0, 0, 0};  // wall nodes that copy this node's pressure
+  {
+    const int lx = tid % LX, ly = tid / LX;
+    int hx2 = x0 - 2 + lx, hy2 = y0 - 2 + ly;
+    bool ok = tid < LP && wrap_axis(g, 0, hx2) && wrap_axis(g, 1, hy2);
+    lown = ok && lx >= 2 && lx < TX + 2 && ly >= 2 && ly < TY + 2 && (x0 - 2 + lx) == hx2 &&
+           (y0 - 2 + ly) == hy2;
+    ok = ok && !(on_wall(g, 0, hx2) || on_wall(g, 1, hy2));
+    lok = ok;
+    lofs = ok ? hx2 + g.n[0] * hy2 : 0;
+    ltg = ok && a.seed && hx2 >= g.tlo[0] && hx2 < g.thi[0] && hy2 >= g.tlo[1] && hy2 < g.thi[1];
+    if (ok) {
+      int ox[2] = {hx2, hx2}, oy[2] = {hy2, hy2};
+      int cx = 1, cy = 1;
+      if (g.bc[0] == 1) {
+        if (hx2 == 1) ox[cx++] = 0;
+        else if (hx2 == g.n[0] - 2) ox[cx++] = g.n[0] - 1;
+      }
+      if (g.bc[1] == 1) {
+        if (hy2 == 1) oy[cy++] = 0;
+        else if (hy2 == g.n[1] - 2) oy[cy++] = g.n[1] - 1;
+      }
+      for (int ky = 0; ky < cy; ++ky)
+        for (int kx = 0; kx < cx; ++kx)
+          if (kx || ky) wofs[nwn++] = ox[kx] + g.n[0] * oy[ky];
+    }
+    int bb = -1;
+    if (ok && body) {
+      int r0 = hx2 - a.box.lo[0], r1 = hy2 - a.box.lo[1];
       if (g.bc[0] == 0) { r0 %= g.n[0]; if (r0 < 0) r0 += g.n[0]; }
       if (g.bc[1] == 0) { r1 %= g.n[1]; if (r1 < 0) r1 += g.n[1]; }
-      if (r0 >= 0 && r0 < a.box.ext[0] && r1 >= 0 && r1 < a.box.ext[1]) b = r0 + a.box.sx * r1;
+      if (r0 >= 0 && r0 < a.box.ext[0] && r1 >= 0 && r1 < a.box.ext[1]) bb = r0 + a.box.sx * r1;
     }
-    bxy[j] = b;
+    bxy = bb;
   }
-  // raw values of the next plane, fetched one iteration ahead
-  R rl[NLD][4], run[NLD][3], rbk[NLD], rbu[NLD][3];
-  int rbi[NLD];
-  bool rtg[NLD];
-  auto fetch = [&](int zp) {
-    int zw = zp % nz;
+
+  const bool outer = tid < TX * TY;
+  const int tx = tid % TX, ty = tid / TX;
+  const int gx = x0 + tx, gy = y0 + ty;
+  const bool own = outer && gx >= 0 && gx < g.n[0] && gy >= 0 && gy < g.n[1];
+  const int oc = (ty + 1) * FX + (tx + 1);
+  const int ocol = own ? gx + g.n[0] * gy : 0;
+  const R* up_x = (const R*)a.u_prev + N;
+  const R* up_y = up_x + N;
+  const R* up_z = up_x + 2 * N;
+
+  // Register buffers of two planes in flight.  The per-lane conditional
+  // loads of a plane are issued first and the unconditional ones (clamped
+  // node) last, so the wait before a commit counts only the other buffer's
+  // loads, never the stores.
+  struct Buf {
+    R l[4];       // raw adjoint state of the slot node, plane zp
+    R w[3];       // wall-node pressure adjoints that copy it (0 if none)
+    R un[3];      // u^n of the slot node (target or owned body node)
+    R bk, bu[3];  // body fields of the slot node
+    R up[3];      // own column u^(n-1), output plane zp - 2
+    int bi;       // body-box index of the slot node, -1 outside
+    bool tg, bown;
+  };
+  auto fetch = [&](int zp, Buf& B) {
+    int zw = min(zp, z1 + 1) % nz;
     if (zw < 0) zw += nz;
     const int pl = NP * zw;
     int r2 = (zw - a.box.lo[2]) % nz;
@@ -829,145 +900,124 @@ __global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
     const bool zbox = r2 < a.box.ext[2];
     const bool ztg = zw >= g.tlo[2] && zw < g.thi[2];
     const bool own_plane = zp >= z0 && zp < z1;
-#pragma unroll
-    for (int j = 0; j < NLD; ++j) {
-      rtg[j] = false;
-      rbi[j] = -1;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) rl[j][q] = R(0);
-      if (!lok[j]) continue;
-      const int i = pl + lofs[j];
-      rl[j][0] = lam_p[i];
-      rl[j][1] = lam_x[i];
-      rl[j][2] = lam_y[i];
-      rl[j][3] = lam_z[i];
-      rtg[j] = ltg[j] && ztg;
-      const int bi = (bxy[j] >= 0 && zbox) ? bxy[j] + bplane * r2 : -1;
-      rbi[j] = bi;
-      if (rtg[j] || (bi >= 0 && lown[j] && own_plane)) {
-        run[j][0] = uc_x[i];
-        run[j][1] = uc_y[i];
-        run[j][2] = uc_z[i];
-      }
-      if (bi >= 0) {
-        rbk[j] = bkp[bi];
-        rbu[j][0] = bux[bi];
-        rbu[j][1] = buy[bi];
-        rbu[j][2] = buz[bi];
-      }
+    B.tg = ltg && ztg;
+    B.bi = (bxy >= 0 && zbox) ? bxy + bplane * r2 : -1;
+    B.bown = B.bi >= 0 && lown && own_plane;
+    B.w[0] = B.w[1] = B.w[2] = R(0);
+    if (nwn > 0) B.w[0] = lam_p[pl + wofs[0]];
+    if (nwn > 1) B.w[1] = lam_p[pl + wofs[1]];
+    if (nwn > 2) B.w[2] = lam_p[pl + wofs[2]];
+    B.un[0] = B.un[1] = B.un[2] = R(0);
+    if (B.tg || B.bown) {
+      B.un[0] = uc_x[pl + lofs];
+      B.un[1] = uc_y[pl + lofs];
+      B.un[2] = uc_z[pl + lofs];
     }
+    B.bk = R(0);
+    B.bu[0] = B.bu[1] = B.bu[2] = R(0);
+    if (B.bi >= 0) {
+      B.bk = bkp[B.bi];
+      B.bu[0] = bux[B.bi];
+      B.bu[1] = buy[B.bi];
+      B.bu[2] = buz[B.bi];
+    }
+    int zo = zp - 2;
+    const bool zown = zo >= z0 && zo < z1;
+    const int iu = (zown ? NP * zo : 0) + ocol;
+    B.up[0] = up_x[iu];
+    B.up[1] = up_y[iu];
+    B.up[2] = up_z[iu];
+    B.l[0] = lam_p[pl + lofs];
+    B.l[1] = lam_x[pl + lofs];
+    B.l[2] = lam_y[pl + lofs];
+    B.l[3] = lam_z[pl + lofs];
   };
-  auto commit = [&](int zp) {
-    int zw = zp % nz;
-    if (zw < 0) zw += nz;
-    const int sl = (zp + 3) % 3;
-    const bool own_plane = zp >= z0 && zp < z1;
-#pragma unroll
-    for (int j = 0; j < NLD; ++j) {
-      const int k = threadIdx.x + j * THREADS3D;
-      if (k >= LP) continue;
-      R v0 = R(0), v1 = R(0), v2 = R(0), v3 = R(0);
-      if (lok[j]) {
-        R pb = rl[j][0];
-        if (lwn[j]) {
-          // wall nodes that copy this node's pressure hand their adjoint back
-          const int gx = lgx[j], gy = lgy[j];
-          int ox[2] = {gx, gx}, oy[2] = {gy, gy};
-          int cx = 1, cy = 1;
-          if (g.bc[0] == 1) {
-            if (gx == 1) ox[cx++] = 0;
-            else if (gx == g.n[0] - 2) ox[cx++] = g.n[0] - 1;
-          }
-          if (g.bc[1] == 1) {
-            if (gy == 1) oy[cy++] = 0;
-            else if (gy == g.n[1] - 2) oy[cy++] = g.n[1] - 1;
-          }
-          for (int ky = 0; ky < cy; ++ky)
-            for (int kx = 0; kx < cx; ++kx)
-              if (kx || ky) pb += lam_p[ox[kx] + g.n[0] * oy[ky] + NP * zw];
-        }
-        R ub0 = rl[j][1], ub1 = rl[j][2], ub2 = rl[j][3];
-        if (rtg[j]) {
-          const double un = g.ndir[0] * (double)run[j][0] + g.ndir[1] * (double)run[j][1] +
-                            g.ndir[2] * (double)run[j][2];
-          const R gs = (R)(seed * g.NTinv * (1.0 - 2.0 * g.phi * (un - Ebar)));
-          ub0 += gs * nd0;
-          ub1 += gs * nd1;
-          ub2 += gs * nd2;
-        }
-        const int bi = rbi[j];
-        if (bi >= 0) {
-          const R kk = rbk[j];
-          const R inv = R(1) / (R(1) + kk);
-          if (lown[j] && own_plane) {
-            const R kb = ub0 * (rbu[j][0] - run[j][0]) + ub1 * (rbu[j][1] - run[j][1]) +
-                         ub2 * (rbu[j][2] - run[j][2]);
-            bkbar[bi] = kb * inv;
-            bubar_x[bi] = kk * ub0 * inv;
-            bubar_y[bi] = kk * ub1 * inv;
-            bubar_z[bi] = kk * ub2 * inv;
-          }
-          ub0 *= inv;
-          ub1 *= inv;
-          ub2 *= inv;
-        }
-        v0 = pb;
-        v1 = ub0;
-        v2 = ub1;
-        v3 = ub2;
-      }
-      ring[sl][0][k] = v0;
-      ring[sl][1][k] = v1;
-      ring[sl][2][k] = v2;
-      ring[sl][3][k] = v3;
+  auto commit = [&](int zp, const Buf& B) {
+    const int sl = (zp + 2 * NR) % NR;
+    R pb = B.l[0] + (B.w[0] + B.w[1] + B.w[2]);
+    R ub0 = B.l[1], ub1 = B.l[2], ub2 = B.l[3];
+    if (B.tg) {
+      const double un = g.ndir[0] * (double)B.un[0] + g.ndir[1] * (double)B.un[1] +
+                        g.ndir[2] * (double)B.un[2];
+      const R gs = (R)(seed * g.NTinv * (1.0 - 2.0 * g.phi * (un - Ebar)));
+      ub0 += gs * nd0;
+      ub1 += gs * nd1;
+      ub2 += gs * nd2;
     }
+    if (B.bi >= 0) {
+      const R kk = B.bk;
+      const R inv = R(1) / (R(1) + kk);
+      if (B.bown) {
+        const R kb = ub0 * (B.bu[0] - B.un[0]) + ub1 * (B.bu[1] - B.un[1]) +
+                     ub2 * (B.bu[2] - B.un[2]);
+        bkbar[B.bi] = kb * inv;
+        bubar_x[B.bi] = kk * ub0 * inv;
+        bubar_y[B.bi] = kk * ub1 * inv;
+        bubar_z[B.bi] = kk * ub2 * inv;
+      }
+      ub0 *= inv;
+      ub1 *= inv;
+      ub2 *= inv;
+    }
+    ring[sl][0][tid] = lok ? pb : R(0);
+    ring[sl][1][tid] = lok ? ub0 : R(0);
+    ring[sl][2][tid] = lok ? ub1 : R(0);
+    ring[sl][3][tid] = lok ? ub2 : R(0);
   };
 
-  const int tid = threadIdx.x;
-  const bool outer = tid < TX * TY;
-  const int tx = tid % TX, ty = tid / TX;
-  const int gx = x0 + tx, gy = y0 + ty;
-  const bool own = outer && gx >= 0 && gx < g.n[0] && gy >= 0 && gy < g.n[1];
-  const int oc = (ty + 1) * FX + (tx + 1);
   // own nodes within two nodes of a wall take the one-sided stencil transposes
   const bool owx = own && g.bc[0] == 1 && (gx <= 2 || gx >= g.n[0] - 3);
   const bool owy = own && g.bc[1] == 1 && (gy <= 2 || gy >= g.n[1] - 3);
   const R A2 = R(2) * (R)g.A;
-  const R* up_x = (const R*)a.u_prev + N;
-  const R* up_y = up_x + N;
-  const R* up_z = up_x + 2 * N;
   R* lp_p = (R*)a.lam_prev;
   R* lp_x = lp_p + N;
   R* lp_y = lp_p + 2 * N;
   R* lp_z = lp_p + 3 * N;
-  R zprev[3] = {R(0), R(0), R(0)};  // own column M2_{zx}, M2_{zy}, M2_{zz} at zo - 1
-  const int fk = tid;
-  const bool fok = fk < FP;
-  const int fc = (fk / FX + 1) * LX + (fk % FX + 1);
-  const int ocol = gx + g.n[0] * gy;
-
-  fetch(z0 - 2);
-  commit(z0 - 2);
-  fetch(z0 - 1);
-  commit(z0 - 1);
-  fetch(z0);
-  for (int zs = z0 - 1; zs <= z1; ++zs) {
-    commit(zs + 1);
-    __syncthreads();
-    if (zs + 2 <= z1 + 1) fetch(zs + 2);
-    R upx = R(0), upy = R(0), upz = R(0);
-    if (zs - 1 >= z0 && own) {
-      const int i = ocol + NP * (zs - 1);
-      upx = up_x[i];
-      upy = up_y[i];
-      upz = up_z[i];
+  // moment slot: threads 0..255 take their own output position (its moments
+  // stay in registers for the output), threads 256..339 the 1-node halo ring
+  const bool fok = tid < FP;
+  int fx, fy;
+  if (outer) {
+    fx = tx + 1;
+    fy = ty + 1;
+  } else {
+    const int r = tid - TX * TY;
+    if (r < FX) {
+      fx = r;
+      fy = 0;
+    } else if (r < 2 * FX) {
+      fx = r - FX;
+      fy = FY - 1;
+    } else {
+      const int q = r - 2 * FX;  // 0 .. 2 (FY - 2) - 1
+      fx = (q & 1) ? FX - 1 : 0;
+      fy = 1 + (q >> 1);
     }
-    if (fok) {
-      const int s0 = (zs + 2) % 3, s1 = (zs + 3) % 3, s2 = (zs + 4) % 3;
-      const int rs[3] = {s0, s1, s2};  // planes zs-1, zs, zs+1
-      R M[10];
+  }
+  const int fpos = fx + FX * fy;
+  const int fc = (fy + 1) * LX + (fx + 1);
+  R Mp[10];                          // own-position moments of plane zs - 1
+  R zprev[3] = {R(0), R(0), R(0)};  // own column M2_{zx}, M2_{zy}, M2_{zz} at zs - 2
 #pragma unroll
-      for (int q = 0; q < 10; ++q) M[q] = R(0);
+  for (int q = 0; q < 10; ++q) Mp[q] = R(0);
+
+  // Iteration zs: commit plane zs+1 (buffer X) | barrier | fetch plane zs+3
+  // into X | moments of plane zs | output of plane zs-1.  The output reads
+  // other threads' moments of plane zs-1 only (written before the barrier);
+  // the z transposes use the own column's moments of planes zs-2 and zs from
+  // registers.  With a 4-plane ring one barrier per plane suffices; a
+  // 3-plane ring (less LDS) needs a second one before the next commit.
+  auto iter = [&](int zs, Buf& X) {
+    commit(zs + 1, X);
+    const R upx = X.up[0], upy = X.up[1], upz = X.up[2];
+    __syncthreads();
+    fetch(zs + 3, X);
+    R M[10];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) M[q] = R(0);
+    if (fok) {
+      const int rs[3] = {(zs + 2 * NR - 1) % NR, (zs + 2 * NR) % NR,
+                         (zs + 2 * NR + 1) % NR};  // planes zs-1, zs, zs+1
 #pragma unroll
       for (int i = 0; i < 15; ++i) {
         const int cx = Lat<15>::c[i][0], cy = Lat<15>::c[i][1], cz = Lat<15>::c[i][2];
@@ -990,56 +1040,71 @@ __global__ __launch_bounds__(THREADS3D) void k_adj3d(Geo g, AdjArgs a) {
         if (cy * cz != 0) M[9] += (cy * cz) * wF;
       }
       R(*mo)[FP] = mb[zs & 1];
-#pragma unroll
-      for (int q = 0; q < 10; ++q) mo[q][fk] = M[q];
+      mo[0][fpos] = M[4];
+      mo[1][fpos] = M[5];
+      mo[2][fpos] = M[7];
+      mo[3][fpos] = M[8];
+      mo[4][fpos] = M[9];
     }
-    __syncthreads();
     const int zo = zs - 1;
     if (zo >= z0 && own) {
-      R(*m0)[FP] = mb[zo & 1];   // plane zo
-      R(*m1)[FP] = mb[zs & 1];   // plane zo + 1
+      R(*m0)[FP] = mb[zo & 1];  // plane zo, written before this iteration's barrier
       const int i = ocol + NP * zo;
       const R ux = upx, uy = upy, uz = upz;
-      const R M0 = m0[0][oc];
-      const R Mxx = m0[4][oc], Myy = m0[5][oc], Mzz = m0[6][oc];
-      const R Mxy = m0[7][oc], Mxz = m0[8][oc], Myz = m0[9][oc];
-      R bx = R(3) * m0[1][oc] + R(9) * (Mxx * ux + Mxy * uy + Mxz * uz) - R(3) * ux * M0;
-      R by = R(3) * m0[2][oc] + R(9) * (Mxy * ux + Myy * uy + Myz * uz) - R(3) * uy * M0;
-      R bz = R(3) * m0[3][oc] + R(9) * (Mxz * ux + Myz * uy + Mzz * uz) - R(3) * uz * M0;
+      const R M0 = Mp[0];
+      const R Mxx = Mp[4], Myy = Mp[5], Mzz = Mp[6];
+      const R Mxy = Mp[7], Mxz = Mp[8], Myz = Mp[9];
+      R bx = R(3) * Mp[1] + R(9) * (Mxx * ux + Mxy * uy + Mxz * uz) - R(3) * ux * M0;
+      R by = R(3) * Mp[2] + R(9) * (Mxy * ux + Myy * uy + Myz * uz) - R(3) * uy * M0;
+      R bz = R(3) * Mp[3] + R(9) * (Mxz * ux + Myz * uy + Mzz * uz) - R(3) * uz * M0;
       // velocity-gradient transpose: D_x^T, D_y^T in plane (central, then the
       // one-sided transposes next to walls); D_z^T (periodic) from zo -+ 1
-      R tx0 = R(0.5) * (m0[4][oc - 1] - m0[4][oc + 1]);
-      R tx1 = R(0.5) * (m0[7][oc - 1] - m0[7][oc + 1]);
-      R tx2 = R(0.5) * (m0[8][oc - 1] - m0[8][oc + 1]);
-      R ty0 = R(0.5) * (m0[7][oc - FX] - m0[7][oc + FX]);
-      R ty1 = R(0.5) * (m0[5][oc - FX] - m0[5][oc + FX]);
-      R ty2 = R(0.5) * (m0[9][oc - FX] - m0[9][oc + FX]);
+      R tx0 = R(0.5) * (m0[0][oc - 1] - m0[0][oc + 1]);
+      R tx1 = R(0.5) * (m0[2][oc - 1] - m0[2][oc + 1]);
+      R tx2 = R(0.5) * (m0[3][oc - 1] - m0[3][oc + 1]);
+      R ty0 = R(0.5) * (m0[2][oc - FX] - m0[2][oc + FX]);
+      R ty1 = R(0.5) * (m0[1][oc - FX] - m0[1][oc + FX]);
+      R ty2 = R(0.5) * (m0[4][oc - FX] - m0[4][oc + FX]);
       if (owx) {
-        tx0 = dnumT(g, 0, gx, m0[4], oc, 1);
-        tx1 = dnumT(g, 0, gx, m0[7], oc, 1);
-        tx2 = dnumT(g, 0, gx, m0[8], oc, 1);
+        tx0 = dnumT(g, 0, gx, m0[0], oc, 1);
+        tx1 = dnumT(g, 0, gx, m0[2], oc, 1);
+        tx2 = dnumT(g, 0, gx, m0[3], oc, 1);
       }
       if (owy) {
-        ty0 = dnumT(g, 1, gy, m0[7], oc, FX);
-        ty1 = dnumT(g, 1, gy, m0[5], oc, FX);
-        ty2 = dnumT(g, 1, gy, m0[9], oc, FX);
+        ty0 = dnumT(g, 1, gy, m0[2], oc, FX);
+        ty1 = dnumT(g, 1, gy, m0[1], oc, FX);
+        ty2 = dnumT(g, 1, gy, m0[4], oc, FX);
       }
-      bx += A2 * (tx0 + ty0 + R(0.5) * (zprev[0] - m1[8][oc]));
-      by += A2 * (tx1 + ty1 + R(0.5) * (zprev[1] - m1[9][oc]));
-      bz += A2 * (tx2 + ty2 + R(0.5) * (zprev[2] - m1[6][oc]));
+      bx += A2 * (tx0 + ty0 + R(0.5) * (zprev[0] - M[8]));
+      by += A2 * (tx1 + ty1 + R(0.5) * (zprev[1] - M[9]));
+      bz += A2 * (tx2 + ty2 + R(0.5) * (zprev[2] - M[6]));
       lp_p[i] = R(3) * M0;
       lp_x[i] = bx;
       lp_y[i] = by;
       lp_z[i] = bz;
     }
-    if (zs >= z0 && outer) {
-      // keep own-column z-moments of plane zs - 1 for the next output
-      R(*mz)[FP] = mb[(zs - 1) & 1];
-      zprev[0] = mz[8][oc];
-      zprev[1] = mz[9][oc];
-      zprev[2] = mz[6][oc];
-    }
+    zprev[0] = Mp[8];
+    zprev[1] = Mp[9];
+    zprev[2] = Mp[6];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) Mp[q] = M[q];
+    // with three ring slots the next commit overwrites plane zs-1, read above
+    if (NR == 3) __syncthreads();
+  };
+
+  Buf bA, bB;
+  fetch(z0 - 2, bA);
+  commit(z0 - 2, bA);
+  fetch(z0 - 1, bA);
+  commit(z0 - 1, bA);
+  fetch(z0, bA);
+  fetch(z0 + 1, bB);
+  int zs = z0 - 1;
+  for (; zs + 1 <= z1; zs += 2) {
+    iter(zs, bA);
+    iter(zs + 1, bB);
   }
+  if (zs <= z1) iter(zs, bA);
 }
 
 // --------------------------------------------------------------- map
