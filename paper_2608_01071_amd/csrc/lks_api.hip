@@ -70,22 +70,38 @@ struct Profiler {
 };
 Profiler g_prof;
 
-// Wraps one launch in an event pair (on the launch stream) while profiling.
+// Times one launch while profiling.  A single-kernel scope hands its event
+// pair to the launch itself (recorded in the dispatch, so the pair brackets
+// the kernel's execution only); other scopes record the pair on the stream
+// around their launches.
 struct Scope {
   int cls = -1;
+  bool single = false;
   hipEvent_t a = nullptr, b = nullptr;
   hipStream_t s;
-  Scope(const char* name, hipStream_t st) : s(st) {
+  Scope(const char* name, hipStream_t st, bool single_kernel = false) : s(st) {
     if (!g_prof.on) return;
     std::lock_guard<std::mutex> lk(g_prof.mu);
     cls = g_prof.cls_id(name);
     a = g_prof.ev();
     b = g_prof.ev();
-    if (a) (void)hipEventRecord(a, s);
+    if (!a || !b) return;
+    single = single_kernel;
+    if (single)
+      launch_events() = {a, b};
+    else
+      (void)hipEventRecord(a, s);
   }
   ~Scope() {
     if (cls < 0 || !a || !b) return;
-    (void)hipEventRecord(b, s);
+    LaunchEvents& le = launch_events();
+    if (single && le.start) {  // the launch did not take the pair
+      le = {};
+      (void)hipEventRecord(a, s);
+      (void)hipEventRecord(b, s);
+    } else if (!single) {
+      (void)hipEventRecord(b, s);
+    }
     std::lock_guard<std::mutex> lk(g_prof.mu);
     g_prof.recs.push_back({cls, a, b});
   }
@@ -223,7 +239,7 @@ void* btape_slot(lks_plan* P, void* ws, int j) {
 
 // Body fields (kappa, u_s) of step n into `body` (layout [1+d][bmax.vol]).
 lks_status map_step(lks_plan* P, void* ws, int n, void* body, hipStream_t s) {
-  Scope sc("map", s);
+  Scope sc("map", s, true);
   HIPCHK(launch_map(P->g, P->prec, wsp(ws, P->o_kref), wsp(ws, P->o_kz), P->bmax.ext[2], nullptr,
                     tab(P, ws, n), P->bmax, body, (char*)body + P->bmax.vol * P->es, 0, s));
   return LKS_OK;
@@ -242,7 +258,7 @@ lks_status fwd_step(lks_plan* P, void* ws, int n, const void* in, void* out, con
   a.opart = obj ? (double*)wsp(ws, P->o_opart) : nullptr;
   a.flags = (int*)wsp(ws, P->o_flags);
   a.lazy_wall = lazy;
-  Scope sc("fwd_step", s);
+  Scope sc("fwd_step", s, true);
   HIPCHK(launch_forward_step(P->g, P->prec, a, s));
   return LKS_OK;
 }
@@ -342,11 +358,11 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
       a.seed = seed;
       a.E = (const double*)wsp(ws, P->o_J3) + 1;
       {
-        Scope sc("adj_step", s);
+        Scope sc("adj_step", s, true);
         HIPCHK(launch_adjoint_step(P->g, P->prec, a, s));
       }
       {
-        Scope sc("map_adj", s);
+        Scope sc("map_adj", s, true);
         HIPCHK(launch_map_adjoint(P->g, P->prec, wsp(ws, P->o_kref), nullptr, tab(P, ws, n),
                                   P->bmax, a.bkbar, a.bubar, kref_bar, n == nt ? 1 : 0,
                                   (double*)wsp(ws, P->o_mpart) + (size_t)(n - 1) * P->nblk_map * 8,
@@ -618,7 +634,7 @@ lks_status lks_map_design_to_grid(lks_plan* P, const void* kappa_ref, const doub
   HIPCHK(launch_zero(kappa, (size_t)P->g.N * P->es, s));
   HIPCHK(launch_zero(u_s, (size_t)P->g.d * P->g.N * P->es, s));
   HIPCHK(launch_kref_t(P->g, P->prec, kappa_ref, wsp(ws, P->o_kz), s));
-  Scope sc("map", s);
+  Scope sc("map", s, true);
   HIPCHK(launch_map(P->g, P->prec, kappa_ref, wsp(ws, P->o_kz), P->bmax.ext[2], m8, nullptr, box,
                     kappa, u_s, 1, s));
   return LKS_OK;
@@ -637,7 +653,7 @@ lks_status lks_step(lks_plan* P, const void* state_in, const void* kappa, const 
   a.box = full_box(P);
   a.lazy_wall = 0;
   {
-    Scope sc("fwd_step", s);
+    Scope sc("fwd_step", s, true);
     HIPCHK(launch_forward_step(P->g, P->prec, a, s));
   }
   HIPCHK(launch_wall_fixup(P->g, P->prec, state_out, s));
@@ -662,7 +678,7 @@ lks_status lks_step_adjoint(lks_plan* P, const void* state_in, const void* state
   a.bkbar = kbar;
   a.bubar = usbar;
   a.box = full_box(P);
-  Scope sc("adj_step", s);
+  Scope sc("adj_step", s, true);
   HIPCHK(launch_adjoint_step(P->g, P->prec, a, s));
   return LKS_OK;
 }
@@ -680,7 +696,7 @@ lks_status lks_map_adjoint(lks_plan* P, const void* kappa_ref, const double* mot
   if (lks_status e = host_box(P, motion8, m8, box, s)) return e;
   double* part = motion_bar8 + 8;
   {
-    Scope sc("map_adj", s);
+    Scope sc("map_adj", s, true);
     HIPCHK(launch_map_adjoint(P->g, P->prec, kappa_ref, m8, nullptr, full_box(P), kbar, usbar,
                               kref_bar, 1, part, s));
   }

@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 namespace lks {
@@ -102,6 +103,14 @@ struct Lat<15> {
                                    1.0 / 9,  1.0 / 9,  1.0 / 72, 1.0 / 72, 1.0 / 72,
                                    1.0 / 72, 1.0 / 72, 1.0 / 72, 1.0 / 72, 1.0 / 72};
 };
+
+// Profiling: when `start` is set, the next step or map launch carries this
+// event pair in its dispatch (hipExtLaunchKernelGGL), so the pair times the
+// kernel itself; the launch clears it.  Thread-local, host side only.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchEvents& launch_events();
 
 // ---- launch wrappers (lks_kernels.hip) ----
 struct FwdArgs {

@@ -1833,18 +1833,36 @@ int step_blocks(const Geo& g) {
   return d.x * d.y * d.z;
 }
 
+LaunchEvents& launch_events() {
+  static thread_local LaunchEvents e;
+  return e;
+}
+
+// Launch that carries the pending profiling event pair, if any.
+#define LKS_LAUNCH(K, GRID, BLOCK, SHMEM, STREAM, ...)                                    \
+  do {                                                                                   \
+    LaunchEvents& le_ = launch_events();                                                 \
+    if (le_.start) {                                                                     \
+      hipExtLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, le_.start, le_.stop, 0,        \
+                            __VA_ARGS__);                                                \
+      le_.start = le_.stop = nullptr;                                                    \
+    } else {                                                                             \
+      hipLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                   \
+    }                                                                                    \
+  } while (0)
+
 hipError_t launch_forward_step(const Geo& g, int precision, const FwdArgs& a, hipStream_t s) {
   dim3 grid = step_grid(g);
   if (g.d == 2) {
     if (precision == 0)
-      hipLaunchKernelGGL(k_fwd2d<float>, grid, dim3(STEP_THREADS), 0, s, g, a);
+      LKS_LAUNCH(k_fwd2d<float>, grid, dim3(STEP_THREADS), 0, s, g, a);
     else
-      hipLaunchKernelGGL(k_fwd2d<double>, grid, dim3(STEP_THREADS), 0, s, g, a);
+      LKS_LAUNCH(k_fwd2d<double>, grid, dim3(STEP_THREADS), 0, s, g, a);
   } else {
     if (precision == 0)
-      hipLaunchKernelGGL(k_fwd3d<float>, grid, dim3(THREADS3D), 0, s, g, a);
+      LKS_LAUNCH(k_fwd3d<float>, grid, dim3(THREADS3D), 0, s, g, a);
     else
-      hipLaunchKernelGGL(k_fwd3d<double>, grid, dim3(THREADS3D), 0, s, g, a);
+      LKS_LAUNCH(k_fwd3d<double>, grid, dim3(THREADS3D), 0, s, g, a);
   }
   return hipGetLastError();
 }
@@ -1853,14 +1871,14 @@ hipError_t launch_adjoint_step(const Geo& g, int precision, const AdjArgs& a, hi
   dim3 grid = step_grid(g);
   if (g.d == 2) {
     if (precision == 0)
-      hipLaunchKernelGGL(k_adj2d<float>, grid, dim3(STEP_THREADS), 0, s, g, a);
+      LKS_LAUNCH(k_adj2d<float>, grid, dim3(STEP_THREADS), 0, s, g, a);
     else
-      hipLaunchKernelGGL(k_adj2d<double>, grid, dim3(STEP_THREADS), 0, s, g, a);
+      LKS_LAUNCH(k_adj2d<double>, grid, dim3(STEP_THREADS), 0, s, g, a);
   } else {
     if (precision == 0)
-      hipLaunchKernelGGL(k_adj3d<float>, grid, dim3(THREADS3D), 0, s, g, a);
+      LKS_LAUNCH(k_adj3d<float>, grid, dim3(THREADS3D), 0, s, g, a);
     else
-      hipLaunchKernelGGL(k_adj3d<double>, grid, dim3(THREADS3D), 0, s, g, a);
+      LKS_LAUNCH(k_adj3d<double>, grid, dim3(THREADS3D), 0, s, g, a);
   }
   return hipGetLastError();
 }
@@ -1898,20 +1916,20 @@ hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf
   if (g.d == 2) {
     dim3 grid((box.ext[0] + 255) / 256, box.ext[1]);
     if (precision == 0)
-      hipLaunchKernelGGL(k_map2d<float>, grid, dim3(256), 0, s, g, (const float*)kref, m, box, si,
+      LKS_LAUNCH(k_map2d<float>, grid, dim3(256), 0, s, g, (const float*)kref, m, box, si,
                          (float*)bk, (float*)bu, full_grid);
     else
-      hipLaunchKernelGGL(k_map2d<double>, grid, dim3(256), 0, s, g, (const double*)kref, m, box, si,
+      LKS_LAUNCH(k_map2d<double>, grid, dim3(256), 0, s, g, (const double*)kref, m, box, si,
                          (double*)bk, (double*)bu, full_grid);
   } else {
     const int lz = kz_levels(g);
     constexpr int ZC = MAP_ZC_RUN;
     dim3 grid((box.ext[0] + 63) / 64, box.ext[1], (box.ext[2] + ZC - 1) / ZC);
     if (precision == 0)
-      hipLaunchKernelGGL((k_map3d<float, ZC>), grid, dim3(64), 0, s, g, (const float*)kzbuf, lz, m,
+      LKS_LAUNCH((k_map3d<float, ZC>), grid, dim3(64), 0, s, g, (const float*)kzbuf, lz, m,
                          box, si, (float*)bk, (float*)bu, full_grid);
     else
-      hipLaunchKernelGGL((k_map3d<double, ZC>), grid, dim3(64), 0, s, g, (const double*)kzbuf, lz,
+      LKS_LAUNCH((k_map3d<double, ZC>), grid, dim3(64), 0, s, g, (const double*)kzbuf, lz,
                          m, box, si, (double*)bk, (double*)bu, full_grid);
   }
   return hipGetLastError();
@@ -1938,21 +1956,21 @@ hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
   dim3 grid(mapadj_blocks(g));
   if (g.d == 3) {
     if (precision == 0)
-      hipLaunchKernelGGL(k_mapadj3d<float>, grid, dim3(MAPADJ_THREADS), 0, s, g,
+      LKS_LAUNCH(k_mapadj3d<float>, grid, dim3(MAPADJ_THREADS), 0, s, g,
                          (const float*)kref, m, box, si, (const float*)bkbar, (const float*)bubar,
                          kref_bar, overwrite, mpart);
     else
-      hipLaunchKernelGGL(k_mapadj3d<double>, grid, dim3(MAPADJ_THREADS), 0, s, g,
+      LKS_LAUNCH(k_mapadj3d<double>, grid, dim3(MAPADJ_THREADS), 0, s, g,
                          (const double*)kref, m, box, si, (const double*)bkbar, (const double*)bubar,
                          kref_bar, overwrite, mpart);
     return hipGetLastError();
   }
   if (precision == 0)
-    hipLaunchKernelGGL(k_mapadj<float>, grid, dim3(MAPADJ_THREADS), 0, s, g, (const float*)kref,
+    LKS_LAUNCH(k_mapadj<float>, grid, dim3(MAPADJ_THREADS), 0, s, g, (const float*)kref,
                        m, box, si, (const float*)bkbar, (const float*)bubar, kref_bar, overwrite,
                        mpart);
   else
-    hipLaunchKernelGGL(k_mapadj<double>, grid, dim3(MAPADJ_THREADS), 0, s, g,
+    LKS_LAUNCH(k_mapadj<double>, grid, dim3(MAPADJ_THREADS), 0, s, g,
                        (const double*)kref, m, box, si, (const double*)bkbar, (const double*)bubar,
                        kref_bar, overwrite, mpart);
   return hipGetLastError();
