@@ -188,11 +188,22 @@ lks_status lks_map_adjoint(lks_plan* plan, const void* kappa_ref, const double* 
 
 /* ---- batching: independent instances in one captured graph ---- */
 
-/* Runs forward + adjoint for `count` independent problems (each with its own
- * plan, workspace and inputs, arrays of `count` entries) as one hipGraph
- * launched on `stream`.  Outputs as for lks_forward / lks_adjoint.  The
- * graph is captured on the first call and replayed while the pointer tables
- * are unchanged. */
+/* Runs forward + adjoint for `count` independent problems (a parameter
+ * study: the instances may differ in every lks_problem field) as one hipGraph
+ * launched on `stream`; each instance is one branch of the graph, so the
+ * instances' kernels may run concurrently.
+ *   plans, gamma, chi, psi, workspace, J_out, dJ_dgamma, dJ_dchi, dJ_dpsi:
+ *     (host) arrays of `count` entries, each entry as for lks_forward /
+ *     lks_adjoint of that instance (device pointers, caller-owned).  Plans and
+ *     workspaces must be distinct.  Every instance starts from the rest state
+ *     (p = 1/3, u = 0).
+ *   dJ: device array of `count` objective seeds, or NULL for 1 each.
+ * The per-instance preludes (with their LKS_EDOMAIN checks) run eagerly
+ * first; the graph is captured on the first call and replayed while the
+ * pointer tables are unchanged (it is kept by plans[0]).  The call
+ * synchronises `stream` at its end and returns LKS_EUNSTABLE if any instance
+ * became unstable; lks_last_error names the instance.  After the call each
+ * workspace holds its instance's forward data as after lks_forward. */
 lks_status lks_batch_run(int32_t count, lks_plan* const* plans, const double* const* gamma,
                          const double* const* chi, const double* const* psi,
                          void* const* workspace, double* const* J_out, const double* dJ,

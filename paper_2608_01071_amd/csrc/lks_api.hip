@@ -138,10 +138,13 @@ struct lks_plan {
   bool use_graphs = true;
   hipStream_t cap = nullptr;  // private stream used for graph capture
   GraphCache gfwd, gadj, gbatch;
+  std::vector<const void*> bkey;       // pointer tables the batch graph was captured for
+  std::vector<hipStream_t> bstreams;   // capture branches of the batch graph
   ~lks_plan() {
     gfwd.reset();
     gadj.reset();
     gbatch.reset();
+    for (hipStream_t b : bstreams) (void)hipStreamDestroy(b);
     if (cap) (void)hipStreamDestroy(cap);
   }
 };
@@ -711,9 +714,115 @@ lks_status lks_batch_run(int32_t count, lks_plan* const* plans, const double* co
                          void* const* workspace, double* const* J_out, const double* dJ,
                          double* const* dJ_dgamma, double* const* dJ_dchi,
                          double* const* dJ_dpsi, hipStream_t s) {
-  (void)count; (void)plans; (void)gamma; (void)chi; (void)psi; (void)workspace; (void)J_out;
-  (void)dJ; (void)dJ_dgamma; (void)dJ_dchi; (void)dJ_dpsi; (void)s;
-  return fail(LKS_EINVAL, "lks_batch_run: not available yet");
+  if (count < 1 || !plans || !gamma || !chi || !psi || !workspace || !J_out || !dJ_dgamma ||
+      !dJ_dchi || !dJ_dpsi)
+    return fail(LKS_EINVAL, "lks_batch_run: null table or count < 1");
+  for (int k = 0; k < count; ++k) {
+    if (!plans[k] || !gamma[k] || !chi[k] || !psi[k] || !workspace[k] || !J_out[k] ||
+        !dJ_dgamma[k] || !dJ_dchi[k] || !dJ_dpsi[k])
+      return fail(LKS_EINVAL, "lks_batch_run: null entry " + std::to_string(k));
+    for (int j = 0; j < k; ++j)
+      if (plans[j] == plans[k] || workspace[j] == workspace[k])
+        return fail(LKS_EINVAL, "lks_batch_run: instances must not share a plan or workspace");
+  }
+  lks_plan* P0 = plans[0];
+  // Per-instance set-up, eagerly on `s`: prelude with its domain check, the
+  // initial state, the seed and the zeroed adjoint accumulators.
+  for (int k = 0; k < count; ++k) {
+    lks_plan* P = plans[k];
+    void* ws = workspace[k];
+    if (lks_status e = prelude(P, gamma[k], chi[k], psi[k], ws, s)) {
+      return fail(e, "instance " + std::to_string(k) + ": " + lks_last_error());
+    }
+    HIPCHK(launch_state_init(P->g, P->prec, ck_slot(P, ws, 0), s));
+    P->first_lazy = 1;
+    if (dJ) {
+      HIPCHK(hipMemcpyAsync(wsp(ws, P->o_seed), dJ + k, sizeof(double), hipMemcpyDeviceToDevice,
+                            s));
+    } else {
+      const double one = 1.0;
+      HIPCHK(hipMemcpyAsync(wsp(ws, P->o_seed), &one, sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(launch_zero(lam_slot(P, ws, 0), (size_t)P->S * P->es, s));
+    HIPCHK(launch_zero(wsp(ws, P->o_badj), body_bytes(P), s));
+  }
+  // one graph: instance k's forward march, objective copy, adjoint march and
+  // epilogue form branch k, forked from and joined to the launch stream
+  std::vector<const void*> key;
+  key.push_back((const void*)(intptr_t)count);
+  for (int k = 0; k < count; ++k) {
+    key.insert(key.end(), {plans[k], gamma[k], workspace[k], J_out[k], dJ_dgamma[k], dJ_dchi[k],
+                           dJ_dpsi[k]});
+  }
+  auto branch = [&](int k, hipStream_t st) -> lks_status {
+    lks_plan* P = plans[k];
+    void* ws = workspace[k];
+    if (lks_status e = forward_loop(P, ws, st)) return e;
+    HIPCHK(hipMemcpyAsync(J_out[k], wsp(ws, P->o_J3), 3 * sizeof(double),
+                          hipMemcpyDeviceToDevice, st));
+    if (lks_status e = adjoint_loop(P, ws, st)) return e;
+    return sens(P, gamma[k], ws, dJ_dgamma[k], dJ_dchi[k], dJ_dpsi[k], st);
+  };
+  if (!P0->use_graphs || g_prof.on) {
+    for (int k = 0; k < count; ++k)
+      if (lks_status e = branch(k, s)) return e;
+  } else {
+    GraphCache& gc = P0->gbatch;
+    if (!(gc.exec && P0->bkey == key)) {
+      gc.reset();
+      P0->bkey.clear();
+      if (!P0->cap) HIPCHK(hipStreamCreateWithFlags(&P0->cap, hipStreamNonBlocking));
+      while ((int)P0->bstreams.size() < count) {
+        hipStream_t b;
+        HIPCHK(hipStreamCreateWithFlags(&b, hipStreamNonBlocking));
+        P0->bstreams.push_back(b);
+      }
+      std::vector<hipEvent_t> evs(count + 1, nullptr);
+      for (auto& e : evs) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      auto destroy = [&]() {
+        for (auto& e : evs) (void)hipEventDestroy(e);
+      };
+      HIPCHK(hipStreamBeginCapture(P0->cap, hipStreamCaptureModeThreadLocal));
+      lks_status err = LKS_OK;
+      hipError_t he = hipEventRecord(evs[count], P0->cap);
+      for (int k = 0; k < count && !err && he == hipSuccess; ++k) {
+        hipStream_t b = P0->bstreams[k];
+        he = hipStreamWaitEvent(b, evs[count], 0);
+        if (he == hipSuccess) err = branch(k, b);
+        if (!err && he == hipSuccess) he = hipEventRecord(evs[k], b);
+        if (!err && he == hipSuccess) he = hipStreamWaitEvent(P0->cap, evs[k], 0);
+      }
+      hipGraph_t graph = nullptr;
+      hipError_t ce = hipStreamEndCapture(P0->cap, &graph);
+      destroy();
+      if (err || he != hipSuccess || ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (err) return err;
+        return fail(LKS_EHIP, std::string("batch capture: ") +
+                                  hipGetErrorString(he != hipSuccess ? he : ce));
+      }
+      hipError_t ie = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) {
+        gc.exec = nullptr;
+        return fail(LKS_EHIP, std::string("batch graph instantiate: ") + hipGetErrorString(ie));
+      }
+      P0->bkey = key;
+    }
+    HIPCHK(hipGraphLaunch(gc.exec, s));
+  }
+  // instability flags of every instance (one synchronisation)
+  std::vector<int> flags(count, 0);
+  for (int k = 0; k < count; ++k)
+    HIPCHK(hipMemcpyAsync(&flags[k], wsp(workspace[k], plans[k]->o_flags), sizeof(int),
+                          hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int k = 0; k < count; ++k) plans[k]->fwd_ws = workspace[k];
+  for (int k = 0; k < count; ++k)
+    if (flags[k])
+      return fail(LKS_EUNSTABLE, "instance " + std::to_string(k) +
+                                     ": the march produced |u| >= 0.5 or a non-finite value");
+  return LKS_OK;
 }
 
 lks_status lks_profile_enable(int32_t on) {

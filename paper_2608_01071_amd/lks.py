@@ -268,6 +268,51 @@ class LKSObjective(torch.autograd.Function):
                 g["dpsi"].reshape(psi.shape).to(psi.dtype), None)
 
 
+class Batch:
+    """Independent instances run as one captured graph (lks_batch_run).
+
+    Inputs are copied into buffers owned by this object, so repeated calls
+    keep the same pointer tables and replay the captured graph."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        n = len(self.plans)
+        dev = self.plans[0].device
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.g = [torch.empty(pl.problem.M, **f64) for pl in self.plans]
+        self.c = [torch.empty(pl.problem.nt * 3, **f64) for pl in self.plans]
+        self.s = [torch.empty(pl.problem.nt, **f64) for pl in self.plans]
+        self.J = [torch.empty(3, **f64) for _ in self.plans]
+        self.dg = [torch.empty(pl.problem.M, **f64) for pl in self.plans]
+        self.dc = [torch.empty(pl.problem.nt * 3, **f64) for pl in self.plans]
+        self.dp = [torch.empty(pl.problem.nt, **f64) for pl in self.plans]
+        self.seed = torch.ones(n, **f64)
+        tab = lambda ts: (_VP * n)(*[t.data_ptr() for t in ts])
+        self._tabs = dict(plans=(_VP * n)(*[pl.handle.value for pl in self.plans]),
+                          g=tab(self.g), c=tab(self.c), s=tab(self.s),
+                          ws=tab([pl.workspace for pl in self.plans]), J=tab(self.J),
+                          dg=tab(self.dg), dc=tab(self.dc), dp=tab(self.dp))
+
+    def run(self, gammas, chis, psis, dJ=None):
+        """Returns a list of (J3, {"dgamma", "dchi", "dpsi"}) device tensors."""
+        for k, pl in enumerate(self.plans):
+            self.g[k].copy_(torch.as_tensor(gammas[k], dtype=torch.float64).reshape(-1))
+            self.c[k].copy_(torch.as_tensor(chis[k], dtype=torch.float64).reshape(-1))
+            self.s[k].copy_(torch.as_tensor(psis[k], dtype=torch.float64).reshape(-1))
+        if dJ is not None:
+            self.seed.copy_(torch.as_tensor(dJ, dtype=torch.float64).reshape(-1))
+        t = self._tabs
+        _check(lib().lks_batch_run(len(self.plans), t["plans"], t["g"], t["c"], t["s"], t["ws"],
+                                   t["J"], _ptr(self.seed), t["dg"], t["dc"], t["dp"],
+                                   _stream()))
+        for pl in self.plans:
+            pl._keep = None
+        return [(self.J[k], {"dgamma": self.dg[k],
+                             "dchi": self.dc[k].reshape(pl.problem.nt, 3),
+                             "dpsi": self.dp[k]})
+                for k, pl in enumerate(self.plans)]
+
+
 def profile_enable(on: bool = True):
     _check(lib().lks_profile_enable(1 if on else 0))
 

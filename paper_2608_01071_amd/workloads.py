@@ -136,7 +136,7 @@ def _centred(n: int, half: float) -> Tuple[float, float]:
 def make_2d(nside: int, mside: int, nt: int, r_t: int, nu: float, seed: int,
             kappa_max: float = 300.0, phi: float = 0.0, amp: float = 4.0,
             sigma_n: float = 0.25, th_amp: float = 0.1, precision: int = 1,
-            ckpt_k: int = 0, ny: Optional[int] = None):
+            ckpt_k: int = 0, ny: Optional[int] = None, th_sigma: float = 0.01):
     """D2Q9 channel: periodic x, walls in y, target = column x = 0."""
     ny = nside if ny is None else ny
     lo0, hi0 = _centred(nside, 8.0)
@@ -147,7 +147,7 @@ def make_2d(nside: int, mside: int, nt: int, r_t: int, nu: float, seed: int,
                 tgt_lo=(0, 1, 0), tgt_hi=(1, ny - 1, 1), ndir=(1.0, 0.0, 0.0), phi=phi,
                 precision=precision, ckpt_k=ckpt_k)
     gamma = density(p, seed)
-    chi, psi = motion(p, seed, amp=amp, sigma_n=sigma_n, th_amp=th_amp)
+    chi, psi = motion(p, seed, amp=amp, sigma_n=sigma_n, th_amp=th_amp, th_sigma=th_sigma)
     return p, gamma, chi, psi
 
 
@@ -215,6 +215,10 @@ def c5_instances(seed: int = 4, nt: int = 4000, precision: int = 0):
         u_ref = 2 * math.pi * 4.0 / nt + 2 * math.pi * 0.1 / nt * ms * 0.7071
         nu = max(reynolds_nu(u_ref, ms, res[k % 4]), 0.005)
         rt = radii[k % 4]
+        sig = 0.01 if rt < 5 else 0.25
+        # rotation noise sized so the body's rim moves by about sigma_n cells:
+        # with little temporal filtering a 0.01 rad per-step jitter would move
+        # the rim of a large body faster than the lattice allows
         out.append(make_2d(s, ms, nt, rt, nu=nu, seed=seed * 100 + k, precision=precision,
-                           sigma_n=0.01 if rt < 5 else 0.25, ckpt_k=200))
+                           sigma_n=sig, th_sigma=sig / (0.7071 * ms), ckpt_k=200))
     return out

@@ -400,3 +400,37 @@ def test_graph_replay_matches_eager(name):
                    cpu(g_g["adj_initial"])]
             for a, b in zip(got, ref):
                 assert np.array_equal(a, b), (k, rep)
+
+
+def test_batch_run_matches_solo_runs(orc):
+    """Uneven independent instances in one captured graph give the solo results
+    bitwise (same kernels, same order per instance), and the first instance
+    also matches the oracle; a second call replays the graph."""
+    lks = lk()
+    specs = [
+        W.make_2d(40, 12, 24, 3, nu=0.1, seed=11, amp=0.5, sigma_n=0.05, th_amp=0.05,
+                  precision=0, ckpt_k=7),
+        W.make_2d(53, 16, 24, 5, nu=0.08, seed=12, amp=0.5, sigma_n=0.05, th_amp=0.05,
+                  precision=0, ckpt_k=7),
+        W.make_2d(37, 10, 24, 1, nu=0.12, seed=13, amp=0.5, sigma_n=0.05, th_amp=0.05,
+                  precision=0, ckpt_k=7, ny=29),
+    ]
+    solo = []
+    for p, g, c, s in specs:
+        pl = lks.Plan(p)
+        J3, _ = pl.forward(g, c, s)
+        gr = pl.adjoint(g, c, s)
+        solo.append((cpu(J3), {k: cpu(gr[k]) for k in ("dgamma", "dchi", "dpsi")}))
+    plans = [lks.Plan(p) for p, *_ in specs]
+    b = lks.Batch(plans)
+    for call in range(2):
+        out = b.run([x[1] for x in specs], [x[2] for x in specs], [x[3] for x in specs])
+        for k, (J3, gr) in enumerate(out):
+            assert np.array_equal(cpu(J3), solo[k][0]), (call, k)
+            for key in ("dgamma", "dchi", "dpsi"):
+                assert np.array_equal(cpu(gr[key]), solo[k][1][key]), (call, k, key)
+    p, g, c, s = specs[0]
+    ref = orc.forward(p, g, c, s, want_final=False)
+    assert abs(solo[0][0][0] - ref["J"]) <= 1e-4 * abs(ref["J"])
+    adj = orc.adjoint(p, g, c, s)
+    assert l2err(solo[0][1]["dgamma"], adj["dgamma"]) < 1e-3
