@@ -132,7 +132,7 @@ struct lks_plan {
   Box bmax;     // strides, volume and launch extents of the body buffers
   // workspace offsets (bytes)
   size_t o_mot, o_tab, o_info, o_kref, o_flags, o_J3, o_seed, o_opart, o_ck, o_pp, o_tape,
-      o_body, o_btape, o_badj, o_lam, o_krefbar, o_mpart, o_mbar, o_den, o_kz, total;
+      o_body, o_btape, o_badj, o_lam, o_krefbar, o_mpart, o_mbar, o_den, o_kz, o_geo, total;
   int first_lazy = 1;
   void* fwd_ws = nullptr;
   bool use_graphs = true;
@@ -248,8 +248,8 @@ lks_status map_step(lks_plan* P, void* ws, int n, void* body, hipStream_t s) {
   return LKS_OK;
 }
 
-lks_status fwd_step(lks_plan* P, void* ws, int n, const void* in, void* out, const void* body,
-                    int lazy, int obj, hipStream_t s) {
+FwdArgs fwd_args(lks_plan* P, void* ws, int n, const void* in, void* out, const void* body,
+                 int lazy, int obj) {
   FwdArgs a;
   memset(&a, 0, sizeof a);
   a.in = in;
@@ -261,6 +261,12 @@ lks_status fwd_step(lks_plan* P, void* ws, int n, const void* in, void* out, con
   a.opart = obj ? (double*)wsp(ws, P->o_opart) : nullptr;
   a.flags = (int*)wsp(ws, P->o_flags);
   a.lazy_wall = lazy;
+  return a;
+}
+
+lks_status fwd_step(lks_plan* P, void* ws, int n, const void* in, void* out, const void* body,
+                    int lazy, int obj, hipStream_t s) {
+  const FwdArgs a = fwd_args(P, ws, n, in, out, body, lazy, obj);
   Scope sc("fwd_step", s, true);
   HIPCHK(launch_forward_step(P->g, P->prec, a, s));
   return LKS_OK;
@@ -328,11 +334,46 @@ const void* final_state(lks_plan* P, void* ws) {
 
 // Reverse sweep with segment recomputation: launches only.  The recompute
 // keeps each step's body fields, which the reverse steps then reuse.
+// Adjoint step n of segment sg (first step nb = sg K + 1), reading the
+// adjoint state from lambda slot `cur`.
+AdjArgs adj_args(lks_plan* P, void* ws, int n, int sg, int cur) {
+  const int nb = sg * P->K + 1;
+  const void* body = btape_slot(P, ws, n - nb);
+  AdjArgs a;
+  memset(&a, 0, sizeof a);
+  a.lam = lam_slot(P, ws, cur);
+  a.lam_prev = lam_slot(P, ws, 1 - cur);
+  a.u_prev = (n == nb) ? ck_slot(P, ws, sg) : tape_slot(P, ws, n - nb - 1);
+  a.u_cur = tape_slot(P, ws, n - nb);
+  a.bk = body;
+  a.bu = (const char*)body + P->bmax.vol * P->es;
+  a.bkbar = wsp(ws, P->o_badj);
+  a.bubar = wsp(ws, P->o_badj) + P->bmax.vol * P->es;
+  a.box = P->bmax;
+  a.si = tab(P, ws, n);
+  a.seed = (const double*)wsp(ws, P->o_seed);
+  a.E = (const double*)wsp(ws, P->o_J3) + 1;
+  return a;
+}
+
+// Map transpose of step n: the per-step motion partials go to row n - 1.
+MapAdjArgs mapadj_args(lks_plan* P, void* ws, int n) {
+  MapAdjArgs m;
+  memset(&m, 0, sizeof m);
+  m.kref = wsp(ws, P->o_kref);
+  m.si = tab(P, ws, n);
+  m.box = P->bmax;
+  m.bkbar = wsp(ws, P->o_badj);
+  m.bubar = wsp(ws, P->o_badj) + P->bmax.vol * P->es;
+  m.kref_bar = (double*)wsp(ws, P->o_krefbar);
+  m.mpart = (double*)wsp(ws, P->o_mpart) + (size_t)(n - 1) * P->nblk_map * 8;
+  m.overwrite = n == P->g.nt ? 1 : 0;
+  return m;
+}
+
 lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
   const int nt = P->g.nt, K = P->K;
   int cur = 0;
-  double* kref_bar = (double*)wsp(ws, P->o_krefbar);
-  const double* seed = (const double*)wsp(ws, P->o_seed);
   for (int sg = P->nck - 1; sg >= 0; --sg) {
     const int nb = sg * K + 1, ne = std::min((sg + 1) * K, nt);
     // recompute the segment into the tape: tape[n - nb] holds state n
@@ -345,31 +386,16 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
         return e;
     }
     for (int n = ne; n >= nb; --n) {
-      const void* body = btape_slot(P, ws, n - nb);
-      AdjArgs a;
-      memset(&a, 0, sizeof a);
-      a.lam = lam_slot(P, ws, cur);
-      a.lam_prev = lam_slot(P, ws, 1 - cur);
-      a.u_prev = (n == nb) ? ck_slot(P, ws, sg) : tape_slot(P, ws, n - nb - 1);
-      a.u_cur = tape_slot(P, ws, n - nb);
-      a.bk = body;
-      a.bu = (const char*)body + P->bmax.vol * P->es;
-      a.bkbar = wsp(ws, P->o_badj);
-      a.bubar = wsp(ws, P->o_badj) + P->bmax.vol * P->es;
-      a.box = P->bmax;
-      a.si = tab(P, ws, n);
-      a.seed = seed;
-      a.E = (const double*)wsp(ws, P->o_J3) + 1;
+      const AdjArgs a = adj_args(P, ws, n, sg, cur);
       {
         Scope sc("adj_step", s, true);
         HIPCHK(launch_adjoint_step(P->g, P->prec, a, s));
       }
       {
+        const MapAdjArgs m = mapadj_args(P, ws, n);
         Scope sc("map_adj", s, true);
-        HIPCHK(launch_map_adjoint(P->g, P->prec, wsp(ws, P->o_kref), nullptr, tab(P, ws, n),
-                                  P->bmax, a.bkbar, a.bubar, kref_bar, n == nt ? 1 : 0,
-                                  (double*)wsp(ws, P->o_mpart) + (size_t)(n - 1) * P->nblk_map * 8,
-                                  s));
+        HIPCHK(launch_map_adjoint(P->g, P->prec, m.kref, nullptr, m.si, m.box, m.bkbar, m.bubar,
+                                  m.kref_bar, m.overwrite, m.mpart, s));
       }
       cur = 1 - cur;
     }
@@ -510,6 +536,7 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   P->o_mbar = take((size_t)g.nt * 8 * sizeof(double));
   P->o_den = take((size_t)g.nt * 6 * sizeof(double));
   P->o_kz = take(kz_bytes(g, P->bmax.ext[2], P->prec));
+  P->o_geo = take(sizeof(Geo));
   P->total = off;
   *out = P;
   if (workspace_bytes) *workspace_bytes = P->total;
@@ -709,6 +736,109 @@ lks_status lks_map_adjoint(lks_plan* P, const void* kappa_ref, const double* mot
 
 int32_t lks_map_adjoint_blocks(lks_plan* P) { return P ? P->nblk_map : 0; }
 
+// Forward + adjoint of up to BATCH_MAX 2D instances with equal step count,
+// checkpoint interval and precision: every kernel of a step is ONE launch
+// covering all instances (instance k owns a block range), so the per-step
+// launch count does not grow with the number of instances.  The argument
+// construction is the single-instance loops' own (fwd_args, adj_args,
+// mapadj_args), so each instance computes exactly what it computes alone.
+lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
+                         const double* const* gamma, double* const* J_out, double* const* dg,
+                         double* const* dchi, double* const* dpsi, hipStream_t s) {
+  const int prec = plans[0]->prec, nt = plans[0]->g.nt, K = plans[0]->K;
+  const int nck = plans[0]->nck;
+  auto round8 = [](int v) { return (v + 7) / 8 * 8; };
+  Batch<FwdArgs> fb;
+  Batch<AdjArgs> ab;
+  Batch<MapArgs> mb;
+  Batch<MapAdjArgs> qb;
+  memset(&fb, 0, sizeof fb);
+  memset(&ab, 0, sizeof ab);
+  memset(&mb, 0, sizeof mb);
+  memset(&qb, 0, sizeof qb);
+  fb.count = ab.count = mb.count = qb.count = count;
+  for (int k = 0; k < count; ++k) {
+    lks_plan* P = plans[k];
+    const Geo* gp = (const Geo*)wsp(ws[k], P->o_geo);
+    fb.geo[k] = ab.geo[k] = mb.geo[k] = qb.geo[k] = gp;
+    const int sb = round8(step_blocks_2d(P->g));
+    fb.start[k + 1] = fb.start[k] + sb;
+    ab.start[k + 1] = ab.start[k] + sb;
+    int bxn = 0;
+    mb.start[k + 1] = mb.start[k] + round8(map_blocks_2d(P->bmax, &bxn));
+    mb.a[k].kref = wsp(ws[k], P->o_kref);
+    mb.a[k].box = P->bmax;
+    mb.a[k].bxn = bxn;
+    qb.start[k + 1] = qb.start[k] + round8(mapadj_blocks(P->g));
+  }
+  auto map_all = [&](int n, int sg_body) -> lks_status {
+    // sg_body < 0: the forward march's body buffer; else the tape slot of step n
+    for (int k = 0; k < count; ++k) {
+      lks_plan* P = plans[k];
+      void* body = sg_body < 0 ? wsp(ws[k], P->o_body)
+                               : btape_slot(P, ws[k], n - (sg_body * K + 1));
+      mb.a[k].si = tab(P, ws[k], n);
+      mb.a[k].bk = body;
+      mb.a[k].bu = (char*)body + P->bmax.vol * P->es;
+    }
+    HIPCHK(launch_map_batch(prec, mb, s));
+    return LKS_OK;
+  };
+  // forward march
+  std::vector<const void*> in(count);
+  for (int k = 0; k < count; ++k) {
+    lks_plan* P = plans[k];
+    HIPCHK(launch_zero(wsp(ws[k], P->o_flags), 64 * sizeof(int), s));
+    HIPCHK(launch_zero(wsp(ws[k], P->o_opart), (size_t)P->nblk_step * 2 * sizeof(double), s));
+    in[k] = ck_slot(P, ws[k], 0);
+  }
+  for (int n = 1; n <= nt; ++n) {
+    if (lks_status e = map_all(n, -1)) return e;
+    for (int k = 0; k < count; ++k) {
+      lks_plan* P = plans[k];
+      void* out = (n % K == 0 && n / K < nck) ? ck_slot(P, ws[k], n / K) : pp_slot(P, ws[k], n & 1);
+      fb.a[k] = fwd_args(P, ws[k], n, in[k], out, wsp(ws[k], P->o_body),
+                         n == 1 ? P->first_lazy : 1, 1);
+      in[k] = out;
+    }
+    HIPCHK(launch_forward_step_batch(prec, fb, s));
+  }
+  for (int k = 0; k < count; ++k) {
+    lks_plan* P = plans[k];
+    HIPCHK(launch_objective_final(P->g, (const double*)wsp(ws[k], P->o_opart),
+                                  step_blocks(P->g), (double*)wsp(ws[k], P->o_J3), s));
+    HIPCHK(hipMemcpyAsync(J_out[k], wsp(ws[k], P->o_J3), 3 * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+  }
+  // adjoint march, segment by segment
+  int cur = 0;
+  for (int sg = nck - 1; sg >= 0; --sg) {
+    const int nb = sg * K + 1, ne = std::min((sg + 1) * K, nt);
+    for (int n = nb; n <= ne; ++n) {
+      if (lks_status e = map_all(n, sg)) return e;
+      for (int k = 0; k < count; ++k) {
+        lks_plan* P = plans[k];
+        const void* src = (n == nb) ? ck_slot(P, ws[k], sg) : tape_slot(P, ws[k], n - nb - 1);
+        fb.a[k] = fwd_args(P, ws[k], n, src, tape_slot(P, ws[k], n - nb),
+                           btape_slot(P, ws[k], n - nb), (n == 1) ? P->first_lazy : 1, 0);
+      }
+      HIPCHK(launch_forward_step_batch(prec, fb, s));
+    }
+    for (int n = ne; n >= nb; --n) {
+      for (int k = 0; k < count; ++k) {
+        ab.a[k] = adj_args(plans[k], ws[k], n, sg, cur);
+        qb.a[k] = mapadj_args(plans[k], ws[k], n);
+      }
+      HIPCHK(launch_adjoint_step_batch(prec, ab, s));
+      HIPCHK(launch_map_adjoint_batch(prec, qb, s));
+      cur = 1 - cur;
+    }
+  }
+  for (int k = 0; k < count; ++k)
+    if (lks_status e = sens(plans[k], gamma[k], ws[k], dg[k], dchi[k], dpsi[k], s)) return e;
+  return LKS_OK;
+}
+
 lks_status lks_batch_run(int32_t count, lks_plan* const* plans, const double* const* gamma,
                          const double* const* chi, const double* const* psi,
                          void* const* workspace, double* const* J_out, const double* dJ,
@@ -745,7 +875,14 @@ lks_status lks_batch_run(int32_t count, lks_plan* const* plans, const double* co
     }
     HIPCHK(launch_zero(lam_slot(P, ws, 0), (size_t)P->S * P->es, s));
     HIPCHK(launch_zero(wsp(ws, P->o_badj), body_bytes(P), s));
+    HIPCHK(hipMemcpyAsync(wsp(ws, P->o_geo), &P->g, sizeof(Geo), hipMemcpyHostToDevice, s));
   }
+  // 2D instances with a common step count, checkpoint interval and precision
+  // share every launch (groups of BATCH_MAX); others run as graph branches
+  bool shared = true;
+  for (int k = 0; k < count; ++k)
+    shared = shared && plans[k]->g.d == 2 && plans[k]->prec == P0->prec &&
+             plans[k]->g.nt == P0->g.nt && plans[k]->K == P0->K && plans[k]->nck == P0->nck;
   // one graph: instance k's forward march, objective copy, adjoint march and
   // epilogue form branch k, forked from and joined to the launch stream
   std::vector<const void*> key;
@@ -754,6 +891,15 @@ lks_status lks_batch_run(int32_t count, lks_plan* const* plans, const double* co
     key.insert(key.end(), {plans[k], gamma[k], workspace[k], J_out[k], dJ_dgamma[k], dJ_dchi[k],
                            dJ_dpsi[k]});
   }
+  auto shared_march = [&](hipStream_t st) -> lks_status {
+    for (int k0 = 0; k0 < count; k0 += BATCH_MAX) {
+      const int c = std::min(BATCH_MAX, count - k0);
+      if (lks_status e = batched_march(c, plans + k0, workspace + k0, gamma + k0, J_out + k0,
+                                       dJ_dgamma + k0, dJ_dchi + k0, dJ_dpsi + k0, st))
+        return e;
+    }
+    return LKS_OK;
+  };
   auto branch = [&](int k, hipStream_t st) -> lks_status {
     lks_plan* P = plans[k];
     void* ws = workspace[k];
@@ -763,9 +909,24 @@ lks_status lks_batch_run(int32_t count, lks_plan* const* plans, const double* co
     if (lks_status e = adjoint_loop(P, ws, st)) return e;
     return sens(P, gamma[k], ws, dJ_dgamma[k], dJ_dchi[k], dJ_dpsi[k], st);
   };
+  key.push_back((const void*)(intptr_t)(shared ? 1 : 0));
   if (!P0->use_graphs || g_prof.on) {
-    for (int k = 0; k < count; ++k)
-      if (lks_status e = branch(k, s)) return e;
+    if (shared) {
+      if (lks_status e = shared_march(s)) return e;
+    } else {
+      for (int k = 0; k < count; ++k)
+        if (lks_status e = branch(k, s)) return e;
+    }
+  } else if (shared) {
+    GraphCache& gc = P0->gbatch;
+    if (!(gc.exec && P0->bkey == key)) {
+      gc.reset();
+      P0->bkey.clear();
+      if (lks_status e = run_loop(P0, gc, workspace[0], 0, s, shared_march)) return e;
+      P0->bkey = key;
+    } else {
+      HIPCHK(hipGraphLaunch(gc.exec, s));
+    }
   } else {
     GraphCache& gc = P0->gbatch;
     if (!(gc.exec && P0->bkey == key)) {

@@ -168,6 +168,46 @@ hipError_t launch_reduce_parts(const Geo& g, const double* part, int nblk, doubl
                               hipStream_t s);
 hipError_t launch_wall_fixup(const Geo& g, int precision, void* st, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// ---- batched 2D launches: one launch covers the same step of up to
+// BATCH_MAX independent instances; instance k owns blocks
+// [start[k], start[k+1]) (starts are multiples of 8, the extra blocks of an
+// instance exit at once).  Geo lives in each instance's workspace.
+constexpr int BATCH_MAX = 16;
+struct MapArgs {
+  const void* kref;
+  const StepInfo* si;
+  Box box;
+  void* bk;
+  void* bu;
+  int bxn;  // blocks along x of one box row
+};
+struct MapAdjArgs {
+  const void* kref;
+  const StepInfo* si;
+  Box box;
+  const void* bkbar;
+  const void* bubar;
+  double* kref_bar;
+  double* mpart;
+  int overwrite;
+};
+template <class A>
+struct Batch {
+  const Geo* geo[BATCH_MAX];
+  A a[BATCH_MAX];
+  int start[BATCH_MAX + 1];
+  int count;
+};
+static_assert(sizeof(Batch<AdjArgs>) < 4000 && sizeof(Batch<FwdArgs>) < 4000 &&
+                  sizeof(Batch<MapArgs>) < 4000 && sizeof(Batch<MapAdjArgs>) < 4000,
+              "batched launch arguments must fit the kernel argument buffer");
+int step_blocks_2d(const Geo& g);  // tiles of the 2D step kernels
+int map_blocks_2d(const Box& bmax, int* bxn);
+hipError_t launch_forward_step_batch(int precision, const Batch<FwdArgs>& b, hipStream_t s);
+hipError_t launch_adjoint_step_batch(int precision, const Batch<AdjArgs>& b, hipStream_t s);
+hipError_t launch_map_batch(int precision, const Batch<MapArgs>& b, hipStream_t s);
+hipError_t launch_map_adjoint_batch(int precision, const Batch<MapAdjArgs>& b, hipStream_t s);
 __host__ __device__ void body_box(const Geo& g, const double* m8, int* out);
 
 }  // namespace lks

@@ -142,9 +142,9 @@ __device__ __forceinline__ R dnumT(const Geo& g, int a, int v, const R* s, int c
 // contiguous run of tiles (x fastest, then y, then z segment), so tiles that
 // share halo nodes run on the same XCD and hit the same L2.
 constexpr int NUM_XCD = 8;
-__device__ __forceinline__ int xcd_tile(int nbx, int nby, int nbz, int& bx, int& by, int& bz) {
+__device__ __forceinline__ int xcd_tile_of(int b, int nbx, int nby, int nbz, int& bx, int& by,
+                                           int& bz) {
   const int total = nbx * nby * nbz;
-  const int b = blockIdx.x;
   const int xcd = b % NUM_XCD, slot = b / NUM_XCD;
   const int q = total / NUM_XCD, r = total % NUM_XCD;
   const int t = (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
@@ -152,6 +152,9 @@ __device__ __forceinline__ int xcd_tile(int nbx, int nby, int nbz, int& bx, int&
   by = (t / nbx) % nby;
   bz = t / (nbx * nby);
   return t;
+}
+__device__ __forceinline__ int xcd_tile(int nbx, int nby, int nbz, int& bx, int& by, int& bz) {
+  return xcd_tile_of(blockIdx.x, nbx, nby, nbz, bx, by, bz);
 }
 __device__ __forceinline__ int tiles_x(const Geo& g) { return (g.n[0] - g.org[0] + TILE_X - 1) / TILE_X; }
 __device__ __forceinline__ int tiles_y(const Geo& g) { return (g.n[1] - g.org[1] + TILE_Y - 1) / TILE_Y; }
@@ -266,7 +269,7 @@ __device__ __forceinline__ void finish_node(const Geo& g, const FwdArgs& a, int 
 
 // ------------------------------------------------------ forward, D2Q9
 template <class R>
-__global__ __launch_bounds__(STEP_THREADS) void k_fwd2d(Geo g, FwdArgs a) {
+__device__ __forceinline__ void fwd2d_tile(const Geo& g, FwdArgs a, int bid) {
   apply_step(a.box, a.si);
   constexpr int TX = TILE_X, TY = TILE_Y;
   constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
@@ -275,7 +278,7 @@ __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d(Geo g, FwdArgs a) {
   const R* in = (const R*)a.in;
   const long long N = g.N;
   int tbx, tby, tbz;
-  const int tlin = xcd_tile(tiles_x(g), tiles_y(g), 1, tbx, tby, tbz);
+  const int tlin = xcd_tile_of(bid, tiles_x(g), tiles_y(g), 1, tbx, tby, tbz);
   const int x0 = tbx * TX + g.org[0], y0 = tby * TY + g.org[1];
   for (int k = threadIdx.x; k < LX * LY; k += STEP_THREADS) {
     int gx = x0 - 2 + k % LX, gy = y0 - 2 + k / LX;
@@ -339,6 +342,11 @@ __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d(Geo g, FwdArgs a) {
       a.opart[2 * tlin + 1] += tot[1];
     }
   }
+}
+
+template <class R>
+__global__ __launch_bounds__(STEP_THREADS) void k_fwd2d(Geo g, FwdArgs a) {
+  fwd2d_tile<R>(g, a, blockIdx.x);
 }
 
 // ------------------------------------------------------ forward, D3Q15
@@ -706,7 +714,7 @@ __device__ __forceinline__ void adj_star(const Geo& g, const AdjArgs& a, int x, 
 
 // ------------------------------------------------------ adjoint, D2Q9
 template <class R>
-__global__ __launch_bounds__(STEP_THREADS) void k_adj2d(Geo g, AdjArgs a) {
+__device__ __forceinline__ void adj2d_tile(const Geo& g, AdjArgs a, int bid) {
   apply_step(a.box, a.si);
   constexpr int TX = TILE_X, TY = TILE_Y;
   constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
@@ -714,7 +722,7 @@ __global__ __launch_bounds__(STEP_THREADS) void k_adj2d(Geo g, AdjArgs a) {
   __shared__ R sm[6][FY * FX];     // M0, M1x, M1y, M2xx, M2yy, M2xy
   const long long N = g.N;
   int tbx, tby, tbz;
-  xcd_tile(tiles_x(g), tiles_y(g), 1, tbx, tby, tbz);
+  xcd_tile_of(bid, tiles_x(g), tiles_y(g), 1, tbx, tby, tbz);
   const int x0 = tbx * TX + g.org[0], y0 = tby * TY + g.org[1];
   for (int k = threadIdx.x; k < LX * LY; k += STEP_THREADS) {
     int lx = k % LX, ly = k / LX;
@@ -778,6 +786,11 @@ __global__ __launch_bounds__(STEP_THREADS) void k_adj2d(Geo g, AdjArgs a) {
   lp[i] = px;
   lp[N + i] = bx;
   lp[2 * N + i] = by;
+}
+
+template <class R>
+__global__ __launch_bounds__(STEP_THREADS) void k_adj2d(Geo g, AdjArgs a) {
+  adj2d_tile<R>(g, a, blockIdx.x);
 }
 
 // ------------------------------------------------------ adjoint, D3Q15
@@ -1139,11 +1152,11 @@ __device__ __forceinline__ void apply_step(Box& b, Mot& m, const StepInfo* si) {
 // within the kernel support of analysis position (bx, by):
 // W-weighted kappa_ref (per z value for 3D), sum W, sum W r1, sum W r2.
 template <class R>
-__global__ __launch_bounds__(256) void k_map2d(Geo g, const R* kref, Mot m, Box box,
-                                               const StepInfo* si, R* bk, R* bu, int full_grid) {
+__device__ __forceinline__ void map2d_row(const Geo& g, const R* kref, Mot m, Box box,
+                                          const StepInfo* si, R* bk, R* bu, int full_grid,
+                                          int bx_blk, int j) {
   apply_step(box, m, si);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
+  const int i = bx_blk * 256 + threadIdx.x;
   if (i >= box.ext[0] || j >= box.ext[1]) return;
   const int bx = box.lo[0] + i, by = box.lo[1] + j;
   int x = bx, y = by;
@@ -1188,6 +1201,12 @@ __global__ __launch_bounds__(256) void k_map2d(Geo g, const R* kref, Mot m, Box 
     bu[bi] = usx;
     bu[box.vol + bi] = usy;
   }
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_map2d(Geo g, const R* kref, Mot m, Box box,
+                                               const StepInfo* si, R* bk, R* bu, int full_grid) {
+  map2d_row<R>(g, kref, m, box, si, bk, bu, full_grid, blockIdx.x, blockIdx.y);
 }
 
 // 3D transfer.  The z factor of the kernel is axis aligned and its 4 weights
@@ -1457,12 +1476,12 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
 
 // Transpose of the transfer for one step, one thread per design point.
 template <class R>
-__global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj(Geo g, const R* kref, Mot m, Box box,
-                                                           const StepInfo* si, const R* bkbar,
-                                                           const R* bubar, double* kref_bar,
-                                                           int overwrite, double* mpart) {
+__device__ __forceinline__ void mapadj_block(const Geo& g, const R* kref, Mot m, Box box,
+                                             const StepInfo* si, const R* bkbar, const R* bubar,
+                                             double* kref_bar, int overwrite, double* mpart,
+                                             int bid) {
   apply_step(box, m, si);
-  const long long k = blockIdx.x * (long long)MAPADJ_THREADS + threadIdx.x;
+  const long long k = bid * (long long)MAPADJ_THREADS + threadIdx.x;
   double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (k < g.Mtot) {
     const int e0 = (int)(k % g.D[0]);
@@ -1548,7 +1567,15 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj(Geo g, const R* kref,
   double tot[8];
   block_sum<8, MAPADJ_THREADS>(part, tot);
   if (threadIdx.x == 0)
-    for (int q = 0; q < 8; ++q) mpart[(long long)blockIdx.x * 8 + q] = tot[q];
+    for (int q = 0; q < 8; ++q) mpart[(long long)bid * 8 + q] = tot[q];
+}
+
+template <class R>
+__global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj(Geo g, const R* kref, Mot m, Box box,
+                                                           const StepInfo* si, const R* bkbar,
+                                                           const R* bubar, double* kref_bar,
+                                                           int overwrite, double* mpart) {
+  mapadj_block<R>(g, kref, m, box, si, bkbar, bubar, kref_bar, overwrite, mpart, blockIdx.x);
 }
 
 // ----------------------------------------------------------- prelude
@@ -1833,6 +1860,58 @@ int step_blocks(const Geo& g) {
   return d.x * d.y * d.z;
 }
 
+// ------------------------------------------------------ batched 2D launches
+__device__ __forceinline__ int batch_instance(const int* start, int count, int b) {
+  int k = 0;
+#pragma unroll
+  for (int q = 1; q < BATCH_MAX; ++q)
+    if (q < count && b >= start[q]) k = q;
+  return k;
+}
+
+template <class R>
+__global__ __launch_bounds__(STEP_THREADS) void k_fwd2d_batch(Batch<FwdArgs> b) {
+  const int k = batch_instance(b.start, b.count, blockIdx.x);
+  const int bid = blockIdx.x - b.start[k];
+  const Geo& g = *b.geo[k];
+  if (bid >= tiles_x(g) * tiles_y(g)) return;
+  fwd2d_tile<R>(g, b.a[k], bid);
+}
+
+template <class R>
+__global__ __launch_bounds__(STEP_THREADS) void k_adj2d_batch(Batch<AdjArgs> b) {
+  const int k = batch_instance(b.start, b.count, blockIdx.x);
+  const int bid = blockIdx.x - b.start[k];
+  const Geo& g = *b.geo[k];
+  if (bid >= tiles_x(g) * tiles_y(g)) return;
+  adj2d_tile<R>(g, b.a[k], bid);
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_map2d_batch(Batch<MapArgs> b) {
+  const int k = batch_instance(b.start, b.count, blockIdx.x);
+  const int bid = blockIdx.x - b.start[k];
+  const MapArgs& a = b.a[k];
+  if (bid >= a.bxn * a.box.ext[1]) return;
+  Mot m;
+  memset(&m, 0, sizeof m);
+  map2d_row<R>(*b.geo[k], (const R*)a.kref, m, a.box, a.si, (R*)a.bk, (R*)a.bu, 0, bid % a.bxn,
+               bid / a.bxn);
+}
+
+template <class R>
+__global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj_batch(Batch<MapAdjArgs> b) {
+  const int k = batch_instance(b.start, b.count, blockIdx.x);
+  const int bid = blockIdx.x - b.start[k];
+  const Geo& g = *b.geo[k];
+  if (bid >= (int)((g.Mtot + MAPADJ_THREADS - 1) / MAPADJ_THREADS)) return;
+  const MapAdjArgs& a = b.a[k];
+  Mot m;
+  memset(&m, 0, sizeof m);
+  mapadj_block<R>(g, (const R*)a.kref, m, a.box, a.si, (const R*)a.bkbar, (const R*)a.bubar,
+                  a.kref_bar, a.overwrite, a.mpart, bid);
+}
+
 LaunchEvents& launch_events() {
   static thread_local LaunchEvents e;
   return e;
@@ -2055,6 +2134,53 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
 
 hipError_t launch_state_init(const Geo& g, int precision, void* st, hipStream_t s) {
   return launch_zero(st, (size_t)(g.d + 1) * g.N * (precision == 0 ? 4 : 8), s);
+}
+
+
+// ------------------------------------------------------ batched launchers
+int step_blocks_2d(const Geo& g) {
+  return ((g.n[0] - g.org[0] + TILE_X - 1) / TILE_X) * ((g.n[1] - g.org[1] + TILE_Y - 1) / TILE_Y);
+}
+
+int map_blocks_2d(const Box& bmax, int* bxn) {
+  *bxn = (bmax.ext[0] + 255) / 256;
+  return *bxn * bmax.ext[1];
+}
+
+hipError_t launch_forward_step_batch(int precision, const Batch<FwdArgs>& b, hipStream_t s) {
+  dim3 grid(b.start[b.count]);
+  if (precision == 0)
+    LKS_LAUNCH(k_fwd2d_batch<float>, grid, dim3(STEP_THREADS), 0, s, b);
+  else
+    LKS_LAUNCH(k_fwd2d_batch<double>, grid, dim3(STEP_THREADS), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step_batch(int precision, const Batch<AdjArgs>& b, hipStream_t s) {
+  dim3 grid(b.start[b.count]);
+  if (precision == 0)
+    LKS_LAUNCH(k_adj2d_batch<float>, grid, dim3(STEP_THREADS), 0, s, b);
+  else
+    LKS_LAUNCH(k_adj2d_batch<double>, grid, dim3(STEP_THREADS), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_batch(int precision, const Batch<MapArgs>& b, hipStream_t s) {
+  dim3 grid(b.start[b.count]);
+  if (precision == 0)
+    LKS_LAUNCH(k_map2d_batch<float>, grid, dim3(256), 0, s, b);
+  else
+    LKS_LAUNCH(k_map2d_batch<double>, grid, dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_adjoint_batch(int precision, const Batch<MapAdjArgs>& b, hipStream_t s) {
+  dim3 grid(b.start[b.count]);
+  if (precision == 0)
+    LKS_LAUNCH(k_mapadj_batch<float>, grid, dim3(MAPADJ_THREADS), 0, s, b);
+  else
+    LKS_LAUNCH(k_mapadj_batch<double>, grid, dim3(MAPADJ_THREADS), 0, s, b);
+  return hipGetLastError();
 }
 
 }  // namespace lks

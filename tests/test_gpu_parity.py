@@ -434,3 +434,31 @@ def test_batch_run_matches_solo_runs(orc):
     assert abs(solo[0][0][0] - ref["J"]) <= 1e-4 * abs(ref["J"])
     adj = orc.adjoint(p, g, c, s)
     assert l2err(solo[0][1]["dgamma"], adj["dgamma"]) < 1e-3
+
+
+def test_batch_run_unequal_instances_use_graph_branches():
+    """Instances with different step counts (or a 3D one) cannot share
+    launches; they run as graph branches and still match their solo runs."""
+    lks = lk()
+    specs = [
+        W.make_2d(40, 12, 20, 3, nu=0.1, seed=21, amp=0.5, sigma_n=0.05, th_amp=0.05,
+                  precision=0, ckpt_k=6),
+        W.make_2d(45, 12, 26, 3, nu=0.1, seed=22, amp=0.5, sigma_n=0.05, th_amp=0.05,
+                  precision=0, ckpt_k=6),
+    ]
+    p3 = prob3d(prec=0)
+    rng = np.random.default_rng(5)
+    specs.append((p3, rng.uniform(0.2, 0.8, size=p3.M), rng.uniform(0.3, 0.7, size=(p3.nt, 3)),
+                  rng.uniform(0.3, 0.7, size=p3.nt)))
+    solo = []
+    for p, g, c, s in specs:
+        pl = lks.Plan(p)
+        J3, _ = pl.forward(g, c, s)
+        gr = pl.adjoint(g, c, s)
+        solo.append((cpu(J3), cpu(gr["dgamma"]), cpu(gr["dpsi"])))
+    b = lks.Batch([lks.Plan(p) for p, *_ in specs])
+    out = b.run([x[1] for x in specs], [x[2] for x in specs], [x[3] for x in specs])
+    for k, (J3, gr) in enumerate(out):
+        assert np.array_equal(cpu(J3), solo[k][0]), k
+        assert np.array_equal(cpu(gr["dgamma"]), solo[k][1]), k
+        assert np.array_equal(cpu(gr["dpsi"]), solo[k][2]), k
