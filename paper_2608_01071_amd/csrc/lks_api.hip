@@ -781,7 +781,10 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
       mb.a[k].bk = body;
       mb.a[k].bu = (char*)body + P->bmax.vol * P->es;
     }
-    HIPCHK(launch_map_batch(prec, mb, s));
+    {
+      Scope sc("map", s, true);
+      HIPCHK(launch_map_batch(prec, mb, s));
+    }
     return LKS_OK;
   };
   // forward march
@@ -801,7 +804,10 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
                          n == 1 ? P->first_lazy : 1, 1);
       in[k] = out;
     }
-    HIPCHK(launch_forward_step_batch(prec, fb, s));
+    {
+      Scope sc("fwd_step", s, true);
+      HIPCHK(launch_forward_step_batch(prec, fb, s));
+    }
   }
   for (int k = 0; k < count; ++k) {
     lks_plan* P = plans[k];
@@ -822,15 +828,24 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
         fb.a[k] = fwd_args(P, ws[k], n, src, tape_slot(P, ws[k], n - nb),
                            btape_slot(P, ws[k], n - nb), (n == 1) ? P->first_lazy : 1, 0);
       }
-      HIPCHK(launch_forward_step_batch(prec, fb, s));
+      {
+        Scope sc("fwd_step", s, true);
+        HIPCHK(launch_forward_step_batch(prec, fb, s));
+      }
     }
     for (int n = ne; n >= nb; --n) {
       for (int k = 0; k < count; ++k) {
         ab.a[k] = adj_args(plans[k], ws[k], n, sg, cur);
         qb.a[k] = mapadj_args(plans[k], ws[k], n);
       }
-      HIPCHK(launch_adjoint_step_batch(prec, ab, s));
-      HIPCHK(launch_map_adjoint_batch(prec, qb, s));
+      {
+        Scope sc("adj_step", s, true);
+        HIPCHK(launch_adjoint_step_batch(prec, ab, s));
+      }
+      {
+        Scope sc("map_adj", s, true);
+        HIPCHK(launch_map_adjoint_batch(prec, qb, s));
+      }
       cur = 1 - cur;
     }
   }

@@ -1316,6 +1316,29 @@ __global__ __launch_bounds__(64) void k_map3d(Geo g, const R* kt, int lz, Mot m,
   }
 }
 
+// Sum over the 4 lanes of a quad (lanes 4q..4q+3), the same value in every
+// lane: two DPP quad permutations (xor 1, then xor 2), no LDS traffic.
+__device__ __forceinline__ float quad_sum(float v) {
+  float t = v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+  return t + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(t), 0x4E, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double dpp_quad(double v, int ctrl) {
+  const long long b = __double_as_longlong(v);
+  int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+  if (ctrl == 0xB1) {
+    lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
+  } else {
+    lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
+  }
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double quad_sum(double v) {
+  const double t = v + dpp_quad(v, 0xB1);
+  return t + dpp_quad(t, 0x4E);
+}
+
 // 3D transfer transpose: MAPADJ_TPC consecutive lanes per (design column,
 // chunk of MAPADJ_LCH design levels), lane r owning the r-th row of the 4x4
 // xy taps.  The z factor is the same 4-tap kernel for every level and
@@ -1330,13 +1353,15 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
                                                              const R* bubar, double* kref_bar,
                                                              int overwrite, double* mpart) {
   apply_step(box, m, si);
+  static_assert(MAPADJ_TPC == 4, "a (column, chunk) group is one DPP quad");
+  static_assert(MAPADJ_LCH % 4 == 0, "levels are finished four at a time, one per quad lane");
   const int cols = g.D[0] * g.D[1];
   const int nch = (g.D[2] + MAPADJ_LCH - 1) / MAPADJ_LCH;
   const int gid = blockIdx.x * MAPADJ_THREADS + threadIdx.x;
   const int item = gid / MAPADJ_TPC, row = gid % MAPADJ_TPC;
   const bool active = item < cols * nch;
   double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  // all lanes of a group take the same trip counts (the butterfly needs them)
+  // all lanes of a group take the same trip counts (the quad sums need them)
   const int col = active ? item % cols : 0;
   const int ch = active ? item / cols : 0;
   const int l0 = ch * MAPADJ_LCH, l1 = active ? min(l0 + MAPADJ_LCH, g.D[2]) : l0;
@@ -1344,8 +1369,9 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
   const double r0 = e0 - g.xiG[0], r1 = e1 - g.xiG[1];
   const double X0 = m.c * r0 - m.s * r1 + m.xg[0];
   const double X1 = m.s * r0 + m.c * r1 + m.xg[1];
+  constexpr unsigned BAD = 0x80000000u;  // byte offset past every buffer: loads return 0
   R wx[4], dx[4];
-  int bix[4];
+  unsigned ox[4];  // byte offset of each x tap within a box row, BAD if outside
   const int lx = (int)floor(X0) - 1;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -1353,28 +1379,26 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
     const R rx = (R)((double)vx - X0);
     wx[q] = wk(rx);
     dx[q] = wkd(rx);
-    int b = -1;
+    unsigned o = BAD;
     if (wrap_axis(g, 0, vx) && !on_wall(g, 0, vx)) {
-      b = vx - box.lo[0];
+      int b = vx - box.lo[0];
       if (g.bc[0] == 0) { b %= g.n[0]; if (b < 0) b += g.n[0]; }
-      if (b < 0 || b >= box.ext[0]) b = -1;
+      if (b >= 0 && b < box.ext[0]) o = (unsigned)b * sizeof(R);
     }
-    bix[q] = b;
+    ox[q] = o;
   }
   R wy, dy;
-  int biy;
+  int biy = -1;
   {
     int vy = (int)floor(X1) - 1 + row;
     const R ry = (R)((double)vy - X1);
     wy = wk(ry);
     dy = wkd(ry);
-    int b = -1;
     if (wrap_axis(g, 1, vy) && !on_wall(g, 1, vy)) {
-      b = vy - box.lo[1];
+      int b = vy - box.lo[1];
       if (g.bc[1] == 0) { b %= g.n[1]; if (b < 0) b += g.n[1]; }
-      if (b < 0 || b >= box.ext[1]) b = -1;
+      if (b >= 0 && b < box.ext[1]) biy = b;
     }
-    biy = b;
   }
   const double o2 = m.xg[2] - g.xiG[2];
   const int fo = (int)floor(o2);
@@ -1386,86 +1410,108 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
     dz[q] = wkd(R(q) - R(1) - f);
   }
   const int bvol = (int)box.vol, bplane = box.sx * box.sy;
-  const R* bux = bubar;
-  const R* buy = bubar + bvol;
-  const R* buz = bubar + 2 * bvol;
-  // this lane's share of the plane sums of analysis plane z, then the
-  // butterfly over the group's 4 lanes
-  auto plane_sums = [&](int z, R* P) {
-#pragma unroll
-    for (int q = 0; q < 12; ++q) P[q] = R(0);
+  const int nrec = bvol * (int)sizeof(R);
+  const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc((void*)bkbar, 0, nrec, 0x00020000);
+  const __amdgpu_buffer_rsrc_t ru0 = __builtin_amdgcn_make_buffer_rsrc((void*)bubar, 0, nrec, 0x00020000);
+  const __amdgpu_buffer_rsrc_t ru1 =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(bubar + bvol), 0, nrec, 0x00020000);
+  const __amdgpu_buffer_rsrc_t ru2 =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(bubar + 2 * bvol), 0, nrec, 0x00020000);
+  auto bload = [](__amdgpu_buffer_rsrc_t r, unsigned off) -> R {
+    if constexpr (sizeof(R) == 4)
+      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+    else
+      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+  };
+  // Weighted sums of this lane's 4 taps of analysis plane z, summed over the
+  // quad: P = (W k, W u_x, W u_y, W u_z, dW/dx (same 4), dW/dy (same 4)).
+  // Taps outside the box read 0 through the buffer range check.
+  auto plane = [&](int z, R* P) {
+    unsigned base = BAD;
     bool zok = wrap_axis(g, 2, z);
     int r2 = z - box.lo[2];
     if (g.bc[2] == 0) { r2 %= g.n[2]; if (r2 < 0) r2 += g.n[2]; }
-    if (zok && r2 >= 0 && r2 < box.ext[2] && biy >= 0) {
-      const int rowb = box.sx * biy + bplane * r2;
+    if (zok && r2 >= 0 && r2 < box.ext[2] && biy >= 0)
+      base = (unsigned)(box.sx * biy + bplane * r2) * sizeof(R);
+    R S[4] = {R(0), R(0), R(0), R(0)}, D[4] = {R(0), R(0), R(0), R(0)};
 #pragma unroll
-      for (int cx = 0; cx < 4; ++cx) {
-        if (bix[cx] < 0) continue;
-        const int bi = bix[cx] + rowb;
-        const R kb = bkbar[bi];
-        const R u0 = bux[bi], u1 = buy[bi], u2 = buz[bi];
-        const R w = wx[cx] * wy, wxd = dx[cx] * wy, wyd = wx[cx] * dy;
-        P[0] += w * kb;
-        P[1] += w * u0;
-        P[2] += w * u1;
-        P[3] += w * u2;
-        P[4] += wxd * kb;
-        P[5] += wxd * u0;
-        P[6] += wxd * u1;
-        P[7] += wxd * u2;
-        P[8] += wyd * kb;
-        P[9] += wyd * u0;
-        P[10] += wyd * u1;
-        P[11] += wyd * u2;
+    for (int cx = 0; cx < 4; ++cx) {
+      const unsigned off = (base == BAD || ox[cx] == BAD) ? BAD : base + ox[cx];
+      const R v[4] = {bload(rk, off), bload(ru0, off), bload(ru1, off), bload(ru2, off)};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        S[q] += wx[cx] * v[q];
+        D[q] += dx[cx] * v[q];
       }
     }
 #pragma unroll
-    for (int q = 0; q < 12; ++q) {
-      P[q] += __shfl_xor(P[q], 1, MAPADJ_TPC);
-      P[q] += __shfl_xor(P[q], 2, MAPADJ_TPC);
+    for (int q = 0; q < 4; ++q) {
+      P[q] = quad_sum(wy * S[q]);
+      P[4 + q] = quad_sum(wy * D[q]);
+      P[8 + q] = quad_sum(dy * S[q]);
     }
   };
-  const int zb = l0 + fo - 1;  // first plane of level l0
-  R W0[12], W1[12], W2[12], W3[12];
-  plane_sums(zb, W0);
-  plane_sums(zb + 1, W1);
-  plane_sums(zb + 2, W2);
   const double U0 = m.om * (-m.s * r0 - m.c * r1) + m.ug[0];
   const double U1 = m.om * (m.c * r0 - m.s * r1) + m.ug[1];
   const double U2 = m.ug[2];
   const double dX0 = -m.s * r0 - m.c * r1, dX1 = m.c * r0 - m.s * r1;                      // R' r
   const double dU0 = m.om * (-m.c * r0 + m.s * r1), dU1 = m.om * (-m.s * r0 - m.c * r1);  // om R'' r
-  for (int L = l0; L < l1; ++L) {
-    plane_sums(L + fo + 2, W3);
-    if (row == 0) {
-      R A[16];
+  // this lane finishes levels l0 + row + 4 j; their kappa_ref and previous
+  // accumulator values are read up front
+  constexpr int NJ = MAPADJ_LCH / 4;
+  double krj[NJ], kbj[NJ];
 #pragma unroll
-      for (int t = 0; t < 12; ++t)
-        A[t] = wz[0] * W0[t] + wz[1] * W1[t] + wz[2] * W2[t] + wz[3] * W3[t];
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        A[12 + t] = dz[0] * W0[t] + dz[1] * W1[t] + dz[2] * W2[t] + dz[3] * W3[t];
+  for (int j = 0; j < NJ; ++j) {
+    const int L = l0 + row + 4 * j;
+    krj[j] = kbj[j] = 0.0;
+    if (L < l1) {
       const long long k = col + (long long)cols * L;
-      const double kr = (double)kref[k];
-      const double Xb0 = -(kr * A[4] + U0 * A[5] + U1 * A[6] + U2 * A[7]);
-      const double Xb1 = -(kr * A[8] + U0 * A[9] + U1 * A[10] + U2 * A[11]);
-      const double Xb2 = -(kr * A[12] + U0 * A[13] + U1 * A[14] + U2 * A[15]);
-      kref_bar[k] = (overwrite ? 0.0 : kref_bar[k]) + (double)A[0];
-      part[0] += Xb0;
-      part[1] += Xb1;
-      part[2] += Xb2;
-      part[3] += A[1];
-      part[4] += A[2];
-      part[5] += A[3];
-      part[6] += Xb0 * dX0 + Xb1 * dX1 + (double)A[1] * dU0 + (double)A[2] * dU1;
-      part[7] += (double)A[1] * dX0 + (double)A[2] * dX1;
+      krj[j] = (double)kref[k];
+      kbj[j] = overwrite ? 0.0 : kref_bar[k];
     }
+  }
+  // level l0 + t uses analysis planes zb + t .. zb + t + 3
+  const int zb = l0 + fo - 1;
+  R Wp[4][12];
+  plane(zb, Wp[0]);
+  plane(zb + 1, Wp[1]);
+  plane(zb + 2, Wp[2]);
+  R mine[16];
 #pragma unroll
-    for (int t = 0; t < 12; ++t) {
-      W0[t] = W1[t];
-      W1[t] = W2[t];
-      W2[t] = W3[t];
+  for (int q = 0; q < 16; ++q) mine[q] = R(0);
+#pragma unroll
+  for (int t = 0; t < MAPADJ_LCH; ++t) {
+    plane(zb + t + 3, Wp[(t + 3) & 3]);
+    const R* P0 = Wp[t & 3];
+    const R* P1 = Wp[(t + 1) & 3];
+    const R* P2 = Wp[(t + 2) & 3];
+    const R* P3 = Wp[(t + 3) & 3];
+    if (row == (t & 3)) {
+#pragma unroll
+      for (int q = 0; q < 12; ++q) mine[q] = wz[0] * P0[q] + wz[1] * P1[q] + wz[2] * P2[q] + wz[3] * P3[q];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) mine[12 + q] = dz[0] * P0[q] + dz[1] * P1[q] + dz[2] * P2[q] + dz[3] * P3[q];
+    }
+    if ((t & 3) == 3) {
+      // the quad's four lanes finish levels l0 + t - 3 .. l0 + t, one each
+      const int j = t >> 2;
+      const int L = l0 + 4 * j + row;
+      if (L < l1) {
+        const R* A = mine;
+        const double kr = krj[j];
+        const double Xb0 = -(kr * A[4] + U0 * A[5] + U1 * A[6] + U2 * A[7]);
+        const double Xb1 = -(kr * A[8] + U0 * A[9] + U1 * A[10] + U2 * A[11]);
+        const double Xb2 = -(kr * A[12] + U0 * A[13] + U1 * A[14] + U2 * A[15]);
+        kref_bar[col + (long long)cols * L] = kbj[j] + (double)A[0];
+        part[0] += Xb0;
+        part[1] += Xb1;
+        part[2] += Xb2;
+        part[3] += A[1];
+        part[4] += A[2];
+        part[5] += A[3];
+        part[6] += Xb0 * dX0 + Xb1 * dX1 + (double)A[1] * dU0 + (double)A[2] * dU1;
+        part[7] += (double)A[1] * dX0 + (double)A[2] * dX1;
+      }
     }
   }
   double tot[8];
