@@ -27,10 +27,11 @@ constexpr int CU_COUNT = 256;
 constexpr int ADJ_RING = LKS_ADJ_RING;
 // design points per block of the map transpose.
 constexpr int MAPADJ_THREADS = 256;
-// 3D map: most z values per thread the kappa_ref copy is padded for, and the
-// value the launches use (smaller = more threads, more candidate searches).
+// 3D map: most z values per lane the kappa_ref copy is padded for, and the
+// value the map uses (one half-wave per analysis column, 32 * MAP_ZPL z
+// values per pass).
 constexpr int MAP_ZC = 16;
-constexpr int MAP_ZC_RUN = 4;
+constexpr int MAP_ZPL = 3;
 // 3D map: zero padding (design levels) of the z-fastest kappa_ref copy.
 constexpr int KZ_PAD = 8;
 // 3D map transpose: design levels per thread.

@@ -1226,92 +1226,147 @@ __global__ __launch_bounds__(256) void k_kref_t(Geo g, const R* kref, R* kt, int
   kt[idx] = (e2 >= 0 && e2 < g.D[2]) ? kref[col + cols * e2] : R(0);
 }
 
-template <class R, int ZC>
-__global__ __launch_bounds__(64) void k_map3d(Geo g, const R* kt, int lz, Mot m, Box box,
-                                              const StepInfo* si, R* bk, R* bu, int full_grid) {
-  static_assert(ZC <= MAP_ZC, "the z-fastest copy is padded for ZC values per thread");
+template <class R>
+__global__ __launch_bounds__(256) void k_map3d(Geo g, const R* kt, int lz, Mot m, Box box,
+                                               const StepInfo* si, R* bk, R* bu, int full_grid) {
+  constexpr int ZPL = MAP_ZPL;  // z values per lane
+  static_assert(ZPL <= MAP_ZC, "the z-fastest copy is padded for ZPL values per lane");
+  constexpr int NS = 36;         // candidate window: at most 6 x 6 design columns
+  __shared__ R cw[8][NS], cr0[8][NS], cr1[8][NS];  // weight, design offsets r0, r1
+  __shared__ int ci[8][NS];                         // design column index
   apply_step(box, m, si);
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  const int zc = blockIdx.z * ZC;
-  if (i >= box.ext[0] || j >= box.ext[1] || zc >= box.ext[2]) return;
+  const int hw = threadIdx.x >> 5, lane = threadIdx.x & 31;
+  const int ncol = box.ext[0] * box.ext[1];
+  const int colid = blockIdx.x * 8 + hw;
+  const bool cok = colid < ncol;
+  const int i = cok ? colid % box.ext[0] : 0, j = cok ? colid / box.ext[0] : 0;
   const int bx = box.lo[0] + i, by = box.lo[1] + j;
   int x = bx, y = by;
-  const bool col_inside = wrap_axis(g, 0, x) && wrap_axis(g, 1, y);
+  const bool col_inside = cok && wrap_axis(g, 0, x) && wrap_axis(g, 1, y);
   const bool col_wall = col_inside && (on_wall(g, 0, x) || on_wall(g, 1, y));
-  // analysis z = lo2 + zc + t uses design levels L0 + t + q (q = 0..3),
-  // L0 = lo2 + zc + floor(xiG2 - xg2) - 1, with weights w(f + 1 - q)
-  const double o = g.xiG[2] - m.xg[2];
-  const int fo = (int)floor(o);
-  const R f = (R)(o - fo);
-  const int L0 = box.lo[2] + zc + fo - 1;
-  R G[ZC + 3];
+  const bool col_live = col_inside && !col_wall;
+  // candidate slots of this column's window (e1 outer, e0 inner), lanes in
+  // parallel; the half-wave then walks the valid ones in slot order
+  const double rx = bx - m.xg[0], ry = by - m.xg[1];
+  const double q0 = m.c * rx + m.s * ry + g.xiG[0];
+  const double q1 = -m.s * rx + m.c * ry + g.xiG[1];
+  const double h = 2.0 * (fabs(m.c) + fabs(m.s));
+  const int i0 = max(0, (int)ceil(q0 - h)), i1 = min(g.D[0] - 1, (int)floor(q0 + h));
+  const int j0 = max(0, (int)ceil(q1 - h)), j1 = min(g.D[1] - 1, (int)floor(q1 + h));
+  unsigned long long mk = 0;
 #pragma unroll
-  for (int t = 0; t < ZC + 3; ++t) G[t] = R(0);
-  R m0 = R(0), m1 = R(0), m2 = R(0);
-  if (col_inside && !col_wall) {
-    const double rx = bx - m.xg[0], ry = by - m.xg[1];
-    const double q0 = m.c * rx + m.s * ry + g.xiG[0];
-    const double q1 = -m.s * rx + m.c * ry + g.xiG[1];
-    const double h = 2.0 * (fabs(m.c) + fabs(m.s));
-    const int i0 = max(0, (int)ceil(q0 - h)), i1 = min(g.D[0] - 1, (int)floor(q0 + h));
-    const int j0 = max(0, (int)ceil(q1 - h)), j1 = min(g.D[1] - 1, (int)floor(q1 + h));
-    const int zoff = L0 + KZ_PAD;
-    for (int e1 = j0; e1 <= j1; ++e1) {
-      const double r1 = e1 - g.xiG[1];
-      for (int e0 = i0; e0 <= i1; ++e0) {
-        const double r0 = e0 - g.xiG[0];
+  for (int r = 0; r < 2; ++r) {
+    const int sl = lane + 32 * r;
+    bool ok = false;
+    if (col_live && sl < NS) {
+      const int e0 = i0 + sl % 6, e1 = j0 + sl / 6;
+      if (e0 <= i1 && e1 <= j1) {
+        const double r0 = e0 - g.xiG[0], r1 = e1 - g.xiG[1];
         const double d0 = bx - (m.c * r0 - m.s * r1 + m.xg[0]);
         const double d1 = by - (m.s * r0 + m.c * r1 + m.xg[1]);
         if (fabs(d0) < 2.0 && fabs(d1) < 2.0) {
-          const R W = wk((R)d0) * wk((R)d1);
-          m0 += W;
-          m1 += W * (R)r0;
-          m2 += W * (R)r1;
-          const R* col = kt + (long long)(e0 + g.D[0] * e1) * lz + zoff;
-#pragma unroll
-          for (int t = 0; t < ZC + 3; ++t) G[t] += W * col[t];
+          ok = true;
+          cw[hw][sl] = wk((R)d0) * wk((R)d1);
+          cr0[hw][sl] = (R)r0;
+          cr1[hw][sl] = (R)r1;
+          ci[hw][sl] = e0 + g.D[0] * e1;
         }
       }
     }
+    const unsigned long long b = __ballot(ok);
+    mk |= ((b >> (32 * (hw & 1))) & 0xffffffffull) << (32 * r);
   }
+  __syncthreads();
+  const double o = g.xiG[2] - m.xg[2];
+  const int fo = (int)floor(o);
+  const R f = (R)(o - fo);
   R wz[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) wz[q] = wk(f + R(1) - R(q));
-  const R om = (R)m.om, c = (R)m.c, s = (R)m.s;
-  const R vx = om * (-s * m1 - c * m2) + (R)m.ug[0] * m0;
-  const R vy = om * (c * m1 - s * m2) + (R)m.ug[1] * m0;
-  const R vz = (R)m.ug[2] * m0;
+  const R om = (R)m.om, c = (R)m.c, sn = (R)m.s;
+  for (int zblk = 0; zblk < box.ext[2]; zblk += 32 * ZPL) {
+    const int zbase = zblk + lane * ZPL;
+    const bool zlive = zbase < box.ext[2];
+    // analysis z = lo2 + zbase + t uses design levels L0 + t + q (q = 0..3),
+    // L0 = lo2 + zbase + floor(xiG2 - xg2) - 1, with weights w(f + 1 - q)
+    const int L0 = box.lo[2] + zbase + fo - 1;
+    R G[ZPL + 3];
 #pragma unroll
-  for (int t = 0; t < ZC; ++t) {
-    const int kk = zc + t;
-    if (kk >= box.ext[2]) break;
-    int z = box.lo[2] + kk;
-    const bool inside = col_inside && wrap_axis(g, 2, z);
-    const bool wall = !inside || col_wall || on_wall(g, 2, z);
-    // z weight sum over the design levels that exist
-    R zs = R(0), kv = R(0);
+    for (int t = 0; t < ZPL + 3; ++t) G[t] = R(0);
+    R m0 = R(0), m1 = R(0), m2 = R(0);
+    // candidates four at a time: all their loads are issued before the
+    // sums, which then run in slot order
+    constexpr int CG = 4;
+    unsigned long long it = mk;
+    while (it) {
+      int sl[CG];
+      bool v[CG];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e2 = L0 + t + q;
-      if (e2 >= 0 && e2 < g.D[2]) zs += wz[q];
-      kv += wz[q] * G[t + q];
+      for (int u = 0; u < CG; ++u) {
+        v[u] = it != 0;
+        sl[u] = v[u] ? __ffsll((long long)it) - 1 : 0;
+        it &= it - 1;
+      }
+      R W[CG], V[CG][ZPL + 3], a0[CG], a1[CG];
+      int cidx[CG];
+#pragma unroll
+      for (int u = 0; u < CG; ++u) {
+        W[u] = v[u] ? cw[hw][sl[u]] : R(0);
+        a0[u] = v[u] ? cr0[hw][sl[u]] : R(0);
+        a1[u] = v[u] ? cr1[hw][sl[u]] : R(0);
+        cidx[u] = v[u] ? ci[hw][sl[u]] : 0;
+#pragma unroll
+        for (int t = 0; t < ZPL + 3; ++t) V[u][t] = R(0);
+        if (v[u] && zlive) {
+          const R* col = kt + (long long)cidx[u] * lz + (L0 + KZ_PAD);
+#pragma unroll
+          for (int t = 0; t < ZPL + 3; ++t) V[u][t] = col[t];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < CG; ++u) {
+        if (!v[u]) continue;
+        m0 += W[u];
+        m1 += W[u] * a0[u];
+        m2 += W[u] * a1[u];
+#pragma unroll
+        for (int t = 0; t < ZPL + 3; ++t) G[t] += W[u] * V[u][t];
+      }
     }
-    if (wall) kv = R(0);
-    const R ux = wall ? R(0) : zs * vx, uy = wall ? R(0) : zs * vy, uz = wall ? R(0) : zs * vz;
-    if (full_grid) {
-      if (wall) continue;
-      const long long n = nidx(g, x, y, z);
-      bk[n] = kv;
-      bu[n] = ux;
-      bu[g.N + n] = uy;
-      bu[2 * g.N + n] = uz;
-    } else {
-      const long long bi = i + (long long)box.sx * (j + (long long)box.sy * kk);
-      bk[bi] = kv;
-      bu[bi] = ux;
-      bu[box.vol + bi] = uy;
-      bu[2 * box.vol + bi] = uz;
+    const R vx = om * (-sn * m1 - c * m2) + (R)m.ug[0] * m0;
+    const R vy = om * (c * m1 - sn * m2) + (R)m.ug[1] * m0;
+    const R vz = (R)m.ug[2] * m0;
+#pragma unroll
+    for (int t = 0; t < ZPL; ++t) {
+      const int kk = zbase + t;
+      if (!cok || kk >= box.ext[2]) break;
+      int z = box.lo[2] + kk;
+      const bool inside = col_inside && wrap_axis(g, 2, z);
+      const bool wall = !inside || col_wall || on_wall(g, 2, z);
+      // z weight sum over the design levels that exist
+      R zs = R(0), kv = R(0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e2 = L0 + t + q;
+        if (e2 >= 0 && e2 < g.D[2]) zs += wz[q];
+        kv += wz[q] * G[t + q];
+      }
+      if (wall) kv = R(0);
+      const R ux = wall ? R(0) : zs * vx, uy = wall ? R(0) : zs * vy, uz = wall ? R(0) : zs * vz;
+      if (full_grid) {
+        if (wall) continue;
+        const long long n = nidx(g, x, y, z);
+        bk[n] = kv;
+        bu[n] = ux;
+        bu[g.N + n] = uy;
+        bu[2 * g.N + n] = uz;
+      } else {
+        const long long bi = i + (long long)box.sx * (j + (long long)box.sy * kk);
+        bk[bi] = kv;
+        bu[bi] = ux;
+        bu[box.vol + bi] = uy;
+        bu[2 * box.vol + bi] = uz;
+      }
     }
   }
 }
@@ -2048,14 +2103,13 @@ hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf
                          (double*)bk, (double*)bu, full_grid);
   } else {
     const int lz = kz_levels(g);
-    constexpr int ZC = MAP_ZC_RUN;
-    dim3 grid((box.ext[0] + 63) / 64, box.ext[1], (box.ext[2] + ZC - 1) / ZC);
+    dim3 grid((unsigned)((box.ext[0] * box.ext[1] + 7) / 8));
     if (precision == 0)
-      LKS_LAUNCH((k_map3d<float, ZC>), grid, dim3(64), 0, s, g, (const float*)kzbuf, lz, m,
-                         box, si, (float*)bk, (float*)bu, full_grid);
+      LKS_LAUNCH(k_map3d<float>, grid, dim3(256), 0, s, g, (const float*)kzbuf, lz, m, box, si,
+                 (float*)bk, (float*)bu, full_grid);
     else
-      LKS_LAUNCH((k_map3d<double, ZC>), grid, dim3(64), 0, s, g, (const double*)kzbuf, lz,
-                         m, box, si, (double*)bk, (double*)bu, full_grid);
+      LKS_LAUNCH(k_map3d<double>, grid, dim3(256), 0, s, g, (const double*)kzbuf, lz, m, box,
+                 si, (double*)bk, (double*)bu, full_grid);
   }
   return hipGetLastError();
 }
