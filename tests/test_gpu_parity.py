@@ -462,3 +462,59 @@ def test_batch_run_unequal_instances_use_graph_branches():
         assert np.array_equal(cpu(J3), solo[k][0]), k
         assert np.array_equal(cpu(gr["dgamma"]), solo[k][1]), k
         assert np.array_equal(cpu(gr["dpsi"]), solo[k][2]), k
+
+
+# ----------------------------------------------------------------------------
+# The benchmark workload at full size: D3Q15 128^3, design 64^3 + margin 4,
+# FP32 state, the plan the benchmark builds (z segments, tile origin, body box
+# sized over all 5000 steps).  The oracle finishes single full-grid stages in
+# seconds, so these compare every node.
+
+@pytest.fixture(scope="module")
+def c4_full(orc):
+    p, gamma, chi, psi = W.c4()
+    mot = orc.motion(p, chi, psi)
+    kref = orc.kappa_ref(p, gamma)
+    return p, gamma, chi, psi, mot, kref
+
+
+def test_c4_full_size_map_and_step(orc, c4_full):
+    p, gamma, chi, psi, mot, kref = c4_full
+    plan = lk().Plan(p)
+    for n in (1, 1250, 2500):  # rotation 0, about pi/2 and about pi
+        m8 = mot[n - 1]
+        k, us = plan.map(kref, m8)
+        ko, uo = orc.map_fields(p, kref, m8)
+        assert relerr(cpu(k), ko) < 2e-6, n
+        assert relerr(cpu(us), uo) < 2e-6, n
+    rng = np.random.default_rng(41)
+    s = rand_state(p, 42, amp=0.03)
+    out = cpu(plan.step(gpu_state(s, p), ko, uo))
+    ref = orc.step(p, s, ko, uo)
+    assert relerr(out[: p.N], ref[: p.N] - THIRD) < 2e-5
+    assert relerr(out[p.N:], ref[p.N:]) < 2e-6
+    lam = rng.standard_normal((p.d + 1) * p.N)
+    lp, kb, ub = plan.step_adjoint(gpu_state(s, p), gpu_state(ref, p), ko, uo, lam)
+    rlp, rkb, rub = orc.step_adjoint(p, s, ref, ko, uo, lam)
+    assert relerr(cpu(lp), rlp) < 2e-5
+    assert relerr(cpu(kb), rkb) < 2e-5
+    assert relerr(cpu(ub), rub) < 2e-5
+    kbm, mbm = plan.map_adjoint(kref, m8, rkb, rub)
+    rkbm, rmbm = orc.map_adjoint(p, kref, m8, rkb, rub)
+    assert relerr(cpu(kbm), rkbm) < 2e-5
+    assert relerr(cpu(mbm), rmbm) < 1e-4
+
+
+def test_c4_full_size_forward_adjoint_first_steps(orc, c4_full):
+    """Forward + adjoint through lks_forward / lks_adjoint on the full grid for
+    the run's first two steps (checkpoint every step), against the oracle."""
+    p, gamma, chi, psi, _, _ = c4_full
+    p2 = p.replace(nt=2, ckpt_k=1)
+    plan = lk().Plan(p2)
+    J3, _ = plan.forward(gamma, chi[:2], psi[:2])
+    g = plan.adjoint(gamma, chi[:2], psi[:2])
+    ref = orc.forward(p2, gamma, chi[:2], psi[:2], want_final=False)
+    adj = orc.adjoint(p2, gamma, chi[:2], psi[:2])
+    assert abs(cpu(J3)[0] - ref["J"]) <= 1e-5 * abs(ref["J"])
+    for k in ("dgamma", "dchi", "dpsi"):
+        assert l2err(cpu(g[k]), adj[k]) < 1e-3, k
