@@ -160,42 +160,76 @@ __device__ __forceinline__ int tiles_x(const Geo& g) { return (g.n[0] - g.org[0]
 __device__ __forceinline__ int tiles_y(const Geo& g) { return (g.n[1] - g.org[1] + TILE_Y - 1) / TILE_Y; }
 __device__ __forceinline__ int tiles_z(const Geo& g) { return g.d == 3 ? (g.n[2] + g.zseg - 1) / g.zseg : 1; }
 
+// Lattice constants of the equilibria in the state type.  In FP32 the
+// nearest floats of the weights sum to 1 + 7e-9 and the velocity
+// coefficients 3 w_i (summed over c_ia^2) to 1 + 3e-8: a per-step gain on the
+// pressure and velocity that compounds over thousands of steps (a 4e-5
+// relative drift of J1 over 5000 steps).  The FP32 set moves one weight and
+// one velocity coefficient by one ulp so both sums are exactly 1
+// (sum_i w_i = 1, sum_i 3 w_i c_ix^2 = 1); the isotropy error this leaves is
+// 1e-7.  FP64 uses the nearest doubles.
+template <class R>
+struct EqC {
+  static constexpr R w0_9 = R(4.0 / 9.0), wa = R(1.0 / 9.0), wd_9 = R(1.0 / 36.0);
+  static constexpr R w0_15 = R(2.0 / 9.0), wd_15 = R(1.0 / 72.0);
+  static constexpr R ca = R(1.0 / 3.0), cd_9 = R(1.0 / 12.0), cd_15 = R(1.0 / 24.0);
+  static constexpr R third_hi = R(1.0 / 3.0), third_lo = R(0);
+};
+template <>
+struct EqC<float> {
+  static constexpr float w0_9 = 0x1.c71c72p-2f, wa = 0x1.c71c72p-4f, wd_9 = 0x1.c71c70p-6f;
+  static constexpr float w0_15 = 0x1.c71c72p-3f, wd_15 = 0x1.c71c70p-7f;
+  static constexpr float ca = 0x1.555556p-2f, cd_9 = 0x1.555554p-4f, cd_15 = 0x1.555554p-5f;
+  // 1/3 = third_hi + third_lo to about 1e-16
+  static constexpr float third_hi = 0x1.555556p-2f, third_lo = -0x1.555556p-27f;
+};
+// x / 3 without the bias of the rounded constant 1/3.
+template <class R>
+__device__ __forceinline__ R third_of(R x) {
+  if constexpr (sizeof(R) == 4)
+    return fmaf(x, EqC<float>::third_lo, x * EqC<float>::third_hi);
+  else
+    return x * R(1.0 / 3.0);
+}
+
 // Inamuro equilibria for one node (pairs of opposite directions share
 // their even part).  S holds D_a u_b + D_b u_a.
 template <class R>
 __device__ __forceinline__ void feq9(R p, R ux, R uy, R Sxx, R Syy, R Sxy, R A, R* f) {
+  using C = EqC<R>;
   const R base = R(3) * p - R(1.5) * (ux * ux + uy * uy);
-  f[0] = R(4.0 / 9.0) * base;
-  auto pair = [&](int i, R w, R cu, R cSc) {
+  f[0] = C::w0_9 * base;
+  auto pair = [&](int i, R w, R c3w, R cu, R cSc) {
     R com = w * (base + R(4.5) * cu * cu + A * cSc);
-    R od = R(3) * w * cu;
+    R od = c3w * cu;
     f[i] = com + od;
     f[i + 1] = com - od;
   };
-  pair(1, R(1.0 / 9.0), ux, Sxx);
-  pair(3, R(1.0 / 9.0), uy, Syy);
-  pair(5, R(1.0 / 36.0), ux + uy, Sxx + Syy + R(2) * Sxy);
-  pair(7, R(1.0 / 36.0), uy - ux, Sxx + Syy - R(2) * Sxy);
+  pair(1, C::wa, C::ca, ux, Sxx);
+  pair(3, C::wa, C::ca, uy, Syy);
+  pair(5, C::wd_9, C::cd_9, ux + uy, Sxx + Syy + R(2) * Sxy);
+  pair(7, C::wd_9, C::cd_9, uy - ux, Sxx + Syy - R(2) * Sxy);
 }
 template <class R>
 __device__ __forceinline__ void feq15(R p, R ux, R uy, R uz, R Sxx, R Syy, R Szz, R Sxy, R Sxz,
                                       R Syz, R A, R* f) {
+  using C = EqC<R>;
   const R base = R(3) * p - R(1.5) * (ux * ux + uy * uy + uz * uz);
-  f[0] = R(2.0 / 9.0) * base;
-  auto pair = [&](int i, R w, R cu, R cSc) {
+  f[0] = C::w0_15 * base;
+  auto pair = [&](int i, R w, R c3w, R cu, R cSc) {
     R com = w * (base + R(4.5) * cu * cu + A * cSc);
-    R od = R(3) * w * cu;
+    R od = c3w * cu;
     f[i] = com + od;
     f[i + 1] = com - od;
   };
   const R tr = Sxx + Syy + Szz;
-  pair(1, R(1.0 / 9.0), ux, Sxx);
-  pair(3, R(1.0 / 9.0), uy, Syy);
-  pair(5, R(1.0 / 9.0), uz, Szz);
-  pair(7, R(1.0 / 72.0), ux + uy + uz, tr + R(2) * (Sxy + Sxz + Syz));
-  pair(9, R(1.0 / 72.0), -ux + uy + uz, tr + R(2) * (-Sxy - Sxz + Syz));
-  pair(11, R(1.0 / 72.0), ux - uy + uz, tr + R(2) * (-Sxy + Sxz - Syz));
-  pair(13, R(1.0 / 72.0), ux + uy - uz, tr + R(2) * (Sxy - Sxz - Syz));
+  pair(1, C::wa, C::ca, ux, Sxx);
+  pair(3, C::wa, C::ca, uy, Syy);
+  pair(5, C::wa, C::ca, uz, Szz);
+  pair(7, C::wd_15, C::cd_15, ux + uy + uz, tr + R(2) * (Sxy + Sxz + Syz));
+  pair(9, C::wd_15, C::cd_15, -ux + uy + uz, tr + R(2) * (-Sxy - Sxz + Syz));
+  pair(11, C::wd_15, C::cd_15, ux - uy + uz, tr + R(2) * (-Sxy + Sxz - Syz));
+  pair(13, C::wd_15, C::cd_15, ux + uy - uz, tr + R(2) * (Sxy - Sxz - Syz));
 }
 
 // Block-wide fixed-order sum of K doubles per thread into out[0..K) (thread 0).
@@ -238,7 +272,7 @@ __device__ __forceinline__ void finish_node(const Geo& g, const FwdArgs& a, int 
     u[2] = (R)uw[2];
     p = R(0);  // wall pressure follows the wall rule when read
   } else {
-    p = sp * R(1.0 / 3.0);
+    p = third_of(sp);
     u[0] = sux;
     u[1] = suy;
     u[2] = suz;
@@ -579,7 +613,7 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
           u2 = cw[2];
           p = R(0);  // wall pressure follows the wall rule when read
         } else {
-          p = am[0] * R(1.0 / 3.0);
+          p = third_of(am[0]);
           u0 = am[1];
           u1 = am[2];
           u2 = am[3];
