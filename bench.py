@@ -96,6 +96,42 @@ def counters_drive():
     print(f"[bench] counters drive done: copy of {src.numel() * 4} bytes x3", flush=True)
 
 
+def c5_batch(nt: int = 4000):
+    """The batched parameter study: 16 independent D2Q9 instances (sides
+    128..384, Re and filter radius round-robin), FP32, forward + adjoint,
+    run as one lks_batch_run call (one captured graph, one launch per kernel
+    per step for all instances) and, for comparison, one instance after the
+    other."""
+    import torch
+    from paper_2608_01071_amd import lks, workloads as W
+    inst = W.c5_instances(nt=nt)
+    ns = sum(p.N for p, *_ in inst) * nt
+    G = [x[1] for x in inst]
+    C = [x[2] for x in inst]
+    S = [x[3] for x in inst]
+    b = lks.Batch([lks.Plan(p) for p, *_ in inst])
+    b.run(G, C, S)                      # capture + first replay
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(G, C, S)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    solo = [lks.Plan(p) for p, *_ in inst]
+    for pl, (p, g, c, s) in zip(solo, inst):
+        pl.forward(g, c, s)
+        pl.adjoint(g, c, s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for pl, (p, g, c, s) in zip(solo, inst):
+        pl.forward(g, c, s)
+        pl.adjoint(g, c, s)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    return {"instances": len(inst), "sides": [p.n[0] for p, *_ in inst], "nt": nt,
+            "node_steps": ns, "batch_s": round(tb, 3), "batch_mlups": round(ns / tb / 1e6, 1),
+            "sequential_s": round(ts, 3), "sequential_mlups": round(ns / ts / 1e6, 1)}
+
+
 def run_pass(plan, g, c, s, seed):
     import torch
     t0 = time.perf_counter()
@@ -132,6 +168,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-c5", action="store_true", help="skip the batched 16-instance study")
     ap.add_argument("--counters", action="store_true",
                     help="run only the short drive used for hardware-counter passes")
     args = ap.parse_args()
@@ -218,6 +255,7 @@ def main():
         del plan64
         torch.cuda.empty_cache()
 
+    c5 = None if args.no_c5 else c5_batch()
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_steps)
 
     line = {
@@ -233,6 +271,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_plain": fp64,
+        "c5_batch": c5,
         "kernels": kernels,
     }
     print(json.dumps(line), flush=True)
