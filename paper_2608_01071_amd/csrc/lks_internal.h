@@ -36,6 +36,7 @@ constexpr int MAP_ZPL = 3;
 constexpr int KZ_PAD = 8;
 // 3D map transpose: design levels per thread.
 constexpr int MAPADJ_LCH = 8;
+constexpr int MAPADJ_LCH_LONG = 24;  // used when the design grid has >= 72 levels
 // 3D map transpose: lanes per (design column, level chunk), one per xy tap row.
 constexpr int MAPADJ_TPC = 4;
 

@@ -1429,23 +1429,23 @@ __device__ __forceinline__ double quad_sum(double v) {
 }
 
 // 3D transfer transpose: MAPADJ_TPC consecutive lanes per (design column,
-// chunk of MAPADJ_LCH design levels), lane r owning the r-th row of the 4x4
+// chunk of LCH design levels), lane r owning the r-th row of the 4x4
 // xy taps.  The z factor is the same 4-tap kernel for every level and
 // consecutive levels are one node apart, so the lanes march the analysis
 // planes once: each plane's xy taps are reduced to 12 plane sums (a 4-lane
 // butterfly joins the rows); a window of the last 4 planes' sums gives each
 // level its z-weighted sums.  Finishing a level adds dJ/dkappa_ref and the
 // level's motion partials.
-template <class R>
+template <class R, int LCH>
 __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kref, Mot m, Box box,
                                                              const StepInfo* si, const R* bkbar,
                                                              const R* bubar, double* kref_bar,
                                                              int overwrite, double* mpart) {
   apply_step(box, m, si);
   static_assert(MAPADJ_TPC == 4, "a (column, chunk) group is one DPP quad");
-  static_assert(MAPADJ_LCH % 4 == 0, "levels are finished four at a time, one per quad lane");
+  static_assert(LCH % 4 == 0, "levels are finished four at a time, one per quad lane");
   const int cols = g.D[0] * g.D[1];
-  const int nch = (g.D[2] + MAPADJ_LCH - 1) / MAPADJ_LCH;
+  const int nch = (g.D[2] + LCH - 1) / LCH;
   const int gid = blockIdx.x * MAPADJ_THREADS + threadIdx.x;
   const int item = gid / MAPADJ_TPC, row = gid % MAPADJ_TPC;
   const bool active = item < cols * nch;
@@ -1453,7 +1453,7 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
   // all lanes of a group take the same trip counts (the quad sums need them)
   const int col = active ? item % cols : 0;
   const int ch = active ? item / cols : 0;
-  const int l0 = ch * MAPADJ_LCH, l1 = active ? min(l0 + MAPADJ_LCH, g.D[2]) : l0;
+  const int l0 = ch * LCH, l1 = active ? min(l0 + LCH, g.D[2]) : l0;
   const int e0 = col % g.D[0], e1 = col / g.D[0];
   const double r0 = e0 - g.xiG[0], r1 = e1 - g.xiG[1];
   const double X0 = m.c * r0 - m.s * r1 + m.xg[0];
@@ -1547,7 +1547,7 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
   const double dU0 = m.om * (-m.c * r0 + m.s * r1), dU1 = m.om * (-m.s * r0 - m.c * r1);  // om R'' r
   // this lane finishes levels l0 + row + 4 j; their kappa_ref and previous
   // accumulator values are read up front
-  constexpr int NJ = MAPADJ_LCH / 4;
+  constexpr int NJ = LCH / 4;
   double krj[NJ], kbj[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
@@ -1569,7 +1569,7 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
 #pragma unroll
   for (int q = 0; q < 16; ++q) mine[q] = R(0);
 #pragma unroll
-  for (int t = 0; t < MAPADJ_LCH; ++t) {
+  for (int t = 0; t < LCH; ++t) {
     plane(zb + t + 3, Wp[(t + 3) & 3]);
     const R* P0 = Wp[t & 3];
     const R* P1 = Wp[(t + 1) & 3];
@@ -2148,10 +2148,14 @@ hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf
   return hipGetLastError();
 }
 
+// Design levels per lane group of the 3D map transpose: long chunks reuse
+// more of the sliding z window, short ones give more waves.
+static int mapadj_lch(const Geo& g) { return g.D[2] >= 3 * MAPADJ_LCH_LONG ? MAPADJ_LCH_LONG : MAPADJ_LCH; }
+
 int mapadj_blocks(const Geo& g) {
   if (g.d == 3) {
-    const long long n = (long long)g.D[0] * g.D[1] * ((g.D[2] + MAPADJ_LCH - 1) / MAPADJ_LCH) *
-                        MAPADJ_TPC;
+    const int lch = mapadj_lch(g);
+    const long long n = (long long)g.D[0] * g.D[1] * ((g.D[2] + lch - 1) / lch) * MAPADJ_TPC;
     return (int)((n + MAPADJ_THREADS - 1) / MAPADJ_THREADS);
   }
   return (int)((g.Mtot + MAPADJ_THREADS - 1) / MAPADJ_THREADS);
@@ -2168,14 +2172,26 @@ hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
     memset(&m, 0, sizeof m);
   dim3 grid(mapadj_blocks(g));
   if (g.d == 3) {
-    if (precision == 0)
-      LKS_LAUNCH(k_mapadj3d<float>, grid, dim3(MAPADJ_THREADS), 0, s, g,
-                         (const float*)kref, m, box, si, (const float*)bkbar, (const float*)bubar,
-                         kref_bar, overwrite, mpart);
-    else
-      LKS_LAUNCH(k_mapadj3d<double>, grid, dim3(MAPADJ_THREADS), 0, s, g,
-                         (const double*)kref, m, box, si, (const double*)bkbar, (const double*)bubar,
-                         kref_bar, overwrite, mpart);
+    const bool lng = mapadj_lch(g) == MAPADJ_LCH_LONG;
+    if (precision == 0) {
+      if (lng)
+        LKS_LAUNCH((k_mapadj3d<float, MAPADJ_LCH_LONG>), grid, dim3(MAPADJ_THREADS), 0, s, g,
+                   (const float*)kref, m, box, si, (const float*)bkbar, (const float*)bubar,
+                   kref_bar, overwrite, mpart);
+      else
+        LKS_LAUNCH((k_mapadj3d<float, MAPADJ_LCH>), grid, dim3(MAPADJ_THREADS), 0, s, g,
+                   (const float*)kref, m, box, si, (const float*)bkbar, (const float*)bubar,
+                   kref_bar, overwrite, mpart);
+    } else {
+      if (lng)
+        LKS_LAUNCH((k_mapadj3d<double, MAPADJ_LCH_LONG>), grid, dim3(MAPADJ_THREADS), 0, s, g,
+                   (const double*)kref, m, box, si, (const double*)bkbar, (const double*)bubar,
+                   kref_bar, overwrite, mpart);
+      else
+        LKS_LAUNCH((k_mapadj3d<double, MAPADJ_LCH>), grid, dim3(MAPADJ_THREADS), 0, s, g,
+                   (const double*)kref, m, box, si, (const double*)bkbar, (const double*)bubar,
+                   kref_bar, overwrite, mpart);
+    }
     return hipGetLastError();
   }
   if (precision == 0)
