@@ -209,18 +209,24 @@ void fill_geo(const lks_problem& p, Geo& g) {
   for (int a = 0; a < p.d; ++a) T *= std::max(0, p.tgt_hi[a] - p.tgt_lo[a]);
   g.NTinv = T > 0 ? 1.0 / ((double)p.nt * (double)T) : 0.0;
   // tile-grid origin: keeps every node's wall-stencil partners within one tile halo
-  const int tile[2] = {TILE_X, TILE_Y};
+  g.ty3 = p.d == 3 ? tile3_y(p.precision) : TILE_Y;
+  const int tile[2] = {TILE_X, g.ty3};
   for (int a = 0; a < 2; ++a) g.org[a] = (g.bc[a] == 1 && g.n[a] % tile[a] == 2) ? -1 : 0;
-  // z segments: enough blocks to fill every CU with STEP_RESIDENT blocks, but
-  // no segment shorter than 4 planes (each segment re-reads 2 halo planes)
-  g.zseg = 1;
+  // z segments: enough blocks to fill every CU with the resident block count
+  // of each 3D step kernel, but no segment shorter than 4 planes (each
+  // segment re-reads 2 halo planes)
+  g.zseg = g.zseg_f = 1;
   if (g.d == 3) {
     const long long tiles = (long long)((g.n[0] - g.org[0] + TILE_X - 1) / TILE_X) *
-                            ((g.n[1] - g.org[1] + TILE_Y - 1) / TILE_Y);
-    const long long want = (long long)STEP_RESIDENT * CU_COUNT;
-    long long nseg = std::max(1LL, (want + tiles - 1) / tiles);
-    int zs = (int)((g.n[2] + nseg - 1) / nseg);
-    g.zseg = std::max(std::min(zs, g.n[2]), std::min(4, g.n[2]));
+                            ((g.n[1] - g.org[1] + g.ty3 - 1) / g.ty3);
+    auto seg_for = [&](int resident) {
+      const long long want = (long long)resident * CU_COUNT;
+      long long nseg = std::max(1LL, (want + tiles - 1) / tiles);
+      int zs = (int)((g.n[2] + nseg - 1) / nseg);
+      return std::max(std::min(zs, g.n[2]), std::min(4, g.n[2]));
+    };
+    g.zseg = seg_for(step_resident_adj(p.precision));
+    g.zseg_f = seg_for(STEP_RESIDENT_FWD);
   }
 }
 
@@ -489,7 +495,7 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   P->nblk_step = step_blocks(g);
   if (g.d == 3) {
     Geo g4 = g;
-    g4.zseg = std::min(4, g.n[2]);
+    g4.zseg = g4.zseg_f = std::min(4, g.n[2]);
     P->nblk_step = std::max(P->nblk_step, step_blocks(g4));
   }
   P->nblk_map = mapadj_blocks(g);
@@ -558,18 +564,21 @@ lks_status lks_plan_set_zseg(lks_plan* P, int32_t zseg) {
   if (!P) return fail(LKS_EINVAL, "null plan");
   if (P->g.d != 3) return LKS_OK;
   if (zseg < 0) return fail(LKS_EINVAL, "zseg must be >= 0");
+  // zseg > 0 sets both step kernels' segment length; 0 restores the defaults
+  Geo g2 = P->g;
   if (zseg == 0) {
-    Geo g2;
-    fill_geo(P->prob, g2);
-    zseg = g2.zseg;
+    Geo gd;
+    fill_geo(P->prob, gd);
+    g2.zseg = gd.zseg;
+    g2.zseg_f = gd.zseg_f;
+  } else {
+    g2.zseg = g2.zseg_f = std::min(zseg, P->g.n[2]);
   }
-  zseg = std::min(zseg, P->g.n[2]);
-  if (zseg != P->g.zseg) {
+  if (g2.zseg != P->g.zseg || g2.zseg_f != P->g.zseg_f) {
     // the step grid (and with it the objective partial slots) changes
-    Geo g2 = P->g;
-    g2.zseg = zseg;
     if (step_blocks(g2) > P->nblk_step) return fail(LKS_EINVAL, "zseg too small for this plan");
-    P->g.zseg = zseg;
+    P->g.zseg = g2.zseg;
+    P->g.zseg_f = g2.zseg_f;
     P->gfwd.reset();
     P->gadj.reset();
   }

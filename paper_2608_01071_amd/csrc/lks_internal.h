@@ -8,16 +8,27 @@
 
 namespace lks {
 
-// Output tile of the 2D / 3D step kernels (threads = TILE_X * TILE_Y).
+// Output tile of the 2D step kernels (threads = TILE_X * TILE_Y); the 3D
+// kernels use TILE_X x Tile3<R>::TY.
 constexpr int TILE_X = 32;
 constexpr int TILE_Y = 8;
 constexpr int STEP_THREADS = TILE_X * TILE_Y;
-// 3D step kernels: one thread per node of the 2-node halo plane (36 x 12).
-constexpr int THREADS3D = 448;
-// Resident blocks per CU the 3D step kernels are sized for (LDS-limited) and
-// the CU count of the target; the z-segment length is chosen so the grid is
-// about STEP_RESIDENT * CU_COUNT blocks.
-constexpr int STEP_RESIDENT = 2;
+// 3D step kernels: one thread per node of the 2-node halo plane.  FP32 takes
+// 32 x 16 tiles (36 x 20 halo plane, 768 threads: less halo recomputation);
+// FP64 keeps 32 x 8 (36 x 12, 448 threads) so its adjoint, at about 210
+// VGPRs, still fits a block on the CU.
+template <class R>
+struct Tile3 {
+  static constexpr int TY = sizeof(R) == 4 ? 16 : 8;
+  static constexpr int NT = sizeof(R) == 4 ? 768 : 448;
+};
+inline int tile3_y(int precision) { return precision == 0 ? 16 : 8; }
+// Resident blocks per CU the z-segment lengths of the 3D step kernels are
+// chosen for (the grid is about that many times CU_COUNT blocks): the
+// forward step holds two blocks per CU; the FP32 adjoint (768 threads at up to
+// 128 VGPRs) one, the FP64 adjoint two.
+constexpr int STEP_RESIDENT_FWD = 2;
+inline int step_resident_adj(int precision) { return precision == 0 ? 1 : 2; }
 constexpr int CU_COUNT = 256;
 // 3D adjoint step: planes of its LDS ring (3: two barriers per plane and
 // about 34 KB of LDS in FP32; 4: one barrier and about 41 KB).
@@ -61,7 +72,9 @@ struct Geo {
   int nt, r_t, r_w;
   double xmin[3], xmax[3], thmin, thmax;
   int org[3];             // tile-grid origin per axis (0 or -1)
-  int zseg;               // z planes per block segment (3D step kernels)
+  int zseg;               // z planes per block segment (3D adjoint step)
+  int zseg_f;             // z planes per block segment (3D forward step)
+  int ty3;                // tile height of the step kernels (3D: Tile3<R>::TY; 2D: TILE_Y)
 };
 
 // Support box of the body at one step, in unwrapped analysis coordinates;

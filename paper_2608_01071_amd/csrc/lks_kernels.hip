@@ -157,7 +157,7 @@ __device__ __forceinline__ int xcd_tile(int nbx, int nby, int nbz, int& bx, int&
   return xcd_tile_of(blockIdx.x, nbx, nby, nbz, bx, by, bz);
 }
 __device__ __forceinline__ int tiles_x(const Geo& g) { return (g.n[0] - g.org[0] + TILE_X - 1) / TILE_X; }
-__device__ __forceinline__ int tiles_y(const Geo& g) { return (g.n[1] - g.org[1] + TILE_Y - 1) / TILE_Y; }
+__device__ __forceinline__ int tiles_y(const Geo& g) { return (g.n[1] - g.org[1] + g.ty3 - 1) / g.ty3; }
 __device__ __forceinline__ int tiles_z(const Geo& g) { return g.d == 3 ? (g.n[2] + g.zseg - 1) / g.zseg : 1; }
 
 // Lattice constants of the equilibria in the state type.  In FP32 the
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d(Geo g, FwdArgs a) {
 }
 
 // ------------------------------------------------------ forward, D3Q15
-// Block = one 32x8 column tile marching z over a g.zseg segment.  Per plane:
+// Block = one 32 x Tile3<R>::TY column tile marching z over a g.zseg segment.  Per plane:
 // (1) the (p, u) plane with a 2-node halo enters a 3-plane LDS ring from
 // registers fetched one iteration earlier (the global loads of the next
 // plane overlap this plane's arithmetic); (2) the 15 equilibria of the
@@ -395,14 +395,14 @@ __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d(Geo g, FwdArgs a) {
 // (FP32) keeps four blocks resident per CU.
 // Node offsets within a plane set are 32-bit (plan validation bounds N).
 template <class R>
-__global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
+__global__ __launch_bounds__(Tile3<R>::NT) void k_fwd3d(Geo g, FwdArgs a) {
   apply_step(a.box, a.si);
-  constexpr int TX = TILE_X, TY = TILE_Y;
+  constexpr int TX = TILE_X, TY = Tile3<R>::TY, NT = Tile3<R>::NT;
   constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
   constexpr int LP = LX * LY, FP = FX * FY;
-  static_assert(THREADS3D >= LP && THREADS3D >= FP, "one load and one equilibrium slot per thread");
+  static_assert(NT >= LP && NT >= FP, "one load and one equilibrium slot per thread");
   // planes (mod 3): p, ux, uy, uz; entries LP.. take the commits of idle slots
-  __shared__ R ring[3][4][THREADS3D];
+  __shared__ R ring[3][4][NT];
   __shared__ R sf[12][FP];  // the 12 equilibria that move within the plane
   const int N = (int)g.N;
   const R* in_p = (const R*)a.in;
@@ -663,7 +663,7 @@ __global__ __launch_bounds__(THREADS3D) void k_fwd3d(Geo g, FwdArgs a) {
   if (a.opart) {
     double v[2] = {s1, s2};
     double tot[2];
-    block_sum<2, THREADS3D>(v, tot);
+    block_sum<2, NT>(v, tot);
     if (threadIdx.x == 0) {
       a.opart[2 * tlin] += tot[0];
       a.opart[2 * tlin + 1] += tot[1];
@@ -837,15 +837,15 @@ __global__ __launch_bounds__(STEP_THREADS) void k_adj2d(Geo g, AdjArgs a) {
 // velocity gradient (in-plane from the moment plane, along z from the
 // neighbouring planes' moments of the own column).
 template <class R>
-__global__ __launch_bounds__(THREADS3D, sizeof(R) == 4 ? 4 : 2) void k_adj3d(Geo g, AdjArgs a) {
+__global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 4 : 2) void k_adj3d(Geo g, AdjArgs a) {
   apply_step(a.box, a.si);
-  constexpr int TX = TILE_X, TY = TILE_Y;
+  constexpr int TX = TILE_X, TY = Tile3<R>::TY, NT = Tile3<R>::NT;
   constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
   constexpr int LP = LX * LY, FP = FX * FY;
-  static_assert(THREADS3D >= LP && THREADS3D >= FP, "one load and one moment slot per thread");
+  static_assert(NT >= LP && NT >= FP, "one load and one moment slot per thread");
   constexpr int NR = ADJ_RING;  // 3: two barriers per plane, 4: one
   // adjoint star planes (mod NR); entries LP.. take the commits of idle slots
-  __shared__ R ring[NR][4][THREADS3D];
+  __shared__ R ring[NR][4][NT];
   __shared__ R mb[2][5][FP];  // in-plane second moments (mod 2): Mxx, Myy, Mxy, Mxz, Myz
   const int N = (int)g.N;
   const R* lam_p = (const R*)a.lam;
@@ -1986,12 +1986,18 @@ __global__ void k_zero(uint32_t* p, long long n) {
 // ------------------------------------------------------------ launchers
 static dim3 step_grid(const Geo& g) {
   const int bx = (g.n[0] - g.org[0] + TILE_X - 1) / TILE_X;
-  const int by = (g.n[1] - g.org[1] + TILE_Y - 1) / TILE_Y;
+  const int by = (g.n[1] - g.org[1] + g.ty3 - 1) / g.ty3;
   const int bz = g.d == 3 ? (g.n[2] + g.zseg - 1) / g.zseg : 1;
   return dim3(bx * by * bz);
 }
+// The 3D forward step runs with its own z-segment length.
+static Geo fwd_geo(const Geo& g) {
+  Geo f = g;
+  if (g.d == 3) f.zseg = g.zseg_f;
+  return f;
+}
 int step_blocks(const Geo& g) {
-  dim3 d = step_grid(g);
+  dim3 d = step_grid(fwd_geo(g));
   return d.x * d.y * d.z;
 }
 
@@ -2066,17 +2072,19 @@ LaunchEvents& launch_events() {
   } while (0)
 
 hipError_t launch_forward_step(const Geo& g, int precision, const FwdArgs& a, hipStream_t s) {
-  dim3 grid = step_grid(g);
   if (g.d == 2) {
+    dim3 grid = step_grid(g);
     if (precision == 0)
       LKS_LAUNCH(k_fwd2d<float>, grid, dim3(STEP_THREADS), 0, s, g, a);
     else
       LKS_LAUNCH(k_fwd2d<double>, grid, dim3(STEP_THREADS), 0, s, g, a);
   } else {
+    const Geo f = fwd_geo(g);
+    dim3 grid = step_grid(f);
     if (precision == 0)
-      LKS_LAUNCH(k_fwd3d<float>, grid, dim3(THREADS3D), 0, s, g, a);
+      LKS_LAUNCH(k_fwd3d<float>, grid, dim3(Tile3<float>::NT), 0, s, f, a);
     else
-      LKS_LAUNCH(k_fwd3d<double>, grid, dim3(THREADS3D), 0, s, g, a);
+      LKS_LAUNCH(k_fwd3d<double>, grid, dim3(Tile3<double>::NT), 0, s, f, a);
   }
   return hipGetLastError();
 }
@@ -2090,9 +2098,9 @@ hipError_t launch_adjoint_step(const Geo& g, int precision, const AdjArgs& a, hi
       LKS_LAUNCH(k_adj2d<double>, grid, dim3(STEP_THREADS), 0, s, g, a);
   } else {
     if (precision == 0)
-      LKS_LAUNCH(k_adj3d<float>, grid, dim3(THREADS3D), 0, s, g, a);
+      LKS_LAUNCH(k_adj3d<float>, grid, dim3(Tile3<float>::NT), 0, s, g, a);
     else
-      LKS_LAUNCH(k_adj3d<double>, grid, dim3(THREADS3D), 0, s, g, a);
+      LKS_LAUNCH(k_adj3d<double>, grid, dim3(Tile3<double>::NT), 0, s, g, a);
   }
   return hipGetLastError();
 }
