@@ -30,12 +30,13 @@ inline int tile3_y(int precision) { return precision == 0 ? 16 : 8; }
 constexpr int STEP_RESIDENT_FWD = 2;
 inline int step_resident_adj(int precision) { return precision == 0 ? 1 : 2; }
 constexpr int CU_COUNT = 256;
-// 3D adjoint step: planes of its LDS ring (3: two barriers per plane and
-// about 34 KB of LDS in FP32; 4: one barrier and about 41 KB).
-#ifndef LKS_ADJ_RING
-#define LKS_ADJ_RING 3
-#endif
-constexpr int ADJ_RING = LKS_ADJ_RING;
+// 3D adjoint step: planes of its LDS ring (4: one barrier per plane; 3: two,
+// and less LDS).  FP32 takes 4 (its one block per CU has LDS to spare); FP64
+// takes 3 so two blocks fit a CU.
+template <class R>
+struct AdjRing {
+  static constexpr int NR = sizeof(R) == 4 ? 4 : 3;
+};
 // design points per block of the map transpose.
 constexpr int MAPADJ_THREADS = 256;
 // 3D map: most z values per lane the kappa_ref copy is padded for, and the

@@ -837,13 +837,13 @@ __global__ __launch_bounds__(STEP_THREADS) void k_adj2d(Geo g, AdjArgs a) {
 // velocity gradient (in-plane from the moment plane, along z from the
 // neighbouring planes' moments of the own column).
 template <class R>
-__global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 4 : 2) void k_adj3d(Geo g, AdjArgs a) {
+__global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(Geo g, AdjArgs a) {
   apply_step(a.box, a.si);
   constexpr int TX = TILE_X, TY = Tile3<R>::TY, NT = Tile3<R>::NT;
   constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
   constexpr int LP = LX * LY, FP = FX * FY;
   static_assert(NT >= LP && NT >= FP, "one load and one moment slot per thread");
-  constexpr int NR = ADJ_RING;  // 3: two barriers per plane, 4: one
+  constexpr int NR = AdjRing<R>::NR;  // 3: two barriers per plane, 4: one
   // adjoint star planes (mod NR); entries LP.. take the commits of idle slots
   __shared__ R ring[NR][4][NT];
   __shared__ R mb[2][5][FP];  // in-plane second moments (mod 2): Mxx, Myy, Mxy, Mxz, Myz
