@@ -1006,7 +1006,7 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
       ub1 *= inv;
       ub2 *= inv;
     }
-    ring[sl][0][tid] = lok ? pb : R(0);
+    ring[sl][0][tid] = lok ? pb * R(1.0 / 3.0) : R(0);  // the gather transpose takes p-bar / 3
     ring[sl][1][tid] = lok ? ub0 : R(0);
     ring[sl][2][tid] = lok ? ub1 : R(0);
     ring[sl][3][tid] = lok ? ub2 : R(0);
@@ -1065,26 +1065,31 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
     if (fok) {
       const int rs[3] = {(zs + 2 * NR - 1) % NR, (zs + 2 * NR) % NR,
                          (zs + 2 * NR + 1) % NR};  // planes zs-1, zs, zs+1
+      // F_i(y) = p-bar(y + c_i) / 3 + c_i . u-bar(y + c_i); each opposite pair
+      // enters the even moments through its sum and the first moments through
+      // its difference
+      M[0] = R(Lat<15>::w[0]) * ring[rs[1]][0][fc];
 #pragma unroll
-      for (int i = 0; i < 15; ++i) {
+      for (int i = 1; i < 15; i += 2) {
         const int cx = Lat<15>::c[i][0], cy = Lat<15>::c[i][1], cz = Lat<15>::c[i][2];
-        const int pl = rs[cz + 1];
-        const int j = fc + cx + cy * LX;
-        R F = ring[pl][0][j] * R(1.0 / 3.0);
-        if (cx == 1) F += ring[pl][1][j];
-        if (cx == -1) F -= ring[pl][1][j];
-        if (cy == 1) F += ring[pl][2][j];
-        if (cy == -1) F -= ring[pl][2][j];
-        if (cz == 1) F += ring[pl][3][j];
-        if (cz == -1) F -= ring[pl][3][j];
-        const R wF = R(Lat<15>::w[i]) * F;
-        M[0] += wF;
-        if (cx != 0) { M[1] += cx * wF; M[4] += wF; }
-        if (cy != 0) { M[2] += cy * wF; M[5] += wF; }
-        if (cz != 0) { M[3] += cz * wF; M[6] += wF; }
-        if (cx * cy != 0) M[7] += (cx * cy) * wF;
-        if (cx * cz != 0) M[8] += (cx * cz) * wF;
-        if (cy * cz != 0) M[9] += (cy * cz) * wF;
+        const int pp = rs[cz + 1], pm = rs[1 - cz];
+        const int jp = fc + cx + cy * LX, jm = fc - cx - cy * LX;
+        R cu_p = R(0), cu_m = R(0);
+        if (cx == 1) { cu_p += ring[pp][1][jp]; cu_m += ring[pm][1][jm]; }
+        if (cx == -1) { cu_p -= ring[pp][1][jp]; cu_m -= ring[pm][1][jm]; }
+        if (cy == 1) { cu_p += ring[pp][2][jp]; cu_m += ring[pm][2][jm]; }
+        if (cy == -1) { cu_p -= ring[pp][2][jp]; cu_m -= ring[pm][2][jm]; }
+        if (cz == 1) { cu_p += ring[pp][3][jp]; cu_m += ring[pm][3][jm]; }
+        if (cz == -1) { cu_p -= ring[pp][3][jp]; cu_m -= ring[pm][3][jm]; }
+        const R Fp = ring[pp][0][jp] + cu_p, Fm = ring[pm][0][jm] - cu_m;
+        const R wS = R(Lat<15>::w[i]) * (Fp + Fm), wD = R(Lat<15>::w[i]) * (Fp - Fm);
+        M[0] += wS;
+        if (cx != 0) { M[1] += cx > 0 ? wD : -wD; M[4] += wS; }
+        if (cy != 0) { M[2] += cy > 0 ? wD : -wD; M[5] += wS; }
+        if (cz != 0) { M[3] += cz > 0 ? wD : -wD; M[6] += wS; }
+        if (cx * cy != 0) M[7] += cx * cy > 0 ? wS : -wS;
+        if (cx * cz != 0) M[8] += cx * cz > 0 ? wS : -wS;
+        if (cy * cz != 0) M[9] += cy * cz > 0 ? wS : -wS;
       }
       R(*mo)[FP] = mb[zs & 1];
       mo[0][fpos] = M[4];
