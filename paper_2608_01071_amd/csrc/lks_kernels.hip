@@ -384,18 +384,19 @@ __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d(Geo g, FwdArgs a) {
 }
 
 // ------------------------------------------------------ forward, D3Q15
-// Block = one 32 x Tile3<R>::TY column tile marching z over a g.zseg segment.  Per plane:
+// Block = one 32 x Tile3<R>::TY column tile marching z over a z segment
+// (the launcher passes the forward's segment length in g.zseg).  Per plane:
 // (1) the (p, u) plane with a 2-node halo enters a 3-plane LDS ring from
-// registers fetched one iteration earlier (the global loads of the next
-// plane overlap this plane's arithmetic); (2) the 15 equilibria of the
-// plane are formed on the 1-node halo region, the 12 that move within the
-// plane go through LDS; (3) each output column adds them into the
-// accumulators of the three output planes they feed; the plane below is
-// then complete and is finished (Brinkman, walls, J1).  About 37 KB of LDS
-// (FP32) keeps four blocks resident per CU.
+// registers filled two planes ahead (the global loads overlap the
+// arithmetic of the planes in between); (2) the 15 equilibria of the plane
+// are formed on the 1-node halo region, the 12 that move within the plane go
+// through LDS; (3) each output column adds them into the accumulators of the
+// three output planes they feed; the plane below is then complete and is
+// finished (Brinkman, walls, J1).  In FP32 (32 x 16 tiles, 768 threads,
+// 66 KB of LDS, at most 80 VGPRs) two blocks are resident per CU.
 // Node offsets within a plane set are 32-bit (plan validation bounds N).
 template <class R>
-__global__ __launch_bounds__(Tile3<R>::NT) void k_fwd3d(Geo g, FwdArgs a) {
+__global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(Geo g, FwdArgs a) {
   apply_step(a.box, a.si);
   constexpr int TX = TILE_X, TY = Tile3<R>::TY, NT = Tile3<R>::NT;
   constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
