@@ -66,7 +66,7 @@ __device__ __forceinline__ long long wall_src(const Geo& g, int x, int y, int z)
 __device__ __forceinline__ void wall_vel(const Geo& g, int x, int y, int z, double u[3]) {
   u[0] = u[1] = u[2] = 0.0;
   const int c[3] = {x, y, z};
-  for (int a = 0; a < g.d; ++a) {
+  _Pragma("unroll") for (int a = 0; a < 3; ++a) if (a < g.d) {
     if (g.bc[a] != 1) continue;
     int side = -1;
     if (c[a] == 0) side = 0;
@@ -84,7 +84,7 @@ __device__ __forceinline__ bool in_target(const Geo& g, int x, int y, int z) {
 __device__ __forceinline__ long long box_index(const Geo& g, const Box& b, int x, int y, int z) {
   const int c[3] = {x, y, z};
   int r[3] = {0, 0, 0};
-  for (int a = 0; a < g.d; ++a) {
+  _Pragma("unroll") for (int a = 0; a < 3; ++a) if (a < g.d) {
     int v = c[a] - b.lo[a];
     if (g.bc[a] == 0) {
       v %= g.n[a];
@@ -283,7 +283,7 @@ __device__ __forceinline__ void finish_node(const Geo& g, const FwdArgs& a, int 
         const R* bu = (const R*)a.bu;
         R k = bk[bi];
         R inv = R(1) / (R(1) + k);
-        for (int c = 0; c < g.d; ++c) u[c] = (u[c] + k * bu[c * a.box.vol + bi]) * inv;
+        _Pragma("unroll") for (int c = 0; c < 3; ++c) if (c < g.d) u[c] = (u[c] + k * bu[c * a.box.vol + bi]) * inv;
       }
     }
     R uu = u[0] * u[0] + u[1] * u[1] + (g.d == 3 ? u[2] * u[2] : R(0));
@@ -688,23 +688,23 @@ __device__ __forceinline__ void adj_star(const Geo& g, const AdjArgs& a, int x, 
   const long long i = nidx(g, x, y, z);
   // pressure adjoint plus the wall nodes that copy this node's pressure
   R pb = lam[i];
+  // wall node next to this one along each wall axis (-1: none)
   const int c[3] = {x, y, z};
-  int opt[3][2];
-  int cnt[3];
+  int ex[3];
+#pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
-    opt[ax][0] = c[ax];
-    cnt[ax] = 1;
+    ex[ax] = -1;
     if (ax < g.d && g.bc[ax] == 1) {
-      if (c[ax] == 1) opt[ax][cnt[ax]++] = 0;
-      else if (c[ax] == g.n[ax] - 2) opt[ax][cnt[ax]++] = g.n[ax] - 1;
+      if (c[ax] == 1) ex[ax] = 0;
+      else if (c[ax] == g.n[ax] - 2) ex[ax] = g.n[ax] - 1;
     }
   }
-  for (int kz = 0; kz < cnt[2]; ++kz)
-    for (int ky = 0; ky < cnt[1]; ++ky)
-      for (int kx = 0; kx < cnt[0]; ++kx) {
-        if (kx == 0 && ky == 0 && kz == 0) continue;
-        pb += lam[nidx(g, opt[0][kx], opt[1][ky], opt[2][kz])];
-      }
+#pragma unroll
+  for (int m = 1; m < 8; ++m) {
+    const int kx = m & 1, ky = (m >> 1) & 1, kz = m >> 2;
+    if ((kx && ex[0] < 0) || (ky && ex[1] < 0) || (kz && ex[2] < 0)) continue;
+    pb += lam[nidx(g, kx ? ex[0] : x, ky ? ex[1] : y, kz ? ex[2] : z)];
+  }
   R ub[3];
   ub[0] = lam[N + i];
   ub[1] = lam[2 * N + i];
@@ -712,12 +712,12 @@ __device__ __forceinline__ void adj_star(const Geo& g, const AdjArgs& a, int x, 
   R un3[3] = {R(0), R(0), R(0)};
   bool have_u = false;
   if (a.seed && in_target(g, x, y, z)) {
-    for (int k = 0; k < g.d; ++k) un3[k] = uc[(k + 1) * N + i];
+    _Pragma("unroll") for (int k = 0; k < 3; ++k) if (k < g.d) un3[k] = uc[(k + 1) * N + i];
     have_u = true;
     double un = 0.0;
-    for (int k = 0; k < g.d; ++k) un += g.ndir[k] * (double)un3[k];
+    _Pragma("unroll") for (int k = 0; k < 3; ++k) if (k < g.d) un += g.ndir[k] * (double)un3[k];
     double gs = a.seed[0] * g.NTinv * (1.0 - 2.0 * g.phi * (un - a.E[0]));
-    for (int k = 0; k < g.d; ++k) ub[k] += (R)(gs * g.ndir[k]);
+    _Pragma("unroll") for (int k = 0; k < 3; ++k) if (k < g.d) ub[k] += (R)(gs * g.ndir[k]);
   }
   out[0] = pb;
   if (a.bk) {
@@ -729,17 +729,17 @@ __device__ __forceinline__ void adj_star(const Geo& g, const AdjArgs& a, int x, 
       const R inv = R(1) / (R(1) + k);
       if (owned) {
         if (!have_u)
-          for (int q = 0; q < g.d; ++q) un3[q] = uc[(q + 1) * N + i];
+          _Pragma("unroll") for (int q = 0; q < 3; ++q) if (q < g.d) un3[q] = uc[(q + 1) * N + i];
         R kb = R(0);
         R* bkbar = (R*)a.bkbar;
         R* bubar = (R*)a.bubar;
-        for (int q = 0; q < g.d; ++q) {
+        _Pragma("unroll") for (int q = 0; q < 3; ++q) if (q < g.d) {
           kb += ub[q] * (bu[q * a.box.vol + bi] - un3[q]);
           bubar[q * a.box.vol + bi] = k * ub[q] * inv;
         }
         bkbar[bi] = kb * inv;
       }
-      for (int q = 0; q < g.d; ++q) ub[q] *= inv;
+      _Pragma("unroll") for (int q = 0; q < 3; ++q) if (q < g.d) ub[q] *= inv;
     }
   }
   out[1] = ub[0];
@@ -1801,14 +1801,14 @@ __host__ __device__ void body_box(const Geo& g, const double* m8, int* out) {
       mn[2] = lo2 + m8[2];
       mx[2] = hi2 + m8[2];
     }
-    for (int a = 0; a < g.d; ++a) {
+    _Pragma("unroll") for (int a = 0; a < 3; ++a) if (a < g.d) {
       lo[a] = (int)floor(mn[a]) - 1;
       hi[a] = (int)floor(mx[a]) + 2;
       if (pass == 0 && g.bc[a] == 1 && (lo[a] < 1 || hi[a] > g.n[a] - 2)) flag = 1;
     }
     if (pass == 0) {
       bool empty = false;
-      for (int a = 0; a < g.d; ++a) empty = empty || g.m[a] == 0;
+      _Pragma("unroll") for (int a = 0; a < 3; ++a) if (a < g.d) empty = empty || g.m[a] == 0;
       if (empty) flag = 0;
     }
   }
@@ -1871,7 +1871,7 @@ __global__ void k_kref(Geo g, const double* gamma, R* kref) {
                     (int)(k / ((long long)g.D[0] * g.D[1]))};
   bool inner = true;
   int j[3] = {0, 0, 0};
-  for (int a = 0; a < g.d; ++a) {
+  _Pragma("unroll") for (int a = 0; a < 3; ++a) if (a < g.d) {
     j[a] = e[a] - g.margin;
     inner = inner && j[a] >= 0 && j[a] < g.m[a];
   }
@@ -1905,7 +1905,7 @@ __global__ void k_obj_final(Geo g, const double* opart, int nblk, double* J3) {
 __global__ void k_sens_gamma(Geo g, const double* gamma, const double* kref_bar, double* dg) {
   const long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   long long M = 1;
-  for (int a = 0; a < g.d; ++a) M *= g.m[a];
+  _Pragma("unroll") for (int a = 0; a < 3; ++a) if (a < g.d) M *= g.m[a];
   if (j >= M) return;
   const int i0 = (int)(j % g.m[0]);
   const int i1 = (int)((j / g.m[0]) % g.m[1]);
