@@ -50,7 +50,11 @@ constexpr int KZ_PAD = 8;
 constexpr int MAPADJ_LCH = 8;
 constexpr int MAPADJ_LCH_LONG = 24;  // used when the design grid has >= 72 levels
 // 3D map transpose: lanes per (design column, level chunk), one per xy tap row.
+// 2D transfer: a block is a MAP2_TX x MAP2_TY patch of analysis nodes.
+constexpr int MAP2_TX = 64, MAP2_TY = 4;
 constexpr int MAPADJ_TPC = 4;
+// Runs of 64 design points per block of the 2D map transpose.
+constexpr int MAPADJ_PTS2 = 2;
 
 // Device copy of the problem (passed by value to every kernel).
 struct Geo {
@@ -77,6 +81,12 @@ struct Geo {
   int zseg_f;             // z planes per block segment (3D forward step)
   int ty3;                // tile height of the step kernels (3D: Tile3<R>::TY; 2D: TILE_Y)
 };
+
+// Blocks of the 2D map transpose (MAPADJ_PTS2 runs of 64 points each).
+__host__ __device__ inline int mapadj_blocks_2d(const Geo& g) {
+  constexpr long long per = (long long)MAPADJ_PTS2 * (MAPADJ_THREADS / MAPADJ_TPC);
+  return (int)((g.Mtot + per - 1) / per);
+}
 
 // Support box of the body at one step, in unwrapped analysis coordinates;
 // the body buffers are laid out with fixed strides sx, sy (max extents).

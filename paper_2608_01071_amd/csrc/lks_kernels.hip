@@ -105,10 +105,39 @@ __device__ __forceinline__ void apply_step(Box& b, const StepInfo* si) {
   }
 }
 
-// Cosine kernel w(r) = (1 + cos(pi r / 2)) / 4 and its derivative (Sec. 2.3).
-__device__ __forceinline__ float wk(float r) { return 0.25f * (1.0f + cospif(0.5f * r)); }
+// Cosine kernel w(r) = (1 + cos(pi r / 2)) / 4 and its derivative (Sec. 2.3),
+// for |r| <= 2.  In single precision w = cos^2(y) / 2 and
+// w' = -(pi / 4) sin(y) cos(y) with y = pi r / 4 in [-pi/2, pi/2], where the
+// Taylor series of cos through y^12 and of sin through y^13 are below 7e-9
+// from the functions; the coefficients absorb the powers of pi / 4 so the
+// polynomials run in r^2.
+namespace wpoly {
+constexpr double Q = 0.78539816339744830962;  // pi / 4
+constexpr double Q2 = Q * Q;
+constexpr float c1 = (float)(-Q2 / 2), c2 = (float)(Q2 * Q2 / 24),
+                c3 = (float)(-Q2 * Q2 * Q2 / 720), c4 = (float)(Q2 * Q2 * Q2 * Q2 / 40320),
+                c5 = (float)(-Q2 * Q2 * Q2 * Q2 * Q2 / 3628800.0),
+                c6 = (float)(Q2 * Q2 * Q2 * Q2 * Q2 * Q2 / 479001600.0);
+constexpr float s0 = (float)Q, s1 = (float)(-Q * Q2 / 6), s2 = (float)(Q * Q2 * Q2 / 120),
+                s3 = (float)(-Q * Q2 * Q2 * Q2 / 5040), s4 = (float)(Q * Q2 * Q2 * Q2 * Q2 / 362880),
+                s5 = (float)(-Q * Q2 * Q2 * Q2 * Q2 * Q2 / 39916800.0),
+                s6 = (float)(Q * Q2 * Q2 * Q2 * Q2 * Q2 * Q2 / 6227020800.0);
+__device__ __forceinline__ float cosq(float z) {  // cos(pi r / 4), z = r^2
+  return fmaf(fmaf(fmaf(fmaf(fmaf(fmaf(c6, z, c5), z, c4), z, c3), z, c2), z, c1), z, 1.0f);
+}
+__device__ __forceinline__ float sinq(float r, float z) {  // sin(pi r / 4)
+  return r * fmaf(fmaf(fmaf(fmaf(fmaf(fmaf(s6, z, s5), z, s4), z, s3), z, s2), z, s1), z, s0);
+}
+}  // namespace wpoly
+__device__ __forceinline__ float wk(float r) {
+  const float c = wpoly::cosq(r * r);
+  return 0.5f * c * c;
+}
 __device__ __forceinline__ double wk(double r) { return 0.25 * (1.0 + cospi(0.5 * r)); }
-__device__ __forceinline__ float wkd(float r) { return -0.39269908169872414f * sinpif(0.5f * r); }
+__device__ __forceinline__ float wkd(float r) {
+  const float z = r * r;
+  return -0.78539816f * wpoly::sinq(r, z) * wpoly::cosq(z);
+}
 __device__ __forceinline__ double wkd(double r) { return -0.39269908169872414 * sinpi(0.5 * r); }
 
 // Derivative along one axis from an LDS row (stride st): central, or
@@ -1190,19 +1219,25 @@ __device__ __forceinline__ void apply_step(Box& b, Mot& m, const StepInfo* si) {
 
 // Cosine-kernel sums over the design points whose rotated position lies
 // within the kernel support of analysis position (bx, by):
-// W-weighted kappa_ref (per z value for 3D), sum W, sum W r1, sum W r2.
+// W-weighted kappa_ref, sum W, sum W r1, sum W r2.  A block is a
+// MAP2_TX x MAP2_TY patch of the box.  The offset of design point e from the
+// analysis node is R (q - e), q being the node in design coordinates, so the
+// candidate loop works on q - e relative to the window corner (small numbers,
+// exact in the working precision) instead of on absolute positions.
 template <class R>
 __device__ __forceinline__ void map2d_row(const Geo& g, const R* kref, Mot m, Box box,
                                           const StepInfo* si, R* bk, R* bu, int full_grid,
-                                          int bx_blk, int j) {
+                                          int bx_blk, int by_blk) {
   apply_step(box, m, si);
-  const int i = bx_blk * 256 + threadIdx.x;
+  const int i = bx_blk * MAP2_TX + (int)threadIdx.x % MAP2_TX;
+  const int j = by_blk * MAP2_TY + (int)threadIdx.x / MAP2_TX;
   if (i >= box.ext[0] || j >= box.ext[1]) return;
   const int bx = box.lo[0] + i, by = box.lo[1] + j;
   int x = bx, y = by;
   const bool inside = wrap_axis(g, 0, x) && wrap_axis(g, 1, y);
   const bool wall = inside && is_wall(g, x, y, 0);
   R k = R(0), m0 = R(0), m1 = R(0), m2 = R(0);
+  const R c = (R)m.c, s = (R)m.s;
   if (inside && !wall) {
     const double rx = bx - m.xg[0], ry = by - m.xg[1];
     const double q0 = m.c * rx + m.s * ry + g.xiG[0];
@@ -1210,23 +1245,34 @@ __device__ __forceinline__ void map2d_row(const Geo& g, const R* kref, Mot m, Bo
     const double h = 2.0 * (fabs(m.c) + fabs(m.s));
     const int i0 = max(0, (int)ceil(q0 - h)), i1 = min(g.D[0] - 1, (int)floor(q0 + h));
     const int j0 = max(0, (int)ceil(q1 - h)), j1 = min(g.D[1] - 1, (int)floor(q1 + h));
-    for (int e1 = j0; e1 <= j1; ++e1) {
-      const double r1 = e1 - g.xiG[1];
-      for (int e0 = i0; e0 <= i1; ++e0) {
-        const double r0 = e0 - g.xiG[0];
-        const double d0 = bx - (m.c * r0 - m.s * r1 + m.xg[0]);
-        const double d1 = by - (m.s * r0 + m.c * r1 + m.xg[1]);
-        if (fabs(d0) < 2.0 && fabs(d1) < 2.0) {
-          const R W = wk((R)d0) * wk((R)d1);
+    const R f0 = (R)(q0 - i0), f1 = (R)(q1 - j0);  // q - (window corner)
+    const R a0 = (R)((double)i0 - g.xiG[0]), a1 = (R)((double)j0 - g.xiG[1]);
+    // a window row has at most 6 points (its width is below 2 h + 1 <= 6.7):
+    // the row's loads are issued together, clamped into the row
+    const int jn = (i0 <= i1) ? j1 : j0 - 1;
+    for (int e1 = j0; e1 <= jn; ++e1) {
+      const R t1 = f1 - (R)(e1 - j0);
+      const R r1 = a1 + (R)(e1 - j0);
+      const R* kr = kref + (long long)g.D[0] * e1;
+      R v[6];
+#pragma unroll
+      for (int u = 0; u < 6; ++u) v[u] = kr[min(i0 + u, i1)];
+#pragma unroll
+      for (int u = 0; u < 6; ++u) {
+        const R t0 = f0 - (R)u;
+        const R d0 = c * t0 - s * t1;
+        const R d1 = s * t0 + c * t1;
+        if (i0 + u <= i1 && fabs(d0) < R(2) && fabs(d1) < R(2)) {
+          const R W = wk(d0) * wk(d1);
           m0 += W;
-          m1 += W * (R)r0;
-          m2 += W * (R)r1;
-          k += W * kref[e0 + (long long)g.D[0] * e1];
+          m1 += W * (a0 + (R)u);
+          m2 += W * r1;
+          k += W * v[u];
         }
       }
     }
   }
-  const R om = (R)m.om, c = (R)m.c, s = (R)m.s;
+  const R om = (R)m.om;
   const R usx = om * (-s * m1 - c * m2) + (R)m.ug[0] * m0;
   const R usy = om * (c * m1 - s * m2) + (R)m.ug[1] * m0;
   if (full_grid) {
@@ -1244,8 +1290,9 @@ __device__ __forceinline__ void map2d_row(const Geo& g, const R* kref, Mot m, Bo
 }
 
 template <class R>
-__global__ __launch_bounds__(256) void k_map2d(Geo g, const R* kref, Mot m, Box box,
-                                               const StepInfo* si, R* bk, R* bu, int full_grid) {
+__global__ __launch_bounds__(MAP2_TX * MAP2_TY) void k_map2d(Geo g, const R* kref, Mot m,
+                                                             Box box, const StepInfo* si, R* bk,
+                                                             R* bu, int full_grid) {
   map2d_row<R>(g, kref, m, box, si, bk, bu, full_grid, blockIdx.x, blockIdx.y);
 }
 
@@ -1615,95 +1662,106 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
     for (int q = 0; q < 8; ++q) mpart[(long long)blockIdx.x * 8 + q] = tot[q];
 }
 
-// Transpose of the transfer for one step, one thread per design point.
+// 2D transpose of the transfer for one step: one DPP quad per design point,
+// lane r owning the r-th row of its 4 x 4 analysis taps (buffer loads, taps
+// outside the box read 0); lane 0 accumulates kappa_ref-bar and the point's
+// motion terms.  A block covers MAPADJ_PTS2 runs of 64 consecutive points and
+// writes one fixed-order set of motion partials.
 template <class R>
 __device__ __forceinline__ void mapadj_block(const Geo& g, const R* kref, Mot m, Box box,
                                              const StepInfo* si, const R* bkbar, const R* bubar,
                                              double* kref_bar, int overwrite, double* mpart,
                                              int bid) {
   apply_step(box, m, si);
-  const long long k = bid * (long long)MAPADJ_THREADS + threadIdx.x;
+  static_assert(MAPADJ_TPC == 4, "a design point is one DPP quad");
+  constexpr int PPR = MAPADJ_THREADS / MAPADJ_TPC;  // points per run
+  constexpr unsigned BAD = 0x80000000u;  // byte offset past every buffer: loads return 0
+  const int bvol = (int)box.vol;
+  const int nrec = bvol * (int)sizeof(R);
+  const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc((void*)bkbar, 0, nrec, 0x00020000);
+  const __amdgpu_buffer_rsrc_t ru0 = __builtin_amdgcn_make_buffer_rsrc((void*)bubar, 0, nrec, 0x00020000);
+  const __amdgpu_buffer_rsrc_t ru1 =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(bubar + bvol), 0, nrec, 0x00020000);
+  auto bload = [](__amdgpu_buffer_rsrc_t r, unsigned off) -> R {
+    if constexpr (sizeof(R) == 4)
+      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+    else
+      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+  };
+  const int row = threadIdx.x % MAPADJ_TPC;
   double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (k < g.Mtot) {
-    const int e0 = (int)(k % g.D[0]);
-    const int e1 = (int)((k / g.D[0]) % g.D[1]);
-    const int e2 = (int)(k / ((long long)g.D[0] * g.D[1]));
+  for (int run = 0; run < MAPADJ_PTS2; ++run) {
+    const long long k = ((long long)bid * MAPADJ_PTS2 + run) * PPR + threadIdx.x / MAPADJ_TPC;
+    const bool active = k < g.Mtot;
+    const long long kk = active ? k : 0;
+    const int e0 = (int)(kk % g.D[0]), e1 = (int)(kk / g.D[0]);
     const double r0 = e0 - g.xiG[0], r1 = e1 - g.xiG[1];
-    double X[3], U[3];
-    X[0] = m.c * r0 - m.s * r1 + m.xg[0];
-    X[1] = m.s * r0 + m.c * r1 + m.xg[1];
-    X[2] = (g.d == 3) ? (e2 - g.xiG[2]) + m.xg[2] : 0.0;
-    U[0] = m.om * (-m.s * r0 - m.c * r1) + m.ug[0];
-    U[1] = m.om * (m.c * r0 - m.s * r1) + m.ug[1];
-    U[2] = (g.d == 3) ? m.ug[2] : 0.0;
-    const double kr = (double)kref[k];
-    R wv[3][4], dv[3][4];
-    int node[3][4], bidx[3][4];
-    const int na = g.d;
-    for (int a = 0; a < 3; ++a) {
-      const int lo = (a < na) ? (int)floor(X[a]) - 1 : 0;
-      for (int q = 0; q < 4; ++q) {
-        if (a >= na) {
-          wv[a][q] = (q == 0) ? R(1) : R(0);
-          dv[a][q] = R(0);
-          node[a][q] = 0;
-          bidx[a][q] = (q == 0) ? 0 : -1;
-          continue;
-        }
-        int v = lo + q;
-        const R r = (R)((double)v - X[a]);
-        wv[a][q] = wk(r);
-        dv[a][q] = wkd(r);
-        bool ok = wrap_axis(g, a, v);
-        node[a][q] = v;
-        if (!ok || on_wall(g, a, v)) {
-          bidx[a][q] = -1;
-          continue;
-        }
-        int b = v - box.lo[a];
-        if (g.bc[a] == 0) {
-          b %= g.n[a];
-          if (b < 0) b += g.n[a];
-        }
-        bidx[a][q] = (b >= 0 && b < box.ext[a]) ? b : -1;
+    const double X0 = m.c * r0 - m.s * r1 + m.xg[0];
+    const double X1 = m.s * r0 + m.c * r1 + m.xg[1];
+    R wx[4], dx[4];
+    unsigned ox[4];
+    const int lx = (int)floor(X0) - 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int vx = lx + q;
+      const R rx = (R)((double)vx - X0);
+      wx[q] = wk(rx);
+      dx[q] = wkd(rx);
+      unsigned o = BAD;
+      if (active && wrap_axis(g, 0, vx) && !on_wall(g, 0, vx)) {
+        int bb = vx - box.lo[0];
+        if (g.bc[0] == 0) { bb %= g.n[0]; if (bb < 0) bb += g.n[0]; }
+        if (bb >= 0 && bb < box.ext[0]) o = (unsigned)bb * sizeof(R);
+      }
+      ox[q] = o;
+    }
+    R wy, dy;
+    unsigned base = BAD;
+    {
+      int vy = (int)floor(X1) - 1 + row;
+      const R ry = (R)((double)vy - X1);
+      wy = wk(ry);
+      dy = wkd(ry);
+      if (active && wrap_axis(g, 1, vy) && !on_wall(g, 1, vy)) {
+        int bb = vy - box.lo[1];
+        if (g.bc[1] == 0) { bb %= g.n[1]; if (bb < 0) bb += g.n[1]; }
+        if (bb >= 0 && bb < box.ext[1]) base = (unsigned)(box.sx * bb) * sizeof(R);
       }
     }
-    double kb = 0.0, Ub[3] = {0, 0, 0}, Xb[3] = {0, 0, 0};
-    const int qz = (na == 3) ? 4 : 1;
-    for (int cz = 0; cz < qz; ++cz) {
-      if (bidx[2][cz] < 0) continue;
-      for (int cy = 0; cy < 4; ++cy) {
-        if (bidx[1][cy] < 0) continue;
-        for (int cx = 0; cx < 4; ++cx) {
-          if (bidx[0][cx] < 0) continue;
-          const long long bi =
-              bidx[0][cx] + (long long)box.sx * (bidx[1][cy] + (long long)box.sy * bidx[2][cz]);
-          const double kbv = (double)bkbar[bi];
-          double ubv[3] = {(double)bubar[bi], (double)bubar[box.vol + bi],
-                           na == 3 ? (double)bubar[2 * box.vol + bi] : 0.0};
-          const double wx = wv[0][cx], wy = wv[1][cy], wz = wv[2][cz];
-          const double W = wx * wy * wz;
-          kb += W * kbv;
-          double gs = kr * kbv;
-          for (int a = 0; a < na; ++a) {
-            Ub[a] += W * ubv[a];
-            gs += U[a] * ubv[a];
-          }
-          Xb[0] -= (double)dv[0][cx] * wy * wz * gs;
-          Xb[1] -= wx * (double)dv[1][cy] * wz * gs;
-          if (na == 3) Xb[2] -= wx * wy * (double)dv[2][cz] * gs;
-        }
+    R S[3] = {R(0), R(0), R(0)}, D[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int cx = 0; cx < 4; ++cx) {
+      const unsigned off = (base == BAD || ox[cx] == BAD) ? BAD : base + ox[cx];
+      const R v[3] = {bload(rk, off), bload(ru0, off), bload(ru1, off)};
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        S[q] += wx[cx] * v[q];
+        D[q] += dx[cx] * v[q];
       }
     }
-    kref_bar[k] = (overwrite ? 0.0 : kref_bar[k]) + kb;
-    const double dX0 = -m.s * r0 - m.c * r1, dX1 = m.c * r0 - m.s * r1;              // R' r
-    const double dU0 = m.om * (-m.c * r0 + m.s * r1), dU1 = m.om * (-m.s * r0 - m.c * r1);  // om R'' r
-    for (int a = 0; a < 3; ++a) {
-      part[a] = Xb[a];
-      part[3 + a] = Ub[a];
+    R P[9];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      P[q] = quad_sum(wy * S[q]);      // W k-bar, W u-bar
+      P[3 + q] = quad_sum(wy * D[q]);  // dW/dx ...
+      P[6 + q] = quad_sum(dy * S[q]);  // dW/dy ...
     }
-    part[6] = Xb[0] * dX0 + Xb[1] * dX1 + Ub[0] * dU0 + Ub[1] * dU1;
-    part[7] = Ub[0] * dX0 + Ub[1] * dX1;
+    if (active && row == 0) {
+      const double kr = (double)kref[k];
+      const double U0 = m.om * (-m.s * r0 - m.c * r1) + m.ug[0];
+      const double U1 = m.om * (m.c * r0 - m.s * r1) + m.ug[1];
+      const double Xb0 = -(kr * P[3] + U0 * P[4] + U1 * P[5]);
+      const double Xb1 = -(kr * P[6] + U0 * P[7] + U1 * P[8]);
+      kref_bar[k] = (overwrite ? 0.0 : kref_bar[k]) + (double)P[0];
+      const double dX0 = -m.s * r0 - m.c * r1, dX1 = m.c * r0 - m.s * r1;                      // R' r
+      const double dU0 = m.om * (-m.c * r0 + m.s * r1), dU1 = m.om * (-m.s * r0 - m.c * r1);  // om R'' r
+      part[0] += Xb0;
+      part[1] += Xb1;
+      part[3] += P[1];
+      part[4] += P[2];
+      part[6] += Xb0 * dX0 + Xb1 * dX1 + (double)P[1] * dU0 + (double)P[2] * dU1;
+      part[7] += (double)P[1] * dX0 + (double)P[2] * dX1;
+    }
   }
   double tot[8];
   block_sum<8, MAPADJ_THREADS>(part, tot);
@@ -1918,15 +1976,27 @@ __global__ void k_sens_gamma(Geo g, const double* gamma, const double* kref_bar,
   dg[j] = kref_bar[k] * g.kmax * g.q * (1.0 + g.q) / (den * den);
 }
 
-// Per-step motion partials: fixed-order sum over map-transpose blocks.
-__global__ void k_sens_mbar(Geo g, const double* mpart, int nblk, double* mbar) {
+// Per-step motion partials: fixed-order sum over map-transpose blocks.  Lane
+// (j, q) of the 256 sums component q over blocks j, j+32, ...; the 32 partial
+// sums are then added in index order.
+constexpr int SENS_MBAR_THREADS = 256;
+__global__ __launch_bounds__(SENS_MBAR_THREADS) void k_sens_mbar(Geo g, const double* mpart,
+                                                                  int nblk, double* mbar) {
+  __shared__ double red[SENS_MBAR_THREADS];
   const int t = blockIdx.x;
-  const int q = threadIdx.x;  // 0..7
-  if (t >= g.nt || q >= 8) return;
+  const int j = threadIdx.x / 8, q = threadIdx.x % 8;
   double s = 0.0;
-  const double* p = mpart + (long long)t * nblk * 8;
-  for (int b = 0; b < nblk; ++b) s += p[b * 8 + q];
-  mbar[t * 8 + q] = s;
+  if (t < g.nt) {
+    const double* p = mpart + (long long)t * nblk * 8;
+    for (int b = j; b < nblk; b += SENS_MBAR_THREADS / 8) s += p[b * 8 + q];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (t < g.nt && j == 0) {
+    double a = 0.0;
+    for (int i = 0; i < SENS_MBAR_THREADS / 8; ++i) a += red[i * 8 + q];
+    mbar[t * 8 + q] = a;
+  }
 }
 
 // tot[t][c] = span_c * (xbar(t) + (D_t^T vbar)(t)); den_t, den_w filter normalisers.
@@ -2035,11 +2105,11 @@ __global__ __launch_bounds__(STEP_THREADS) void k_adj2d_batch(Batch<AdjArgs> b) 
 }
 
 template <class R>
-__global__ __launch_bounds__(256) void k_map2d_batch(Batch<MapArgs> b) {
+__global__ __launch_bounds__(MAP2_TX * MAP2_TY) void k_map2d_batch(Batch<MapArgs> b) {
   const int k = batch_instance(b.start, b.count, blockIdx.x);
   const int bid = blockIdx.x - b.start[k];
   const MapArgs& a = b.a[k];
-  if (bid >= a.bxn * a.box.ext[1]) return;
+  if (bid >= a.bxn * ((a.box.ext[1] + MAP2_TY - 1) / MAP2_TY)) return;
   Mot m;
   memset(&m, 0, sizeof m);
   map2d_row<R>(*b.geo[k], (const R*)a.kref, m, a.box, a.si, (R*)a.bk, (R*)a.bu, 0, bid % a.bxn,
@@ -2051,7 +2121,7 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj_batch(Batch<MapAdjArg
   const int k = batch_instance(b.start, b.count, blockIdx.x);
   const int bid = blockIdx.x - b.start[k];
   const Geo& g = *b.geo[k];
-  if (bid >= (int)((g.Mtot + MAPADJ_THREADS - 1) / MAPADJ_THREADS)) return;
+  if (bid >= mapadj_blocks_2d(g)) return;
   const MapAdjArgs& a = b.a[k];
   Mot m;
   memset(&m, 0, sizeof m);
@@ -2142,12 +2212,12 @@ hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf
   else
     memset(&m, 0, sizeof m);
   if (g.d == 2) {
-    dim3 grid((box.ext[0] + 255) / 256, box.ext[1]);
+    dim3 grid((box.ext[0] + MAP2_TX - 1) / MAP2_TX, (box.ext[1] + MAP2_TY - 1) / MAP2_TY);
     if (precision == 0)
-      LKS_LAUNCH(k_map2d<float>, grid, dim3(256), 0, s, g, (const float*)kref, m, box, si,
+      LKS_LAUNCH(k_map2d<float>, grid, dim3(MAP2_TX * MAP2_TY), 0, s, g, (const float*)kref, m, box, si,
                          (float*)bk, (float*)bu, full_grid);
     else
-      LKS_LAUNCH(k_map2d<double>, grid, dim3(256), 0, s, g, (const double*)kref, m, box, si,
+      LKS_LAUNCH(k_map2d<double>, grid, dim3(MAP2_TX * MAP2_TY), 0, s, g, (const double*)kref, m, box, si,
                          (double*)bk, (double*)bu, full_grid);
   } else {
     const int lz = kz_levels(g);
@@ -2172,7 +2242,7 @@ int mapadj_blocks(const Geo& g) {
     const long long n = (long long)g.D[0] * g.D[1] * ((g.D[2] + lch - 1) / lch) * MAPADJ_TPC;
     return (int)((n + MAPADJ_THREADS - 1) / MAPADJ_THREADS);
   }
-  return (int)((g.Mtot + MAPADJ_THREADS - 1) / MAPADJ_THREADS);
+  return mapadj_blocks_2d(g);
 }
 
 hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
@@ -2263,7 +2333,7 @@ hipError_t launch_sens(const Geo& g, int precision, const double* gamma, const d
   if (M > 0)
     hipLaunchKernelGGL(k_sens_gamma, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, g, gamma,
                        kref_bar, dgamma);
-  hipLaunchKernelGGL(k_sens_mbar, dim3(g.nt), dim3(64), 0, s, g, mpart, nblk, mbar);
+  hipLaunchKernelGGL(k_sens_mbar, dim3(g.nt), dim3(SENS_MBAR_THREADS), 0, s, g, mpart, nblk, mbar);
   // tot buffer follows den_w (nt * 4 doubles) -- see workspace layout
   double* tot = den_w + g.nt;
   dim3 grid((g.nt + 255) / 256, 4);
@@ -2276,7 +2346,7 @@ hipError_t launch_reduce_parts(const Geo& g, const double* part, int nblk, doubl
                               hipStream_t s) {
   Geo g1 = g;
   g1.nt = 1;
-  hipLaunchKernelGGL(k_sens_mbar, dim3(1), dim3(64), 0, s, g1, part, nblk, out8);
+  hipLaunchKernelGGL(k_sens_mbar, dim3(1), dim3(SENS_MBAR_THREADS), 0, s, g1, part, nblk, out8);
   return hipGetLastError();
 }
 
@@ -2307,8 +2377,8 @@ int step_blocks_2d(const Geo& g) {
 }
 
 int map_blocks_2d(const Box& bmax, int* bxn) {
-  *bxn = (bmax.ext[0] + 255) / 256;
-  return *bxn * bmax.ext[1];
+  *bxn = (bmax.ext[0] + MAP2_TX - 1) / MAP2_TX;
+  return *bxn * ((bmax.ext[1] + MAP2_TY - 1) / MAP2_TY);
 }
 
 hipError_t launch_forward_step_batch(int precision, const Batch<FwdArgs>& b, hipStream_t s) {
@@ -2332,9 +2402,9 @@ hipError_t launch_adjoint_step_batch(int precision, const Batch<AdjArgs>& b, hip
 hipError_t launch_map_batch(int precision, const Batch<MapArgs>& b, hipStream_t s) {
   dim3 grid(b.start[b.count]);
   if (precision == 0)
-    LKS_LAUNCH(k_map2d_batch<float>, grid, dim3(256), 0, s, b);
+    LKS_LAUNCH(k_map2d_batch<float>, grid, dim3(MAP2_TX * MAP2_TY), 0, s, b);
   else
-    LKS_LAUNCH(k_map2d_batch<double>, grid, dim3(256), 0, s, b);
+    LKS_LAUNCH(k_map2d_batch<double>, grid, dim3(MAP2_TX * MAP2_TY), 0, s, b);
   return hipGetLastError();
 }
 
