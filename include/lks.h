@@ -92,7 +92,9 @@ typedef struct lks_plan lks_plan;
 /* Validate `prob` (host) and build a plan.  *workspace_bytes receives the
  * device workspace size the caller must allocate (256-byte aligned).
  * Errors: LKS_EINVAL for inconsistent sizes (e.g. a wall axis with fewer
- * than 4 nodes, design grid larger than a periodic extent). */
+ * than 4 nodes, design grid larger than a periodic extent) and for grids
+ * above 2^29 nodes, or in 3D whose (p, u) state reaches 4 GiB (2^28 nodes in
+ * FP32, 2^27 in FP64). */
 lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* workspace_bytes);
 lks_status lks_plan_destroy(lks_plan* plan);
 

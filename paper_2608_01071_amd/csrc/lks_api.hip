@@ -174,6 +174,11 @@ lks_status validate(const lks_problem* p) {
   for (int a = 0; a < p->d; ++a) N *= p->n[a];
   // node offsets inside the (d+1)-plane state are 32-bit in the kernels
   if (N > (1LL << 29)) return fail(LKS_EINVAL, "grid too large (at most 2^29 nodes)");
+  // the 3D step kernels address the whole (p, u) state through one buffer
+  // resource with 32-bit byte offsets
+  const long long es = p->precision == LKS_FP32 ? 4 : 8;
+  if (p->d == 3 && 4 * N * es > 0xFFFFFFFFLL)
+    return fail(LKS_EINVAL, "3D grid too large (the (p, u) state must stay below 4 GiB: fewer than 2^28 nodes in FP32, 2^27 in FP64)");
   return LKS_OK;
 }
 

@@ -221,6 +221,51 @@ __device__ __forceinline__ R third_of(R x) {
     return x * R(1.0 / 3.0);
 }
 
+// Brinkman factor 1 / (1 + kappa).  FP32: the hardware reciprocal refined by
+// one Newton step (within an ulp of the quotient, 3 instructions instead of
+// the IEEE division sequence); FP64: the division.
+template <class R>
+__device__ __forceinline__ R brinkman_inv(R k) {
+  if constexpr (sizeof(R) == 4) {
+    const float d = 1.0f + k;
+    const float r = __builtin_amdgcn_rcpf(d);
+    return fmaf(r, fmaf(-d, r, 1.0f), r);
+  } else {
+    return 1.0 / (1.0 + k);
+  }
+}
+
+// Buffer-resource access with a per-thread byte offset (VGPR) and a uniform
+// byte offset (SGPR): the 3D step kernels keep the per-thread part of every
+// address fixed over their z march.  Offsets past the resource's size read 0
+// and drop stores.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t brsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
+}
+template <class R>
+__device__ __forceinline__ R bld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(R) == 4)
+    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+  else
+    return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+template <class R>
+__device__ __forceinline__ void bst(R v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(R) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+  } else {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)voff, (int)soff, 0);
+  }
+}
+
+// Doubled one-sided wall derivative (second order) of an LDS row: at the low
+// wall o = +stride, at the high wall o = -stride and the result is negated.
+template <class R>
+__device__ __forceinline__ R dwall2(const R* s, int c, int o) {
+  return R(-3) * s[c] + R(4) * s[c + o] - s[c + 2 * o];
+}
+
 // Inamuro equilibria for one node (pairs of opposite directions share
 // their even part).  S holds D_a u_b + D_b u_a.
 template <class R>
@@ -239,9 +284,12 @@ __device__ __forceinline__ void feq9(R p, R ux, R uy, R Sxx, R Syy, R Sxy, R A, 
   pair(5, C::wd_9, C::cd_9, ux + uy, Sxx + Syy + R(2) * Sxy);
   pair(7, C::wd_9, C::cd_9, uy - ux, Sxx + Syy - R(2) * Sxy);
 }
+// D3Q15: the diagonal arguments are S_aa = 2 D_a u_a as above, the
+// off-diagonal ones twice S_ab (the sums of raw central differences, which
+// need no scaling).
 template <class R>
-__device__ __forceinline__ void feq15(R p, R ux, R uy, R uz, R Sxx, R Syy, R Szz, R Sxy, R Sxz,
-                                      R Syz, R A, R* f) {
+__device__ __forceinline__ void feq15(R p, R ux, R uy, R uz, R Sxx, R Syy, R Szz, R Txy, R Txz,
+                                      R Tyz, R A, R* f) {
   using C = EqC<R>;
   const R base = R(3) * p - R(1.5) * (ux * ux + uy * uy + uz * uz);
   f[0] = C::w0_15 * base;
@@ -255,10 +303,10 @@ __device__ __forceinline__ void feq15(R p, R ux, R uy, R uz, R Sxx, R Syy, R Szz
   pair(1, C::wa, C::ca, ux, Sxx);
   pair(3, C::wa, C::ca, uy, Syy);
   pair(5, C::wa, C::ca, uz, Szz);
-  pair(7, C::wd_15, C::cd_15, ux + uy + uz, tr + R(2) * (Sxy + Sxz + Syz));
-  pair(9, C::wd_15, C::cd_15, -ux + uy + uz, tr + R(2) * (-Sxy - Sxz + Syz));
-  pair(11, C::wd_15, C::cd_15, ux - uy + uz, tr + R(2) * (-Sxy + Sxz - Syz));
-  pair(13, C::wd_15, C::cd_15, ux + uy - uz, tr + R(2) * (Sxy - Sxz - Syz));
+  pair(7, C::wd_15, C::cd_15, ux + uy + uz, tr + (Txy + Txz + Tyz));
+  pair(9, C::wd_15, C::cd_15, -ux + uy + uz, tr + (-Txy - Txz + Tyz));
+  pair(11, C::wd_15, C::cd_15, ux - uy + uz, tr + (-Txy + Txz - Tyz));
+  pair(13, C::wd_15, C::cd_15, ux + uy - uz, tr + (Txy - Txz - Tyz));
 }
 
 // Block-wide fixed-order sum of K doubles per thread into out[0..K) (thread 0).
@@ -311,7 +359,7 @@ __device__ __forceinline__ void finish_node(const Geo& g, const FwdArgs& a, int 
         const R* bk = (const R*)a.bk;
         const R* bu = (const R*)a.bu;
         R k = bk[bi];
-        R inv = R(1) / (R(1) + k);
+        R inv = brinkman_inv(k);
         _Pragma("unroll") for (int c = 0; c < 3; ++c) if (c < g.d) u[c] = (u[c] + k * bu[c * a.box.vol + bi]) * inv;
       }
     }
@@ -435,10 +483,9 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
   __shared__ R ring[3][4][NT];
   __shared__ R sf[12][FP];  // the 12 equilibria that move within the plane
   const int N = (int)g.N;
-  const R* in_p = (const R*)a.in;
-  const R* in_x = in_p + N;
-  const R* in_y = in_p + 2 * N;
-  const R* in_z = in_p + 3 * N;
+  constexpr unsigned es = sizeof(R);
+  const unsigned fb = (unsigned)N * es;  // bytes of one field (4 fields fit 32 bits)
+  const __amdgpu_buffer_rsrc_t rin = brsrc(a.in, 4u * fb);
   const int nz = g.n[2];
   const int NP = g.n[0] * g.n[1];
   int tbx, tby, tbz;
@@ -473,26 +520,26 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
   }
   const int bvol = (int)a.box.vol, bplane = a.box.sx * a.box.sy;
   const bool body = a.bk && bvol > 0;
-  const R* bkp = (const R*)a.bk;
-  const R* bux = (const R*)a.bu;
-  const R* buy = bux + bvol;
-  const R* buz = bux + 2 * bvol;
-  R* out_p = (R*)a.out;
-  R* out_x = out_p + N;
-  R* out_y = out_p + 2 * N;
-  R* out_z = out_p + 3 * N;
+  const unsigned bb = (unsigned)bvol * es;  // bytes of one body field
+  const __amdgpu_buffer_rsrc_t rbk = brsrc(a.bk, bb);
+  const __amdgpu_buffer_rsrc_t rbu = brsrc(a.bu, 3u * bb);
+  const unsigned cvo = cbxy >= 0 ? (unsigned)cbxy * es : 0u;
+  const __amdgpu_buffer_rsrc_t rout = brsrc(a.out, 4u * fb);
+  const unsigned ovo = own ? (unsigned)(gx + g.n[0] * gy) * es : 0u;
 
   // load slot of the halo plane (fixed over the march); slots outside the
   // grid or the halo read node 0 of the plane and commit zeros
-  int lofs, lpofs;
+  unsigned lvo, lpvo;  // byte offsets within a plane of (u) and (p)
   bool lok;
   {
     int hx2 = x0 - 2 + tid % LX, hy2 = y0 - 2 + tid / LX;
     lok = tid < LP && wrap_axis(g, 0, hx2) && wrap_axis(g, 1, hy2);
-    lofs = lok ? hx2 + g.n[0] * hy2 : 0;
-    lpofs = (lok && a.lazy_wall && is_wall(g, hx2, hy2, 0))
-                ? inward(g, 0, hx2) + g.n[0] * inward(g, 1, hy2)
-                : lofs;
+    const int lofs = lok ? hx2 + g.n[0] * hy2 : 0;
+    const int lpofs = (lok && a.lazy_wall && is_wall(g, hx2, hy2, 0))
+                          ? inward(g, 0, hx2) + g.n[0] * inward(g, 1, hy2)
+                          : lofs;
+    lvo = (unsigned)lofs * es;
+    lpvo = (unsigned)lpofs * es;
   }
   // Register buffers of two planes in flight.  Every load and every commit
   // is unconditional (clamped plane and node), so the wait before a commit
@@ -502,28 +549,32 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
     R bk, bu[3];  // body fields of output plane zp - 2
     bool bin;
   };
+  // fetches come in plane order, so the wrapped plane index zp mod nz and
+  // the body-box plane (zp - 2 - lo_z) mod nz advance by one per call
+  int fzw = (z0 - 2) % nz, fr2 = (z0 - 4 - a.box.lo[2]) % nz;
+  if (fzw < 0) fzw += nz;
+  if (fr2 < 0) fr2 += nz;
   auto fetch = [&](int zp, Buf& B) {
+    const int zw = fzw, r2 = fr2;
+    fzw = fzw + 1 == nz ? 0 : fzw + 1;
+    fr2 = fr2 + 1 == nz ? 0 : fr2 + 1;
     B.bin = false;
     if (body) {
-      int r2 = (zp - 2 - a.box.lo[2]) % nz;
-      if (r2 < 0) r2 += nz;
       B.bin = cbxy >= 0 && r2 < a.box.ext[2] && zp - 2 >= z0 && zp - 2 < z1;
-      const int bi = B.bin ? cbxy + bplane * r2 : 0;
-      B.bk = bkp[bi];
-      B.bu[0] = bux[bi];
-      B.bu[1] = buy[bi];
-      B.bu[2] = buz[bi];
+      // (plane offsets past the box read 0; B.bin decides)
+      const unsigned so = (unsigned)(bplane * r2) * es;
+      B.bk = bld<R>(rbk, cvo, so);
+      B.bu[0] = bld<R>(rbu, cvo, so);
+      B.bu[1] = bld<R>(rbu, cvo, so + bb);
+      B.bu[2] = bld<R>(rbu, cvo, so + 2u * bb);
     }
-    int zw = min(zp, z1 + 1) % nz;
-    if (zw < 0) zw += nz;
-    const int pl = NP * zw;
-    B.v[0] = in_p[pl + lpofs];
-    B.v[1] = in_x[pl + lofs];
-    B.v[2] = in_y[pl + lofs];
-    B.v[3] = in_z[pl + lofs];
+    const unsigned so = (unsigned)(NP * zw) * es;
+    B.v[0] = bld<R>(rin, lpvo, so);
+    B.v[1] = bld<R>(rin, lvo, so + fb);
+    B.v[2] = bld<R>(rin, lvo, so + 2u * fb);
+    B.v[3] = bld<R>(rin, lvo, so + 3u * fb);
   };
-  auto commit = [&](int zp, const Buf& B) {
-    const int sl = (zp + 3) % 3;
+  auto commit = [&](int sl, const Buf& B) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) ring[sl][q][tid] = lok ? B.v[q] : R(0);
   };
@@ -554,8 +605,11 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
   int hx = x0 - 1 + fx, hy = y0 - 1 + fy;
   const bool fin = fok && wrap_axis(g, 0, hx) && wrap_axis(g, 1, hy);
   const int fc = (fy + 1) * LX + (fx + 1);
-  // wall positions take one-sided derivatives (rare: handled after the central ones)
+  // wall positions take one-sided derivatives (rare: handled after the central
+  // ones): direction into the grid and sign of the doubled derivative
   const bool fwx = fin && on_wall(g, 0, hx), fwy = fin && on_wall(g, 1, hy);
+  const int wox = hx == 0 ? 1 : -1, woy = hy == 0 ? LX : -LX;
+  const R wsx = hx == 0 ? R(1) : R(-1), wsy = hy == 0 ? R(1) : R(-1);
 
   R am[4] = {R(0), R(0), R(0), R(0)}, a0[4] = {R(0), R(0), R(0), R(0)},
     ap[4] = {R(0), R(0), R(0), R(0)};
@@ -565,41 +619,38 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
   // Iteration zf: commit plane zf+1 (buffer X) | barrier | fetch plane zf+3
   // into X | equilibria of plane zf | barrier | gather of plane zf, finish
   // of plane zf-1.
-  auto iter = [&](int zf, Buf& X) {
-    commit(zf + 1, X);
+  // rs = zf mod 3: ring slots of planes zf, zf + 1, zf - 1
+  auto iter = [&](int zf, int rs, Buf& X) {
+    const int sc = rs, sp1 = rs == 2 ? 0 : rs + 1, sm = rs == 0 ? 2 : rs - 1;
+    commit(sp1, X);
     const bool binb = X.bin;
     const R bkv = X.bk, bu0 = X.bu[0], bu1 = X.bu[1], bu2 = X.bu[2];
     __syncthreads();
     fetch(zf + 3, X);
     R f0 = R(0), fzp = R(0), fzm = R(0);
     if (fok) {
-      const int sm = (zf + 2) % 3, sc = (zf + 3) % 3, sp1 = (zf + 4) % 3;
       const R* ux = ring[sc][1];
       const R* uy = ring[sc][2];
       const R* uz = ring[sc][3];
       const int c = fc;
-      R dxux = R(0.5) * (ux[c + 1] - ux[c - 1]);
-      R dxuy = R(0.5) * (uy[c + 1] - uy[c - 1]);
-      R dxuz = R(0.5) * (uz[c + 1] - uz[c - 1]);
-      R dyux = R(0.5) * (ux[c + LX] - ux[c - LX]);
-      R dyuy = R(0.5) * (uy[c + LX] - uy[c - LX]);
-      R dyuz = R(0.5) * (uz[c + LX] - uz[c - LX]);
+      // raw central differences, twice the derivatives (one-sided at walls)
+      R xx = ux[c + 1] - ux[c - 1], xy = uy[c + 1] - uy[c - 1], xz = uz[c + 1] - uz[c - 1];
+      R yx = ux[c + LX] - ux[c - LX], yy = uy[c + LX] - uy[c - LX], yz = uz[c + LX] - uz[c - LX];
       if (fwx) {
-        dxux = dnum(g, 0, hx, ux, c, 1);
-        dxuy = dnum(g, 0, hx, uy, c, 1);
-        dxuz = dnum(g, 0, hx, uz, c, 1);
+        xx = wsx * dwall2(ux, c, wox);
+        xy = wsx * dwall2(uy, c, wox);
+        xz = wsx * dwall2(uz, c, wox);
       }
       if (fwy) {
-        dyux = dnum(g, 1, hy, ux, c, LX);
-        dyuy = dnum(g, 1, hy, uy, c, LX);
-        dyuz = dnum(g, 1, hy, uz, c, LX);
+        yx = wsy * dwall2(ux, c, woy);
+        yy = wsy * dwall2(uy, c, woy);
+        yz = wsy * dwall2(uz, c, woy);
       }
-      const R dzux = R(0.5) * (ring[sp1][1][c] - ring[sm][1][c]);
-      const R dzuy = R(0.5) * (ring[sp1][2][c] - ring[sm][2][c]);
-      const R dzuz = R(0.5) * (ring[sp1][3][c] - ring[sm][3][c]);
+      const R zx = ring[sp1][1][c] - ring[sm][1][c];
+      const R zy = ring[sp1][2][c] - ring[sm][2][c];
+      const R zz = ring[sp1][3][c] - ring[sm][3][c];
       R f[15];
-      feq15(ring[sc][0][c], ux[c], uy[c], uz[c], R(2) * dxux, R(2) * dyuy, R(2) * dzuz,
-            dxuy + dyux, dxuz + dzux, dyuz + dzuy, A, f);
+      feq15(ring[sc][0][c], ux[c], uy[c], uz[c], xx, yy, zz, xy + yx, xz + zx, yz + zy, A, f);
       if (!fin) {
 #pragma unroll
         for (int i = 0; i < 15; ++i) f[i] = R(0);
@@ -613,29 +664,39 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
     }
     __syncthreads();
     if (outer) {
-      // gather plane zf into the three output planes it feeds
-      a0[0] += f0;
-      ap[0] += fzp;
-      ap[3] += fzp;
-      am[0] += fzm;
-      am[3] -= fzm;
-#pragma unroll
-      for (int i = 1; i < 15; ++i) {
-        if (i == 5 || i == 6) continue;
-        const int cx = Lat<15>::c[i][0], cy = Lat<15>::c[i][1], cz = Lat<15>::c[i][2];
-        R v = sf[i < 5 ? i - 1 : i - 3][oc - cx - cy * FX];
-        R* acc = (cz == 1) ? ap : ((cz == 0) ? a0 : am);
-        acc[0] += v;
-        if (cx == 1) acc[1] += v;
-        if (cx == -1) acc[1] -= v;
-        if (cy == 1) acc[2] += v;
-        if (cy == -1) acc[2] -= v;
-        if (cz == 1) acc[3] += v;
-        if (cz == -1) acc[3] -= v;
+      // gather plane zf into the three output planes it feeds; each group of
+      // four equilibria enters through sums and differences of its pairs
+      auto rd = [&](int i) {
+        return sf[i < 5 ? i - 1 : i - 3][oc - Lat<15>::c[i][0] - Lat<15>::c[i][1] * FX];
+      };
+      const R v1 = rd(1), v2 = rd(2), v3 = rd(3), v4 = rd(4);       // c_z = 0
+      const R v7 = rd(7), v9 = rd(9), v11 = rd(11), v14 = rd(14);  // c_z = +1
+      const R v8 = rd(8), v10 = rd(10), v12 = rd(12), v13 = rd(13);  // c_z = -1
+      a0[0] += (f0 + (v1 + v2)) + (v3 + v4);
+      a0[1] += v1 - v2;
+      a0[2] += v3 - v4;
+      {
+        // c_z = +1, the first contributions to plane zf + 1:
+        // (1,1,1) (-1,1,1) (1,-1,1) (-1,-1,1)
+        const R s1 = v7 + v9, s2 = v11 + v14, d1 = v7 - v9, d2 = v11 - v14;
+        const R P = (s1 + s2) + fzp;
+        ap[0] = P;
+        ap[1] = d1 + d2;
+        ap[2] = s1 - s2;
+        ap[3] = P;
+      }
+      {
+        // c_z = -1, the last contributions to plane zf - 1:
+        // (1,1,-1) (-1,1,-1) (1,-1,-1) (-1,-1,-1)
+        const R s1 = v13 + v12, s2 = v10 + v8, d1 = v13 - v12, d2 = v10 - v8;
+        const R P = (s1 + s2) + fzm;
+        am[0] += P;
+        am[1] += d1 + d2;
+        am[2] += s1 - s2;
+        am[3] -= P;
       }
       const int zo = zf - 1;
       if (zo >= z0 && own) {
-        const int i = gx + g.n[0] * gy + NP * zo;
         R u0, u1, u2, p;
         if (cwall) {
           u0 = cw[0];
@@ -648,7 +709,7 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
           u1 = am[2];
           u2 = am[3];
           if (binb) {
-            const R inv = R(1) / (R(1) + bkv);
+            const R inv = brinkman_inv(bkv);
             u0 = (u0 + bkv * bu0) * inv;
             u1 = (u1 + bkv * bu1) * inv;
             u2 = (u2 + bkv * bu2) * inv;
@@ -656,10 +717,11 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
           const R uu = u0 * u0 + u1 * u1 + u2 * u2;
           if (a.flags && !(uu < R(0.25))) a.flags[0] = 1;  // non-finite or |u| >= 0.5
         }
-        out_p[i] = p;
-        out_x[i] = u0;
-        out_y[i] = u1;
-        out_z[i] = u2;
+        const unsigned so = (unsigned)(NP * zo) * es;
+        bst<R>(p, rout, ovo, so);
+        bst<R>(u0, rout, ovo, so + fb);
+        bst<R>(u1, rout, ovo, so + 2u * fb);
+        bst<R>(u2, rout, ovo, so + 3u * fb);
         if (ctgt && zo >= g.tlo[2] && zo < g.thi[2]) {
           const double un = g.ndir[0] * (double)u0 + g.ndir[1] * (double)u1 + g.ndir[2] * (double)u2;
           s1 += un;
@@ -670,26 +732,29 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
       for (int k = 0; k < 4; ++k) {
         am[k] = a0[k];
         a0[k] = ap[k];
-        ap[k] = R(0);
       }
     }
   };
 
   Buf bA, bB;
+  // z0 - 1 >= -1, so z0 + 2 keeps the residues nonnegative
+  const int r0 = (z0 + 2) % 3;  // slot of plane z0 - 1
   fetch(z0 - 2, bA);
-  commit(z0 - 2, bA);
+  commit(r0 == 0 ? 2 : r0 - 1, bA);
   fetch(z0 - 1, bA);
-  commit(z0 - 1, bA);
+  commit(r0, bA);
   fetch(z0, bA);
   fetch(z0 + 1, bB);
   // iterations z0-1 .. z1, two per trip so each buffer stays in fixed
   // registers (and every trip ends with the loads of the other buffer)
-  int zf = z0 - 1;
+  int zf = z0 - 1, rs = r0;
   for (; zf + 1 <= z1; zf += 2) {
-    iter(zf, bA);
-    iter(zf + 1, bB);
+    iter(zf, rs, bA);
+    rs = rs == 2 ? 0 : rs + 1;
+    iter(zf + 1, rs, bB);
+    rs = rs == 2 ? 0 : rs + 1;
   }
-  if (zf <= z1) iter(zf, bA);
+  if (zf <= z1) iter(zf, rs, bA);
   if (a.opart) {
     double v[2] = {s1, s2};
     double tot[2];
@@ -755,7 +820,7 @@ __device__ __forceinline__ void adj_star(const Geo& g, const AdjArgs& a, int x, 
       const R* bk = (const R*)a.bk;
       const R* bu = (const R*)a.bu;
       const R k = bk[bi];
-      const R inv = R(1) / (R(1) + k);
+      const R inv = brinkman_inv(k);
       if (owned) {
         if (!have_u)
           _Pragma("unroll") for (int q = 0; q < 3; ++q) if (q < g.d) un3[q] = uc[(q + 1) * N + i];
@@ -968,12 +1033,16 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
     int bi;       // body-box index of the slot node, -1 outside
     bool tg, bown;
   };
+  // fetches come in plane order, so the wrapped plane index zp mod nz and
+  // the body-box plane (zp - lo_z) mod nz advance by one per call
+  int fzw = (z0 - 2) % nz, fr2 = (z0 - 2 - a.box.lo[2]) % nz;
+  if (fzw < 0) fzw += nz;
+  if (fr2 < 0) fr2 += nz;
   auto fetch = [&](int zp, Buf& B) {
-    int zw = min(zp, z1 + 1) % nz;
-    if (zw < 0) zw += nz;
+    const int zw = fzw, r2 = fr2;
+    fzw = fzw + 1 == nz ? 0 : fzw + 1;
+    fr2 = fr2 + 1 == nz ? 0 : fr2 + 1;
     const int pl = NP * zw;
-    int r2 = (zw - a.box.lo[2]) % nz;
-    if (r2 < 0) r2 += nz;
     const bool zbox = r2 < a.box.ext[2];
     const bool ztg = zw >= g.tlo[2] && zw < g.thi[2];
     const bool own_plane = zp >= z0 && zp < z1;
@@ -1023,7 +1092,7 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
     }
     if (B.bi >= 0) {
       const R kk = B.bk;
-      const R inv = R(1) / (R(1) + kk);
+      const R inv = brinkman_inv(kk);
       if (B.bown) {
         const R kb = ub0 * (B.bu[0] - B.un[0]) + ub1 * (B.bu[1] - B.un[1]) +
                      ub2 * (B.bu[2] - B.un[2]);

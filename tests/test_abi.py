@@ -49,12 +49,25 @@ def test_plan_validation_and_workspace(L):
     bad = [p.replace(d=4), p.replace(n=(64, 3, 1)), p.replace(nt=0), p.replace(r_t=0),
            p.replace(ckpt_k=500), p.replace(precision=2), p.replace(q=0.0)]
     p3, *_ = W.make_3d(16, 4, 5, 2, nu=0.1, seed=0)
+    p3 = p3.replace(ckpt_k=5)
+    h0 = C.c_void_p()
+    assert L.lks_plan_create(C.byref(lks.to_struct(p3)), C.byref(h0), C.byref(nb)) == 0
+    L.lks_plan_destroy(h0)
     bad.append(p3.replace(bc=(1, 1, 1)))
+    # 3D (p, u) states of 4 GiB and more (2^28 nodes in FP32, 2^27 in FP64)
+    bad.append(p3.replace(n=(512, 512, 1024), precision=0))
+    bad.append(p3.replace(n=(512, 512, 512), precision=1))
     for b in bad:
         h3 = C.c_void_p()
         rc = L.lks_plan_create(C.byref(lks.to_struct(b)), C.byref(h3), C.byref(nb))
         assert rc == lks.LKS_EINVAL, b
         assert len(L.lks_last_error()) > 0
+    # just below: 2^28 - 2^18 nodes in FP32, 2^27 - 2^18 in FP64
+    for n, prec in (((512, 512, 1023), 0), ((512, 512, 511), 1)):
+        h4 = C.c_void_p()
+        assert L.lks_plan_create(C.byref(lks.to_struct(p3.replace(n=n, precision=prec))),
+                                 C.byref(h4), C.byref(nb)) == 0, n
+        L.lks_plan_destroy(h4)
 
 
 def test_null_arguments_rejected_before_any_launch(L):
