@@ -943,23 +943,21 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
   __shared__ R ring[NR][4][NT];
   __shared__ R mb[2][5][FP];  // in-plane second moments (mod 2): Mxx, Myy, Mxy, Mxz, Myz
   const int N = (int)g.N;
-  const R* lam_p = (const R*)a.lam;
-  const R* lam_x = lam_p + N;
-  const R* lam_y = lam_p + 2 * N;
-  const R* lam_z = lam_p + 3 * N;
-  const R* uc_x = (const R*)a.u_cur + N;
-  const R* uc_y = uc_x + N;
-  const R* uc_z = uc_x + 2 * N;
+  // the arrays read or written on every plane go through buffer resources
+  // (per-thread byte offsets fixed over the march, plane offsets uniform);
+  // the conditional body and target accesses keep flat pointers
+  constexpr unsigned es = sizeof(R);
+  const unsigned fb = (unsigned)N * es;  // bytes of one field (4 fields fit 32 bits)
+  const __amdgpu_buffer_rsrc_t rlam = brsrc(a.lam, 4u * fb);
+  const __amdgpu_buffer_rsrc_t rup = brsrc(a.u_prev, 4u * fb);
+  const __amdgpu_buffer_rsrc_t rlp = brsrc(a.lam_prev, 4u * fb);
+  const R* ucur = (const R*)a.u_cur;
   const int bvol = (int)a.box.vol, bplane = a.box.sx * a.box.sy;
   const bool body = a.bk && bvol > 0;
   const R* bkp = (const R*)a.bk;
-  const R* bux = (const R*)a.bu;
-  const R* buy = bux + bvol;
-  const R* buz = bux + 2 * bvol;
+  const R* bup = (const R*)a.bu;
   R* bkbar = (R*)a.bkbar;
-  R* bubar_x = (R*)a.bubar;
-  R* bubar_y = bubar_x + bvol;
-  R* bubar_z = bubar_x + 2 * bvol;
+  R* bubar = (R*)a.bubar;
   const int nz = g.n[2];
   const int NP = g.n[0] * g.n[1];
   int tbx, tby, tbz;
@@ -1016,9 +1014,8 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
   const bool own = outer && gx >= 0 && gx < g.n[0] && gy >= 0 && gy < g.n[1];
   const int oc = (ty + 1) * FX + (tx + 1);
   const int ocol = own ? gx + g.n[0] * gy : 0;
-  const R* up_x = (const R*)a.u_prev + N;
-  const R* up_y = up_x + N;
-  const R* up_z = up_x + 2 * N;
+  const unsigned ovo = (unsigned)ocol * es;
+  const unsigned lvo = (unsigned)lofs * es;
 
   // Register buffers of two planes in flight.  The per-lane conditional
   // loads of a plane are issued first and the unconditional ones (clamped
@@ -1042,7 +1039,7 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
     const int zw = fzw, r2 = fr2;
     fzw = fzw + 1 == nz ? 0 : fzw + 1;
     fr2 = fr2 + 1 == nz ? 0 : fr2 + 1;
-    const int pl = NP * zw;
+    const unsigned so = (unsigned)(NP * zw) * es;
     const bool zbox = r2 < a.box.ext[2];
     const bool ztg = zw >= g.tlo[2] && zw < g.thi[2];
     const bool own_plane = zp >= z0 && zp < z1;
@@ -1050,33 +1047,34 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
     B.bi = (bxy >= 0 && zbox) ? bxy + bplane * r2 : -1;
     B.bown = B.bi >= 0 && lown && own_plane;
     B.w[0] = B.w[1] = B.w[2] = R(0);
-    if (nwn > 0) B.w[0] = lam_p[pl + wofs[0]];
-    if (nwn > 1) B.w[1] = lam_p[pl + wofs[1]];
-    if (nwn > 2) B.w[2] = lam_p[pl + wofs[2]];
+    if (nwn > 0) B.w[0] = bld<R>(rlam, (unsigned)wofs[0] * es, so);
+    if (nwn > 1) B.w[1] = bld<R>(rlam, (unsigned)wofs[1] * es, so);
+    if (nwn > 2) B.w[2] = bld<R>(rlam, (unsigned)wofs[2] * es, so);
     B.un[0] = B.un[1] = B.un[2] = R(0);
     if (B.tg || B.bown) {
-      B.un[0] = uc_x[pl + lofs];
-      B.un[1] = uc_y[pl + lofs];
-      B.un[2] = uc_z[pl + lofs];
+      const R* uc = ucur + NP * zw + lofs;
+      B.un[0] = uc[N];
+      B.un[1] = uc[2 * N];
+      B.un[2] = uc[3 * N];
     }
     B.bk = R(0);
     B.bu[0] = B.bu[1] = B.bu[2] = R(0);
     if (B.bi >= 0) {
       B.bk = bkp[B.bi];
-      B.bu[0] = bux[B.bi];
-      B.bu[1] = buy[B.bi];
-      B.bu[2] = buz[B.bi];
+      B.bu[0] = bup[B.bi];
+      B.bu[1] = bup[B.bi + bvol];
+      B.bu[2] = bup[B.bi + 2 * bvol];
     }
     int zo = zp - 2;
     const bool zown = zo >= z0 && zo < z1;
-    const int iu = (zown ? NP * zo : 0) + ocol;
-    B.up[0] = up_x[iu];
-    B.up[1] = up_y[iu];
-    B.up[2] = up_z[iu];
-    B.l[0] = lam_p[pl + lofs];
-    B.l[1] = lam_x[pl + lofs];
-    B.l[2] = lam_y[pl + lofs];
-    B.l[3] = lam_z[pl + lofs];
+    const unsigned uso = (unsigned)(zown ? NP * zo : 0) * es;
+    B.up[0] = bld<R>(rup, ovo, uso + fb);
+    B.up[1] = bld<R>(rup, ovo, uso + 2u * fb);
+    B.up[2] = bld<R>(rup, ovo, uso + 3u * fb);
+    B.l[0] = bld<R>(rlam, lvo, so);
+    B.l[1] = bld<R>(rlam, lvo, so + fb);
+    B.l[2] = bld<R>(rlam, lvo, so + 2u * fb);
+    B.l[3] = bld<R>(rlam, lvo, so + 3u * fb);
   };
   auto commit = [&](int zp, const Buf& B) {
     const int sl = (zp + 2 * NR) % NR;
@@ -1097,9 +1095,9 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
         const R kb = ub0 * (B.bu[0] - B.un[0]) + ub1 * (B.bu[1] - B.un[1]) +
                      ub2 * (B.bu[2] - B.un[2]);
         bkbar[B.bi] = kb * inv;
-        bubar_x[B.bi] = kk * ub0 * inv;
-        bubar_y[B.bi] = kk * ub1 * inv;
-        bubar_z[B.bi] = kk * ub2 * inv;
+        bubar[B.bi] = kk * ub0 * inv;
+        bubar[B.bi + bvol] = kk * ub1 * inv;
+        bubar[B.bi + 2 * bvol] = kk * ub2 * inv;
       }
       ub0 *= inv;
       ub1 *= inv;
@@ -1115,10 +1113,6 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
   const bool owx = own && g.bc[0] == 1 && (gx <= 2 || gx >= g.n[0] - 3);
   const bool owy = own && g.bc[1] == 1 && (gy <= 2 || gy >= g.n[1] - 3);
   const R A2 = R(2) * (R)g.A;
-  R* lp_p = (R*)a.lam_prev;
-  R* lp_x = lp_p + N;
-  R* lp_y = lp_p + 2 * N;
-  R* lp_z = lp_p + 3 * N;
   // moment slot: threads 0..255 take their own output position (its moments
   // stay in registers for the output), threads 256..339 the 1-node halo ring
   const bool fok = tid < FP;
@@ -1200,7 +1194,7 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
     const int zo = zs - 1;
     if (zo >= z0 && own) {
       R(*m0)[FP] = mb[zo & 1];  // plane zo, written before this iteration's barrier
-      const int i = ocol + NP * zo;
+      const unsigned so = (unsigned)(NP * zo) * es;
       const R ux = upx, uy = upy, uz = upz;
       const R M0 = Mp[0];
       const R Mxx = Mp[4], Myy = Mp[5], Mzz = Mp[6];
@@ -1229,10 +1223,10 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
       bx += A2 * (tx0 + ty0 + R(0.5) * (zprev[0] - M[8]));
       by += A2 * (tx1 + ty1 + R(0.5) * (zprev[1] - M[9]));
       bz += A2 * (tx2 + ty2 + R(0.5) * (zprev[2] - M[6]));
-      lp_p[i] = R(3) * M0;
-      lp_x[i] = bx;
-      lp_y[i] = by;
-      lp_z[i] = bz;
+      bst<R>(R(3) * M0, rlp, ovo, so);
+      bst<R>(bx, rlp, ovo, so + fb);
+      bst<R>(by, rlp, ovo, so + 2u * fb);
+      bst<R>(bz, rlp, ovo, so + 3u * fb);
     }
     zprev[0] = Mp[8];
     zprev[1] = Mp[9];
