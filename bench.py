@@ -132,6 +132,35 @@ def c5_batch(nt: int = 4000):
             "sequential_s": round(ts, 3), "sequential_mlups": round(ns / ts / 1e6, 1)}
 
 
+def fwd_step_out_of_cache(nside: int = 256, nt: int = 12):
+    """The forward step on a D3Q15 grid whose state (nside^3 x 4 x 4 B, 268 MB
+    at 256^3) exceeds the 256 MB last-level cache: an HBM-resident point for
+    the same kernel (event-timed launches of one short forward march)."""
+    import torch
+    from paper_2608_01071_amd import lks, workloads as W
+    p, gamma, chi, psi = W.make_3d(nside, nside // 2, nt, 500, nu=0.04, seed=5, precision=0,
+                                   ckpt_k=nt)
+    plan = lks.Plan(p)
+    plan.forward(gamma, chi, psi)
+    torch.cuda.synchronize()
+    lks.profile_enable(True)
+    plan.forward(gamma, chi, psi)
+    torch.cuda.synchronize()
+    prof = lks.profile_read()
+    lks.profile_enable(False)
+    tot_ms, cnt = prof["fwd_step"]
+    avg_s = tot_ms / 1e3 / cnt
+    bpn = algorithmic_bytes_per_node("fwd_step", 3, 4)
+    achieved = p.N * bpn / avg_s / 1e9
+    del plan
+    torch.cuda.empty_cache()
+    return {"workload": f"D3Q15 {nside}^3, {nside // 2}^3 design, FP32, {nt} forward steps",
+            "kernel": "fwd_step", "avg_launch_us": round(avg_s * 1e6, 2),
+            "algorithmic_bytes": round(p.N * bpn), "achieved": round(achieved, 1),
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "mlups": round(p.N / avg_s / 1e6, 1)}
+
+
 def run_pass(plan, g, c, s, seed):
     import torch
     t0 = time.perf_counter()
@@ -169,6 +198,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the batched 16-instance study")
+    ap.add_argument("--no-big", action="store_true",
+                    help="skip the 256^3 forward-step point (state larger than the LLC)")
     ap.add_argument("--counters", action="store_true",
                     help="run only the short drive used for hardware-counter passes")
     args = ap.parse_args()
@@ -255,6 +286,9 @@ def main():
         del plan64
         torch.cuda.empty_cache()
 
+    del plan
+    torch.cuda.empty_cache()
+    big = None if args.no_big else fwd_step_out_of_cache()
     c5 = None if args.no_c5 else c5_batch()
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_steps)
 
@@ -272,6 +306,7 @@ def main():
         "cpu_baseline": cpu,
         "fp64_plain": fp64,
         "c5_batch": c5,
+        "fwd_step_256": big,
         "kernels": kernels,
     }
     print(json.dumps(line), flush=True)

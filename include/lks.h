@@ -85,7 +85,15 @@ typedef struct lks_problem {
   double ndir[3];          /* flow direction n of J1 */
   double phi;              /* J1 = E - phi V */
   int32_t ckpt_k;          /* checkpoint interval K (1..nt); 0 means nt */
+  int32_t body_tape;       /* body fields (kappa, u_s) kept for the reverse sweep:
+                              1 every step's, written by the forward march, so the
+                              segment recompute skips the map; -1 only the segment
+                              being reversed (the recompute maps again); 0 the
+                              former when it takes at most LKS_BODY_TAPE_AUTO_MAX
+                              bytes, else the latter.  Results are the same. */
 } lks_problem;
+
+#define LKS_BODY_TAPE_AUTO_MAX (96ull << 30)
 
 typedef struct lks_plan lks_plan;
 

@@ -128,6 +128,7 @@ struct lks_plan {
   size_t es;
   long long S;  // state elements
   int K, nck;
+  bool full_btape;  // body fields of every step kept (else of one segment)
   int nblk_step, nblk_map;
   Box bmax;     // strides, volume and launch extents of the body buffers
   // workspace offsets (bytes)
@@ -168,6 +169,7 @@ lks_status validate(const lks_problem* p) {
   if (p->nt < 1) return fail(LKS_EINVAL, "nt must be >= 1");
   if (p->r_t < 1 || p->r_w < 1) return fail(LKS_EINVAL, "filter radii must be >= 1");
   if (p->ckpt_k < 0 || p->ckpt_k > p->nt) return fail(LKS_EINVAL, "ckpt_k must be in 0..nt");
+  if (p->body_tape < -1 || p->body_tape > 1) return fail(LKS_EINVAL, "body_tape must be -1, 0 or 1");
   if (!(p->nu >= 0.0) || !(p->kappa_max >= 0.0) || !(p->q > 0.0))
     return fail(LKS_EINVAL, "need nu >= 0, kappa_max >= 0, q > 0");
   long long N = 1;
@@ -215,6 +217,7 @@ void fill_geo(const lks_problem& p, Geo& g) {
   g.NTinv = T > 0 ? 1.0 / ((double)p.nt * (double)T) : 0.0;
   // tile-grid origin: keeps every node's wall-stencil partners within one tile halo
   g.ty3 = p.d == 3 ? tile3_y(p.precision) : TILE_Y;
+  g.prec = p.precision;
   const int tile[2] = {TILE_X, g.ty3};
   for (int a = 0; a < 2; ++a) g.org[a] = (g.bc[a] == 1 && g.n[a] % tile[a] == 2) ? -1 : 0;
   // z segments: enough blocks to fill every CU with the resident block count
@@ -249,6 +252,15 @@ void* lam_slot(lks_plan* P, void* ws, int j) { return wsp(ws, P->o_lam) + (size_
 size_t body_bytes(const lks_plan* P) { return (size_t)(1 + P->g.d) * P->bmax.vol * P->es; }
 void* btape_slot(lks_plan* P, void* ws, int j) {
   return wsp(ws, P->o_btape) + (size_t)j * body_bytes(P);
+}
+// Body fields of step n in the reverse sweep of segment sg: the full tape's
+// slot n - 1, or the segment tape's slot n - nb.
+void* rev_body(lks_plan* P, void* ws, int n, int sg) {
+  return btape_slot(P, ws, P->full_btape ? n - 1 : n - (sg * P->K + 1));
+}
+// Body fields the forward march maps step n into.
+void* fwd_body(lks_plan* P, void* ws, int n) {
+  return P->full_btape ? btape_slot(P, ws, n - 1) : wsp(ws, P->o_body);
 }
 
 // Body fields (kappa, u_s) of step n into `body` (layout [1+d][bmax.vol]).
@@ -322,11 +334,11 @@ lks_status prelude(lks_plan* P, const double* gamma, const double* chi, const do
 lks_status forward_loop(lks_plan* P, void* ws, hipStream_t s) {
   HIPCHK(launch_zero(wsp(ws, P->o_flags), 64 * sizeof(int), s));
   HIPCHK(launch_zero(wsp(ws, P->o_opart), (size_t)P->nblk_step * 2 * sizeof(double), s));
-  void* body = wsp(ws, P->o_body);
   const void* in = ck_slot(P, ws, 0);
   for (int n = 1; n <= P->g.nt; ++n) {
     void* out = (n % P->K == 0 && n / P->K < P->nck) ? ck_slot(P, ws, n / P->K)
                                                       : pp_slot(P, ws, n & 1);
+    void* body = fwd_body(P, ws, n);
     if (lks_status e = map_step(P, ws, n, body, s)) return e;
     if (lks_status e = fwd_step(P, ws, n, in, out, body, n == 1 ? P->first_lazy : 1, 1, s))
       return e;
@@ -344,12 +356,14 @@ const void* final_state(lks_plan* P, void* ws) {
 }
 
 // Reverse sweep with segment recomputation: launches only.  The recompute
-// keeps each step's body fields, which the reverse steps then reuse.
+// keeps each step's body fields, which the reverse steps then reuse (with the
+// full body tape the forward march's are reused and the recompute maps
+// nothing).
 // Adjoint step n of segment sg (first step nb = sg K + 1), reading the
 // adjoint state from lambda slot `cur`.
 AdjArgs adj_args(lks_plan* P, void* ws, int n, int sg, int cur) {
   const int nb = sg * P->K + 1;
-  const void* body = btape_slot(P, ws, n - nb);
+  const void* body = rev_body(P, ws, n, sg);
   AdjArgs a;
   memset(&a, 0, sizeof a);
   a.lam = lam_slot(P, ws, cur);
@@ -391,8 +405,9 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
     for (int n = nb; n <= ne; ++n) {
       const void* in = (n == nb) ? ck_slot(P, ws, sg) : tape_slot(P, ws, n - nb - 1);
       const int lazy = (n == 1) ? P->first_lazy : 1;
-      void* body = btape_slot(P, ws, n - nb);
-      if (lks_status e = map_step(P, ws, n, body, s)) return e;
+      void* body = rev_body(P, ws, n, sg);
+      if (!P->full_btape)
+        if (lks_status e = map_step(P, ws, n, body, s)) return e;
       if (lks_status e = fwd_step(P, ws, n, in, tape_slot(P, ws, n - nb), body, lazy, 0, s))
         return e;
     }
@@ -538,8 +553,10 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   P->o_ck = take((size_t)P->nck * Sb);
   P->o_pp = take(2 * Sb);
   P->o_tape = take((size_t)P->K * Sb);
-  P->o_body = take(body_bytes(P));
-  P->o_btape = take((size_t)P->K * body_bytes(P));
+  const size_t full_tape = (size_t)g.nt * body_bytes(P);
+  P->full_btape = prob->body_tape == 1 || (prob->body_tape == 0 && full_tape <= LKS_BODY_TAPE_AUTO_MAX);
+  P->o_body = take(P->full_btape ? 0 : body_bytes(P));
+  P->o_btape = take(P->full_btape ? full_tape : (size_t)P->K * body_bytes(P));
   P->o_badj = take(body_bytes(P));
   P->o_lam = take(2 * Sb);
   P->o_krefbar = take((size_t)g.Mtot * sizeof(double));
@@ -785,12 +802,12 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
     mb.a[k].bxn = bxn;
     qb.start[k + 1] = qb.start[k] + round8(mapadj_blocks(P->g));
   }
+  const bool full = plans[0]->full_btape;
   auto map_all = [&](int n, int sg_body) -> lks_status {
     // sg_body < 0: the forward march's body buffer; else the tape slot of step n
     for (int k = 0; k < count; ++k) {
       lks_plan* P = plans[k];
-      void* body = sg_body < 0 ? wsp(ws[k], P->o_body)
-                               : btape_slot(P, ws[k], n - (sg_body * K + 1));
+      void* body = sg_body < 0 ? fwd_body(P, ws[k], n) : rev_body(P, ws[k], n, sg_body);
       mb.a[k].si = tab(P, ws[k], n);
       mb.a[k].bk = body;
       mb.a[k].bu = (char*)body + P->bmax.vol * P->es;
@@ -814,7 +831,7 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
     for (int k = 0; k < count; ++k) {
       lks_plan* P = plans[k];
       void* out = (n % K == 0 && n / K < nck) ? ck_slot(P, ws[k], n / K) : pp_slot(P, ws[k], n & 1);
-      fb.a[k] = fwd_args(P, ws[k], n, in[k], out, wsp(ws[k], P->o_body),
+      fb.a[k] = fwd_args(P, ws[k], n, in[k], out, fwd_body(P, ws[k], n),
                          n == 1 ? P->first_lazy : 1, 1);
       in[k] = out;
     }
@@ -835,12 +852,13 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
   for (int sg = nck - 1; sg >= 0; --sg) {
     const int nb = sg * K + 1, ne = std::min((sg + 1) * K, nt);
     for (int n = nb; n <= ne; ++n) {
-      if (lks_status e = map_all(n, sg)) return e;
+      if (!full)
+        if (lks_status e = map_all(n, sg)) return e;
       for (int k = 0; k < count; ++k) {
         lks_plan* P = plans[k];
         const void* src = (n == nb) ? ck_slot(P, ws[k], sg) : tape_slot(P, ws[k], n - nb - 1);
         fb.a[k] = fwd_args(P, ws[k], n, src, tape_slot(P, ws[k], n - nb),
-                           btape_slot(P, ws[k], n - nb), (n == 1) ? P->first_lazy : 1, 0);
+                           rev_body(P, ws[k], n, sg), (n == 1) ? P->first_lazy : 1, 0);
       }
       {
         Scope sc("fwd_step", s, true);
@@ -906,12 +924,13 @@ lks_status lks_batch_run(int32_t count, lks_plan* const* plans, const double* co
     HIPCHK(launch_zero(wsp(ws, P->o_badj), body_bytes(P), s));
     HIPCHK(hipMemcpyAsync(wsp(ws, P->o_geo), &P->g, sizeof(Geo), hipMemcpyHostToDevice, s));
   }
-  // 2D instances with a common step count, checkpoint interval and precision
-  // share every launch (groups of BATCH_MAX); others run as graph branches
+  // 2D instances with a common step count, checkpoint interval, precision and
+  // body-tape mode share every launch (groups of BATCH_MAX); others run as graph branches
   bool shared = true;
   for (int k = 0; k < count; ++k)
     shared = shared && plans[k]->g.d == 2 && plans[k]->prec == P0->prec &&
-             plans[k]->g.nt == P0->g.nt && plans[k]->K == P0->K && plans[k]->nck == P0->nck;
+             plans[k]->g.nt == P0->g.nt && plans[k]->K == P0->K && plans[k]->nck == P0->nck &&
+             plans[k]->full_btape == P0->full_btape;
   // one graph: instance k's forward march, objective copy, adjoint march and
   // epilogue form branch k, forked from and joined to the launch stream
   std::vector<const void*> key;

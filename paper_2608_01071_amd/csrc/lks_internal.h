@@ -80,6 +80,7 @@ struct Geo {
   int zseg;               // z planes per block segment (3D adjoint step)
   int zseg_f;             // z planes per block segment (3D forward step)
   int ty3;                // tile height of the step kernels (3D: Tile3<R>::TY; 2D: TILE_Y)
+  int prec;               // state precision (0 FP32, 1 FP64)
 };
 
 // Blocks of the 2D map transpose (MAPADJ_PTS2 runs of 64 points each).

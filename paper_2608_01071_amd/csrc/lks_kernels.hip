@@ -460,6 +460,13 @@ __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d(Geo g, FwdArgs a) {
   fwd2d_tile<R>(g, a, blockIdx.x);
 }
 
+// One node's (u_x, u_y, u_z, p) in LDS: the 3D step kernels read a
+// neighbour's values with one 16-byte (or, for u alone, 12-byte) access.
+template <class R>
+struct alignas(4 * sizeof(R)) Q4 {
+  R x, y, z, p;
+};
+
 // ------------------------------------------------------ forward, D3Q15
 // Block = one 32 x Tile3<R>::TY column tile marching z over a z segment
 // (the launcher passes the forward's segment length in g.zseg).  Per plane:
@@ -614,6 +621,7 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
   R am[4] = {R(0), R(0), R(0), R(0)}, a0[4] = {R(0), R(0), R(0), R(0)},
     ap[4] = {R(0), R(0), R(0), R(0)};
   double s1 = 0.0, s2 = 0.0;
+  bool bad = false;  // instability seen by this thread (reported once at the end)
   const R A = (R)g.A;
 
   // Iteration zf: commit plane zf+1 (buffer X) | barrier | fetch plane zf+3
@@ -715,7 +723,7 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
             u2 = (u2 + bkv * bu2) * inv;
           }
           const R uu = u0 * u0 + u1 * u1 + u2 * u2;
-          if (a.flags && !(uu < R(0.25))) a.flags[0] = 1;  // non-finite or |u| >= 0.5
+          bad = bad || !(uu < R(0.25));  // non-finite or |u| >= 0.5
         }
         const unsigned so = (unsigned)(NP * zo) * es;
         bst<R>(p, rout, ovo, so);
@@ -755,6 +763,7 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
     rs = rs == 2 ? 0 : rs + 1;
   }
   if (zf <= z1) iter(zf, rs, bA);
+  if (bad && a.flags) a.flags[0] = 1;
   if (a.opart) {
     double v[2] = {s1, s2};
     double tot[2];
@@ -940,7 +949,7 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
   static_assert(NT >= LP && NT >= FP, "one load and one moment slot per thread");
   constexpr int NR = AdjRing<R>::NR;  // 3: two barriers per plane, 4: one
   // adjoint star planes (mod NR); entries LP.. take the commits of idle slots
-  __shared__ R ring[NR][4][NT];
+  __shared__ Q4<R> ring[NR][NT];
   __shared__ R mb[2][5][FP];  // in-plane second moments (mod 2): Mxx, Myy, Mxy, Mxz, Myz
   const int N = (int)g.N;
   // the arrays read or written on every plane go through buffer resources
@@ -1103,10 +1112,12 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
       ub1 *= inv;
       ub2 *= inv;
     }
-    ring[sl][0][tid] = lok ? pb * R(1.0 / 3.0) : R(0);  // the gather transpose takes p-bar / 3
-    ring[sl][1][tid] = lok ? ub0 : R(0);
-    ring[sl][2][tid] = lok ? ub1 : R(0);
-    ring[sl][3][tid] = lok ? ub2 : R(0);
+    Q4<R> v;
+    v.p = lok ? pb * R(1.0 / 3.0) : R(0);  // the gather transpose takes p-bar / 3
+    v.x = lok ? ub0 : R(0);
+    v.y = lok ? ub1 : R(0);
+    v.z = lok ? ub2 : R(0);
+    ring[sl][tid] = v;
   };
 
   // own nodes within two nodes of a wall take the one-sided stencil transposes
@@ -1161,20 +1172,21 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
       // F_i(y) = p-bar(y + c_i) / 3 + c_i . u-bar(y + c_i); each opposite pair
       // enters the even moments through its sum and the first moments through
       // its difference
-      M[0] = R(Lat<15>::w[0]) * ring[rs[1]][0][fc];
+      M[0] = R(Lat<15>::w[0]) * ring[rs[1]][fc].p;
 #pragma unroll
       for (int i = 1; i < 15; i += 2) {
         const int cx = Lat<15>::c[i][0], cy = Lat<15>::c[i][1], cz = Lat<15>::c[i][2];
         const int pp = rs[cz + 1], pm = rs[1 - cz];
         const int jp = fc + cx + cy * LX, jm = fc - cx - cy * LX;
+        const Q4<R> vp = ring[pp][jp], vm = ring[pm][jm];
         R cu_p = R(0), cu_m = R(0);
-        if (cx == 1) { cu_p += ring[pp][1][jp]; cu_m += ring[pm][1][jm]; }
-        if (cx == -1) { cu_p -= ring[pp][1][jp]; cu_m -= ring[pm][1][jm]; }
-        if (cy == 1) { cu_p += ring[pp][2][jp]; cu_m += ring[pm][2][jm]; }
-        if (cy == -1) { cu_p -= ring[pp][2][jp]; cu_m -= ring[pm][2][jm]; }
-        if (cz == 1) { cu_p += ring[pp][3][jp]; cu_m += ring[pm][3][jm]; }
-        if (cz == -1) { cu_p -= ring[pp][3][jp]; cu_m -= ring[pm][3][jm]; }
-        const R Fp = ring[pp][0][jp] + cu_p, Fm = ring[pm][0][jm] - cu_m;
+        if (cx == 1) { cu_p += vp.x; cu_m += vm.x; }
+        if (cx == -1) { cu_p -= vp.x; cu_m -= vm.x; }
+        if (cy == 1) { cu_p += vp.y; cu_m += vm.y; }
+        if (cy == -1) { cu_p -= vp.y; cu_m -= vm.y; }
+        if (cz == 1) { cu_p += vp.z; cu_m += vm.z; }
+        if (cz == -1) { cu_p -= vp.z; cu_m -= vm.z; }
+        const R Fp = vp.p + cu_p, Fm = vm.p - cu_m;
         const R wS = R(Lat<15>::w[i]) * (Fp + Fm), wD = R(Lat<15>::w[i]) * (Fp - Fm);
         M[0] += wS;
         if (cx != 0) { M[1] += cx > 0 ? wD : -wD; M[4] += wS; }
@@ -1628,25 +1640,34 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
     else
       return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
   };
-  // Weighted sums of this lane's 4 taps of analysis plane z, summed over the
-  // quad: P = (W k, W u_x, W u_y, W u_z, dW/dx (same 4), dW/dy (same 4)).
-  // Taps outside the box read 0 through the buffer range check.
-  auto plane = [&](int z, R* P) {
+  // The analysis planes are visited in order (z is periodic in 3D): issue()
+  // loads this lane's 4 taps x 4 fields of the next plane (taps outside the
+  // box read 0 through the buffer range check); reduce() turns a loaded plane
+  // into its weighted sums over the quad, P = (W k, W u_x, W u_y, W u_z,
+  // dW/dx (same 4), dW/dy (same 4)).  Loads run one plane ahead of the sums.
+  int r2 = (l0 + fo - 1 - box.lo[2]) % g.n[2];  // box plane of the next issue
+  if (r2 < 0) r2 += g.n[2];
+  auto issue = [&](R* V) {
     unsigned base = BAD;
-    bool zok = wrap_axis(g, 2, z);
-    int r2 = z - box.lo[2];
-    if (g.bc[2] == 0) { r2 %= g.n[2]; if (r2 < 0) r2 += g.n[2]; }
-    if (zok && r2 >= 0 && r2 < box.ext[2] && biy >= 0)
-      base = (unsigned)(box.sx * biy + bplane * r2) * sizeof(R);
-    R S[4] = {R(0), R(0), R(0), R(0)}, D[4] = {R(0), R(0), R(0), R(0)};
+    if (r2 < box.ext[2] && biy >= 0) base = (unsigned)(box.sx * biy + bplane * r2) * sizeof(R);
+    r2 = r2 + 1 == g.n[2] ? 0 : r2 + 1;
 #pragma unroll
     for (int cx = 0; cx < 4; ++cx) {
       const unsigned off = (base == BAD || ox[cx] == BAD) ? BAD : base + ox[cx];
-      const R v[4] = {bload(rk, off), bload(ru0, off), bload(ru1, off), bload(ru2, off)};
+      V[4 * cx] = bload(rk, off);
+      V[4 * cx + 1] = bload(ru0, off);
+      V[4 * cx + 2] = bload(ru1, off);
+      V[4 * cx + 3] = bload(ru2, off);
+    }
+  };
+  auto reduce = [&](const R* V, R* P) {
+    R S[4] = {R(0), R(0), R(0), R(0)}, D[4] = {R(0), R(0), R(0), R(0)};
+#pragma unroll
+    for (int cx = 0; cx < 4; ++cx) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        S[q] += wx[cx] * v[q];
-        D[q] += dx[cx] * v[q];
+        S[q] += wx[cx] * V[4 * cx + q];
+        D[q] += dx[cx] * V[4 * cx + q];
       }
     }
 #pragma unroll
@@ -1675,18 +1696,26 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
       kbj[j] = overwrite ? 0.0 : kref_bar[k];
     }
   }
-  // level l0 + t uses analysis planes zb + t .. zb + t + 3
-  const int zb = l0 + fo - 1;
+  // level l0 + t uses analysis planes zb + t .. zb + t + 3, zb = l0 + fo - 1;
+  // plane zb + p is loaded into V[p & 1]
   R Wp[4][12];
-  plane(zb, Wp[0]);
-  plane(zb + 1, Wp[1]);
-  plane(zb + 2, Wp[2]);
+  R V[2][16];
+  issue(V[0]);
+  issue(V[1]);
+  reduce(V[0], Wp[0]);
+  issue(V[0]);
+  reduce(V[1], Wp[1]);
+  issue(V[1]);
+  reduce(V[0], Wp[2]);
+  issue(V[0]);
   R mine[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) mine[q] = R(0);
 #pragma unroll
   for (int t = 0; t < LCH; ++t) {
-    plane(zb + t + 3, Wp[(t + 3) & 3]);
+    const int p = t + 3;
+    reduce(V[p & 1], Wp[p & 3]);
+    if (p + 2 <= LCH + 2) issue(V[p & 1]);
     const R* P0 = Wp[t & 3];
     const R* P1 = Wp[(t + 1) & 3];
     const R* P2 = Wp[(t + 2) & 3];
@@ -2296,8 +2325,11 @@ hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf
 }
 
 // Design levels per lane group of the 3D map transpose: long chunks reuse
-// more of the sliding z window, short ones give more waves.
-static int mapadj_lch(const Geo& g) { return g.D[2] >= 3 * MAPADJ_LCH_LONG ? MAPADJ_LCH_LONG : MAPADJ_LCH; }
+// more of the sliding z window, short ones give more waves.  FP64 keeps the
+// short chunks (the long ones exceed its register file).
+static int mapadj_lch(const Geo& g) {
+  return g.prec == 0 && g.D[2] >= 3 * MAPADJ_LCH_LONG ? MAPADJ_LCH_LONG : MAPADJ_LCH;
+}
 
 int mapadj_blocks(const Geo& g) {
   if (g.d == 3) {
@@ -2330,14 +2362,9 @@ hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
                    (const float*)kref, m, box, si, (const float*)bkbar, (const float*)bubar,
                    kref_bar, overwrite, mpart);
     } else {
-      if (lng)
-        LKS_LAUNCH((k_mapadj3d<double, MAPADJ_LCH_LONG>), grid, dim3(MAPADJ_THREADS), 0, s, g,
-                   (const double*)kref, m, box, si, (const double*)bkbar, (const double*)bubar,
-                   kref_bar, overwrite, mpart);
-      else
-        LKS_LAUNCH((k_mapadj3d<double, MAPADJ_LCH>), grid, dim3(MAPADJ_THREADS), 0, s, g,
-                   (const double*)kref, m, box, si, (const double*)bkbar, (const double*)bubar,
-                   kref_bar, overwrite, mpart);
+      LKS_LAUNCH((k_mapadj3d<double, MAPADJ_LCH>), grid, dim3(MAPADJ_THREADS), 0, s, g,
+                 (const double*)kref, m, box, si, (const double*)bkbar, (const double*)bubar,
+                 kref_bar, overwrite, mpart);
     }
     return hipGetLastError();
   }

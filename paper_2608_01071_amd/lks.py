@@ -37,7 +37,7 @@ class LksProblem(C.Structure):
         ("xg_min", C.c_double * 3), ("xg_max", C.c_double * 3), ("th_min", C.c_double),
         ("th_max", C.c_double), ("nt", C.c_int32), ("r_t", C.c_int32), ("r_w", C.c_int32),
         ("tgt_lo", C.c_int32 * 3), ("tgt_hi", C.c_int32 * 3), ("ndir", C.c_double * 3),
-        ("phi", C.c_double), ("ckpt_k", C.c_int32),
+        ("phi", C.c_double), ("ckpt_k", C.c_int32), ("body_tape", C.c_int32),
     ]
 
 
@@ -104,6 +104,7 @@ def to_struct(p) -> LksProblem:
     s.nt, s.r_t, s.r_w = p.nt, p.r_t, p.r_w
     s.phi = p.phi
     s.ckpt_k = p.ckpt_k
+    s.body_tape = p.body_tape
     return s
 
 

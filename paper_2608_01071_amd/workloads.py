@@ -53,6 +53,7 @@ class Problem:
     phi: float = 0.0
     precision: int = 1                        # GPU state: 0 = FP32, 1 = FP64
     ckpt_k: int = 0                           # checkpoint interval (0 = nt)
+    body_tape: int = 0                        # body fields kept: 1 all steps, -1 a segment, 0 auto
 
     @property
     def N(self) -> int:

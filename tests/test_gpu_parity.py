@@ -257,18 +257,42 @@ def test_c1_forward_adjoint(orc, prec):
 
 
 def test_checkpoint_interval_does_not_change_gradients(orc):
-    """K in {1, 3, 7, nt} and full tape give bit-identical gradients."""
+    """K in {1, 3, 7, nt} and full tape give bit-identical gradients, with the
+    body fields of every step kept or re-mapped per segment."""
     p0 = prob2d((45, 21), 0, nt=14)
     gamma, chi, psi = rand_inputs(p0, 10)
     outs = []
     for K in (1, 3, 7, 14):
-        plan = lk().Plan(p0.replace(ckpt_k=K))
-        J3, _ = plan.forward(gamma, chi, psi)
-        g = plan.adjoint(gamma, chi, psi)
-        outs.append((cpu(J3), cpu(g["dgamma"]), cpu(g["dchi"]), cpu(g["dpsi"])))
+        for tape in (-1, 1):
+            plan = lk().Plan(p0.replace(ckpt_k=K, body_tape=tape))
+            J3, _ = plan.forward(gamma, chi, psi)
+            g = plan.adjoint(gamma, chi, psi)
+            outs.append((cpu(J3), cpu(g["dgamma"]), cpu(g["dchi"]), cpu(g["dpsi"])))
     for o in outs[1:]:
         for a, b in zip(o, outs[0]):
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_body_tape_modes_agree_3d(orc, prec):
+    """3D: keeping every step's body fields (no map in the recompute) and
+    re-mapping them per segment give bit-identical objective and gradients,
+    and both match the oracle."""
+    p0 = prob3d(prec=prec)
+    gamma, chi, psi = rand_inputs(p0, 21)
+    outs = []
+    for tape in (-1, 1):
+        plan = lk().Plan(p0.replace(body_tape=tape))
+        J3, _ = plan.forward(gamma, chi, psi)
+        g = plan.adjoint(gamma, chi, psi)
+        outs.append((cpu(J3), cpu(g["dgamma"]), cpu(g["dchi"]), cpu(g["dpsi"])))
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+    ref = orc.forward(p0, gamma, chi, psi)
+    adj = orc.adjoint(p0, gamma, chi, psi)
+    assert abs(outs[1][0][0] - ref["J"]) <= (1e-10 if prec == 1 else 1e-5) * abs(ref["J"])
+    for k, key in enumerate(("dgamma", "dchi", "dpsi")):
+        assert l2err(outs[1][1 + k], adj[key]) < (1e-9 if prec == 1 else 1e-3), key
 
 
 def test_periodic_approximation_state_carry(orc):
