@@ -48,6 +48,8 @@ constexpr int MAP_ZPL = 3;
 constexpr int KZ_PAD = 8;
 // 3D map transpose: design levels per thread.
 constexpr int MAPADJ_LCH = 8;
+// 3D map transpose: planes whose loads are in flight per lane group.
+constexpr int MAPADJ_PREFETCH = 2;
 constexpr int MAPADJ_LCH_LONG = 24;  // used when the design grid has >= 72 levels
 // 3D map transpose: lanes per (design column, level chunk), one per xy tap row.
 // 2D transfer: a block is a MAP2_TX x MAP2_TY patch of analysis nodes.

@@ -249,6 +249,29 @@ __device__ __forceinline__ R bld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsign
   else
     return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
+// N consecutive values from a buffer resource at byte offset `off` (4-byte
+// aligned), in 16-byte loads and one 8- or 4-byte remainder.
+template <class R, int N>
+__device__ __forceinline__ void bld_run(__amdgpu_buffer_rsrc_t r, unsigned off, R* out) {
+  constexpr int W = 16 / (int)sizeof(R);  // values per 16-byte load
+#pragma unroll
+  for (int k = 0; k + W <= N; k += W) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(off + k * sizeof(R)), 0, 0);
+    const R* pv = reinterpret_cast<const R*>(&v);
+#pragma unroll
+    for (int q = 0; q < W; ++q) out[k + q] = pv[q];
+  }
+  constexpr int D = N / W * W;
+  if constexpr (N - D >= 2 && sizeof(R) == 4) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)(off + D * sizeof(R)), 0, 0);
+    const R* pv = reinterpret_cast<const R*>(&v);
+    out[D] = pv[0];
+    out[D + 1] = pv[1];
+    if constexpr (N - D == 3) out[D + 2] = bld<R>(r, off + (D + 2) * sizeof(R), 0);
+  } else if constexpr (N - D == 1) {
+    out[D] = bld<R>(r, off + D * sizeof(R), 0);
+  }
+}
 template <class R>
 __device__ __forceinline__ void bst(R v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
   if constexpr (sizeof(R) == 4) {
@@ -1446,6 +1469,8 @@ __global__ __launch_bounds__(256) void k_map3d(Geo g, const R* kt, int lz, Mot m
 #pragma unroll
   for (int q = 0; q < 4; ++q) wz[q] = wk(f + R(1) - R(q));
   const R om = (R)m.om, c = (R)m.c, sn = (R)m.s;
+  // the z-fastest kappa_ref copy: each candidate's ZPL + 3 levels in wide loads
+  const __amdgpu_buffer_rsrc_t rkt = brsrc(kt, (unsigned)(g.D[0] * g.D[1] * lz) * sizeof(R));
   for (int zblk = 0; zblk < box.ext[2]; zblk += 32 * ZPL) {
     const int zbase = zblk + lane * ZPL;
     const bool zlive = zbase < box.ext[2];
@@ -1479,11 +1504,8 @@ __global__ __launch_bounds__(256) void k_map3d(Geo g, const R* kt, int lz, Mot m
         cidx[u] = v[u] ? ci[hw][sl[u]] : 0;
 #pragma unroll
         for (int t = 0; t < ZPL + 3; ++t) V[u][t] = R(0);
-        if (v[u] && zlive) {
-          const R* col = kt + (long long)cidx[u] * lz + (L0 + KZ_PAD);
-#pragma unroll
-          for (int t = 0; t < ZPL + 3; ++t) V[u][t] = col[t];
-        }
+        if (v[u] && zlive)
+          bld_run<R, ZPL + 3>(rkt, (unsigned)(cidx[u] * lz + L0 + KZ_PAD) * sizeof(R), V[u]);
       }
 #pragma unroll
       for (int u = 0; u < CG; ++u) {
@@ -1697,25 +1719,27 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
     }
   }
   // level l0 + t uses analysis planes zb + t .. zb + t + 3, zb = l0 + fo - 1;
-  // plane zb + p is loaded into V[p & 1]
+  // plane zb + p is loaded into V[p % PD] (PD >= 2), PD - 1 planes ahead of its sums
+  // (a grid of a few waves per SIMD hides little latency by itself)
+  constexpr int PD = sizeof(R) == 4 ? MAPADJ_PREFETCH : 2;  // FP64: registers
+  static_assert(PD >= 2, "one plane in flight while another is summed");
   R Wp[4][12];
-  R V[2][16];
-  issue(V[0]);
-  issue(V[1]);
-  reduce(V[0], Wp[0]);
-  issue(V[0]);
-  reduce(V[1], Wp[1]);
-  issue(V[1]);
-  reduce(V[0], Wp[2]);
-  issue(V[0]);
+  R V[PD][16];
+#pragma unroll
+  for (int p = 0; p < PD; ++p) issue(V[p]);
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    reduce(V[p % PD], Wp[p]);
+    if (p + PD <= LCH + 2) issue(V[p % PD]);
+  }
   R mine[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) mine[q] = R(0);
 #pragma unroll
   for (int t = 0; t < LCH; ++t) {
     const int p = t + 3;
-    reduce(V[p & 1], Wp[p & 3]);
-    if (p + 2 <= LCH + 2) issue(V[p & 1]);
+    reduce(V[p % PD], Wp[p & 3]);
+    if (p + PD <= LCH + 2) issue(V[p % PD]);
     const R* P0 = Wp[t & 3];
     const R* P1 = Wp[(t + 1) & 3];
     const R* P2 = Wp[(t + 2) & 3];
