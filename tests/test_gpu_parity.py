@@ -556,3 +556,84 @@ def test_fp32_objective_over_a_long_horizon():
         J3, _ = plan.forward(g, c, s)
         Js.append(cpu(J3)[0])
     assert abs(Js[1] - Js[0]) <= 1e-5 * abs(Js[0]), Js
+
+
+# ----------------------------------------------------------------------------
+# The D2Q9 workloads at full size: 512^2 (256^2 design, 20000 steps) and
+# 1024^2 (512^2 design, 10000 steps), in the plans their own problem
+# statements build (checkpoint interval, body box, motion bounds).
+
+@pytest.mark.parametrize("cfg", ["c2", "c3"])
+def test_d2q9_full_size_first_steps(orc, cfg):
+    """The first two steps of the workload's motion through lks_forward /
+    lks_adjoint on every node, FP64 and FP32, against the oracle.  A random
+    start state and a target over the whole interior make the objective and
+    all three gradients depend on the body within two steps."""
+    p, gamma, chi, psi = getattr(W, cfg)()
+    nx, ny = p.n[0], p.n[1]
+    p2 = p.replace(nt=2, ckpt_k=1, precision=1, tgt_lo=(0, 1, 0), tgt_hi=(nx, ny - 1, 1),
+                   phi=0.1)
+    s0 = rand_state(p2, 51, amp=0.02)
+    ref = orc.forward(p2, gamma, chi[:2], psi[:2], state0=s0, want_final=False)
+    adj = orc.adjoint(p2, gamma, chi[:2], psi[:2], state0=s0)
+    for prec in (1, 0):
+        pp = p2.replace(precision=prec)
+        plan = lk().Plan(pp)
+        J3, _ = plan.forward(gamma, chi[:2], psi[:2], state0=gpu_state(s0, pp))
+        g = plan.adjoint(gamma, chi[:2], psi[:2])
+        tj, tg = (1e-10, 1e-9) if prec == 1 else (1e-5, 1e-3)
+        assert abs(cpu(J3)[0] - ref["J"]) <= tj * abs(ref["J"]), prec
+        for k in ("dgamma", "dchi", "dpsi"):
+            assert np.linalg.norm(adj[k]) > 0, k
+            assert l2err(cpu(g[k]), adj[k]) < tg, (prec, k)
+
+
+def test_c2_fp32_against_fp64_full_horizon():
+    """512^2, 20000 steps from rest, forward + adjoint: the FP32 state with
+    FP64 sums against the FP64 plain form (objective within 1e-5, gradients
+    within 1e-3)."""
+    out = {}
+    for prec in (1, 0):
+        p, gamma, chi, psi = W.c2(precision=prec)
+        plan = lk().Plan(p)
+        J3, _ = plan.forward(gamma, chi, psi)
+        g = plan.adjoint(gamma, chi, psi)
+        out[prec] = (cpu(J3)[0], {k: cpu(g[k]) for k in ("dgamma", "dchi", "dpsi")})
+        del plan
+    J64, g64 = out[1]
+    J32, g32 = out[0]
+    assert abs(J32 - J64) <= 1e-5 * abs(J64), (J32, J64)
+    for k in g64:
+        assert l2err(g32[k], g64[k]) < 1e-3, k
+
+
+@pytest.mark.timeout(900)  # the oracle's 10000-step adjoint takes about 90 s
+def test_c3_crop_gradient_through_autograd(orc):
+    """The 1024^2 workload's gradient check: a 64^2 crop (the centre 32^2 of its
+    generated design field, the same chi, psi, nu and kappa_max, 10000 steps)
+    through torch.autograd with checkpoints every K in {50, 100, 200}, FP32
+    state, against the oracle."""
+    lks = lk()
+    p3, gamma3, chi, psi = W.c3()
+    g2 = gamma3.reshape(p3.m[1], p3.m[0])
+    c0 = p3.m[0] // 2 - 16
+    gamma = g2[c0:c0 + 32, c0:c0 + 32].ravel().copy()
+    p, *_ = W.make_2d(64, 32, p3.nt, p3.r_t, nu=p3.nu, seed=2, kappa_max=p3.kappa_max,
+                      precision=0)
+    ref = orc.forward(p.replace(precision=1), gamma, chi, psi, want_final=False)
+    adj = orc.adjoint(p.replace(precision=1), gamma, chi, psi)
+    grads = []
+    for K in (50, 100, 200):
+        plan = lks.Plan(p.replace(ckpt_k=K))
+        tg = torch.tensor(gamma, device="cuda", requires_grad=True)
+        tc = torch.tensor(chi, device="cuda", requires_grad=True)
+        tp = torch.tensor(psi, device="cuda", requires_grad=True)
+        J = lks.LKSObjective.apply(tg, tc, tp, plan)
+        J.backward()
+        assert abs(float(J.detach()) - ref["J"]) <= 1e-5 * abs(ref["J"]), K
+        grads.append([cpu(tg.grad), cpu(tc.grad), cpu(tp.grad)])
+        for a, k in zip(grads[-1], ("dgamma", "dchi", "dpsi")):
+            assert l2err(a, adj[k]) < 1e-3, (K, k)
+    for gk in grads[1:]:
+        for a, b in zip(gk, grads[0]):
+            assert np.array_equal(a, b)
