@@ -166,6 +166,26 @@ __device__ __forceinline__ R dnumT(const Geo& g, int a, int v, const R* s, int c
   return r;
 }
 
+// dnumT at node coordinate v as weights of the row entries at offsets
+// -2 .. +2 (k[2 + o]): the same terms, so a wall node's transpose is one
+// straight-line 5-tap sum.
+template <class R>
+__device__ __forceinline__ void dnumT_taps(const Geo& g, int a, int v, R k[5]) {
+  const int n = g.n[a];
+  for (int q = 0; q < 5; ++q) k[q] = R(0);
+  if (g.bc[a] != 1) {
+    k[1] = R(0.5);
+    k[3] = R(-0.5);
+    return;
+  }
+  if (v == 0) k[2] += R(-1.5);
+  if (v == n - 1) k[2] += R(1.5);
+  if (v - 1 >= 0) k[1] = v - 1 == 0 ? R(2) : R(0.5);
+  if (v + 1 <= n - 1) k[3] = v + 1 == n - 1 ? R(-2) : R(-0.5);
+  if (v - 2 == 0) k[0] = R(-0.5);
+  if (v + 2 == n - 1) k[4] = R(0.5);
+}
+
 // XCD-aware tile order.  Workgroups are dealt to the 8 XCDs round robin by
 // their linear id, and each XCD has its own L2; this remap gives every XCD a
 // contiguous run of tiles (x fastest, then y, then z segment), so tiles that
@@ -1146,7 +1166,17 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
   // own nodes within two nodes of a wall take the one-sided stencil transposes
   const bool owx = own && g.bc[0] == 1 && (gx <= 2 || gx >= g.n[0] - 3);
   const bool owy = own && g.bc[1] == 1 && (gy <= 2 || gy >= g.n[1] - 3);
-  const R A2 = R(2) * (R)g.A;
+  // their transposed stencils, doubled (the central transposes below are the
+  // raw differences: the factor 1/2 of the central difference sits in A)
+  R kxw[5], kyw[5];
+  dnumT_taps(g, 0, gx, kxw);
+  dnumT_taps(g, 1, gy, kyw);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    kxw[q] *= R(2);
+    kyw[q] *= R(2);
+  }
+  const R A = (R)g.A;
   // moment slot: threads 0..255 take their own output position (its moments
   // stay in registers for the output), threads 256..339 the 1-node halo ring
   const bool fok = tid < FP;
@@ -1239,25 +1269,38 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
       R bz = R(3) * Mp[3] + R(9) * (Mxz * ux + Myz * uy + Mzz * uz) - R(3) * uz * M0;
       // velocity-gradient transpose: D_x^T, D_y^T in plane (central, then the
       // one-sided transposes next to walls); D_z^T (periodic) from zo -+ 1
-      R tx0 = R(0.5) * (m0[0][oc - 1] - m0[0][oc + 1]);
-      R tx1 = R(0.5) * (m0[2][oc - 1] - m0[2][oc + 1]);
-      R tx2 = R(0.5) * (m0[3][oc - 1] - m0[3][oc + 1]);
-      R ty0 = R(0.5) * (m0[2][oc - FX] - m0[2][oc + FX]);
-      R ty1 = R(0.5) * (m0[1][oc - FX] - m0[1][oc + FX]);
-      R ty2 = R(0.5) * (m0[4][oc - FX] - m0[4][oc + FX]);
+      R tx0 = m0[0][oc - 1] - m0[0][oc + 1];
+      R tx1 = m0[2][oc - 1] - m0[2][oc + 1];
+      R tx2 = m0[3][oc - 1] - m0[3][oc + 1];
+      R ty0 = m0[2][oc - FX] - m0[2][oc + FX];
+      R ty1 = m0[1][oc - FX] - m0[1][oc + FX];
+      R ty2 = m0[4][oc - FX] - m0[4][oc + FX];
+      // taps with a zero weight may fall outside the moment plane: their
+      // row or column is clamped into it (nonzero weights never leave it)
       if (owx) {
-        tx0 = dnumT(g, 0, gx, m0[0], oc, 1);
-        tx1 = dnumT(g, 0, gx, m0[2], oc, 1);
-        tx2 = dnumT(g, 0, gx, m0[3], oc, 1);
+        tx0 = tx1 = tx2 = R(0);
+        const int r0 = oc - (tx + 1);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const int j = r0 + min(max(tx + 1 + q - 2, 0), FX - 1);
+          tx0 += kxw[q] * m0[0][j];
+          tx1 += kxw[q] * m0[2][j];
+          tx2 += kxw[q] * m0[3][j];
+        }
       }
       if (owy) {
-        ty0 = dnumT(g, 1, gy, m0[2], oc, FX);
-        ty1 = dnumT(g, 1, gy, m0[1], oc, FX);
-        ty2 = dnumT(g, 1, gy, m0[4], oc, FX);
+        ty0 = ty1 = ty2 = R(0);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const int j = (tx + 1) + min(max(ty + 1 + q - 2, 0), FY - 1) * FX;
+          ty0 += kyw[q] * m0[2][j];
+          ty1 += kyw[q] * m0[1][j];
+          ty2 += kyw[q] * m0[4][j];
+        }
       }
-      bx += A2 * (tx0 + ty0 + R(0.5) * (zprev[0] - M[8]));
-      by += A2 * (tx1 + ty1 + R(0.5) * (zprev[1] - M[9]));
-      bz += A2 * (tx2 + ty2 + R(0.5) * (zprev[2] - M[6]));
+      bx += A * (tx0 + ty0 + (zprev[0] - M[8]));
+      by += A * (tx1 + ty1 + (zprev[1] - M[9]));
+      bz += A * (tx2 + ty2 + (zprev[2] - M[6]));
       bst<R>(R(3) * M0, rlp, ovo, so);
       bst<R>(bx, rlp, ovo, so + fb);
       bst<R>(by, rlp, ovo, so + 2u * fb);
