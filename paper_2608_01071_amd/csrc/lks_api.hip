@@ -792,9 +792,8 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
     lks_plan* P = plans[k];
     const Geo* gp = (const Geo*)wsp(ws[k], P->o_geo);
     fb.geo[k] = ab.geo[k] = mb.geo[k] = qb.geo[k] = gp;
-    const int sb = round8(step_blocks_2d(P->g));
-    fb.start[k + 1] = fb.start[k] + sb;
-    ab.start[k + 1] = ab.start[k] + sb;
+    fb.start[k + 1] = fb.start[k] + round8(step_blocks_2d(P->g));
+    ab.start[k + 1] = ab.start[k] + round8(adj2d_blocks(P->g));
     int bxn = 0;
     mb.start[k + 1] = mb.start[k] + round8(map_blocks_2d(P->bmax, &bxn));
     mb.a[k].kref = wsp(ws[k], P->o_kref);

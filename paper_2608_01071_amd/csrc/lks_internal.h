@@ -13,6 +13,13 @@ namespace lks {
 constexpr int TILE_X = 32;
 constexpr int TILE_Y = 8;
 constexpr int STEP_THREADS = TILE_X * TILE_Y;
+// The 2D adjoint step takes TILE_X x ADJ2D_TY tiles with one thread per node
+// of the 2-node halo region (36 x 20 of 768 threads): every load, moment and
+// output slot is one thread's.  (The forward keeps 32 x 8 tiles: at 768
+// threads per block it holds fewer waves per CU and runs slower.)
+constexpr int ADJ2D_TY = 16;
+constexpr int ADJ2D_THREADS = 768;
+static_assert(ADJ2D_THREADS >= (TILE_X + 4) * (ADJ2D_TY + 4), "one halo-region slot per thread");
 // 3D step kernels: one thread per node of the 2-node halo plane.  FP32 takes
 // 32 x 16 tiles (36 x 20 halo plane, 768 threads: less halo recomputation);
 // FP64 keeps 32 x 8 (36 x 12, 448 threads) so its adjoint, at about 210
@@ -231,7 +238,8 @@ struct Batch {
 static_assert(sizeof(Batch<AdjArgs>) < 4000 && sizeof(Batch<FwdArgs>) < 4000 &&
                   sizeof(Batch<MapArgs>) < 4000 && sizeof(Batch<MapAdjArgs>) < 4000,
               "batched launch arguments must fit the kernel argument buffer");
-int step_blocks_2d(const Geo& g);  // tiles of the 2D step kernels
+int step_blocks_2d(const Geo& g);
+int adj2d_blocks(const Geo& g);  // tiles of the 2D adjoint step  // tiles of the 2D step kernels
 int map_blocks_2d(const Box& bmax, int* bxn);
 hipError_t launch_forward_step_batch(int precision, const Batch<FwdArgs>& b, hipStream_t s);
 hipError_t launch_adjoint_step_batch(int precision, const Batch<AdjArgs>& b, hipStream_t s);

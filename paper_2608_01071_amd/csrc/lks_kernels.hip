@@ -207,6 +207,9 @@ __device__ __forceinline__ int xcd_tile(int nbx, int nby, int nbz, int& bx, int&
 }
 __device__ __forceinline__ int tiles_x(const Geo& g) { return (g.n[0] - g.org[0] + TILE_X - 1) / TILE_X; }
 __device__ __forceinline__ int tiles_y(const Geo& g) { return (g.n[1] - g.org[1] + g.ty3 - 1) / g.ty3; }
+__host__ __device__ inline int adj2d_tiles_y(const Geo& g) {
+  return (g.n[1] - g.org[1] + ADJ2D_TY - 1) / ADJ2D_TY;
+}
 __device__ __forceinline__ int tiles_z(const Geo& g) { return g.d == 3 ? (g.n[2] + g.zseg - 1) / g.zseg : 1; }
 
 // Lattice constants of the equilibria in the state type.  In FP32 the
@@ -897,15 +900,15 @@ __device__ __forceinline__ void adj_star(const Geo& g, const AdjArgs& a, int x, 
 template <class R>
 __device__ __forceinline__ void adj2d_tile(const Geo& g, AdjArgs a, int bid) {
   apply_step(a.box, a.si);
-  constexpr int TX = TILE_X, TY = TILE_Y;
+  constexpr int TX = TILE_X, TY = ADJ2D_TY;
   constexpr int LX = TX + 4, LY = TY + 4, FX = TX + 2, FY = TY + 2;
   __shared__ R sl[3][LY * LX];     // pbar*, ubar*_x, ubar*_y
   __shared__ R sm[6][FY * FX];     // M0, M1x, M1y, M2xx, M2yy, M2xy
   const long long N = g.N;
   int tbx, tby, tbz;
-  xcd_tile_of(bid, tiles_x(g), tiles_y(g), 1, tbx, tby, tbz);
+  xcd_tile_of(bid, tiles_x(g), adj2d_tiles_y(g), 1, tbx, tby, tbz);
   const int x0 = tbx * TX + g.org[0], y0 = tby * TY + g.org[1];
-  for (int k = threadIdx.x; k < LX * LY; k += STEP_THREADS) {
+  for (int k = threadIdx.x; k < LX * LY; k += ADJ2D_THREADS) {
     int lx = k % LX, ly = k / LX;
     int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
     bool inside = wrap_axis(g, 0, gx) && wrap_axis(g, 1, gy);
@@ -918,7 +921,7 @@ __device__ __forceinline__ void adj2d_tile(const Geo& g, AdjArgs a, int bid) {
     sl[2][k] = v[2];
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < FX * FY; k += STEP_THREADS) {
+  for (int k = threadIdx.x; k < FX * FY; k += ADJ2D_THREADS) {
     int fx = k % FX, fy = k / FX;
     const int c = (fy + 1) * LX + (fx + 1);
     R M0 = R(0), M1x = R(0), M1y = R(0), Mxx = R(0), Myy = R(0), Mxy = R(0);
@@ -950,7 +953,7 @@ __device__ __forceinline__ void adj2d_tile(const Geo& g, AdjArgs a, int bid) {
   __syncthreads();
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
   const int gx = x0 + tx, gy = y0 + ty;
-  if (gx < 0 || gx >= g.n[0] || gy < 0 || gy >= g.n[1]) return;
+  if (ty >= TY || gx < 0 || gx >= g.n[0] || gy < 0 || gy >= g.n[1]) return;
   const int c = (ty + 1) * FX + (tx + 1);
   const long long i = nidx(g, gx, gy, 0);
   const R* up = (const R*)a.u_prev;
@@ -970,7 +973,7 @@ __device__ __forceinline__ void adj2d_tile(const Geo& g, AdjArgs a, int bid) {
 }
 
 template <class R>
-__global__ __launch_bounds__(STEP_THREADS) void k_adj2d(Geo g, AdjArgs a) {
+__global__ __launch_bounds__(ADJ2D_THREADS, 2) void k_adj2d(Geo g, AdjArgs a) {
   adj2d_tile<R>(g, a, blockIdx.x);
 }
 
@@ -2255,11 +2258,11 @@ __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d_batch(Batch<FwdArgs> b) 
 }
 
 template <class R>
-__global__ __launch_bounds__(STEP_THREADS) void k_adj2d_batch(Batch<AdjArgs> b) {
+__global__ __launch_bounds__(ADJ2D_THREADS, 2) void k_adj2d_batch(Batch<AdjArgs> b) {
   const int k = batch_instance(b.start, b.count, blockIdx.x);
   const int bid = blockIdx.x - b.start[k];
   const Geo& g = *b.geo[k];
-  if (bid >= tiles_x(g) * tiles_y(g)) return;
+  if (bid >= tiles_x(g) * adj2d_tiles_y(g)) return;
   adj2d_tile<R>(g, b.a[k], bid);
 }
 
@@ -2327,10 +2330,11 @@ hipError_t launch_forward_step(const Geo& g, int precision, const FwdArgs& a, hi
 hipError_t launch_adjoint_step(const Geo& g, int precision, const AdjArgs& a, hipStream_t s) {
   dim3 grid = step_grid(g);
   if (g.d == 2) {
+    grid = dim3(adj2d_blocks(g));
     if (precision == 0)
-      LKS_LAUNCH(k_adj2d<float>, grid, dim3(STEP_THREADS), 0, s, g, a);
+      LKS_LAUNCH(k_adj2d<float>, grid, dim3(ADJ2D_THREADS), 0, s, g, a);
     else
-      LKS_LAUNCH(k_adj2d<double>, grid, dim3(STEP_THREADS), 0, s, g, a);
+      LKS_LAUNCH(k_adj2d<double>, grid, dim3(ADJ2D_THREADS), 0, s, g, a);
   } else {
     if (precision == 0)
       LKS_LAUNCH(k_adj3d<float>, grid, dim3(Tile3<float>::NT), 0, s, g, a);
@@ -2532,6 +2536,9 @@ hipError_t launch_state_init(const Geo& g, int precision, void* st, hipStream_t 
 int step_blocks_2d(const Geo& g) {
   return ((g.n[0] - g.org[0] + TILE_X - 1) / TILE_X) * ((g.n[1] - g.org[1] + TILE_Y - 1) / TILE_Y);
 }
+int adj2d_blocks(const Geo& g) {
+  return ((g.n[0] - g.org[0] + TILE_X - 1) / TILE_X) * adj2d_tiles_y(g);
+}
 
 int map_blocks_2d(const Box& bmax, int* bxn) {
   *bxn = (bmax.ext[0] + MAP2_TX - 1) / MAP2_TX;
@@ -2550,9 +2557,9 @@ hipError_t launch_forward_step_batch(int precision, const Batch<FwdArgs>& b, hip
 hipError_t launch_adjoint_step_batch(int precision, const Batch<AdjArgs>& b, hipStream_t s) {
   dim3 grid(b.start[b.count]);
   if (precision == 0)
-    LKS_LAUNCH(k_adj2d_batch<float>, grid, dim3(STEP_THREADS), 0, s, b);
+    LKS_LAUNCH(k_adj2d_batch<float>, grid, dim3(ADJ2D_THREADS), 0, s, b);
   else
-    LKS_LAUNCH(k_adj2d_batch<double>, grid, dim3(STEP_THREADS), 0, s, b);
+    LKS_LAUNCH(k_adj2d_batch<double>, grid, dim3(ADJ2D_THREADS), 0, s, b);
   return hipGetLastError();
 }
 
