@@ -581,7 +581,7 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
   const unsigned ovo = own ? (unsigned)(gx + g.n[0] * gy) * es : 0u;
 
   // load slot of the halo plane (fixed over the march); slots outside the
-  // grid or the halo read node 0 of the plane and commit zeros
+  // grid or the halo read node 0 of the plane
   unsigned lvo, lpvo;  // byte offsets within a plane of (u) and (p)
   bool lok;
   {
@@ -627,9 +627,12 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
     B.v[2] = bld<R>(rin, lvo, so + 2u * fb);
     B.v[3] = bld<R>(rin, lvo, so + 3u * fb);
   };
+  // Slots outside the grid (beyond a wall) hold node 0's values, which no
+  // equilibrium that is used reads: a wall node takes one-sided derivatives
+  // into the grid, and the equilibria of slots outside the grid are zeroed.
   auto commit = [&](int sl, const Buf& B) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) ring[sl][q][tid] = lok ? B.v[q] : R(0);
+    for (int q = 0; q < 4; ++q) ring[sl][q][tid] = B.v[q];
   };
 
   // equilibrium slot: threads 0..255 take their own output position (the
