@@ -33,7 +33,7 @@ inline int tile3_y(int precision) { return precision == 0 ? 16 : 8; }
 // Resident blocks per CU the z-segment lengths of the 3D step kernels are
 // chosen for (the grid is about that many times CU_COUNT blocks): the
 // forward step holds two blocks per CU; the FP32 adjoint (768 threads at up to
-// 128 VGPRs) one, the FP64 adjoint two.
+// 168 VGPRs) one, the FP64 adjoint two.
 constexpr int STEP_RESIDENT_FWD = 2;
 inline int step_resident_adj(int precision) { return precision == 0 ? 1 : 2; }
 constexpr int CU_COUNT = 256;
@@ -44,7 +44,7 @@ template <class R>
 struct AdjRing {
   static constexpr int NR = sizeof(R) == 4 ? 4 : 3;
 };
-// design points per block of the map transpose.
+// Threads per block of the map transposes (2D and 3D).
 constexpr int MAPADJ_THREADS = 256;
 // 3D map: most z values per lane the kappa_ref copy is padded for, and the
 // value the map uses (one half-wave per analysis column, 32 * MAP_ZPL z
@@ -53,17 +53,19 @@ constexpr int MAP_ZC = 16;
 constexpr int MAP_ZPL = 3;
 // 3D map: zero padding (design levels) of the z-fastest kappa_ref copy.
 constexpr int KZ_PAD = 8;
-// 3D map transpose: design levels per thread.
+// 3D map transpose: design levels per lane group (short chunks, and long
+// ones for FP32 when the design grid has at least 3 x 24 levels).
 constexpr int MAPADJ_LCH = 8;
+constexpr int MAPADJ_LCH_LONG = 24;
 // 3D map transpose: planes whose loads are in flight per lane group.
 constexpr int MAPADJ_PREFETCH = 2;
-constexpr int MAPADJ_LCH_LONG = 24;  // used when the design grid has >= 72 levels
-// 3D map transpose: lanes per (design column, level chunk), one per xy tap row.
+// Map transposes: lanes per design column (3D: per level chunk), one per
+// row of the 4 x 4 xy taps.
+constexpr int MAPADJ_TPC = 4;
+// 2D map transpose: runs of 64 design points per block.
+constexpr int MAPADJ_PTS2 = 2;
 // 2D transfer: a block is a MAP2_TX x MAP2_TY patch of analysis nodes.
 constexpr int MAP2_TX = 64, MAP2_TY = 4;
-constexpr int MAPADJ_TPC = 4;
-// Runs of 64 design points per block of the 2D map transpose.
-constexpr int MAPADJ_PTS2 = 2;
 
 // Device copy of the problem (passed by value to every kernel).
 struct Geo {
