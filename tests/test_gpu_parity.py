@@ -637,3 +637,44 @@ def test_c3_crop_gradient_through_autograd(orc):
     for gk in grads[1:]:
         for a, b in zip(gk, grads[0]):
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_gpu_gradient_against_central_differences(d):
+    """On the GPU alone, FP64: central differences (h = 1e-6) of J from
+    lks_forward on 8 design entries and 8 motion entries agree with
+    lks_adjoint's gradient (the paper's verification method, Appendix A)."""
+    lks = lk()
+    p = prob2d((45, 21), 1, nt=12) if d == 2 else prob3d(prec=1)
+    plan = lks.Plan(p)
+    gamma, chi, psi = rand_inputs(p, 61)
+    plan.forward(gamma, chi, psi)
+    g = plan.adjoint(gamma, chi, psi)
+    dg, dc, dp = cpu(g["dgamma"]), cpu(g["dchi"]), cpu(g["dpsi"])
+    J = lambda ga, ch, ps: cpu(plan.forward(ga, ch, ps)[0])[0]
+    rng = np.random.default_rng(62)
+    h = 1e-6
+    gmax = max(np.abs(dg).max(), 1e-300)
+    for j in rng.choice(p.M, 8, replace=False):
+        gp, gm = gamma.copy(), gamma.copy()
+        gp[j] += h
+        gm[j] -= h
+        fd = (J(gp, chi, psi) - J(gm, chi, psi)) / (2 * h)
+        assert abs(fd - dg[j]) < 1e-6 * max(abs(fd), 1e-2 * gmax), (j, fd, dg[j])
+    cmax = max(np.abs(dc).max(), np.abs(dp).max())
+    for j in range(8):
+        t = int(rng.integers(p.nt))
+        comp = j % 4 if d == 3 else (0, 1, 3)[j % 3]
+        if comp < 3:
+            cp, cm = chi.copy(), chi.copy()
+            cp[t, comp] += h
+            cm[t, comp] -= h
+            fd = (J(gamma, cp, psi) - J(gamma, cm, psi)) / (2 * h)
+            ad = dc[t, comp]
+        else:
+            pp, pm = psi.copy(), psi.copy()
+            pp[t] += h
+            pm[t] -= h
+            fd = (J(gamma, chi, pp) - J(gamma, chi, pm)) / (2 * h)
+            ad = dp[t]
+        assert abs(fd - ad) < 1e-6 * max(abs(fd), 1e-2 * cmax), (t, comp, fd, ad)
