@@ -80,3 +80,16 @@ def test_null_arguments_rejected_before_any_launch(L):
     assert L.lks_adjoint(h, *([None] * 11)) == lks.LKS_EINVAL
     assert L.lks_step(h, None, None, None, None, None) == lks.LKS_EINVAL
     L.lks_plan_destroy(h)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on exactly one GPU: --gpus N > 1 exits with a message
+    (before touching a device)."""
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
