@@ -717,6 +717,180 @@ struct Oracle {
     if (mbar_out) std::copy(mbar.begin(), mbar.end(), mbar_out);
     sensitivities(gamma, kref_bar.data(), mbar.data(), dg, dchi, dpsi);
   }
+
+  // ------------------------------------------------ ALKS backward (Sec. 2.5)
+  // The continuous-adjoint lattice kinetic scheme as the paper states it.
+  // Multipliers of one time level: pt [N], ut [d][N], sl [3*3][N] (s~_ab in
+  // plane a*3+b).  Sign and scale are the paper's: the source terms enter
+  // with the signs of Eqs. ap, au, as and the sensitivities of Eqs. dJdgamma,
+  // dJdchi, dJdpsi use u~ as it is.
+  //
+  // Vector multiplying c_i in the adjoint equilibrium at every node y:
+  //   V_a = 3 (u~_a + 3 s~_ab u_b - p~ u_a) - A d_b (s~_ab + s~_ba),
+  // where the divergence is read as minus the transpose of the forward's
+  // difference operator (central inside, and the transposed one-sided
+  // stencil next to walls).
+  void alks_vector(const T* pt, const T* ut, const T* sl, const T* u, std::vector<T>& V) const {
+    V.assign((size_t)d * N, T(0.0));
+    for (long xn = 0; xn < N; ++xn) {
+      int x[3];
+      coords(xn, x);
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+          T g = A * (sl[(size_t)(a * 3 + b) * N + xn] + sl[(size_t)(b * 3 + a) * N + xn]);
+          long nodes[3];
+          double coef[3];
+          int k = deriv_stencil(b, x, nodes, coef);
+          for (int j = 0; j < k; ++j) V[a * N + nodes[j]] += coef[j] * g;
+        }
+    }
+    for (long y = 0; y < N; ++y)
+      for (int a = 0; a < d; ++a) {
+        T su = 0.0;
+        for (int b = 0; b < d; ++b) su += sl[(size_t)(a * 3 + b) * N + y] * u[b * N + y];
+        V[a * N + y] += 3.0 * (ut[a * N + y] + 3.0 * su - pt[y] * u[a * N + y]);
+      }
+  }
+
+  // Adjoint equilibrium f~eq_i(y) = (p~ + pw) + c_i . V at every node of one
+  // level; pw (nullable) is the pressure multiplier that wall nodes hand to
+  // their interior source node.  It joins the pressure term only: the wall's
+  // copy of p never multiplies the source node's velocity, so the coupling
+  // in V keeps the node's own p~.  The forward never gathers into a wall
+  // node, so no adjoint leaves one: f~eq is zero there.
+  void alks_equilibria(const T* pt, const T* pw, const T* ut, const T* sl, const T* u,
+                       std::vector<T>& ft) const {
+    std::vector<T> V;
+    alks_vector(pt, ut, sl, u, V);
+    ft.assign((size_t)L.Q * N, T(0.0));
+    for (long y = 0; y < N; ++y) {
+      int x[3];
+      coords(y, x);
+      if (is_wall(x)) continue;
+      for (int i = 0; i < L.Q; ++i) {
+        T f = pt[y] + (pw ? pw[y] : T(0.0));
+        for (int a = 0; a < d; ++a) f += (double)L.c[i][a] * V[a * N + y];
+        ft[(size_t)i * N + y] = f;
+      }
+    }
+  }
+
+  // Eqs. ap_tmp .. as_tmp: moments of the adjoint equilibria one level
+  // later, read at x + c_i (periodic wrap; nothing from outside the grid).
+  void alks_gather(const std::vector<T>& ft, T* pt, T* ut, T* sl) const {
+    for (long i = 0; i < N; ++i) pt[i] = 0.0;
+    for (long i = 0; i < (long)d * N; ++i) ut[i] = 0.0;
+    for (long i = 0; i < 9 * N; ++i) sl[i] = 0.0;
+    for (long yn = 0; yn < N; ++yn) {
+      int y[3];
+      coords(yn, y);
+      for (int i = 0; i < L.Q; ++i) {
+        int x[3] = {y[0] + L.c[i][0], y[1] + L.c[i][1], y[2] + L.c[i][2]};
+        bool ok = true;
+        for (int a = 0; a < d; ++a) ok = ok && wrap(a, x[a]);
+        if (!ok) continue;
+        T f = L.w[i] * ft[(size_t)i * N + idx(x)];
+        pt[yn] += f;
+        for (int a = 0; a < d; ++a) ut[a * N + yn] += (double)L.c[i][a] * f;
+        for (int a = 0; a < d; ++a)
+          for (int b = 0; b < d; ++b)
+            sl[(size_t)(a * 3 + b) * N + yn] += (double)(L.c[i][a] * L.c[i][b]) * f;
+      }
+    }
+  }
+
+  // Full ALKS backward.  adj_initial (nullable) receives (-3 p~, -V) of
+  // level 0: the scheme's estimate of dJ/d(state0) in the forward's
+  // variables (the multipliers carry the opposite sign).
+  void alks_adjoint(const T* gamma, const T* chi, const T* psi, const T* state0, double dJ,
+                    T* adj_initial, T* dg, T* dchi, T* dpsi, T* kref_bar_out, T* mbar_out) const {
+    const long S = (long)(d + 1) * N;
+    const int nt = P.nt;
+    std::vector<T> traj((size_t)(nt + 1) * S);
+    T J3[3];
+    forward(gamma, chi, psi, state0, nullptr, J3, traj.data());
+    T E = J3[1];
+    std::vector<T> mot((size_t)nt * 8), kref(Mtot), kappa(N), us((size_t)d * N);
+    motion(chi, psi, mot.data());
+    kappa_ref(gamma, kref.data());
+    std::vector<T> pt(N, T(0.0)), ut((size_t)d * N, T(0.0)), sl((size_t)9 * N, T(0.0));
+    std::vector<T> pw(N, T(0.0));
+    std::vector<T> ft, kbar(N), usbar((size_t)d * N);
+    std::vector<T> kref_bar(Mtot, T(0.0)), mbar((size_t)nt * 8, T(0.0));
+    long NT = (long)nt * target_count();
+    for (int t = nt; t >= 1; --t) {
+      const T* st = &traj[(size_t)t * S];
+      // moments of level t from the adjoint equilibria of level t + 1 (zero
+      // after the last step)
+      if (t < nt) {
+        alks_equilibria(pt.data(), pw.data(), ut.data(), sl.data(),
+                        &traj[(size_t)(t + 1) * S + N], ft);
+        alks_gather(ft, pt.data(), ut.data(), sl.data());
+      }
+      map(kref.data(), &mot[(size_t)(t - 1) * 8], kappa.data(), us.data());
+      // Eq. au: objective source -sum_i w_i c_i dJ/df_i = -(1/3) dJ/du, and
+      // the Brinkman source -kappa u~ taken at the new value (implicit); the
+      // kappa and objective terms of Eqs. ap and as are odd moments and vanish
+      if (NT > 0) {
+        for (long xn = 0; xn < N; ++xn) {
+          int x[3];
+          coords(xn, x);
+          if (!in_target(x)) continue;
+          T un = 0.0;
+          for (int k = 0; k < d; ++k) un += P.ndir[k] * st[(k + 1) * N + xn];
+          T g = dJ * (1.0 - 2.0 * P.phi * (un - E)) / (double)NT;
+          for (int k = 0; k < d; ++k) ut[k * N + xn] -= g * P.ndir[k] / 3.0;
+        }
+      }
+      for (long xn = 0; xn < N; ++xn)
+        for (int a = 0; a < d; ++a) ut[a * N + xn] /= (1.0 + kappa[xn]);
+      // wall rule: a wall node's pressure is a copy of its interior source,
+      // so its multiplier moves there (into pw); imposed velocities carry none
+      for (long xn = 0; xn < N; ++xn) pw[xn] = 0.0;
+      for (long xn = 0; xn < N; ++xn) {
+        int x[3];
+        coords(xn, x);
+        if (!is_wall(x)) continue;
+        pw[wall_source(x)] += pt[xn];
+      }
+      for (long xn = 0; xn < N; ++xn) {
+        int x[3];
+        coords(xn, x);
+        if (!is_wall(x)) continue;
+        pt[xn] = 0.0;
+        for (int a = 0; a < d; ++a) ut[a * N + xn] = 0.0;
+      }
+      // Eqs. dJdgamma, dJdchi, dJdpsi: dJ/dkappa = 3 (u - u^S) . u~ and
+      // dJ/du^S = -3 kappa u~, pulled back to the design grid by the
+      // transfer's transpose
+      for (long xn = 0; xn < N; ++xn) {
+        T kb = 0.0;
+        for (int a = 0; a < d; ++a) {
+          kb += 3.0 * (st[(a + 1) * N + xn] - us[a * N + xn]) * ut[a * N + xn];
+          usbar[a * N + xn] = -3.0 * kappa[xn] * ut[a * N + xn];
+        }
+        kbar[xn] = kb;
+      }
+      map_adjoint(kref.data(), &mot[(size_t)(t - 1) * 8], kbar.data(), usbar.data(),
+                  kref_bar.data(), &mbar[(size_t)(t - 1) * 8]);
+    }
+    if (adj_initial) {
+      // level 0: moments gathered from level 1, no sources
+      if (nt >= 1) {
+        alks_equilibria(pt.data(), pw.data(), ut.data(), sl.data(), &traj[(size_t)1 * S + N], ft);
+        alks_gather(ft, pt.data(), ut.data(), sl.data());
+      }
+      std::vector<T> V;
+      alks_vector(pt.data(), ut.data(), sl.data(), &traj[N], V);
+      for (long i = 0; i < N; ++i) adj_initial[i] = -3.0 * pt[i];
+      for (long i = 0; i < (long)d * N; ++i) adj_initial[N + i] = -V[i];
+    }
+    if (kref_bar_out) std::copy(kref_bar.begin(), kref_bar.end(), kref_bar_out);
+    if (mbar_out) std::copy(mbar.begin(), mbar.end(), mbar_out);
+    // the sign of the multipliers is folded into dJ/dkappa and dJ/du^S above,
+    // so the chain rule is the one of the discrete adjoint
+    sensitivities(gamma, kref_bar.data(), mbar.data(), dg, dchi, dpsi);
+  }
 };
 
 int validate(const orc_problem* p) {
@@ -804,6 +978,28 @@ int orc_adjoint(const orc_problem* p, const double* gamma, const double* chi, co
   if (int e = validate(p)) return e;
   Oracle<double>(*p).adjoint(gamma, chi, psi, state0, dJ, adj_terminal, adj_initial, dJ_dgamma,
                              dJ_dchi, dJ_dpsi, kref_bar, motion_bar);
+  return 0;
+}
+
+int orc_alks_adjoint(const orc_problem* p, const double* gamma, const double* chi,
+                     const double* psi, const double* state0, double dJ, double* adj_initial,
+                     double* dJ_dgamma, double* dJ_dchi, double* dJ_dpsi, double* kref_bar,
+                     double* motion_bar) {
+  if (int e = validate(p)) return e;
+  Oracle<double>(*p).alks_adjoint(gamma, chi, psi, state0, dJ, adj_initial, dJ_dgamma, dJ_dchi,
+                                  dJ_dpsi, kref_bar, motion_bar);
+  return 0;
+}
+
+int orc_alks_gather(const orc_problem* p, const double* fields_next, const double* u_next,
+                    double* fields_out) {
+  if (int e = validate(p)) return e;
+  Oracle<double> o(*p);
+  const long N = o.N;
+  const int d = o.d;
+  std::vector<double> ft;
+  o.alks_equilibria(fields_next, nullptr, fields_next + N, fields_next + (1 + d) * N, u_next, ft);
+  o.alks_gather(ft, fields_out, fields_out + N, fields_out + (1 + d) * N);
   return 0;
 }
 

@@ -89,6 +89,22 @@ int orc_adjoint(const orc_problem* p, const double* gamma, const double* chi,
                 const double* adj_terminal, double* adj_initial, double* dJ_dgamma,
                 double* dJ_dchi, double* dJ_dpsi, double* kref_bar, double* motion_bar);
 
+/* Paper-literal ALKS backward (Sec. 2.5): the continuous-adjoint lattice
+ * kinetic scheme with the adjoint equilibrium and Eqs. ap_tmp .. as, run from
+ * the last step to the first, and the sensitivities of Eqs. dJdgamma, dJdchi,
+ * dJdpsi.  Outputs as orc_adjoint; adj_initial (nullable, [d+1][N]) receives
+ * the scheme's estimate of dJ/d(state0).  No terminal multipliers. */
+int orc_alks_adjoint(const orc_problem* p, const double* gamma, const double* chi,
+                     const double* psi, const double* state0, double dJ, double* adj_initial,
+                     double* dJ_dgamma, double* dJ_dchi, double* dJ_dpsi, double* kref_bar,
+                     double* motion_bar);
+
+/* One ALKS level without sources: multipliers (p~ [N], u~ [d][N], s~ [9][N],
+ * s~_ab in plane 3a+b) of level t+1 and that level's velocity u [d][N] ->
+ * the gathered moments p~*, u~*, s~* of level t (same layout). */
+int orc_alks_gather(const orc_problem* p, const double* fields_next, const double* u_next,
+                    double* fields_out);
+
 /* Sensitivity epilogue alone: raw accumulators -> dJ/dgamma, dJ/dchi, dJ/dpsi. */
 int orc_sensitivities(const orc_problem* p, const double* gamma, const double* kref_bar,
                       const double* motion_bar, const double* motion, double* dJ_dgamma,

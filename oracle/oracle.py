@@ -174,6 +174,32 @@ def adjoint(p, gamma, chi, psi, state0=None, dJ=1.0, adj_terminal=None):
             "kref_bar": kb, "motion_bar": mb.reshape(p.nt, 8)}
 
 
+def alks_adjoint(p, gamma, chi, psi, state0=None, dJ=1.0):
+    """Paper-literal ALKS backward (Sec. 2.5); same outputs as adjoint()."""
+    S = (p.d + 1) * p.N
+    ai = np.zeros(S)
+    dg = np.zeros(p.M)
+    dc = np.zeros(p.nt * 3)
+    dp = np.zeros(p.nt)
+    kb = np.zeros(p.Mtot)
+    mb = np.zeros(p.nt * 8)
+    _check(lib().orc_alks_adjoint(C.byref(to_struct(p)), _ptr(_f64(gamma)), _ptr(_f64(chi)),
+                                  _ptr(_f64(psi)), _ptr(_f64(state0)), C.c_double(dJ), _ptr(ai),
+                                  _ptr(dg), _ptr(dc), _ptr(dp), _ptr(kb), _ptr(mb)),
+           "orc_alks_adjoint")
+    return {"adj_initial": ai, "dgamma": dg, "dchi": dc.reshape(p.nt, 3), "dpsi": dp,
+            "kref_bar": kb, "motion_bar": mb.reshape(p.nt, 8)}
+
+
+def alks_gather(p, fields_next, u_next):
+    """One source-free ALKS level: (p~, u~ [d], s~ [9]) planes of level t+1 and
+    u of level t+1 -> the gathered moments of level t, same [1+d+9][N] layout."""
+    out = np.zeros((1 + p.d + 9) * p.N)
+    _check(lib().orc_alks_gather(C.byref(to_struct(p)), _ptr(_f64(fields_next)),
+                                 _ptr(_f64(u_next)), _ptr(out)), "orc_alks_gather")
+    return out
+
+
 def sensitivities(p, gamma, kref_bar, motion_bar):
     dg = np.zeros(p.M)
     dc = np.zeros(p.nt * 3)
