@@ -91,7 +91,14 @@ typedef struct lks_problem {
                               being reversed (the recompute maps again); 0 the
                               former when it takes at most LKS_BODY_TAPE_AUTO_MAX
                               bytes, else the latter.  Results are the same. */
+  int32_t scheme;          /* reverse sweep of lks_adjoint: LKS_ADJ_EXACT, the exact
+                              discrete adjoint of the march (the true gradient), or
+                              LKS_ADJ_ALKS, the paper's adjoint lattice kinetic
+                              scheme (Sec. 2.5), an approximation of it */
 } lks_problem;
+
+#define LKS_ADJ_EXACT 0
+#define LKS_ADJ_ALKS 1
 
 #define LKS_BODY_TAPE_AUTO_MAX (96ull << 30)
 
@@ -132,10 +139,14 @@ lks_status lks_forward(lks_plan* plan, const double* gamma, const double* chi,
                        const double* psi, const void* state0, void* state_final,
                        void* workspace, double* J_out, hipStream_t stream);
 
-/* Discrete adjoint of the forward march with the same inputs (Sec. 2.5).
+/* Reverse sweep of the forward march with the same inputs (Sec. 2.5): the
+ * exact discrete adjoint, or with scheme = LKS_ADJ_ALKS the paper's adjoint
+ * lattice kinetic scheme (adjoint equilibrium, Eqs. ap_tmp .. as, and the
+ * sensitivities of Eqs. dJdgamma, dJdchi, dJdpsi), which approximates it.
  * dJ: 1 double, the seed (dJ/dJ; usually 1).
  * adj_terminal: adjoint state added at step nt (nullable; periodic
- *   approximation of Sec. 3.3).  adj_initial: receives dJ/d(state0) (nullable).
+ *   approximation of Sec. 3.3; LKS_EINVAL with the ALKS scheme).
+ * adj_initial: receives dJ/d(state0) (nullable; the ALKS gives its estimate).
  * dJ_dgamma [m2][m1][m0], dJ_dchi [nt][3], dJ_dpsi [nt]: gradients of J
  *   (the paper maximises J; these are +grad J).
  * Recomputes each K-step segment from its checkpoint. */

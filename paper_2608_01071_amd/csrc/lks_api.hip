@@ -129,11 +129,12 @@ struct lks_plan {
   long long S;  // state elements
   int K, nck;
   bool full_btape;  // body fields of every step kept (else of one segment)
+  bool alks;        // reverse sweep by the paper's ALKS instead of the exact adjoint
   int nblk_step, nblk_map;
   Box bmax;     // strides, volume and launch extents of the body buffers
   // workspace offsets (bytes)
   size_t o_mot, o_tab, o_info, o_kref, o_flags, o_J3, o_seed, o_opart, o_ck, o_pp, o_tape,
-      o_body, o_btape, o_badj, o_lam, o_krefbar, o_mpart, o_mbar, o_den, o_kz, o_geo, total;
+      o_body, o_btape, o_badj, o_lam, o_xadj, o_krefbar, o_mpart, o_mbar, o_den, o_kz, o_geo, total;
   int first_lazy = 1;
   void* fwd_ws = nullptr;
   bool use_graphs = true;
@@ -170,6 +171,8 @@ lks_status validate(const lks_problem* p) {
   if (p->r_t < 1 || p->r_w < 1) return fail(LKS_EINVAL, "filter radii must be >= 1");
   if (p->ckpt_k < 0 || p->ckpt_k > p->nt) return fail(LKS_EINVAL, "ckpt_k must be in 0..nt");
   if (p->body_tape < -1 || p->body_tape > 1) return fail(LKS_EINVAL, "body_tape must be -1, 0 or 1");
+  if (p->scheme != LKS_ADJ_EXACT && p->scheme != LKS_ADJ_ALKS)
+    return fail(LKS_EINVAL, "scheme must be LKS_ADJ_EXACT or LKS_ADJ_ALKS");
   if (!(p->nu >= 0.0) || !(p->kappa_max >= 0.0) || !(p->q > 0.0))
     return fail(LKS_EINVAL, "need nu >= 0, kappa_max >= 0, q > 0");
   long long N = 1;
@@ -249,6 +252,9 @@ void* tape_slot(lks_plan* P, void* ws, int j) {
   return wsp(ws, P->o_tape) + (size_t)j * P->S * P->es;
 }
 void* lam_slot(lks_plan* P, void* ws, int j) { return wsp(ws, P->o_lam) + (size_t)j * P->S * P->es; }
+void* xadj_slot(lks_plan* P, void* ws, int j) {
+  return wsp(ws, P->o_xadj) + (size_t)j * P->g.d * P->g.N * P->es;
+}
 size_t body_bytes(const lks_plan* P) { return (size_t)(1 + P->g.d) * P->bmax.vol * P->es; }
 void* btape_slot(lks_plan* P, void* ws, int j) {
   return wsp(ws, P->o_btape) + (size_t)j * body_bytes(P);
@@ -378,6 +384,10 @@ AdjArgs adj_args(lks_plan* P, void* ws, int n, int sg, int cur) {
   a.si = tab(P, ws, n);
   a.seed = (const double*)wsp(ws, P->o_seed);
   a.E = (const double*)wsp(ws, P->o_J3) + 1;
+  if (P->alks) {
+    a.xin = xadj_slot(P, ws, cur);
+    a.xout = xadj_slot(P, ws, 1 - cur);
+  }
   return a;
 }
 
@@ -559,6 +569,9 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   P->o_btape = take(P->full_btape ? full_tape : (size_t)P->K * body_bytes(P));
   P->o_badj = take(body_bytes(P));
   P->o_lam = take(2 * Sb);
+  P->alks = prob->scheme == LKS_ADJ_ALKS;
+  // ALKS: raw first-moment part of the adjoint velocity, two slots like lambda
+  P->o_xadj = take(P->alks ? 2 * (size_t)g.d * g.N * P->es : 0);
   P->o_krefbar = take((size_t)g.Mtot * sizeof(double));
   P->o_mpart = take((size_t)g.nt * P->nblk_map * 8 * sizeof(double));
   P->o_mbar = take((size_t)g.nt * 8 * sizeof(double));
@@ -646,8 +659,11 @@ lks_status lks_adjoint(lks_plan* P, const double* gamma, const double* chi, cons
     return fail(LKS_EINVAL, "null argument");
   if (P->fwd_ws != ws)
     return fail(LKS_EINVAL, "lks_adjoint needs a preceding lks_forward on this plan and workspace");
+  if (adj_terminal && P->alks)
+    return fail(LKS_EINVAL, "adj_terminal is not supported with the ALKS scheme");
   const size_t Sb = (size_t)P->S * P->es;
   HIPCHK(hipMemcpyAsync(wsp(ws, P->o_seed), dJ, sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (P->alks) HIPCHK(launch_zero(xadj_slot(P, ws, 0), (size_t)P->g.d * P->g.N * P->es, s));
   if (adj_terminal) {
     HIPCHK(hipMemcpyAsync(lam_slot(P, ws, 0), adj_terminal, Sb, hipMemcpyDeviceToDevice, s));
   } else {
@@ -920,16 +936,18 @@ lks_status lks_batch_run(int32_t count, lks_plan* const* plans, const double* co
       HIPCHK(hipMemcpyAsync(wsp(ws, P->o_seed), &one, sizeof(double), hipMemcpyHostToDevice, s));
     }
     HIPCHK(launch_zero(lam_slot(P, ws, 0), (size_t)P->S * P->es, s));
+    if (P->alks) HIPCHK(launch_zero(xadj_slot(P, ws, 0), (size_t)P->g.d * P->g.N * P->es, s));
     HIPCHK(launch_zero(wsp(ws, P->o_badj), body_bytes(P), s));
     HIPCHK(hipMemcpyAsync(wsp(ws, P->o_geo), &P->g, sizeof(Geo), hipMemcpyHostToDevice, s));
   }
-  // 2D instances with a common step count, checkpoint interval, precision and
-  // body-tape mode share every launch (groups of BATCH_MAX); others run as graph branches
+  // 2D instances with a common step count, checkpoint interval, precision,
+  // body-tape mode and adjoint scheme share every launch (groups of
+  // BATCH_MAX); others run as graph branches
   bool shared = true;
   for (int k = 0; k < count; ++k)
     shared = shared && plans[k]->g.d == 2 && plans[k]->prec == P0->prec &&
              plans[k]->g.nt == P0->g.nt && plans[k]->K == P0->K && plans[k]->nck == P0->nck &&
-             plans[k]->full_btape == P0->full_btape;
+             plans[k]->full_btape == P0->full_btape && plans[k]->alks == P0->alks;
   // one graph: instance k's forward march, objective copy, adjoint march and
   // epilogue form branch k, forked from and joined to the launch stream
   std::vector<const void*> key;

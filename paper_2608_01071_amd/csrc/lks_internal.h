@@ -175,6 +175,13 @@ struct AdjArgs {
   const double* seed;   // dJ (device, nullable -> no objective seed)
   const double* E;      // mean of n.u from the forward (device)
   const StepInfo* si;   // nullable: step box taken from the device table
+  // Paper-literal ALKS instead of the exact transpose (both null: exact).
+  // The adjoint velocity state then has two parts: lam holds the whole
+  // vector of the adjoint equilibrium, xin its raw first-moment part
+  // 3 u~ ([d][N], read on body-box nodes only), on which alone the
+  // Brinkman source acts; xout receives the raw part of step n - 1.
+  const void* xin;
+  void* xout;
 };
 
 int step_blocks(const Geo& g);

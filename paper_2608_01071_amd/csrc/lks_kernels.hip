@@ -828,8 +828,10 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
 // Adjoint-state value of node (x,y,z) after the objective seed, the
 // transposed wall rule and the transposed Brinkman correction:
 // returns (pbar*, ubar*).  Wall nodes and nodes outside the grid give 0.
-// Owned nodes of the body box also emit dJ/dkappa and dJ/du_s.
-template <class R>
+// Owned nodes of the body box also emit dJ/dkappa and dJ/du_s.  ALK: the
+// ALKS sources of Sec. 2.5 instead (Eq. au): seed and Brinkman act on the
+// raw first-moment part X = 3 u~ alone, the coupling part passes through.
+template <class R, bool ALK>
 __device__ __forceinline__ void adj_star(const Geo& g, const AdjArgs& a, int x, int y, int z,
                                          bool inside, bool owned, R out[4]) {
   out[0] = out[1] = out[2] = out[3] = R(0);
@@ -862,6 +864,7 @@ __device__ __forceinline__ void adj_star(const Geo& g, const AdjArgs& a, int x, 
   ub[1] = lam[2 * N + i];
   ub[2] = g.d == 3 ? lam[3 * N + i] : R(0);
   R un3[3] = {R(0), R(0), R(0)};
+  R sd[3] = {R(0), R(0), R(0)};  // objective seed
   bool have_u = false;
   if (a.seed && in_target(g, x, y, z)) {
     _Pragma("unroll") for (int k = 0; k < 3; ++k) if (k < g.d) un3[k] = uc[(k + 1) * N + i];
@@ -869,8 +872,10 @@ __device__ __forceinline__ void adj_star(const Geo& g, const AdjArgs& a, int x, 
     double un = 0.0;
     _Pragma("unroll") for (int k = 0; k < 3; ++k) if (k < g.d) un += g.ndir[k] * (double)un3[k];
     double gs = a.seed[0] * g.NTinv * (1.0 - 2.0 * g.phi * (un - a.E[0]));
-    _Pragma("unroll") for (int k = 0; k < 3; ++k) if (k < g.d) ub[k] += (R)(gs * g.ndir[k]);
+    _Pragma("unroll") for (int k = 0; k < 3; ++k) if (k < g.d) sd[k] = (R)(gs * g.ndir[k]);
   }
+  R T[3] = {ub[0], ub[1], ub[2]};  // state as loaded
+  _Pragma("unroll") for (int k = 0; k < 3; ++k) ub[k] += sd[k];
   out[0] = pb;
   if (a.bk) {
     long long bi = box_index(g, a.box, x, y, z);
@@ -879,6 +884,15 @@ __device__ __forceinline__ void adj_star(const Geo& g, const AdjArgs& a, int x, 
       const R* bu = (const R*)a.bu;
       const R k = bk[bi];
       const R inv = brinkman_inv(k);
+      // the part the Brinkman correction acts on
+      R xs[3] = {ub[0], ub[1], ub[2]}, X[3] = {R(0), R(0), R(0)};
+      if constexpr (ALK) {
+        const R* xi = (const R*)a.xin;
+        _Pragma("unroll") for (int q = 0; q < 3; ++q) if (q < g.d) {
+          X[q] = xi[q * N + i];
+          xs[q] = X[q] + sd[q];
+        }
+      }
       if (owned) {
         if (!have_u)
           _Pragma("unroll") for (int q = 0; q < 3; ++q) if (q < g.d) un3[q] = uc[(q + 1) * N + i];
@@ -886,12 +900,16 @@ __device__ __forceinline__ void adj_star(const Geo& g, const AdjArgs& a, int x, 
         R* bkbar = (R*)a.bkbar;
         R* bubar = (R*)a.bubar;
         _Pragma("unroll") for (int q = 0; q < 3; ++q) if (q < g.d) {
-          kb += ub[q] * (bu[q * a.box.vol + bi] - un3[q]);
-          bubar[q * a.box.vol + bi] = k * ub[q] * inv;
+          kb += xs[q] * (bu[q * a.box.vol + bi] - un3[q]);
+          bubar[q * a.box.vol + bi] = k * xs[q] * inv;
         }
         bkbar[bi] = kb * inv;
       }
-      _Pragma("unroll") for (int q = 0; q < 3; ++q) if (q < g.d) ub[q] *= inv;
+      if constexpr (ALK) {
+        _Pragma("unroll") for (int q = 0; q < 3; ++q) if (q < g.d) ub[q] = xs[q] * inv + (T[q] - X[q]);
+      } else {
+        _Pragma("unroll") for (int q = 0; q < 3; ++q) if (q < g.d) ub[q] *= inv;
+      }
     }
   }
   out[1] = ub[0];
@@ -900,7 +918,7 @@ __device__ __forceinline__ void adj_star(const Geo& g, const AdjArgs& a, int x, 
 }
 
 // ------------------------------------------------------ adjoint, D2Q9
-template <class R>
+template <class R, bool ALK>
 __device__ __forceinline__ void adj2d_tile(const Geo& g, AdjArgs a, int bid) {
   apply_step(a.box, a.si);
   constexpr int TX = TILE_X, TY = ADJ2D_TY;
@@ -918,7 +936,7 @@ __device__ __forceinline__ void adj2d_tile(const Geo& g, AdjArgs a, int bid) {
     bool owned = lx >= 2 && lx < TX + 2 && ly >= 2 && ly < TY + 2 && (x0 - 2 + lx) == gx &&
                  (y0 - 2 + ly) == gy;
     R v[4];
-    adj_star<R>(g, a, gx, gy, 0, inside, owned, v);
+    adj_star<R, ALK>(g, a, gx, gy, 0, inside, owned, v);
     sl[0][k] = v[0];
     sl[1][k] = v[1];
     sl[2][k] = v[2];
@@ -973,11 +991,16 @@ __device__ __forceinline__ void adj2d_tile(const Geo& g, AdjArgs a, int bid) {
   lp[i] = px;
   lp[N + i] = bx;
   lp[2 * N + i] = by;
+  if constexpr (ALK) {
+    R* xo = (R*)a.xout;
+    xo[i] = R(3) * sm[1][c];
+    xo[N + i] = R(3) * sm[2][c];
+  }
 }
 
-template <class R>
+template <class R, bool ALK>
 __global__ __launch_bounds__(ADJ2D_THREADS, 2) void k_adj2d(Geo g, AdjArgs a) {
-  adj2d_tile<R>(g, a, blockIdx.x);
+  adj2d_tile<R, ALK>(g, a, blockIdx.x);
 }
 
 // ------------------------------------------------------ adjoint, D3Q15
@@ -989,7 +1012,7 @@ __global__ __launch_bounds__(ADJ2D_THREADS, 2) void k_adj2d(Geo g, AdjArgs a) {
 // plane z-1 is then finished: equilibrium transpose plus the transposed
 // velocity gradient (in-plane from the moment plane, along z from the
 // neighbouring planes' moments of the own column).
-template <class R>
+template <class R, bool ALK>
 __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(Geo g, AdjArgs a) {
   apply_step(a.box, a.si);
   constexpr int TX = TILE_X, TY = Tile3<R>::TY, NT = Tile3<R>::NT;
@@ -1085,6 +1108,7 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
     R un[3];      // u^n of the slot node (target or owned body node)
     R bk, bu[3];  // body fields of the slot node
     R up[3];      // own column u^(n-1), output plane zp - 2
+    R x[ALK ? 3 : 1];  // ALKS: raw first-moment part of the slot node (body box)
     int bi;       // body-box index of the slot node, -1 outside
     bool tg, bown;
   };
@@ -1123,6 +1147,15 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
       B.bu[1] = bup[B.bi + bvol];
       B.bu[2] = bup[B.bi + 2 * bvol];
     }
+    if constexpr (ALK) {
+      B.x[0] = B.x[1] = B.x[2] = R(0);
+      if (B.bi >= 0) {
+        const R* xp = (const R*)a.xin + NP * zw + lofs;
+        B.x[0] = xp[0];
+        B.x[1] = xp[N];
+        B.x[2] = xp[2 * N];
+      }
+    }
     int zo = zp - 2;
     const bool zown = zo >= z0 && zo < z1;
     const unsigned uso = (unsigned)(zown ? NP * zo : 0) * es;
@@ -1138,28 +1171,52 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
     const int sl = (zp + 2 * NR) % NR;
     R pb = B.l[0] + (B.w[0] + B.w[1] + B.w[2]);
     R ub0 = B.l[1], ub1 = B.l[2], ub2 = B.l[3];
+    R s0 = R(0), s1 = R(0), s2 = R(0);  // objective seed
     if (B.tg) {
       const double un = g.ndir[0] * (double)B.un[0] + g.ndir[1] * (double)B.un[1] +
                         g.ndir[2] * (double)B.un[2];
       const R gs = (R)(seed * g.NTinv * (1.0 - 2.0 * g.phi * (un - Ebar)));
-      ub0 += gs * nd0;
-      ub1 += gs * nd1;
-      ub2 += gs * nd2;
+      s0 = gs * nd0;
+      s1 = gs * nd1;
+      s2 = gs * nd2;
+      if constexpr (!ALK) {
+        ub0 += s0;
+        ub1 += s1;
+        ub2 += s2;
+      }
     }
     if (B.bi >= 0) {
       const R kk = B.bk;
       const R inv = brinkman_inv(kk);
-      if (B.bown) {
-        const R kb = ub0 * (B.bu[0] - B.un[0]) + ub1 * (B.bu[1] - B.un[1]) +
-                     ub2 * (B.bu[2] - B.un[2]);
-        bkbar[B.bi] = kb * inv;
-        bubar[B.bi] = kk * ub0 * inv;
-        bubar[B.bi + bvol] = kk * ub1 * inv;
-        bubar[B.bi + 2 * bvol] = kk * ub2 * inv;
+      // the part the Brinkman correction acts on: all of it, or (ALKS) the
+      // raw first-moment part with the seed
+      R x0 = ub0, x1 = ub1, x2 = ub2;
+      if constexpr (ALK) {
+        x0 = B.x[0] + s0;
+        x1 = B.x[1] + s1;
+        x2 = B.x[2] + s2;
       }
-      ub0 *= inv;
-      ub1 *= inv;
-      ub2 *= inv;
+      if (B.bown) {
+        const R kb = x0 * (B.bu[0] - B.un[0]) + x1 * (B.bu[1] - B.un[1]) +
+                     x2 * (B.bu[2] - B.un[2]);
+        bkbar[B.bi] = kb * inv;
+        bubar[B.bi] = kk * x0 * inv;
+        bubar[B.bi + bvol] = kk * x1 * inv;
+        bubar[B.bi + 2 * bvol] = kk * x2 * inv;
+      }
+      if constexpr (ALK) {
+        ub0 = x0 * inv + (ub0 - B.x[0]);
+        ub1 = x1 * inv + (ub1 - B.x[1]);
+        ub2 = x2 * inv + (ub2 - B.x[2]);
+      } else {
+        ub0 *= inv;
+        ub1 *= inv;
+        ub2 *= inv;
+      }
+    } else if constexpr (ALK) {
+      ub0 += s0;
+      ub1 += s1;
+      ub2 += s2;
     }
     Q4<R> v;
     v.p = lok ? pb * R(1.0 / 3.0) : R(0);  // the gather transpose takes p-bar / 3
@@ -1311,6 +1368,12 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
       bst<R>(bx, rlp, ovo, so + fb);
       bst<R>(by, rlp, ovo, so + 2u * fb);
       bst<R>(bz, rlp, ovo, so + 3u * fb);
+      if constexpr (ALK) {
+        const __amdgpu_buffer_rsrc_t rxo = brsrc(a.xout, 3u * fb);
+        bst<R>(R(3) * Mp[1], rxo, ovo, so);
+        bst<R>(R(3) * Mp[2], rxo, ovo, so + fb);
+        bst<R>(R(3) * Mp[3], rxo, ovo, so + 2u * fb);
+      }
     }
     zprev[0] = Mp[8];
     zprev[1] = Mp[9];
@@ -2260,13 +2323,13 @@ __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d_batch(Batch<FwdArgs> b) 
   fwd2d_tile<R>(g, b.a[k], bid);
 }
 
-template <class R>
+template <class R, bool ALK>
 __global__ __launch_bounds__(ADJ2D_THREADS, 2) void k_adj2d_batch(Batch<AdjArgs> b) {
   const int k = batch_instance(b.start, b.count, blockIdx.x);
   const int bid = blockIdx.x - b.start[k];
   const Geo& g = *b.geo[k];
   if (bid >= tiles_x(g) * adj2d_tiles_y(g)) return;
-  adj2d_tile<R>(g, b.a[k], bid);
+  adj2d_tile<R, ALK>(g, b.a[k], bid);
 }
 
 template <class R>
@@ -2330,20 +2393,33 @@ hipError_t launch_forward_step(const Geo& g, int precision, const FwdArgs& a, hi
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_step(const Geo& g, int precision, const AdjArgs& a, hipStream_t s) {
-  dim3 grid = step_grid(g);
+template <bool ALK>
+static void launch_adjoint_step_t(const Geo& g, int precision, const AdjArgs& a, hipStream_t s) {
   if (g.d == 2) {
-    grid = dim3(adj2d_blocks(g));
-    if (precision == 0)
-      LKS_LAUNCH(k_adj2d<float>, grid, dim3(ADJ2D_THREADS), 0, s, g, a);
-    else
-      LKS_LAUNCH(k_adj2d<double>, grid, dim3(ADJ2D_THREADS), 0, s, g, a);
+    const dim3 grid(adj2d_blocks(g));
+    if (precision == 0) {
+      auto k = &k_adj2d<float, ALK>;
+      LKS_LAUNCH(k, grid, dim3(ADJ2D_THREADS), 0, s, g, a);
+    } else {
+      auto k = &k_adj2d<double, ALK>;
+      LKS_LAUNCH(k, grid, dim3(ADJ2D_THREADS), 0, s, g, a);
+    }
   } else {
-    if (precision == 0)
-      LKS_LAUNCH(k_adj3d<float>, grid, dim3(Tile3<float>::NT), 0, s, g, a);
-    else
-      LKS_LAUNCH(k_adj3d<double>, grid, dim3(Tile3<double>::NT), 0, s, g, a);
+    const dim3 grid = step_grid(g);
+    if (precision == 0) {
+      auto k = &k_adj3d<float, ALK>;
+      LKS_LAUNCH(k, grid, dim3(Tile3<float>::NT), 0, s, g, a);
+    } else {
+      auto k = &k_adj3d<double, ALK>;
+      LKS_LAUNCH(k, grid, dim3(Tile3<double>::NT), 0, s, g, a);
+    }
   }
+}
+hipError_t launch_adjoint_step(const Geo& g, int precision, const AdjArgs& a, hipStream_t s) {
+  if (a.xin)
+    launch_adjoint_step_t<true>(g, precision, a, s);
+  else
+    launch_adjoint_step_t<false>(g, precision, a, s);
   return hipGetLastError();
 }
 
@@ -2558,11 +2634,13 @@ hipError_t launch_forward_step_batch(int precision, const Batch<FwdArgs>& b, hip
 }
 
 hipError_t launch_adjoint_step_batch(int precision, const Batch<AdjArgs>& b, hipStream_t s) {
-  dim3 grid(b.start[b.count]);
-  if (precision == 0)
-    LKS_LAUNCH(k_adj2d_batch<float>, grid, dim3(ADJ2D_THREADS), 0, s, b);
-  else
-    LKS_LAUNCH(k_adj2d_batch<double>, grid, dim3(ADJ2D_THREADS), 0, s, b);
+  // the instances of one batch share the adjoint scheme
+  const dim3 grid(b.start[b.count]);
+  const bool alk = b.a[0].xin != nullptr;
+  using KB = void (*)(Batch<AdjArgs>);
+  KB k = precision == 0 ? (alk ? &k_adj2d_batch<float, true> : &k_adj2d_batch<float, false>)
+                        : (alk ? &k_adj2d_batch<double, true> : &k_adj2d_batch<double, false>);
+  LKS_LAUNCH(k, grid, dim3(ADJ2D_THREADS), 0, s, b);
   return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ class LksProblem(C.Structure):
         ("th_max", C.c_double), ("nt", C.c_int32), ("r_t", C.c_int32), ("r_w", C.c_int32),
         ("tgt_lo", C.c_int32 * 3), ("tgt_hi", C.c_int32 * 3), ("ndir", C.c_double * 3),
         ("phi", C.c_double), ("ckpt_k", C.c_int32), ("body_tape", C.c_int32),
+        ("scheme", C.c_int32),
     ]
 
 
@@ -105,6 +106,7 @@ def to_struct(p) -> LksProblem:
     s.phi = p.phi
     s.ckpt_k = p.ckpt_k
     s.body_tape = p.body_tape
+    s.scheme = p.scheme
     return s
 
 

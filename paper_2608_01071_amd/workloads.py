@@ -54,6 +54,7 @@ class Problem:
     precision: int = 1                        # GPU state: 0 = FP32, 1 = FP64
     ckpt_k: int = 0                           # checkpoint interval (0 = nt)
     body_tape: int = 0                        # body fields kept: 1 all steps, -1 a segment, 0 auto
+    scheme: int = 0                           # reverse sweep: 0 exact adjoint, 1 the paper's ALKS
 
     @property
     def N(self) -> int:

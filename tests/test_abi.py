@@ -46,8 +46,17 @@ def test_plan_validation_and_workspace(L):
     assert nb2.value != nb.value
     L.lks_plan_destroy(h)
     L.lks_plan_destroy(h2)
+    # the ALKS scheme carries the raw first-moment part of the adjoint
+    # velocity in two more [d][N] slots
+    s5 = lks.to_struct(p.replace(scheme=1))
+    h5 = C.c_void_p()
+    nb5 = C.c_size_t()
+    assert L.lks_plan_create(C.byref(s5), C.byref(h5), C.byref(nb5)) == 0
+    assert nb5.value >= nb.value + 2 * p.d * p.N * 8
+    L.lks_plan_destroy(h5)
     bad = [p.replace(d=4), p.replace(n=(64, 3, 1)), p.replace(nt=0), p.replace(r_t=0),
-           p.replace(ckpt_k=500), p.replace(precision=2), p.replace(q=0.0)]
+           p.replace(ckpt_k=500), p.replace(precision=2), p.replace(q=0.0),
+           p.replace(scheme=2), p.replace(scheme=-1)]
     p3, *_ = W.make_3d(16, 4, 5, 2, nu=0.1, seed=0)
     p3 = p3.replace(ckpt_k=5)
     h0 = C.c_void_p()
