@@ -198,6 +198,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the batched 16-instance study")
+    ap.add_argument("--no-alks", action="store_true", help="skip the ALKS reverse-sweep run")
     ap.add_argument("--no-big", action="store_true",
                     help="skip the 256^3 forward-step point (state larger than the LLC)")
     ap.add_argument("--counters", action="store_true",
@@ -286,6 +287,22 @@ def main():
         del plan64
         torch.cuda.empty_cache()
 
+    alks = None
+    if not args.no_alks:
+        # the paper's ALKS reverse sweep on the same workload: its rate, and
+        # how far its gradient lies from the exact one
+        plan_a = lks.Plan(p.replace(scheme=1))
+        run_pass(plan_a, g, c, s, seed)  # warm-up (graph capture)
+        _, ga, tfa, taa = run_pass(plan_a, g, c, s, seed)
+        rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+        alks = {"value": round(N * nt / (tfa + taa) / 1e6, 2), "unit": "MLUPS",
+                "ms_per_pass": round((tfa + taa) * 1e3, 2),
+                "adjoint_ms": round(taa * 1e3, 2),
+                "rel_to_exact_gradient": {k: rel(ga[k].cpu().numpy(), g32[k])
+                                          for k in ("dgamma", "dchi", "dpsi")}}
+        del plan_a
+        torch.cuda.empty_cache()
+
     del plan
     torch.cuda.empty_cache()
     big = None if args.no_big else fwd_step_out_of_cache()
@@ -305,6 +322,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_plain": fp64,
+        "alks": alks,
         "c5_batch": c5,
         "fwd_step_256": big,
         "kernels": kernels,

@@ -387,6 +387,7 @@ AdjArgs adj_args(lks_plan* P, void* ws, int n, int sg, int cur) {
   if (P->alks) {
     a.xin = xadj_slot(P, ws, cur);
     a.xout = xadj_slot(P, ws, 1 - cur);
+    a.si_next = n > 1 ? tab(P, ws, n - 1) : nullptr;
   }
   return a;
 }

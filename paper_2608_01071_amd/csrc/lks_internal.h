@@ -179,9 +179,11 @@ struct AdjArgs {
   // The adjoint velocity state then has two parts: lam holds the whole
   // vector of the adjoint equilibrium, xin its raw first-moment part
   // 3 u~ ([d][N], read on body-box nodes only), on which alone the
-  // Brinkman source acts; xout receives the raw part of step n - 1.
+  // Brinkman source acts; xout receives the raw part of step n - 1 on the
+  // body box of step n - 1 (si_next; nullable: nowhere, no step reads it).
   const void* xin;
   void* xout;
+  const StepInfo* si_next;
 };
 
 int step_blocks(const Geo& g);

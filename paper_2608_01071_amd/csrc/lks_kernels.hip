@@ -96,6 +96,17 @@ __device__ __forceinline__ long long box_index(const Geo& g, const Box& b, int x
   return r[0] + (long long)b.sx * (r[1] + (long long)b.sy * r[2]);
 }
 
+// Whether (wrapped) coordinate v of axis ax lies in [lo, lo + ext) of a
+// step's body box (periodic axes measure the offset modulo n).
+__device__ __forceinline__ bool in_step_box(const Geo& g, const StepInfo* si, int ax, int v) {
+  int r = v - si->lo[ax];
+  if (g.bc[ax] == 0) {
+    r %= g.n[ax];
+    if (r < 0) r += g.n[ax];
+  }
+  return r >= 0 && r < si->ext[ax];
+}
+
 // Step box from the device table (when given).
 __device__ __forceinline__ void apply_step(Box& b, const StepInfo* si) {
   if (!si) return;
@@ -992,9 +1003,12 @@ __device__ __forceinline__ void adj2d_tile(const Geo& g, AdjArgs a, int bid) {
   lp[N + i] = bx;
   lp[2 * N + i] = by;
   if constexpr (ALK) {
-    R* xo = (R*)a.xout;
-    xo[i] = R(3) * sm[1][c];
-    xo[N + i] = R(3) * sm[2][c];
+    // raw first-moment part, read by the next step on its body box only
+    if (a.si_next && in_step_box(g, a.si_next, 0, gx) && in_step_box(g, a.si_next, 1, gy)) {
+      R* xo = (R*)a.xout;
+      xo[i] = R(3) * sm[1][c];
+      xo[N + i] = R(3) * sm[2][c];
+    }
   }
 }
 
@@ -1097,6 +1111,9 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
   const int ocol = own ? gx + g.n[0] * gy : 0;
   const unsigned ovo = (unsigned)ocol * es;
   const unsigned lvo = (unsigned)lofs * es;
+  // ALKS: the raw first-moment part is stored on the next step's body box
+  const bool xcol = ALK && own && a.si_next && in_step_box(g, a.si_next, 0, gx) &&
+                    in_step_box(g, a.si_next, 1, gy);
 
   // Register buffers of two planes in flight.  The per-lane conditional
   // loads of a plane are issued first and the unconditional ones (clamped
@@ -1369,10 +1386,12 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
       bst<R>(by, rlp, ovo, so + 2u * fb);
       bst<R>(bz, rlp, ovo, so + 3u * fb);
       if constexpr (ALK) {
-        const __amdgpu_buffer_rsrc_t rxo = brsrc(a.xout, 3u * fb);
-        bst<R>(R(3) * Mp[1], rxo, ovo, so);
-        bst<R>(R(3) * Mp[2], rxo, ovo, so + fb);
-        bst<R>(R(3) * Mp[3], rxo, ovo, so + 2u * fb);
+        if (xcol && in_step_box(g, a.si_next, 2, zo)) {
+          const __amdgpu_buffer_rsrc_t rxo = brsrc(a.xout, 3u * fb);
+          bst<R>(R(3) * Mp[1], rxo, ovo, so);
+          bst<R>(R(3) * Mp[2], rxo, ovo, so + fb);
+          bst<R>(R(3) * Mp[3], rxo, ovo, so + 2u * fb);
+        }
       }
     }
     zprev[0] = Mp[8];
