@@ -718,6 +718,114 @@ struct Oracle {
     sensitivities(gamma, kref_bar.data(), mbar.data(), dg, dchi, dpsi);
   }
 
+  // ------------------------------------------ design prelude (Sec. 3.1, 2.6)
+  // Eq. filtering on the inner design grid (gamma is [m2][m1][m0], design
+  // spacing 1): cone weights (R - |x_i - x_j|) / R for |x_i - x_j| < R,
+  // normalised by their sum at each point; points outside the grid are left
+  // out of both sums.
+  template <class F>
+  void design_stencil(double R, const int i[3], F fn) const {
+    const int r = (int)std::floor(R);
+    const int rz = d == 3 ? r : 0;
+    for (int dz = -rz; dz <= rz; ++dz)
+      for (int dy = -r; dy <= r; ++dy)
+        for (int dx = -r; dx <= r; ++dx) {
+          const int j[3] = {i[0] + dx, i[1] + dy, i[2] + dz};
+          bool in = true;
+          for (int a = 0; a < d; ++a) in = in && j[a] >= 0 && j[a] < P.m[a];
+          if (!in) continue;
+          const double w = (R - std::sqrt((double)(dx * dx + dy * dy + dz * dz))) / R;
+          if (w <= 0.0) continue;
+          fn(j[0] + (long)P.m[0] * (j[1] + (long)(d >= 2 ? P.m[1] : 1) * j[2]), w);
+        }
+  }
+  void inner_coords(long k, int i[3]) const {
+    i[0] = (int)(k % P.m[0]);
+    i[1] = (int)((k / P.m[0]) % P.m[1]);
+    i[2] = d == 3 ? (int)(k / ((long)P.m[0] * P.m[1])) : 0;
+  }
+  void design_filter(const T* g, double R, T* out) const {
+    for (long k = 0; k < Min; ++k) {
+      int i[3];
+      inner_coords(k, i);
+      T acc = 0.0;
+      double W = 0.0;
+      design_stencil(R, i, [&](long j, double w) {
+        acc += w * g[j];
+        W += w;
+      });
+      out[k] = acc / W;
+    }
+  }
+  // Eq. projection (beta <= 0: the identity, its limit as beta -> 0).
+  T project(const T& x, double beta, double eta) const {
+    if (beta <= 0.0) return x;
+    const double den = std::tanh(beta * eta) + std::tanh(beta * (1.0 - eta));
+    return (std::tanh(beta * eta) + std::tanh(beta * (x - eta))) / den;
+  }
+  T project_d(const T& x, double beta, double eta) const {
+    if (beta <= 0.0) return T(1.0);
+    const double den = std::tanh(beta * eta) + std::tanh(beta * (1.0 - eta));
+    const T c = std::cosh(beta * (x - eta));
+    return beta / (c * c) / den;
+  }
+  void design_prelude(const T* g, double R, double beta, double eta, T* phys) const {
+    std::vector<T> ft(Min);
+    design_filter(g, R, ft.data());
+    for (long k = 0; k < Min; ++k) phys[k] = project(ft[k], beta, eta);
+  }
+  // Chain rule back through the projection and the filter: the transposed
+  // Jacobian, scattered from each filtered point to its stencil.
+  void design_prelude_adjoint(const T* g, double R, double beta, double eta, const T* gbar,
+                              T* out) const {
+    std::vector<T> ft(Min);
+    design_filter(g, R, ft.data());
+    for (long k = 0; k < Min; ++k) out[k] = 0.0;
+    for (long k = 0; k < Min; ++k) {
+      int i[3];
+      inner_coords(k, i);
+      double W = 0.0;
+      design_stencil(R, i, [&](long, double w) { W += w; });
+      const T h = project_d(ft[k], beta, eta) * gbar[k];
+      design_stencil(R, i, [&](long j, double w) { out[j] += (w / W) * h; });
+    }
+  }
+  // Eqs. constraint1 .. constraint3.  G1, G2 on the projected density (the
+  // field the flow sees), over the M inner design points; G3 from the motion
+  // prelude's omega, summed over the steps 1..nt (dt = 1) with |omega|.
+  void constraints(const T* phys, const T* chi, const T* psi, double vmax, double omax,
+                   double pw, T* G, T* dG1, T* dG2, T* dG3_dpsi) const {
+    T s = 0.0, sf = 0.0;
+    for (long k = 0; k < Min; ++k) {
+      s += phys[k];
+      sf += 1.0 - phys[k];
+    }
+    G[0] = s / (vmax * (double)Min) - 1.0;
+    G[1] = sf / (vmax * (double)Min) - 1.0;
+    for (long k = 0; k < Min; ++k) {
+      if (dG1) dG1[k] = 1.0 / (vmax * (double)Min);
+      if (dG2) dG2[k] = -1.0 / (vmax * (double)Min);
+    }
+    const int nt = P.nt;
+    std::vector<T> mot((size_t)nt * 8);
+    motion(chi, psi, mot.data());
+    T S = 0.0;
+    for (int t = 0; t < nt; ++t) S += std::pow(std::abs(mot[(size_t)t * 8 + 7] / omax), pw);
+    G[2] = std::pow(S, 1.0 / pw) - 1.0;
+    if (dG3_dpsi) {
+      // dG3/domega_n, then the motion prelude's chain rule (D_t^T, bounds,
+      // filter^T) as for the adjoint's motion partials
+      std::vector<T> mbar((size_t)nt * 8, T(0.0)), kb(Mtot, T(0.0)), dg(Min), dchi((size_t)nt * 3);
+      for (int t = 0; t < nt; ++t) {
+        const T om = mot[(size_t)t * 8 + 7];
+        const T a = std::abs(om / omax);
+        const double sg = re(om) < 0.0 ? -1.0 : 1.0;
+        mbar[(size_t)t * 8 + 7] = std::pow(S, 1.0 / pw - 1.0) * std::pow(a, pw - 1.0) * sg / omax;
+      }
+      sensitivities(phys, kb.data(), mbar.data(), dg.data(), dchi.data(), dG3_dpsi);
+    }
+  }
+
   // ------------------------------------------------ ALKS backward (Sec. 2.5)
   // The continuous-adjoint lattice kinetic scheme as the paper states it.
   // Multipliers of one time level: pt [N], ut [d][N], sl [3*3][N] (s~_ab in
@@ -1000,6 +1108,33 @@ int orc_alks_gather(const orc_problem* p, const double* fields_next, const doubl
   std::vector<double> ft;
   o.alks_equilibria(fields_next, nullptr, fields_next + N, fields_next + (1 + d) * N, u_next, ft);
   o.alks_gather(ft, fields_out, fields_out + N, fields_out + (1 + d) * N);
+  return 0;
+}
+
+int orc_design_prelude(const orc_problem* p, const double* gamma, double radius, double beta,
+                       double eta, double* phys) {
+  if (int e = validate(p)) return e;
+  if (!(radius > 0.0)) return -1;
+  Oracle<double>(*p).design_prelude(gamma, radius, beta, eta, phys);
+  return 0;
+}
+
+int orc_design_prelude_adjoint(const orc_problem* p, const double* gamma, double radius,
+                               double beta, double eta, const double* dJ_dphys,
+                               double* dJ_dgamma) {
+  if (int e = validate(p)) return e;
+  if (!(radius > 0.0)) return -1;
+  Oracle<double>(*p).design_prelude_adjoint(gamma, radius, beta, eta, dJ_dphys, dJ_dgamma);
+  return 0;
+}
+
+int orc_constraints(const orc_problem* p, const double* phys, const double* chi,
+                    const double* psi, double vmax, double omega_max, double p_omega,
+                    double* G_out, double* dG1, double* dG2, double* dG3_dpsi) {
+  if (int e = validate(p)) return e;
+  if (!(vmax > 0.0) || !(omega_max > 0.0) || !(p_omega >= 1.0)) return -1;
+  Oracle<double>(*p).constraints(phys, chi, psi, vmax, omega_max, p_omega, G_out, dG1, dG2,
+                                 dG3_dpsi);
   return 0;
 }
 

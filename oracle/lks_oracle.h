@@ -105,6 +105,23 @@ int orc_alks_adjoint(const orc_problem* p, const double* gamma, const double* ch
 int orc_alks_gather(const orc_problem* p, const double* fields_next, const double* u_next,
                     double* fields_out);
 
+/* Design prelude of the optimisation loop (Sec. 3.1, Algorithm 1): the
+ * density filter of radius R (Eq. filtering) on the inner design grid, then
+ * the Heaviside projection (Eq. projection; beta <= 0 means none).
+ * gamma, phys [M]. */
+int orc_design_prelude(const orc_problem* p, const double* gamma, double radius, double beta,
+                       double eta, double* phys);
+/* Its chain rule: dJ/dphys [M] -> dJ/dgamma [M]. */
+int orc_design_prelude_adjoint(const orc_problem* p, const double* gamma, double radius,
+                               double beta, double eta, const double* dJ_dphys,
+                               double* dJ_dgamma);
+/* Constraints (Sec. 2.6, Eqs. constraint1 .. constraint3): G_out = (G1, G2,
+ * G3) and the gradients dG1, dG2 [M] w.r.t. the projected density and
+ * dG3/dpsi [nt] (each nullable). */
+int orc_constraints(const orc_problem* p, const double* phys, const double* chi,
+                    const double* psi, double vmax, double omega_max, double p_omega,
+                    double* G_out, double* dG1, double* dG2, double* dG3_dpsi);
+
 /* Sensitivity epilogue alone: raw accumulators -> dJ/dgamma, dJ/dchi, dJ/dpsi. */
 int orc_sensitivities(const orc_problem* p, const double* gamma, const double* kref_bar,
                       const double* motion_bar, const double* motion, double* dJ_dgamma,

@@ -200,6 +200,35 @@ def alks_gather(p, fields_next, u_next):
     return out
 
 
+def design_prelude(p, gamma, radius, beta, eta):
+    """Density filter and Heaviside projection (Sec. 3.1) on the inner design grid."""
+    out = np.zeros(p.M)
+    _check(lib().orc_design_prelude(C.byref(to_struct(p)), _ptr(_f64(gamma)), C.c_double(radius),
+                                    C.c_double(beta), C.c_double(eta), _ptr(out)),
+           "orc_design_prelude")
+    return out
+
+
+def design_prelude_adjoint(p, gamma, radius, beta, eta, dphys):
+    out = np.zeros(p.M)
+    _check(lib().orc_design_prelude_adjoint(C.byref(to_struct(p)), _ptr(_f64(gamma)),
+                                            C.c_double(radius), C.c_double(beta),
+                                            C.c_double(eta), _ptr(_f64(dphys)), _ptr(out)),
+           "orc_design_prelude_adjoint")
+    return out
+
+
+def constraints(p, phys, chi, psi, vmax, omega_max, p_omega):
+    """(G1, G2, G3) of Sec. 2.6 with dG1, dG2 [M] and dG3/dpsi [nt]."""
+    G = np.zeros(3)
+    d1, d2, d3 = np.zeros(p.M), np.zeros(p.M), np.zeros(p.nt)
+    _check(lib().orc_constraints(C.byref(to_struct(p)), _ptr(_f64(phys)), _ptr(_f64(chi)),
+                                 _ptr(_f64(psi)), C.c_double(vmax), C.c_double(omega_max),
+                                 C.c_double(p_omega), _ptr(G), _ptr(d1), _ptr(d2), _ptr(d3)),
+           "orc_constraints")
+    return G, d1, d2, d3
+
+
 def sensitivities(p, gamma, kref_bar, motion_bar):
     dg = np.zeros(p.M)
     dc = np.zeros(p.nt * 3)
