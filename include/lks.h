@@ -155,6 +155,39 @@ lks_status lks_adjoint(lks_plan* plan, const double* gamma, const double* chi,
                        const void* adj_terminal, void* adj_initial, double* dJ_dgamma,
                        double* dJ_dchi, double* dJ_dpsi, hipStream_t stream);
 
+/* Design prelude of the optimisation loop (Sec. 3.1, Algorithm 1), for a
+ * caller's optimiser: gamma [m2][m1][m0] (the design variables, device)
+ * -> the density filter of radius `radius` (Eq. filtering: cone weights
+ * (R - |x_i - x_j|) / R on the inner design grid, spacing 1, normalised
+ * per point) -> the Heaviside projection with steepness beta and threshold
+ * eta (Eq. projection; beta <= 0 skips it) -> gamma_phys [M] (device), the
+ * field lks_forward takes as gamma.  FP64.  LKS_EINVAL unless
+ * 0 < radius <= 64 and 0 <= eta <= 1. */
+lks_status lks_design_filter(lks_plan* plan, const double* gamma, double radius, double beta,
+                             double eta, double* gamma_phys, hipStream_t stream);
+
+/* Chain rule of lks_design_filter: dJ_dphys [M] (e.g. lks_adjoint's
+ * dJ_dgamma) -> dJ_dgamma [M] w.r.t. the design variables.  work: M
+ * doubles of device scratch owned by the caller. */
+lks_status lks_design_filter_adjoint(lks_plan* plan, const double* gamma, double radius,
+                                     double beta, double eta, const double* dJ_dphys,
+                                     double* work, double* dJ_dgamma, hipStream_t stream);
+
+/* Constraint functionals of Sec. 2.6 and their gradients (device arrays):
+ *   G_out[0] = G1 = sum(gamma_phys) / (vmax M) - 1      (Eq. constraint1)
+ *   G_out[1] = G2 = sum(1 - gamma_phys) / (vmax M) - 1  (Eq. constraint2)
+ *   G_out[2] = G3 = (sum_n |omega_n / omega_max|^p)^(1/p) - 1 over the steps
+ *              n = 1..nt, omega from chi, psi by the motion prelude
+ *              (Eq. constraint3).
+ * dG1, dG2 [M] w.r.t. gamma_phys, dG3_dpsi [nt] (each nullable; G3 does not
+ * depend on chi or gamma).  workspace: the plan's; this call uses scratch
+ * regions of its own and leaves lks_forward's data intact.  LKS_EINVAL
+ * unless vmax > 0, omega_max > 0 and p >= 1. */
+lks_status lks_constraints(lks_plan* plan, void* workspace, const double* gamma_phys,
+                           const double* chi, const double* psi, double vmax, double omega_max,
+                           double p_omega, double* G_out, double* dG1, double* dG2,
+                           double* dG3_dpsi, hipStream_t stream);
+
 /* Design -> analysis transfer for one time step (Sec. 2.3, Eqs. kappa, u_s):
  * kappa_ref [D2][D1][D0] (state type), motion8 = (xg[3], ug[3], theta, omega)
  * doubles -> kappa [N] and u_s [d][N] (state type).  Wall nodes receive 0.

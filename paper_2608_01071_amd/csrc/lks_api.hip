@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <mutex>
 #include <string>
+#include <cmath>
 #include <vector>
 
 #include "../../include/lks.h"
@@ -134,7 +135,7 @@ struct lks_plan {
   Box bmax;     // strides, volume and launch extents of the body buffers
   // workspace offsets (bytes)
   size_t o_mot, o_tab, o_info, o_kref, o_flags, o_J3, o_seed, o_opart, o_ck, o_pp, o_tape,
-      o_body, o_btape, o_badj, o_lam, o_xadj, o_krefbar, o_mpart, o_mbar, o_den, o_kz, o_geo, total;
+      o_body, o_btape, o_badj, o_lam, o_xadj, o_cmot, o_krefbar, o_mpart, o_mbar, o_den, o_kz, o_geo, total;
   int first_lazy = 1;
   void* fwd_ws = nullptr;
   bool use_graphs = true;
@@ -577,6 +578,8 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   P->o_mpart = take((size_t)g.nt * P->nblk_map * 8 * sizeof(double));
   P->o_mbar = take((size_t)g.nt * 8 * sizeof(double));
   P->o_den = take((size_t)g.nt * 6 * sizeof(double));
+  // lks_constraints: its own motion table and a discarded chi-gradient
+  P->o_cmot = take((size_t)g.nt * 11 * sizeof(double));
   P->o_kz = take(kz_bytes(g, P->bmax.ext[2], P->prec));
   P->o_geo = take(sizeof(Geo));
   P->total = off;
@@ -687,6 +690,44 @@ lks_status lks_sensitivities(lks_plan* P, const double* gamma, const void* ws, d
   if (!P || !ws || !gamma || !dJ_dgamma || !dJ_dchi || !dJ_dpsi)
     return fail(LKS_EINVAL, "null argument");
   return sens(P, gamma, ws, dJ_dgamma, dJ_dchi, dJ_dpsi, s);
+}
+
+lks_status lks_design_filter(lks_plan* P, const double* gamma, double radius, double beta,
+                             double eta, double* gamma_phys, hipStream_t s) {
+  if (!P || !gamma || !gamma_phys) return fail(LKS_EINVAL, "null argument");
+  if (!(radius > 0.0 && radius <= 64.0)) return fail(LKS_EINVAL, "filter radius must be in (0, 64]");
+  if (!(eta >= 0.0 && eta <= 1.0) || !std::isfinite(beta))
+    return fail(LKS_EINVAL, "projection needs 0 <= eta <= 1 and a finite beta");
+  Scope sc("design", s);
+  HIPCHK(launch_design_filter(P->g, gamma, radius, beta, eta, gamma_phys, s));
+  return LKS_OK;
+}
+
+lks_status lks_design_filter_adjoint(lks_plan* P, const double* gamma, double radius, double beta,
+                                     double eta, const double* dJ_dphys, double* work,
+                                     double* dJ_dgamma, hipStream_t s) {
+  if (!P || !gamma || !dJ_dphys || !work || !dJ_dgamma) return fail(LKS_EINVAL, "null argument");
+  if (!(radius > 0.0 && radius <= 64.0)) return fail(LKS_EINVAL, "filter radius must be in (0, 64]");
+  if (!(eta >= 0.0 && eta <= 1.0) || !std::isfinite(beta))
+    return fail(LKS_EINVAL, "projection needs 0 <= eta <= 1 and a finite beta");
+  Scope sc("design", s);
+  HIPCHK(launch_design_filter_adjoint(P->g, gamma, radius, beta, eta, dJ_dphys, work, dJ_dgamma, s));
+  return LKS_OK;
+}
+
+lks_status lks_constraints(lks_plan* P, void* ws, const double* gamma_phys, const double* chi,
+                           const double* psi, double vmax, double omega_max, double p_omega,
+                           double* G_out, double* dG1, double* dG2, double* dG3_dpsi,
+                           hipStream_t s) {
+  if (!P || !ws || !gamma_phys || !chi || !psi || !G_out) return fail(LKS_EINVAL, "null argument");
+  if (!(vmax > 0.0) || !(omega_max > 0.0) || !(p_omega >= 1.0 && std::isfinite(p_omega)))
+    return fail(LKS_EINVAL, "constraints need vmax > 0, omega_max > 0 and 1 <= p finite");
+  double* cm = (double*)wsp(ws, P->o_cmot);
+  Scope sc("constraints", s);
+  HIPCHK(launch_constraints(P->g, gamma_phys, chi, psi, vmax, omega_max, p_omega, G_out, dG1, dG2,
+                            dG3_dpsi, cm, (double*)wsp(ws, P->o_mbar),
+                            (double*)wsp(ws, P->o_den), cm + (size_t)P->g.nt * 8, s));
+  return LKS_OK;
 }
 
 lks_status lks_motion(lks_plan* P, const double* chi, const double* psi, double* motion,

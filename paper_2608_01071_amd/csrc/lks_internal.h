@@ -202,6 +202,15 @@ hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
 hipError_t launch_steps(const Geo& g, const double* mot, StepInfo* tab, int* info, hipStream_t s);
 hipError_t launch_kappa_ref(const Geo& g, int precision, const double* gamma, void* kref,
                             hipStream_t s);
+hipError_t launch_design_filter(const Geo& g, const double* gamma, double radius, double beta,
+                                double eta, double* phys, hipStream_t s);
+hipError_t launch_design_filter_adjoint(const Geo& g, const double* gamma, double radius,
+                                        double beta, double eta, const double* gbar, double* work,
+                                        double* out, hipStream_t s);
+hipError_t launch_constraints(const Geo& g, const double* phys, const double* chi,
+                              const double* psi, double vmax, double omax, double pw,
+                              double* Gout, double* dG1, double* dG2, double* dG3_dpsi, double* mot,
+                              double* mbar, double* den, double* dchi_scratch, hipStream_t s);
 hipError_t launch_motion(const Geo& g, const double* chi, const double* psi, double* mot,
                          hipStream_t s);
 hipError_t launch_boxes(const Geo& g, const double* mot, int* boxes, int* info, hipStream_t s);

@@ -2306,6 +2306,135 @@ __global__ void k_zero(uint32_t* p, long long n) {
   if (i < n) p[i] = 0u;
 }
 
+// ------------------------------------------ design prelude and constraints
+// Optimiser side of the loop (Sec. 3.1, Sec. 2.6), once per design
+// iteration, all in FP64 on the inner design grid (gamma is [m2][m1][m0],
+// design spacing 1).  One thread per design point walks the cone stencil of
+// Eq. filtering: weights (R - |x_i - x_j|) / R for distances below R,
+// restricted to the grid; the filter normalises by their sum at i.
+struct DesignGrid {
+  int m[3], d, r;
+  double R;
+};
+__device__ __forceinline__ void design_point(const DesignGrid& G, long long k, int i[3]) {
+  i[0] = (int)(k % G.m[0]);
+  i[1] = (int)((k / G.m[0]) % G.m[1]);
+  i[2] = (int)(k / ((long long)G.m[0] * G.m[1]));
+}
+// fn(j, w) over the stencil of point i
+template <class F>
+__device__ __forceinline__ void design_walk(const DesignGrid& G, const int i[3], F fn) {
+  const int rz = G.d == 3 ? G.r : 0;
+  const int z0 = max(i[2] - rz, 0), z1 = min(i[2] + rz, G.m[2] - 1);
+  const int y0 = max(i[1] - G.r, 0), y1 = min(i[1] + G.r, G.m[1] - 1);
+  const int x0 = max(i[0] - G.r, 0), x1 = min(i[0] + G.r, G.m[0] - 1);
+  for (int z = z0; z <= z1; ++z)
+    for (int y = y0; y <= y1; ++y) {
+      const int dz = z - i[2], dy = y - i[1];
+      const long long row = (long long)G.m[0] * (y + (long long)G.m[1] * z);
+      for (int x = x0; x <= x1; ++x) {
+        const int dx = x - i[0];
+        const double w = (G.R - sqrt((double)(dx * dx + dy * dy + dz * dz))) / G.R;
+        if (w > 0.0) fn(row + x, w);
+      }
+    }
+}
+// Eq. projection and its derivative (beta <= 0: the identity).
+__device__ __forceinline__ double project(double x, double beta, double eta) {
+  if (beta <= 0.0) return x;
+  const double den = tanh(beta * eta) + tanh(beta * (1.0 - eta));
+  return (tanh(beta * eta) + tanh(beta * (x - eta))) / den;
+}
+__device__ __forceinline__ double project_d(double x, double beta, double eta) {
+  if (beta <= 0.0) return 1.0;
+  const double den = tanh(beta * eta) + tanh(beta * (1.0 - eta));
+  const double c = cosh(beta * (x - eta));
+  return beta / (c * c) / den;
+}
+// phys = P(filter(gamma))
+__global__ void k_design_fwd(DesignGrid G, long long M, const double* gamma, double beta,
+                             double eta, double* phys) {
+  const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  int i[3];
+  design_point(G, k, i);
+  double a = 0.0, W = 0.0;
+  design_walk(G, i, [&](long long j, double w) {
+    a += w * gamma[j];
+    W += w;
+  });
+  phys[k] = project(a / W, beta, eta);
+}
+// Chain rule, first half: h_i = P'(filtered gamma_i) gbar_i / W_i.
+__global__ void k_design_bwd1(DesignGrid G, long long M, const double* gamma, double beta,
+                              double eta, const double* gbar, double* h) {
+  const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  int i[3];
+  design_point(G, k, i);
+  double a = 0.0, W = 0.0;
+  design_walk(G, i, [&](long long j, double w) {
+    a += w * gamma[j];
+    W += w;
+  });
+  h[k] = project_d(a / W, beta, eta) * gbar[k] / W;
+}
+// Second half: dJ/dgamma_j = sum_i w_ij h_i (the weights are symmetric, so
+// the transposed stencil is the same walk).
+__global__ void k_design_bwd2(DesignGrid G, long long M, const double* h, double* out) {
+  const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  int i[3];
+  design_point(G, k, i);
+  double a = 0.0;
+  design_walk(G, i, [&](long long j, double w) { a += w * h[j]; });
+  out[k] = a;
+}
+// Eqs. constraint1, constraint2 on the projected density, fixed-order sum.
+__global__ __launch_bounds__(256) void k_con_volume(long long M, const double* phys, double vmax,
+                                                    double* Gout) {
+  double v[2] = {0.0, 0.0};
+  for (long long k = threadIdx.x; k < M; k += 256) {
+    v[0] += phys[k];
+    v[1] += 1.0 - phys[k];
+  }
+  double tot[2];
+  block_sum<2, 256>(v, tot);
+  if (threadIdx.x == 0) {
+    Gout[0] = tot[0] / (vmax * (double)M) - 1.0;
+    Gout[1] = tot[1] / (vmax * (double)M) - 1.0;
+  }
+}
+__global__ void k_fill(double* p, long long n, double v) {
+  const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+// Eq. constraint3 over the steps (dt = 1), |omega| to the power p; writes
+// G3 and, into the motion-partial table, dG3/domega_n (all other partials 0)
+// for the prelude's chain rule.
+__global__ __launch_bounds__(256) void k_con_omega(Geo g, const double* mot, double omax,
+                                                   double pw, double* Gout, double* mbar) {
+  __shared__ double S_all;
+  double v[1] = {0.0};
+  for (int t = threadIdx.x; t < g.nt; t += 256) v[0] += pow(fabs(mot[t * 8 + 7] / omax), pw);
+  double tot[1];
+  block_sum<1, 256>(v, tot);
+  if (threadIdx.x == 0) {
+    S_all = tot[0];
+    Gout[2] = pow(tot[0], 1.0 / pw) - 1.0;
+  }
+  __syncthreads();
+  const double S = S_all;
+  for (int t = threadIdx.x; t < g.nt; t += 256) {
+    const double om = mot[t * 8 + 7];
+    const double a = fabs(om / omax);
+    const double gb = S > 0.0 ? pow(S, 1.0 / pw - 1.0) * pow(a, pw - 1.0) * (om < 0.0 ? -1.0 : 1.0) / omax
+                              : 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) mbar[t * 8 + q] = q == 7 ? gb : 0.0;
+  }
+}
+
 // ------------------------------------------------------------ launchers
 static dim3 step_grid(const Geo& g) {
   const int bx = (g.n[0] - g.org[0] + TILE_X - 1) / TILE_X;
@@ -2615,6 +2744,61 @@ hipError_t launch_wall_fixup(const Geo& g, int precision, void* st, hipStream_t 
     hipLaunchKernelGGL(k_wall_fixup<float>, grid, dim3(256), 0, s, g, (float*)st);
   else
     hipLaunchKernelGGL(k_wall_fixup<double>, grid, dim3(256), 0, s, g, (double*)st);
+  return hipGetLastError();
+}
+
+static DesignGrid design_grid(const Geo& g, double radius) {
+  DesignGrid G;
+  for (int a = 0; a < 3; ++a) G.m[a] = a < g.d ? g.m[a] : 1;
+  G.d = g.d;
+  G.R = radius;
+  G.r = (int)floor(radius);
+  return G;
+}
+static long long design_points(const Geo& g) {
+  long long M = 1;
+  for (int a = 0; a < g.d; ++a) M *= g.m[a];
+  return M;
+}
+hipError_t launch_design_filter(const Geo& g, const double* gamma, double radius, double beta,
+                                double eta, double* phys, hipStream_t s) {
+  const long long M = design_points(g);
+  hipLaunchKernelGGL(k_design_fwd, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s,
+                     design_grid(g, radius), M, gamma, beta, eta, phys);
+  return hipGetLastError();
+}
+hipError_t launch_design_filter_adjoint(const Geo& g, const double* gamma, double radius,
+                                        double beta, double eta, const double* gbar, double* work,
+                                        double* out, hipStream_t s) {
+  const long long M = design_points(g);
+  const DesignGrid G = design_grid(g, radius);
+  const dim3 grid((unsigned)((M + 255) / 256));
+  hipLaunchKernelGGL(k_design_bwd1, grid, dim3(256), 0, s, G, M, gamma, beta, eta, gbar, work);
+  hipLaunchKernelGGL(k_design_bwd2, grid, dim3(256), 0, s, G, M, (const double*)work, out);
+  return hipGetLastError();
+}
+hipError_t launch_constraints(const Geo& g, const double* phys, const double* chi,
+                              const double* psi, double vmax, double omax, double pw,
+                              double* Gout, double* dG1, double* dG2, double* dG3_dpsi, double* mot,
+                              double* mbar, double* den, double* dchi_scratch, hipStream_t s) {
+  const long long M = design_points(g);
+  hipLaunchKernelGGL(k_con_volume, dim3(1), dim3(256), 0, s, M, phys, vmax, Gout);
+  const dim3 gm((unsigned)((M + 255) / 256));
+  if (dG1) hipLaunchKernelGGL(k_fill, gm, dim3(256), 0, s, dG1, M, 1.0 / (vmax * (double)M));
+  if (dG2) hipLaunchKernelGGL(k_fill, gm, dim3(256), 0, s, dG2, M, -1.0 / (vmax * (double)M));
+  if (hipError_t e = launch_motion(g, chi, psi, mot, s)) return e;
+  hipLaunchKernelGGL(k_con_omega, dim3(1), dim3(256), 0, s, g, (const double*)mot, omax, pw, Gout,
+                     mbar);
+  if (dG3_dpsi) {
+    // the motion prelude's chain rule, as for the adjoint's motion partials
+    double* den_t = den;
+    double* den_w = den + g.nt;
+    double* tot = den_w + g.nt;
+    const dim3 grid((g.nt + 255) / 256, 4);
+    hipLaunchKernelGGL(k_sens_tot, grid, dim3(256), 0, s, g, (const double*)mbar, tot, den_t, den_w);
+    hipLaunchKernelGGL(k_sens_filter, grid, dim3(256), 0, s, g, (const double*)tot,
+                       (const double*)den_t, (const double*)den_w, dchi_scratch, dG3_dpsi);
+  }
   return hipGetLastError();
 }
 

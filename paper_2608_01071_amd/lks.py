@@ -74,6 +74,10 @@ def lib():
                                        C.POINTER(C.c_int64), C.c_int32]
         L.lks_profile_read.restype = C.c_int32
         L.lks_batch_run.argtypes = [C.c_int32] + [_VP] * 11
+        D = C.c_double
+        L.lks_design_filter.argtypes = [_VP, _VP, D, D, D, _VP, _VP]
+        L.lks_design_filter_adjoint.argtypes = [_VP, _VP, D, D, D, _VP, _VP, _VP, _VP]
+        L.lks_constraints.argtypes = [_VP] * 5 + [D, D, D] + [_VP] * 5
         _lib = L
     return _lib
 
@@ -197,6 +201,40 @@ class Plan:
         _check(lib().lks_sensitivities(self.handle, _ptr(g), _ptr(self.workspace), _ptr(dg),
                                        _ptr(dc), _ptr(dp), _stream()))
         return dg, dc.reshape(p.nt, 3), dp
+
+    # ---------------------------------------------------- optimiser side
+    def design_filter(self, gamma, radius: float, beta: float, eta: float):
+        """Density filter and Heaviside projection (Sec. 3.1): gamma -> the
+        projected density that forward() takes."""
+        g = self._f64(gamma)
+        out = torch.empty(self.problem.M, dtype=torch.float64, device=self.device)
+        _check(lib().lks_design_filter(self.handle, _ptr(g), C.c_double(radius), C.c_double(beta),
+                                       C.c_double(eta), _ptr(out), _stream()))
+        return out
+
+    def design_filter_adjoint(self, gamma, radius: float, beta: float, eta: float, dJ_dphys):
+        """Chain rule of design_filter: dJ/d(projected density) -> dJ/dgamma."""
+        g, gb = self._f64(gamma), self._f64(dJ_dphys)
+        work = torch.empty(self.problem.M, dtype=torch.float64, device=self.device)
+        out = torch.empty(self.problem.M, dtype=torch.float64, device=self.device)
+        _check(lib().lks_design_filter_adjoint(self.handle, _ptr(g), C.c_double(radius),
+                                               C.c_double(beta), C.c_double(eta), _ptr(gb),
+                                               _ptr(work), _ptr(out), _stream()))
+        return out
+
+    def constraints(self, gamma_phys, chi, psi, vmax: float, omega_max: float, p_omega: float):
+        """(G1, G2, G3) of Sec. 2.6 and dG1, dG2 (w.r.t. the projected
+        density) and dG3/dpsi."""
+        p = self.problem
+        g, c, s = self._f64(gamma_phys), self._f64(chi), self._f64(psi)
+        G = torch.empty(3, dtype=torch.float64, device=self.device)
+        d1 = torch.empty(p.M, dtype=torch.float64, device=self.device)
+        d2 = torch.empty(p.M, dtype=torch.float64, device=self.device)
+        d3 = torch.empty(p.nt, dtype=torch.float64, device=self.device)
+        _check(lib().lks_constraints(self.handle, _ptr(self.workspace), _ptr(g), _ptr(c), _ptr(s),
+                                     C.c_double(vmax), C.c_double(omega_max), C.c_double(p_omega),
+                                     _ptr(G), _ptr(d1), _ptr(d2), _ptr(d3), _stream()))
+        return G, d1, d2, d3
 
     # ---------------------------------------------------- single stages
     def motion(self, chi, psi):

@@ -30,6 +30,30 @@ def test_exports_every_declared_symbol(L):
         assert hasattr(L, n), f"{n} declared in include/lks.h but not exported"
 
 
+def declared_parameter_counts():
+    src = open(os.path.join(ROOT, "include", "lks.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for name, params in re.findall(r"\b(lks_[a-z_0-9]+)\s*\(([^)]*)\)\s*;", src):
+        params = params.strip()
+        out[name] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_declares_every_argument_type(L):
+    """Every entry point the header declares has its argument types declared
+    in the binding, one per parameter: without them ctypes passes Python
+    ints as 32-bit C ints and truncates device pointers."""
+    counts = declared_parameter_counts()
+    assert set(counts) == set(declared_functions())
+    for name, n in counts.items():
+        at = getattr(L, name).argtypes
+        if n == 0:
+            continue
+        assert at is not None, f"{name}: no argtypes in the binding"
+        assert len(at) == n, f"{name}: {len(at)} argtypes for {n} parameters"
+
+
 def test_plan_validation_and_workspace(L):
     from paper_2608_01071_amd import lks
     p, *_ = W.c1()
@@ -87,6 +111,12 @@ def test_null_arguments_rejected_before_any_launch(L):
     assert L.lks_plan_create(C.byref(lks.to_struct(p)), C.byref(h), C.byref(nb)) == 0
     assert L.lks_forward(h, None, None, None, None, None, None, None, None) == lks.LKS_EINVAL
     assert L.lks_adjoint(h, *([None] * 11)) == lks.LKS_EINVAL
+    one = C.c_double(1.0)
+    assert L.lks_design_filter(h, None, one, one, C.c_double(0.5), None, None) == lks.LKS_EINVAL
+    assert L.lks_design_filter_adjoint(h, None, one, one, C.c_double(0.5), None, None, None,
+                                       None) == lks.LKS_EINVAL
+    assert L.lks_constraints(h, None, None, None, None, one, one, one, None, None, None, None,
+                             None) == lks.LKS_EINVAL
     assert L.lks_step(h, None, None, None, None, None) == lks.LKS_EINVAL
     L.lks_plan_destroy(h)
 
