@@ -161,6 +161,32 @@ def fwd_step_out_of_cache(nside: int = 256, nt: int = 12):
             "mlups": round(p.N / avg_s / 1e6, 1)}
 
 
+def design_side(plan, g, c, s, reps: int = 20):
+    """The optimiser-side calls once per design iteration on the workload's
+    design grid: filter + projection (radius 4.8, beta 8, eta 0.5), their
+    chain rule, and the three constraints with gradients; event-timed on the
+    stream they run on, averaged over `reps` calls."""
+    import torch
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    gb = torch.ones_like(g)
+    out = {"design_points": int(g.numel()), "radius": 4.8, "beta": 8.0, "eta": 0.5}
+    calls = {
+        "filter_us": lambda: plan.design_filter(g, 4.8, 8.0, 0.5),
+        "chain_rule_us": lambda: plan.design_filter_adjoint(g, 4.8, 8.0, 0.5, gb),
+        "constraints_us": lambda: plan.constraints(g, c, s, 0.8, 1e-3, 16.0),
+    }
+    for k, fn in calls.items():
+        fn()
+        a, b = ev(), ev()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        out[k] = round(a.elapsed_time(b) * 1e3 / reps, 2)
+    return out
+
+
 def run_pass(plan, g, c, s, seed):
     import torch
     t0 = time.perf_counter()
@@ -199,6 +225,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the batched 16-instance study")
     ap.add_argument("--no-alks", action="store_true", help="skip the ALKS reverse-sweep run")
+    ap.add_argument("--no-design", action="store_true",
+                    help="skip timing the design prelude and constraints")
     ap.add_argument("--no-big", action="store_true",
                     help="skip the 256^3 forward-step point (state larger than the LLC)")
     ap.add_argument("--counters", action="store_true",
@@ -303,6 +331,8 @@ def main():
         del plan_a
         torch.cuda.empty_cache()
 
+    design = None if args.no_design else design_side(plan, g, c, s)
+
     del plan
     torch.cuda.empty_cache()
     big = None if args.no_big else fwd_step_out_of_cache()
@@ -323,6 +353,7 @@ def main():
         "cpu_baseline": cpu,
         "fp64_plain": fp64,
         "alks": alks,
+        "design_side": design,
         "c5_batch": c5,
         "fwd_step_256": big,
         "kernels": kernels,

@@ -529,18 +529,27 @@ def test_c4_full_size_map_and_step(orc, c4_full):
     assert relerr(cpu(mbm), rmbm) < 1e-4
 
 
-def test_c4_full_size_forward_adjoint_first_steps(orc, c4_full):
-    """Forward + adjoint through lks_forward / lks_adjoint on the full grid for
-    the run's first two steps (checkpoint every step), against the oracle."""
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_c4_full_size_forward_adjoint_first_steps(orc, c4_full, scheme):
+    """Forward + reverse sweep (exact adjoint, and the ALKS) through
+    lks_forward / lks_adjoint on the full FP32 grid for the run's first two
+    steps (checkpoint every step), against the oracle.  A random start state
+    and a target over the whole interior make J and all three gradients
+    depend on the body within two steps."""
     p, gamma, chi, psi, _, _ = c4_full
-    p2 = p.replace(nt=2, ckpt_k=1)
+    p2 = p.replace(nt=2, ckpt_k=1, scheme=scheme, tgt_lo=(1, 1, 0), tgt_hi=(127, 127, 128))
+    s0 = rand_state(p2, 61, amp=0.02)
     plan = lk().Plan(p2)
-    J3, _ = plan.forward(gamma, chi[:2], psi[:2])
+    J3, _ = plan.forward(gamma, chi[:2], psi[:2], state0=gpu_state(s0, p2))
     g = plan.adjoint(gamma, chi[:2], psi[:2])
-    ref = orc.forward(p2, gamma, chi[:2], psi[:2], want_final=False)
-    adj = orc.adjoint(p2, gamma, chi[:2], psi[:2])
+    ref = orc.forward(p2, gamma, chi[:2], psi[:2], state0=s0, want_final=False)
+    if scheme == 0:
+        adj = orc.adjoint(p2, gamma, chi[:2], psi[:2], state0=s0)
+    else:
+        adj = orc.alks_adjoint(p2, gamma, chi[:2], psi[:2], state0=s0)
     assert abs(cpu(J3)[0] - ref["J"]) <= 1e-5 * abs(ref["J"])
     for k in ("dgamma", "dchi", "dpsi"):
+        assert np.linalg.norm(adj[k]) > 0, k
         assert l2err(cpu(g[k]), adj[k]) < 1e-3, k
 
 
