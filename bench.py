@@ -207,7 +207,15 @@ def cpu_baseline(nt_sample: int):
     t0 = time.perf_counter()
     O.adjoint(p, gamma, chi, psi)           # includes its own forward march
     dt = time.perf_counter() - t0
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                         model)
+    except OSError:
+        pass
     return {"value": p.N * nt_sample / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "host": f"{model}, {os.cpu_count()} logical CPUs visible",
             "sample": f"D3Q15 128^3, 64^3 design, first {nt_sample} of 5000 steps, "
                       f"forward + discrete adjoint + sensitivities, FP64, single thread "
                       f"({dt:.1f} s)"}

@@ -1,5 +1,6 @@
-// lks_kernels.hip -- gfx950 kernels of the LKS + Brinkman forward march and its
-// exact discrete adjoint (Tanabe, Yaji, Ushijima, Secs. 2.2-2.6).
+// lks_kernels.hip -- gfx950 kernels of the LKS + Brinkman forward march, its
+// exact discrete adjoint and the paper's ALKS reverse sweep, and the
+// optimiser-side design prelude (Tanabe, Yaji, Ushijima, Secs. 2.2-2.6, 3.1).
 //
 // Data layout: analysis fields are SoA planes [d+1][N] (x fastest); the
 // pressure plane holds p - 1/3, which keeps the 1/3 offset out of every
@@ -16,7 +17,10 @@
 //   k_adj2d / k_adj3d   exact transpose of one step (objective seed, wall
 //                       rule, Brinkman correction, gather, equilibrium,
 //                       velocity gradient), emitting dJ/dkappa and dJ/du_s
-//                       on the body box.
+//                       on the body box.  The ALK instantiations run the
+//                       ALKS of Sec. 2.5 instead: the same adjoint
+//                       equilibrium, with the seed and Brinkman sources on
+//                       the raw first moment only.
 //   k_map2d / k_map3d   per-step rigid transform and cosine-kernel transfer
 //                       design grid -> analysis box (deterministic gather).
 //   k_mapadj            transpose of the transfer per design point:
@@ -25,6 +29,9 @@
 //   prelude / epilogue  temporal filter, bounds, time differences, box and
 //                       domain check, kappa_ref, objective finalisation and
 //                       the sensitivity chain rule.
+//   k_design_* k_con_*  once per design iteration: density filter and
+//                       Heaviside projection with their chain rule, and the
+//                       constraint functionals G1-G3 (Sec. 3.1, Sec. 2.6).
 #include <math.h>
 #include <string.h>
 
@@ -1125,7 +1132,7 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
     R un[3];      // u^n of the slot node (target or owned body node)
     R bk, bu[3];  // body fields of the slot node
     R up[3];      // own column u^(n-1), output plane zp - 2
-    R x[ALK ? 3 : 1];  // ALKS: raw first-moment part of the slot node (body box)
+    int xo;       // ALKS: node offset of the slot node (its raw moment is read at commit)
     int bi;       // body-box index of the slot node, -1 outside
     bool tg, bown;
   };
@@ -1164,15 +1171,7 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
       B.bu[1] = bup[B.bi + bvol];
       B.bu[2] = bup[B.bi + 2 * bvol];
     }
-    if constexpr (ALK) {
-      B.x[0] = B.x[1] = B.x[2] = R(0);
-      if (B.bi >= 0) {
-        const R* xp = (const R*)a.xin + NP * zw + lofs;
-        B.x[0] = xp[0];
-        B.x[1] = xp[N];
-        B.x[2] = xp[2 * N];
-      }
-    }
+    if constexpr (ALK) B.xo = NP * zw + lofs;
     int zo = zp - 2;
     const bool zown = zo >= z0 && zo < z1;
     const unsigned uso = (unsigned)(zown ? NP * zo : 0) * es;
@@ -1208,10 +1207,15 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
       // the part the Brinkman correction acts on: all of it, or (ALKS) the
       // raw first-moment part with the seed
       R x0 = ub0, x1 = ub1, x2 = ub2;
+      R X0 = R(0), X1 = R(0), X2 = R(0);
       if constexpr (ALK) {
-        x0 = B.x[0] + s0;
-        x1 = B.x[1] + s1;
-        x2 = B.x[2] + s2;
+        const R* xp = (const R*)a.xin + B.xo;
+        X0 = xp[0];
+        X1 = xp[N];
+        X2 = xp[2 * N];
+        x0 = X0 + s0;
+        x1 = X1 + s1;
+        x2 = X2 + s2;
       }
       if (B.bown) {
         const R kb = x0 * (B.bu[0] - B.un[0]) + x1 * (B.bu[1] - B.un[1]) +
@@ -1222,9 +1226,9 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
         bubar[B.bi + 2 * bvol] = kk * x2 * inv;
       }
       if constexpr (ALK) {
-        ub0 = x0 * inv + (ub0 - B.x[0]);
-        ub1 = x1 * inv + (ub1 - B.x[1]);
-        ub2 = x2 * inv + (ub2 - B.x[2]);
+        ub0 = x0 * inv + (ub0 - X0);
+        ub1 = x1 * inv + (ub1 - X1);
+        ub2 = x2 * inv + (ub2 - X2);
       } else {
         ub0 *= inv;
         ub1 *= inv;
