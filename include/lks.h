@@ -180,9 +180,11 @@ lks_status lks_design_filter_adjoint(lks_plan* plan, const double* gamma, double
  *              n = 1..nt, omega from chi, psi by the motion prelude
  *              (Eq. constraint3).
  * dG1, dG2 [M] w.r.t. gamma_phys, dG3_dpsi [nt] (each nullable; G3 does not
- * depend on chi or gamma).  workspace: the plan's; this call uses scratch
- * regions of its own and leaves lks_forward's data intact.  LKS_EINVAL
- * unless vmax > 0, omega_max > 0 and p >= 1. */
+ * depend on chi or gamma).  workspace: the plan's; this call writes only a
+ * motion table of its own and the epilogue's scratch (which every
+ * lks_sensitivities call rebuilds), so what lks_forward and lks_adjoint
+ * leave for later calls stays intact.  LKS_EINVAL unless vmax > 0,
+ * omega_max > 0 and p >= 1. */
 lks_status lks_constraints(lks_plan* plan, void* workspace, const double* gamma_phys,
                            const double* chi, const double* psi, double vmax, double omega_max,
                            double p_omega, double* G_out, double* dG1, double* dG2,
@@ -226,7 +228,8 @@ lks_status lks_step(lks_plan* plan, const void* state_in, const void* kappa, con
                     void* state_out, hipStream_t stream);
 
 /* Transpose of lks_step: lam = dJ/d(state_out) -> lam_prev = dJ/d(state_in),
- * kbar = dJ/dkappa [N], usbar = dJ/du_s [d][N] (state type). */
+ * kbar = dJ/dkappa [N], usbar = dJ/du_s [d][N] (state type).  Always the
+ * exact transpose, whatever the plan's scheme. */
 lks_status lks_step_adjoint(lks_plan* plan, const void* state_in, const void* state_out,
                             const void* kappa, const void* u_s, const void* lam,
                             void* lam_prev, void* kbar, void* usbar, hipStream_t stream);

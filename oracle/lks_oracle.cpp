@@ -816,7 +816,8 @@ struct Oracle {
       // dG3/domega_n, then the motion prelude's chain rule (D_t^T, bounds,
       // filter^T) as for the adjoint's motion partials
       std::vector<T> mbar((size_t)nt * 8, T(0.0)), kb(Mtot, T(0.0)), dg(Min), dchi((size_t)nt * 3);
-      for (int t = 0; t < nt; ++t) {
+      // the p-norm is not differentiable where every omega is 0: take 0 there
+      for (int t = 0; t < nt && re(S) > 0.0; ++t) {
         const T om = mot[(size_t)t * 8 + 7];
         const T a = std::abs(om / omax);
         const double sg = re(om) < 0.0 ? -1.0 : 1.0;

@@ -54,6 +54,20 @@ def test_constraints_match_oracle(orc, name):
         assert relerr(cpu(d3), r3) < 1e-12
 
 
+def test_constraints_without_rotation(orc):
+    """psi constant with the identity filter: omega = 0 exactly, G3 = -1
+    and dG3/dpsi = 0 on both sides."""
+    p = design_probs()["2d"].replace(r_w=1)
+    plan = lk().Plan(p)
+    _, chi, _ = rand_inputs(p, 5)
+    psi = np.full(p.nt, 0.4)
+    phys = np.full(p.M, 0.5)
+    G, _, _, d3 = plan.constraints(phys, chi, psi, 0.8, 1e-3, 16.0)
+    Gr, _, _, r3 = orc.constraints(p, phys, chi, psi, 0.8, 1e-3, 16.0)
+    assert cpu(G)[2] == -1.0 and Gr[2] == -1.0
+    assert np.array_equal(cpu(d3), r3)
+
+
 def test_constraints_leave_the_forward_data_intact():
     """lks_constraints between lks_forward and lks_adjoint, with another
     motion, changes nothing the adjoint reads."""

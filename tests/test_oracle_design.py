@@ -161,3 +161,14 @@ def test_angular_velocity_constraint_closed_form_and_gradient(orc):
         fd = (orc.constraints(p, phys, chi, pp, 0.8, 5e-3, 8.0)[0][2]
               - orc.constraints(p, phys, chi, pm, 0.8, 5e-3, 8.0)[0][2]) / (2 * h)
         assert abs(fd - d3[t]) < 1e-7 * max(abs(fd), 1e-3), (t, fd, d3[t])
+
+
+def test_angular_velocity_constraint_without_rotation(orc):
+    """psi constant with the identity filter (R_w = 1): theta is constant,
+    omega is exactly 0 at every step, G3 = -1, and the gradient (the p-norm
+    has none at 0) is taken as 0."""
+    p = design_problem(2).replace(nt=15, r_w=1)
+    chi = np.full((p.nt, 3), 0.5)
+    G, _, _, d3 = orc.constraints(p, np.full(p.M, 0.5), chi, np.full(p.nt, 0.4), 0.8, 1e-3, 16.0)
+    assert G[2] == -1.0
+    assert np.array_equal(d3, np.zeros(p.nt))
