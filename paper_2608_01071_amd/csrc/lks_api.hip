@@ -135,7 +135,7 @@ struct lks_plan {
   Box bmax;     // strides, volume and launch extents of the body buffers
   // workspace offsets (bytes)
   size_t o_mot, o_tab, o_info, o_kref, o_flags, o_J3, o_seed, o_opart, o_ck, o_pp, o_tape,
-      o_body, o_btape, o_badj, o_lam, o_xadj, o_cmot, o_krefbar, o_mpart, o_mbar, o_den, o_kz, o_geo, total;
+      o_body, o_btape, o_badj, o_lam, o_xadj, o_cmot, o_badjt, o_kpart, o_krefbar, o_mpart, o_mbar, o_den, o_kz, o_geo, total;
   int first_lazy = 1;
   void* fwd_ws = nullptr;
   bool use_graphs = true;
@@ -257,6 +257,8 @@ void* xadj_slot(lks_plan* P, void* ws, int j) {
   return wsp(ws, P->o_xadj) + (size_t)j * P->g.d * P->g.N * P->es;
 }
 size_t body_bytes(const lks_plan* P) { return (size_t)(1 + P->g.d) * P->bmax.vol * P->es; }
+// Body adjoint (dJ/dkappa, dJ/du_s on the box) of segment step j.
+void* badj_slot(lks_plan* P, void* ws, int j) { return wsp(ws, P->o_badjt) + (size_t)j * body_bytes(P); }
 void* btape_slot(lks_plan* P, void* ws, int j) {
   return wsp(ws, P->o_btape) + (size_t)j * body_bytes(P);
 }
@@ -342,6 +344,10 @@ lks_status forward_loop(lks_plan* P, void* ws, hipStream_t s) {
   HIPCHK(launch_zero(wsp(ws, P->o_flags), 64 * sizeof(int), s));
   HIPCHK(launch_zero(wsp(ws, P->o_opart), (size_t)P->nblk_step * 2 * sizeof(double), s));
   const void* in = ck_slot(P, ws, 0);
+  // Each step's map runs right before its step, which then reads the body
+  // fields from cache.  (Mapping every step up front in a few wide launches
+  // costs as much per step: the map is bound by its stores, not by how well
+  // one step fills the GPU.)
   for (int n = 1; n <= P->g.nt; ++n) {
     void* out = (n % P->K == 0 && n / P->K < P->nck) ? ck_slot(P, ws, n / P->K)
                                                       : pp_slot(P, ws, n & 1);
@@ -423,19 +429,30 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
       if (lks_status e = fwd_step(P, ws, n, in, tape_slot(P, ws, n - nb), body, lazy, 0, s))
         return e;
     }
+    // reverse steps, each keeping its body adjoint in a slot of its own
     for (int n = ne; n >= nb; --n) {
-      const AdjArgs a = adj_args(P, ws, n, sg, cur);
+      AdjArgs a = adj_args(P, ws, n, sg, cur);
+      a.bkbar = badj_slot(P, ws, n - nb);
+      a.bubar = (char*)a.bkbar + P->bmax.vol * P->es;
       {
         Scope sc("adj_step", s, true);
         HIPCHK(launch_adjoint_step(P->g, P->prec, a, s));
       }
-      {
-        const MapAdjArgs m = mapadj_args(P, ws, n);
-        Scope sc("map_adj", s, true);
-        HIPCHK(launch_map_adjoint(P->g, P->prec, m.kref, nullptr, m.si, m.box, m.bkbar, m.bubar,
-                                  m.kref_bar, m.overwrite, m.mpart, s));
-      }
       cur = 1 - cur;
+    }
+    // the segment's map transposes in one launch (one step alone fills the
+    // GPU poorly), then its kappa_ref partials summed in a fixed order
+    {
+      const int cnt = ne - nb + 1;
+      const MapAdjArgs m = mapadj_args(P, ws, nb);
+      double* kp = (double*)wsp(ws, P->o_kpart);
+      void* b0 = badj_slot(P, ws, 0);
+      const StepBatch sb{(long long)(body_bytes(P) / P->es), P->g.Mtot,
+                         (long long)P->nblk_map * 8};
+      Scope sc("map_adj", s, true);
+      HIPCHK(launch_map_adjoint(P->g, P->prec, m.kref, nullptr, m.si, m.box, b0,
+                                (char*)b0 + P->bmax.vol * P->es, kp, 1, m.mpart, s, cnt, sb));
+      HIPCHK(launch_kref_accum(P->g.Mtot, cnt, kp, (double*)wsp(ws, P->o_krefbar), s));
     }
   }
   return LKS_OK;
@@ -570,6 +587,10 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   P->o_body = take(P->full_btape ? 0 : body_bytes(P));
   P->o_btape = take(P->full_btape ? full_tape : (size_t)P->K * body_bytes(P));
   P->o_badj = take(body_bytes(P));
+  // the reverse sweep keeps each segment step's body adjoint and transposes
+  // the segment's maps in one launch, each step's kappa_ref partials apart
+  P->o_badjt = take((size_t)P->K * body_bytes(P));
+  P->o_kpart = take((size_t)P->K * g.Mtot * sizeof(double));
   P->o_lam = take(2 * Sb);
   P->alks = prob->scheme == LKS_ADJ_ALKS;
   // ALKS: raw first-moment part of the adjoint velocity, two slots like lambda
@@ -674,6 +695,7 @@ lks_status lks_adjoint(lks_plan* P, const double* gamma, const double* chi, cons
     HIPCHK(launch_zero(lam_slot(P, ws, 0), Sb, s));
   }
   HIPCHK(launch_zero(wsp(ws, P->o_badj), body_bytes(P), s));
+  HIPCHK(launch_zero(wsp(ws, P->o_krefbar), (size_t)P->g.Mtot * sizeof(double), s));
   // the z-fastest kappa_ref copy may have been reused by a stand-alone map call
   HIPCHK(launch_kref_t(P->g, P->prec, wsp(ws, P->o_kref), wsp(ws, P->o_kz), s));
   if (lks_status e = run_loop(P, P->gadj, ws, P->first_lazy, s,
@@ -980,6 +1002,7 @@ lks_status lks_batch_run(int32_t count, lks_plan* const* plans, const double* co
     HIPCHK(launch_zero(lam_slot(P, ws, 0), (size_t)P->S * P->es, s));
     if (P->alks) HIPCHK(launch_zero(xadj_slot(P, ws, 0), (size_t)P->g.d * P->g.N * P->es, s));
     HIPCHK(launch_zero(wsp(ws, P->o_badj), body_bytes(P), s));
+    HIPCHK(launch_zero(wsp(ws, P->o_krefbar), (size_t)P->g.Mtot * sizeof(double), s));
     HIPCHK(hipMemcpyAsync(wsp(ws, P->o_geo), &P->g, sizeof(Geo), hipMemcpyHostToDevice, s));
   }
   // 2D instances with a common step count, checkpoint interval, precision,

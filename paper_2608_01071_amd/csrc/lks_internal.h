@@ -195,10 +195,21 @@ hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf
                       const double* mot8_host, const StepInfo* si, const Box& box, void* bk,
                       void* bu, int full_grid, hipStream_t s);
 int mapadj_blocks(const Geo& g);
+// Map transposes of consecutive steps in one launch (blockIdx.y = step
+// within the batch): step k reads si[k] and its body adjoint advanced by
+// k * body values, and writes its kappa_ref partials and motion partials
+// advanced by k * kref and k * mpart values.
+struct StepBatch {
+  long long body, kref, mpart;
+};
 hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
                               const double* mot8_host, const StepInfo* si, const Box& box,
                               const void* bkbar, const void* bubar, double* kref_bar, int overwrite,
-                              double* mpart, hipStream_t s);
+                              double* mpart, hipStream_t s, int nsteps = 1,
+                              StepBatch sb = StepBatch{0, 0, 0});
+// kref_bar[k] += part[j * M + k] for j = n - 1 down to 0, one at a time.
+hipError_t launch_kref_accum(long long M, int n, const double* part, double* kref_bar,
+                             hipStream_t s);
 hipError_t launch_steps(const Geo& g, const double* mot, StepInfo* tab, int* info, hipStream_t s);
 hipError_t launch_kappa_ref(const Geo& g, int precision, const double* gamma, void* kref,
                             hipStream_t s);

@@ -1725,7 +1725,16 @@ template <class R, int LCH>
 __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kref, Mot m, Box box,
                                                              const StepInfo* si, const R* bkbar,
                                                              const R* bubar, double* kref_bar,
-                                                             int overwrite, double* mpart) {
+                                                             int overwrite, double* mpart,
+                                                             StepBatch sb) {
+  {
+    const int st = blockIdx.y;  // step within a batch of consecutive steps
+    if (si) si += st;
+    bkbar += st * sb.body;
+    bubar += st * sb.body;
+    kref_bar += st * sb.kref;
+    mpart += st * sb.mpart;
+  }
   apply_step(box, m, si);
   static_assert(MAPADJ_TPC == 4, "a (column, chunk) group is one DPP quad");
   static_assert(LCH % 4 == 0, "levels are finished four at a time, one per quad lane");
@@ -2024,8 +2033,12 @@ template <class R>
 __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj(Geo g, const R* kref, Mot m, Box box,
                                                            const StepInfo* si, const R* bkbar,
                                                            const R* bubar, double* kref_bar,
-                                                           int overwrite, double* mpart) {
-  mapadj_block<R>(g, kref, m, box, si, bkbar, bubar, kref_bar, overwrite, mpart, blockIdx.x);
+                                                           int overwrite, double* mpart,
+                                                           StepBatch sb) {
+  const int st = blockIdx.y;  // step within a batch of consecutive steps
+  if (si) si += st;
+  mapadj_block<R>(g, kref, m, box, si, bkbar + st * sb.body, bubar + st * sb.body,
+                  kref_bar + st * sb.kref, overwrite, mpart + st * sb.mpart, blockIdx.x);
 }
 
 // ----------------------------------------------------------- prelude
@@ -2645,39 +2658,55 @@ int mapadj_blocks(const Geo& g) {
 hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
                               const double* mot8_host, const StepInfo* si, const Box& box,
                               const void* bkbar, const void* bubar, double* kref_bar, int overwrite,
-                              double* mpart, hipStream_t s) {
+                              double* mpart, hipStream_t s, int nsteps, StepBatch sb) {
   Mot m;
   if (mot8_host)
     m = make_mot(mot8_host);
   else
     memset(&m, 0, sizeof m);
-  dim3 grid(mapadj_blocks(g));
+  const dim3 grid(mapadj_blocks(g), nsteps);
   if (g.d == 3) {
     const bool lng = mapadj_lch(g) == MAPADJ_LCH_LONG;
     if (precision == 0) {
       if (lng)
         LKS_LAUNCH((k_mapadj3d<float, MAPADJ_LCH_LONG>), grid, dim3(MAPADJ_THREADS), 0, s, g,
                    (const float*)kref, m, box, si, (const float*)bkbar, (const float*)bubar,
-                   kref_bar, overwrite, mpart);
+                   kref_bar, overwrite, mpart, sb);
       else
         LKS_LAUNCH((k_mapadj3d<float, MAPADJ_LCH>), grid, dim3(MAPADJ_THREADS), 0, s, g,
                    (const float*)kref, m, box, si, (const float*)bkbar, (const float*)bubar,
-                   kref_bar, overwrite, mpart);
+                   kref_bar, overwrite, mpart, sb);
     } else {
       LKS_LAUNCH((k_mapadj3d<double, MAPADJ_LCH>), grid, dim3(MAPADJ_THREADS), 0, s, g,
                  (const double*)kref, m, box, si, (const double*)bkbar, (const double*)bubar,
-                 kref_bar, overwrite, mpart);
+                 kref_bar, overwrite, mpart, sb);
     }
     return hipGetLastError();
   }
   if (precision == 0)
     LKS_LAUNCH(k_mapadj<float>, grid, dim3(MAPADJ_THREADS), 0, s, g, (const float*)kref,
                        m, box, si, (const float*)bkbar, (const float*)bubar, kref_bar, overwrite,
-                       mpart);
+                       mpart, sb);
   else
     LKS_LAUNCH(k_mapadj<double>, grid, dim3(MAPADJ_THREADS), 0, s, g,
                        (const double*)kref, m, box, si, (const double*)bkbar, (const double*)bubar,
-                       kref_bar, overwrite, mpart);
+                       kref_bar, overwrite, mpart, sb);
+  return hipGetLastError();
+}
+
+// The steps' partials join the accumulator one at a time, last step first:
+// the order (and rounding) of a transpose per step run in reverse.
+__global__ void k_kref_accum(long long M, int n, const double* part, double* kref_bar) {
+  const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  double a = kref_bar[k];
+  for (int j = n - 1; j >= 0; --j) a += part[j * M + k];
+  kref_bar[k] = a;
+}
+hipError_t launch_kref_accum(long long M, int n, const double* part, double* kref_bar,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_kref_accum, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, M, n, part,
+                     kref_bar);
   return hipGetLastError();
 }
 
