@@ -944,20 +944,42 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
         HIPCHK(launch_forward_step_batch(prec, fb, s));
       }
     }
+    // reverse steps, each keeping its body adjoint in a slot of its own;
+    // then the segment's map transposes of every instance in one launch, as
+    // in the single-instance sweep (adjoint_loop)
     for (int n = ne; n >= nb; --n) {
       for (int k = 0; k < count; ++k) {
-        ab.a[k] = adj_args(plans[k], ws[k], n, sg, cur);
-        qb.a[k] = mapadj_args(plans[k], ws[k], n);
+        lks_plan* P = plans[k];
+        ab.a[k] = adj_args(P, ws[k], n, sg, cur);
+        ab.a[k].bkbar = badj_slot(P, ws[k], n - nb);
+        ab.a[k].bubar = (char*)ab.a[k].bkbar + P->bmax.vol * P->es;
       }
       {
         Scope sc("adj_step", s, true);
         HIPCHK(launch_adjoint_step_batch(prec, ab, s));
       }
-      {
-        Scope sc("map_adj", s, true);
-        HIPCHK(launch_map_adjoint_batch(prec, qb, s));
-      }
       cur = 1 - cur;
+    }
+    {
+      const int cnt = ne - nb + 1;
+      for (int k = 0; k < count; ++k) {
+        lks_plan* P = plans[k];
+        MapAdjArgs m = mapadj_args(P, ws[k], nb);
+        m.bkbar = badj_slot(P, ws[k], 0);
+        m.bubar = (const char*)m.bkbar + P->bmax.vol * P->es;
+        m.kref_bar = (double*)wsp(ws[k], P->o_kpart);
+        m.overwrite = 1;
+        m.sb = StepBatch{(long long)(body_bytes(P) / P->es), P->g.Mtot,
+                         (long long)P->nblk_map * 8};
+        qb.a[k] = m;
+      }
+      Scope sc("map_adj", s, true);
+      HIPCHK(launch_map_adjoint_batch(prec, qb, s, cnt));
+      for (int k = 0; k < count; ++k) {
+        lks_plan* P = plans[k];
+        HIPCHK(launch_kref_accum(P->g.Mtot, cnt, (const double*)wsp(ws[k], P->o_kpart),
+                                 (double*)wsp(ws[k], P->o_krefbar), s));
+      }
     }
   }
   for (int k = 0; k < count; ++k)

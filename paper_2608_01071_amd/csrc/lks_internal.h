@@ -258,6 +258,7 @@ struct MapAdjArgs {
   double* kref_bar;
   double* mpart;
   int overwrite;
+  StepBatch sb;  // strides between the steps of a launch over several steps
 };
 template <class A>
 struct Batch {
@@ -275,7 +276,8 @@ int map_blocks_2d(const Box& bmax, int* bxn);
 hipError_t launch_forward_step_batch(int precision, const Batch<FwdArgs>& b, hipStream_t s);
 hipError_t launch_adjoint_step_batch(int precision, const Batch<AdjArgs>& b, hipStream_t s);
 hipError_t launch_map_batch(int precision, const Batch<MapArgs>& b, hipStream_t s);
-hipError_t launch_map_adjoint_batch(int precision, const Batch<MapAdjArgs>& b, hipStream_t s);
+hipError_t launch_map_adjoint_batch(int precision, const Batch<MapAdjArgs>& b, hipStream_t s,
+                                    int nsteps = 1);
 __host__ __device__ void body_box(const Geo& g, const double* m8, int* out);
 
 }  // namespace lks

@@ -2518,8 +2518,10 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj_batch(Batch<MapAdjArg
   const MapAdjArgs& a = b.a[k];
   Mot m;
   memset(&m, 0, sizeof m);
-  mapadj_block<R>(g, (const R*)a.kref, m, a.box, a.si, (const R*)a.bkbar, (const R*)a.bubar,
-                  a.kref_bar, a.overwrite, a.mpart, bid);
+  const int st = blockIdx.y;  // step within a batch of consecutive steps
+  mapadj_block<R>(g, (const R*)a.kref, m, a.box, a.si ? a.si + st : nullptr,
+                  (const R*)a.bkbar + st * a.sb.body, (const R*)a.bubar + st * a.sb.body,
+                  a.kref_bar + st * a.sb.kref, a.overwrite, a.mpart + st * a.sb.mpart, bid);
 }
 
 LaunchEvents& launch_events() {
@@ -2889,8 +2891,9 @@ hipError_t launch_map_batch(int precision, const Batch<MapArgs>& b, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_map_adjoint_batch(int precision, const Batch<MapAdjArgs>& b, hipStream_t s) {
-  dim3 grid(b.start[b.count]);
+hipError_t launch_map_adjoint_batch(int precision, const Batch<MapAdjArgs>& b, hipStream_t s,
+                                    int nsteps) {
+  dim3 grid(b.start[b.count], nsteps);
   if (precision == 0)
     LKS_LAUNCH(k_mapadj_batch<float>, grid, dim3(MAPADJ_THREADS), 0, s, b);
   else
