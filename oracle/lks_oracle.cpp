@@ -867,10 +867,17 @@ struct Oracle {
   // copy of p never multiplies the source node's velocity, so the coupling
   // in V keeps the node's own p~.  The forward never gathers into a wall
   // node, so no adjoint leaves one: f~eq is zero there.
+  // cfix (nullable): a given coupling part, V = 3 u~ + cfix, in place of
+  // the one formed from p~, s~ and u (a carried terminal state, below).
   void alks_equilibria(const T* pt, const T* pw, const T* ut, const T* sl, const T* u,
-                       std::vector<T>& ft) const {
+                       std::vector<T>& ft, const T* cfix = nullptr) const {
     std::vector<T> V;
-    alks_vector(pt, ut, sl, u, V);
+    if (cfix) {
+      V.assign((size_t)d * N, T(0.0));
+      for (long i = 0; i < (long)d * N; ++i) V[i] = 3.0 * ut[i] + cfix[i];
+    } else {
+      alks_vector(pt, ut, sl, u, V);
+    }
     ft.assign((size_t)L.Q * N, T(0.0));
     for (long y = 0; y < N; ++y) {
       int x[3];
@@ -908,11 +915,16 @@ struct Oracle {
     }
   }
 
-  // Full ALKS backward.  adj_initial (nullable) receives (-3 p~, -V) of
-  // level 0: the scheme's estimate of dJ/d(state0) in the forward's
-  // variables (the multipliers carry the opposite sign).
+  // Full ALKS backward.  adj_initial (nullable, [2d+1][N]) receives
+  // (-3 p~, -V, -3 u~) of level 0: the scheme's estimate of dJ/d(state0) in
+  // the forward's variables (the multipliers carry the opposite sign),
+  // followed by the raw first moment alone.  adj_terminal (nullable, same
+  // layout) is the state carried from an earlier run's adj_initial for the
+  // periodic approximation (Sec. 3.3): it stands for the gathered moments of
+  // the last level, with its coupling part (-V + 3 u~) taken as given.
   void alks_adjoint(const T* gamma, const T* chi, const T* psi, const T* state0, double dJ,
-                    T* adj_initial, T* dg, T* dchi, T* dpsi, T* kref_bar_out, T* mbar_out) const {
+                    const T* adj_terminal, T* adj_initial, T* dg, T* dchi, T* dpsi,
+                    T* kref_bar_out, T* mbar_out) const {
     const long S = (long)(d + 1) * N;
     const int nt = P.nt;
     std::vector<T> traj((size_t)(nt + 1) * S);
@@ -926,14 +938,27 @@ struct Oracle {
     std::vector<T> pw(N, T(0.0));
     std::vector<T> ft, kbar(N), usbar((size_t)d * N);
     std::vector<T> kref_bar(Mtot, T(0.0)), mbar((size_t)nt * 8, T(0.0));
+    // a carried terminal state: p~ = -pbar / 3, u~* = -X / 3 and the coupling
+    // part -(V - X) of the last level
+    std::vector<T> cfix;
+    if (adj_terminal) {
+      cfix.assign((size_t)d * N, T(0.0));
+      for (long i = 0; i < N; ++i) pt[i] = -adj_terminal[i] / 3.0;
+      for (long i = 0; i < (long)d * N; ++i) {
+        const T Vt = adj_terminal[N + i], X = adj_terminal[(1 + d) * N + i];
+        ut[i] = -X / 3.0;
+        cfix[i] = -(Vt - X);
+      }
+    }
     long NT = (long)nt * target_count();
     for (int t = nt; t >= 1; --t) {
       const T* st = &traj[(size_t)t * S];
       // moments of level t from the adjoint equilibria of level t + 1 (zero
-      // after the last step)
+      // after the last step, or the carried terminal state)
       if (t < nt) {
         alks_equilibria(pt.data(), pw.data(), ut.data(), sl.data(),
-                        &traj[(size_t)(t + 1) * S + N], ft);
+                        &traj[(size_t)(t + 1) * S + N], ft,
+                        (t == nt - 1 && adj_terminal) ? cfix.data() : nullptr);
         alks_gather(ft, pt.data(), ut.data(), sl.data());
       }
       map(kref.data(), &mot[(size_t)(t - 1) * 8], kappa.data(), us.data());
@@ -986,13 +1011,17 @@ struct Oracle {
     if (adj_initial) {
       // level 0: moments gathered from level 1, no sources
       if (nt >= 1) {
-        alks_equilibria(pt.data(), pw.data(), ut.data(), sl.data(), &traj[(size_t)1 * S + N], ft);
+        alks_equilibria(pt.data(), pw.data(), ut.data(), sl.data(), &traj[(size_t)1 * S + N], ft,
+                        (nt == 1 && adj_terminal) ? cfix.data() : nullptr);
         alks_gather(ft, pt.data(), ut.data(), sl.data());
       }
       std::vector<T> V;
       alks_vector(pt.data(), ut.data(), sl.data(), &traj[N], V);
       for (long i = 0; i < N; ++i) adj_initial[i] = -3.0 * pt[i];
-      for (long i = 0; i < (long)d * N; ++i) adj_initial[N + i] = -V[i];
+      for (long i = 0; i < (long)d * N; ++i) {
+        adj_initial[N + i] = -V[i];
+        adj_initial[(1 + d) * N + i] = -3.0 * ut[i];
+      }
     }
     if (kref_bar_out) std::copy(kref_bar.begin(), kref_bar.end(), kref_bar_out);
     if (mbar_out) std::copy(mbar.begin(), mbar.end(), mbar_out);
@@ -1091,12 +1120,12 @@ int orc_adjoint(const orc_problem* p, const double* gamma, const double* chi, co
 }
 
 int orc_alks_adjoint(const orc_problem* p, const double* gamma, const double* chi,
-                     const double* psi, const double* state0, double dJ, double* adj_initial,
-                     double* dJ_dgamma, double* dJ_dchi, double* dJ_dpsi, double* kref_bar,
-                     double* motion_bar) {
+                     const double* psi, const double* state0, double dJ,
+                     const double* adj_terminal, double* adj_initial, double* dJ_dgamma,
+                     double* dJ_dchi, double* dJ_dpsi, double* kref_bar, double* motion_bar) {
   if (int e = validate(p)) return e;
-  Oracle<double>(*p).alks_adjoint(gamma, chi, psi, state0, dJ, adj_initial, dJ_dgamma, dJ_dchi,
-                                  dJ_dpsi, kref_bar, motion_bar);
+  Oracle<double>(*p).alks_adjoint(gamma, chi, psi, state0, dJ, adj_terminal, adj_initial,
+                                  dJ_dgamma, dJ_dchi, dJ_dpsi, kref_bar, motion_bar);
   return 0;
 }
 

@@ -92,12 +92,15 @@ int orc_adjoint(const orc_problem* p, const double* gamma, const double* chi,
 /* Paper-literal ALKS backward (Sec. 2.5): the continuous-adjoint lattice
  * kinetic scheme with the adjoint equilibrium and Eqs. ap_tmp .. as, run from
  * the last step to the first, and the sensitivities of Eqs. dJdgamma, dJdchi,
- * dJdpsi.  Outputs as orc_adjoint; adj_initial (nullable, [d+1][N]) receives
- * the scheme's estimate of dJ/d(state0).  No terminal multipliers. */
+ * dJdpsi.  Outputs as orc_adjoint.  adj_initial (nullable, [2d+1][N]): the
+ * scheme's estimate of dJ/d(state0) ([d+1][N]) followed by the raw first
+ * moment 3 u~ in the forward's sign ([d][N]).  adj_terminal (nullable, same
+ * layout): a state carried from an earlier run's adj_initial (periodic
+ * approximation, Sec. 3.3). */
 int orc_alks_adjoint(const orc_problem* p, const double* gamma, const double* chi,
-                     const double* psi, const double* state0, double dJ, double* adj_initial,
-                     double* dJ_dgamma, double* dJ_dchi, double* dJ_dpsi, double* kref_bar,
-                     double* motion_bar);
+                     const double* psi, const double* state0, double dJ,
+                     const double* adj_terminal, double* adj_initial, double* dJ_dgamma,
+                     double* dJ_dchi, double* dJ_dpsi, double* kref_bar, double* motion_bar);
 
 /* One ALKS level without sources: multipliers (p~ [N], u~ [d][N], s~ [9][N],
  * s~_ab in plane 3a+b) of level t+1 and that level's velocity u [d][N] ->

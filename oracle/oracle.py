@@ -174,9 +174,11 @@ def adjoint(p, gamma, chi, psi, state0=None, dJ=1.0, adj_terminal=None):
             "kref_bar": kb, "motion_bar": mb.reshape(p.nt, 8)}
 
 
-def alks_adjoint(p, gamma, chi, psi, state0=None, dJ=1.0):
-    """Paper-literal ALKS backward (Sec. 2.5); same outputs as adjoint()."""
-    S = (p.d + 1) * p.N
+def alks_adjoint(p, gamma, chi, psi, state0=None, dJ=1.0, adj_terminal=None):
+    """Paper-literal ALKS backward (Sec. 2.5); outputs as adjoint(), with
+    adj_initial [2d+1][N] (dJ/d(state0) estimate, then the raw first moment);
+    adj_terminal: the same layout, carried from an earlier run."""
+    S = (2 * p.d + 1) * p.N
     ai = np.zeros(S)
     dg = np.zeros(p.M)
     dc = np.zeros(p.nt * 3)
@@ -184,8 +186,9 @@ def alks_adjoint(p, gamma, chi, psi, state0=None, dJ=1.0):
     kb = np.zeros(p.Mtot)
     mb = np.zeros(p.nt * 8)
     _check(lib().orc_alks_adjoint(C.byref(to_struct(p)), _ptr(_f64(gamma)), _ptr(_f64(chi)),
-                                  _ptr(_f64(psi)), _ptr(_f64(state0)), C.c_double(dJ), _ptr(ai),
-                                  _ptr(dg), _ptr(dc), _ptr(dp), _ptr(kb), _ptr(mb)),
+                                  _ptr(_f64(psi)), _ptr(_f64(state0)), C.c_double(dJ),
+                                  _ptr(_f64(adj_terminal)), _ptr(ai), _ptr(dg), _ptr(dc),
+                                  _ptr(dp), _ptr(kb), _ptr(mb)),
            "orc_alks_adjoint")
     return {"adj_initial": ai, "dgamma": dg, "dchi": dc.reshape(p.nt, 3), "dpsi": dp,
             "kref_bar": kb, "motion_bar": mb.reshape(p.nt, 8)}
