@@ -145,8 +145,12 @@ lks_status lks_forward(lks_plan* plan, const double* gamma, const double* chi,
  * sensitivities of Eqs. dJdgamma, dJdchi, dJdpsi), which approximates it.
  * dJ: 1 double, the seed (dJ/dJ; usually 1).
  * adj_terminal: adjoint state added at step nt (nullable; periodic
- *   approximation of Sec. 3.3; LKS_EINVAL with the ALKS scheme).
- * adj_initial: receives dJ/d(state0) (nullable; the ALKS gives its estimate).
+ *   approximation of Sec. 3.3).
+ * adj_initial: receives dJ/d(state0) (nullable).
+ *   Both are [d+1][N] (state type) with the exact adjoint.  With the ALKS
+ *   they are [2d+1][N]: the scheme's estimate of dJ/d(state0), then the raw
+ *   first-moment part 3 u~ of its adjoint velocity, so that a run's
+ *   adj_initial can be carried into the next run's adj_terminal.
  * dJ_dgamma [m2][m1][m0], dJ_dchi [nt][3], dJ_dpsi [nt]: gradients of J
  *   (the paper maximises J; these are +grad J).
  * Recomputes each K-step segment from its checkpoint. */

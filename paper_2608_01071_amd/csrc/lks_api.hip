@@ -395,6 +395,7 @@ AdjArgs adj_args(lks_plan* P, void* ws, int n, int sg, int cur) {
     a.xin = xadj_slot(P, ws, cur);
     a.xout = xadj_slot(P, ws, 1 - cur);
     a.si_next = n > 1 ? tab(P, ws, n - 1) : nullptr;
+    a.xall = n == 1;  // the raw part of state 0 goes out with adj_initial
   }
   return a;
 }
@@ -684,11 +685,16 @@ lks_status lks_adjoint(lks_plan* P, const double* gamma, const double* chi, cons
     return fail(LKS_EINVAL, "null argument");
   if (P->fwd_ws != ws)
     return fail(LKS_EINVAL, "lks_adjoint needs a preceding lks_forward on this plan and workspace");
-  if (adj_terminal && P->alks)
-    return fail(LKS_EINVAL, "adj_terminal is not supported with the ALKS scheme");
   const size_t Sb = (size_t)P->S * P->es;
+  const size_t Xb = (size_t)P->g.d * P->g.N * P->es;  // ALKS raw-moment part
   HIPCHK(hipMemcpyAsync(wsp(ws, P->o_seed), dJ, sizeof(double), hipMemcpyDeviceToDevice, s));
-  if (P->alks) HIPCHK(launch_zero(xadj_slot(P, ws, 0), (size_t)P->g.d * P->g.N * P->es, s));
+  if (P->alks) {
+    if (adj_terminal)
+      HIPCHK(hipMemcpyAsync(xadj_slot(P, ws, 0), (const char*)adj_terminal + Sb, Xb,
+                            hipMemcpyDeviceToDevice, s));
+    else
+      HIPCHK(launch_zero(xadj_slot(P, ws, 0), Xb, s));
+  }
   if (adj_terminal) {
     HIPCHK(hipMemcpyAsync(lam_slot(P, ws, 0), adj_terminal, Sb, hipMemcpyDeviceToDevice, s));
   } else {
@@ -702,8 +708,12 @@ lks_status lks_adjoint(lks_plan* P, const double* gamma, const double* chi, cons
                               [&](hipStream_t st) { return adjoint_loop(P, ws, st); }))
     return e;
   const int fin = P->g.nt % 2;  // lambda slot holding dJ/d state0
-  if (adj_initial)
+  if (adj_initial) {
     HIPCHK(hipMemcpyAsync(adj_initial, lam_slot(P, ws, fin), Sb, hipMemcpyDeviceToDevice, s));
+    if (P->alks)
+      HIPCHK(hipMemcpyAsync((char*)adj_initial + Sb, xadj_slot(P, ws, fin), Xb,
+                            hipMemcpyDeviceToDevice, s));
+  }
   return sens(P, gamma, ws, dJ_dgamma, dJ_dchi, dJ_dpsi, s);
 }
 

@@ -184,6 +184,7 @@ struct AdjArgs {
   const void* xin;
   void* xout;
   const StepInfo* si_next;
+  int xall;  // ALKS: store the raw part at every node (the sweep's last step)
 };
 
 int step_blocks(const Geo& g);

@@ -1011,7 +1011,8 @@ __device__ __forceinline__ void adj2d_tile(const Geo& g, AdjArgs a, int bid) {
   lp[2 * N + i] = by;
   if constexpr (ALK) {
     // raw first-moment part, read by the next step on its body box only
-    if (a.si_next && in_step_box(g, a.si_next, 0, gx) && in_step_box(g, a.si_next, 1, gy)) {
+    if (a.xall ||
+        (a.si_next && in_step_box(g, a.si_next, 0, gx) && in_step_box(g, a.si_next, 1, gy))) {
       R* xo = (R*)a.xout;
       xo[i] = R(3) * sm[1][c];
       xo[N + i] = R(3) * sm[2][c];
@@ -1119,8 +1120,9 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
   const unsigned ovo = (unsigned)ocol * es;
   const unsigned lvo = (unsigned)lofs * es;
   // ALKS: the raw first-moment part is stored on the next step's body box
-  const bool xcol = ALK && own && a.si_next && in_step_box(g, a.si_next, 0, gx) &&
-                    in_step_box(g, a.si_next, 1, gy);
+  const bool xcol = ALK && own &&
+                    (a.xall || (a.si_next && in_step_box(g, a.si_next, 0, gx) &&
+                                in_step_box(g, a.si_next, 1, gy)));
 
   // Register buffers of two planes in flight.  The per-lane conditional
   // loads of a plane are issued first and the unconditional ones (clamped
@@ -1390,7 +1392,7 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
       bst<R>(by, rlp, ovo, so + 2u * fb);
       bst<R>(bz, rlp, ovo, so + 3u * fb);
       if constexpr (ALK) {
-        if (xcol && in_step_box(g, a.si_next, 2, zo)) {
+        if (xcol && (a.xall || in_step_box(g, a.si_next, 2, zo))) {
           const __amdgpu_buffer_rsrc_t rxo = brsrc(a.xout, 3u * fb);
           bst<R>(R(3) * Mp[1], rxo, ovo, so);
           bst<R>(R(3) * Mp[2], rxo, ovo, so + fb);

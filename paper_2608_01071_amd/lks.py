@@ -161,6 +161,13 @@ class Plan:
         return torch.as_tensor(a, dtype=self.dtype, device=self.device).contiguous()
 
     @property
+    def adj_state_size(self) -> int:
+        """Values of adj_terminal / adj_initial: the state's with the exact
+        adjoint; with the ALKS also the raw first-moment part ([2d+1][N])."""
+        p = self.problem
+        return (2 * p.d + 1) * p.N if p.scheme == 1 else self.state_size
+
+    @property
     def state_size(self) -> int:
         p = self.problem
         return (p.d + 1) * p.N
@@ -183,7 +190,10 @@ class Plan:
         g, c, s = self._f64(gamma), self._f64(chi), self._f64(psi)
         seed = self._f64([1.0]) if dJ is None else self._f64(dJ).reshape(1)
         at = None if adj_terminal is None else self._st(adj_terminal)
-        ai = torch.empty(self.state_size, dtype=self.dtype, device=self.device) if want_initial else None
+        if at is not None and at.numel() != self.adj_state_size:
+            raise ValueError(f"adj_terminal needs {self.adj_state_size} values")
+        ai = (torch.empty(self.adj_state_size, dtype=self.dtype, device=self.device)
+              if want_initial else None)
         dg = torch.empty(p.M, dtype=torch.float64, device=self.device)
         dc = torch.empty(p.nt * 3, dtype=torch.float64, device=self.device)
         dp = torch.empty(p.nt, dtype=torch.float64, device=self.device)
