@@ -251,8 +251,11 @@ lks_status lks_map_adjoint(lks_plan* plan, const void* kappa_ref, const double* 
 
 /* Runs forward + adjoint for `count` independent problems (a parameter
  * study: the instances may differ in every lks_problem field) as one hipGraph
- * launched on `stream`; each instance is one branch of the graph, so the
- * instances' kernels may run concurrently.
+ * launched on `stream`.  2D instances with a common step count, checkpoint
+ * interval, precision, body-tape mode and adjoint scheme share every launch:
+ * each kernel runs once per step for up to 16 of them, instance k owning a
+ * block range.  Other mixes run as parallel branches of the graph, so their
+ * kernels may run concurrently.
  *   plans, gamma, chi, psi, workspace, J_out, dJ_dgamma, dJ_dchi, dJ_dpsi:
  *     (host) arrays of `count` entries, each entry as for lks_forward /
  *     lks_adjoint of that instance (device pointers, caller-owned).  Plans and
