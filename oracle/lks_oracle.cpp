@@ -549,6 +549,92 @@ struct Oracle {
     }
   }
 
+  // ------------------------------------------------- objective J2 (Sec. 2.6)
+  // Eq. objective2 per step: the force density f(xi) = kappa_ref (u_ref -
+  // u_S_ref) on the design points, u_ref the fluid velocity taken to the
+  // design point by the transfer kernel W, u_S_ref the rigid velocity.  Step
+  // sums: sum f_1 (F_L), u^G_2 sum f_2 (F_D) and omega sum e3 (x_ref - x^G) x f
+  // (T); the normalisations are applied at the end.
+  void j2_sums(const T* kref, const T* mot, const T* u, T& jl, T& jd, T& jt) const {
+    for (long k = 0; k < Mtot; ++k) {
+      int xi[3];
+      design_coords(k, xi);
+      T X[3], U[3];
+      rigid(xi, mot, X, U);
+      T ur[2] = {0.0, 0.0};
+      support(X, [&](long node, const T r[3]) {
+        const T W = wker(r[0]) * wker(r[1]);
+        for (int a = 0; a < 2; ++a) ur[a] += W * u[a * N + node];
+      });
+      const T f0 = kref[k] * (ur[0] - U[0]), f1 = kref[k] * (ur[1] - U[1]);
+      const T v0 = X[0] - mot[0], v1 = X[1] - mot[1];
+      jl += f0;
+      jd += mot[4] * f1;
+      jt += mot[7] * (v0 * f1 - v1 * f0);
+    }
+  }
+  double j2_scale_l() const { return 1.0 / ((double)P.nt * (double)Min); }
+  double j2_scale_d() const { return 1.0 / ((P.xg_max[1] - P.xg_min[1]) * (double)Min); }
+  double j2_scale_t() const { return 1.0 / (2.0 * M_PI * P.l_m * (double)Min); }
+  // dJ2/d(everything the step-t sums depend on), scaled by dJ: the seed on
+  // the fluid velocity (added into ubar [d][N], times `useed`), and the
+  // direct terms into kref_bar and the step's motion partials mbar[8].
+  void j2_adjoint(const T* kref, const T* mot, const T* u, double dJ, T* ubar, double useed,
+                  T* kref_bar, T* mbar) const {
+    const T th = mot[6], om = mot[7];
+    const T c = std::cos(th), s = std::sin(th);
+    const T a0 = j2_scale_l(), a1 = P.w_d * mot[4] * j2_scale_d();
+    const T b = P.w_t * om * j2_scale_t();
+    T sf1 = 0.0, svf = 0.0;
+    for (long k = 0; k < Mtot; ++k) {
+      int xi[3];
+      design_coords(k, xi);
+      T X[3], U[3];
+      rigid(xi, mot, X, U);
+      T ur[2] = {0.0, 0.0}, dur[2][2] = {{0.0, 0.0}, {0.0, 0.0}};  // dur[a][b] = d u_ref_b / dX_a
+      support(X, [&](long node, const T r[3]) {
+        const T w0 = wker(r[0]), w1 = wker(r[1]);
+        const T d0 = -wker_d(r[0]) * w1, d1 = -w0 * wker_d(r[1]);
+        for (int q = 0; q < 2; ++q) {
+          const T uq = u[q * N + node];
+          ur[q] += w0 * w1 * uq;
+          dur[0][q] += d0 * uq;
+          dur[1][q] += d1 * uq;
+        }
+      });
+      const T f0 = kref[k] * (ur[0] - U[0]), f1 = kref[k] * (ur[1] - U[1]);
+      const T v0 = X[0] - mot[0], v1 = X[1] - mot[1];
+      // dJ_t/df
+      const T g0 = a0 - b * v1, g1 = a1 + b * v0;
+      // seed on the fluid velocity: sum_xi W kappa_ref g
+      support(X, [&](long node, const T r[3]) {
+        const T W = wker(r[0]) * wker(r[1]);
+        ubar[node] += useed * dJ * W * kref[k] * g0;
+        ubar[N + node] += useed * dJ * W * kref[k] * g1;
+      });
+      kref_bar[k] += dJ * (g0 * (ur[0] - U[0]) + g1 * (ur[1] - U[1]));
+      const double r1 = xi[0] - xiG[0], r2 = xi[1] - xiG[1];
+      const T dX0 = -s * r1 - c * r2, dX1 = c * r1 - s * r2;            // R' r
+      const T dU0 = om * (-c * r1 + s * r2), dU1 = om * (-s * r1 - c * r2);  // omega R'' r
+      const T Xb0 = dJ * kref[k] * (g0 * dur[0][0] + g1 * dur[0][1]);
+      const T Xb1 = dJ * kref[k] * (g0 * dur[1][0] + g1 * dur[1][1]);
+      const T Ub0 = -dJ * kref[k] * g0, Ub1 = -dJ * kref[k] * g1;
+      mbar[0] += Xb0;
+      mbar[1] += Xb1;
+      mbar[3] += Ub0;
+      mbar[4] += Ub1;
+      // theta: through X (kernel position), U (rigid velocity) and v = R r
+      mbar[6] += Xb0 * dX0 + Xb1 * dX1 + Ub0 * dU0 + Ub1 * dU1 +
+                 dJ * b * (dX0 * f1 - dX1 * f0);
+      mbar[7] += Ub0 * dX0 + Ub1 * dX1;
+      sf1 += f1;
+      svf += v0 * f1 - v1 * f0;
+    }
+    // explicit factors u^G_2 (F_D) and omega (T)
+    mbar[4] += dJ * P.w_d * j2_scale_d() * sf1;
+    mbar[7] += dJ * P.w_t * j2_scale_t() * svf;
+  }
+
   // ------------------------------------------------------------ objective
   long target_count() const {
     long c = 1;
@@ -585,11 +671,16 @@ struct Oracle {
     initial_state(state0, a.data());
     if (traj) std::copy(a.begin(), a.end(), traj);
     T s1 = 0.0, s2 = 0.0;
+    T jl = 0.0, jd = 0.0, jt = 0.0;  // J2 step sums
     for (int t = 1; t <= P.nt; ++t) {
       map(kref.data(), &mot[(size_t)(t - 1) * 8], kappa.data(), us.data());
       step(a.data(), kappa.data(), us.data(), b.data());
       std::swap(a, b);
       if (traj) std::copy(a.begin(), a.end(), traj + (long)t * S);
+      if (P.objective == 1) {
+        j2_sums(kref.data(), &mot[(size_t)(t - 1) * 8], a.data() + N, jl, jd, jt);
+        continue;
+      }
       for (long xn = 0; xn < N; ++xn) {
         int x[3];
         coords(xn, x);
@@ -609,6 +700,13 @@ struct Oracle {
     J3[0] = E - P.phi * V;
     J3[1] = E;
     J3[2] = V;
+    if (P.objective == 1) {
+      // Eq. objective2: J2 = F_L + w_D F_D + w_T T
+      const T FL = jl * j2_scale_l(), FD = jd * j2_scale_d(), TT = jt * j2_scale_t();
+      J3[0] = FL + P.w_d * FD + P.w_t * TT;
+      J3[1] = FL;
+      J3[2] = FD;
+    }
     if (state_final) std::copy(a.begin(), a.end(), state_final);
   }
 
@@ -694,7 +792,13 @@ struct Oracle {
     long NT = (long)nt * target_count();
     for (int t = nt; t >= 1; --t) {
       const T* st = &traj[(size_t)t * S];
-      if (NT > 0) {
+      // J2: seed now, motion partials after the map transpose (which writes
+      // the step's row)
+      T j2m[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      if (P.objective == 1)
+        j2_adjoint(kref.data(), &mot[(size_t)(t - 1) * 8], st + N, dJ, lam.data() + N, 1.0,
+                   kref_bar.data(), j2m);
+      if (NT > 0 && P.objective != 1) {
         for (long xn = 0; xn < N; ++xn) {
           int x[3];
           coords(xn, x);
@@ -710,6 +814,7 @@ struct Oracle {
                    lprev.data(), kbar.data(), usbar.data());
       map_adjoint(kref.data(), &mot[(size_t)(t - 1) * 8], kbar.data(), usbar.data(),
                   kref_bar.data(), &mbar[(size_t)(t - 1) * 8]);
+      for (int q = 0; q < 8; ++q) mbar[(size_t)(t - 1) * 8 + q] += j2m[q];
       std::swap(lam, lprev);
     }
     if (adj_initial) std::copy(lam.begin(), lam.end(), adj_initial);
@@ -965,7 +1070,11 @@ struct Oracle {
       // Eq. au: objective source -sum_i w_i c_i dJ/df_i = -(1/3) dJ/du, and
       // the Brinkman source -kappa u~ taken at the new value (implicit); the
       // kappa and objective terms of Eqs. ap and as are odd moments and vanish
-      if (NT > 0) {
+      T j2m[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      if (P.objective == 1)
+        j2_adjoint(kref.data(), &mot[(size_t)(t - 1) * 8], st + N, dJ, ut.data(), -1.0 / 3.0,
+                   kref_bar.data(), j2m);
+      if (NT > 0 && P.objective != 1) {
         for (long xn = 0; xn < N; ++xn) {
           int x[3];
           coords(xn, x);
@@ -1007,6 +1116,7 @@ struct Oracle {
       }
       map_adjoint(kref.data(), &mot[(size_t)(t - 1) * 8], kbar.data(), usbar.data(),
                   kref_bar.data(), &mbar[(size_t)(t - 1) * 8]);
+      for (int q = 0; q < 8; ++q) mbar[(size_t)(t - 1) * 8 + q] += j2m[q];
     }
     if (adj_initial) {
       // level 0: moments gathered from level 1, no sources
@@ -1040,6 +1150,9 @@ int validate(const orc_problem* p) {
     if (p->m[a] < 0) return -5;
   }
   if (p->margin < 0 || p->nt < 1 || p->r_t < 1 || p->r_w < 1) return -6;
+  if (p->objective != 0 && p->objective != 1) return -7;
+  if (p->objective == 1 && (p->d != 2 || !(p->l_m > 0.0) || !(p->xg_max[1] > p->xg_min[1])))
+    return -8;
   return 0;
 }
 

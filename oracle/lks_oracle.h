@@ -44,6 +44,8 @@ typedef struct orc_problem {
   int32_t tgt_lo[3], tgt_hi[3]; /* objective target box [lo, hi) */
   double ndir[3];          /* flow direction n */
   double phi;              /* J1 = E - phi * V */
+  int32_t objective;       /* 0: J1 (Eq. objective1); 1: J2 (Eq. objective2, 2D) */
+  double w_d, w_t, l_m;    /* J2 weights w_D, w_T and moment arm l_m */
 } orc_problem;
 
 /* Motion prelude (Sec. 2.4): chi [nt][3], psi [nt] -> motion [nt][8]. */
@@ -76,7 +78,8 @@ int orc_step_adjoint(const orc_problem* p, const double* state_in, const double*
                      double* lam_prev, double* kbar, double* usbar);
 
 /* Full forward march.  state0 nullable (p = 1/3, u = 0); state_final, traj
- * nullable; traj receives [(nt+1)][d+1][N].  J_out = (J, E, V). */
+ * nullable; traj receives [(nt+1)][d+1][N].  J_out = (J, E, V) for J1 and
+ * (J, F_L, F_D) for J2. */
 int orc_forward(const orc_problem* p, const double* gamma, const double* chi,
                 const double* psi, const double* state0, double* state_final,
                 double* J_out, double* traj);

@@ -30,6 +30,7 @@ class OrcProblem(C.Structure):
         ("th_min", C.c_double), ("th_max", C.c_double), ("nt", C.c_int32),
         ("r_t", C.c_int32), ("r_w", C.c_int32), ("tgt_lo", C.c_int32 * 3),
         ("tgt_hi", C.c_int32 * 3), ("ndir", C.c_double * 3), ("phi", C.c_double),
+        ("objective", C.c_int32), ("w_d", C.c_double), ("w_t", C.c_double), ("l_m", C.c_double),
     ]
 
 
@@ -76,6 +77,8 @@ def to_struct(p) -> OrcProblem:
     s.th_min, s.th_max = p.th_min, p.th_max
     s.nt, s.r_t, s.r_w = p.nt, p.r_t, p.r_w
     s.phi = p.phi
+    s.objective = p.objective
+    s.w_d, s.w_t, s.l_m = p.w_d, p.w_t, p.l_m
     return s
 
 

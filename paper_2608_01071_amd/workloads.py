@@ -55,6 +55,10 @@ class Problem:
     ckpt_k: int = 0                           # checkpoint interval (0 = nt)
     body_tape: int = 0                        # body fields kept: 1 all steps, -1 a segment, 0 auto
     scheme: int = 0                           # reverse sweep: 0 exact adjoint, 1 the paper's ALKS
+    objective: int = 0                        # 0: J1 (flow rate), 1: J2 (oar force, 2D)
+    w_d: float = 0.0                          # J2 weight of the drag work F_D
+    w_t: float = 0.0                          # J2 weight of the torque work T
+    l_m: float = 1.0                          # J2 moment arm
 
     @property
     def N(self) -> int:
