@@ -95,10 +95,21 @@ typedef struct lks_problem {
                               discrete adjoint of the march (the true gradient), or
                               LKS_ADJ_ALKS, the paper's adjoint lattice kinetic
                               scheme (Sec. 2.5), an approximation of it */
+  int32_t objective;       /* LKS_OBJ_J1: Eq. objective1 (flow through the target
+                              box, target box, ndir and phi used); LKS_OBJ_J2:
+                              Eq. objective2 (2D only), the propulsive force F_L,
+                              drag work F_D and torque work T of the force density
+                              kappa_ref (u_ref - u_S_ref) on the design points,
+                              J2 = F_L + w_d F_D + w_t T */
+  double w_d, w_t;         /* J2 weights of F_D and T */
+  double l_m;              /* J2 moment arm in T's normalisation 2 pi l_m (> 0);
+                              F_D is normalised by xg_max[1] - xg_min[1] (> 0) */
 } lks_problem;
 
 #define LKS_ADJ_EXACT 0
 #define LKS_ADJ_ALKS 1
+#define LKS_OBJ_J1 0
+#define LKS_OBJ_J2 1
 
 #define LKS_BODY_TAPE_AUTO_MAX (96ull << 30)
 
@@ -130,7 +141,7 @@ lks_status lks_plan_set_zseg(lks_plan* plan, int32_t zseg);
  *   nodes' given p is used for the first step as is).
  * state_final: receives the state after nt steps (nullable); with state0
  *   this supports the periodic approximation of Sec. 3.3.
- * J_out: 3 doubles (J, E, V).
+ * J_out: 3 doubles: (J, E, V) for J1, (J2, F_L, F_D) for J2.
  * Leaves motion, kappa_ref, checkpoints and E in the workspace for
  * lks_adjoint.  Returns LKS_EDOMAIN (before the march) if an inner design
  * point's kernel support reaches a wall node at some step, LKS_EUNSTABLE if
@@ -251,7 +262,7 @@ lks_status lks_map_adjoint(lks_plan* plan, const void* kappa_ref, const double* 
 
 /* Runs forward + adjoint for `count` independent problems (a parameter
  * study: the instances may differ in every lks_problem field) as one hipGraph
- * launched on `stream`.  2D instances with a common step count, checkpoint
+ * launched on `stream`.  2D J1 instances with a common step count, checkpoint
  * interval, precision, body-tape mode and adjoint scheme share every launch:
  * each kernel runs once per step for up to 16 of them, instance k owning a
  * block range.  Other mixes run as parallel branches of the graph, so their

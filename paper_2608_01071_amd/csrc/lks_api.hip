@@ -131,11 +131,14 @@ struct lks_plan {
   int K, nck;
   bool full_btape;  // body fields of every step kept (else of one segment)
   bool alks;        // reverse sweep by the paper's ALKS instead of the exact adjoint
+  bool j2;          // objective J2 (Eq. objective2) instead of J1
   int nblk_step, nblk_map;
+  int nblk_j2;      // J2 design-point blocks (0 without J2)
+  int mrow;         // block slots per step of the motion partials: map transpose, then J2
   Box bmax;     // strides, volume and launch extents of the body buffers
   // workspace offsets (bytes)
   size_t o_mot, o_tab, o_info, o_kref, o_flags, o_J3, o_seed, o_opart, o_ck, o_pp, o_tape,
-      o_body, o_btape, o_badj, o_lam, o_xadj, o_cmot, o_badjt, o_kpart, o_krefbar, o_mpart, o_mbar, o_den, o_kz, o_geo, total;
+      o_body, o_btape, o_badj, o_lam, o_xadj, o_cmot, o_badjt, o_kpart, o_krefbar, o_mpart, o_mbar, o_den, o_kz, o_geo, o_j2acc, o_j2seed, total;
   int first_lazy = 1;
   void* fwd_ws = nullptr;
   bool use_graphs = true;
@@ -174,6 +177,11 @@ lks_status validate(const lks_problem* p) {
   if (p->body_tape < -1 || p->body_tape > 1) return fail(LKS_EINVAL, "body_tape must be -1, 0 or 1");
   if (p->scheme != LKS_ADJ_EXACT && p->scheme != LKS_ADJ_ALKS)
     return fail(LKS_EINVAL, "scheme must be LKS_ADJ_EXACT or LKS_ADJ_ALKS");
+  if (p->objective != LKS_OBJ_J1 && p->objective != LKS_OBJ_J2)
+    return fail(LKS_EINVAL, "objective must be LKS_OBJ_J1 or LKS_OBJ_J2");
+  if (p->objective == LKS_OBJ_J2 &&
+      (p->d != 2 || !(p->l_m > 0.0) || !(p->xg_max[1] > p->xg_min[1])))
+    return fail(LKS_EINVAL, "J2 needs d = 2, l_m > 0 and xg_max[1] > xg_min[1]");
   if (!(p->nu >= 0.0) || !(p->kappa_max >= 0.0) || !(p->q > 0.0))
     return fail(LKS_EINVAL, "need nu >= 0, kappa_max >= 0, q > 0");
   long long N = 1;
@@ -219,6 +227,16 @@ void fill_geo(const lks_problem& p, Geo& g) {
   long long T = 1;
   for (int a = 0; a < p.d; ++a) T *= std::max(0, p.tgt_hi[a] - p.tgt_lo[a]);
   g.NTinv = T > 0 ? 1.0 / ((double)p.nt * (double)T) : 0.0;
+  g.obj = p.objective;
+  if (p.objective == LKS_OBJ_J2) {
+    double Min = 1.0;
+    for (int a = 0; a < p.d; ++a) Min *= p.m[a];
+    g.j2s[0] = 1.0 / ((double)p.nt * Min);
+    g.j2s[1] = 1.0 / ((p.xg_max[1] - p.xg_min[1]) * Min);
+    g.j2s[2] = 1.0 / (2.0 * M_PI * p.l_m * Min);
+    g.j2w[0] = p.w_d;
+    g.j2w[1] = p.w_t;
+  }
   // tile-grid origin: keeps every node's wall-stencil partners within one tile halo
   g.ty3 = p.d == 3 ? tile3_y(p.precision) : TILE_Y;
   g.prec = p.precision;
@@ -343,6 +361,7 @@ lks_status prelude(lks_plan* P, const double* gamma, const double* chi, const do
 lks_status forward_loop(lks_plan* P, void* ws, hipStream_t s) {
   HIPCHK(launch_zero(wsp(ws, P->o_flags), 64 * sizeof(int), s));
   HIPCHK(launch_zero(wsp(ws, P->o_opart), (size_t)P->nblk_step * 2 * sizeof(double), s));
+  if (P->j2) HIPCHK(launch_zero(wsp(ws, P->o_j2acc), (size_t)P->nblk_j2 * 3 * sizeof(double), s));
   const void* in = ck_slot(P, ws, 0);
   // Each step's map runs right before its step, which then reads the body
   // fields from cache.  (Mapping every step up front in a few wide launches
@@ -353,12 +372,20 @@ lks_status forward_loop(lks_plan* P, void* ws, hipStream_t s) {
                                                       : pp_slot(P, ws, n & 1);
     void* body = fwd_body(P, ws, n);
     if (lks_status e = map_step(P, ws, n, body, s)) return e;
-    if (lks_status e = fwd_step(P, ws, n, in, out, body, n == 1 ? P->first_lazy : 1, 1, s))
+    if (lks_status e = fwd_step(P, ws, n, in, out, body, n == 1 ? P->first_lazy : 1, !P->j2, s))
       return e;
+    if (P->j2) {
+      Scope sc("j2", s, true);
+      HIPCHK(launch_j2_forward(P->g, P->prec, wsp(ws, P->o_kref), tab(P, ws, n), out,
+                               (double*)wsp(ws, P->o_j2acc), s));
+    }
     in = out;
   }
-  HIPCHK(launch_objective_final(P->g, (const double*)wsp(ws, P->o_opart), step_blocks(P->g),
-                                (double*)wsp(ws, P->o_J3), s));
+  if (P->j2)
+    HIPCHK(launch_j2_final(P->g, (const double*)wsp(ws, P->o_j2acc), (double*)wsp(ws, P->o_J3), s));
+  else
+    HIPCHK(launch_objective_final(P->g, (const double*)wsp(ws, P->o_opart), step_blocks(P->g),
+                                  (double*)wsp(ws, P->o_J3), s));
   return LKS_OK;
 }
 
@@ -410,7 +437,7 @@ MapAdjArgs mapadj_args(lks_plan* P, void* ws, int n) {
   m.bkbar = wsp(ws, P->o_badj);
   m.bubar = wsp(ws, P->o_badj) + P->bmax.vol * P->es;
   m.kref_bar = (double*)wsp(ws, P->o_krefbar);
-  m.mpart = (double*)wsp(ws, P->o_mpart) + (size_t)(n - 1) * P->nblk_map * 8;
+  m.mpart = (double*)wsp(ws, P->o_mpart) + (size_t)(n - 1) * P->mrow * 8;
   m.overwrite = n == P->g.nt ? 1 : 0;
   return m;
 }
@@ -435,6 +462,14 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
       AdjArgs a = adj_args(P, ws, n, sg, cur);
       a.bkbar = badj_slot(P, ws, n - nb);
       a.bubar = (char*)a.bkbar + P->bmax.vol * P->es;
+      if (P->j2) {
+        // J2 seeds the fluid velocity on the body box instead of the target box
+        a.seed = nullptr;
+        a.j2s = wsp(ws, P->o_j2seed);
+        Scope sc("j2", s, true);
+        HIPCHK(launch_j2_seed(P->g, P->prec, wsp(ws, P->o_kref), a.si, P->bmax,
+                              (const double*)wsp(ws, P->o_seed), wsp(ws, P->o_j2seed), s));
+      }
       {
         Scope sc("adj_step", s, true);
         HIPCHK(launch_adjoint_step(P->g, P->prec, a, s));
@@ -448,11 +483,19 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
       const MapAdjArgs m = mapadj_args(P, ws, nb);
       double* kp = (double*)wsp(ws, P->o_kpart);
       void* b0 = badj_slot(P, ws, 0);
-      const StepBatch sb{(long long)(body_bytes(P) / P->es), P->g.Mtot,
-                         (long long)P->nblk_map * 8};
-      Scope sc("map_adj", s, true);
-      HIPCHK(launch_map_adjoint(P->g, P->prec, m.kref, nullptr, m.si, m.box, b0,
-                                (char*)b0 + P->bmax.vol * P->es, kp, 1, m.mpart, s, cnt, sb));
+      const StepBatch sb{(long long)(body_bytes(P) / P->es), P->g.Mtot, (long long)P->mrow * 8};
+      {
+        Scope sc("map_adj", s, true);
+        HIPCHK(launch_map_adjoint(P->g, P->prec, m.kref, nullptr, m.si, m.box, b0,
+                                  (char*)b0 + P->bmax.vol * P->es, kp, 1, m.mpart, s, cnt, sb));
+      }
+      // J2's direct terms join the same rows, in their own block slots
+      if (P->j2) {
+        Scope sc("j2", s, true);
+        HIPCHK(launch_j2_adjoint(P->g, P->prec, m.kref, m.si, tape_slot(P, ws, 0), P->S,
+                                 (const double*)wsp(ws, P->o_seed), kp, P->g.Mtot, m.mpart,
+                                 (long long)P->mrow * 8, P->nblk_map, cnt, s));
+      }
       HIPCHK(launch_kref_accum(P->g.Mtot, cnt, kp, (double*)wsp(ws, P->o_krefbar), s));
     }
   }
@@ -464,7 +507,7 @@ lks_status sens(lks_plan* P, const double* gamma, const void* ws, double* dg, do
   Scope sc("sensitivities", s);
   double* den = (double*)wsp((void*)ws, P->o_den);
   HIPCHK(launch_sens(P->g, P->prec, gamma, (const double*)wsp((void*)ws, P->o_krefbar),
-                     (const double*)wsp((void*)ws, P->o_mpart), P->nblk_map,
+                     (const double*)wsp((void*)ws, P->o_mpart), P->mrow,
                      (double*)wsp((void*)ws, P->o_mbar), den, den + P->g.nt, dg, dchi, dpsi, s));
   return LKS_OK;
 }
@@ -549,6 +592,9 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
     P->nblk_step = std::max(P->nblk_step, step_blocks(g4));
   }
   P->nblk_map = mapadj_blocks(g);
+  P->j2 = prob->objective == LKS_OBJ_J2;
+  P->nblk_j2 = P->j2 ? j2_blocks(g) : 0;
+  P->mrow = P->nblk_map + P->nblk_j2;
   // body-box bound over any rotation about z and any translation
   const double diag = sqrt((double)(g.D[0] - 1) * (g.D[0] - 1) + (double)(g.D[1] - 1) * (g.D[1] - 1));
   int ext[3];
@@ -597,7 +643,10 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   // ALKS: raw first-moment part of the adjoint velocity, two slots like lambda
   P->o_xadj = take(P->alks ? 2 * (size_t)g.d * g.N * P->es : 0);
   P->o_krefbar = take((size_t)g.Mtot * sizeof(double));
-  P->o_mpart = take((size_t)g.nt * P->nblk_map * 8 * sizeof(double));
+  P->o_mpart = take((size_t)g.nt * P->mrow * 8 * sizeof(double));
+  // J2: per-block step sums, and the reverse-step seed on the body box
+  P->o_j2acc = take((size_t)P->nblk_j2 * 3 * sizeof(double));
+  P->o_j2seed = take(P->j2 ? 2 * (size_t)P->bmax.vol * P->es : 0);
   P->o_mbar = take((size_t)g.nt * 8 * sizeof(double));
   P->o_den = take((size_t)g.nt * 6 * sizeof(double));
   // lks_constraints: its own motion table and a discarded chi-gradient
@@ -980,7 +1029,7 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
         m.kref_bar = (double*)wsp(ws[k], P->o_kpart);
         m.overwrite = 1;
         m.sb = StepBatch{(long long)(body_bytes(P) / P->es), P->g.Mtot,
-                         (long long)P->nblk_map * 8};
+                         (long long)P->mrow * 8};
         qb.a[k] = m;
       }
       Scope sc("map_adj", s, true);
@@ -1037,14 +1086,15 @@ lks_status lks_batch_run(int32_t count, lks_plan* const* plans, const double* co
     HIPCHK(launch_zero(wsp(ws, P->o_krefbar), (size_t)P->g.Mtot * sizeof(double), s));
     HIPCHK(hipMemcpyAsync(wsp(ws, P->o_geo), &P->g, sizeof(Geo), hipMemcpyHostToDevice, s));
   }
-  // 2D instances with a common step count, checkpoint interval, precision,
+  // 2D J1 instances with a common step count, checkpoint interval, precision,
   // body-tape mode and adjoint scheme share every launch (groups of
   // BATCH_MAX); others run as graph branches
   bool shared = true;
   for (int k = 0; k < count; ++k)
     shared = shared && plans[k]->g.d == 2 && plans[k]->prec == P0->prec &&
              plans[k]->g.nt == P0->g.nt && plans[k]->K == P0->K && plans[k]->nck == P0->nck &&
-             plans[k]->full_btape == P0->full_btape && plans[k]->alks == P0->alks;
+             plans[k]->full_btape == P0->full_btape && plans[k]->alks == P0->alks &&
+             !plans[k]->j2;
   // one graph: instance k's forward march, objective copy, adjoint march and
   // epilogue form branch k, forked from and joined to the launch stream
   std::vector<const void*> key;

@@ -46,6 +46,8 @@ struct AdjRing {
 };
 // Threads per block of the map transposes (2D and 3D).
 constexpr int MAPADJ_THREADS = 256;
+// Objective J2 kernels: one thread per design point (per box node for the seed).
+constexpr int J2_THREADS = 256;
 // 3D map: most z values per lane the kappa_ref copy is padded for, and the
 // value the map uses (one half-wave per analysis column, 32 * MAP_ZPL z
 // values per pass).
@@ -92,6 +94,10 @@ struct Geo {
   int zseg_f;             // z planes per block segment (3D forward step)
   int ty3;                // tile height of the step kernels (3D: Tile3<R>::TY; 2D: TILE_Y)
   int prec;               // state precision (0 FP32, 1 FP64)
+  int obj;                // objective: 0 J1, 1 J2
+  double j2s[3];          // J2 normalisations 1/(nt M), 1/((x2max - x2min) M),
+                          // 1/(2 pi l_m M), M = inner design points
+  double j2w[2];          // J2 weights w_d, w_t
 };
 
 // Blocks of the 2D map transpose (MAPADJ_PTS2 runs of 64 points each).
@@ -185,6 +191,9 @@ struct AdjArgs {
   void* xout;
   const StepInfo* si_next;
   int xall;  // ALKS: store the raw part at every node (the sweep's last step)
+  // Objective J2: seed on the fluid velocity on the body box ([2][box.vol],
+  // box-indexed like bk; nullable), applied where the J1 seed would be.
+  const void* j2s;
 };
 
 int step_blocks(const Geo& g);
@@ -209,6 +218,20 @@ hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
                               double* mpart, hipStream_t s, int nsteps = 1,
                               StepBatch sb = StepBatch{0, 0, 0});
 // kref_bar[k] += part[j * M + k] for j = n - 1 down to 0, one at a time.
+// Objective J2 (2D): blocks of the per-design-point kernels; the step sums
+// of state st after step si added into jacc [j2_blocks][3]; (J2, F_L, F_D)
+// from them; the reverse-step seed on the body box; the direct terms of
+// nsteps consecutive reverse steps (see the kernels).
+int j2_blocks(const Geo& g);
+hipError_t launch_j2_forward(const Geo& g, int precision, const void* kref, const StepInfo* si,
+                             const void* st, double* jacc, hipStream_t s);
+hipError_t launch_j2_final(const Geo& g, const double* jacc, double* J3, hipStream_t s);
+hipError_t launch_j2_seed(const Geo& g, int precision, const void* kref, const StepInfo* si,
+                          const Box& box, const double* dJ, void* js, hipStream_t s);
+hipError_t launch_j2_adjoint(const Geo& g, int precision, const void* kref, const StepInfo* si,
+                             const void* st0, long long sstride, const double* dJ, double* kpart,
+                             long long kstride, double* mpart, long long mstride, int slot0,
+                             int nsteps, hipStream_t s);
 hipError_t launch_kref_accum(long long M, int n, const double* part, double* kref_bar,
                              hipStream_t s);
 hipError_t launch_steps(const Geo& g, const double* mot, StepInfo* tab, int* info, hipStream_t s);

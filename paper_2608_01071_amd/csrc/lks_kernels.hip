@@ -902,6 +902,13 @@ __device__ __forceinline__ void adj_star(const Geo& g, const AdjArgs& a, int x, 
       const R* bu = (const R*)a.bu;
       const R k = bk[bi];
       const R inv = brinkman_inv(k);
+      if (a.j2s) {
+        const R* js = (const R*)a.j2s;
+        _Pragma("unroll") for (int q = 0; q < 2; ++q) {
+          sd[q] += js[q * a.box.vol + bi];
+          ub[q] += js[q * a.box.vol + bi];
+        }
+      }
       // the part the Brinkman correction acts on
       R xs[3] = {ub[0], ub[1], ub[2]}, X[3] = {R(0), R(0), R(0)};
       if constexpr (ALK) {
@@ -2043,6 +2050,193 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj(Geo g, const R* kref,
                   kref_bar + st * sb.kref, overwrite, mpart + st * sb.mpart, blockIdx.x);
 }
 
+// ------------------------------------------------- objective J2 (Sec. 2.6)
+// Eq. objective2 on a 2D body.  Design point k of step n sits at
+// X = x^G + R(theta) r (r its offset from the design centre, v = R r) and
+// moves with U = u^G + omega R'(theta) r.  Its force density is
+// f = kappa_ref (u_ref - U), u_ref = sum_x W(x - X) u(x) over the 4 x 4 taps
+// of the cosine kernel, wall nodes left out.  Per step: sum f_1 (F_L),
+// u^G_2 sum f_2 (F_D), omega sum (v_1 f_2 - v_2 f_1) (T); J2 = F_L + w_D F_D
+// + w_T T with the normalisations of Geo::j2s.  dJ2/df = (g_1, g_2),
+// g_1 = a_1 - b v_2, g_2 = a_2 + b v_1 with a_1 = 1/(nt M),
+// a_2 = w_D u^G_2 / ((x2max - x2min) M), b = w_T omega / (2 pi l_m M), M the
+// inner design points: it does not depend on the flow.
+struct J2Pt {
+  double r0, r1, v0, v1, X0, X1, U0, U1;
+};
+__device__ __forceinline__ J2Pt j2_point(const Geo& g, const StepInfo& S, long long k) {
+  J2Pt p;
+  p.r0 = (double)(k % g.D[0]) - g.xiG[0];
+  p.r1 = (double)(k / g.D[0]) - g.xiG[1];
+  p.v0 = S.c * p.r0 - S.s * p.r1;
+  p.v1 = S.s * p.r0 + S.c * p.r1;
+  p.X0 = p.v0 + S.xg[0];
+  p.X1 = p.v1 + S.xg[1];
+  p.U0 = S.om * (-S.s * p.r0 - S.c * p.r1) + S.ug[0];
+  p.U1 = S.om * (S.c * p.r0 - S.s * p.r1) + S.ug[1];
+  return p;
+}
+__device__ __forceinline__ void j2_coef(const Geo& g, const StepInfo& S, double& a0, double& a1,
+                                        double& b) {
+  a0 = g.j2s[0];
+  a1 = g.j2w[0] * S.ug[1] * g.j2s[1];
+  b = g.j2w[1] * S.om * g.j2s[2];
+}
+// u_ref at X and (DER) its derivatives dur[a][q] = d u_ref_q / d X_a.
+template <class R, bool DER>
+__device__ __forceinline__ void j2_gather(const Geo& g, const R* st, double X0, double X1,
+                                          double ur[2], double dur[2][2]) {
+  const long long N = g.N;
+  const int lx = (int)floor(X0) - 1, ly = (int)floor(X1) - 1;
+  for (int ky = 0; ky < 4; ++ky) {
+    int y = ly + ky;
+    const double ry = (double)y - X1;
+    if (!wrap_axis(g, 1, y)) continue;
+    const double wy = wk(ry), dy = wkd(ry);
+#pragma unroll
+    for (int kx = 0; kx < 4; ++kx) {
+      int x = lx + kx;
+      const double rx = (double)x - X0;
+      if (!wrap_axis(g, 0, x) || is_wall(g, x, y, 0)) continue;
+      const long long i = nidx(g, x, y, 0);
+      const double wx = wk(rx);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const double uq = (double)st[(1 + q) * N + i];
+        ur[q] += wx * wy * uq;
+        if constexpr (DER) {
+          dur[0][q] -= wkd(rx) * wy * uq;
+          dur[1][q] -= wx * dy * uq;
+        }
+      }
+    }
+  }
+}
+
+// Step sums of one step, one thread per design point: each block adds its
+// fixed-order partial to its own slot of jacc [blocks][3].
+template <class R>
+__global__ __launch_bounds__(J2_THREADS) void k_j2_fwd(Geo g, const R* kref, const StepInfo* si,
+                                                       const R* st, double* jacc) {
+  const long long k = blockIdx.x * (long long)J2_THREADS + threadIdx.x;
+  double part[3] = {0.0, 0.0, 0.0};
+  if (k < g.Mtot) {
+    const StepInfo S = *si;
+    const J2Pt p = j2_point(g, S, k);
+    double ur[2] = {0.0, 0.0}, dur[2][2];
+    j2_gather<R, false>(g, st, p.X0, p.X1, ur, dur);
+    const double kr = (double)kref[k];
+    const double f0 = kr * (ur[0] - p.U0), f1 = kr * (ur[1] - p.U1);
+    part[0] = f0;
+    part[1] = S.ug[1] * f1;
+    part[2] = S.om * (p.v0 * f1 - p.v1 * f0);
+  }
+  double tot[3];
+  block_sum<3, J2_THREADS>(part, tot);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q) jacc[blockIdx.x * 3 + q] += tot[q];
+}
+
+// J_out = (J2, F_L, F_D) from the block slots, in a fixed order.
+__global__ void k_j2_final(Geo g, const double* jacc, int nblk, double* J3) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int b = 0; b < nblk; ++b)
+    for (int q = 0; q < 3; ++q) s[q] += jacc[b * 3 + q];
+  const double FL = s[0] * g.j2s[0], FD = s[1] * g.j2s[1], T = s[2] * g.j2s[2];
+  J3[0] = FL + g.j2w[0] * FD + g.j2w[1] * T;
+  J3[1] = FL;
+  J3[2] = FD;
+}
+
+// Reverse-step seed on the fluid velocity, dJ sum_k W(x - X_k) kappa_ref g,
+// on the body box of the step ([2][box.vol], box-indexed like the body
+// fields; 0 at wall nodes): one thread per box node gathers the design
+// points in its rotated window, as the transfer does.
+template <class R>
+__global__ __launch_bounds__(J2_THREADS) void k_j2_seed(Geo g, const R* kref, const StepInfo* si,
+                                                        Box box, const double* dJ, R* js) {
+  apply_step(box, si);
+  const long long t = blockIdx.x * (long long)J2_THREADS + threadIdx.x;
+  if (t >= (long long)box.ext[0] * box.ext[1]) return;
+  const int i = (int)(t % box.ext[0]), j = (int)(t / box.ext[0]);
+  const int bx = box.lo[0] + i, by = box.lo[1] + j;
+  int x = bx, y = by;
+  double s0 = 0.0, s1 = 0.0;
+  if (wrap_axis(g, 0, x) && wrap_axis(g, 1, y) && !is_wall(g, x, y, 0)) {
+    const StepInfo S = *si;
+    double a0, a1, b;
+    j2_coef(g, S, a0, a1, b);
+    const double rx = bx - S.xg[0], ry = by - S.xg[1];
+    const double q0 = S.c * rx + S.s * ry + g.xiG[0];
+    const double q1 = -S.s * rx + S.c * ry + g.xiG[1];
+    const double h = 2.0 * (fabs(S.c) + fabs(S.s));
+    const int i0 = max(0, (int)ceil(q0 - h)), i1 = min(g.D[0] - 1, (int)floor(q0 + h));
+    const int j0 = max(0, (int)ceil(q1 - h)), j1 = min(g.D[1] - 1, (int)floor(q1 + h));
+    for (int e1 = j0; e1 <= j1; ++e1)
+      for (int e0 = i0; e0 <= i1; ++e0) {
+        const long long k = e0 + (long long)g.D[0] * e1;
+        const J2Pt p = j2_point(g, S, k);
+        const double d0 = bx - p.X0, d1 = by - p.X1;
+        if (fabs(d0) < 2.0 && fabs(d1) < 2.0) {
+          const double wkr = wk(d0) * wk(d1) * (double)kref[k];
+          s0 += wkr * (a0 - b * p.v1);
+          s1 += wkr * (a1 + b * p.v0);
+        }
+      }
+  }
+  const double sc = dJ[0];
+  const long long bi = i + (long long)box.sx * j;
+  js[bi] = (R)(sc * s0);
+  js[box.vol + bi] = (R)(sc * s1);
+}
+
+// Direct J2 terms of consecutive reverse steps (blockIdx.y = step within the
+// batch, state st0 + y sstride): dJ/dkappa_ref added into the step's
+// kappa_ref partial row, and the motion partials (position, velocity, angle,
+// angular velocity; the explicit u^G_2 of F_D and omega of T included) into
+// block slot slot0 + blockIdx.x of the step's motion-partial row.
+template <class R>
+__global__ __launch_bounds__(J2_THREADS) void k_j2_adj(Geo g, const R* kref, const StepInfo* si,
+                                                       const R* st0, long long sstride,
+                                                       const double* dJ, double* kpart,
+                                                       long long kstride, double* mpart,
+                                                       long long mstride, int slot0) {
+  const int y = blockIdx.y;
+  const StepInfo S = si[y];
+  const R* st = st0 + y * sstride;
+  const long long k = blockIdx.x * (long long)J2_THREADS + threadIdx.x;
+  double part[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (k < g.Mtot) {
+    const J2Pt p = j2_point(g, S, k);
+    double ur[2] = {0.0, 0.0}, dur[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    j2_gather<R, true>(g, st, p.X0, p.X1, ur, dur);
+    double a0, a1, b;
+    j2_coef(g, S, a0, a1, b);
+    const double dj = dJ[0], kr = (double)kref[k];
+    const double e0 = ur[0] - p.U0, e1 = ur[1] - p.U1;
+    const double f0 = kr * e0, f1 = kr * e1;
+    const double g0 = a0 - b * p.v1, g1 = a1 + b * p.v0;
+    kpart[y * kstride + k] += dj * (g0 * e0 + g1 * e1);
+    const double dX0 = -S.s * p.r0 - S.c * p.r1, dX1 = S.c * p.r0 - S.s * p.r1;  // R' r
+    const double dU0 = S.om * (-S.c * p.r0 + S.s * p.r1);                        // omega R'' r
+    const double dU1 = S.om * (-S.s * p.r0 - S.c * p.r1);
+    const double Xb0 = dj * kr * (g0 * dur[0][0] + g1 * dur[0][1]);
+    const double Xb1 = dj * kr * (g0 * dur[1][0] + g1 * dur[1][1]);
+    const double Ub0 = -dj * kr * g0, Ub1 = -dj * kr * g1;
+    part[0] = Xb0;
+    part[1] = Xb1;
+    part[3] = Ub0;
+    part[4] = Ub1 + dj * g.j2w[0] * g.j2s[1] * f1;
+    part[6] = Xb0 * dX0 + Xb1 * dX1 + Ub0 * dU0 + Ub1 * dU1 + dj * b * (dX0 * f1 - dX1 * f0);
+    part[7] = Ub0 * dX0 + Ub1 * dX1 + dj * g.j2w[1] * g.j2s[2] * (p.v0 * f1 - p.v1 * f0);
+  }
+  double tot[8];
+  block_sum<8, J2_THREADS>(part, tot);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 8; ++q) mpart[y * mstride + (long long)(slot0 + blockIdx.x) * 8 + q] = tot[q];
+}
+
 // ----------------------------------------------------------- prelude
 __device__ double filter_den(int t, int nt, int R) {
   double den = 0.0;
@@ -2711,6 +2905,53 @@ hipError_t launch_kref_accum(long long M, int n, const double* part, double* kre
                              hipStream_t s) {
   hipLaunchKernelGGL(k_kref_accum, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, M, n, part,
                      kref_bar);
+  return hipGetLastError();
+}
+
+int j2_blocks(const Geo& g) { return (int)((g.Mtot + J2_THREADS - 1) / J2_THREADS); }
+
+hipError_t launch_j2_forward(const Geo& g, int precision, const void* kref, const StepInfo* si,
+                             const void* st, double* jacc, hipStream_t s) {
+  const dim3 grid(j2_blocks(g));
+  if (precision == 0)
+    LKS_LAUNCH(k_j2_fwd<float>, grid, dim3(J2_THREADS), 0, s, g, (const float*)kref, si,
+               (const float*)st, jacc);
+  else
+    LKS_LAUNCH(k_j2_fwd<double>, grid, dim3(J2_THREADS), 0, s, g, (const double*)kref, si,
+               (const double*)st, jacc);
+  return hipGetLastError();
+}
+
+hipError_t launch_j2_final(const Geo& g, const double* jacc, double* J3, hipStream_t s) {
+  LKS_LAUNCH(k_j2_final, dim3(1), dim3(64), 0, s, g, jacc, j2_blocks(g), J3);
+  return hipGetLastError();
+}
+
+hipError_t launch_j2_seed(const Geo& g, int precision, const void* kref, const StepInfo* si,
+                          const Box& box, const double* dJ, void* js, hipStream_t s) {
+  // box: the largest step box (strides, volume and launch extents)
+  const long long nodes = (long long)box.ext[0] * box.ext[1];
+  const dim3 grid((unsigned)((nodes + J2_THREADS - 1) / J2_THREADS));
+  if (precision == 0)
+    LKS_LAUNCH(k_j2_seed<float>, grid, dim3(J2_THREADS), 0, s, g, (const float*)kref, si, box,
+               dJ, (float*)js);
+  else
+    LKS_LAUNCH(k_j2_seed<double>, grid, dim3(J2_THREADS), 0, s, g, (const double*)kref, si, box,
+               dJ, (double*)js);
+  return hipGetLastError();
+}
+
+hipError_t launch_j2_adjoint(const Geo& g, int precision, const void* kref, const StepInfo* si,
+                             const void* st0, long long sstride, const double* dJ, double* kpart,
+                             long long kstride, double* mpart, long long mstride, int slot0,
+                             int nsteps, hipStream_t s) {
+  const dim3 grid(j2_blocks(g), nsteps);
+  if (precision == 0)
+    LKS_LAUNCH(k_j2_adj<float>, grid, dim3(J2_THREADS), 0, s, g, (const float*)kref, si,
+               (const float*)st0, sstride, dJ, kpart, kstride, mpart, mstride, slot0);
+  else
+    LKS_LAUNCH(k_j2_adj<double>, grid, dim3(J2_THREADS), 0, s, g, (const double*)kref, si,
+               (const double*)st0, sstride, dJ, kpart, kstride, mpart, mstride, slot0);
   return hipGetLastError();
 }
 

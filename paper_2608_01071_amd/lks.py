@@ -38,7 +38,8 @@ class LksProblem(C.Structure):
         ("th_max", C.c_double), ("nt", C.c_int32), ("r_t", C.c_int32), ("r_w", C.c_int32),
         ("tgt_lo", C.c_int32 * 3), ("tgt_hi", C.c_int32 * 3), ("ndir", C.c_double * 3),
         ("phi", C.c_double), ("ckpt_k", C.c_int32), ("body_tape", C.c_int32),
-        ("scheme", C.c_int32),
+        ("scheme", C.c_int32), ("objective", C.c_int32), ("w_d", C.c_double),
+        ("w_t", C.c_double), ("l_m", C.c_double),
     ]
 
 
@@ -111,6 +112,8 @@ def to_struct(p) -> LksProblem:
     s.ckpt_k = p.ckpt_k
     s.body_tape = p.body_tape
     s.scheme = p.scheme
+    s.objective = p.objective
+    s.w_d, s.w_t, s.l_m = p.w_d, p.w_t, p.l_m
     return s
 
 

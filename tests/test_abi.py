@@ -78,15 +78,24 @@ def test_plan_validation_and_workspace(L):
     assert L.lks_plan_create(C.byref(s5), C.byref(h5), C.byref(nb5)) == 0
     assert nb5.value >= nb.value + 2 * p.d * p.N * 8
     L.lks_plan_destroy(h5)
+    # J2 keeps per-block step sums and a seed slot on the body box
+    s6 = lks.to_struct(p.replace(objective=1, w_d=0.1, w_t=0.2, l_m=3.0))
+    h6 = C.c_void_p()
+    nb6 = C.c_size_t()
+    assert L.lks_plan_create(C.byref(s6), C.byref(h6), C.byref(nb6)) == 0
+    assert nb6.value > nb.value
+    L.lks_plan_destroy(h6)
     bad = [p.replace(d=4), p.replace(n=(64, 3, 1)), p.replace(nt=0), p.replace(r_t=0),
            p.replace(ckpt_k=500), p.replace(precision=2), p.replace(q=0.0),
-           p.replace(scheme=2), p.replace(scheme=-1)]
+           p.replace(scheme=2), p.replace(scheme=-1), p.replace(objective=2),
+           p.replace(objective=1, w_d=0.1, w_t=0.1, l_m=0.0)]
     p3, *_ = W.make_3d(16, 4, 5, 2, nu=0.1, seed=0)
     p3 = p3.replace(ckpt_k=5)
     h0 = C.c_void_p()
     assert L.lks_plan_create(C.byref(lks.to_struct(p3)), C.byref(h0), C.byref(nb)) == 0
     L.lks_plan_destroy(h0)
     bad.append(p3.replace(bc=(1, 1, 1)))
+    bad.append(p3.replace(objective=1, l_m=2.0))  # J2 is 2D only
     # 3D (p, u) states of 4 GiB and more (2^28 nodes in FP32, 2^27 in FP64)
     bad.append(p3.replace(n=(512, 512, 1024), precision=0))
     bad.append(p3.replace(n=(512, 512, 512), precision=1))
