@@ -161,6 +161,36 @@ def fwd_step_out_of_cache(nside: int = 256, nt: int = 12):
             "mlups": round(p.N / avg_s / 1e6, 1)}
 
 
+def oar_j2(nt: int = 4000):
+    """The 2D oar workload (objective J2, D2Q9 512^2, 256^2 design, FP32,
+    4000 steps, K = 100): forward + adjoint rate with J2 and with J1 on the
+    same shape and motion, and the J2 kernels' cost per step (event-timed
+    launches of one eager pass)."""
+    import torch
+    from paper_2608_01071_amd import lks, workloads as W
+    p, g, c, s = W.oar(nt=nt)
+    seed = torch.ones(1, dtype=torch.float64, device="cuda")
+    out = {"workload": "2D oar: D2Q9 512^2 channel, 256^2 design, J2 (w_D 0.01, w_T 0.15), "
+                       f"FP32, {nt} steps, K 100"}
+    for key, q in (("j2", p), ("j1_same_shape", p.replace(objective=0))):
+        plan = lks.Plan(q)
+        run_pass(plan, g, c, s, seed)  # warm-up (graph capture)
+        J3, _, tf, ta = run_pass(plan, g, c, s, seed)
+        out[key] = {"mlups": round(p.N * nt / (tf + ta) / 1e6, 1),
+                    "ms_per_pass": round((tf + ta) * 1e3, 2)}
+        if key == "j2":
+            out[key]["J_FL_FD"] = [float(v) for v in J3.cpu().numpy()]
+            lks.profile_enable(True)
+            run_pass(plan, g, c, s, seed)
+            torch.cuda.synchronize()
+            prof = lks.profile_read()
+            lks.profile_enable(False)
+            out["us_per_step"] = {k: round(v[0] * 1e3 / nt, 2) for k, v in prof.items()}
+        del plan
+        torch.cuda.empty_cache()
+    return out
+
+
 def design_side(plan, g, c, s, reps: int = 20):
     """The optimiser-side calls once per design iteration on the workload's
     design grid: filter + projection (radius 4.8, beta 8, eta 0.5), their
@@ -233,6 +263,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-c5", action="store_true", help="skip the batched 16-instance study")
     ap.add_argument("--no-alks", action="store_true", help="skip the ALKS reverse-sweep run")
+    ap.add_argument("--no-oar", action="store_true", help="skip the 2D oar (J2) run")
     ap.add_argument("--no-design", action="store_true",
                     help="skip timing the design prelude and constraints")
     ap.add_argument("--no-big", action="store_true",
@@ -345,6 +376,7 @@ def main():
     torch.cuda.empty_cache()
     big = None if args.no_big else fwd_step_out_of_cache()
     c5 = None if args.no_c5 else c5_batch()
+    oar = None if args.no_oar else oar_j2()
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_steps)
 
     line = {
@@ -363,6 +395,7 @@ def main():
         "alks": alks,
         "design_side": design,
         "c5_batch": c5,
+        "oar_j2": oar,
         "fwd_step_256": big,
         "kernels": kernels,
     }

@@ -375,7 +375,7 @@ lks_status forward_loop(lks_plan* P, void* ws, hipStream_t s) {
     if (lks_status e = fwd_step(P, ws, n, in, out, body, n == 1 ? P->first_lazy : 1, !P->j2, s))
       return e;
     if (P->j2) {
-      Scope sc("j2", s, true);
+      Scope sc("j2_fwd", s, true);
       HIPCHK(launch_j2_forward(P->g, P->prec, wsp(ws, P->o_kref), tab(P, ws, n), out,
                                (double*)wsp(ws, P->o_j2acc), s));
     }
@@ -457,6 +457,15 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
       if (lks_status e = fwd_step(P, ws, n, in, tape_slot(P, ws, n - nb), body, lazy, 0, s))
         return e;
     }
+    // J2: the segment's seeds on the fluid velocity in one launch (they
+    // depend on the motion and kappa_ref only)
+    const size_t js_bytes = 2 * (size_t)P->bmax.vol * P->es;
+    if (P->j2) {
+      Scope sc("j2_seed", s, true);
+      HIPCHK(launch_j2_seed(P->g, P->prec, wsp(ws, P->o_kref), tab(P, ws, nb), P->bmax,
+                            (const double*)wsp(ws, P->o_seed), wsp(ws, P->o_j2seed), ne - nb + 1,
+                            s));
+    }
     // reverse steps, each keeping its body adjoint in a slot of its own
     for (int n = ne; n >= nb; --n) {
       AdjArgs a = adj_args(P, ws, n, sg, cur);
@@ -465,10 +474,7 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
       if (P->j2) {
         // J2 seeds the fluid velocity on the body box instead of the target box
         a.seed = nullptr;
-        a.j2s = wsp(ws, P->o_j2seed);
-        Scope sc("j2", s, true);
-        HIPCHK(launch_j2_seed(P->g, P->prec, wsp(ws, P->o_kref), a.si, P->bmax,
-                              (const double*)wsp(ws, P->o_seed), wsp(ws, P->o_j2seed), s));
+        a.j2s = wsp(ws, P->o_j2seed) + (size_t)(n - nb) * js_bytes;
       }
       {
         Scope sc("adj_step", s, true);
@@ -491,7 +497,7 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
       }
       // J2's direct terms join the same rows, in their own block slots
       if (P->j2) {
-        Scope sc("j2", s, true);
+        Scope sc("j2_adj", s, true);
         HIPCHK(launch_j2_adjoint(P->g, P->prec, m.kref, m.si, tape_slot(P, ws, 0), P->S,
                                  (const double*)wsp(ws, P->o_seed), kp, P->g.Mtot, m.mpart,
                                  (long long)P->mrow * 8, P->nblk_map, cnt, s));
@@ -644,9 +650,9 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   P->o_xadj = take(P->alks ? 2 * (size_t)g.d * g.N * P->es : 0);
   P->o_krefbar = take((size_t)g.Mtot * sizeof(double));
   P->o_mpart = take((size_t)g.nt * P->mrow * 8 * sizeof(double));
-  // J2: per-block step sums, and the reverse-step seed on the body box
+  // J2: per-block step sums, and the reverse-step seeds of one segment on the body box
   P->o_j2acc = take((size_t)P->nblk_j2 * 3 * sizeof(double));
-  P->o_j2seed = take(P->j2 ? 2 * (size_t)P->bmax.vol * P->es : 0);
+  P->o_j2seed = take(P->j2 ? (size_t)P->K * 2 * P->bmax.vol * P->es : 0);
   P->o_mbar = take((size_t)g.nt * 8 * sizeof(double));
   P->o_den = take((size_t)g.nt * 6 * sizeof(double));
   // lks_constraints: its own motion table and a discarded chi-gradient

@@ -220,14 +220,14 @@ hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
 // kref_bar[k] += part[j * M + k] for j = n - 1 down to 0, one at a time.
 // Objective J2 (2D): blocks of the per-design-point kernels; the step sums
 // of state st after step si added into jacc [j2_blocks][3]; (J2, F_L, F_D)
-// from them; the reverse-step seed on the body box; the direct terms of
-// nsteps consecutive reverse steps (see the kernels).
+// from them; the reverse-step seeds on the body box and the direct terms of
+// nsteps consecutive steps (see the kernels).
 int j2_blocks(const Geo& g);
 hipError_t launch_j2_forward(const Geo& g, int precision, const void* kref, const StepInfo* si,
                              const void* st, double* jacc, hipStream_t s);
 hipError_t launch_j2_final(const Geo& g, const double* jacc, double* J3, hipStream_t s);
 hipError_t launch_j2_seed(const Geo& g, int precision, const void* kref, const StepInfo* si,
-                          const Box& box, const double* dJ, void* js, hipStream_t s);
+                          const Box& box, const double* dJ, void* js, int nsteps, hipStream_t s);
 hipError_t launch_j2_adjoint(const Geo& g, int precision, const void* kref, const StepInfo* si,
                              const void* st0, long long sstride, const double* dJ, double* kpart,
                              long long kstride, double* mpart, long long mstride, int slot0,

@@ -2064,10 +2064,10 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj(Geo g, const R* kref,
 struct J2Pt {
   double r0, r1, v0, v1, X0, X1, U0, U1;
 };
-__device__ __forceinline__ J2Pt j2_point(const Geo& g, const StepInfo& S, long long k) {
+__device__ __forceinline__ J2Pt j2_point(const Geo& g, const StepInfo& S, int e0, int e1) {
   J2Pt p;
-  p.r0 = (double)(k % g.D[0]) - g.xiG[0];
-  p.r1 = (double)(k / g.D[0]) - g.xiG[1];
+  p.r0 = (double)e0 - g.xiG[0];
+  p.r1 = (double)e1 - g.xiG[1];
   p.v0 = S.c * p.r0 - S.s * p.r1;
   p.v1 = S.s * p.r0 + S.c * p.r1;
   p.X0 = p.v0 + S.xg[0];
@@ -2082,31 +2082,43 @@ __device__ __forceinline__ void j2_coef(const Geo& g, const StepInfo& S, double&
   a1 = g.j2w[0] * S.ug[1] * g.j2s[1];
   b = g.j2w[1] * S.om * g.j2s[2];
 }
-// u_ref at X and (DER) its derivatives dur[a][q] = d u_ref_q / d X_a.
+// u_ref at X and (DER) its derivatives dur[a][q] = d u_ref_q / d X_a.  The
+// kernel factors are taken once per axis, in the state precision (the offsets
+// are small numbers, exact enough in it); the sums are FP64.
 template <class R, bool DER>
 __device__ __forceinline__ void j2_gather(const Geo& g, const R* st, double X0, double X1,
                                           double ur[2], double dur[2][2]) {
   const long long N = g.N;
   const int lx = (int)floor(X0) - 1, ly = (int)floor(X1) - 1;
+  double wx[4], dx[4], wy[4], dy[4];
+  int xs[4], ys[4];
+  bool okx[4], oky[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    xs[q] = lx + q;
+    ys[q] = ly + q;
+    const R rx = (R)((double)xs[q] - X0), ry = (R)((double)ys[q] - X1);
+    wx[q] = (double)wk(rx);
+    wy[q] = (double)wk(ry);
+    dx[q] = DER ? (double)wkd(rx) : 0.0;
+    dy[q] = DER ? (double)wkd(ry) : 0.0;
+    okx[q] = wrap_axis(g, 0, xs[q]) && !on_wall(g, 0, xs[q]);
+    oky[q] = wrap_axis(g, 1, ys[q]) && !on_wall(g, 1, ys[q]);
+  }
+#pragma unroll
   for (int ky = 0; ky < 4; ++ky) {
-    int y = ly + ky;
-    const double ry = (double)y - X1;
-    if (!wrap_axis(g, 1, y)) continue;
-    const double wy = wk(ry), dy = wkd(ry);
+    if (!oky[ky]) continue;
 #pragma unroll
     for (int kx = 0; kx < 4; ++kx) {
-      int x = lx + kx;
-      const double rx = (double)x - X0;
-      if (!wrap_axis(g, 0, x) || is_wall(g, x, y, 0)) continue;
-      const long long i = nidx(g, x, y, 0);
-      const double wx = wk(rx);
+      if (!okx[kx]) continue;
+      const long long i = nidx(g, xs[kx], ys[ky], 0);
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const double uq = (double)st[(1 + q) * N + i];
-        ur[q] += wx * wy * uq;
+        ur[q] += wx[kx] * wy[ky] * uq;
         if constexpr (DER) {
-          dur[0][q] -= wkd(rx) * wy * uq;
-          dur[1][q] -= wx * dy * uq;
+          dur[0][q] -= dx[kx] * wy[ky] * uq;
+          dur[1][q] -= wx[kx] * dy[ky] * uq;
         }
       }
     }
@@ -2122,7 +2134,8 @@ __global__ __launch_bounds__(J2_THREADS) void k_j2_fwd(Geo g, const R* kref, con
   double part[3] = {0.0, 0.0, 0.0};
   if (k < g.Mtot) {
     const StepInfo S = *si;
-    const J2Pt p = j2_point(g, S, k);
+    const int e1 = (int)(k / g.D[0]);
+    const J2Pt p = j2_point(g, S, (int)k - e1 * g.D[0], e1);
     double ur[2] = {0.0, 0.0}, dur[2][2];
     j2_gather<R, false>(g, st, p.X0, p.X1, ur, dur);
     const double kr = (double)kref[k];
@@ -2152,40 +2165,54 @@ __global__ void k_j2_final(Geo g, const double* jacc, int nblk, double* J3) {
 // Reverse-step seed on the fluid velocity, dJ sum_k W(x - X_k) kappa_ref g,
 // on the body box of the step ([2][box.vol], box-indexed like the body
 // fields; 0 at wall nodes): one thread per box node gathers the design
-// points in its rotated window, as the transfer does.
+// points in its rotated window, as the transfer does, in the state
+// precision on offsets relative to the window corner.  With d = X_k - x,
+// v = (x - x^G) + d, so the seed needs only sum W kappa_ref and its first
+// moments in d.  Consecutive steps in one launch: blockIdx.y = step within
+// the batch, its seed in slot y of js.
 template <class R>
 __global__ __launch_bounds__(J2_THREADS) void k_j2_seed(Geo g, const R* kref, const StepInfo* si,
                                                         Box box, const double* dJ, R* js) {
+  si += blockIdx.y;
+  js += blockIdx.y * 2 * box.vol;
   apply_step(box, si);
   const long long t = blockIdx.x * (long long)J2_THREADS + threadIdx.x;
   if (t >= (long long)box.ext[0] * box.ext[1]) return;
   const int i = (int)(t % box.ext[0]), j = (int)(t / box.ext[0]);
   const int bx = box.lo[0] + i, by = box.lo[1] + j;
   int x = bx, y = by;
-  double s0 = 0.0, s1 = 0.0;
+  const StepInfo S = *si;
+  R m0 = R(0), m1 = R(0), m2 = R(0);  // sum W kappa_ref, times d_1, times d_2
   if (wrap_axis(g, 0, x) && wrap_axis(g, 1, y) && !is_wall(g, x, y, 0)) {
-    const StepInfo S = *si;
-    double a0, a1, b;
-    j2_coef(g, S, a0, a1, b);
     const double rx = bx - S.xg[0], ry = by - S.xg[1];
     const double q0 = S.c * rx + S.s * ry + g.xiG[0];
     const double q1 = -S.s * rx + S.c * ry + g.xiG[1];
     const double h = 2.0 * (fabs(S.c) + fabs(S.s));
     const int i0 = max(0, (int)ceil(q0 - h)), i1 = min(g.D[0] - 1, (int)floor(q0 + h));
     const int j0 = max(0, (int)ceil(q1 - h)), j1 = min(g.D[1] - 1, (int)floor(q1 + h));
-    for (int e1 = j0; e1 <= j1; ++e1)
+    const R c = (R)S.c, sn = (R)S.s;
+    const R f0 = (R)(q0 - i0), f1 = (R)(q1 - j0);  // q - (window corner)
+    for (int e1 = j0; e1 <= j1; ++e1) {
+      const R t1 = f1 - (R)(e1 - j0);
+      const R* kr = kref + (long long)g.D[0] * e1;
       for (int e0 = i0; e0 <= i1; ++e0) {
-        const long long k = e0 + (long long)g.D[0] * e1;
-        const J2Pt p = j2_point(g, S, k);
-        const double d0 = bx - p.X0, d1 = by - p.X1;
-        if (fabs(d0) < 2.0 && fabs(d1) < 2.0) {
-          const double wkr = wk(d0) * wk(d1) * (double)kref[k];
-          s0 += wkr * (a0 - b * p.v1);
-          s1 += wkr * (a1 + b * p.v0);
+        const R t0 = f0 - (R)(e0 - i0);
+        const R d0 = sn * t1 - c * t0, d1 = -(sn * t0 + c * t1);  // X_k - x = R (e - q)
+        if (fabs(d0) < R(2) && fabs(d1) < R(2)) {
+          const R w = wk(d0) * wk(d1) * kr[e0];
+          m0 += w;
+          m1 += w * d0;
+          m2 += w * d1;
         }
       }
+    }
   }
+  double a0, a1, b;
+  j2_coef(g, S, a0, a1, b);
+  const double vx = bx - S.xg[0], vy = by - S.xg[1];
   const double sc = dJ[0];
+  const double s0 = (a0 - b * vy) * (double)m0 - b * (double)m2;
+  const double s1 = (a1 + b * vx) * (double)m0 + b * (double)m1;
   const long long bi = i + (long long)box.sx * j;
   js[bi] = (R)(sc * s0);
   js[box.vol + bi] = (R)(sc * s1);
@@ -2208,7 +2235,8 @@ __global__ __launch_bounds__(J2_THREADS) void k_j2_adj(Geo g, const R* kref, con
   const long long k = blockIdx.x * (long long)J2_THREADS + threadIdx.x;
   double part[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (k < g.Mtot) {
-    const J2Pt p = j2_point(g, S, k);
+    const int k1 = (int)(k / g.D[0]);
+    const J2Pt p = j2_point(g, S, (int)k - k1 * g.D[0], k1);
     double ur[2] = {0.0, 0.0}, dur[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
     j2_gather<R, true>(g, st, p.X0, p.X1, ur, dur);
     double a0, a1, b;
@@ -2928,10 +2956,10 @@ hipError_t launch_j2_final(const Geo& g, const double* jacc, double* J3, hipStre
 }
 
 hipError_t launch_j2_seed(const Geo& g, int precision, const void* kref, const StepInfo* si,
-                          const Box& box, const double* dJ, void* js, hipStream_t s) {
+                          const Box& box, const double* dJ, void* js, int nsteps, hipStream_t s) {
   // box: the largest step box (strides, volume and launch extents)
   const long long nodes = (long long)box.ext[0] * box.ext[1];
-  const dim3 grid((unsigned)((nodes + J2_THREADS - 1) / J2_THREADS));
+  const dim3 grid((unsigned)((nodes + J2_THREADS - 1) / J2_THREADS), nsteps);
   if (precision == 0)
     LKS_LAUNCH(k_j2_seed<float>, grid, dim3(J2_THREADS), 0, s, g, (const float*)kref, si, box,
                dJ, (float*)js);

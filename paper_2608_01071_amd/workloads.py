@@ -197,6 +197,23 @@ def c2(seed: int = 1, precision: int = 0, nt: int = 20000):
     return make_2d(512, 256, nt, 2000, nu=0.018, seed=seed, precision=precision, ckpt_k=200)
 
 
+def oar(nside: int = 512, mside: int = 256, nt: int = 4000, seed: int = 4, precision: int = 0,
+        ckpt_k: int = 100):
+    """The 2D oar setting of Sec. 4.2 on a D2Q9 channel (periodic x, walls
+    in y): objective J2 with w_D = 0.01, w_T = 0.15 and l_m half the design
+    grid's diagonal; the design grid translates vertically only and rotates;
+    nu = 0.1, kappa_max = 300, q = 0.1, R_t = 1000 and R_w = 2000 steps
+    (capped at nt).  The domain size is not given in the text: a square
+    channel of side nside with an mside^2 design grid stands in for it."""
+    p, gamma, chi, psi = make_2d(nside, mside, nt, min(1000, nt), nu=0.1, seed=seed,
+                                 precision=precision, ckpt_k=min(ckpt_k, nt))
+    x0 = p.xg_min[0] + 0.5 * (p.xg_max[0] - p.xg_min[0])
+    p = p.replace(xg_min=(x0, p.xg_min[1], 0.0), xg_max=(x0, p.xg_max[1], 0.0),
+                  r_w=min(2000, nt), objective=1, w_d=0.01, w_t=0.15,
+                  l_m=0.5 * math.sqrt(2.0) * mside)
+    return p, gamma, chi, psi
+
+
 def c3(seed: int = 2, precision: int = 0, nt: int = 10000, ckpt_k: int = 100):
     """D2Q9 1024x1024, 512x512 design, 10000 steps."""
     return make_2d(1024, 512, nt, 1000, nu=0.02, seed=seed, precision=precision,

@@ -85,6 +85,10 @@ def test_plan_validation_and_workspace(L):
     assert L.lks_plan_create(C.byref(s6), C.byref(h6), C.byref(nb6)) == 0
     assert nb6.value > nb.value
     L.lks_plan_destroy(h6)
+    po, *_ = W.oar(nt=20)
+    assert po.objective == 1 and po.xg_min[0] == po.xg_max[0]
+    assert L.lks_plan_create(C.byref(lks.to_struct(po)), C.byref(h6), C.byref(nb6)) == 0
+    L.lks_plan_destroy(h6)
     bad = [p.replace(d=4), p.replace(n=(64, 3, 1)), p.replace(nt=0), p.replace(r_t=0),
            p.replace(ckpt_k=500), p.replace(precision=2), p.replace(q=0.0),
            p.replace(scheme=2), p.replace(scheme=-1), p.replace(objective=2),
