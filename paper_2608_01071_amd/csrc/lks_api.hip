@@ -371,15 +371,23 @@ lks_status forward_loop(lks_plan* P, void* ws, hipStream_t s) {
     void* out = (n % P->K == 0 && n / P->K < P->nck) ? ck_slot(P, ws, n / P->K)
                                                       : pp_slot(P, ws, n & 1);
     void* body = fwd_body(P, ws, n);
-    if (lks_status e = map_step(P, ws, n, body, s)) return e;
+    if (P->j2 && n > 1) {
+      // J2: the step sums of state n - 1 ride along with this step's map
+      Scope sc("map", s, true);
+      HIPCHK(launch_map_j2(P->g, P->prec, wsp(ws, P->o_kref), tab(P, ws, n), P->bmax, body,
+                           (char*)body + P->bmax.vol * P->es, tab(P, ws, n - 1), in,
+                           (double*)wsp(ws, P->o_j2acc), s));
+    } else if (lks_status e = map_step(P, ws, n, body, s)) {
+      return e;
+    }
     if (lks_status e = fwd_step(P, ws, n, in, out, body, n == 1 ? P->first_lazy : 1, !P->j2, s))
       return e;
-    if (P->j2) {
-      Scope sc("j2_fwd", s, true);
-      HIPCHK(launch_j2_forward(P->g, P->prec, wsp(ws, P->o_kref), tab(P, ws, n), out,
-                               (double*)wsp(ws, P->o_j2acc), s));
-    }
     in = out;
+  }
+  if (P->j2) {
+    Scope sc("j2_fwd", s, true);
+    HIPCHK(launch_j2_forward(P->g, P->prec, wsp(ws, P->o_kref), tab(P, ws, P->g.nt), in,
+                             (double*)wsp(ws, P->o_j2acc), s));
   }
   if (P->j2)
     HIPCHK(launch_j2_final(P->g, (const double*)wsp(ws, P->o_j2acc), (double*)wsp(ws, P->o_J3), s));

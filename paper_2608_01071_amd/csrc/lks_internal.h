@@ -225,6 +225,11 @@ hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
 int j2_blocks(const Geo& g);
 hipError_t launch_j2_forward(const Geo& g, int precision, const void* kref, const StepInfo* si,
                              const void* st, double* jacc, hipStream_t s);
+// 2D: the transfer of step si into the body fields (bk, bu on the box) and
+// the J2 step sums of state jst after step jsi, in one launch.
+hipError_t launch_map_j2(const Geo& g, int precision, const void* kref, const StepInfo* si,
+                         const Box& box, void* bk, void* bu, const StepInfo* jsi, const void* jst,
+                         double* jacc, hipStream_t s);
 hipError_t launch_j2_final(const Geo& g, const double* jacc, double* J3, hipStream_t s);
 hipError_t launch_j2_seed(const Geo& g, int precision, const void* kref, const StepInfo* si,
                           const Box& box, const double* dJ, void* js, int nsteps, hipStream_t s);

@@ -2128,9 +2128,9 @@ __device__ __forceinline__ void j2_gather(const Geo& g, const R* st, double X0, 
 // Step sums of one step, one thread per design point: each block adds its
 // fixed-order partial to its own slot of jacc [blocks][3].
 template <class R>
-__global__ __launch_bounds__(J2_THREADS) void k_j2_fwd(Geo g, const R* kref, const StepInfo* si,
-                                                       const R* st, double* jacc) {
-  const long long k = blockIdx.x * (long long)J2_THREADS + threadIdx.x;
+__device__ __forceinline__ void j2_fwd_block(const Geo& g, const R* kref, const StepInfo* si,
+                                             const R* st, double* jacc, int bid) {
+  const long long k = bid * (long long)J2_THREADS + threadIdx.x;
   double part[3] = {0.0, 0.0, 0.0};
   if (k < g.Mtot) {
     const StepInfo S = *si;
@@ -2147,7 +2147,31 @@ __global__ __launch_bounds__(J2_THREADS) void k_j2_fwd(Geo g, const R* kref, con
   double tot[3];
   block_sum<3, J2_THREADS>(part, tot);
   if (threadIdx.x == 0)
-    for (int q = 0; q < 3; ++q) jacc[blockIdx.x * 3 + q] += tot[q];
+    for (int q = 0; q < 3; ++q) jacc[bid * 3 + q] += tot[q];
+}
+
+template <class R>
+__global__ __launch_bounds__(J2_THREADS) void k_j2_fwd(Geo g, const R* kref, const StepInfo* si,
+                                                       const R* st, double* jacc) {
+  j2_fwd_block<R>(g, kref, si, st, jacc, blockIdx.x);
+}
+
+// The transfer of step n and the J2 step sums of state n - 1 in one launch
+// (both are short, latency-bound kernels with no dependence on each other):
+// blocks [0, nmap) map, the rest sum.
+template <class R>
+__global__ __launch_bounds__(J2_THREADS) void k_map2d_j2(Geo g, const R* kref, Box box,
+                                                         const StepInfo* si, R* bk, R* bu, int nbx,
+                                                         int nmap, const StepInfo* jsi,
+                                                         const R* jst, double* jacc) {
+  static_assert(MAP2_TX * MAP2_TY == J2_THREADS, "one block size for both parts");
+  const int b = blockIdx.x;
+  if (b < nmap) {
+    Mot m{};  // taken from si
+    map2d_row<R>(g, kref, m, box, si, bk, bu, 0, b % nbx, b / nbx);
+    return;
+  }
+  j2_fwd_block<R>(g, kref, jsi, jst, jacc, b - nmap);
 }
 
 // J_out = (J2, F_L, F_D) from the block slots, in a fixed order.
@@ -2947,6 +2971,20 @@ hipError_t launch_j2_forward(const Geo& g, int precision, const void* kref, cons
   else
     LKS_LAUNCH(k_j2_fwd<double>, grid, dim3(J2_THREADS), 0, s, g, (const double*)kref, si,
                (const double*)st, jacc);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_j2(const Geo& g, int precision, const void* kref, const StepInfo* si,
+                         const Box& box, void* bk, void* bu, const StepInfo* jsi, const void* jst,
+                         double* jacc, hipStream_t s) {
+  const int nbx = (box.ext[0] + MAP2_TX - 1) / MAP2_TX, nby = (box.ext[1] + MAP2_TY - 1) / MAP2_TY;
+  const dim3 grid(nbx * nby + j2_blocks(g));
+  if (precision == 0)
+    LKS_LAUNCH(k_map2d_j2<float>, grid, dim3(J2_THREADS), 0, s, g, (const float*)kref, box, si,
+               (float*)bk, (float*)bu, nbx, nbx * nby, jsi, (const float*)jst, jacc);
+  else
+    LKS_LAUNCH(k_map2d_j2<double>, grid, dim3(J2_THREADS), 0, s, g, (const double*)kref, box, si,
+               (double*)bk, (double*)bu, nbx, nbx * nby, jsi, (const double*)jst, jacc);
   return hipGetLastError();
 }
 
