@@ -2,15 +2,18 @@
  * lks_oracle.h -- TEST INFRASTRUCTURE ONLY.
  *
  * A plain, slow, double-precision CPU reference of the Lattice Kinetic Scheme
- * (LKS) time march with a rigidly moving Brinkman body, the objective J1, and
- * the exact discrete adjoint of that march (shape and motion sensitivities).
+ * (LKS) time march with a rigidly moving Brinkman body, the objectives J1 and
+ * J2, the exact discrete adjoint of that march and the paper's ALKS (shape and
+ * motion sensitivities), and the optimiser-side filter, projection and
+ * constraints.
  * It exists to check the GPU library; only the test suite, the smoke check and
  * the benchmark's CPU-baseline leg may load it.  It shares no source with the
  * GPU library.
  *
  * Paper: Tanabe, Yaji, Ushijima, "4D topology optimization of moving rigid
  * bodies in fluid flows".  Sections cited: 2.2 (LKS), 2.3 (grid separation),
- * 2.4 (motion representation), 2.5 (sensitivities), 2.6 (objective J1).
+ * 2.4 (motion representation), 2.5 (sensitivities), 2.6 (objectives and
+ * constraints), 3.1 (filter and projection).
  *
  * Conventions (lattice units, dx = dt = 1):
  *   - analysis fields are stored as planes [d+1][N]: plane 0 is the pressure p
