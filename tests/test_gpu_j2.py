@@ -12,6 +12,8 @@ the J1 parity tests.
 import numpy as np
 import pytest
 
+from paper_2608_01071_amd import workloads as W
+
 from test_gpu_parity import cpu, l2err, lk, prob2d, rand_inputs
 
 pytestmark = pytest.mark.gpu
@@ -100,3 +102,34 @@ def test_j2_in_a_batch_matches_solo_runs(orc):
         assert np.array_equal(cpu(J3), solo[k][0]), k
         for key in ("dgamma", "dchi", "dpsi"):
             assert np.array_equal(cpu(gr[key]), solo[k][1][key]), (k, key)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_oar_full_size_first_steps(orc, scheme):
+    """The 2D oar workload at the size the benchmark runs (512^2, 256^2
+    design) in the plan its problem statement builds: the first three steps
+    of its motion (two checkpoint segments, the second ragged) from a random
+    start state with a mean flow, J2 and all three gradients on every point
+    against the oracle, FP64 and FP32.  (Without the mean flow the forces of
+    a random field nearly cancel: J2 is then some 1e-3 of its terms, and the
+    FP32 state's rounding moves it by about 5e-5 of itself.)"""
+    from test_gpu_parity import gpu_state, rand_state
+    p, gamma, chi, psi = W.oar()
+    p3 = p.replace(nt=3, ckpt_k=2, precision=1, scheme=scheme)
+    s0 = rand_state(p3, 61, amp=0.02)
+    s0[p3.N: 2 * p3.N] += 0.03
+    ref = orc.forward(p3, gamma, chi[:3], psi[:3], state0=s0, want_final=False)
+    adj = (orc.adjoint if scheme == 0 else orc.alks_adjoint)(p3, gamma, chi[:3], psi[:3],
+                                                            state0=s0)
+    for prec in (1, 0):
+        pp = p3.replace(precision=prec)
+        plan = lk().Plan(pp)
+        J3, _ = plan.forward(gamma, chi[:3], psi[:3], state0=gpu_state(s0, pp))
+        g = plan.adjoint(gamma, chi[:3], psi[:3])
+        tj, tg = (1e-10, 1e-9) if prec == 1 else (1e-5, 1e-3)
+        for k, key in enumerate(("J", "E", "V")):
+            assert abs(cpu(J3)[k] - ref[key]) <= tj * abs(ref[key]), (prec, key)
+        for k in ("dgamma", "dchi", "dpsi"):
+            assert np.linalg.norm(adj[k]) > 0, k
+            assert l2err(cpu(g[k]), adj[k]) < tg, (prec, k)
+        del plan
