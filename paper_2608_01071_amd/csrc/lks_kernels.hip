@@ -2156,6 +2156,24 @@ __global__ __launch_bounds__(J2_THREADS) void k_j2_fwd(Geo g, const R* kref, con
   j2_fwd_block<R>(g, kref, si, st, jacc, blockIdx.x);
 }
 
+// 2D: the LKS step n and the transfer of step n + 1 (into another body
+// slot) in one launch: both are short, latency-bound kernels and neither
+// depends on the other.  Blocks [0, nstep) step, the rest map.
+template <class R>
+__global__ __launch_bounds__(STEP_THREADS) void k_fwd2d_map(Geo g, FwdArgs a, int nstep,
+                                                           const R* kref, Box box,
+                                                           const StepInfo* msi, R* bk, R* bu,
+                                                           int nbx) {
+  static_assert(MAP2_TX * MAP2_TY == STEP_THREADS, "one block size for both parts");
+  const int b = blockIdx.x;
+  if (b < nstep) {
+    fwd2d_tile<R>(g, a, b);
+    return;
+  }
+  Mot m{};  // taken from msi
+  map2d_row<R>(g, kref, m, box, msi, bk, bu, 0, (b - nstep) % nbx, (b - nstep) / nbx);
+}
+
 // The transfer of step n and the J2 step sums of state n - 1 in one launch
 // (both are short, latency-bound kernels with no dependence on each other):
 // blocks [0, nmap) map, the rest sum.
@@ -2971,6 +2989,22 @@ hipError_t launch_j2_forward(const Geo& g, int precision, const void* kref, cons
   else
     LKS_LAUNCH(k_j2_fwd<double>, grid, dim3(J2_THREADS), 0, s, g, (const double*)kref, si,
                (const double*)st, jacc);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_step_map(const Geo& g, int precision, const FwdArgs& a,
+                                  const void* kref, const StepInfo* msi, const Box& box, void* bk,
+                                  void* bu, hipStream_t s) {
+  const dim3 sg = step_grid(g);
+  const int nstep = (int)(sg.x * sg.y * sg.z);
+  const int nbx = (box.ext[0] + MAP2_TX - 1) / MAP2_TX, nby = (box.ext[1] + MAP2_TY - 1) / MAP2_TY;
+  const dim3 grid(nstep + nbx * nby);
+  if (precision == 0)
+    LKS_LAUNCH(k_fwd2d_map<float>, grid, dim3(STEP_THREADS), 0, s, g, a, nstep,
+               (const float*)kref, box, msi, (float*)bk, (float*)bu, nbx);
+  else
+    LKS_LAUNCH(k_fwd2d_map<double>, grid, dim3(STEP_THREADS), 0, s, g, a, nstep,
+               (const double*)kref, box, msi, (double*)bk, (double*)bu, nbx);
   return hipGetLastError();
 }
 
