@@ -366,27 +366,36 @@ lks_status forward_loop(lks_plan* P, void* ws, hipStream_t s) {
   // Each step's map runs right before its step, which then reads the body
   // fields from cache.  (Mapping every step up front in a few wide launches
   // costs as much per step: the map is bound by its stores, not by how well
-  // one step fills the GPU.)  In 2D with a body slot per step, step n and
-  // the map of step n + 1 share one launch.
-  if (P->g.d == 2 && P->full_btape && !P->j2) {
+  // one step fills the GPU.)  In 2D with a body slot per step, step n, the
+  // map of step n + 1 and (J2) the step sums of state n - 1 share one launch.
+  if (P->g.d == 2 && P->full_btape) {
     if (lks_status e = map_step(P, ws, 1, fwd_body(P, ws, 1), s)) return e;
-    for (int n = 1; n <= P->g.nt; ++n) {
+    const int nt = P->g.nt;
+    double* jacc = (double*)wsp(ws, P->o_j2acc);
+    for (int n = 1; n <= nt; ++n) {
       void* out = (n % P->K == 0 && n / P->K < P->nck) ? ck_slot(P, ws, n / P->K)
                                                         : pp_slot(P, ws, n & 1);
       const FwdArgs a = fwd_args(P, ws, n, in, out, fwd_body(P, ws, n),
-                                 n == 1 ? P->first_lazy : 1, 1);
+                                 n == 1 ? P->first_lazy : 1, !P->j2);
+      char* nb = n < nt ? (char*)fwd_body(P, ws, n + 1) : nullptr;
+      const bool j2 = P->j2 && n > 1;
       Scope sc("fwd_step", s, true);
-      if (n < P->g.nt) {
-        void* nb = fwd_body(P, ws, n + 1);
-        HIPCHK(launch_forward_step_map(P->g, P->prec, a, wsp(ws, P->o_kref), tab(P, ws, n + 1),
-                                       P->bmax, nb, (char*)nb + P->bmax.vol * P->es, s));
-      } else {
-        HIPCHK(launch_forward_step(P->g, P->prec, a, s));
-      }
+      HIPCHK(launch_forward_step_map(P->g, P->prec, a, wsp(ws, P->o_kref),
+                                     nb ? tab(P, ws, n + 1) : nullptr, P->bmax, nb,
+                                     nb ? nb + P->bmax.vol * P->es : nullptr,
+                                     j2 ? tab(P, ws, n - 1) : nullptr, j2 ? in : nullptr, jacc, s));
       in = out;
     }
-    HIPCHK(launch_objective_final(P->g, (const double*)wsp(ws, P->o_opart), step_blocks(P->g),
-                                  (double*)wsp(ws, P->o_J3), s));
+    if (P->j2) {
+      {
+        Scope sc("j2_fwd", s, true);
+        HIPCHK(launch_j2_forward(P->g, P->prec, wsp(ws, P->o_kref), tab(P, ws, nt), in, jacc, s));
+      }
+      HIPCHK(launch_j2_final(P->g, jacc, (double*)wsp(ws, P->o_J3), s));
+    } else {
+      HIPCHK(launch_objective_final(P->g, (const double*)wsp(ws, P->o_opart), step_blocks(P->g),
+                                    (double*)wsp(ws, P->o_J3), s));
+    }
     return LKS_OK;
   }
   for (int n = 1; n <= P->g.nt; ++n) {

@@ -225,11 +225,13 @@ hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
 int j2_blocks(const Geo& g);
 hipError_t launch_j2_forward(const Geo& g, int precision, const void* kref, const StepInfo* si,
                              const void* st, double* jacc, hipStream_t s);
-// 2D: the LKS step of `a` and the transfer of step msi into the body fields
-// (bk, bu on the box; not the step's own), in one launch.
+// 2D: the LKS step of `a`, the transfer of step msi into the body fields
+// (bk, bu on the box; not the step's own; msi null: none) and, when jst is
+// non-null, the J2 step sums of state jst after step jsi, in one launch.
 hipError_t launch_forward_step_map(const Geo& g, int precision, const FwdArgs& a,
                                   const void* kref, const StepInfo* msi, const Box& box, void* bk,
-                                  void* bu, hipStream_t s);
+                                  void* bu, const StepInfo* jsi, const void* jst, double* jacc,
+                                  hipStream_t s);
 // 2D: the transfer of step si into the body fields (bk, bu on the box) and
 // the J2 step sums of state jst after step jsi, in one launch.
 hipError_t launch_map_j2(const Geo& g, int precision, const void* kref, const StepInfo* si,

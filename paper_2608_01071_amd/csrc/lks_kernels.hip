@@ -2159,19 +2159,28 @@ __global__ __launch_bounds__(J2_THREADS) void k_j2_fwd(Geo g, const R* kref, con
 // 2D: the LKS step n and the transfer of step n + 1 (into another body
 // slot) in one launch: both are short, latency-bound kernels and neither
 // depends on the other.  Blocks [0, nstep) step, the rest map.
+// With J2 (jst non-null) a third range of blocks adds the J2 step sums of
+// the step's input state (after step jsi), which the step only reads.
 template <class R>
 __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d_map(Geo g, FwdArgs a, int nstep,
                                                            const R* kref, Box box,
                                                            const StepInfo* msi, R* bk, R* bu,
-                                                           int nbx) {
-  static_assert(MAP2_TX * MAP2_TY == STEP_THREADS, "one block size for both parts");
+                                                           int nbx, int nmap,
+                                                           const StepInfo* jsi, const R* jst,
+                                                           double* jacc) {
+  static_assert(MAP2_TX * MAP2_TY == STEP_THREADS && J2_THREADS == STEP_THREADS,
+                "one block size for every part");
   const int b = blockIdx.x;
   if (b < nstep) {
     fwd2d_tile<R>(g, a, b);
     return;
   }
-  Mot m{};  // taken from msi
-  map2d_row<R>(g, kref, m, box, msi, bk, bu, 0, (b - nstep) % nbx, (b - nstep) / nbx);
+  if (b < nstep + nmap) {
+    Mot m{};  // taken from msi
+    map2d_row<R>(g, kref, m, box, msi, bk, bu, 0, (b - nstep) % nbx, (b - nstep) / nbx);
+    return;
+  }
+  j2_fwd_block<R>(g, kref, jsi, jst, jacc, b - nstep - nmap);
 }
 
 // The transfer of step n and the J2 step sums of state n - 1 in one launch
@@ -2994,17 +3003,21 @@ hipError_t launch_j2_forward(const Geo& g, int precision, const void* kref, cons
 
 hipError_t launch_forward_step_map(const Geo& g, int precision, const FwdArgs& a,
                                   const void* kref, const StepInfo* msi, const Box& box, void* bk,
-                                  void* bu, hipStream_t s) {
+                                  void* bu, const StepInfo* jsi, const void* jst, double* jacc,
+                                  hipStream_t s) {
   const dim3 sg = step_grid(g);
   const int nstep = (int)(sg.x * sg.y * sg.z);
-  const int nbx = (box.ext[0] + MAP2_TX - 1) / MAP2_TX, nby = (box.ext[1] + MAP2_TY - 1) / MAP2_TY;
-  const dim3 grid(nstep + nbx * nby);
+  const int nbx = msi ? (box.ext[0] + MAP2_TX - 1) / MAP2_TX : 0;
+  const int nmap = msi ? nbx * ((box.ext[1] + MAP2_TY - 1) / MAP2_TY) : 0;
+  const dim3 grid(nstep + nmap + (jst ? j2_blocks(g) : 0));
   if (precision == 0)
     LKS_LAUNCH(k_fwd2d_map<float>, grid, dim3(STEP_THREADS), 0, s, g, a, nstep,
-               (const float*)kref, box, msi, (float*)bk, (float*)bu, nbx);
+               (const float*)kref, box, msi, (float*)bk, (float*)bu, nbx, nmap, jsi,
+               (const float*)jst, jacc);
   else
     LKS_LAUNCH(k_fwd2d_map<double>, grid, dim3(STEP_THREADS), 0, s, g, a, nstep,
-               (const double*)kref, box, msi, (double*)bk, (double*)bu, nbx);
+               (const double*)kref, box, msi, (double*)bk, (double*)bu, nbx, nmap, jsi,
+               (const double*)jst, jacc);
   return hipGetLastError();
 }
 
