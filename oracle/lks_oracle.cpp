@@ -972,17 +972,10 @@ struct Oracle {
   // copy of p never multiplies the source node's velocity, so the coupling
   // in V keeps the node's own p~.  The forward never gathers into a wall
   // node, so no adjoint leaves one: f~eq is zero there.
-  // cfix (nullable): a given coupling part, V = 3 u~ + cfix, in place of
-  // the one formed from p~, s~ and u (a carried terminal state, below).
   void alks_equilibria(const T* pt, const T* pw, const T* ut, const T* sl, const T* u,
-                       std::vector<T>& ft, const T* cfix = nullptr) const {
+                       std::vector<T>& ft) const {
     std::vector<T> V;
-    if (cfix) {
-      V.assign((size_t)d * N, T(0.0));
-      for (long i = 0; i < (long)d * N; ++i) V[i] = 3.0 * ut[i] + cfix[i];
-    } else {
-      alks_vector(pt, ut, sl, u, V);
-    }
+    alks_vector(pt, ut, sl, u, V);
     ft.assign((size_t)L.Q * N, T(0.0));
     for (long y = 0; y < N; ++y) {
       int x[3];
@@ -1020,13 +1013,30 @@ struct Oracle {
     }
   }
 
-  // Full ALKS backward.  adj_initial (nullable, [2d+1][N]) receives
-  // (-3 p~, -V, -3 u~) of level 0: the scheme's estimate of dJ/d(state0) in
-  // the forward's variables (the multipliers carry the opposite sign),
-  // followed by the raw first moment alone.  adj_terminal (nullable, same
-  // layout) is the state carried from an earlier run's adj_initial for the
-  // periodic approximation (Sec. 3.3): it stands for the gathered moments of
-  // the last level, with its coupling part (-V + 3 u~) taken as given.
+  // Symmetric components of s~ in the carried state: (xx, yy, xy) in 2D,
+  // (xx, yy, zz, xy, xz, yz) in 3D.
+  int sym_count() const { return d * (d + 1) / 2; }
+  void sym_pair(int k, int& a, int& b) const {
+    if (k < d) {
+      a = b = k;
+      return;
+    }
+    const int off[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    a = off[k - d][0];
+    b = off[k - d][1];
+  }
+
+  // Full ALKS backward.  adj_initial (nullable, [(d+1) + 1 + d + d(d+1)/2][N])
+  // receives first (-3 p~, -V) of level 0, the scheme's estimate of
+  // dJ/d(state0) in the forward's variables (the multipliers carry the
+  // opposite sign), and then the ALKS state of level 0 itself: p~, u~ and
+  // the symmetric components of s~.  adj_terminal (nullable, same layout)
+  // carries an earlier run's state for the periodic approximation (Sec. 3.3,
+  // Algorithm 1): its (p~, u~, s~) part becomes the moments of the last
+  // level, t1, before that level's sources, exactly where a run without it
+  // starts from zero; the adjoint equilibria of that level are then formed
+  // like every other level's, with this run's velocity at t1.  Its first
+  // d+1 planes are not read.
   void alks_adjoint(const T* gamma, const T* chi, const T* psi, const T* state0, double dJ,
                     const T* adj_terminal, T* adj_initial, T* dg, T* dchi, T* dpsi,
                     T* kref_bar_out, T* mbar_out) const {
@@ -1043,16 +1053,18 @@ struct Oracle {
     std::vector<T> pw(N, T(0.0));
     std::vector<T> ft, kbar(N), usbar((size_t)d * N);
     std::vector<T> kref_bar(Mtot, T(0.0)), mbar((size_t)nt * 8, T(0.0));
-    // a carried terminal state: p~ = -pbar / 3, u~* = -X / 3 and the coupling
-    // part -(V - X) of the last level
-    std::vector<T> cfix;
     if (adj_terminal) {
-      cfix.assign((size_t)d * N, T(0.0));
-      for (long i = 0; i < N; ++i) pt[i] = -adj_terminal[i] / 3.0;
-      for (long i = 0; i < (long)d * N; ++i) {
-        const T Vt = adj_terminal[N + i], X = adj_terminal[(1 + d) * N + i];
-        ut[i] = -X / 3.0;
-        cfix[i] = -(Vt - X);
+      const T* c = adj_terminal + S;
+      for (long i = 0; i < N; ++i) pt[i] = c[i];
+      for (long i = 0; i < (long)d * N; ++i) ut[i] = c[N + i];
+      for (int k = 0; k < sym_count(); ++k) {
+        int a, b;
+        sym_pair(k, a, b);
+        for (long i = 0; i < N; ++i) {
+          const T v = c[(1 + d + k) * N + i];
+          sl[(size_t)(a * 3 + b) * N + i] = v;
+          sl[(size_t)(b * 3 + a) * N + i] = v;
+        }
       }
     }
     long NT = (long)nt * target_count();
@@ -1062,8 +1074,7 @@ struct Oracle {
       // after the last step, or the carried terminal state)
       if (t < nt) {
         alks_equilibria(pt.data(), pw.data(), ut.data(), sl.data(),
-                        &traj[(size_t)(t + 1) * S + N], ft,
-                        (t == nt - 1 && adj_terminal) ? cfix.data() : nullptr);
+                        &traj[(size_t)(t + 1) * S + N], ft);
         alks_gather(ft, pt.data(), ut.data(), sl.data());
       }
       map(kref.data(), &mot[(size_t)(t - 1) * 8], kappa.data(), us.data());
@@ -1120,17 +1131,19 @@ struct Oracle {
     }
     if (adj_initial) {
       // level 0: moments gathered from level 1, no sources
-      if (nt >= 1) {
-        alks_equilibria(pt.data(), pw.data(), ut.data(), sl.data(), &traj[(size_t)1 * S + N], ft,
-                        (nt == 1 && adj_terminal) ? cfix.data() : nullptr);
-        alks_gather(ft, pt.data(), ut.data(), sl.data());
-      }
+      alks_equilibria(pt.data(), pw.data(), ut.data(), sl.data(), &traj[(size_t)1 * S + N], ft);
+      alks_gather(ft, pt.data(), ut.data(), sl.data());
       std::vector<T> V;
       alks_vector(pt.data(), ut.data(), sl.data(), &traj[N], V);
       for (long i = 0; i < N; ++i) adj_initial[i] = -3.0 * pt[i];
-      for (long i = 0; i < (long)d * N; ++i) {
-        adj_initial[N + i] = -V[i];
-        adj_initial[(1 + d) * N + i] = -3.0 * ut[i];
+      for (long i = 0; i < (long)d * N; ++i) adj_initial[N + i] = -V[i];
+      T* c = adj_initial + S;
+      for (long i = 0; i < N; ++i) c[i] = pt[i];
+      for (long i = 0; i < (long)d * N; ++i) c[N + i] = ut[i];
+      for (int k = 0; k < sym_count(); ++k) {
+        int a, b;
+        sym_pair(k, a, b);
+        for (long i = 0; i < N; ++i) c[(1 + d + k) * N + i] = sl[(size_t)(a * 3 + b) * N + i];
       }
     }
     if (kref_bar_out) std::copy(kref_bar.begin(), kref_bar.end(), kref_bar_out);
@@ -1239,6 +1252,37 @@ int orc_alks_adjoint(const orc_problem* p, const double* gamma, const double* ch
   if (int e = validate(p)) return e;
   Oracle<double>(*p).alks_adjoint(gamma, chi, psi, state0, dJ, adj_terminal, adj_initial,
                                   dJ_dgamma, dJ_dchi, dJ_dpsi, kref_bar, motion_bar);
+  return 0;
+}
+
+int orc_alks_vector(const orc_problem* p, const double* carry, const double* u, double* V) {
+  if (int e = validate(p)) return e;
+  Oracle<double> o(*p);
+  const long N = o.N;
+  const int d = o.d;
+  std::vector<double> sl((size_t)9 * N, 0.0), Vv;
+  for (int k = 0; k < o.sym_count(); ++k) {
+    int a, b;
+    o.sym_pair(k, a, b);
+    for (long i = 0; i < N; ++i) {
+      sl[(size_t)(a * 3 + b) * N + i] = carry[(1 + d + k) * N + i];
+      sl[(size_t)(b * 3 + a) * N + i] = carry[(1 + d + k) * N + i];
+    }
+  }
+  o.alks_vector(carry, carry + N, sl.data(), u, Vv);
+  std::copy(Vv.begin(), Vv.end(), V);
+  return 0;
+}
+
+int orc_j2_sums(const orc_problem* p, const double* kappa_ref, const double* motion8,
+                const double* u, double* sums3) {
+  if (int e = validate(p)) return e;
+  if (p->d != 2) return -9;
+  double jl = 0.0, jd = 0.0, jt = 0.0;
+  Oracle<double>(*p).j2_sums(kappa_ref, motion8, u, jl, jd, jt);
+  sums3[0] = jl;
+  sums3[1] = jd;
+  sums3[2] = jt;
   return 0;
 }
 

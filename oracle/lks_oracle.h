@@ -98,15 +98,32 @@ int orc_adjoint(const orc_problem* p, const double* gamma, const double* chi,
 /* Paper-literal ALKS backward (Sec. 2.5): the continuous-adjoint lattice
  * kinetic scheme with the adjoint equilibrium and Eqs. ap_tmp .. as, run from
  * the last step to the first, and the sensitivities of Eqs. dJdgamma, dJdchi,
- * dJdpsi.  Outputs as orc_adjoint.  adj_initial (nullable, [2d+1][N]): the
- * scheme's estimate of dJ/d(state0) ([d+1][N]) followed by the raw first
- * moment 3 u~ in the forward's sign ([d][N]).  adj_terminal (nullable, same
- * layout): a state carried from an earlier run's adj_initial (periodic
- * approximation, Sec. 3.3). */
+ * dJdpsi.  Outputs as orc_adjoint.  adj_initial (nullable,
+ * [(d+1) + 1 + d + d(d+1)/2][N]): the scheme's estimate of dJ/d(state0)
+ * ([d+1][N]) followed by the ALKS state of level 0: p~ [N], u~ [d][N] and
+ * the symmetric components of s~ (xx, yy, xy in 2D; xx, yy, zz, xy, xz, yz
+ * in 3D).  adj_terminal (nullable, same layout; the first d+1 planes are not
+ * read): the state carried from an earlier run's adj_initial for the
+ * periodic approximation (Sec. 3.3, Algorithm 1), p~(t1) = p~(t0) of the
+ * earlier run and likewise u~, s~; it stands for the moments of the last
+ * level before that level's sources. */
 int orc_alks_adjoint(const orc_problem* p, const double* gamma, const double* chi,
                      const double* psi, const double* state0, double dJ,
                      const double* adj_terminal, double* adj_initial, double* dJ_dgamma,
                      double* dJ_dchi, double* dJ_dpsi, double* kref_bar, double* motion_bar);
+
+/* Vector of the adjoint equilibrium f~eq_i = p~ + c_i . V of one ALKS level
+ * (Sec. 2.5): carry = (p~ [N], u~ [d][N], symmetric s~ [d(d+1)/2][N]) as in
+ * the ALKS carried state, u [d][N] the level's velocity -> V [d][N],
+ * V = 3 (u~ + 3 s~ u - p~ u) - A d_b (s~_ab + s~_ba). */
+int orc_alks_vector(const orc_problem* p, const double* carry, const double* u, double* V);
+
+/* Objective J2 (Eq. objective2) step sums of one state, unnormalised: with
+ * f = kappa_ref (u_ref - u_S_ref) on the design points, sums3 receives
+ * (sum f_1, u^G_2 sum f_2, omega sum (v_1 f_2 - v_2 f_1)), v = x_ref - x^G;
+ * u [2][N] is the fluid velocity, motion8 the step's motion row.  2D only. */
+int orc_j2_sums(const orc_problem* p, const double* kappa_ref, const double* motion8,
+                const double* u, double* sums3);
 
 /* One ALKS level without sources: multipliers (p~ [N], u~ [d][N], s~ [9][N],
  * s~_ab in plane 3a+b) of level t+1 and that level's velocity u [d][N] ->

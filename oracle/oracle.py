@@ -177,11 +177,19 @@ def adjoint(p, gamma, chi, psi, state0=None, dJ=1.0, adj_terminal=None):
             "kref_bar": kb, "motion_bar": mb.reshape(p.nt, 8)}
 
 
+def alks_state_size(p) -> int:
+    """Values of the ALKS adj_initial / adj_terminal: the dJ/d(state0)
+    estimate [d+1][N], then p~ [N], u~ [d][N] and the symmetric s~
+    [d(d+1)/2][N]."""
+    return (p.d + 1 + 1 + p.d + p.d * (p.d + 1) // 2) * p.N
+
+
 def alks_adjoint(p, gamma, chi, psi, state0=None, dJ=1.0, adj_terminal=None):
     """Paper-literal ALKS backward (Sec. 2.5); outputs as adjoint(), with
-    adj_initial [2d+1][N] (dJ/d(state0) estimate, then the raw first moment);
-    adj_terminal: the same layout, carried from an earlier run."""
-    S = (2 * p.d + 1) * p.N
+    adj_initial of alks_state_size(p) values (the dJ/d(state0) estimate, then
+    the ALKS state p~, u~, s~ of level 0); adj_terminal: the same layout,
+    carried from an earlier run (Algorithm 1's periodic approximation)."""
+    S = alks_state_size(p)
     ai = np.zeros(S)
     dg = np.zeros(p.M)
     dc = np.zeros(p.nt * 3)
@@ -195,6 +203,24 @@ def alks_adjoint(p, gamma, chi, psi, state0=None, dJ=1.0, adj_terminal=None):
            "orc_alks_adjoint")
     return {"adj_initial": ai, "dgamma": dg, "dchi": dc.reshape(p.nt, 3), "dpsi": dp,
             "kref_bar": kb, "motion_bar": mb.reshape(p.nt, 8)}
+
+
+def alks_vector(p, carry, u):
+    """V of the ALKS adjoint equilibrium for carry = (p~, u~, symmetric s~)
+    [(1 + d + d(d+1)/2)][N] and the level's velocity u [d][N]."""
+    out = np.zeros(p.d * p.N)
+    _check(lib().orc_alks_vector(C.byref(to_struct(p)), _ptr(_f64(carry)), _ptr(_f64(u)),
+                                 _ptr(out)), "orc_alks_vector")
+    return out
+
+
+def j2_sums(p, kref, motion8, u):
+    """Unnormalised J2 step sums (sum f_1, u^G_2 sum f_2, omega sum v x f) of
+    the fluid velocity u [2][N] at one step's motion (Eq. objective2)."""
+    out = np.zeros(3)
+    _check(lib().orc_j2_sums(C.byref(to_struct(p)), _ptr(_f64(kref)), _ptr(_f64(motion8)),
+                             _ptr(_f64(u)), _ptr(out)), "orc_j2_sums")
+    return out
 
 
 def alks_gather(p, fields_next, u_next):
