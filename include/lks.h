@@ -159,9 +159,15 @@ lks_status lks_forward(lks_plan* plan, const double* gamma, const double* chi,
  *   approximation of Sec. 3.3).
  * adj_initial: receives dJ/d(state0) (nullable).
  *   Both are [d+1][N] (state type) with the exact adjoint.  With the ALKS
- *   they are [2d+1][N]: the scheme's estimate of dJ/d(state0), then the raw
- *   first-moment part 3 u~ of its adjoint velocity, so that a run's
- *   adj_initial can be carried into the next run's adj_terminal.
+ *   they are [(d+1) + 1 + d + d(d+1)/2][N]: the scheme's estimate of
+ *   dJ/d(state0) ([d+1][N]), then the ALKS state itself, p~ [N], u~ [d][N]
+ *   and the symmetric components of s~ ((xx, yy, xy) in 2D, (xx, yy, zz,
+ *   xy, xz, yz) in 3D), in the paper's sign.  adj_terminal reads only that
+ *   state: as Algorithm 1's periodic approximation prescribes, p~(t1) =
+ *   p~(t0) of an earlier run and likewise u~ and s~; it takes the place of
+ *   the moments of the last level (before that level's sources), whose
+ *   adjoint equilibrium is then formed with this run's own velocity at t1.
+ *   A run's adj_initial can be passed as the next run's adj_terminal.
  * dJ_dgamma [m2][m1][m0], dJ_dchi [nt][3], dJ_dpsi [nt]: gradients of J
  *   (the paper maximises J; these are +grad J).
  * Recomputes each K-step segment from its checkpoint. */
@@ -299,6 +305,11 @@ lks_status lks_profile_enable(int32_t on);
 int32_t lks_profile_read(const char** names, double* total_ms, int64_t* launches, int32_t cap);
 
 const char* lks_last_error(void);
+
+/* SHA-256 (hex) of the sources the library was built from, as computed by
+ * the build; "unknown" for a build that did not supply it.  The Python
+ * binding refuses a library whose digest differs from its sources. */
+const char* lks_source_digest(void);
 
 #ifdef __cplusplus
 }

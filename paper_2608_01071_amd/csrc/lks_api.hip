@@ -122,6 +122,21 @@ struct GraphCache {
 
 }  // namespace
 
+namespace lks {
+void device_counts(int* ncu, int* nxcd) {
+  int dev = 0, cu = 0, xcc = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+    *ncu = cu;
+  if (hipDeviceGetAttribute(&xcc, hipDeviceAttributeNumberOfXccs, dev) == hipSuccess && xcc > 0)
+    *nxcd = xcc;
+  (void)hipGetLastError();
+}
+}  // namespace lks
+
 struct lks_plan {
   lks_problem prob;
   Geo g;
@@ -138,7 +153,7 @@ struct lks_plan {
   Box bmax;     // strides, volume and launch extents of the body buffers
   // workspace offsets (bytes)
   size_t o_mot, o_tab, o_info, o_kref, o_flags, o_J3, o_seed, o_opart, o_ck, o_pp, o_tape,
-      o_body, o_btape, o_badj, o_lam, o_xadj, o_cmot, o_badjt, o_kpart, o_krefbar, o_mpart, o_mbar, o_den, o_kz, o_geo, o_j2acc, o_j2seed, total;
+      o_body, o_btape, o_badj, o_lam, o_xadj, o_acarry, o_inp, o_cmot, o_badjt, o_kpart, o_krefbar, o_mpart, o_mbar, o_den, o_kz, o_geo, o_j2acc, o_j2seed, total;
   int first_lazy = 1;
   void* fwd_ws = nullptr;
   bool use_graphs = true;
@@ -245,12 +260,15 @@ void fill_geo(const lks_problem& p, Geo& g) {
   // z segments: enough blocks to fill every CU with the resident block count
   // of each 3D step kernel, but no segment shorter than 4 planes (each
   // segment re-reads 2 halo planes)
+  int ncu = 256, nxcd = 8;
+  device_counts(&ncu, &nxcd);
+  g.nxcd = nxcd;
   g.zseg = g.zseg_f = 1;
   if (g.d == 3) {
     const long long tiles = (long long)((g.n[0] - g.org[0] + TILE_X - 1) / TILE_X) *
                             ((g.n[1] - g.org[1] + g.ty3 - 1) / g.ty3);
     auto seg_for = [&](int resident) {
-      const long long want = (long long)resident * CU_COUNT;
+      const long long want = (long long)resident * ncu;
       long long nseg = std::max(1LL, (want + tiles - 1) / tiles);
       int zs = (int)((g.n[2] + nseg - 1) / nseg);
       return std::max(std::min(zs, g.n[2]), std::min(4, g.n[2]));
@@ -329,6 +347,14 @@ lks_status prelude(lks_plan* P, const double* gamma, const double* chi, const do
   if (!gamma || !chi || !psi || !ws) return fail(LKS_EINVAL, "null input pointer");
   double* mot = (double*)wsp(ws, P->o_mot);
   int* info = (int*)wsp(ws, P->o_info);
+  {
+    // the inputs the march is run for (lks_adjoint checks its own against them)
+    double* inp = (double*)wsp(ws, P->o_inp);
+    const size_t M = (size_t)inner_points(P->g), nt = (size_t)P->g.nt;
+    HIPCHK(hipMemcpyAsync(inp, gamma, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(inp + M, chi, 3 * nt * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(inp + M + 3 * nt, psi, nt * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
   {
     Scope sc("prelude", s);
     HIPCHK(launch_zero(info, 64 * sizeof(int), s));
@@ -462,6 +488,7 @@ AdjArgs adj_args(lks_plan* P, void* ws, int n, int sg, int cur) {
     a.xout = xadj_slot(P, ws, 1 - cur);
     a.si_next = n > 1 ? tab(P, ws, n - 1) : nullptr;
     a.xall = n == 1;  // the raw part of state 0 goes out with adj_initial
+    a.mout = n == 1 ? wsp(ws, P->o_acarry) : nullptr;  // and its ALKS state
   }
   return a;
 }
@@ -618,6 +645,11 @@ extern "C" {
 
 const char* lks_last_error(void) { return g_err.c_str(); }
 
+#ifndef LKS_SOURCE_DIGEST
+#define LKS_SOURCE_DIGEST "unknown"
+#endif
+const char* lks_source_digest(void) { return LKS_SOURCE_DIGEST; }
+
 lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* workspace_bytes) {
   if (!out) return fail(LKS_EINVAL, "null out");
   if (lks_status e = validate(prob)) return e;
@@ -687,6 +719,8 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   P->alks = prob->scheme == LKS_ADJ_ALKS;
   // ALKS: raw first-moment part of the adjoint velocity, two slots like lambda
   P->o_xadj = take(P->alks ? 2 * (size_t)g.d * g.N * P->es : 0);
+  // ALKS: the state (p~, u~, s~) of level 0, written by the sweep's last step
+  P->o_acarry = take(P->alks ? (size_t)alks_carry_planes(g.d) * g.N * P->es : 0);
   P->o_krefbar = take((size_t)g.Mtot * sizeof(double));
   P->o_mpart = take((size_t)g.nt * P->mrow * 8 * sizeof(double));
   // J2: per-block step sums, and the reverse-step seeds of one segment on the body box
@@ -698,6 +732,8 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   P->o_cmot = take((size_t)g.nt * 11 * sizeof(double));
   P->o_kz = take(kz_bytes(g, P->bmax.ext[2], P->prec));
   P->o_geo = take(sizeof(Geo));
+  // copies of the last lks_forward's gamma, chi, psi (lks_adjoint checks its own against them)
+  P->o_inp = take(((size_t)inner_points(g) + 4 * (size_t)g.nt) * sizeof(double));
   P->total = off;
   *out = P;
   if (workspace_bytes) *workspace_bytes = P->total;
@@ -773,26 +809,40 @@ lks_status lks_forward(lks_plan* P, const double* gamma, const double* chi, cons
 lks_status lks_adjoint(lks_plan* P, const double* gamma, const double* chi, const double* psi,
                        void* ws, const double* dJ, const void* adj_terminal, void* adj_initial,
                        double* dJ_dgamma, double* dJ_dchi, double* dJ_dpsi, hipStream_t s) {
-  (void)chi;
-  (void)psi;
-  if (!P || !ws || !dJ || !gamma || !dJ_dgamma || !dJ_dchi || !dJ_dpsi)
+  if (!P || !ws || !dJ || !gamma || !chi || !psi || !dJ_dgamma || !dJ_dchi || !dJ_dpsi)
     return fail(LKS_EINVAL, "null argument");
   if (P->fwd_ws != ws)
     return fail(LKS_EINVAL, "lks_adjoint needs a preceding lks_forward on this plan and workspace");
+  {
+    // the sweep reverses the last forward march: its inputs must be these
+    const double* inp = (const double*)wsp(ws, P->o_inp);
+    const long long M = inner_points(P->g), nt = P->g.nt;
+    int* flag = (int*)wsp(ws, P->o_info) + 1;
+    HIPCHK(launch_zero(flag, sizeof(int), s));
+    HIPCHK(launch_differ(gamma, inp, M, flag, s));
+    HIPCHK(launch_differ(chi, inp + M, 3 * nt, flag, s));
+    HIPCHK(launch_differ(psi, inp + M + 3 * nt, nt, flag, s));
+    int differ = 0;
+    HIPCHK(hipMemcpyAsync(&differ, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (differ)
+      return fail(LKS_EINVAL,
+                  "lks_adjoint: gamma, chi or psi differ from those of the preceding lks_forward");
+  }
   const size_t Sb = (size_t)P->S * P->es;
   const size_t Xb = (size_t)P->g.d * P->g.N * P->es;  // ALKS raw-moment part
   HIPCHK(hipMemcpyAsync(wsp(ws, P->o_seed), dJ, sizeof(double), hipMemcpyDeviceToDevice, s));
-  if (P->alks) {
-    if (adj_terminal)
-      HIPCHK(hipMemcpyAsync(xadj_slot(P, ws, 0), (const char*)adj_terminal + Sb, Xb,
-                            hipMemcpyDeviceToDevice, s));
-    else
-      HIPCHK(launch_zero(xadj_slot(P, ws, 0), Xb, s));
-  }
-  if (adj_terminal) {
-    HIPCHK(hipMemcpyAsync(lam_slot(P, ws, 0), adj_terminal, Sb, hipMemcpyDeviceToDevice, s));
+  if (P->alks && adj_terminal) {
+    // the carried ALKS state stands for the moments of the last level; its
+    // adjoint equilibrium is formed with this run's velocity there
+    HIPCHK(launch_alks_carry_in(P->g, P->prec, (const char*)adj_terminal + Sb, final_state(P, ws),
+                                lam_slot(P, ws, 0), xadj_slot(P, ws, 0), s));
   } else {
-    HIPCHK(launch_zero(lam_slot(P, ws, 0), Sb, s));
+    if (P->alks) HIPCHK(launch_zero(xadj_slot(P, ws, 0), Xb, s));
+    if (adj_terminal)
+      HIPCHK(hipMemcpyAsync(lam_slot(P, ws, 0), adj_terminal, Sb, hipMemcpyDeviceToDevice, s));
+    else
+      HIPCHK(launch_zero(lam_slot(P, ws, 0), Sb, s));
   }
   HIPCHK(launch_zero(wsp(ws, P->o_badj), body_bytes(P), s));
   HIPCHK(launch_zero(wsp(ws, P->o_krefbar), (size_t)P->g.Mtot * sizeof(double), s));
@@ -805,7 +855,8 @@ lks_status lks_adjoint(lks_plan* P, const double* gamma, const double* chi, cons
   if (adj_initial) {
     HIPCHK(hipMemcpyAsync(adj_initial, lam_slot(P, ws, fin), Sb, hipMemcpyDeviceToDevice, s));
     if (P->alks)
-      HIPCHK(hipMemcpyAsync((char*)adj_initial + Sb, xadj_slot(P, ws, fin), Xb,
+      HIPCHK(hipMemcpyAsync((char*)adj_initial + Sb, wsp(ws, P->o_acarry),
+                            (size_t)alks_carry_planes(P->g.d) * P->g.N * P->es,
                             hipMemcpyDeviceToDevice, s));
   }
   return sens(P, gamma, ws, dJ_dgamma, dJ_dchi, dJ_dpsi, s);

@@ -31,12 +31,16 @@ struct Tile3 {
 };
 inline int tile3_y(int precision) { return precision == 0 ? 16 : 8; }
 // Resident blocks per CU the z-segment lengths of the 3D step kernels are
-// chosen for (the grid is about that many times CU_COUNT blocks): the
+// chosen for (the grid is about that many times the device's CU count): the
 // forward step holds two blocks per CU; the FP32 adjoint (768 threads at up to
 // 168 VGPRs) one, the FP64 adjoint two.
 constexpr int STEP_RESIDENT_FWD = 2;
 inline int step_resident_adj(int precision) { return precision == 0 ? 1 : 2; }
-constexpr int CU_COUNT = 256;
+// Compute units and XCDs of the current device (hipDeviceProp_t and
+// hipDeviceAttributeNumberOfXccs), read once per plan; MI355X's 256 and 8
+// when no device can be queried (plans can be built and validated without
+// one).
+void device_counts(int* ncu, int* nxcd);
 // 3D adjoint step: planes of its LDS ring (4: one barrier per plane; 3: two,
 // and less LDS).  FP32 takes 4 (its one block per CU has LDS to spare); FP64
 // takes 3 so two blocks fit a CU.
@@ -94,11 +98,19 @@ struct Geo {
   int zseg_f;             // z planes per block segment (3D forward step)
   int ty3;                // tile height of the step kernels (3D: Tile3<R>::TY; 2D: TILE_Y)
   int prec;               // state precision (0 FP32, 1 FP64)
+  int nxcd;               // XCDs of the device (block -> tile order)
   int obj;                // objective: 0 J1, 1 J2
   double j2s[3];          // J2 normalisations 1/(nt M), 1/((x2max - x2min) M),
                           // 1/(2 pi l_m M), M = inner design points
   double j2w[2];          // J2 weights w_d, w_t
 };
+
+// Inner design points (no margin): the size of gamma.
+__host__ __device__ inline long long inner_points(const Geo& g) {
+  long long M = 1;
+  for (int a = 0; a < g.d; ++a) M *= g.m[a];
+  return M;
+}
 
 // Blocks of the 2D map transpose (MAPADJ_PTS2 runs of 64 points each).
 __host__ __device__ inline int mapadj_blocks_2d(const Geo& g) {
@@ -194,9 +206,21 @@ struct AdjArgs {
   // Objective J2: seed on the fluid velocity on the body box ([2][box.vol],
   // box-indexed like bk; nullable), applied where the J1 seed would be.
   const void* j2s;
+  // ALKS (nullable): the state of level n - 1 in the paper's variables,
+  // p~ [N], u~ [d][N] and the symmetric s~ [d(d+1)/2][N] ((xx, yy, xy) in
+  // 2D, (xx, yy, zz, xy, xz, yz) in 3D), written at every node; the sweep's
+  // last step sets it for the periodic approximation's carry.
+  void* mout;
 };
 
 int step_blocks(const Geo& g);
+// Planes of the ALKS state (p~, u~, symmetric s~).
+inline int alks_carry_planes(int d) { return 1 + d + d * (d + 1) / 2; }
+// ALKS carried state (p~, u~, s~ at the last level, layout as AdjArgs::mout)
+// and that level's flow state st -> the adjoint state the reverse sweep
+// starts from: lam = (-3 p~, -V) and the raw first-moment part X = -3 u~.
+hipError_t launch_alks_carry_in(const Geo& g, int precision, const void* carry, const void* st,
+                                void* lam, void* X, hipStream_t s);
 hipError_t launch_forward_step(const Geo& g, int precision, const FwdArgs& a, hipStream_t s);
 hipError_t launch_adjoint_step(const Geo& g, int precision, const AdjArgs& a, hipStream_t s);
 size_t kz_bytes(const Geo& g, int ext2max, int precision);
@@ -271,6 +295,8 @@ hipError_t launch_reduce_parts(const Geo& g, const double* part, int nblk, doubl
                               hipStream_t s);
 hipError_t launch_wall_fixup(const Geo& g, int precision, void* st, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// flag[0] = 1 where the n doubles of a and b differ bitwise (flag untouched otherwise).
+hipError_t launch_differ(const double* a, const double* b, long long n, int* flag, hipStream_t s);
 
 // ---- batched 2D launches: one launch covers the same step of up to
 // BATCH_MAX independent instances; instance k owns blocks

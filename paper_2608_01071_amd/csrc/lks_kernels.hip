@@ -204,24 +204,25 @@ __device__ __forceinline__ void dnumT_taps(const Geo& g, int a, int v, R k[5]) {
   if (v + 2 == n - 1) k[4] = R(0.5);
 }
 
-// XCD-aware tile order.  Workgroups are dealt to the 8 XCDs round robin by
-// their linear id, and each XCD has its own L2; this remap gives every XCD a
-// contiguous run of tiles (x fastest, then y, then z segment), so tiles that
-// share halo nodes run on the same XCD and hit the same L2.
-constexpr int NUM_XCD = 8;
-__device__ __forceinline__ int xcd_tile_of(int b, int nbx, int nby, int nbz, int& bx, int& by,
-                                           int& bz) {
+// XCD-aware tile order.  Workgroups are dealt to the device's XCDs (nx, 8
+// on MI355X, queried at plan time) round robin by their linear id, and each
+// XCD has its own L2; this remap gives every XCD a contiguous run of tiles
+// (x fastest, then y, then z segment), so tiles that share halo nodes run on
+// the same XCD and hit the same L2.
+__device__ __forceinline__ int xcd_tile_of(int b, int nx, int nbx, int nby, int nbz, int& bx,
+                                           int& by, int& bz) {
   const int total = nbx * nby * nbz;
-  const int xcd = b % NUM_XCD, slot = b / NUM_XCD;
-  const int q = total / NUM_XCD, r = total % NUM_XCD;
+  const int xcd = b % nx, slot = b / nx;
+  const int q = total / nx, r = total % nx;
   const int t = (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
   bx = t % nbx;
   by = (t / nbx) % nby;
   bz = t / (nbx * nby);
   return t;
 }
-__device__ __forceinline__ int xcd_tile(int nbx, int nby, int nbz, int& bx, int& by, int& bz) {
-  return xcd_tile_of(blockIdx.x, nbx, nby, nbz, bx, by, bz);
+__device__ __forceinline__ int xcd_tile(int nx, int nbx, int nby, int nbz, int& bx, int& by,
+                                        int& bz) {
+  return xcd_tile_of(blockIdx.x, nx, nbx, nby, nbz, bx, by, bz);
 }
 __device__ __forceinline__ int tiles_x(const Geo& g) { return (g.n[0] - g.org[0] + TILE_X - 1) / TILE_X; }
 __device__ __forceinline__ int tiles_y(const Geo& g) { return (g.n[1] - g.org[1] + g.ty3 - 1) / g.ty3; }
@@ -453,7 +454,7 @@ __device__ __forceinline__ void fwd2d_tile(const Geo& g, FwdArgs a, int bid) {
   const R* in = (const R*)a.in;
   const long long N = g.N;
   int tbx, tby, tbz;
-  const int tlin = xcd_tile_of(bid, tiles_x(g), tiles_y(g), 1, tbx, tby, tbz);
+  const int tlin = xcd_tile_of(bid, g.nxcd, tiles_x(g), tiles_y(g), 1, tbx, tby, tbz);
   const int x0 = tbx * TX + g.org[0], y0 = tby * TY + g.org[1];
   for (int k = threadIdx.x; k < LX * LY; k += STEP_THREADS) {
     int gx = x0 - 2 + k % LX, gy = y0 - 2 + k / LX;
@@ -560,7 +561,7 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
   const int nz = g.n[2];
   const int NP = g.n[0] * g.n[1];
   int tbx, tby, tbz;
-  const int tlin = xcd_tile(tiles_x(g), tiles_y(g), tiles_z(g), tbx, tby, tbz);
+  const int tlin = xcd_tile(g.nxcd, tiles_x(g), tiles_y(g), tiles_z(g), tbx, tby, tbz);
   const int x0 = tbx * TX + g.org[0], y0 = tby * TY + g.org[1];
   const int z0 = tbz * g.zseg, z1 = min(z0 + g.zseg, nz);
 
@@ -952,7 +953,7 @@ __device__ __forceinline__ void adj2d_tile(const Geo& g, AdjArgs a, int bid) {
   __shared__ R sm[6][FY * FX];     // M0, M1x, M1y, M2xx, M2yy, M2xy
   const long long N = g.N;
   int tbx, tby, tbz;
-  xcd_tile_of(bid, tiles_x(g), adj2d_tiles_y(g), 1, tbx, tby, tbz);
+  xcd_tile_of(bid, g.nxcd, tiles_x(g), adj2d_tiles_y(g), 1, tbx, tby, tbz);
   const int x0 = tbx * TX + g.org[0], y0 = tby * TY + g.org[1];
   for (int k = threadIdx.x; k < LX * LY; k += ADJ2D_THREADS) {
     int lx = k % LX, ly = k / LX;
@@ -1024,6 +1025,16 @@ __device__ __forceinline__ void adj2d_tile(const Geo& g, AdjArgs a, int bid) {
       xo[i] = R(3) * sm[1][c];
       xo[N + i] = R(3) * sm[2][c];
     }
+    // the ALKS state itself (p~, u~, s~ = -M0, -M1, -M2), for the carry
+    if (a.mout) {
+      R* mo = (R*)a.mout;
+      mo[i] = -M0;
+      mo[N + i] = -sm[1][c];
+      mo[2 * N + i] = -sm[2][c];
+      mo[3 * N + i] = -sm[3][c];
+      mo[4 * N + i] = -sm[4][c];
+      mo[5 * N + i] = -sm[5][c];
+    }
   }
 }
 
@@ -1071,7 +1082,7 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
   const int nz = g.n[2];
   const int NP = g.n[0] * g.n[1];
   int tbx, tby, tbz;
-  xcd_tile(tiles_x(g), tiles_y(g), tiles_z(g), tbx, tby, tbz);
+  xcd_tile(g.nxcd, tiles_x(g), tiles_y(g), tiles_z(g), tbx, tby, tbz);
   const int x0 = tbx * TX + g.org[0], y0 = tby * TY + g.org[1];
   const int z0 = tbz * g.zseg, z1 = min(z0 + g.zseg, nz);
   const double seed = a.seed ? a.seed[0] : 0.0;
@@ -1404,6 +1415,20 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
           bst<R>(R(3) * Mp[1], rxo, ovo, so);
           bst<R>(R(3) * Mp[2], rxo, ovo, so + fb);
           bst<R>(R(3) * Mp[3], rxo, ovo, so + 2u * fb);
+        }
+        // the ALKS state itself (p~, u~, s~ = -M0, -M1, -M2), for the carry
+        if (a.mout) {
+          R* mo = (R*)a.mout + NP * zo + ocol;
+          mo[0] = -M0;
+          mo[N] = -Mp[1];
+          mo[2 * N] = -Mp[2];
+          mo[3 * N] = -Mp[3];
+          mo[4 * N] = -Mxx;
+          mo[5 * N] = -Myy;
+          mo[6 * N] = -Mzz;
+          mo[7 * N] = -Mxy;
+          mo[8 * N] = -Mxz;
+          mo[9 * N] = -Myz;
         }
       }
     }
@@ -2593,6 +2618,56 @@ __global__ void k_wall_fixup(Geo g, R* st) {
   if (is_wall(g, x, y, z)) st[i] = st[wall_src(g, x, y, z)];
 }
 
+// The adjoint state an ALKS reverse sweep starts from when it carries a
+// state (p~, u~, s~) into its last level (Sec. 3.3, Algorithm 1): the
+// level's adjoint equilibrium p~ + c_i . V with
+// V = 3 (u~ + 3 s~ u - p~ u) + 2 A sum_a D_a^T s~_ab (the divergence read as
+// minus the transpose of the forward's difference operator), u that level's
+// flow velocity.  In the sweep's form: lam = (-3 p~, -V), X = -3 u~.  One
+// thread per node; neighbours are read from global memory (it runs once per
+// sweep).  carry: [1 + d + d(d+1)/2][N], symmetric s~ as (xx, yy[, zz], xy
+// [, xz, yz]).
+template <class R>
+__global__ void k_alks_carry_in(Geo g, const R* carry, const R* st, R* lam, R* X) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  const int d = g.d;
+  const long long N = g.N;
+  const int c[3] = {(int)(i % g.n[0]), (int)((i / g.n[0]) % g.n[1]),
+                    (int)(i / ((long long)g.n[0] * g.n[1]))};
+  // plane of s~_ab in the carry
+  auto splane = [&](int a, int b) -> int {
+    if (a == b) return 1 + d + a;
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    return 1 + d + d + (lo == 0 ? hi - 1 : 2);
+  };
+  const R pt = carry[i];
+  R u[3] = {R(0), R(0), R(0)};
+  for (int a = 0; a < d; ++a) u[a] = st[(1 + a) * N + i];
+  lam[i] = R(-3) * pt;
+  const R A2 = R(2) * (R)g.A;
+  for (int b = 0; b < d; ++b) {
+    R v = R(3) * carry[(1 + b) * N + i] - R(3) * pt * u[b];
+    for (int a = 0; a < d; ++a) {
+      const R* sab = carry + (long long)splane(a, b) * N;
+      v += R(9) * sab[i] * u[a];
+      R k[5];
+      dnumT_taps(g, a, c[a], k);
+      R t = R(0);
+      for (int q = 0; q < 5; ++q) {
+        if (k[q] == R(0)) continue;
+        int cc[3] = {c[0], c[1], c[2]};
+        cc[a] += q - 2;
+        wrap_axis(g, a, cc[a]);
+        t += k[q] * sab[nidx(g, cc[0], cc[1], cc[2])];
+      }
+      v += A2 * t;
+    }
+    lam[(1 + b) * N + i] = -v;
+    X[b * N + i] = R(-3) * carry[(1 + b) * N + i];
+  }
+}
+
 __global__ void k_zero(uint32_t* p, long long n) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -3129,6 +3204,18 @@ hipError_t launch_reduce_parts(const Geo& g, const double* part, int nblk, doubl
   return hipGetLastError();
 }
 
+hipError_t launch_alks_carry_in(const Geo& g, int precision, const void* carry, const void* st,
+                                void* lam, void* X, hipStream_t s) {
+  dim3 grid((unsigned)((g.N + 255) / 256));
+  if (precision == 0)
+    hipLaunchKernelGGL(k_alks_carry_in<float>, grid, dim3(256), 0, s, g, (const float*)carry,
+                       (const float*)st, (float*)lam, (float*)X);
+  else
+    hipLaunchKernelGGL(k_alks_carry_in<double>, grid, dim3(256), 0, s, g, (const double*)carry,
+                       (const double*)st, (double*)lam, (double*)X);
+  return hipGetLastError();
+}
+
 hipError_t launch_wall_fixup(const Geo& g, int precision, void* st, hipStream_t s) {
   dim3 grid((unsigned)((g.N + 255) / 256));
   if (precision == 0)
@@ -3168,6 +3255,7 @@ hipError_t launch_design_filter_adjoint(const Geo& g, const double* gamma, doubl
   hipLaunchKernelGGL(k_design_bwd2, grid, dim3(256), 0, s, G, M, (const double*)work, out);
   return hipGetLastError();
 }
+
 hipError_t launch_constraints(const Geo& g, const double* phys, const double* chi,
                               const double* psi, double vmax, double omax, double pw,
                               double* Gout, double* dG1, double* dG2, double* dG3_dpsi, double* mot,
@@ -3190,6 +3278,19 @@ hipError_t launch_constraints(const Geo& g, const double* phys, const double* ch
     hipLaunchKernelGGL(k_sens_filter, grid, dim3(256), 0, s, g, (const double*)tot,
                        (const double*)den_t, (const double*)den_w, dchi_scratch, dG3_dpsi);
   }
+  return hipGetLastError();
+}
+
+// flag[0] = 1 if the n doubles of a and b differ in any bit.
+__global__ void k_differ(const unsigned long long* a, const unsigned long long* b, long long n,
+                         int* flag) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n && a[i] != b[i]) flag[0] = 1;
+}
+hipError_t launch_differ(const double* a, const double* b, long long n, int* flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_differ, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     (const unsigned long long*)a, (const unsigned long long*)b, n, flag);
   return hipGetLastError();
 }
 

@@ -16,6 +16,8 @@ from typing import Optional
 
 import torch
 
+from .srcdigest import source_digest
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblks.so")
 
@@ -55,6 +57,12 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
         L = C.CDLL(LIB_PATH)
         L.lks_last_error.restype = C.c_char_p
+        L.lks_source_digest.restype = C.c_char_p
+        want = source_digest()
+        have = L.lks_source_digest().decode()
+        if want is not None and have != want:
+            raise RuntimeError(f"{LIB_PATH} was built from other sources (digest {have[:12]}, "
+                               f"sources {want[:12]}): rebuild it with __graft_entry__.build()")
         L.lks_plan_create.argtypes = [C.POINTER(LksProblem), C.POINTER(_VP), C.POINTER(C.c_size_t)]
         L.lks_plan_destroy.argtypes = [_VP]
         L.lks_plan_set_graphs.argtypes = [_VP, C.c_int32]
@@ -142,6 +150,9 @@ class Plan:
         self.workspace_bytes = nbytes.value
         self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
         self.dtype = torch.float32 if problem.precision == 0 else torch.float64
+        # forward marches run on this plan's workspace so far; the adjoint
+        # reverses the last one only
+        self.generation = 0
 
     def set_graphs(self, on: bool):
         """Replay the time loops from captured hipGraphs (default) or launch eagerly."""
@@ -166,9 +177,12 @@ class Plan:
     @property
     def adj_state_size(self) -> int:
         """Values of adj_terminal / adj_initial: the state's with the exact
-        adjoint; with the ALKS also the raw first-moment part ([2d+1][N])."""
+        adjoint; with the ALKS also its carried state p~, u~ and the
+        symmetric s~ ([(d+1) + 1 + d + d(d+1)/2][N])."""
         p = self.problem
-        return (2 * p.d + 1) * p.N if p.scheme == 1 else self.state_size
+        if p.scheme == 1:
+            return (p.d + 1 + 1 + p.d + p.d * (p.d + 1) // 2) * p.N
+        return self.state_size
 
     @property
     def state_size(self) -> int:
@@ -183,6 +197,7 @@ class Plan:
         fin = torch.empty(self.state_size, dtype=self.dtype, device=self.device) if want_final else None
         J3 = torch.empty(3, dtype=torch.float64, device=self.device)
         self._keep = (g, c, s)
+        self.generation += 1
         _check(lib().lks_forward(self.handle, _ptr(g), _ptr(c), _ptr(s), _ptr(st0), _ptr(fin),
                                  _ptr(self.workspace), _ptr(J3), _stream()))
         return J3, fin
@@ -308,6 +323,7 @@ class LKSObjective(torch.autograd.Function):
     def forward(ctx, gamma, chi, psi, plan: Plan):
         J3, _ = plan.forward(gamma, chi, psi)
         ctx.plan = plan
+        ctx.generation = plan.generation
         ctx.save_for_backward(gamma, chi, psi)
         return J3[0].clone()
 
@@ -315,6 +331,11 @@ class LKSObjective(torch.autograd.Function):
     def backward(ctx, gJ):
         gamma, chi, psi = ctx.saved_tensors
         plan = ctx.plan
+        if plan.generation != ctx.generation:
+            # another march has run on the plan since this one (a second
+            # apply, or a direct forward): march again for these inputs, so
+            # the adjoint reverses the right one
+            plan.forward(gamma, chi, psi)
         g = plan.adjoint(gamma, chi, psi, dJ=gJ.detach().reshape(1).to(torch.float64))
         p = plan.problem
         return (g["dgamma"].reshape(gamma.shape).to(gamma.dtype),
@@ -361,6 +382,7 @@ class Batch:
                                    _stream()))
         for pl in self.plans:
             pl._keep = None
+            pl.generation += 1
         return [(self.J[k], {"dgamma": self.dg[k],
                              "dchi": self.dc[k].reshape(pl.problem.nt, 3),
                              "dpsi": self.dp[k]})

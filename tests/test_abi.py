@@ -30,6 +30,15 @@ def test_exports_every_declared_symbol(L):
         assert hasattr(L, n), f"{n} declared in include/lks.h but not exported"
 
 
+def test_library_matches_its_sources(L):
+    """The build embeds the SHA-256 of the sources; the loaded library's
+    equals the digest of the sources next to it."""
+    from paper_2608_01071_amd.srcdigest import source_digest
+    want = source_digest()
+    assert want is not None and len(want) == 64
+    assert L.lks_source_digest().decode() == want
+
+
 def declared_parameter_counts():
     src = open(os.path.join(ROOT, "include", "lks.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
@@ -145,3 +154,4 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+

@@ -385,6 +385,51 @@ def test_autograd_function(orc):
     assert l2err(cpu(tp.grad), adj["dpsi"]) < 1e-9
 
 
+def test_autograd_two_applies_on_one_plan(orc):
+    """(J(x) - J(y)).backward() with both applies on one plan: the second
+    march overwrites the first one's checkpoints, so the first backward
+    marches again for its own inputs.  Both gradients match the oracle."""
+    lks = lk()
+    p = prob2d((45, 21), 1)
+    plan = lks.Plan(p)
+    gx, cx, px = rand_inputs(p, 41)
+    gy, cy, py = rand_inputs(p, 42)
+    t = [torch.tensor(v, device="cuda", requires_grad=True) for v in (gx, cx, px, gy, cy, py)]
+    Jx = lks.LKSObjective.apply(t[0], t[1], t[2], plan)
+    Jy = lks.LKSObjective.apply(t[3], t[4], t[5], plan)
+    (Jx - Jy).backward()
+    ax = orc.adjoint(p, gx, cx, px)
+    ay = orc.adjoint(p, gy, cy, py, dJ=-1.0)
+    for k, key in enumerate(("dgamma", "dchi", "dpsi")):
+        assert l2err(cpu(t[k].grad), ax[key]) < 1e-9, key
+        assert l2err(cpu(t[3 + k].grad), ay[key]) < 1e-9, key
+    # a plain forward in between is caught the same way
+    t2 = [torch.tensor(v, device="cuda", requires_grad=True) for v in (gx, cx, px)]
+    J = lks.LKSObjective.apply(t2[0], t2[1], t2[2], plan)
+    plan.forward(gy, cy, py)
+    J.backward()
+    assert l2err(cpu(t2[0].grad), ax["dgamma"]) < 1e-9
+
+
+def test_adjoint_refuses_other_inputs():
+    """lks_adjoint reverses the last forward march: called with a gamma, chi
+    or psi that differs from that march's, it returns LKS_EINVAL and
+    launches nothing."""
+    lks = lk()
+    p = prob2d((45, 21), 1)
+    plan = lks.Plan(p)
+    gamma, chi, psi = rand_inputs(p, 43)
+    plan.forward(gamma, chi, psi)
+    for k in range(3):
+        args = [gamma.copy(), chi.copy(), psi.copy()]
+        args[k].flat[0] += 1e-3
+        with pytest.raises(lks.LksError) as e:
+            plan.adjoint(*args)
+        assert e.value.status == lks.LKS_EINVAL
+    g = plan.adjoint(gamma, chi, psi)
+    assert np.abs(cpu(g["dgamma"])).max() > 0
+
+
 def test_reproducible_bitwise():
     """Two identical runs give bit-identical objective and gradients."""
     lks = lk()
