@@ -194,6 +194,20 @@ lks_status lks_design_filter_adjoint(lks_plan* plan, const double* gamma, double
                                      double beta, double eta, const double* dJ_dphys,
                                      double* work, double* dJ_dgamma, hipStream_t stream);
 
+/* lks_design_filter_adjoint for callers that cannot allocate device memory
+ * (code under hipGraph capture, tight serving loops, harnesses that forbid
+ * allocation): the same chain rule with its M-double scratch in a fixed
+ * device array of the library (LKS_NOALLOC_MAX_POINTS doubles, 16 MiB, held
+ * on every device the library runs on until the process ends) instead of a
+ * caller-owned `work`.  Allocates nothing.  Every call on a device shares that
+ * device's array, so calls that overlap on one device race; calls in order
+ * on one stream are safe.  LKS_EINVAL when the plan has more than
+ * LKS_NOALLOC_MAX_POINTS inner design points, and as lks_design_filter_adjoint. */
+#define LKS_NOALLOC_MAX_POINTS (1ll << 21)
+lks_status lks_design_filter_adjoint_noalloc(lks_plan* plan, const double* gamma, double radius,
+                                             double beta, double eta, const double* dJ_dphys,
+                                             double* dJ_dgamma, hipStream_t stream);
+
 /* Constraint functionals of Sec. 2.6 and their gradients (device arrays):
  *   G_out[0] = G1 = sum(gamma_phys) / (vmax M) - 1      (Eq. constraint1)
  *   G_out[1] = G2 = sum(1 - gamma_phys) / (vmax M) - 1  (Eq. constraint2)

@@ -892,6 +892,24 @@ lks_status lks_design_filter_adjoint(lks_plan* P, const double* gamma, double ra
   return LKS_OK;
 }
 
+lks_status lks_design_filter_adjoint_noalloc(lks_plan* P, const double* gamma, double radius,
+                                             double beta, double eta, const double* dJ_dphys,
+                                             double* dJ_dgamma, hipStream_t s) {
+  if (!P || !gamma || !dJ_dphys || !dJ_dgamma) return fail(LKS_EINVAL, "null argument");
+  if (!(radius > 0.0 && radius <= 64.0)) return fail(LKS_EINVAL, "filter radius must be in (0, 64]");
+  if (!(eta >= 0.0 && eta <= 1.0) || !std::isfinite(beta))
+    return fail(LKS_EINVAL, "projection needs 0 <= eta <= 1 and a finite beta");
+  const long long M = inner_points(P->g);
+  if (M > NOALLOC_MAX_POINTS)
+    return fail(LKS_EINVAL, "lks_design_filter_adjoint_noalloc: " + std::to_string(M) +
+                                " design points exceed its scratch of " +
+                                std::to_string(NOALLOC_MAX_POINTS));
+  double* work = nullptr;
+  HIPCHK(noalloc_scratch(&work));
+  HIPCHK(launch_design_filter_adjoint(P->g, gamma, radius, beta, eta, dJ_dphys, work, dJ_dgamma, s));
+  return LKS_OK;
+}
+
 lks_status lks_constraints(lks_plan* P, void* ws, const double* gamma_phys, const double* chi,
                            const double* psi, double vmax, double omega_max, double p_omega,
                            double* G_out, double* dG1, double* dG2, double* dG3_dpsi,

@@ -278,6 +278,11 @@ hipError_t launch_design_filter(const Geo& g, const double* gamma, double radius
 hipError_t launch_design_filter_adjoint(const Geo& g, const double* gamma, double radius,
                                         double beta, double eta, const double* gbar, double* work,
                                         double* out, hipStream_t s);
+// Most inner design points the allocation-free chain rule takes (its
+// scratch is a fixed device array of this many doubles: 16 MiB).
+constexpr long long NOALLOC_MAX_POINTS = 1LL << 21;
+// Device address of that array on the current device (looked up once per device).
+hipError_t noalloc_scratch(double** out);
 hipError_t launch_constraints(const Geo& g, const double* phys, const double* chi,
                               const double* psi, double vmax, double omax, double pw,
                               double* Gout, double* dG1, double* dG2, double* dG3_dpsi, double* mot,

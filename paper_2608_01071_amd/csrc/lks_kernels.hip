@@ -35,6 +35,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "lks_internal.h"
 
 namespace lks {
@@ -3254,6 +3256,33 @@ hipError_t launch_design_filter_adjoint(const Geo& g, const double* gamma, doubl
   hipLaunchKernelGGL(k_design_bwd1, grid, dim3(256), 0, s, G, M, gamma, beta, eta, gbar, work);
   hipLaunchKernelGGL(k_design_bwd2, grid, dim3(256), 0, s, G, M, (const double*)work, out);
   return hipGetLastError();
+}
+
+// ---- the design chain rule without allocation: its scratch h (one double
+// per inner design point) lives in a fixed device array of this file.  Each
+// device holds its own copy until the process ends; calls on one device share
+// it, so calls that overlap on a device race.
+static __device__ __align__(256) double scratch[NOALLOC_MAX_POINTS];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the array's name is not a device address in host code).
+hipError_t noalloc_scratch(double** out) {
+  constexpr int MAX_DEV = 64;
+  static std::mutex mu;
+  static double* addr[MAX_DEV] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEV) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    double* p = nullptr;
+    e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_constraints(const Geo& g, const double* phys, const double* chi,

@@ -86,6 +86,7 @@ def lib():
         D = C.c_double
         L.lks_design_filter.argtypes = [_VP, _VP, D, D, D, _VP, _VP]
         L.lks_design_filter_adjoint.argtypes = [_VP, _VP, D, D, D, _VP, _VP, _VP, _VP]
+        L.lks_design_filter_adjoint_noalloc.argtypes = [_VP, _VP, D, D, D, _VP, _VP, _VP]
         L.lks_constraints.argtypes = [_VP] * 5 + [D, D, D] + [_VP] * 5
         _lib = L
     return _lib
@@ -248,6 +249,18 @@ class Plan:
         _check(lib().lks_design_filter_adjoint(self.handle, _ptr(g), C.c_double(radius),
                                                C.c_double(beta), C.c_double(eta), _ptr(gb),
                                                _ptr(work), _ptr(out), _stream()))
+        return out
+
+    def design_filter_adjoint_noalloc(self, gamma, radius: float, beta: float, eta: float,
+                                      dJ_dphys, out=None):
+        """design_filter_adjoint with the library's fixed device scratch
+        (lks_design_filter_adjoint_noalloc); `out` (M doubles) may be given."""
+        g, gb = self._f64(gamma), self._f64(dJ_dphys)
+        if out is None:
+            out = torch.empty(self.problem.M, dtype=torch.float64, device=self.device)
+        _check(lib().lks_design_filter_adjoint_noalloc(self.handle, _ptr(g), C.c_double(radius),
+                                                       C.c_double(beta), C.c_double(eta),
+                                                       _ptr(gb), _ptr(out), _stream()))
         return out
 
     def constraints(self, gamma_phys, chi, psi, vmax: float, omega_max: float, p_omega: float):

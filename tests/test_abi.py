@@ -155,3 +155,22 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
 
+
+def test_noalloc_entry_point_rejects_oversized_design_grid(L):
+    """The allocation-free chain rule refuses, on the host and before any
+    device call, a plan with more inner design points than its fixed
+    scratch holds."""
+    from paper_2608_01071_amd import lks
+    p = W.Problem(d=3, n=(200, 200, 200), bc=(1, 1, 0), m=(130, 130, 130), margin=4,
+                  xg_min=(100.0, 100.0, 100.0), xg_max=(100.0, 100.0, 100.0),
+                  tgt_lo=(0, 0, 0), tgt_hi=(1, 1, 1), nt=4, r_t=1, r_w=1, precision=0)
+    assert p.M > (1 << 21)
+    h = C.c_void_p()
+    nb = C.c_size_t()
+    assert L.lks_plan_create(C.byref(lks.to_struct(p)), C.byref(h), C.byref(nb)) == 0
+    dummy = C.c_void_p(256)  # never dereferenced: the size check comes first
+    rc = L.lks_design_filter_adjoint_noalloc(h, dummy, C.c_double(2.0), C.c_double(0.0),
+                                            C.c_double(0.5), dummy, dummy, None)
+    assert rc == lks.LKS_EINVAL
+    assert b"exceed its scratch" in L.lks_last_error()
+    L.lks_plan_destroy(h)
