@@ -106,6 +106,7 @@ struct Oracle {
   long Mtot;     // design points incl. margin
   long Min;      // inner design points
   double xiG[3];
+  int MW;        // motion row width: 8 (rotation about z) or 12 (three angles)
 
   explicit Oracle(const orc_problem& p) : P(p) {
     d = p.d;
@@ -118,6 +119,7 @@ struct Oracle {
     Min = 1;
     for (int a = 0; a < d; ++a) Min *= p.m[a];
     for (int a = 0; a < 3; ++a) xiG[a] = 0.5 * (D[a] - 1);
+    MW = p.rot == 1 ? 12 : 8;
   }
 
   long idx(const int x[3]) const { return x[0] + (long)n[0] * (x[1] + (long)n[1] * x[2]); }
@@ -237,17 +239,77 @@ struct Oracle {
         for (int t = 0; t < nt; ++t) x[t] = v[t] = 0.0;
       }
       for (int t = 0; t < nt; ++t) {
-        mot[t * 8 + a] = x[t];
-        mot[t * 8 + 3 + a] = v[t];
+        mot[t * MW + a] = x[t];
+        mot[t * MW + 3 + a] = v[t];
       }
+    }
+    if (P.rot == 1) {
+      // three angle series, each through the same filter, bounds and rate
+      for (int k = 0; k < 3; ++k) {
+        filter(psi + k, 3, P.r_w, f.data());
+        const double lo = k < 2 ? P.tilt_min[k] : P.th_min;
+        const double hi = k < 2 ? P.tilt_max[k] : P.th_max;
+        for (int t = 0; t < nt; ++t) x[t] = (hi - lo) * f[t] + lo;
+        time_derivative(x.data(), v.data());
+        for (int t = 0; t < nt; ++t) {
+          mot[t * MW + 6 + k] = x[t];
+          mot[t * MW + 9 + k] = v[t];
+        }
+      }
+      return;
     }
     filter(psi, 1, P.r_w, f.data());
     for (int t = 0; t < nt; ++t) x[t] = (P.th_max - P.th_min) * f[t] + P.th_min;
     time_derivative(x.data(), v.data());
     for (int t = 0; t < nt; ++t) {
-      mot[t * 8 + 6] = x[t];
-      mot[t * 8 + 7] = v[t];
+      mot[t * MW + 6] = x[t];
+      mot[t * MW + 7] = v[t];
     }
+  }
+
+  // Rotation about coordinate axis `ax` by angle a, differentiated `order`
+  // times with respect to a: the 2 x 2 block [[c, -s], [s, c]] sits on the
+  // two other axes in cyclic order (y, z for x; z, x for y; x, y for z).
+  void axis_rot(int ax, const T& a, int order, T M[3][3]) const {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) M[i][j] = 0.0;
+    // n-th derivatives of cos and sin
+    const T c = std::cos(a), s = std::sin(a);
+    T cn = c, sn = s;
+    if (order == 1) {
+      cn = -s;
+      sn = c;
+    } else if (order == 2) {
+      cn = -c;
+      sn = -s;
+    }
+    const int i = (ax + 1) % 3, j = (ax + 2) % 3;
+    M[ax][ax] = order == 0 ? 1.0 : 0.0;
+    M[i][i] = cn;
+    M[i][j] = -sn;
+    M[j][i] = sn;
+    M[j][j] = cn;
+  }
+  void matmul(const T A_[3][3], const T B[3][3], T C[3][3]) const {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        T v = 0.0;
+        for (int k = 0; k < 3; ++k) v += A_[i][k] * B[k][j];
+        C[i][j] = v;
+      }
+  }
+  // R = Rz(th3) Ry(th2) Rx(th1) differentiated o[k] times in th_k.
+  void euler_rot(const T* th, const int o[3], T R[3][3]) const {
+    T X[3][3], Y[3][3], Z[3][3], ZY[3][3];
+    axis_rot(0, th[0], o[0], X);
+    axis_rot(1, th[1], o[1], Y);
+    axis_rot(2, th[2], o[2], Z);
+    matmul(Z, Y, ZY);
+    matmul(ZY, X, R);
+  }
+  // M r for a 3 x 3 matrix and an offset r.
+  void apply(const T M[3][3], const double r[3], T out[3]) const {
+    for (int i = 0; i < 3; ++i) out[i] = M[i][0] * r[0] + M[i][1] * r[1] + M[i][2] * r[2];
   }
 
   // -------------------------------------------------------------- design
@@ -283,6 +345,27 @@ struct Oracle {
   // Rigid position and velocity of design point xi (Eqs. rigid_body_position,
   // rigid_body_velocity); rotation about z.
   void rigid(const int xi[3], const T* mot, T X[3], T U[3]) const {
+    if (P.rot == 1) {
+      // x_ref = R(th) r + x^G and its time derivative sum_k om_k (dR/dth_k) r + u^G
+      const double r[3] = {xi[0] - xiG[0], xi[1] - xiG[1], xi[2] - xiG[2]};
+      T R[3][3], v[3];
+      const int o0[3] = {0, 0, 0};
+      euler_rot(mot + 6, o0, R);
+      apply(R, r, v);
+      for (int a = 0; a < 3; ++a) {
+        X[a] = v[a] + mot[a];
+        U[a] = mot[3 + a];
+      }
+      for (int k = 0; k < 3; ++k) {
+        int o[3] = {0, 0, 0};
+        o[k] = 1;
+        T dR[3][3], dv[3];
+        euler_rot(mot + 6, o, dR);
+        apply(dR, r, dv);
+        for (int a = 0; a < 3; ++a) U[a] += mot[9 + k] * dv[a];
+      }
+      return;
+    }
     T th = mot[6], om = mot[7];
     T c = std::cos(th), s = std::sin(th);
     double r1 = xi[0] - xiG[0], r2 = xi[1] - xiG[1];
@@ -348,7 +431,7 @@ struct Oracle {
   // dJdchi, dJdpsi and the multipliers u~^G, omega~ of Sec. 2.5).
   void map_adjoint(const T* kref, const T* mot, const T* kbar, const T* usbar, T* kref_bar,
                    T* mbar) const {
-    for (int j = 0; j < 8; ++j) mbar[j] = 0.0;
+    for (int j = 0; j < MW; ++j) mbar[j] = 0.0;
     T th = mot[6], om = mot[7];
     T c = std::cos(th), s = std::sin(th);
     for (long k = 0; k < Mtot; ++k) {
@@ -378,6 +461,36 @@ struct Oracle {
         }
       });
       kref_bar[k] += kb;
+      if (P.rot == 1) {
+        // through x_ref = R r + x^G and u_ref = sum_j om_j (dR/dth_j) r + u^G:
+        // th_k gets Xb . (dR/dth_k) r + Ub . sum_j om_j (d2R/dth_k dth_j) r,
+        // om_k gets Ub . (dR/dth_k) r
+        const double r[3] = {xi[0] - xiG[0], xi[1] - xiG[1], xi[2] - xiG[2]};
+        for (int a = 0; a < 3; ++a) {
+          mbar[a] += Xb[a];
+          mbar[3 + a] += Ub[a];
+        }
+        for (int kk = 0; kk < 3; ++kk) {
+          int o[3] = {0, 0, 0};
+          o[kk] = 1;
+          T dR[3][3], dv[3];
+          euler_rot(mot + 6, o, dR);
+          apply(dR, r, dv);
+          T thb = Xb[0] * dv[0] + Xb[1] * dv[1] + Xb[2] * dv[2];
+          for (int j = 0; j < 3; ++j) {
+            int o2[3] = {0, 0, 0};
+            o2[kk] += 1;
+            o2[j] += 1;
+            T d2R[3][3], d2v[3];
+            euler_rot(mot + 6, o2, d2R);
+            apply(d2R, r, d2v);
+            thb += mot[9 + j] * (Ub[0] * d2v[0] + Ub[1] * d2v[1] + Ub[2] * d2v[2]);
+          }
+          mbar[6 + kk] += thb;
+          mbar[9 + kk] += Ub[0] * dv[0] + Ub[1] * dv[1] + Ub[2] * dv[2];
+        }
+        continue;
+      }
       double r1 = xi[0] - xiG[0], r2 = xi[1] - xiG[1];
       T dX1 = -s * r1 - c * r2, dX2 = c * r1 - s * r2;       // R'(theta) r
       T dU1 = om * (-c * r1 + s * r2), dU2 = om * (-s * r1 - c * r2);  // omega R''(theta) r
@@ -664,7 +777,7 @@ struct Oracle {
   void forward(const T* gamma, const T* chi, const T* psi, const T* state0, T* state_final,
                T* J3, T* traj) const {
     const long S = (long)(d + 1) * N;
-    std::vector<T> mot((size_t)P.nt * 8), kref(Mtot), kappa(N), us((size_t)d * N);
+    std::vector<T> mot((size_t)P.nt * MW), kref(Mtot), kappa(N), us((size_t)d * N);
     std::vector<T> a(S), b(S);
     motion(chi, psi, mot.data());
     kappa_ref(gamma, kref.data());
@@ -673,12 +786,12 @@ struct Oracle {
     T s1 = 0.0, s2 = 0.0;
     T jl = 0.0, jd = 0.0, jt = 0.0;  // J2 step sums
     for (int t = 1; t <= P.nt; ++t) {
-      map(kref.data(), &mot[(size_t)(t - 1) * 8], kappa.data(), us.data());
+      map(kref.data(), &mot[(size_t)(t - 1) * MW], kappa.data(), us.data());
       step(a.data(), kappa.data(), us.data(), b.data());
       std::swap(a, b);
       if (traj) std::copy(a.begin(), a.end(), traj + (long)t * S);
       if (P.objective == 1) {
-        j2_sums(kref.data(), &mot[(size_t)(t - 1) * 8], a.data() + N, jl, jd, jt);
+        j2_sums(kref.data(), &mot[(size_t)(t - 1) * MW], a.data() + N, jl, jd, jt);
         continue;
       }
       for (long xn = 0; xn < N; ++xn) {
@@ -761,14 +874,25 @@ struct Oracle {
         continue;
       }
       for (int t = 0; t < nt; ++t) {
-        xb[t] = mbar[t * 8 + a];
-        vb[t] = mbar[t * 8 + 3 + a];
+        xb[t] = mbar[t * MW + a];
+        vb[t] = mbar[t * MW + 3 + a];
       }
       chain(P.r_t, P.xg_max[a] - P.xg_min[a], dchi + a, 3);
     }
+    if (P.rot == 1) {
+      for (int k = 0; k < 3; ++k) {
+        for (int t = 0; t < nt; ++t) {
+          xb[t] = mbar[t * MW + 6 + k];
+          vb[t] = mbar[t * MW + 9 + k];
+        }
+        const double span = k < 2 ? P.tilt_max[k] - P.tilt_min[k] : P.th_max - P.th_min;
+        chain(P.r_w, span, dpsi + k, 3);
+      }
+      return;
+    }
     for (int t = 0; t < nt; ++t) {
-      xb[t] = mbar[t * 8 + 6];
-      vb[t] = mbar[t * 8 + 7];
+      xb[t] = mbar[t * MW + 6];
+      vb[t] = mbar[t * MW + 7];
     }
     chain(P.r_w, P.th_max - P.th_min, dpsi, 1);
   }
@@ -782,11 +906,11 @@ struct Oracle {
     T J3[3];
     forward(gamma, chi, psi, state0, nullptr, J3, traj.data());
     T E = J3[1];
-    std::vector<T> mot((size_t)nt * 8), kref(Mtot), kappa(N), us((size_t)d * N);
+    std::vector<T> mot((size_t)nt * MW), kref(Mtot), kappa(N), us((size_t)d * N);
     motion(chi, psi, mot.data());
     kappa_ref(gamma, kref.data());
     std::vector<T> lam(S, T(0.0)), lprev(S), kbar(N), usbar((size_t)d * N);
-    std::vector<T> kref_bar(Mtot, T(0.0)), mbar((size_t)nt * 8, T(0.0));
+    std::vector<T> kref_bar(Mtot, T(0.0)), mbar((size_t)nt * MW, T(0.0));
     if (adj_terminal)
       for (long i = 0; i < S; ++i) lam[i] += adj_terminal[i];
     long NT = (long)nt * target_count();
@@ -794,9 +918,9 @@ struct Oracle {
       const T* st = &traj[(size_t)t * S];
       // J2: seed now, motion partials after the map transpose (which writes
       // the step's row)
-      T j2m[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      T j2m[12] = {};
       if (P.objective == 1)
-        j2_adjoint(kref.data(), &mot[(size_t)(t - 1) * 8], st + N, dJ, lam.data() + N, 1.0,
+        j2_adjoint(kref.data(), &mot[(size_t)(t - 1) * MW], st + N, dJ, lam.data() + N, 1.0,
                    kref_bar.data(), j2m);
       if (NT > 0 && P.objective != 1) {
         for (long xn = 0; xn < N; ++xn) {
@@ -809,12 +933,12 @@ struct Oracle {
           for (int k = 0; k < d; ++k) lam[(k + 1) * N + xn] += g * P.ndir[k];
         }
       }
-      map(kref.data(), &mot[(size_t)(t - 1) * 8], kappa.data(), us.data());
+      map(kref.data(), &mot[(size_t)(t - 1) * MW], kappa.data(), us.data());
       step_adjoint(&traj[(size_t)(t - 1) * S], st, kappa.data(), us.data(), lam.data(),
                    lprev.data(), kbar.data(), usbar.data());
-      map_adjoint(kref.data(), &mot[(size_t)(t - 1) * 8], kbar.data(), usbar.data(),
-                  kref_bar.data(), &mbar[(size_t)(t - 1) * 8]);
-      for (int q = 0; q < 8; ++q) mbar[(size_t)(t - 1) * 8 + q] += j2m[q];
+      map_adjoint(kref.data(), &mot[(size_t)(t - 1) * MW], kbar.data(), usbar.data(),
+                  kref_bar.data(), &mbar[(size_t)(t - 1) * MW]);
+      for (int q = 0; q < 8; ++q) mbar[(size_t)(t - 1) * MW + q] += j2m[q];
       std::swap(lam, lprev);
     }
     if (adj_initial) std::copy(lam.begin(), lam.end(), adj_initial);
@@ -912,21 +1036,23 @@ struct Oracle {
       if (dG2) dG2[k] = -1.0 / (vmax * (double)Min);
     }
     const int nt = P.nt;
-    std::vector<T> mot((size_t)nt * 8);
+    std::vector<T> mot((size_t)nt * MW);
     motion(chi, psi, mot.data());
+    // omega about z (with three angles: om_3, the rate of the angle about z)
+    const int oc = P.rot == 1 ? 11 : 7;
     T S = 0.0;
-    for (int t = 0; t < nt; ++t) S += std::pow(std::abs(mot[(size_t)t * 8 + 7] / omax), pw);
+    for (int t = 0; t < nt; ++t) S += std::pow(std::abs(mot[(size_t)t * MW + oc] / omax), pw);
     G[2] = std::pow(S, 1.0 / pw) - 1.0;
     if (dG3_dpsi) {
       // dG3/domega_n, then the motion prelude's chain rule (D_t^T, bounds,
       // filter^T) as for the adjoint's motion partials
-      std::vector<T> mbar((size_t)nt * 8, T(0.0)), kb(Mtot, T(0.0)), dg(Min), dchi((size_t)nt * 3);
+      std::vector<T> mbar((size_t)nt * MW, T(0.0)), kb(Mtot, T(0.0)), dg(Min), dchi((size_t)nt * 3);
       // the p-norm is not differentiable where every omega is 0: take 0 there
       for (int t = 0; t < nt && re(S) > 0.0; ++t) {
-        const T om = mot[(size_t)t * 8 + 7];
+        const T om = mot[(size_t)t * MW + oc];
         const T a = std::abs(om / omax);
         const double sg = re(om) < 0.0 ? -1.0 : 1.0;
-        mbar[(size_t)t * 8 + 7] = std::pow(S, 1.0 / pw - 1.0) * std::pow(a, pw - 1.0) * sg / omax;
+        mbar[(size_t)t * MW + oc] = std::pow(S, 1.0 / pw - 1.0) * std::pow(a, pw - 1.0) * sg / omax;
       }
       sensitivities(phys, kb.data(), mbar.data(), dg.data(), dchi.data(), dG3_dpsi);
     }
@@ -1046,13 +1172,13 @@ struct Oracle {
     T J3[3];
     forward(gamma, chi, psi, state0, nullptr, J3, traj.data());
     T E = J3[1];
-    std::vector<T> mot((size_t)nt * 8), kref(Mtot), kappa(N), us((size_t)d * N);
+    std::vector<T> mot((size_t)nt * MW), kref(Mtot), kappa(N), us((size_t)d * N);
     motion(chi, psi, mot.data());
     kappa_ref(gamma, kref.data());
     std::vector<T> pt(N, T(0.0)), ut((size_t)d * N, T(0.0)), sl((size_t)9 * N, T(0.0));
     std::vector<T> pw(N, T(0.0));
     std::vector<T> ft, kbar(N), usbar((size_t)d * N);
-    std::vector<T> kref_bar(Mtot, T(0.0)), mbar((size_t)nt * 8, T(0.0));
+    std::vector<T> kref_bar(Mtot, T(0.0)), mbar((size_t)nt * MW, T(0.0));
     if (adj_terminal) {
       const T* c = adj_terminal + S;
       for (long i = 0; i < N; ++i) pt[i] = c[i];
@@ -1077,13 +1203,13 @@ struct Oracle {
                         &traj[(size_t)(t + 1) * S + N], ft);
         alks_gather(ft, pt.data(), ut.data(), sl.data());
       }
-      map(kref.data(), &mot[(size_t)(t - 1) * 8], kappa.data(), us.data());
+      map(kref.data(), &mot[(size_t)(t - 1) * MW], kappa.data(), us.data());
       // Eq. au: objective source -sum_i w_i c_i dJ/df_i = -(1/3) dJ/du, and
       // the Brinkman source -kappa u~ taken at the new value (implicit); the
       // kappa and objective terms of Eqs. ap and as are odd moments and vanish
-      T j2m[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      T j2m[12] = {};
       if (P.objective == 1)
-        j2_adjoint(kref.data(), &mot[(size_t)(t - 1) * 8], st + N, dJ, ut.data(), -1.0 / 3.0,
+        j2_adjoint(kref.data(), &mot[(size_t)(t - 1) * MW], st + N, dJ, ut.data(), -1.0 / 3.0,
                    kref_bar.data(), j2m);
       if (NT > 0 && P.objective != 1) {
         for (long xn = 0; xn < N; ++xn) {
@@ -1125,9 +1251,9 @@ struct Oracle {
         }
         kbar[xn] = kb;
       }
-      map_adjoint(kref.data(), &mot[(size_t)(t - 1) * 8], kbar.data(), usbar.data(),
-                  kref_bar.data(), &mbar[(size_t)(t - 1) * 8]);
-      for (int q = 0; q < 8; ++q) mbar[(size_t)(t - 1) * 8 + q] += j2m[q];
+      map_adjoint(kref.data(), &mot[(size_t)(t - 1) * MW], kbar.data(), usbar.data(),
+                  kref_bar.data(), &mbar[(size_t)(t - 1) * MW]);
+      for (int q = 0; q < 8; ++q) mbar[(size_t)(t - 1) * MW + q] += j2m[q];
     }
     if (adj_initial) {
       // level 0: moments gathered from level 1, no sources
@@ -1166,6 +1292,7 @@ int validate(const orc_problem* p) {
   if (p->objective != 0 && p->objective != 1) return -7;
   if (p->objective == 1 && (p->d != 2 || !(p->l_m > 0.0) || !(p->xg_max[1] > p->xg_min[1])))
     return -8;
+  if (p->rot != 0 && (p->rot != 1 || p->d != 3)) return -10;
   return 0;
 }
 
@@ -1342,7 +1469,7 @@ int orc_forward_cs(const orc_problem* p, const double* gamma_re, const double* g
   Oracle<cplx> o(*p);
   auto g = cjoin<cplx>(gamma_re, gamma_im, o.Min);
   auto c = cjoin<cplx>(chi_re, chi_im, (long)p->nt * 3);
-  auto s = cjoin<cplx>(psi_re, psi_im, p->nt);
+  auto s = cjoin<cplx>(psi_re, psi_im, (long)p->nt * (p->rot == 1 ? 3 : 1));
   std::vector<cplx> st;
   if (state0_re) st = cjoin<cplx>(state0_re, state0_im, (long)(o.d + 1) * o.N);
   std::vector<cplx> J(3);
@@ -1374,7 +1501,7 @@ int orc_map_cs(const orc_problem* p, const double* kref_re, const double* kref_i
   if (int e = validate(p)) return e;
   Oracle<cplx> o(*p);
   auto kr = cjoin<cplx>(kref_re, kref_im, o.Mtot);
-  auto m = cjoin<cplx>(mot_re, mot_im, 8);
+  auto m = cjoin<cplx>(mot_re, mot_im, o.MW);
   std::vector<cplx> k(o.N), u((size_t)o.d * o.N);
   o.map(kr.data(), m.data(), k.data(), u.data());
   csplit(k, k_re, k_im);

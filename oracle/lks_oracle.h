@@ -18,7 +18,9 @@
  * Conventions (lattice units, dx = dt = 1):
  *   - analysis fields are stored as planes [d+1][N]: plane 0 is the pressure p
  *     itself, planes 1..d the velocity components; x is fastest, then y, z.
- *   - motion table per time step n = 1..nt (row n-1): xg[3], ug[3], theta, omega.
+ *   - motion table per time step n = 1..nt (row n-1): xg[3], ug[3], theta, omega
+ *     (8 values); with rot = 1: xg[3], ug[3], th[3], om[3] (12 values), and
+ *     psi, dJ/dpsi are [nt][3] instead of [nt]; the motion partials likewise.
  *   - design grid (incl. margin) is [Dz][Dy][Dx], Dx = m[0] + 2*margin, ...;
  *     gamma covers only the inner m[0] x m[1] x m[2] block, margin gamma = 0.
  * All functions return 0 on success and a negative value on bad arguments.
@@ -49,6 +51,11 @@ typedef struct orc_problem {
   double phi;              /* J1 = E - phi * V */
   int32_t objective;       /* 0: J1 (Eq. objective1); 1: J2 (Eq. objective2, 2D) */
   double w_d, w_t, l_m;    /* J2 weights w_D, w_T and moment arm l_m */
+  int32_t rot;             /* 0: one angle about z (Eqs. psi_filtered, theta, omega);
+                              1 (3D only): three angles, R = Rz(th3) Ry(th2) Rx(th1),
+                              the Euler-angle extension closing Sec. 2.4 */
+  double tilt_min[2], tilt_max[2]; /* rot = 1: ranges of th1 (about x), th2 (about y);
+                                      th3 (about z) keeps th_min, th_max */
 } orc_problem;
 
 /* Motion prelude (Sec. 2.4): chi [nt][3], psi [nt] -> motion [nt][8]. */

@@ -31,6 +31,7 @@ class OrcProblem(C.Structure):
         ("r_t", C.c_int32), ("r_w", C.c_int32), ("tgt_lo", C.c_int32 * 3),
         ("tgt_hi", C.c_int32 * 3), ("ndir", C.c_double * 3), ("phi", C.c_double),
         ("objective", C.c_int32), ("w_d", C.c_double), ("w_t", C.c_double), ("l_m", C.c_double),
+        ("rot", C.c_int32), ("tilt_min", C.c_double * 2), ("tilt_max", C.c_double * 2),
     ]
 
 
@@ -79,7 +80,25 @@ def to_struct(p) -> OrcProblem:
     s.phi = p.phi
     s.objective = p.objective
     s.w_d, s.w_t, s.l_m = p.w_d, p.w_t, p.l_m
+    s.rot = getattr(p, "rot", 0)
+    for k in range(2):
+        s.tilt_min[k] = p.tilt_min[k]
+        s.tilt_max[k] = p.tilt_max[k]
     return s
+
+
+def mw(p) -> int:
+    """Motion row width: 8, or 12 with three rotation angles."""
+    return 12 if getattr(p, "rot", 0) == 1 else 8
+
+
+def npsi(p) -> int:
+    """Rotation design variables per step: 1, or 3 with three angles."""
+    return 3 if getattr(p, "rot", 0) == 1 else 1
+
+
+def _psi_shape(p, a):
+    return a.reshape(p.nt, 3) if npsi(p) == 3 else a
 
 
 def _ptr(a: Optional[np.ndarray]):
@@ -99,7 +118,7 @@ def _check(rc: int, name: str):
 
 
 def motion(p, chi, psi) -> np.ndarray:
-    out = np.zeros((p.nt, 8))
+    out = np.zeros((p.nt, mw(p)))
     _check(lib().orc_motion(C.byref(to_struct(p)), _ptr(_f64(chi)), _ptr(_f64(psi)),
                             _ptr(out)), "orc_motion")
     return out
@@ -122,7 +141,7 @@ def map_fields(p, kref, motion8):
 
 def map_adjoint(p, kref, motion8, kbar, usbar, kref_bar=None):
     kb = np.zeros(p.Mtot) if kref_bar is None else kref_bar
-    mb = np.zeros(8)
+    mb = np.zeros(mw(p))
     _check(lib().orc_map_adjoint(C.byref(to_struct(p)), _ptr(_f64(kref)), _ptr(_f64(motion8)),
                                  _ptr(_f64(kbar)), _ptr(_f64(usbar)), _ptr(kb), _ptr(mb)),
            "orc_map_adjoint")
@@ -166,15 +185,15 @@ def adjoint(p, gamma, chi, psi, state0=None, dJ=1.0, adj_terminal=None):
     ai = np.zeros(S)
     dg = np.zeros(p.M)
     dc = np.zeros(p.nt * 3)
-    dp = np.zeros(p.nt)
+    dp = np.zeros(p.nt * npsi(p))
     kb = np.zeros(p.Mtot)
-    mb = np.zeros(p.nt * 8)
+    mb = np.zeros(p.nt * mw(p))
     _check(lib().orc_adjoint(C.byref(to_struct(p)), _ptr(_f64(gamma)), _ptr(_f64(chi)),
                              _ptr(_f64(psi)), _ptr(_f64(state0)), C.c_double(dJ),
                              _ptr(_f64(adj_terminal)), _ptr(ai), _ptr(dg), _ptr(dc), _ptr(dp),
                              _ptr(kb), _ptr(mb)), "orc_adjoint")
-    return {"adj_initial": ai, "dgamma": dg, "dchi": dc.reshape(p.nt, 3), "dpsi": dp,
-            "kref_bar": kb, "motion_bar": mb.reshape(p.nt, 8)}
+    return {"adj_initial": ai, "dgamma": dg, "dchi": dc.reshape(p.nt, 3), "dpsi": _psi_shape(p, dp),
+            "kref_bar": kb, "motion_bar": mb.reshape(p.nt, mw(p))}
 
 
 def alks_state_size(p) -> int:
@@ -193,16 +212,16 @@ def alks_adjoint(p, gamma, chi, psi, state0=None, dJ=1.0, adj_terminal=None):
     ai = np.zeros(S)
     dg = np.zeros(p.M)
     dc = np.zeros(p.nt * 3)
-    dp = np.zeros(p.nt)
+    dp = np.zeros(p.nt * npsi(p))
     kb = np.zeros(p.Mtot)
-    mb = np.zeros(p.nt * 8)
+    mb = np.zeros(p.nt * mw(p))
     _check(lib().orc_alks_adjoint(C.byref(to_struct(p)), _ptr(_f64(gamma)), _ptr(_f64(chi)),
                                   _ptr(_f64(psi)), _ptr(_f64(state0)), C.c_double(dJ),
                                   _ptr(_f64(adj_terminal)), _ptr(ai), _ptr(dg), _ptr(dc),
                                   _ptr(dp), _ptr(kb), _ptr(mb)),
            "orc_alks_adjoint")
-    return {"adj_initial": ai, "dgamma": dg, "dchi": dc.reshape(p.nt, 3), "dpsi": dp,
-            "kref_bar": kb, "motion_bar": mb.reshape(p.nt, 8)}
+    return {"adj_initial": ai, "dgamma": dg, "dchi": dc.reshape(p.nt, 3), "dpsi": _psi_shape(p, dp),
+            "kref_bar": kb, "motion_bar": mb.reshape(p.nt, mw(p))}
 
 
 def alks_vector(p, carry, u):
@@ -253,7 +272,7 @@ def design_prelude_adjoint(p, gamma, radius, beta, eta, dphys):
 def constraints(p, phys, chi, psi, vmax, omega_max, p_omega):
     """(G1, G2, G3) of Sec. 2.6 with dG1, dG2 [M] and dG3/dpsi [nt]."""
     G = np.zeros(3)
-    d1, d2, d3 = np.zeros(p.M), np.zeros(p.M), np.zeros(p.nt)
+    d1, d2, d3 = np.zeros(p.M), np.zeros(p.M), np.zeros(p.nt * npsi(p))
     _check(lib().orc_constraints(C.byref(to_struct(p)), _ptr(_f64(phys)), _ptr(_f64(chi)),
                                  _ptr(_f64(psi)), C.c_double(vmax), C.c_double(omega_max),
                                  C.c_double(p_omega), _ptr(G), _ptr(d1), _ptr(d2), _ptr(d3)),
@@ -264,7 +283,7 @@ def constraints(p, phys, chi, psi, vmax, omega_max, p_omega):
 def sensitivities(p, gamma, kref_bar, motion_bar):
     dg = np.zeros(p.M)
     dc = np.zeros(p.nt * 3)
-    dp = np.zeros(p.nt)
+    dp = np.zeros(p.nt * npsi(p))
     _check(lib().orc_sensitivities(C.byref(to_struct(p)), _ptr(_f64(gamma)),
                                    _ptr(_f64(kref_bar)), _ptr(_f64(motion_bar)), None,
                                    _ptr(dg), _ptr(dc), _ptr(dp)), "orc_sensitivities")

@@ -59,6 +59,9 @@ class Problem:
     w_d: float = 0.0                          # J2 weight of the drag work F_D
     w_t: float = 0.0                          # J2 weight of the torque work T
     l_m: float = 1.0                          # J2 moment arm
+    rot: int = 0                              # 0: one angle about z; 1: three angles (3D)
+    tilt_min: Tuple[float, float] = (0.0, 0.0)  # rot = 1: ranges of the angles about x, y
+    tilt_max: Tuple[float, float] = (0.0, 0.0)
 
     @property
     def N(self) -> int:
