@@ -29,8 +29,10 @@
  *     nearest interior node); states returned by the library satisfy it.
  *   - adjoint state: planes [d+1][N] of the state type, dJ/dp then dJ/du.
  *   - gamma: [m2][m1][m0] doubles in [0,1] (inner design points, no margin).
- *   - chi: [nt][3] doubles (component z ignored when d = 2); psi: [nt] doubles.
- *   - motion table: [nt][8] doubles per step: xg[3], ug[3], theta, omega.
+ *   - chi: [nt][3] doubles (component z ignored when d = 2); psi: [nt] doubles,
+ *     or [nt][3] with rot = LKS_ROT_EULER.
+ *   - motion table: [nt][8] doubles per step: xg[3], ug[3], theta, omega; with
+ *     rot = LKS_ROT_EULER [nt][12]: xg[3], ug[3], th[3], om[3].
  *   - kappa_ref: [D2][D1][D0] of the state type, D = m + 2 * margin.
  *
  * Ownership: every buffer belongs to the caller.  The library never allocates
@@ -104,12 +106,24 @@ typedef struct lks_problem {
   double w_d, w_t;         /* J2 weights of F_D and T */
   double l_m;              /* J2 moment arm in T's normalisation 2 pi l_m (> 0);
                               F_D is normalised by xg_max[1] - xg_min[1] (> 0) */
+  int32_t rot;             /* LKS_ROT_Z: one rotation angle, about z (Sec. 2.4, Eqs.
+                              psi_filtered, theta, omega); LKS_ROT_EULER (3D only):
+                              three angles th1, th2, th3 about x, y, z, each from its
+                              own design series through the same filter, with
+                              R = Rz(th3) Ry(th2) Rx(th1) in Eq. rigid_body_position
+                              and u_ref = sum_k om_k (dR/dth_k) r + u^G (the Euler
+                              angles the closing remark of Sec. 2.4 names).  psi and
+                              dJ_dpsi are then [nt][3], motion rows hold 12 values */
+  double tilt_min[2], tilt_max[2]; /* LKS_ROT_EULER: ranges of th1 (about x) and th2
+                              (about y); th3 (about z) keeps th_min, th_max */
 } lks_problem;
 
 #define LKS_ADJ_EXACT 0
 #define LKS_ADJ_ALKS 1
 #define LKS_OBJ_J1 0
 #define LKS_OBJ_J2 1
+#define LKS_ROT_Z 0
+#define LKS_ROT_EULER 1
 
 #define LKS_BODY_TAPE_AUTO_MAX (96ull << 30)
 
@@ -168,8 +182,8 @@ lks_status lks_forward(lks_plan* plan, const double* gamma, const double* chi,
  *   the moments of the last level (before that level's sources), whose
  *   adjoint equilibrium is then formed with this run's own velocity at t1.
  *   A run's adj_initial can be passed as the next run's adj_terminal.
- * dJ_dgamma [m2][m1][m0], dJ_dchi [nt][3], dJ_dpsi [nt]: gradients of J
- *   (the paper maximises J; these are +grad J).
+ * dJ_dgamma [m2][m1][m0], dJ_dchi [nt][3], dJ_dpsi [nt] ([nt][3] with
+ *   LKS_ROT_EULER): gradients of J (the paper maximises J; these are +grad J).
  * Recomputes each K-step segment from its checkpoint. */
 lks_status lks_adjoint(lks_plan* plan, const double* gamma, const double* chi,
                        const double* psi, void* workspace, const double* dJ,
@@ -226,8 +240,9 @@ lks_status lks_constraints(lks_plan* plan, void* workspace, const double* gamma_
                            double* dG3_dpsi, hipStream_t stream);
 
 /* Design -> analysis transfer for one time step (Sec. 2.3, Eqs. kappa, u_s):
- * kappa_ref [D2][D1][D0] (state type), motion8 = (xg[3], ug[3], theta, omega)
- * doubles -> kappa [N] and u_s [d][N] (state type).  Wall nodes receive 0.
+ * kappa_ref [D2][D1][D0] (state type), motion8 = one motion row, (xg[3],
+ * ug[3], theta, omega) doubles (12 with LKS_ROT_EULER: xg, ug, th[3], om[3])
+ * -> kappa [N] and u_s [d][N] (state type).  Wall nodes receive 0.
  * workspace: the plan's workspace (3D keeps a z-fastest copy of kappa_ref
  * there; the checkpoints left by lks_forward are not touched and a later
  * lks_adjoint rebuilds its copy).  Reads motion8 back to
@@ -248,7 +263,8 @@ lks_status lks_sensitivities(lks_plan* plan, const double* gamma, const void* wo
 
 /* ---- single-stage entry points (used by tests; same kernels as above) ---- */
 
-/* Motion prelude only: chi, psi -> motion [nt][8] doubles (Sec. 2.4). */
+/* Motion prelude only: chi, psi -> motion [nt][8] doubles (Sec. 2.4), or
+ * [nt][12] with LKS_ROT_EULER. */
 lks_status lks_motion(lks_plan* plan, const double* chi, const double* psi, double* motion,
                       hipStream_t stream);
 
@@ -271,9 +287,10 @@ lks_status lks_step_adjoint(lks_plan* plan, const void* state_in, const void* st
 
 /* Transpose of lks_map_design_to_grid at one step: kbar [N], usbar [d][N]
  * (state type) -> kref_bar [Mtot] doubles (OVERWRITTEN) and motion_bar8
- * (first 8 doubles: xg_bar[3], ug_bar[3], theta_bar, omega_bar; the buffer
- * must hold 8 * (lks_map_adjoint_blocks(plan) + 1) doubles, the rest is
- * scratch for the fixed-order block reduction). */
+ * (first W doubles, W = 8 or 12 the motion row width: the partials of the
+ * row's entries, xg_bar[3], ug_bar[3], then the angles' and rates'; the
+ * buffer must hold W * (lks_map_adjoint_blocks(plan) + 1) doubles, the rest
+ * is scratch for the fixed-order block reduction). */
 lks_status lks_map_adjoint(lks_plan* plan, const void* kappa_ref, const double* motion8,
                            const void* kbar, const void* usbar, double* kref_bar,
                            double* motion_bar8, hipStream_t stream);
@@ -306,7 +323,8 @@ lks_status lks_batch_run(int32_t count, lks_plan* const* plans, const double* co
                          double* const* dJ_dpsi, hipStream_t stream);
 
 /* Number of per-block partial slots the stand-alone map transpose uses:
- * motion_bar8 of lks_map_adjoint must hold 8 * (blocks + 1) doubles. */
+ * motion_bar8 of lks_map_adjoint must hold W * (blocks + 1) doubles (W = 8,
+ * or 12 with LKS_ROT_EULER). */
 int32_t lks_map_adjoint_blocks(lks_plan* plan);
 
 /* ---- introspection ---- */

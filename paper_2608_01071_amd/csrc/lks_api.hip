@@ -197,6 +197,10 @@ lks_status validate(const lks_problem* p) {
   if (p->objective == LKS_OBJ_J2 &&
       (p->d != 2 || !(p->l_m > 0.0) || !(p->xg_max[1] > p->xg_min[1])))
     return fail(LKS_EINVAL, "J2 needs d = 2, l_m > 0 and xg_max[1] > xg_min[1]");
+  if (p->rot != LKS_ROT_Z && p->rot != LKS_ROT_EULER)
+    return fail(LKS_EINVAL, "rot must be LKS_ROT_Z or LKS_ROT_EULER");
+  if (p->rot == LKS_ROT_EULER && p->d != 3)
+    return fail(LKS_EINVAL, "three rotation angles need d = 3");
   if (!(p->nu >= 0.0) || !(p->kappa_max >= 0.0) || !(p->q > 0.0))
     return fail(LKS_EINVAL, "need nu >= 0, kappa_max >= 0, q > 0");
   long long N = 1;
@@ -243,6 +247,13 @@ void fill_geo(const lks_problem& p, Geo& g) {
   for (int a = 0; a < p.d; ++a) T *= std::max(0, p.tgt_hi[a] - p.tgt_lo[a]);
   g.NTinv = T > 0 ? 1.0 / ((double)p.nt * (double)T) : 0.0;
   g.obj = p.objective;
+  g.rot = p.rot == LKS_ROT_EULER ? 1 : 0;
+  g.mw = g.rot ? 12 : 8;
+  g.nmc = g.rot ? 6 : 4;
+  for (int k = 0; k < 2; ++k) {
+    g.tmin[k] = p.tilt_min[k];
+    g.tmax[k] = p.tilt_max[k];
+  }
   if (p.objective == LKS_OBJ_J2) {
     double Min = 1.0;
     for (int a = 0; a < p.d; ++a) Min *= p.m[a];
@@ -353,7 +364,9 @@ lks_status prelude(lks_plan* P, const double* gamma, const double* chi, const do
     const size_t M = (size_t)inner_points(P->g), nt = (size_t)P->g.nt;
     HIPCHK(hipMemcpyAsync(inp, gamma, M * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(inp + M, chi, 3 * nt * sizeof(double), hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(inp + M + 3 * nt, psi, nt * sizeof(double), hipMemcpyDeviceToDevice, s));
+    const size_t np = P->g.rot ? 3 : 1;  // rotation design variables per step
+    HIPCHK(hipMemcpyAsync(inp + M + 3 * nt, psi, np * nt * sizeof(double), hipMemcpyDeviceToDevice,
+                          s));
   }
   {
     Scope sc("prelude", s);
@@ -503,7 +516,7 @@ MapAdjArgs mapadj_args(lks_plan* P, void* ws, int n) {
   m.bkbar = wsp(ws, P->o_badj);
   m.bubar = wsp(ws, P->o_badj) + P->bmax.vol * P->es;
   m.kref_bar = (double*)wsp(ws, P->o_krefbar);
-  m.mpart = (double*)wsp(ws, P->o_mpart) + (size_t)(n - 1) * P->mrow * 8;
+  m.mpart = (double*)wsp(ws, P->o_mpart) + (size_t)(n - 1) * P->mrow * P->g.mw;
   m.overwrite = n == P->g.nt ? 1 : 0;
   return m;
 }
@@ -555,7 +568,8 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
       const MapAdjArgs m = mapadj_args(P, ws, nb);
       double* kp = (double*)wsp(ws, P->o_kpart);
       void* b0 = badj_slot(P, ws, 0);
-      const StepBatch sb{(long long)(body_bytes(P) / P->es), P->g.Mtot, (long long)P->mrow * 8};
+      const StepBatch sb{(long long)(body_bytes(P) / P->es), P->g.Mtot,
+                         (long long)P->mrow * P->g.mw};
       {
         Scope sc("map_adj", s, true);
         HIPCHK(launch_map_adjoint(P->g, P->prec, m.kref, nullptr, m.si, m.box, b0,
@@ -566,7 +580,7 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
         Scope sc("j2_adj", s, true);
         HIPCHK(launch_j2_adjoint(P->g, P->prec, m.kref, m.si, tape_slot(P, ws, 0), P->S,
                                  (const double*)wsp(ws, P->o_seed), kp, P->g.Mtot, m.mpart,
-                                 (long long)P->mrow * 8, P->nblk_map, cnt, s));
+                                 (long long)P->mrow * P->g.mw, P->nblk_map, cnt, s));
       }
       HIPCHK(launch_kref_accum(P->g.Mtot, cnt, kp, (double*)wsp(ws, P->o_krefbar), s));
     }
@@ -626,7 +640,7 @@ Box full_box(const lks_plan* P) {
 }
 
 lks_status host_box(lks_plan* P, const double* motion8_dev, double* m8, Box& box, hipStream_t s) {
-  HIPCHK(hipMemcpyAsync(m8, motion8_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(m8, motion8_dev, P->g.mw * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   int b[8];
   body_box(P->g, m8, b);
@@ -672,15 +686,17 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   P->j2 = prob->objective == LKS_OBJ_J2;
   P->nblk_j2 = P->j2 ? j2_blocks(g) : 0;
   P->mrow = P->nblk_map + P->nblk_j2;
-  // body-box bound over any rotation about z and any translation
+  // body-box bound over any rotation about z (or, with three angles, any
+  // rotation) and any translation
   const double diag = sqrt((double)(g.D[0] - 1) * (g.D[0] - 1) + (double)(g.D[1] - 1) * (g.D[1] - 1));
+  const double diag3 = sqrt(diag * diag + (double)(g.D[2] - 1) * (g.D[2] - 1));
   int ext[3];
   for (int a = 0; a < 3; ++a) {
     if (a >= g.d) {
       ext[a] = 1;
       continue;
     }
-    int e = (a < 2) ? (int)ceil(diag) + 6 : g.D[2] + 5;
+    int e = g.rot ? (int)ceil(diag3) + 6 : (a < 2) ? (int)ceil(diag) + 6 : g.D[2] + 5;
     ext[a] = std::min(e, g.n[a]);
   }
   memset(&P->bmax, 0, sizeof(Box));
@@ -695,7 +711,7 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
     return o;
   };
   const size_t Sb = (size_t)P->S * P->es;
-  P->o_mot = take((size_t)g.nt * 8 * sizeof(double));
+  P->o_mot = take((size_t)g.nt * g.mw * sizeof(double));
   P->o_tab = take((size_t)g.nt * sizeof(StepInfo));
   P->o_info = take(64 * sizeof(int));
   P->o_kref = take((size_t)g.Mtot * P->es);
@@ -722,18 +738,19 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   // ALKS: the state (p~, u~, s~) of level 0, written by the sweep's last step
   P->o_acarry = take(P->alks ? (size_t)alks_carry_planes(g.d) * g.N * P->es : 0);
   P->o_krefbar = take((size_t)g.Mtot * sizeof(double));
-  P->o_mpart = take((size_t)g.nt * P->mrow * 8 * sizeof(double));
+  P->o_mpart = take((size_t)g.nt * P->mrow * g.mw * sizeof(double));
   // J2: per-block step sums, and the reverse-step seeds of one segment on the body box
   P->o_j2acc = take((size_t)P->nblk_j2 * 3 * sizeof(double));
   P->o_j2seed = take(P->j2 ? (size_t)P->K * 2 * P->bmax.vol * P->es : 0);
-  P->o_mbar = take((size_t)g.nt * 8 * sizeof(double));
-  P->o_den = take((size_t)g.nt * 6 * sizeof(double));
+  P->o_mbar = take((size_t)g.nt * g.mw * sizeof(double));
+  // filter normalisers (2 nt) and the chain rule's per-component totals (nmc nt)
+  P->o_den = take((size_t)g.nt * (2 + g.nmc) * sizeof(double));
   // lks_constraints: its own motion table and a discarded chi-gradient
-  P->o_cmot = take((size_t)g.nt * 11 * sizeof(double));
+  P->o_cmot = take((size_t)g.nt * (g.mw + 3) * sizeof(double));
   P->o_kz = take(kz_bytes(g, P->bmax.ext[2], P->prec));
   P->o_geo = take(sizeof(Geo));
   // copies of the last lks_forward's gamma, chi, psi (lks_adjoint checks its own against them)
-  P->o_inp = take(((size_t)inner_points(g) + 4 * (size_t)g.nt) * sizeof(double));
+  P->o_inp = take(((size_t)inner_points(g) + 6 * (size_t)g.nt) * sizeof(double));
   P->total = off;
   *out = P;
   if (workspace_bytes) *workspace_bytes = P->total;
@@ -821,7 +838,7 @@ lks_status lks_adjoint(lks_plan* P, const double* gamma, const double* chi, cons
     HIPCHK(launch_zero(flag, sizeof(int), s));
     HIPCHK(launch_differ(gamma, inp, M, flag, s));
     HIPCHK(launch_differ(chi, inp + M, 3 * nt, flag, s));
-    HIPCHK(launch_differ(psi, inp + M + 3 * nt, nt, flag, s));
+    HIPCHK(launch_differ(psi, inp + M + 3 * nt, (P->g.rot ? 3 : 1) * nt, flag, s));
     int differ = 0;
     HIPCHK(hipMemcpyAsync(&differ, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -921,7 +938,7 @@ lks_status lks_constraints(lks_plan* P, void* ws, const double* gamma_phys, cons
   Scope sc("constraints", s);
   HIPCHK(launch_constraints(P->g, gamma_phys, chi, psi, vmax, omega_max, p_omega, G_out, dG1, dG2,
                             dG3_dpsi, cm, (double*)wsp(ws, P->o_mbar),
-                            (double*)wsp(ws, P->o_den), cm + (size_t)P->g.nt * 8, s));
+                            (double*)wsp(ws, P->o_den), cm + (size_t)P->g.nt * P->g.mw, s));
   return LKS_OK;
 }
 
@@ -942,7 +959,7 @@ lks_status lks_map_design_to_grid(lks_plan* P, const void* kappa_ref, const doub
                                   void* kappa, void* u_s, void* ws, hipStream_t s) {
   if (!P || !kappa_ref || !motion8 || !kappa || !u_s || !ws)
     return fail(LKS_EINVAL, "null argument");
-  double m8[8];
+  double m8[12];
   Box box;
   if (lks_status e = host_box(P, motion8, m8, box, s)) return e;
   HIPCHK(launch_zero(kappa, (size_t)P->g.N * P->es, s));
@@ -998,17 +1015,18 @@ lks_status lks_step_adjoint(lks_plan* P, const void* state_in, const void* state
 }
 
 // The stand-alone map transpose reduces its per-block partials in a second
-// fixed-order pass; motion_bar8 must hold 8 * (blocks + 1) doubles: the first
-// 8 receive the result, the rest serve as the partial store.
+// fixed-order pass; motion_bar8 must hold W * (blocks + 1) doubles (W the
+// motion row width, 8 or 12): the first W receive the result, the rest serve
+// as the partial store.
 lks_status lks_map_adjoint(lks_plan* P, const void* kappa_ref, const double* motion8,
                            const void* kbar, const void* usbar, double* kref_bar,
                            double* motion_bar8, hipStream_t s) {
   if (!P || !kappa_ref || !motion8 || !kbar || !usbar || !kref_bar || !motion_bar8)
     return fail(LKS_EINVAL, "null argument");
-  double m8[8];
+  double m8[12];
   Box box;
   if (lks_status e = host_box(P, motion8, m8, box, s)) return e;
-  double* part = motion_bar8 + 8;
+  double* part = motion_bar8 + P->g.mw;
   {
     Scope sc("map_adj", s, true);
     HIPCHK(launch_map_adjoint(P->g, P->prec, kappa_ref, m8, nullptr, full_box(P), kbar, usbar,

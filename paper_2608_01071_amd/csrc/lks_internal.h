@@ -99,6 +99,10 @@ struct Geo {
   int ty3;                // tile height of the step kernels (3D: Tile3<R>::TY; 2D: TILE_Y)
   int prec;               // state precision (0 FP32, 1 FP64)
   int nxcd;               // XCDs of the device (block -> tile order)
+  int rot;                // 0: one angle about z; 1: three angles (3D)
+  int mw;                 // motion row width: 8, or 12 with three angles
+  int nmc;                // motion components: x, y, z and the angles (4 or 6)
+  double tmin[2], tmax[2]; // rot = 1: ranges of the angles about x and y
   int obj;                // objective: 0 J1, 1 J2
   double j2s[3];          // J2 normalisations 1/(nt M), 1/((x2max - x2min) M),
                           // 1/(2 pi l_m M), M = inner design points
@@ -134,7 +138,82 @@ struct Box {
 struct StepInfo {
   double xg[3], ug[3], c, s, om;
   int lo[3], ext[3], flag, pad;
+  // rotation matrix and its time derivative (row major): with three angles
+  // R = Rz(th3) Ry(th2) Rx(th1) and Rd = sum_k om_k dR/dth_k; about z alone
+  // the same for R(theta)
+  double R[9], Rd[9];
+  double th[3], om3[3];  // the angles and their rates (about z alone: th[2], om3[2])
 };
+
+// Rotation about coordinate axis ax by angle a, differentiated `order` times
+// in a (0, 1 or 2), row major.
+__host__ __device__ inline void axis_rot(int ax, double a, int order, double* M) {
+  for (int k = 0; k < 9; ++k) M[k] = 0.0;
+  const double c = cos(a), s = sin(a);
+  double cn = c, sn = s;
+  if (order == 1) {
+    cn = -s;
+    sn = c;
+  } else if (order == 2) {
+    cn = -c;
+    sn = -s;
+  }
+  const int i = (ax + 1) % 3, j = (ax + 2) % 3;
+  M[ax * 3 + ax] = order == 0 ? 1.0 : 0.0;
+  M[i * 3 + i] = cn;
+  M[i * 3 + j] = -sn;
+  M[j * 3 + i] = sn;
+  M[j * 3 + j] = cn;
+}
+// Rz(th[2]) Ry(th[1]) Rx(th[0]), each factor differentiated o[k] times.
+__host__ __device__ inline void euler_mat(const double* th, const int* o, double* M) {
+  double X[9], Y[9], Z[9], ZY[9];
+  axis_rot(0, th[0], o[0], X);
+  axis_rot(1, th[1], o[1], Y);
+  axis_rot(2, th[2], o[2], Z);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double v = 0.0;
+      for (int k = 0; k < 3; ++k) v += Z[i * 3 + k] * Y[k * 3 + j];
+      ZY[i * 3 + j] = v;
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double v = 0.0;
+      for (int k = 0; k < 3; ++k) v += ZY[i * 3 + k] * X[k * 3 + j];
+      M[i * 3 + j] = v;
+    }
+}
+// Angles and rates of a motion row (8 or 12 values): about z alone the
+// angle and rate sit in th[2], om[2].
+__host__ __device__ inline void row_angles(int mw, const double* m, double th[3], double om[3]) {
+  if (mw == 12) {
+    for (int k = 0; k < 3; ++k) {
+      th[k] = m[6 + k];
+      om[k] = m[9 + k];
+    }
+  } else {
+    th[0] = th[1] = om[0] = om[1] = 0.0;
+    th[2] = m[6];
+    om[2] = m[7];
+  }
+}
+// Rotation and rate matrices of a motion row.
+__host__ __device__ inline void row_rotation(int mw, const double* m, double* R, double* Rd) {
+  double th[3], om[3];
+  row_angles(mw, m, th, om);
+  const int o0[3] = {0, 0, 0};
+  euler_mat(th, o0, R);
+  for (int k = 0; k < 9; ++k) Rd[k] = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    if (om[a] == 0.0) continue;
+    int o[3] = {0, 0, 0};
+    o[a] = 1;
+    double D[9];
+    euler_mat(th, o, D);
+    for (int k = 0; k < 9; ++k) Rd[k] += om[a] * D[k];
+  }
+}
 
 // Standard velocity sets with opposite directions in consecutive pairs
 // (rest direction first).
@@ -346,5 +425,7 @@ hipError_t launch_map_batch(int precision, const Batch<MapArgs>& b, hipStream_t 
 hipError_t launch_map_adjoint_batch(int precision, const Batch<MapAdjArgs>& b, hipStream_t s,
                                     int nsteps = 1);
 __host__ __device__ void body_box(const Geo& g, const double* m8, int* out);
+// StepInfo of one motion row (box included).
+__host__ __device__ void step_info(const Geo& g, const double* mrow, StepInfo& si);
 
 }  // namespace lks

@@ -2352,17 +2352,37 @@ __device__ double filter_den(int t, int nt, int R) {
 }
 
 // Temporal filter and bound map (Eqs. chi_filtered, x_g, psi_filtered, theta).
+// Motion component c (0..2 translation, 3.. the angles: one about z, or
+// three with rot = 1): its column of the position and of the rate in a
+// motion row, and its range.
+__host__ __device__ inline int mpos_col(const Geo& g, int c) { return c < 3 ? c : 6 + (c - 3); }
+__host__ __device__ inline int mrate_col(const Geo& g, int c) {
+  return c < 3 ? 3 + c : (g.rot ? 9 + (c - 3) : 7);
+}
+__host__ __device__ inline double mspan(const Geo& g, int c) {
+  if (c < 3) return g.xmax[c] - g.xmin[c];
+  const int k = c - 3;
+  if (g.rot && k < 2) return g.tmax[k] - g.tmin[k];
+  return g.thmax - g.thmin;
+}
+__host__ __device__ inline double mlow(const Geo& g, int c) {
+  if (c < 3) return g.xmin[c];
+  const int k = c - 3;
+  if (g.rot && k < 2) return g.tmin[k];
+  return g.thmin;
+}
+
 __global__ void k_motion_pos(Geo g, const double* chi, const double* psi, double* mot) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int comp = blockIdx.y;  // 0..2 translation, 3 rotation
+  const int comp = blockIdx.y;  // 0..2 translation, 3.. the angles
   if (t >= g.nt) return;
   if (comp < 3 && comp >= g.d) {
-    mot[t * 8 + comp] = 0.0;
+    mot[t * g.mw + comp] = 0.0;
     return;
   }
   const int R = comp < 3 ? g.r_t : g.r_w;
-  const double* src = comp < 3 ? chi + comp : psi;
-  const int stride = comp < 3 ? 3 : 1;
+  const double* src = comp < 3 ? chi + comp : psi + (g.rot ? comp - 3 : 0);
+  const int stride = comp < 3 ? 3 : (g.rot ? 3 : 1);
   double num = 0.0, den = 0.0;
   const int a = max(0, t - R + 1), b = min(g.nt - 1, t + R - 1);
   for (int tau = a; tau <= b; ++tau) {
@@ -2371,10 +2391,7 @@ __global__ void k_motion_pos(Geo g, const double* chi, const double* psi, double
     den += w;
   }
   const double f = num / den;
-  if (comp < 3)
-    mot[t * 8 + comp] = (g.xmax[comp] - g.xmin[comp]) * f + g.xmin[comp];
-  else
-    mot[t * 8 + 6] = (g.thmax - g.thmin) * f + g.thmin;
+  mot[t * g.mw + mpos_col(g, comp)] = mspan(g, comp) * f + mlow(g, comp);
 }
 
 // Time derivative of the filtered motion (Eqs. u_g, omega).
@@ -2382,28 +2399,44 @@ __global__ void k_motion_rate(Geo g, double* mot) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int comp = blockIdx.y;
   if (t >= g.nt) return;
-  const int pc = comp < 3 ? comp : 6, vc = comp < 3 ? 3 + comp : 7;
-  const int nt = g.nt;
+  const int pc = mpos_col(g, comp), vc = mrate_col(g, comp);
+  const int nt = g.nt, W = g.mw;
   double v;
   if (nt == 1)
     v = 0.0;
   else if (t == 0)
-    v = mot[8 + pc] - mot[pc];
+    v = mot[W + pc] - mot[pc];
   else if (t == nt - 1)
-    v = mot[(nt - 1) * 8 + pc] - mot[(nt - 2) * 8 + pc];
+    v = mot[(nt - 1) * W + pc] - mot[(nt - 2) * W + pc];
   else
-    v = 0.5 * (mot[(t + 1) * 8 + pc] - mot[(t - 1) * 8 + pc]);
-  mot[t * 8 + vc] = v;
+    v = 0.5 * (mot[(t + 1) * W + pc] - mot[(t - 1) * W + pc]);
+  mot[t * W + vc] = v;
 }
 
 // Support box per step and the domain check.  boxes[t] = lo[3], ext[3], flag, 0.
 __host__ __device__ void body_box(const Geo& g, const double* m8, int* out) {
   const double c = cos(m8[6]), s = sin(m8[6]);
+  double Rg[9], Rdg[9];
+  if (g.rot) row_rotation(g.mw, m8, Rg, Rdg);
   int lo[3], hi[3];
   int flag = 0;
   for (int pass = 0; pass < 2; ++pass) {  // 0: inner design points, 1: incl. margin
     double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
-    for (int corner = 0; corner < 4; ++corner) {
+    // three angles: the eight corners of the rotated design block
+    for (int corner = 0; g.rot && corner < 8; ++corner) {
+      double r[3];
+      for (int a = 0; a < 3; ++a) {
+        const bool up = (corner >> a) & 1;
+        const double e = pass == 0 ? (up ? g.margin + g.m[a] - 1 : g.margin) : (up ? g.D[a] - 1 : 0);
+        r[a] = e - g.xiG[a];
+      }
+      for (int a = 0; a < 3; ++a) {
+        const double X = Rg[a * 3] * r[0] + Rg[a * 3 + 1] * r[1] + Rg[a * 3 + 2] * r[2] + m8[a];
+        mn[a] = fmin(mn[a], X);
+        mx[a] = fmax(mx[a], X);
+      }
+    }
+    for (int corner = 0; !g.rot && corner < 4; ++corner) {
       double e0, e1;
       if (pass == 0) {
         e0 = (corner & 1) ? g.margin + g.m[0] - 1 : g.margin;
@@ -2419,7 +2452,7 @@ __host__ __device__ void body_box(const Geo& g, const double* m8, int* out) {
       mn[1] = fmin(mn[1], X1);
       mx[1] = fmax(mx[1], X1);
     }
-    if (g.d == 3) {
+    if (g.d == 3 && !g.rot) {
       const double lo2 = (pass == 0 ? g.margin : 0) - g.xiG[2];
       const double hi2 = (pass == 0 ? g.margin + g.m[2] - 1 : g.D[2] - 1) - g.xiG[2];
       mn[2] = lo2 + m8[2];
@@ -2456,34 +2489,39 @@ __host__ __device__ void body_box(const Geo& g, const double* m8, int* out) {
   out[7] = 0;
 }
 
-__global__ void k_steps(Geo g, const double* mot, StepInfo* tab, int* info) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.nt) return;
-  const double* m8 = mot + t * 8;
-  StepInfo si;
+__host__ __device__ void step_info(const Geo& g, const double* m, StepInfo& si) {
   for (int k = 0; k < 3; ++k) {
-    si.xg[k] = m8[k];
-    si.ug[k] = m8[3 + k];
+    si.xg[k] = m[k];
+    si.ug[k] = m[3 + k];
   }
-  si.c = cos(m8[6]);
-  si.s = sin(m8[6]);
-  si.om = m8[7];
+  row_angles(g.mw, m, si.th, si.om3);
+  si.c = cos(si.th[2]);
+  si.s = sin(si.th[2]);
+  si.om = si.om3[2];
+  row_rotation(g.mw, m, si.R, si.Rd);
   int b[8];
-  body_box(g, m8, b);
+  body_box(g, m, b);
   for (int k = 0; k < 3; ++k) {
     si.lo[k] = b[k];
     si.ext[k] = b[3 + k];
   }
   si.flag = b[6];
   si.pad = 0;
+}
+
+__global__ void k_steps(Geo g, const double* mot, StepInfo* tab, int* info) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.nt) return;
+  StepInfo si;
+  step_info(g, mot + t * g.mw, si);
   tab[t] = si;
-  if (b[6]) atomicMax(info, b[6]);
+  if (si.flag) atomicMax(info, si.flag);
 }
 
 __global__ void k_boxes(Geo g, const double* mot, int* boxes) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.nt) return;
-  body_box(g, mot + t * 8, boxes + t * 8);
+  body_box(g, mot + t * g.mw, boxes + t * 8);
 }
 
 // Eq. kappa_ref on the design grid incl. margin.
@@ -2550,35 +2588,36 @@ __global__ __launch_bounds__(SENS_MBAR_THREADS) void k_sens_mbar(Geo g, const do
                                                                   int nblk, double* mbar) {
   __shared__ double red[SENS_MBAR_THREADS];
   const int t = blockIdx.x;
-  const int j = threadIdx.x / 8, q = threadIdx.x % 8;
+  const int W = g.mw, G = SENS_MBAR_THREADS / W;  // G lane groups of W
+  const int j = threadIdx.x / W, q = threadIdx.x % W;
   double s = 0.0;
-  if (t < g.nt) {
-    const double* p = mpart + (long long)t * nblk * 8;
-    for (int b = j; b < nblk; b += SENS_MBAR_THREADS / 8) s += p[b * 8 + q];
+  if (t < g.nt && j < G) {
+    const double* p = mpart + (long long)t * nblk * W;
+    for (int b = j; b < nblk; b += G) s += p[b * W + q];
   }
   red[threadIdx.x] = s;
   __syncthreads();
   if (t < g.nt && j == 0) {
     double a = 0.0;
-    for (int i = 0; i < SENS_MBAR_THREADS / 8; ++i) a += red[i * 8 + q];
-    mbar[t * 8 + q] = a;
+    for (int i = 0; i < G; ++i) a += red[i * W + q];
+    mbar[t * W + q] = a;
   }
 }
 
 // tot[t][c] = span_c * (xbar(t) + (D_t^T vbar)(t)); den_t, den_w filter normalisers.
 __global__ void k_sens_tot(Geo g, const double* mbar, double* tot, double* den_t, double* den_w) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = blockIdx.y;  // 0..2 translation, 3 rotation
-  const int nt = g.nt;
+  const int c = blockIdx.y;  // 0..2 translation, 3.. the angles
+  const int nt = g.nt, W = g.mw;
   if (t >= nt) return;
   if (c == 0) {
     den_t[t] = filter_den(t, nt, g.r_t);
     den_w[t] = filter_den(t, nt, g.r_w);
   }
-  const int pc = c < 3 ? c : 6, vc = c < 3 ? 3 + c : 7;
-  double v = mbar[t * 8 + pc];
+  const int pc = mpos_col(g, c), vc = mrate_col(g, c);
+  double v = mbar[t * W + pc];
   if (nt >= 2) {
-    auto vb = [&](int tt) { return mbar[tt * 8 + vc]; };
+    auto vb = [&](int tt) { return mbar[tt * W + vc]; };
     if (t == 0) v -= vb(0);
     if (t == 1) v += vb(0);
     if (t == nt - 1) v += vb(nt - 1);
@@ -2586,8 +2625,7 @@ __global__ void k_sens_tot(Geo g, const double* mbar, double* tot, double* den_t
     if (t - 1 >= 1 && t - 1 <= nt - 2) v += 0.5 * vb(t - 1);
     if (t + 1 >= 1 && t + 1 <= nt - 2) v -= 0.5 * vb(t + 1);
   }
-  const double span = c < 3 ? (g.xmax[c] - g.xmin[c]) : (g.thmax - g.thmin);
-  tot[t * 4 + c] = (c < 3 && c >= g.d) ? 0.0 : span * v;
+  tot[t * g.nmc + c] = (c < 3 && c >= g.d) ? 0.0 : mspan(g, c) * v;
 }
 
 // Transposed temporal filter -> dJ/dchi, dJ/dpsi.
@@ -2602,10 +2640,12 @@ __global__ void k_sens_filter(Geo g, const double* tot, const double* den_t, con
   double s = 0.0;
   if (!(c < 3 && c >= g.d)) {
     const int a = max(0, tau - R + 1), b = min(nt - 1, tau + R - 1);
-    for (int t = a; t <= b; ++t) s += ((double)(R - abs(t - tau)) / (double)R / den[t]) * tot[t * 4 + c];
+    for (int t = a; t <= b; ++t) s += ((double)(R - abs(t - tau)) / (double)R / den[t]) * tot[t * g.nmc + c];
   }
   if (c < 3)
     dchi[tau * 3 + c] = s;
+  else if (g.rot)
+    dpsi[tau * 3 + (c - 3)] = s;
   else
     dpsi[tau] = s;
 }
@@ -2785,7 +2825,9 @@ __global__ __launch_bounds__(256) void k_con_omega(Geo g, const double* mot, dou
                                                    double pw, double* Gout, double* mbar) {
   __shared__ double S_all;
   double v[1] = {0.0};
-  for (int t = threadIdx.x; t < g.nt; t += 256) v[0] += pow(fabs(mot[t * 8 + 7] / omax), pw);
+  // the rate of the angle about z (Eq. constraint3)
+  const int oc = mrate_col(g, g.nmc - 1), W = g.mw;
+  for (int t = threadIdx.x; t < g.nt; t += 256) v[0] += pow(fabs(mot[t * W + oc] / omax), pw);
   double tot[1];
   block_sum<1, 256>(v, tot);
   if (threadIdx.x == 0) {
@@ -2795,12 +2837,11 @@ __global__ __launch_bounds__(256) void k_con_omega(Geo g, const double* mot, dou
   __syncthreads();
   const double S = S_all;
   for (int t = threadIdx.x; t < g.nt; t += 256) {
-    const double om = mot[t * 8 + 7];
+    const double om = mot[t * W + oc];
     const double a = fabs(om / omax);
     const double gb = S > 0.0 ? pow(S, 1.0 / pw - 1.0) * pow(a, pw - 1.0) * (om < 0.0 ? -1.0 : 1.0) / omax
                               : 0.0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) mbar[t * 8 + q] = q == 7 ? gb : 0.0;
+    for (int q = 0; q < W; ++q) mbar[t * W + q] = q == oc ? gb : 0.0;
   }
 }
 
@@ -2882,6 +2923,190 @@ LaunchEvents& launch_events() {
 }
 
 // Launch that carries the pending profiling event pair, if any.
+// ------------------------------------ map and transpose, three rotation angles
+// With a general rotation R = Rz(th3) Ry(th2) Rx(th1) the kernel window has
+// no axis-aligned factor.  Each analysis node of the box gathers over the
+// design points whose rotated position lies within its kernel support: with
+// q = R^T (x - x^G) + xi^G the node in design coordinates, x - X(e) =
+// R (q - e), and the candidates e are the integer points of the box
+// |e_a - q_a| <= 2 sum_b |R_ba| (the preimage of the support cube's bounding
+// box).  Geometry in FP64, kernel weights in the state precision.  One
+// thread per box node.  sv is the step's data when si is null.
+template <class R>
+__global__ __launch_bounds__(256) void k_map3r(Geo g, const R* kref, StepInfo sv,
+                                               const StepInfo* si, Box box, R* bk, R* bu,
+                                               int full_grid) {
+  const StepInfo& S = si ? *si : sv;
+  const int e0 = S.ext[0], e1 = S.ext[1], e2 = S.ext[2];
+  const long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (idx >= (long long)e0 * e1 * e2) return;
+  const int i = (int)(idx % e0), j = (int)((idx / e0) % e1), kk = (int)(idx / ((long long)e0 * e1));
+  const int bx = S.lo[0] + i, by = S.lo[1] + j, bz = S.lo[2] + kk;
+  int x = bx, y = by, z = bz;
+  const bool inside = wrap_axis(g, 0, x) && wrap_axis(g, 1, y) && wrap_axis(g, 2, z);
+  const bool wall = !inside || is_wall(g, x, y, z);
+  R kv = R(0), m0 = R(0), m1[3] = {R(0), R(0), R(0)};
+  if (!wall) {
+    const double v[3] = {bx - S.xg[0], by - S.xg[1], bz - S.xg[2]};
+    double q[3];
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      q[a] = S.R[a] * v[0] + S.R[3 + a] * v[1] + S.R[6 + a] * v[2] + g.xiG[a];
+      const double h = 2.0 * (fabs(S.R[a]) + fabs(S.R[3 + a]) + fabs(S.R[6 + a]));
+      lo[a] = max(0, (int)ceil(q[a] - h));
+      hi[a] = min(g.D[a] - 1, (int)floor(q[a] + h));
+    }
+    for (int c2 = lo[2]; c2 <= hi[2]; ++c2)
+      for (int c1 = lo[1]; c1 <= hi[1]; ++c1)
+        for (int c0 = lo[0]; c0 <= hi[0]; ++c0) {
+          const double r[3] = {c0 - g.xiG[0], c1 - g.xiG[1], c2 - g.xiG[2]};
+          double d[3];
+          bool in = true;
+          for (int a = 0; a < 3; ++a) {
+            d[a] = v[a] - (S.R[a * 3] * r[0] + S.R[a * 3 + 1] * r[1] + S.R[a * 3 + 2] * r[2]);
+            in = in && fabs(d[a]) < 2.0;
+          }
+          if (!in) continue;
+          const R W = wk((R)d[0]) * wk((R)d[1]) * wk((R)d[2]);
+          kv += W * kref[c0 + (long long)g.D[0] * (c1 + (long long)g.D[1] * c2)];
+          m0 += W;
+          for (int a = 0; a < 3; ++a) m1[a] += W * (R)r[a];
+        }
+  }
+  // u_s = sum W (Rd r + u^G) = Rd m1 + u^G m0
+  R us[3];
+  for (int a = 0; a < 3; ++a)
+    us[a] = (R)S.Rd[a * 3] * m1[0] + (R)S.Rd[a * 3 + 1] * m1[1] + (R)S.Rd[a * 3 + 2] * m1[2] +
+            (R)S.ug[a] * m0;
+  if (full_grid) {
+    if (wall) return;
+    const long long n = nidx(g, x, y, z);
+    bk[n] = kv;
+    for (int a = 0; a < 3; ++a) bu[a * g.N + n] = us[a];
+  } else {
+    const long long bi = i + (long long)box.sx * (j + (long long)box.sy * kk);
+    bk[bi] = kv;
+    for (int a = 0; a < 3; ++a) bu[a * box.vol + bi] = wall ? R(0) : us[a];
+  }
+}
+
+// Transpose of k_map3r at one step per blockIdx.y (a segment's steps in one
+// launch, strides sb): one thread per design point e gathers the body
+// adjoint (dJ/dkappa, dJ/du_s) of the 64 analysis nodes of its kernel
+// support and forms kappa_ref-bar(e) = sum W kbar, U-bar = sum W usbar,
+// X-bar = sum dW/dX (kappa_ref kbar + U . usbar); then the step's motion
+// partials: x^G-bar += X-bar, u^G-bar += U-bar, for each angle
+// th_k-bar += X-bar . (dR/dth_k) r + U-bar . sum_j om_j (d2R/dth_k dth_j) r and
+// om_k-bar += U-bar . (dR/dth_k) r, summed over the block in a fixed order
+// into mpart [blocks][12].  Accumulations in FP64.
+template <class R>
+__global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3r(Geo g, const R* kref, StepInfo sv,
+                                                             const StepInfo* si, Box box,
+                                                             const R* bkbar, const R* bubar,
+                                                             double* kref_bar, int overwrite,
+                                                             double* mpart, StepBatch sb) {
+  const int y = blockIdx.y;
+  if (si) si += y;
+  bkbar += (long long)y * sb.body;
+  bubar += (long long)y * sb.body;
+  kref_bar += (long long)y * sb.kref;
+  mpart += (long long)y * sb.mpart;
+  const StepInfo& S = si ? *si : sv;
+  // dR/dth_k and sum_j om_j d2R/dth_k dth_j, once per block
+  __shared__ double dR[3][9], dW[3][9];
+  if (threadIdx.x < 6) {
+    const int k = threadIdx.x % 3;
+    if (threadIdx.x < 3) {
+      int o[3] = {0, 0, 0};
+      o[k] = 1;
+      euler_mat(S.th, o, dR[k]);
+    } else {
+      double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      for (int jj = 0; jj < 3; ++jj) {
+        int o[3] = {0, 0, 0};
+        o[k] += 1;
+        o[jj] += 1;
+        double M[9];
+        euler_mat(S.th, o, M);
+        for (int q = 0; q < 9; ++q) acc[q] += S.om3[jj] * M[q];
+      }
+      for (int q = 0; q < 9; ++q) dW[k][q] = acc[q];
+    }
+  }
+  __syncthreads();
+  Box b = box;
+  for (int a = 0; a < 3; ++a) {
+    b.lo[a] = S.lo[a];
+    b.ext[a] = S.ext[a];
+  }
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  double mp[12];
+  for (int q = 0; q < 12; ++q) mp[q] = 0.0;
+  if (e < g.Mtot) {
+    const int c0 = (int)(e % g.D[0]), c1 = (int)((e / g.D[0]) % g.D[1]),
+              c2 = (int)(e / ((long long)g.D[0] * g.D[1]));
+    const double r[3] = {c0 - g.xiG[0], c1 - g.xiG[1], c2 - g.xiG[2]};
+    double X[3], U[3];
+    for (int a = 0; a < 3; ++a) {
+      X[a] = S.R[a * 3] * r[0] + S.R[a * 3 + 1] * r[1] + S.R[a * 3 + 2] * r[2] + S.xg[a];
+      U[a] = S.Rd[a * 3] * r[0] + S.Rd[a * 3 + 1] * r[1] + S.Rd[a * 3 + 2] * r[2] + S.ug[a];
+    }
+    const double kr = (double)kref[e];
+    int lo[3];
+    for (int a = 0; a < 3; ++a) lo[a] = (int)floor(X[a]) - 1;
+    double kb = 0.0, Ub[3] = {0.0, 0.0, 0.0}, Xb[3] = {0.0, 0.0, 0.0};
+    for (int t2 = 0; t2 < 4; ++t2)
+      for (int t1 = 0; t1 < 4; ++t1)
+        for (int t0 = 0; t0 < 4; ++t0) {
+          int xx[3] = {lo[0] + t0, lo[1] + t1, lo[2] + t2};
+          double d[3];
+          for (int a = 0; a < 3; ++a) d[a] = xx[a] - X[a];
+          if (!(wrap_axis(g, 0, xx[0]) && wrap_axis(g, 1, xx[1]) && wrap_axis(g, 2, xx[2])))
+            continue;
+          if (is_wall(g, xx[0], xx[1], xx[2])) continue;
+          const long long bi = box_index(g, b, xx[0], xx[1], xx[2]);
+          if (bi < 0) continue;
+          double w[3], dw[3];
+          for (int a = 0; a < 3; ++a) {
+            w[a] = (double)wk((R)d[a]);
+            dw[a] = (double)wkd((R)d[a]);
+          }
+          const double W = w[0] * w[1] * w[2];
+          const double kbv = (double)bkbar[bi];
+          const double ub[3] = {(double)bubar[bi], (double)bubar[b.vol + bi],
+                                (double)bubar[2 * b.vol + bi]};
+          kb += W * kbv;
+          const double gsum = kr * kbv + U[0] * ub[0] + U[1] * ub[1] + U[2] * ub[2];
+          for (int a = 0; a < 3; ++a) Ub[a] += W * ub[a];
+          Xb[0] += -dw[0] * w[1] * w[2] * gsum;
+          Xb[1] += -w[0] * dw[1] * w[2] * gsum;
+          Xb[2] += -w[0] * w[1] * dw[2] * gsum;
+        }
+    if (overwrite)
+      kref_bar[e] = kb;
+    else
+      kref_bar[e] += kb;
+    for (int a = 0; a < 3; ++a) {
+      mp[a] = Xb[a];
+      mp[3 + a] = Ub[a];
+    }
+    for (int k = 0; k < 3; ++k) {
+      double dv[3], wv[3];
+      for (int a = 0; a < 3; ++a) {
+        dv[a] = dR[k][a * 3] * r[0] + dR[k][a * 3 + 1] * r[1] + dR[k][a * 3 + 2] * r[2];
+        wv[a] = dW[k][a * 3] * r[0] + dW[k][a * 3 + 1] * r[1] + dW[k][a * 3 + 2] * r[2];
+      }
+      mp[6 + k] = Xb[0] * dv[0] + Xb[1] * dv[1] + Xb[2] * dv[2] + Ub[0] * wv[0] + Ub[1] * wv[1] +
+                  Ub[2] * wv[2];
+      mp[9 + k] = Ub[0] * dv[0] + Ub[1] * dv[1] + Ub[2] * dv[2];
+    }
+  }
+  double tot[12];
+  block_sum<12, MAPADJ_THREADS>(mp, tot);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 12; ++q) mpart[(long long)blockIdx.x * 12 + q] = tot[q];
+}
+
 #define LKS_LAUNCH(K, GRID, BLOCK, SHMEM, STREAM, ...)                                    \
   do {                                                                                   \
     LaunchEvents& le_ = launch_events();                                                 \
@@ -2967,6 +3192,25 @@ hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf
                       void* bu, int full_grid, hipStream_t s) {
   (void)ext2max;
   if (box.ext[0] <= 0 || box.ext[1] <= 0 || box.ext[2] <= 0) return hipSuccess;
+  if (g.rot) {
+    StepInfo sv;
+    memset(&sv, 0, sizeof sv);
+    if (mot8_host) step_info(g, mot8_host, sv);
+    if (mot8_host && !si)
+      for (int a = 0; a < 3; ++a) {  // the caller's box (a stand-alone map)
+        sv.lo[a] = box.lo[a];
+        sv.ext[a] = box.ext[a];
+      }
+    const long long n = (long long)box.ext[0] * box.ext[1] * box.ext[2];
+    dim3 grid((unsigned)((n + 255) / 256));
+    if (precision == 0)
+      LKS_LAUNCH(k_map3r<float>, grid, dim3(256), 0, s, g, (const float*)kref, sv, si, box,
+                 (float*)bk, (float*)bu, full_grid);
+    else
+      LKS_LAUNCH(k_map3r<double>, grid, dim3(256), 0, s, g, (const double*)kref, sv, si, box,
+                 (double*)bk, (double*)bu, full_grid);
+    return hipGetLastError();
+  }
   Mot m;
   if (mot8_host)
     m = make_mot(mot8_host);
@@ -3001,6 +3245,7 @@ static int mapadj_lch(const Geo& g) {
 }
 
 int mapadj_blocks(const Geo& g) {
+  if (g.rot) return (int)((g.Mtot + MAPADJ_THREADS - 1) / MAPADJ_THREADS);
   if (g.d == 3) {
     const int lch = mapadj_lch(g);
     const long long n = (long long)g.D[0] * g.D[1] * ((g.D[2] + lch - 1) / lch) * MAPADJ_TPC;
@@ -3013,6 +3258,25 @@ hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
                               const double* mot8_host, const StepInfo* si, const Box& box,
                               const void* bkbar, const void* bubar, double* kref_bar, int overwrite,
                               double* mpart, hipStream_t s, int nsteps, StepBatch sb) {
+  if (g.rot) {
+    StepInfo sv;
+    memset(&sv, 0, sizeof sv);
+    if (mot8_host) step_info(g, mot8_host, sv);
+    if (mot8_host && !si)
+      for (int a = 0; a < 3; ++a) {
+        sv.lo[a] = box.lo[a];
+        sv.ext[a] = box.ext[a];
+      }
+    const dim3 grid(mapadj_blocks(g), nsteps);
+    if (precision == 0)
+      LKS_LAUNCH(k_mapadj3r<float>, grid, dim3(MAPADJ_THREADS), 0, s, g, (const float*)kref, sv,
+                 si, box, (const float*)bkbar, (const float*)bubar, kref_bar, overwrite, mpart, sb);
+    else
+      LKS_LAUNCH(k_mapadj3r<double>, grid, dim3(MAPADJ_THREADS), 0, s, g, (const double*)kref,
+                 sv, si, box, (const double*)bkbar, (const double*)bubar, kref_bar, overwrite,
+                 mpart, sb);
+    return hipGetLastError();
+  }
   Mot m;
   if (mot8_host)
     m = make_mot(mot8_host);
@@ -3157,7 +3421,7 @@ hipError_t launch_kappa_ref(const Geo& g, int precision, const double* gamma, vo
 
 hipError_t launch_motion(const Geo& g, const double* chi, const double* psi, double* mot,
                          hipStream_t s) {
-  dim3 grid((g.nt + 255) / 256, 4);
+  dim3 grid((g.nt + 255) / 256, g.nmc);
   hipLaunchKernelGGL(k_motion_pos, grid, dim3(256), 0, s, g, chi, psi, mot);
   hipLaunchKernelGGL(k_motion_rate, grid, dim3(256), 0, s, g, mot);
   return hipGetLastError();
@@ -3190,9 +3454,9 @@ hipError_t launch_sens(const Geo& g, int precision, const double* gamma, const d
     hipLaunchKernelGGL(k_sens_gamma, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, g, gamma,
                        kref_bar, dgamma);
   hipLaunchKernelGGL(k_sens_mbar, dim3(g.nt), dim3(SENS_MBAR_THREADS), 0, s, g, mpart, nblk, mbar);
-  // tot buffer follows den_w (nt * 4 doubles) -- see workspace layout
+  // tot buffer follows den_w (nt * nmc doubles) -- see workspace layout
   double* tot = den_w + g.nt;
-  dim3 grid((g.nt + 255) / 256, 4);
+  dim3 grid((g.nt + 255) / 256, g.nmc);
   hipLaunchKernelGGL(k_sens_tot, grid, dim3(256), 0, s, g, mbar, tot, den_t, den_w);
   hipLaunchKernelGGL(k_sens_filter, grid, dim3(256), 0, s, g, tot, den_t, den_w, dchi, dpsi);
   return hipGetLastError();
@@ -3302,7 +3566,7 @@ hipError_t launch_constraints(const Geo& g, const double* phys, const double* ch
     double* den_t = den;
     double* den_w = den + g.nt;
     double* tot = den_w + g.nt;
-    const dim3 grid((g.nt + 255) / 256, 4);
+    const dim3 grid((g.nt + 255) / 256, g.nmc);
     hipLaunchKernelGGL(k_sens_tot, grid, dim3(256), 0, s, g, (const double*)mbar, tot, den_t, den_w);
     hipLaunchKernelGGL(k_sens_filter, grid, dim3(256), 0, s, g, (const double*)tot,
                        (const double*)den_t, (const double*)den_w, dchi_scratch, dG3_dpsi);

@@ -41,7 +41,8 @@ class LksProblem(C.Structure):
         ("tgt_lo", C.c_int32 * 3), ("tgt_hi", C.c_int32 * 3), ("ndir", C.c_double * 3),
         ("phi", C.c_double), ("ckpt_k", C.c_int32), ("body_tape", C.c_int32),
         ("scheme", C.c_int32), ("objective", C.c_int32), ("w_d", C.c_double),
-        ("w_t", C.c_double), ("l_m", C.c_double),
+        ("w_t", C.c_double), ("l_m", C.c_double), ("rot", C.c_int32),
+        ("tilt_min", C.c_double * 2), ("tilt_max", C.c_double * 2),
     ]
 
 
@@ -123,7 +124,21 @@ def to_struct(p) -> LksProblem:
     s.scheme = p.scheme
     s.objective = p.objective
     s.w_d, s.w_t, s.l_m = p.w_d, p.w_t, p.l_m
+    s.rot = getattr(p, "rot", 0)
+    for k in range(2):
+        s.tilt_min[k] = p.tilt_min[k]
+        s.tilt_max[k] = p.tilt_max[k]
     return s
+
+
+def motion_width(p) -> int:
+    """Values per motion row: 8, or 12 with three rotation angles."""
+    return 12 if getattr(p, "rot", 0) == 1 else 8
+
+
+def psi_per_step(p) -> int:
+    """Rotation design variables per step: 1, or 3 with three angles."""
+    return 3 if getattr(p, "rot", 0) == 1 else 1
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -215,21 +230,25 @@ class Plan:
               if want_initial else None)
         dg = torch.empty(p.M, dtype=torch.float64, device=self.device)
         dc = torch.empty(p.nt * 3, dtype=torch.float64, device=self.device)
-        dp = torch.empty(p.nt, dtype=torch.float64, device=self.device)
+        dp = torch.empty(p.nt * psi_per_step(p), dtype=torch.float64, device=self.device)
         _check(lib().lks_adjoint(self.handle, _ptr(g), _ptr(c), _ptr(s), _ptr(self.workspace),
                                  _ptr(seed), _ptr(at), _ptr(ai), _ptr(dg), _ptr(dc), _ptr(dp),
                                  _stream()))
-        return {"dgamma": dg, "dchi": dc.reshape(p.nt, 3), "dpsi": dp, "adj_initial": ai}
+        return {"dgamma": dg, "dchi": dc.reshape(p.nt, 3), "dpsi": self._psi_view(dp),
+                "adj_initial": ai}
+
+    def _psi_view(self, t):
+        return t.reshape(self.problem.nt, 3) if psi_per_step(self.problem) == 3 else t
 
     def sensitivities(self, gamma):
         p = self.problem
         g = self._f64(gamma)
         dg = torch.empty(p.M, dtype=torch.float64, device=self.device)
         dc = torch.empty(p.nt * 3, dtype=torch.float64, device=self.device)
-        dp = torch.empty(p.nt, dtype=torch.float64, device=self.device)
+        dp = torch.empty(p.nt * psi_per_step(p), dtype=torch.float64, device=self.device)
         _check(lib().lks_sensitivities(self.handle, _ptr(g), _ptr(self.workspace), _ptr(dg),
                                        _ptr(dc), _ptr(dp), _stream()))
-        return dg, dc.reshape(p.nt, 3), dp
+        return dg, dc.reshape(p.nt, 3), self._psi_view(dp)
 
     # ---------------------------------------------------- optimiser side
     def design_filter(self, gamma, radius: float, beta: float, eta: float):
@@ -271,7 +290,7 @@ class Plan:
         G = torch.empty(3, dtype=torch.float64, device=self.device)
         d1 = torch.empty(p.M, dtype=torch.float64, device=self.device)
         d2 = torch.empty(p.M, dtype=torch.float64, device=self.device)
-        d3 = torch.empty(p.nt, dtype=torch.float64, device=self.device)
+        d3 = torch.empty(p.nt * psi_per_step(p), dtype=torch.float64, device=self.device)
         _check(lib().lks_constraints(self.handle, _ptr(self.workspace), _ptr(g), _ptr(c), _ptr(s),
                                      C.c_double(vmax), C.c_double(omega_max), C.c_double(p_omega),
                                      _ptr(G), _ptr(d1), _ptr(d2), _ptr(d3), _stream()))
@@ -280,9 +299,10 @@ class Plan:
     # ---------------------------------------------------- single stages
     def motion(self, chi, psi):
         c, s = self._f64(chi), self._f64(psi)
-        out = torch.empty(self.problem.nt * 8, dtype=torch.float64, device=self.device)
+        W = motion_width(self.problem)
+        out = torch.empty(self.problem.nt * W, dtype=torch.float64, device=self.device)
         _check(lib().lks_motion(self.handle, _ptr(c), _ptr(s), _ptr(out), _stream()))
-        return out.reshape(self.problem.nt, 8)
+        return out.reshape(self.problem.nt, W)
 
     def kappa_ref(self, gamma):
         g = self._f64(gamma)
@@ -320,10 +340,11 @@ class Plan:
         kr, m, kb, ub = self._st(kref), self._f64(motion8), self._st(kbar), self._st(usbar)
         nblk = lib().lks_map_adjoint_blocks(self.handle)
         out = torch.empty(p.Mtot, dtype=torch.float64, device=self.device)
-        mb = torch.empty(8 * (nblk + 1), dtype=torch.float64, device=self.device)
+        W = motion_width(p)
+        mb = torch.empty(W * (nblk + 1), dtype=torch.float64, device=self.device)
         _check(lib().lks_map_adjoint(self.handle, _ptr(kr), _ptr(m), _ptr(kb), _ptr(ub), _ptr(out),
                                      _ptr(mb), _stream()))
-        return out, mb[:8].clone()
+        return out, mb[:W].clone()
 
 
 class LKSObjective(torch.autograd.Function):
@@ -369,11 +390,13 @@ class Batch:
         f64 = dict(dtype=torch.float64, device=dev)
         self.g = [torch.empty(pl.problem.M, **f64) for pl in self.plans]
         self.c = [torch.empty(pl.problem.nt * 3, **f64) for pl in self.plans]
-        self.s = [torch.empty(pl.problem.nt, **f64) for pl in self.plans]
+        self.s = [torch.empty(pl.problem.nt * psi_per_step(pl.problem), **f64)
+                   for pl in self.plans]
         self.J = [torch.empty(3, **f64) for _ in self.plans]
         self.dg = [torch.empty(pl.problem.M, **f64) for pl in self.plans]
         self.dc = [torch.empty(pl.problem.nt * 3, **f64) for pl in self.plans]
-        self.dp = [torch.empty(pl.problem.nt, **f64) for pl in self.plans]
+        self.dp = [torch.empty(pl.problem.nt * psi_per_step(pl.problem), **f64)
+                   for pl in self.plans]
         self.seed = torch.ones(n, **f64)
         tab = lambda ts: (_VP * n)(*[t.data_ptr() for t in ts])
         self._tabs = dict(plans=(_VP * n)(*[pl.handle.value for pl in self.plans]),
@@ -398,7 +421,7 @@ class Batch:
             pl.generation += 1
         return [(self.J[k], {"dgamma": self.dg[k],
                              "dchi": self.dc[k].reshape(pl.problem.nt, 3),
-                             "dpsi": self.dp[k]})
+                             "dpsi": pl._psi_view(self.dp[k])})
                 for k, pl in enumerate(self.plans)]
 
 
