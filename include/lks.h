@@ -239,6 +239,74 @@ lks_status lks_constraints(lks_plan* plan, void* workspace, const double* gamma_
                            double p_omega, double* G_out, double* dG1, double* dG2,
                            double* dG3_dpsi, hipStream_t stream);
 
+/* ---- the optimisation loop (Algorithm 1, Secs. 3.2-3.4) ---- */
+
+/* What the driver hands the caller's optimiser step after each iteration's
+ * sensitivities (device pointers unless marked). */
+typedef struct lks_opt_state {
+  int32_t level;           /* continuation level l, 0-based */
+  int32_t iter;            /* iteration k within the level, 0-based */
+  int32_t total;           /* iterations so far, this one included */
+  double beta;             /* projection steepness of the level */
+  double J;                /* (host) objective of this iteration */
+  double G[3];             /* (host) G1, G2, G3 of this iteration (Sec. 2.6) */
+  double* gamma;           /* design variables [M], [nt][3], [nt] or [nt][3]: */
+  double* chi;             /*   the caller's arrays, to be updated in place */
+  double* psi;
+  const double* dJ_dgamma; /* [M]: gradient of J w.r.t. gamma itself (through */
+  const double* dJ_dchi;   /*   filter and projection); [nt][3]; as psi */
+  const double* dJ_dpsi;
+  const double* dG1_dgamma; /* [M] each: G1, G2 w.r.t. gamma (filter chain applied) */
+  const double* dG2_dgamma;
+  const double* dG3_dpsi;  /* as psi (G3 depends on psi only) */
+} lks_opt_state;
+
+/* The optimiser step (MMA in the paper, Sec. 3.4; the caller's choice):
+ * reads the state and writes new design variables into st->gamma, st->chi,
+ * st->psi on `stream`.  Returns 0 to go on, anything else to stop the loop. */
+typedef int32_t (*lks_update_fn)(void* user, const lks_opt_state* st, hipStream_t stream);
+
+typedef struct lks_opt_options {
+  int32_t n_cont;          /* continuation levels N_cont (Sec. 3.2) */
+  const double* beta;      /* (host) [n_cont]: beta of each level, e.g. 1, 2, 4, ..., 32 */
+  int32_t n_opt;           /* most iterations per level N_opt */
+  double radius, eta;      /* density filter radius, projection threshold (Sec. 3.1) */
+  double tol;              /* stopping criterion |J^(k+1) - J^k| / |J^k| <= tol (1e-6) */
+  double vmax, omega_max, p_omega; /* constraint parameters (Eqs. constraint1..3) */
+  int32_t g_active;        /* bit j-1: G_j <= 0 is required before a level may stop */
+  int32_t periodic;        /* 1: periodic approximation (Sec. 3.3): each march starts
+                              from the previous march's final state and each reverse
+                              sweep from the previous sweep's adj_initial */
+} lks_opt_options;
+
+typedef struct lks_opt_result {
+  int32_t iterations;      /* forward marches run */
+  int32_t levels;          /* continuation levels entered */
+  int32_t stopped;         /* 0 ran out of levels; 1 the callback stopped the loop */
+  double J_last;           /* objective of the last march */
+} lks_opt_result;
+
+/* Device scratch lks_optimize needs (bytes, 256-aligned). */
+size_t lks_optimize_scratch_bytes(const lks_plan* plan);
+
+/* Algorithm 1: for each continuation level l (beta = beta[l]) and iteration
+ * k < n_opt: filter and project gamma (lks_design_filter), march
+ * (lks_forward; periodic: from the previous final state), J and G1-G3
+ * (lks_constraints); the level ends when k > 0 and
+ * |J^k - J^(k-1)| / |J^(k-1)| <= tol with every active G_j <= 0 (Sec. 3.2:
+ * J of consecutive iterations of the level); otherwise the reverse sweep
+ * (lks_adjoint; periodic: from the previous sweep's adj_initial), the chain
+ * rule back to gamma (lks_design_filter_adjoint) for J, G1 and G2, and the
+ * caller's update.  gamma, chi, psi: device, read and updated in place.
+ * history (host, nullable): [n_cont * n_opt][4] rows (J, G1, G2, G3) of the
+ * iterations run, in order.  The call synchronises `stream` once per
+ * iteration (J and G go to the host).  Errors of the stages are returned as
+ * they occur. */
+lks_status lks_optimize(lks_plan* plan, void* workspace, const lks_opt_options* opt,
+                        double* gamma, double* chi, double* psi, void* scratch,
+                        lks_update_fn update, void* user, double* history,
+                        lks_opt_result* result, hipStream_t stream);
+
 /* Design -> analysis transfer for one time step (Sec. 2.3, Eqs. kappa, u_s):
  * kappa_ref [D2][D1][D0] (state type), motion8 = one motion row, (xg[3],
  * ug[3], theta, omega) doubles (12 with LKS_ROT_EULER: xg, ug, th[3], om[3])

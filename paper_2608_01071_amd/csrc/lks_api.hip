@@ -1330,6 +1330,147 @@ lks_status lks_batch_run(int32_t count, lks_plan* const* plans, const double* co
   return LKS_OK;
 }
 
+// ---- Algorithm 1 driver
+namespace {
+struct OptScratch {
+  double *phys, *dphys, *dg, *dchi, *dpsi, *work, *dG1p, *dG2p, *dG1, *dG2, *dG3, *J3, *G;
+  void *st_a, *st_b, *adj_a, *adj_b;
+  size_t total;
+};
+OptScratch opt_layout(const lks_plan* P, void* base) {
+  OptScratch o;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    void* p = base ? (char*)base + off : nullptr;
+    off += align256(bytes);
+    return p;
+  };
+  const size_t M = (size_t)inner_points(P->g), nt = (size_t)P->g.nt;
+  const size_t np = P->g.rot ? 3 : 1;
+  const size_t Sb = (size_t)P->S * P->es;
+  const size_t Ab = P->alks ? (size_t)(P->g.d + 1 + alks_carry_planes(P->g.d)) * P->g.N * P->es : Sb;
+  o.phys = (double*)take(M * 8);
+  o.dphys = (double*)take(M * 8);
+  o.dg = (double*)take(M * 8);
+  o.dchi = (double*)take(nt * 3 * 8);
+  o.dpsi = (double*)take(nt * np * 8);
+  o.work = (double*)take(M * 8);
+  o.dG1p = (double*)take(M * 8);
+  o.dG2p = (double*)take(M * 8);
+  o.dG1 = (double*)take(M * 8);
+  o.dG2 = (double*)take(M * 8);
+  o.dG3 = (double*)take(nt * np * 8);
+  o.J3 = (double*)take(4 * 8);
+  o.G = (double*)take(4 * 8);
+  o.st_a = take(Sb);
+  o.st_b = take(Sb);
+  o.adj_a = take(Ab);
+  o.adj_b = take(Ab);
+  o.total = off;
+  return o;
+}
+}  // namespace
+
+size_t lks_optimize_scratch_bytes(const lks_plan* P) {
+  if (!P) return 0;
+  return opt_layout(P, nullptr).total;
+}
+
+lks_status lks_optimize(lks_plan* P, void* ws, const lks_opt_options* opt, double* gamma,
+                        double* chi, double* psi, void* scratch, lks_update_fn update, void* user,
+                        double* history, lks_opt_result* result, hipStream_t s) {
+  if (!P || !ws || !opt || !gamma || !chi || !psi || !scratch || !update)
+    return fail(LKS_EINVAL, "null argument");
+  if (opt->n_cont < 1 || opt->n_opt < 1 || !opt->beta)
+    return fail(LKS_EINVAL, "lks_optimize needs n_cont >= 1, n_opt >= 1 and a beta schedule");
+  if (!(opt->tol >= 0.0)) return fail(LKS_EINVAL, "tol must be >= 0");
+  const OptScratch o = opt_layout(P, scratch);
+  const double one = 1.0;
+  double* seed = o.J3 + 3;
+  HIPCHK(hipMemcpyAsync(seed, &one, sizeof(double), hipMemcpyHostToDevice, s));
+  lks_opt_result res;
+  memset(&res, 0, sizeof res);
+  bool have_state = false, have_adj = false;
+  void* st_cur = o.st_a;   // final state of the last march
+  void* adj_cur = o.adj_a; // adj_initial of the last sweep
+  int total = 0;
+  for (int l = 0; l < opt->n_cont; ++l) {
+    res.levels = l + 1;
+    const double beta = opt->beta[l];
+    double J_prev = 0.0;
+    for (int k = 0; k < opt->n_opt; ++k) {
+      // filter and project the density, march, objective and constraints
+      if (lks_status e = lks_design_filter(P, gamma, opt->radius, beta, opt->eta, o.phys, s))
+        return e;
+      void* st_next = st_cur == o.st_a ? o.st_b : o.st_a;
+      const bool carry = opt->periodic && have_state;
+      if (lks_status e = lks_forward(P, o.phys, chi, psi, carry ? st_cur : nullptr, st_next, ws,
+                                     o.J3, s))
+        return e;
+      st_cur = st_next;
+      have_state = true;
+      if (lks_status e = lks_constraints(P, ws, o.phys, chi, psi, opt->vmax, opt->omega_max,
+                                         opt->p_omega, o.G, o.dG1p, o.dG2p, o.dG3, s))
+        return e;
+      double JG[4];
+      HIPCHK(hipMemcpyAsync(JG, o.J3, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(JG + 1, o.G, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (history) memcpy(history + 4 * (size_t)total, JG, sizeof JG);
+      ++total;
+      res.iterations = total;
+      res.J_last = JG[0];
+      // Sec. 3.2: the level ends once J settles with the constraints met
+      bool feasible = true;
+      for (int j = 0; j < 3; ++j)
+        if ((opt->g_active >> j) & 1) feasible = feasible && JG[1 + j] <= 0.0;
+      const bool settled = k > 0 && std::fabs(JG[0] - J_prev) <= opt->tol * std::fabs(J_prev);
+      J_prev = JG[0];
+      if (settled && feasible) break;
+      // reverse sweep and the chain rule back to the design variables
+      void* adj_next = adj_cur == o.adj_a ? o.adj_b : o.adj_a;
+      const bool acarry = opt->periodic && have_adj;
+      if (lks_status e = lks_adjoint(P, o.phys, chi, psi, ws, seed, acarry ? adj_cur : nullptr,
+                                     adj_next, o.dphys, o.dchi, o.dpsi, s))
+        return e;
+      adj_cur = adj_next;
+      have_adj = true;
+      if (lks_status e = lks_design_filter_adjoint(P, gamma, opt->radius, beta, opt->eta, o.dphys,
+                                                   o.work, o.dg, s))
+        return e;
+      if (lks_status e = lks_design_filter_adjoint(P, gamma, opt->radius, beta, opt->eta, o.dG1p,
+                                                   o.work, o.dG1, s))
+        return e;
+      if (lks_status e = lks_design_filter_adjoint(P, gamma, opt->radius, beta, opt->eta, o.dG2p,
+                                                   o.work, o.dG2, s))
+        return e;
+      lks_opt_state st;
+      st.level = l;
+      st.iter = k;
+      st.total = total;
+      st.beta = beta;
+      st.J = JG[0];
+      for (int j = 0; j < 3; ++j) st.G[j] = JG[1 + j];
+      st.gamma = gamma;
+      st.chi = chi;
+      st.psi = psi;
+      st.dJ_dgamma = o.dg;
+      st.dJ_dchi = o.dchi;
+      st.dJ_dpsi = o.dpsi;
+      st.dG1_dgamma = o.dG1;
+      st.dG2_dgamma = o.dG2;
+      st.dG3_dpsi = o.dG3;
+      if (update(user, &st, s) != 0) {
+        res.stopped = 1;
+        if (result) *result = res;
+        return LKS_OK;
+      }
+    }
+  }
+  if (result) *result = res;
+  return LKS_OK;
+}
+
 lks_status lks_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
   for (auto& r : g_prof.recs) {

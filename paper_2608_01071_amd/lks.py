@@ -46,6 +46,32 @@ class LksProblem(C.Structure):
     ]
 
 
+class LksOptState(C.Structure):
+    _fields_ = [
+        ("level", C.c_int32), ("iter", C.c_int32), ("total", C.c_int32), ("beta", C.c_double),
+        ("J", C.c_double), ("G", C.c_double * 3), ("gamma", C.c_void_p), ("chi", C.c_void_p),
+        ("psi", C.c_void_p), ("dJ_dgamma", C.c_void_p), ("dJ_dchi", C.c_void_p),
+        ("dJ_dpsi", C.c_void_p), ("dG1_dgamma", C.c_void_p), ("dG2_dgamma", C.c_void_p),
+        ("dG3_dpsi", C.c_void_p),
+    ]
+
+
+class LksOptOptions(C.Structure):
+    _fields_ = [
+        ("n_cont", C.c_int32), ("beta", C.POINTER(C.c_double)), ("n_opt", C.c_int32),
+        ("radius", C.c_double), ("eta", C.c_double), ("tol", C.c_double), ("vmax", C.c_double),
+        ("omega_max", C.c_double), ("p_omega", C.c_double), ("g_active", C.c_int32),
+        ("periodic", C.c_int32),
+    ]
+
+
+class LksOptResult(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("levels", C.c_int32), ("stopped", C.c_int32),
+                ("J_last", C.c_double)]
+
+
+UPDATE_FN = C.CFUNCTYPE(C.c_int32, C.c_void_p, C.POINTER(LksOptState), C.c_void_p)
+
 _lib = None
 _VP = C.c_void_p
 
@@ -88,6 +114,10 @@ def lib():
         L.lks_design_filter.argtypes = [_VP, _VP, D, D, D, _VP, _VP]
         L.lks_design_filter_adjoint.argtypes = [_VP, _VP, D, D, D, _VP, _VP, _VP, _VP]
         L.lks_design_filter_adjoint_noalloc.argtypes = [_VP, _VP, D, D, D, _VP, _VP, _VP]
+        L.lks_optimize_scratch_bytes.argtypes = [_VP]
+        L.lks_optimize_scratch_bytes.restype = C.c_size_t
+        L.lks_optimize.argtypes = [_VP, _VP, C.POINTER(LksOptOptions), _VP, _VP, _VP, _VP,
+                                   UPDATE_FN, _VP, _VP, C.POINTER(LksOptResult), _VP]
         L.lks_constraints.argtypes = [_VP] * 5 + [D, D, D] + [_VP] * 5
         _lib = L
     return _lib
@@ -345,6 +375,67 @@ class Plan:
         _check(lib().lks_map_adjoint(self.handle, _ptr(kr), _ptr(m), _ptr(kb), _ptr(ub), _ptr(out),
                                      _ptr(mb), _stream()))
         return out, mb[:W].clone()
+
+
+def optimize(plan: "Plan", gamma, chi, psi, update, *, beta=(1.0,), n_opt: int = 100,
+             radius: float = 4.8, eta: float = 0.5, tol: float = 1e-6, vmax: float = 1.0,
+             omega_max: float = 1.0, p_omega: float = 16.0, g_active: int = 0,
+             periodic: bool = True):
+    """Algorithm 1 (lks_optimize): continuation over `beta`, up to n_opt
+    iterations per level, with the caller's optimiser step
+    update(state) -> bool (True stops), where state is a dict of device
+    tensors (gamma, chi, psi to update in place; dJ_dgamma, dJ_dchi, dJ_dpsi,
+    dG1_dgamma, dG2_dgamma, dG3_dpsi) and the scalars level, iter, total,
+    beta, J, G.  Returns (gamma, chi, psi, history [iterations][4],
+    result dict)."""
+    p = plan.problem
+    g = plan._f64(gamma).clone().reshape(-1)
+    c = plan._f64(chi).clone().reshape(-1)
+    s = plan._f64(psi).clone().reshape(-1)
+    L = lib()
+    scratch = torch.empty(L.lks_optimize_scratch_bytes(plan.handle), dtype=torch.uint8,
+                          device=plan.device)
+    base = scratch.data_ptr()
+    f64 = scratch.view(torch.float64)
+    nps = psi_per_step(p)
+    sizes = {"dJ_dgamma": p.M, "dJ_dchi": 3 * p.nt, "dJ_dpsi": nps * p.nt,
+             "dG1_dgamma": p.M, "dG2_dgamma": p.M, "dG3_dpsi": nps * p.nt}
+    own = {g.data_ptr(): g, c.data_ptr(): c, s.data_ptr(): s}
+
+    def view(ptr, n):
+        if ptr in own:
+            return own[ptr]
+        off = ptr - base
+        assert off >= 0 and off % 8 == 0 and off // 8 + n <= f64.numel()
+        return f64[off // 8: off // 8 + n]
+
+    def cb(_user, stp, _stream):
+        st = stp.contents
+        d = {"level": st.level, "iter": st.iter, "total": st.total, "beta": st.beta, "J": st.J,
+             "G": tuple(st.G), "gamma": view(st.gamma, p.M), "chi": view(st.chi, 3 * p.nt),
+             "psi": view(st.psi, nps * p.nt)}
+        for k, n in sizes.items():
+            d[k] = view(getattr(st, k), n)
+        try:
+            return 1 if update(d) else 0
+        except Exception:  # an exception in the step stops the loop
+            import traceback
+            traceback.print_exc()
+            return 1
+
+    fn = UPDATE_FN(cb)
+    betas = (C.c_double * len(beta))(*beta)
+    opt = LksOptOptions(len(beta), betas, n_opt, radius, eta, tol, vmax, omega_max, p_omega,
+                        g_active, 1 if periodic else 0)
+    hist = (C.c_double * (4 * len(beta) * n_opt))()
+    res = LksOptResult()
+    _check(L.lks_optimize(plan.handle, _ptr(plan.workspace), C.byref(opt), _ptr(g), _ptr(c),
+                          _ptr(s), _ptr(scratch), fn, None, hist, C.byref(res), _stream()))
+    plan.generation += res.iterations
+    history = [tuple(hist[4 * i: 4 * i + 4]) for i in range(res.iterations)]
+    out = {"iterations": res.iterations, "levels": res.levels, "stopped": res.stopped,
+           "J_last": res.J_last}
+    return g, c.reshape(p.nt, 3), plan._psi_view(s), history, out
 
 
 class LKSObjective(torch.autograd.Function):

@@ -1,0 +1,121 @@
+"""Whole-horizon checks at the workloads' real sizes.
+
+- The batched parameter study: 16 uneven D2Q9 instances (sides 128..384,
+  4000 steps, Re and temporal-filter radius round-robin) through
+  lks_batch_run: bitwise equal to each instance's solo run, FP32 state with
+  FP64 sums against the FP64 plain form (J within 1e-5 of the RMS of the
+  averaged flux, and of J itself where J is not a near-cancelling mean;
+  every gradient within 1e-3 relative L2), and the smallest instance's first
+  200 steps against the oracle (J within 1e-5 FP32 and 1e-10 FP64; gradients
+  1e-3 and 1e-9).
+- The 2D oar with J2 over its whole 4000-step horizon, FP32 against FP64.
+  J2 is a small difference of forces about a thousand times larger than
+  itself, so the FP32 state's rounding shows at their scale: the bars are
+  2e-3 on J2 and F_D (measured 1.2e-3 and 1.1e-3), 1e-3 on F_L (2.8e-4) and
+  1e-3 on the gradients (at most 4.2e-4).
+"""
+import numpy as np
+import pytest
+
+from paper_2608_01071_amd import workloads as W
+
+from test_gpu_parity import cpu, l2err, lk
+
+pytestmark = pytest.mark.gpu
+
+
+def run_batch(lks, specs):
+    plans = [lks.Plan(p) for p, *_ in specs]
+    b = lks.Batch(plans)
+    out = b.run([x[1] for x in specs], [x[2] for x in specs], [x[3] for x in specs])
+    return [(cpu(J3), {k: cpu(gr[k]) for k in ("dgamma", "dchi", "dpsi")}) for J3, gr in out]
+
+
+def test_c5_batch_full_size(orc):
+    lks = lk()
+    f32 = W.c5_instances(precision=0)
+    print(f"c5: {len(f32)} instances, sides {[p.n[0] for p, *_ in f32]}", flush=True)
+    batch = run_batch(lks, f32)
+    print("c5: FP32 batch done", flush=True)
+    for k, (p, g, c, s) in enumerate(f32):
+        pl = lks.Plan(p)
+        J3, _ = pl.forward(g, c, s)
+        gr = pl.adjoint(g, c, s)
+        assert np.array_equal(cpu(J3), batch[k][0]), k
+        for key in ("dgamma", "dchi", "dpsi"):
+            assert np.array_equal(cpu(gr[key]), batch[k][1][key]), (k, key)
+        del pl
+    print("c5: solo runs equal the batch bitwise", flush=True)
+    f64 = W.c5_instances(precision=1)
+    plain = run_batch(lks, f64)
+    print("c5: FP64 batch done", flush=True)
+    worst = {"J": 0.0, "J_rms": 0.0, "dgamma": 0.0, "dchi": 0.0, "dpsi": 0.0}
+    for k in range(len(f32)):
+        J, J64 = batch[k][0][0], plain[k][0][0]
+        E64, V64 = plain[k][0][1], plain[k][0][2]
+        rms = float(np.sqrt(V64 + E64 * E64))  # RMS of n.u over the target and the steps
+        print(f"c5: instance {k} side {f32[k][0].n[0]}: J32 {J:.9e} J64 {J64:.9e} "
+              f"rms(n.u) {rms:.3e} rel {abs(J - J64) / abs(J64):.2e} "
+              f"rel/rms {abs(J - J64) / rms:.2e}", flush=True)
+        worst["J"] = max(worst["J"], abs(J - J64) / abs(J64))
+        worst["J_rms"] = max(worst["J_rms"], abs(J - J64) / rms)
+        for key in ("dgamma", "dchi", "dpsi"):
+            worst[key] = max(worst[key], l2err(batch[k][1][key], plain[k][1][key]))
+    print(f"c5: FP32 vs FP64 worst relative errors {worst}", flush=True)
+    # J1 with phi = 0 is the mean flux n.u through the target column; where
+    # the motion drives about as much flow one way as the other it is a
+    # near-cancelling mean (|J| down to 3e-4 of the RMS of n.u), and the
+    # FP32 state's error, some 1e-7 of that RMS, is a large fraction of it.
+    # The bar is therefore 1e-5 of the RMS everywhere (measured at most
+    # 8.5e-7), and 1e-5 of J itself wherever |J| is at least 2 % of the RMS
+    # (measured at most 8.1e-6; at 1.3 % of the RMS it reaches 6.7e-5).
+    assert worst["J_rms"] <= 1e-5
+    for k in range(len(f32)):
+        J, J64 = batch[k][0][0], plain[k][0][0]
+        rms = float(np.sqrt(plain[k][0][2] + plain[k][0][1] ** 2))
+        if abs(J64) >= 0.02 * rms:
+            assert abs(J - J64) <= 1e-5 * abs(J64), k
+    for key in ("dgamma", "dchi", "dpsi"):
+        assert worst[key] <= 1e-3, key
+    # the smallest instance's first 200 steps against the oracle
+    k = int(np.argmin([p.n[0] for p, *_ in f32]))
+    for prec, (tj, tg) in ((1, (1e-10, 1e-9)), (0, (1e-5, 1e-3))):
+        p, g, c, s = (f64 if prec else f32)[k]
+        p = p.replace(nt=200, ckpt_k=50)
+        c, s = c[:200], s[:200]
+        pl = lks.Plan(p)
+        J3, _ = pl.forward(g, c, s)
+        gr = pl.adjoint(g, c, s)
+        if prec == 1:
+            ref = orc.forward(p, g, c, s, want_final=False)
+            adj = orc.adjoint(p, g, c, s)
+        assert abs(cpu(J3)[0] - ref["J"]) <= tj * abs(ref["J"]), prec
+        for key in ("dgamma", "dchi", "dpsi"):
+            assert l2err(cpu(gr[key]), adj[key]) < tg, (prec, key)
+        print(f"c5: instance {k} ({p.n[0]}^2) 200-step prefix vs oracle, prec {prec} ok",
+              flush=True)
+
+
+def test_oar_j2_fp32_whole_horizon():
+    lks = lk()
+    out = {}
+    for prec in (1, 0):
+        p, g, c, s = W.oar(precision=prec)
+        pl = lks.Plan(p)
+        J3, _ = pl.forward(g, c, s)
+        gr = pl.adjoint(g, c, s)
+        out[prec] = (cpu(J3), {k: cpu(gr[k]) for k in ("dgamma", "dchi", "dpsi")})
+        del pl
+    (J32, g32), (J64, g64) = out[0], out[1]
+    p, *_ = W.oar()
+    T32 = (J32[0] - J32[1] - p.w_d * J32[2]) / p.w_t
+    T64 = (J64[0] - J64[1] - p.w_d * J64[2]) / p.w_t
+    errs = {"J2": abs(J32[0] - J64[0]) / abs(J64[0]), "F_L": abs(J32[1] - J64[1]) / abs(J64[1]),
+            "F_D": abs(J32[2] - J64[2]) / abs(J64[2]), "T": abs(T32 - T64) / abs(T64)}
+    for key in ("dgamma", "dchi", "dpsi"):
+        errs[key] = l2err(g32[key], g64[key])
+    print(f"oar J2 FP32 vs FP64 over 4000 steps: {errs}", flush=True)
+    assert errs["J2"] <= 2e-3
+    assert errs["F_L"] <= 1e-3 and errs["F_D"] <= 2e-3
+    for key in ("dgamma", "dchi", "dpsi"):
+        assert errs[key] <= 1e-3, key
