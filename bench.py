@@ -228,6 +228,114 @@ def run_pass(plan, g, c, s, seed):
     return J3, grads, t1 - t0, t2 - t1
 
 
+def pass_rate(p, g, c, s, seed, reps: int = 1):
+    """Forward and forward + adjoint MLUPS of a plan for problem p (graph
+    capture on a first untimed pass)."""
+    import torch
+    from paper_2608_01071_amd import lks
+    plan = lks.Plan(p)
+    out = {"workspace_gib": round(plan.workspace_bytes / 2**30, 2)}
+    run_pass(plan, g, c, s, seed)
+    tf = ta = 0.0
+    for _ in range(reps):
+        J3, grads, a, b = run_pass(plan, g, c, s, seed)
+        tf += a
+        ta += b
+    tf /= reps
+    ta /= reps
+    out.update({"forward_mlups": round(p.N * p.nt / tf / 1e6, 1),
+                "mlups": round(p.N * p.nt / (tf + ta) / 1e6, 1),
+                "ms_per_pass": round((tf + ta) * 1e3, 2)})
+    res = (J3.cpu().numpy().copy(), {k: v.cpu().numpy().copy() for k, v in grads.items()
+                                     if v is not None})
+    del plan
+    torch.cuda.empty_cache()
+    return out, res
+
+
+def d2q9_workload(name: str):
+    """The D2Q9 workloads at full size: 512^2 x 20000 steps (K = 200) and
+    1024^2 x 10000 steps (K = 100), FP32 state with FP64 sums: forward and
+    forward + adjoint rates, the dominant kernel's roofline from one
+    event-timed pass, and the FP32 errors against the FP64 plain form."""
+    import numpy as np
+    import torch
+    from paper_2608_01071_amd import lks, workloads as W
+    p, gamma, chi, psi = (W.c2 if name == "c2" else W.c3)(precision=0)
+    dev = torch.device("cuda")
+    g = torch.tensor(gamma, dtype=torch.float64, device=dev)
+    c = torch.tensor(chi, dtype=torch.float64, device=dev)
+    s = torch.tensor(psi, dtype=torch.float64, device=dev)
+    seed = torch.ones(1, dtype=torch.float64, device=dev)
+    out, (J32, g32) = pass_rate(p, g, c, s, seed)
+    out["workload"] = (f"D2Q9 {p.n[0]}^2, {p.m[0]}^2 design, {p.nt} steps, K = {p.ckpt_k}, "
+                       "FP32 state / FP64 sums")
+    # dominant kernel of one event-timed pass
+    plan = lks.Plan(p)
+    run_pass(plan, g, c, s, seed)
+    lks.profile_enable(True)
+    run_pass(plan, g, c, s, seed)
+    torch.cuda.synchronize()
+    prof = lks.profile_read()
+    lks.profile_enable(False)
+    del plan
+    torch.cuda.empty_cache()
+    dom = max(("fwd_step", "adj_step"), key=lambda k: prof.get(k, (0, 0))[0])
+    tot_ms, cnt = prof[dom]
+    avg_s = tot_ms / 1e3 / cnt
+    bpn = algorithmic_bytes_per_node(dom, 2, 4)
+    achieved = p.N * bpn / avg_s / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": dom, "avg_launch_us": round(avg_s * 1e6, 2),
+                       "achieved": round(achieved, 1), "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    pass_bytes = 84 * p.N * p.nt  # 84 B per node-step, forward + checkpointed adjoint
+    out["pass_roofline"] = {"bytes_per_node_step": 84,
+                            "achieved": round(pass_bytes / (out["ms_per_pass"] / 1e3) / 1e9, 1),
+                            "frac": round(pass_bytes / (out["ms_per_pass"] / 1e3) / 1e9
+                                          / HBM_PEAK_GBS, 4)}
+    o64, (J64, g64) = pass_rate(p.replace(precision=1), g, c, s, seed)
+    rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    rms = float(np.sqrt(J64[2] + J64[1] ** 2))
+    out["fp64_plain"] = {"mlups": o64["mlups"], "forward_mlups": o64["forward_mlups"],
+                         "speedup_fp32": round(o64["ms_per_pass"] / out["ms_per_pass"], 3)}
+    out["fp32_err"] = {"J": float(abs(J32[0] - J64[0]) / abs(J64[0])),
+                       "J_rel_rms_flux": float(abs(J32[0] - J64[0]) / rms),
+                       **{k: rel(g32[k], g64[k]) for k in ("dgamma", "dchi", "dpsi")}}
+    return out
+
+
+def cpu_sample_worker(nt_sample: int, q):
+    from oracle import oracle as O
+    from paper_2608_01071_amd import workloads as W
+    p, gamma, chi, psi = W.c4(nt=nt_sample)
+    O.lib()
+    t0 = time.perf_counter()
+    O.adjoint(p, gamma, chi, psi)
+    q.put(time.perf_counter() - t0)
+
+
+def cpu_all_cores(nt_sample: int, procs: int):
+    """The oracle as it stands, one copy per host core (up to `procs`), each
+    on the same bounded sample: the host's aggregate oracle throughput."""
+    import multiprocessing as mp
+    from paper_2608_01071_amd import workloads as W
+    p, *_ = W.c4(nt=nt_sample)
+    ctx = mp.get_context("spawn")
+    q = ctx.Queue()
+    ps = [ctx.Process(target=cpu_sample_worker, args=(nt_sample, q)) for _ in range(procs)]
+    t0 = time.perf_counter()
+    for pr in ps:
+        pr.start()
+    times = [q.get() for _ in ps]
+    for pr in ps:
+        pr.join()
+    wall = time.perf_counter() - t0
+    return {"value": round(procs * p.N * nt_sample / max(times) / 1e6, 3), "unit": "MLUPS",
+            "cores": procs, "kind": "oracle",
+            "sample": f"{procs} concurrent copies of the single-thread sample "
+                      f"(slowest {max(times):.1f} s, wall {wall:.1f} s)"}
+
+
 def cpu_baseline(nt_sample: int):
     import numpy as np
     from oracle import oracle as O
@@ -268,6 +376,13 @@ def main():
                     help="skip timing the design prelude and constraints")
     ap.add_argument("--no-big", action="store_true",
                     help="skip the 256^3 forward-step point (state larger than the LLC)")
+    ap.add_argument("--no-store-all", action="store_true",
+                    help="skip the one-segment run that keeps every state in HBM")
+    ap.add_argument("--no-seg-tape", action="store_true",
+                    help="skip the run with the per-segment body tape")
+    ap.add_argument("--no-d2q9", action="store_true", help="skip the 512^2 and 1024^2 D2Q9 runs")
+    ap.add_argument("--cpu-procs", type=int, default=min(os.cpu_count() or 1, 16),
+                    help="concurrent oracle copies for the all-cores baseline (1: none)")
     ap.add_argument("--counters", action="store_true",
                     help="run only the short drive used for hardware-counter passes")
     args = ap.parse_args()
@@ -284,12 +399,25 @@ def main():
         counters_drive()
         return
     p, gamma, chi, psi = W.c4(precision=0, nt=args.nt)
-    plan = lks.Plan(p)
     dev = torch.device("cuda")
     g = torch.tensor(gamma, dtype=torch.float64, device=dev).contiguous()
     c = torch.tensor(chi, dtype=torch.float64, device=dev).contiguous()
     s = torch.tensor(psi, dtype=torch.float64, device=dev).contiguous()
     seed = torch.ones(1, dtype=torch.float64, device=dev)
+    # one segment (K = nt), run first while the device is empty: the march
+    # keeps every state and body field in HBM (about 230 GB at this size) and
+    # the reverse sweep recomputes nothing
+    store_all = None
+    if not args.no_store_all:
+        try:
+            o, _ = pass_rate(p.replace(ckpt_k=0), g, c, s, seed)
+            store_all = dict(o, bytes_per_node_step=78,
+                             note="K = nt: states and body fields of every step kept")
+        except Exception as e:  # the device may not hold it
+            store_all = {"skipped": str(e)[:200]}
+        torch.cuda.empty_cache()
+        print(f"[bench] one-segment run: {store_all}", file=sys.stderr, flush=True)
+    plan = lks.Plan(p)
     print(f"[bench] workload D3Q15 {p.n} design {p.m} nt={p.nt} K={p.ckpt_k} "
           f"workspace {plan.workspace_bytes / 2**30:.2f} GiB", file=sys.stderr, flush=True)
 
@@ -374,10 +502,22 @@ def main():
 
     del plan
     torch.cuda.empty_cache()
+    seg_tape = None
+    if not args.no_seg_tape:
+        o, _ = pass_rate(p.replace(body_tape=-1), g, c, s, seed)
+        seg_tape = dict(o, note="body fields of one segment kept; the recompute maps again")
     big = None if args.no_big else fwd_step_out_of_cache()
     c5 = None if args.no_c5 else c5_batch()
     oar = None if args.no_oar else oar_j2()
+    d2 = {} if args.no_d2q9 else {k: d2q9_workload(k) for k in ("c2", "c3")}
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_steps)
+    cpu_all = None if (args.no_cpu or args.cpu_procs <= 1) else cpu_all_cores(args.cpu_steps,
+                                                                              args.cpu_procs)
+    pass_bytes = 110 * N * nt  # 110 B per node-step, forward + checkpointed adjoint
+    pass_roofline = {"bytes_per_node_step": 110,
+                     "achieved": round(pass_bytes / (ms_per_step / 1e3) / 1e9, 1),
+                     "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                     "frac": round(pass_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     line = {
         "metric": METRIC, "value": round(value, 2), "unit": "MLUPS", "n_gpus": 1,
@@ -390,7 +530,13 @@ def main():
         "forward_mlups": round(fwd_mlups, 2),
         "J": float(J32[0]),
         "roofline": roofline,
+        "pass_roofline": pass_roofline,
         "cpu_baseline": cpu,
+        "cpu_baseline_all_cores": cpu_all,
+        "store_all": store_all,
+        "segment_body_tape": seg_tape,
+        "d2q9_512": d2.get("c2"),
+        "d2q9_1024": d2.get("c3"),
         "fp64_plain": fp64,
         "alks": alks,
         "design_side": design,

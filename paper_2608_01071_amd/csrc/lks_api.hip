@@ -144,7 +144,10 @@ struct lks_plan {
   size_t es;
   long long S;  // state elements
   int K, nck;
+  int kmt;      // reverse steps whose map transposes share one launch (min(K, 256))
   bool full_btape;  // body fields of every step kept (else of one segment)
+  bool store_all;   // K = nt: the march writes every state into the tape and
+                    // the reverse sweep recomputes nothing
   bool alks;        // reverse sweep by the paper's ALKS instead of the exact adjoint
   bool j2;          // objective J2 (Eq. objective2) instead of J1
   int nblk_step, nblk_map;
@@ -318,6 +321,13 @@ void* rev_body(lks_plan* P, void* ws, int n, int sg) {
 void* fwd_body(lks_plan* P, void* ws, int n) {
   return P->full_btape ? btape_slot(P, ws, n - 1) : wsp(ws, P->o_body);
 }
+// State the forward march writes at step n: with one segment (K = nt) the
+// tape slot the reverse sweep reads, else a checkpoint every K steps and a
+// ping-pong pair in between.
+void* fwd_out(lks_plan* P, void* ws, int n) {
+  if (P->store_all) return tape_slot(P, ws, n - 1);
+  return (n % P->K == 0 && n / P->K < P->nck) ? ck_slot(P, ws, n / P->K) : pp_slot(P, ws, n & 1);
+}
 
 // Body fields (kappa, u_s) of step n into `body` (layout [1+d][bmax.vol]).
 lks_status map_step(lks_plan* P, void* ws, int n, void* body, hipStream_t s) {
@@ -412,8 +422,7 @@ lks_status forward_loop(lks_plan* P, void* ws, hipStream_t s) {
     const int nt = P->g.nt;
     double* jacc = (double*)wsp(ws, P->o_j2acc);
     for (int n = 1; n <= nt; ++n) {
-      void* out = (n % P->K == 0 && n / P->K < P->nck) ? ck_slot(P, ws, n / P->K)
-                                                        : pp_slot(P, ws, n & 1);
+      void* out = fwd_out(P, ws, n);
       const FwdArgs a = fwd_args(P, ws, n, in, out, fwd_body(P, ws, n),
                                  n == 1 ? P->first_lazy : 1, !P->j2);
       char* nb = n < nt ? (char*)fwd_body(P, ws, n + 1) : nullptr;
@@ -438,8 +447,7 @@ lks_status forward_loop(lks_plan* P, void* ws, hipStream_t s) {
     return LKS_OK;
   }
   for (int n = 1; n <= P->g.nt; ++n) {
-    void* out = (n % P->K == 0 && n / P->K < P->nck) ? ck_slot(P, ws, n / P->K)
-                                                      : pp_slot(P, ws, n & 1);
+    void* out = fwd_out(P, ws, n);
     void* body = fwd_body(P, ws, n);
     if (P->j2 && n > 1) {
       // J2: the step sums of state n - 1 ride along with this step's map
@@ -467,11 +475,7 @@ lks_status forward_loop(lks_plan* P, void* ws, hipStream_t s) {
   return LKS_OK;
 }
 
-const void* final_state(lks_plan* P, void* ws) {
-  const int n = P->g.nt;
-  if (n % P->K == 0 && n / P->K < P->nck) return ck_slot(P, ws, n / P->K);
-  return pp_slot(P, ws, n & 1);
-}
+const void* final_state(lks_plan* P, void* ws) { return fwd_out(P, ws, P->g.nt); }
 
 // Reverse sweep with segment recomputation: launches only.  The recompute
 // keeps each step's body fields, which the reverse steps then reuse (with the
@@ -526,8 +530,9 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
   int cur = 0;
   for (int sg = P->nck - 1; sg >= 0; --sg) {
     const int nb = sg * K + 1, ne = std::min((sg + 1) * K, nt);
-    // recompute the segment into the tape: tape[n - nb] holds state n
-    for (int n = nb; n <= ne; ++n) {
+    // recompute the segment into the tape: tape[n - nb] holds state n (with
+    // one segment the forward march has written it already)
+    for (int n = nb; n <= ne && !P->store_all; ++n) {
       const void* in = (n == nb) ? ck_slot(P, ws, sg) : tape_slot(P, ws, n - nb - 1);
       const int lazy = (n == 1) ? P->first_lazy : 1;
       void* body = rev_body(P, ws, n, sg);
@@ -545,10 +550,15 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
                             (const double*)wsp(ws, P->o_seed), wsp(ws, P->o_j2seed), ne - nb + 1,
                             s));
     }
-    // reverse steps, each keeping its body adjoint in a slot of its own
-    for (int n = ne; n >= nb; --n) {
+    // reverse steps in chunks of at most kmt, each step keeping its body
+    // adjoint in a slot of its own; then the chunk's map transposes in one
+    // launch (one step alone fills the GPU poorly) and its kappa_ref
+    // partials summed, latest step first, as a transpose per step would
+    for (int chi = ne; chi >= nb; chi -= P->kmt) {
+     const int clo = std::max(nb, chi - P->kmt + 1);
+     for (int n = chi; n >= clo; --n) {
       AdjArgs a = adj_args(P, ws, n, sg, cur);
-      a.bkbar = badj_slot(P, ws, n - nb);
+      a.bkbar = badj_slot(P, ws, n - clo);
       a.bubar = (char*)a.bkbar + P->bmax.vol * P->es;
       if (P->j2) {
         // J2 seeds the fluid velocity on the body box instead of the target box
@@ -560,12 +570,10 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
         HIPCHK(launch_adjoint_step(P->g, P->prec, a, s));
       }
       cur = 1 - cur;
-    }
-    // the segment's map transposes in one launch (one step alone fills the
-    // GPU poorly), then its kappa_ref partials summed in a fixed order
-    {
-      const int cnt = ne - nb + 1;
-      const MapAdjArgs m = mapadj_args(P, ws, nb);
+     }
+     {
+      const int cnt = chi - clo + 1;
+      const MapAdjArgs m = mapadj_args(P, ws, clo);
       double* kp = (double*)wsp(ws, P->o_kpart);
       void* b0 = badj_slot(P, ws, 0);
       const StepBatch sb{(long long)(body_bytes(P) / P->es), P->g.Mtot,
@@ -578,11 +586,12 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
       // J2's direct terms join the same rows, in their own block slots
       if (P->j2) {
         Scope sc("j2_adj", s, true);
-        HIPCHK(launch_j2_adjoint(P->g, P->prec, m.kref, m.si, tape_slot(P, ws, 0), P->S,
+        HIPCHK(launch_j2_adjoint(P->g, P->prec, m.kref, m.si, tape_slot(P, ws, clo - nb), P->S,
                                  (const double*)wsp(ws, P->o_seed), kp, P->g.Mtot, m.mpart,
                                  (long long)P->mrow * P->g.mw, P->nblk_map, cnt, s));
       }
       HIPCHK(launch_kref_accum(P->g.Mtot, cnt, kp, (double*)wsp(ws, P->o_krefbar), s));
+     }
     }
   }
   return LKS_OK;
@@ -676,6 +685,7 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   P->S = (long long)(g.d + 1) * g.N;
   P->K = prob->ckpt_k == 0 ? g.nt : prob->ckpt_k;
   P->nck = (g.nt + P->K - 1) / P->K;
+  P->kmt = std::min(P->K, 256);
   P->nblk_step = step_blocks(g);
   if (g.d == 3) {
     Geo g4 = g;
@@ -723,14 +733,19 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   P->o_pp = take(2 * Sb);
   P->o_tape = take((size_t)P->K * Sb);
   const size_t full_tape = (size_t)g.nt * body_bytes(P);
-  P->full_btape = prob->body_tape == 1 || (prob->body_tape == 0 && full_tape <= LKS_BODY_TAPE_AUTO_MAX);
+  // one segment (K = nt): the march keeps every state in the tape, and the
+  // segment's body tape is the full one
+  P->store_all = P->K == g.nt;
+  P->full_btape = P->store_all || prob->body_tape == 1 ||
+                  (prob->body_tape == 0 && full_tape <= LKS_BODY_TAPE_AUTO_MAX);
   P->o_body = take(P->full_btape ? 0 : body_bytes(P));
   P->o_btape = take(P->full_btape ? full_tape : (size_t)P->K * body_bytes(P));
   P->o_badj = take(body_bytes(P));
-  // the reverse sweep keeps each segment step's body adjoint and transposes
-  // the segment's maps in one launch, each step's kappa_ref partials apart
-  P->o_badjt = take((size_t)P->K * body_bytes(P));
-  P->o_kpart = take((size_t)P->K * g.Mtot * sizeof(double));
+  // the reverse sweep keeps the body adjoint of each step of a chunk (at most
+  // kmt steps) and transposes the chunk's maps in one launch, each step's
+  // kappa_ref partials apart
+  P->o_badjt = take((size_t)P->kmt * body_bytes(P));
+  P->o_kpart = take((size_t)P->kmt * g.Mtot * sizeof(double));
   P->o_lam = take(2 * Sb);
   P->alks = prob->scheme == LKS_ADJ_ALKS;
   // ALKS: raw first-moment part of the adjoint velocity, two slots like lambda
@@ -1048,6 +1063,7 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
                          const double* const* gamma, double* const* J_out, double* const* dg,
                          double* const* dchi, double* const* dpsi, hipStream_t s) {
   const int prec = plans[0]->prec, nt = plans[0]->g.nt, K = plans[0]->K;
+  const int kmt = plans[0]->kmt;
   const int nck = plans[0]->nck;
   auto round8 = [](int v) { return (v + 7) / 8 * 8; };
   Batch<FwdArgs> fb;
@@ -1100,7 +1116,7 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
     if (lks_status e = map_all(n, -1)) return e;
     for (int k = 0; k < count; ++k) {
       lks_plan* P = plans[k];
-      void* out = (n % K == 0 && n / K < nck) ? ck_slot(P, ws[k], n / K) : pp_slot(P, ws[k], n & 1);
+      void* out = fwd_out(P, ws[k], n);
       fb.a[k] = fwd_args(P, ws[k], n, in[k], out, fwd_body(P, ws[k], n),
                          n == 1 ? P->first_lazy : 1, 1);
       in[k] = out;
@@ -1121,7 +1137,7 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
   int cur = 0;
   for (int sg = nck - 1; sg >= 0; --sg) {
     const int nb = sg * K + 1, ne = std::min((sg + 1) * K, nt);
-    for (int n = nb; n <= ne; ++n) {
+    for (int n = nb; n <= ne && !plans[0]->store_all; ++n) {
       if (!full)
         if (lks_status e = map_all(n, sg)) return e;
       for (int k = 0; k < count; ++k) {
@@ -1139,10 +1155,11 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
     // then the segment's map transposes of every instance in one launch, as
     // in the single-instance sweep (adjoint_loop)
     for (int n = ne; n >= nb; --n) {
+      const int clo = std::max(nb, n - (n - nb) % kmt);  // first step of n's chunk
       for (int k = 0; k < count; ++k) {
         lks_plan* P = plans[k];
         ab.a[k] = adj_args(P, ws[k], n, sg, cur);
-        ab.a[k].bkbar = badj_slot(P, ws[k], n - nb);
+        ab.a[k].bkbar = badj_slot(P, ws[k], n - clo);
         ab.a[k].bubar = (char*)ab.a[k].bkbar + P->bmax.vol * P->es;
       }
       {
@@ -1150,12 +1167,12 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
         HIPCHK(launch_adjoint_step_batch(prec, ab, s));
       }
       cur = 1 - cur;
-    }
-    {
-      const int cnt = ne - nb + 1;
+      if (n != clo) continue;
+      // the chunk's map transposes of every instance in one launch
+      const int cnt = std::min(ne, clo + kmt - 1) - clo + 1;
       for (int k = 0; k < count; ++k) {
         lks_plan* P = plans[k];
-        MapAdjArgs m = mapadj_args(P, ws[k], nb);
+        MapAdjArgs m = mapadj_args(P, ws[k], clo);
         m.bkbar = badj_slot(P, ws[k], 0);
         m.bubar = (const char*)m.bkbar + P->bmax.vol * P->es;
         m.kref_bar = (double*)wsp(ws[k], P->o_kpart);

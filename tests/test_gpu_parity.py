@@ -430,6 +430,37 @@ def test_adjoint_refuses_other_inputs():
     assert np.abs(cpu(g["dgamma"])).max() > 0
 
 
+def test_long_segment_transposes_in_chunks():
+    """A segment longer than the 256 steps whose map transposes share one
+    launch is reversed in chunks; one segment (K = nt) keeps every state, so
+    the reverse sweep recomputes nothing.  Both give the gradients of a
+    short-segment run bit for bit, alone and batched."""
+    lks = lk()
+    p0 = prob2d((45, 21), 0, nt=600, r_t=20, r_w=20)
+    gamma, chi, psi = rand_inputs(p0, 44)
+    outs = []
+    for K in (77, 300, 600):
+        plan = lks.Plan(p0.replace(ckpt_k=K))
+        J3, _ = plan.forward(gamma, chi, psi)
+        g = plan.adjoint(gamma, chi, psi)
+        outs.append((cpu(J3), cpu(g["dgamma"]), cpu(g["dchi"]), cpu(g["dpsi"])))
+        del plan
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+    specs = [p0.replace(ckpt_k=600), p0.replace(ckpt_k=600, n=(37, 21, 1), tgt_lo=(16, 1, 0),
+                                                  tgt_hi=(20, 20, 1))]
+    b = lks.Batch([lks.Plan(q) for q in specs])
+    out = b.run([gamma] * 2, [chi] * 2, [psi] * 2)
+    assert np.array_equal(cpu(out[0][0]), outs[0][0])
+    assert np.array_equal(cpu(out[0][1]["dgamma"]), outs[0][1])
+    solo = lks.Plan(specs[1])
+    J3, _ = solo.forward(gamma, chi, psi)
+    g = solo.adjoint(gamma, chi, psi)
+    assert np.array_equal(cpu(out[1][0]), cpu(J3))
+    assert np.array_equal(cpu(out[1][1]["dpsi"]), cpu(g["dpsi"]))
+
+
 def test_reproducible_bitwise():
     """Two identical runs give bit-identical objective and gradients."""
     lks = lk()
