@@ -1749,14 +1749,31 @@ __device__ __forceinline__ double quad_sum(double v) {
   return t + dpp_quad(t, 0x4E);
 }
 
-// 3D transfer transpose: MAPADJ_TPC consecutive lanes per (design column,
-// chunk of LCH design levels), lane r owning the r-th row of the 4x4
-// xy taps.  The z factor is the same 4-tap kernel for every level and
-// consecutive levels are one node apart, so the lanes march the analysis
-// planes once: each plane's xy taps are reduced to 12 plane sums (a 4-lane
-// butterfly joins the rows); a window of the last 4 planes' sums gives each
-// level its z-weighted sums.  Finishing a level adds dJ/dkappa_ref and the
-// level's motion partials.
+// A value every lane of the wave holds, moved to a scalar register.
+__device__ __forceinline__ float uniform(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double uniform(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// 3D transfer transpose.  A block takes an 8 x 8 patch of design columns and
+// a chunk of LCH design levels; its four waves take the four body-adjoint
+// fields (dJ/dkappa and the three components of dJ/du_s), one lane per
+// design column.  The z factor is the same 4-tap kernel for every level and
+// consecutive levels are one node apart, so the block marches the analysis
+// planes once.  The xy taps of the whole patch lie in a 16 x 16 window of
+// the analysis plane (the rotated patch spans at most 7 sqrt(2) nodes, the
+// taps 4 more), so each plane's window is staged in LDS with one coalesced
+// load per field and thread, and every lane reads its 4 x 4 taps from there.
+// Each plane is reduced to its sums weighted by W_xy, dW/dx and dW/dy, and a
+// window of the last four planes gives each level its z-weighted sums.  The
+// motion partials are linear in those sums: each field accumulates its share
+// over the levels and the block adds the four.
+constexpr int MAW = 16;  // staged window side (analysis nodes)
 template <class R, int LCH>
 __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kref, Mot m, Box box,
                                                              const StepInfo* si, const R* bkbar,
@@ -1772,183 +1789,222 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
     mpart += st * sb.mpart;
   }
   apply_step(box, m, si);
-  static_assert(MAPADJ_TPC == 4, "a (column, chunk) group is one DPP quad");
-  static_assert(LCH % 4 == 0, "levels are finished four at a time, one per quad lane");
+  constexpr unsigned BAD = 0x80000000u;  // byte offset past every buffer: loads read 0
+  constexpr unsigned es = sizeof(R);
+  constexpr int WIN = MAW * MAW;
+  static_assert(MAPADJ_THREADS == 256 && WIN == MAPADJ_THREADS,
+                "four waves, one per field; one window node per thread");
+  __shared__ R win[2][4][WIN];  // two planes in turn, four fields
+  const int f = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // field of this wave
+  const int lane = threadIdx.x & 63;
+  const int npx = (g.D[0] + 7) >> 3, npy = (g.D[1] + 7) >> 3;
+  int bi = blockIdx.x;
+  const int px = bi % npx;
+  bi /= npx;
+  const int py = bi % npy;
+  const int ch = bi / npy;
+  const int e0 = px * 8 + (lane & 7), e1 = py * 8 + (lane >> 3);
+  const bool active = e0 < g.D[0] && e1 < g.D[1];
   const int cols = g.D[0] * g.D[1];
-  const int nch = (g.D[2] + LCH - 1) / LCH;
-  const int gid = blockIdx.x * MAPADJ_THREADS + threadIdx.x;
-  const int item = gid / MAPADJ_TPC, row = gid % MAPADJ_TPC;
-  const bool active = item < cols * nch;
-  double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  // all lanes of a group take the same trip counts (the quad sums need them)
-  const int col = active ? item % cols : 0;
-  const int ch = active ? item / cols : 0;
-  const int l0 = ch * LCH, l1 = active ? min(l0 + LCH, g.D[2]) : l0;
-  const int e0 = col % g.D[0], e1 = col / g.D[0];
+  const int col = active ? e0 + g.D[0] * e1 : 0;
+  const int l0 = ch * LCH, l1 = min(l0 + LCH, g.D[2]);
   const double r0 = e0 - g.xiG[0], r1 = e1 - g.xiG[1];
   const double X0 = m.c * r0 - m.s * r1 + m.xg[0];
   const double X1 = m.s * r0 + m.c * r1 + m.xg[1];
-  constexpr unsigned BAD = 0x80000000u;  // byte offset past every buffer: loads return 0
-  R wx[4], dx[4];
-  unsigned ox[4];  // byte offset of each x tap within a box row, BAD if outside
-  const int lx = (int)floor(X0) - 1;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    int vx = lx + q;
-    const R rx = (R)((double)vx - X0);
-    wx[q] = wk(rx);
-    dx[q] = wkd(rx);
-    unsigned o = BAD;
-    if (wrap_axis(g, 0, vx) && !on_wall(g, 0, vx)) {
-      int b = vx - box.lo[0];
-      if (g.bc[0] == 0) { b %= g.n[0]; if (b < 0) b += g.n[0]; }
-      if (b >= 0 && b < box.ext[0]) o = (unsigned)b * sizeof(R);
-    }
-    ox[q] = o;
-  }
-  R wy, dy;
-  int biy = -1;
+  // window origin: the patch's rotated positions are linear in (e0, e1), so
+  // their least floor is at a corner; one node of margin covers rounding
+  int wx0, wy0;
   {
-    int vy = (int)floor(X1) - 1 + row;
-    const R ry = (R)((double)vy - X1);
-    wy = wk(ry);
-    dy = wkd(ry);
-    if (wrap_axis(g, 1, vy) && !on_wall(g, 1, vy)) {
-      int b = vy - box.lo[1];
-      if (g.bc[1] == 0) { b %= g.n[1]; if (b < 0) b += g.n[1]; }
-      if (b >= 0 && b < box.ext[1]) biy = b;
+    double mx = 1e300, my = 1e300;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double q0 = px * 8 + 7 * (k & 1) - g.xiG[0], q1 = py * 8 + 7 * (k >> 1) - g.xiG[1];
+      mx = fmin(mx, m.c * q0 - m.s * q1 + m.xg[0]);
+      my = fmin(my, m.s * q0 + m.c * q1 + m.xg[1]);
     }
+    wx0 = (int)floor(mx) - 2;
+    wy0 = (int)floor(my) - 2;
+  }
+  R wx[4], dx[4], wy[4], dy[4];
+  unsigned tap[16];  // LDS byte offset of tap (row cy, column cx) at 4 cy + cx, field plane 0
+  {
+    const int lx = (int)floor(X0) - 1 - wx0, ly = (int)floor(X1) - 1 - wy0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const R rx = (R)((double)(lx + wx0 + q) - X0), ry = (R)((double)(ly + wy0 + q) - X1);
+      // lanes past the design grid weight their taps by 0
+      wx[q] = active ? wk(rx) : R(0);
+      dx[q] = active ? wkd(rx) : R(0);
+      wy[q] = wk(ry);
+      dy[q] = wkd(ry);
+    }
+    // (lx, ly) in [1, MAW - 5] by the choice of the window: clamped only so
+    // that a lane past the design grid cannot address outside the window
+    const int cx0 = min(max(lx, 0), MAW - 4), cy0 = min(max(ly, 0), MAW - 4);
+#pragma unroll
+    for (int cy = 0; cy < 4; ++cy)
+#pragma unroll
+      for (int cx = 0; cx < 4; ++cx)
+        tap[4 * cy + cx] = (unsigned)((f * WIN + (cy0 + cy) * MAW + cx0 + cx) * es);
   }
   const double o2 = m.xg[2] - g.xiG[2];
   const int fo = (int)floor(o2);
-  const R f = (R)(o2 - fo);
+  const R fr = (R)(o2 - fo);
+  // the z weights are the same for every lane: keep them in scalar registers
   R wz[4], dz[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    wz[q] = wk(R(q) - R(1) - f);
-    dz[q] = wkd(R(q) - R(1) - f);
+    wz[q] = uniform(wk(R(q) - R(1) - fr));
+    dz[q] = uniform(wkd(R(q) - R(1) - fr));
   }
+  // this thread stages window node threadIdx.x of every field: its byte
+  // offset within a box plane, or BAD outside the box or on a wall
   const int bvol = (int)box.vol, bplane = box.sx * box.sy;
-  const int nrec = bvol * (int)sizeof(R);
-  const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc((void*)bkbar, 0, nrec, 0x00020000);
-  const __amdgpu_buffer_rsrc_t ru0 = __builtin_amdgcn_make_buffer_rsrc((void*)bubar, 0, nrec, 0x00020000);
-  const __amdgpu_buffer_rsrc_t ru1 =
-      __builtin_amdgcn_make_buffer_rsrc((void*)(bubar + bvol), 0, nrec, 0x00020000);
-  const __amdgpu_buffer_rsrc_t ru2 =
-      __builtin_amdgcn_make_buffer_rsrc((void*)(bubar + 2 * bvol), 0, nrec, 0x00020000);
-  auto bload = [](__amdgpu_buffer_rsrc_t r, unsigned off) -> R {
-    if constexpr (sizeof(R) == 4)
-      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
-    else
-      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
-  };
-  // The analysis planes are visited in order (z is periodic in 3D): issue()
-  // loads this lane's 4 taps x 4 fields of the next plane (taps outside the
-  // box read 0 through the buffer range check); reduce() turns a loaded plane
-  // into its weighted sums over the quad, P = (W k, W u_x, W u_y, W u_z,
-  // dW/dx (same 4), dW/dy (same 4)).  Loads run one plane ahead of the sums.
-  int r2 = (l0 + fo - 1 - box.lo[2]) % g.n[2];  // box plane of the next issue
-  if (r2 < 0) r2 += g.n[2];
-  auto issue = [&](R* V) {
-    unsigned base = BAD;
-    if (r2 < box.ext[2] && biy >= 0) base = (unsigned)(box.sx * biy + bplane * r2) * sizeof(R);
-    r2 = r2 + 1 == g.n[2] ? 0 : r2 + 1;
-#pragma unroll
-    for (int cx = 0; cx < 4; ++cx) {
-      const unsigned off = (base == BAD || ox[cx] == BAD) ? BAD : base + ox[cx];
-      V[4 * cx] = bload(rk, off);
-      V[4 * cx + 1] = bload(ru0, off);
-      V[4 * cx + 2] = bload(ru1, off);
-      V[4 * cx + 3] = bload(ru2, off);
+  unsigned noff = BAD;
+  {
+    int vx = wx0 + (int)(threadIdx.x % MAW), vy = wy0 + (int)(threadIdx.x / MAW);
+    if (wrap_axis(g, 0, vx) && wrap_axis(g, 1, vy) && !on_wall(g, 0, vx) && !on_wall(g, 1, vy)) {
+      int b0 = vx - box.lo[0], b1 = vy - box.lo[1];
+      if (g.bc[0] == 0) { b0 %= g.n[0]; if (b0 < 0) b0 += g.n[0]; }
+      if (g.bc[1] == 0) { b1 %= g.n[1]; if (b1 < 0) b1 += g.n[1]; }
+      if (b0 >= 0 && b0 < box.ext[0] && b1 >= 0 && b1 < box.ext[1])
+        noff = (unsigned)(b0 + box.sx * b1) * es;
     }
+  }
+  const unsigned fbytes = (unsigned)bvol * es;
+  const __amdgpu_buffer_rsrc_t rk = brsrc(bkbar, fbytes);
+  const __amdgpu_buffer_rsrc_t ru0 = brsrc(bubar, fbytes);
+  const __amdgpu_buffer_rsrc_t ru1 = brsrc(bubar + bvol, fbytes);
+  const __amdgpu_buffer_rsrc_t ru2 = brsrc(bubar + 2LL * bvol, fbytes);
+  // the analysis planes are visited in order (z is periodic in 3D); planes
+  // outside the box read 0 (offset BAD for every thread)
+  int r2 = (l0 + fo - 1 - box.lo[2]) % g.n[2];  // box plane of the next fetch
+  if (r2 < 0) r2 += g.n[2];
+  auto fetch = [&](R* S) {
+    const bool in = r2 < box.ext[2];
+    const unsigned vo = in ? noff : BAD;
+    const unsigned so = in ? (unsigned)(bplane * r2) * es : 0u;
+    S[0] = bld<R>(rk, vo, so);
+    S[1] = bld<R>(ru0, vo, so);
+    S[2] = bld<R>(ru1, vo, so);
+    S[3] = bld<R>(ru2, vo, so);
+    r2 = r2 + 1 == g.n[2] ? 0 : r2 + 1;
   };
-  auto reduce = [&](const R* V, R* P) {
-    R S[4] = {R(0), R(0), R(0), R(0)}, D[4] = {R(0), R(0), R(0), R(0)};
+  auto stage = [&](int buf, const R* S) {
 #pragma unroll
-    for (int cx = 0; cx < 4; ++cx) {
+    for (int q = 0; q < 4; ++q) win[buf][q][threadIdx.x] = S[q];
+  };
+  // a plane's sums: (W_xy, dW/dx W_y, W_x dW/dy) weighted
+  auto reduce = [&](int buf, R* P) {
+    const char* wb = (const char*)&win[buf][0][0];
+    R V[16];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        S[q] += wx[cx] * V[4 * cx + q];
-        D[q] += dx[cx] * V[4 * cx + q];
+    for (int k = 0; k < 16; ++k) V[k] = *(const R*)(wb + tap[k]);
+    R s[4], d[4];
+#pragma unroll
+    for (int cy = 0; cy < 4; ++cy) {
+      s[cy] = wx[0] * V[4 * cy] + wx[1] * V[4 * cy + 1] + wx[2] * V[4 * cy + 2] +
+              wx[3] * V[4 * cy + 3];
+      d[cy] = dx[0] * V[4 * cy] + dx[1] * V[4 * cy + 1] + dx[2] * V[4 * cy + 2] +
+              dx[3] * V[4 * cy + 3];
+    }
+    P[0] = wy[0] * s[0] + wy[1] * s[1] + wy[2] * s[2] + wy[3] * s[3];
+    P[1] = wy[0] * d[0] + wy[1] * d[1] + wy[2] * d[2] + wy[3] * d[3];
+    P[2] = dy[0] * s[0] + dy[1] * s[1] + dy[2] * s[2] + dy[3] * s[3];
+  };
+  // Plane p (p = 0 .. LCH + 2, analysis plane zb + p, zb = l0 + fo - 1) sits
+  // in win[p & 1] while it is reduced; the registers hold the next two
+  // planes' values in flight.  Level l0 + t uses planes t .. t + 3.
+  constexpr int NP = LCH + 3;
+  R S0[4], S1[4];
+  fetch(S0);
+  stage(0, S0);
+  fetch(S0);  // plane 1
+  fetch(S1);  // plane 2
+  __syncthreads();
+  R Wp[4][3];
+  // field 0 writes dJ/dkappa_ref and weights its sums by kappa_ref; the
+  // velocity fields' weights (U) are constant over the column and applied at
+  // the end.  kappa_ref, the previous dJ/dkappa_ref and the stores go through
+  // buffer resources: lanes that take no part get an offset past the buffer
+  // (loads read 0, stores are dropped), levels past the chunk a resource of
+  // size 0, and the level offset is uniform.
+  const unsigned mcount = (unsigned)(cols * g.D[2]);
+  const __amdgpu_buffer_rsrc_t rkr = brsrc(kref, mcount * es);
+  const __amdgpu_buffer_rsrc_t rkb = brsrc(kref_bar, mcount * 8u);
+  const __amdgpu_buffer_rsrc_t rk0 = brsrc(kref_bar, 0u);
+  const bool own = f == 0 && active;
+  const unsigned kro = own ? (unsigned)col * es : BAD;
+  const unsigned kbo = own ? (unsigned)col * 8u : BAD;
+  const unsigned kbl = own && !overwrite ? kbo : BAD;
+  double T[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int t = p - 3;  // level finished after this plane (t >= 0)
+    const int L = l0 + t;
+    const bool lv = t >= 0 && L < l1;
+    const unsigned lo = lv ? (unsigned)(cols * L) : 0u;  // uniform level offset (elements)
+    R kr = R(0);
+    double kb = 0.0;
+    if (t >= 0) {
+      kr = bld<R>(lv ? rkr : rk0, kro, lo * es);
+      kb = bld<double>(lv ? rkb : rk0, kbl, lo * 8u);
+    }
+    reduce(p & 1, Wp[p & 3]);
+    if (p + 1 < NP) {
+      // plane p + 1 enters the other buffer, plane p + 3 is fetched
+      R* S = (p & 1) ? S1 : S0;
+      stage((p + 1) & 1, S);
+      if (p + 3 < NP) fetch(S);
+      __syncthreads();
+    }
+    if (t >= 0) {
+      const R* P0 = Wp[t & 3];
+      const R* P1 = Wp[(t + 1) & 3];
+      const R* P2 = Wp[(t + 2) & 3];
+      const R* P3 = Wp[(t + 3) & 3];
+      const R aS = wz[0] * P0[0] + wz[1] * P1[0] + wz[2] * P2[0] + wz[3] * P3[0];
+      const R aX = wz[0] * P0[1] + wz[1] * P1[1] + wz[2] * P2[1] + wz[3] * P3[1];
+      const R aY = wz[0] * P0[2] + wz[1] * P1[2] + wz[2] * P2[2] + wz[3] * P3[2];
+      const R aZ = dz[0] * P0[0] + dz[1] * P1[0] + dz[2] * P2[0] + dz[3] * P3[0];
+      bst<double>(kb + (double)aS, lv ? rkb : rk0, kbo, lo * 8u);
+      if (lv) {  // uniform: levels past the design grid add nothing
+        const double c = f == 0 ? (double)kr : 1.0;
+        T[0] += c * (double)aX;
+        T[1] += c * (double)aY;
+        T[2] += c * (double)aZ;
+        T[3] += (double)aS;
       }
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      P[q] = quad_sum(wy * S[q]);
-      P[4 + q] = quad_sum(wy * D[q]);
-      P[8 + q] = quad_sum(dy * S[q]);
-    }
-  };
-  const double U0 = m.om * (-m.s * r0 - m.c * r1) + m.ug[0];
-  const double U1 = m.om * (m.c * r0 - m.s * r1) + m.ug[1];
-  const double U2 = m.ug[2];
-  const double dX0 = -m.s * r0 - m.c * r1, dX1 = m.c * r0 - m.s * r1;                      // R' r
-  const double dU0 = m.om * (-m.c * r0 + m.s * r1), dU1 = m.om * (-m.s * r0 - m.c * r1);  // om R'' r
-  // this lane finishes levels l0 + row + 4 j; their kappa_ref and previous
-  // accumulator values are read up front
-  constexpr int NJ = LCH / 4;
-  double krj[NJ], kbj[NJ];
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int L = l0 + row + 4 * j;
-    krj[j] = kbj[j] = 0.0;
-    if (L < l1) {
-      const long long k = col + (long long)cols * L;
-      krj[j] = (double)kref[k];
-      kbj[j] = overwrite ? 0.0 : kref_bar[k];
-    }
   }
-  // level l0 + t uses analysis planes zb + t .. zb + t + 3, zb = l0 + fo - 1;
-  // plane zb + p is loaded into V[p % PD] (PD >= 2), PD - 1 planes ahead of its sums
-  // (a grid of a few waves per SIMD hides little latency by itself)
-  constexpr int PD = sizeof(R) == 4 ? MAPADJ_PREFETCH : 2;  // FP64: registers
-  static_assert(PD >= 2, "one plane in flight while another is summed");
-  R Wp[4][12];
-  R V[PD][16];
-#pragma unroll
-  for (int p = 0; p < PD; ++p) issue(V[p]);
-#pragma unroll
-  for (int p = 0; p < 3; ++p) {
-    reduce(V[p % PD], Wp[p]);
-    if (p + PD <= LCH + 2) issue(V[p % PD]);
-  }
-  R mine[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) mine[q] = R(0);
-#pragma unroll
-  for (int t = 0; t < LCH; ++t) {
-    const int p = t + 3;
-    reduce(V[p % PD], Wp[p & 3]);
-    if (p + PD <= LCH + 2) issue(V[p % PD]);
-    const R* P0 = Wp[t & 3];
-    const R* P1 = Wp[(t + 1) & 3];
-    const R* P2 = Wp[(t + 2) & 3];
-    const R* P3 = Wp[(t + 3) & 3];
-    if (row == (t & 3)) {
-#pragma unroll
-      for (int q = 0; q < 12; ++q) mine[q] = wz[0] * P0[q] + wz[1] * P1[q] + wz[2] * P2[q] + wz[3] * P3[q];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) mine[12 + q] = dz[0] * P0[q] + dz[1] * P1[q] + dz[2] * P2[q] + dz[3] * P3[q];
-    }
-    if ((t & 3) == 3) {
-      // the quad's four lanes finish levels l0 + t - 3 .. l0 + t, one each
-      const int j = t >> 2;
-      const int L = l0 + 4 * j + row;
-      if (L < l1) {
-        const R* A = mine;
-        const double kr = krj[j];
-        const double Xb0 = -(kr * A[4] + U0 * A[5] + U1 * A[6] + U2 * A[7]);
-        const double Xb1 = -(kr * A[8] + U0 * A[9] + U1 * A[10] + U2 * A[11]);
-        const double Xb2 = -(kr * A[12] + U0 * A[13] + U1 * A[14] + U2 * A[15]);
-        kref_bar[col + (long long)cols * L] = kbj[j] + (double)A[0];
-        part[0] += Xb0;
-        part[1] += Xb1;
-        part[2] += Xb2;
-        part[3] += A[1];
-        part[4] += A[2];
-        part[5] += A[3];
-        part[6] += Xb0 * dX0 + Xb1 * dX1 + (double)A[1] * dU0 + (double)A[2] * dU1;
-        part[7] += (double)A[1] * dX0 + (double)A[2] * dX1;
+  // motion partials of this lane's field (Eq. dJdchi, dJdpsi via the rigid
+  // motion): Xb = dJ/dx^G, then u^G, theta and omega
+  double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  {
+    const double dX0 = -m.s * r0 - m.c * r1, dX1 = m.c * r0 - m.s * r1;  // R' r
+    if (f == 0) {
+      part[0] = -T[0];
+      part[1] = -T[1];
+      part[2] = -T[2];
+      part[6] = part[0] * dX0 + part[1] * dX1;
+    } else {
+      // U = om R' r + u^G and its angle derivative om R'' r
+      const double U = f == 1   ? m.om * dX0 + m.ug[0]
+                       : f == 2 ? m.om * dX1 + m.ug[1]
+                                : m.ug[2];
+      part[0] = -U * T[0];
+      part[1] = -U * T[1];
+      part[2] = -U * T[2];
+      part[3] = f == 1 ? T[3] : 0.0;
+      part[4] = f == 2 ? T[3] : 0.0;
+      part[5] = f == 3 ? T[3] : 0.0;
+      part[6] = part[0] * dX0 + part[1] * dX1;
+      if (f == 1) {
+        part[6] += T[3] * (m.om * (-m.c * r0 + m.s * r1));
+        part[7] = T[3] * dX0;
+      } else if (f == 2) {
+        part[6] += T[3] * (m.om * (-m.s * r0 - m.c * r1));
+        part[7] = T[3] * dX1;
       }
     }
   }
@@ -3247,9 +3303,9 @@ static int mapadj_lch(const Geo& g) {
 int mapadj_blocks(const Geo& g) {
   if (g.rot) return (int)((g.Mtot + MAPADJ_THREADS - 1) / MAPADJ_THREADS);
   if (g.d == 3) {
+    // 8 x 8 design columns per block, times the level chunks
     const int lch = mapadj_lch(g);
-    const long long n = (long long)g.D[0] * g.D[1] * ((g.D[2] + lch - 1) / lch) * MAPADJ_TPC;
-    return (int)((n + MAPADJ_THREADS - 1) / MAPADJ_THREADS);
+    return (int)((long long)((g.D[0] + 7) / 8) * ((g.D[1] + 7) / 8) * ((g.D[2] + lch - 1) / lch));
   }
   return mapadj_blocks_2d(g);
 }
