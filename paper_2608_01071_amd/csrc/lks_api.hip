@@ -446,10 +446,23 @@ lks_status forward_loop(lks_plan* P, void* ws, hipStream_t s) {
     }
     return LKS_OK;
   }
+  // 3D about z with a body slot per step: the maps of MAP_BATCH steps run as
+  // one launch ahead of their steps (a one-step map is a few thousand short
+  // waves, all resident at once, so its latency is not hidden)
+  const bool mbatch = P->g.d == 3 && !P->g.rot && P->full_btape && !P->j2;
   for (int n = 1; n <= P->g.nt; ++n) {
     void* out = fwd_out(P, ws, n);
     void* body = fwd_body(P, ws, n);
-    if (P->j2 && n > 1) {
+    if (mbatch) {
+      if ((n - 1) % MAP_BATCH == 0) {
+        const int cnt = std::min(MAP_BATCH, P->g.nt - n + 1);
+        Scope sc("map", s, true);
+        HIPCHK(launch_map(P->g, P->prec, wsp(ws, P->o_kref), wsp(ws, P->o_kz), P->bmax.ext[2],
+                          nullptr, tab(P, ws, n), P->bmax, body,
+                          (char*)body + P->bmax.vol * P->es, 0, s, cnt,
+                          (long long)(body_bytes(P) / P->es)));
+      }
+    } else if (P->j2 && n > 1) {
       // J2: the step sums of state n - 1 ride along with this step's map
       Scope sc("map", s, true);
       HIPCHK(launch_map_j2(P->g, P->prec, wsp(ws, P->o_kref), tab(P, ws, n), P->bmax, body,

@@ -59,6 +59,8 @@ constexpr int MAP_ZC = 16;
 constexpr int MAP_ZPL = 3;
 // 3D map: zero padding (design levels) of the z-fastest kappa_ref copy.
 constexpr int KZ_PAD = 8;
+// 3D forward march with a body slot per step: steps mapped per launch.
+constexpr int MAP_BATCH = 8;
 // 3D map transpose: design levels per lane group (short chunks, and long
 // ones for FP32 when the design grid has at least 3 x 24 levels).
 constexpr int MAPADJ_LCH = 8;
@@ -304,9 +306,12 @@ hipError_t launch_forward_step(const Geo& g, int precision, const FwdArgs& a, hi
 hipError_t launch_adjoint_step(const Geo& g, int precision, const AdjArgs& a, hipStream_t s);
 size_t kz_bytes(const Geo& g, int ext2max, int precision);
 hipError_t launch_kref_t(const Geo& g, int precision, const void* kref, void* kt, hipStream_t s);
+// nsteps > 1 (3D, rotation about z, per-step table): consecutive steps from
+// si, body slots bstride values apart.
 hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf, int ext2max,
                       const double* mot8_host, const StepInfo* si, const Box& box, void* bk,
-                      void* bu, int full_grid, hipStream_t s);
+                      void* bu, int full_grid, hipStream_t s, int nsteps = 1,
+                      long long bstride = 0);
 int mapadj_blocks(const Geo& g);
 // Map transposes of consecutive steps in one launch (blockIdx.y = step
 // within the batch): step k reads si[k] and its body adjoint advanced by

@@ -1584,12 +1584,22 @@ __global__ __launch_bounds__(256) void k_kref_t(Geo g, const R* kref, R* kt, int
 
 template <class R>
 __global__ __launch_bounds__(256) void k_map3d(Geo g, const R* kt, int lz, Mot m, Box box,
-                                               const StepInfo* si, R* bk, R* bu, int full_grid) {
+                                               const StepInfo* si, R* bk, R* bu, int full_grid,
+                                               long long bstride) {
+  // blockIdx.y: step within a batch of consecutive steps (per-step table rows
+  // and body slots bstride values apart)
+  if (si) si += blockIdx.y;
+  bk += blockIdx.y * bstride;
+  bu += blockIdx.y * bstride;
   constexpr int ZPL = MAP_ZPL;  // z values per lane
   static_assert(ZPL <= MAP_ZC, "the z-fastest copy is padded for ZPL values per lane");
   constexpr int NS = 36;         // candidate window: at most 6 x 6 design columns
   __shared__ R cw[8][NS], cr0[8][NS], cr1[8][NS];  // weight, design offsets r0, r1
   __shared__ int ci[8][NS];                         // design column index
+  // outputs of the block's 8 columns (consecutive along x) for one z pass,
+  // stored from here with lanes along x so a store covers 8 nodes of a row
+  constexpr int ZB = 32 * ZPL;
+  __shared__ R ost[4][ZB][8];
   apply_step(box, m, si);
   const int hw = threadIdx.x >> 5, lane = threadIdx.x & 31;
   const int ncol = box.ext[0] * box.ext[1];
@@ -1694,7 +1704,6 @@ __global__ __launch_bounds__(256) void k_map3d(Geo g, const R* kt, int lz, Mot m
 #pragma unroll
     for (int t = 0; t < ZPL; ++t) {
       const int kk = zbase + t;
-      if (!cok || kk >= box.ext[2]) break;
       int z = box.lo[2] + kk;
       const bool inside = col_inside && wrap_axis(g, 2, z);
       const bool wall = !inside || col_wall || on_wall(g, 2, z);
@@ -1707,22 +1716,33 @@ __global__ __launch_bounds__(256) void k_map3d(Geo g, const R* kt, int lz, Mot m
         kv += wz[q] * G[t + q];
       }
       if (wall) kv = R(0);
-      const R ux = wall ? R(0) : zs * vx, uy = wall ? R(0) : zs * vy, uz = wall ? R(0) : zs * vz;
+      const int zz = lane * ZPL + t;
+      ost[0][zz][hw] = kv;
+      ost[1][zz][hw] = wall ? R(0) : zs * vx;
+      ost[2][zz][hw] = wall ? R(0) : zs * vy;
+      ost[3][zz][hw] = wall ? R(0) : zs * vz;
+    }
+    __syncthreads();
+    // element e: column e % 8 (fastest), z e / 8 % ZB, field e / (8 ZB)
+    for (int e = threadIdx.x; e < 4 * ZB * 8; e += 256) {
+      const int c = e & 7, zz = (e >> 3) % ZB, q = e / (8 * ZB);
+      const int kk = zblk + zz;
+      const int cid = blockIdx.x * 8 + c;
+      if (cid >= ncol || kk >= box.ext[2]) continue;
+      const int ic = cid % box.ext[0], jc = cid / box.ext[0];
+      const R v = ost[q][zz][c];
+      R* dst = q == 0 ? bk : bu;
       if (full_grid) {
-        if (wall) continue;
-        const long long n = nidx(g, x, y, z);
-        bk[n] = kv;
-        bu[n] = ux;
-        bu[g.N + n] = uy;
-        bu[2 * g.N + n] = uz;
+        int xc = box.lo[0] + ic, yc = box.lo[1] + jc, zc = box.lo[2] + kk;
+        if (!wrap_axis(g, 0, xc) || !wrap_axis(g, 1, yc) || !wrap_axis(g, 2, zc)) continue;
+        if (on_wall(g, 0, xc) || on_wall(g, 1, yc) || on_wall(g, 2, zc)) continue;
+        dst[(q == 0 ? 0 : (long long)(q - 1) * g.N) + nidx(g, xc, yc, zc)] = v;
       } else {
-        const long long bi = i + (long long)box.sx * (j + (long long)box.sy * kk);
-        bk[bi] = kv;
-        bu[bi] = ux;
-        bu[box.vol + bi] = uy;
-        bu[2 * box.vol + bi] = uz;
+        dst[(q == 0 ? 0 : (long long)(q - 1) * box.vol) + ic +
+            (long long)box.sx * (jc + (long long)box.sy * kk)] = v;
       }
     }
+    __syncthreads();  // before the next pass rewrites the staging array
   }
 }
 
@@ -3245,9 +3265,11 @@ hipError_t launch_kref_t(const Geo& g, int precision, const void* kref, void* kt
 
 hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf, int ext2max,
                       const double* mot8_host, const StepInfo* si, const Box& box, void* bk,
-                      void* bu, int full_grid, hipStream_t s) {
+                      void* bu, int full_grid, hipStream_t s, int nsteps, long long bstride) {
   (void)ext2max;
   if (box.ext[0] <= 0 || box.ext[1] <= 0 || box.ext[2] <= 0) return hipSuccess;
+  // several steps per launch: the 3D map about z with table rows only
+  if (nsteps > 1 && (g.d != 3 || g.rot || !si)) return hipErrorInvalidValue;
   if (g.rot) {
     StepInfo sv;
     memset(&sv, 0, sizeof sv);
@@ -3282,13 +3304,13 @@ hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf
                          (double*)bk, (double*)bu, full_grid);
   } else {
     const int lz = kz_levels(g);
-    dim3 grid((unsigned)((box.ext[0] * box.ext[1] + 7) / 8));
+    dim3 grid((unsigned)((box.ext[0] * box.ext[1] + 7) / 8), (unsigned)nsteps);
     if (precision == 0)
       LKS_LAUNCH(k_map3d<float>, grid, dim3(256), 0, s, g, (const float*)kzbuf, lz, m, box, si,
-                 (float*)bk, (float*)bu, full_grid);
+                 (float*)bk, (float*)bu, full_grid, bstride);
     else
       LKS_LAUNCH(k_map3d<double>, grid, dim3(256), 0, s, g, (const double*)kzbuf, lz, m, box,
-                 si, (double*)bk, (double*)bu, full_grid);
+                 si, (double*)bk, (double*)bu, full_grid, bstride);
   }
   return hipGetLastError();
 }
