@@ -399,10 +399,12 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* out) {
 }
 
 // Brinkman correction, wall rule, objective partials and store of one
-// output node.  acc = (sum_i feq_i, sum_i c_i feq_i) gathered at x.
+// output node.  acc = (sum_i feq_i, sum_i c_i feq_i) gathered at x; the body
+// fields (bin: node in the box) are loaded by the caller ahead of time.
 template <class R>
 __device__ __forceinline__ void finish_node(const Geo& g, const FwdArgs& a, int x, int y, int z,
-                                            R sp, R sux, R suy, R suz, double& s1, double& s2) {
+                                            R sp, R sux, R suy, R suz, double& s1, double& s2,
+                                            bool bin, R bkv, const R (&buv)[3]) {
   R* out = (R*)a.out;
   const long long N = g.N;
   const long long i = nidx(g, x, y, z);
@@ -420,15 +422,9 @@ __device__ __forceinline__ void finish_node(const Geo& g, const FwdArgs& a, int 
     u[0] = sux;
     u[1] = suy;
     u[2] = suz;
-    if (a.bk) {
-      long long bi = box_index(g, a.box, x, y, z);
-      if (bi >= 0) {
-        const R* bk = (const R*)a.bk;
-        const R* bu = (const R*)a.bu;
-        R k = bk[bi];
-        R inv = brinkman_inv(k);
-        _Pragma("unroll") for (int c = 0; c < 3; ++c) if (c < g.d) u[c] = (u[c] + k * bu[c * a.box.vol + bi]) * inv;
-      }
+    if (bin) {
+      const R inv = brinkman_inv(bkv);
+      _Pragma("unroll") for (int c = 0; c < 3; ++c) if (c < g.d) u[c] = (u[c] + bkv * buv[c]) * inv;
     }
     R uu = u[0] * u[0] + u[1] * u[1] + (g.d == 3 ? u[2] * u[2] : R(0));
     if (a.flags && !(uu < R(0.25))) a.flags[0] = 1;  // non-finite or |u| >= 0.5
@@ -458,6 +454,25 @@ __device__ __forceinline__ void fwd2d_tile(const Geo& g, FwdArgs a, int bid) {
   int tbx, tby, tbz;
   const int tlin = xcd_tile_of(bid, g.nxcd, tiles_x(g), tiles_y(g), 1, tbx, tby, tbz);
   const int x0 = tbx * TX + g.org[0], y0 = tby * TY + g.org[1];
+  // the body fields of this thread's output node are loaded first, so their
+  // latency overlaps the state loads and the equilibria
+  static_assert(STEP_THREADS == TX * TY, "one output node per thread");
+  const int otx = threadIdx.x % TX, oty = threadIdx.x / TX;
+  const int ogx = x0 + otx, ogy = y0 + oty;
+  const bool oown = ogx >= 0 && ogx < g.n[0] && ogy >= 0 && ogy < g.n[1];
+  bool bin = false;
+  R bkv = R(0), buv[3] = {R(0), R(0), R(0)};
+  if (oown && a.bk && !is_wall(g, ogx, ogy, 0)) {
+    const long long bi = box_index(g, a.box, ogx, ogy, 0);
+    if (bi >= 0) {
+      const R* bk = (const R*)a.bk;
+      const R* bu = (const R*)a.bu;
+      bin = true;
+      bkv = bk[bi];
+      buv[0] = bu[bi];
+      buv[1] = bu[a.box.vol + bi];
+    }
+  }
   for (int k = threadIdx.x; k < LX * LY; k += STEP_THREADS) {
     int gx = x0 - 2 + k % LX, gy = y0 - 2 + k / LX;
     R p = R(0), ux = R(0), uy = R(0);
@@ -493,9 +508,9 @@ __device__ __forceinline__ void fwd2d_tile(const Geo& g, FwdArgs a, int bid) {
   __syncthreads();
   double s1 = 0.0, s2 = 0.0;
   {
-    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-    const int gx = x0 + tx, gy = y0 + ty;
-    if (gx >= 0 && gx < g.n[0] && gy >= 0 && gy < g.n[1]) {
+    const int tx = otx, ty = oty;
+    const int gx = ogx, gy = ogy;
+    if (oown) {
       const int c = (ty + 1) * FX + (tx + 1);
       R P = R(0), Ux = R(0), Uy = R(0);
 #pragma unroll
@@ -508,7 +523,7 @@ __device__ __forceinline__ void fwd2d_tile(const Geo& g, FwdArgs a, int bid) {
         if (cy == 1) Uy += v;
         if (cy == -1) Uy -= v;
       }
-      finish_node<R>(g, a, gx, gy, 0, P, Ux, Uy, R(0), s1, s2);
+      finish_node<R>(g, a, gx, gy, 0, P, Ux, Uy, R(0), s1, s2, bin, bkv, buv);
     }
   }
   if (a.opart) {
@@ -957,6 +972,18 @@ __device__ __forceinline__ void adj2d_tile(const Geo& g, AdjArgs a, int bid) {
   int tbx, tby, tbz;
   xcd_tile_of(bid, g.nxcd, tiles_x(g), adj2d_tiles_y(g), 1, tbx, tby, tbz);
   const int x0 = tbx * TX + g.org[0], y0 = tby * TY + g.org[1];
+  // this thread's output node and its velocity of the previous step, loaded
+  // first so the latency overlaps the gather
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+  const int gx = x0 + tx, gy = y0 + ty;
+  const bool oown = ty < TY && gx >= 0 && gx < g.n[0] && gy >= 0 && gy < g.n[1];
+  const long long i = oown ? nidx(g, gx, gy, 0) : 0;
+  R ux = R(0), uy = R(0);
+  if (oown) {
+    const R* up = (const R*)a.u_prev;
+    ux = up[N + i];
+    uy = up[2 * N + i];
+  }
   for (int k = threadIdx.x; k < LX * LY; k += ADJ2D_THREADS) {
     int lx = k % LX, ly = k / LX;
     int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
@@ -1000,13 +1027,8 @@ __device__ __forceinline__ void adj2d_tile(const Geo& g, AdjArgs a, int bid) {
     sm[5][k] = Mxy;
   }
   __syncthreads();
-  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
-  const int gx = x0 + tx, gy = y0 + ty;
-  if (ty >= TY || gx < 0 || gx >= g.n[0] || gy < 0 || gy >= g.n[1]) return;
+  if (!oown) return;
   const int c = (ty + 1) * FX + (tx + 1);
-  const long long i = nidx(g, gx, gy, 0);
-  const R* up = (const R*)a.u_prev;
-  const R ux = up[N + i], uy = up[2 * N + i];
   const R M0 = sm[0][c];
   const R A2 = R(2) * (R)g.A;
   R px = R(3) * M0;
