@@ -161,12 +161,14 @@ __device__ __forceinline__ float wkd(float r) {
 __device__ __forceinline__ double wkd(double r) { return -0.39269908169872414 * sinpi(0.5 * r); }
 
 // Derivative along one axis from an LDS row (stride st): central, or
-// second-order one-sided on a wall node.
+// second-order one-sided on a wall node.  The one-sided forms name their
+// fused multiply-add (a sum of two products may otherwise be fused either
+// way), so every kernel that inlines this rounds alike.
 template <class R>
 __device__ __forceinline__ R dnum(const Geo& g, int a, int v, const R* s, int c, int st) {
   if (g.bc[a] == 1) {
-    if (v == 0) return R(-1.5) * s[c] + R(2) * s[c + st] - R(0.5) * s[c + 2 * st];
-    if (v == g.n[a] - 1) return R(1.5) * s[c] - R(2) * s[c - st] + R(0.5) * s[c - 2 * st];
+    if (v == 0) return fma(R(-1.5), s[c], R(2) * s[c + st]) - R(0.5) * s[c + 2 * st];
+    if (v == g.n[a] - 1) return fma(R(1.5), s[c], R(-2) * s[c - st]) + R(0.5) * s[c - 2 * st];
   }
   return R(0.5) * (s[c + st] - s[c - st]);
 }
@@ -334,17 +336,18 @@ __device__ __forceinline__ R dwall2(const R* s, int c, int o) {
 }
 
 // Inamuro equilibria for one node (pairs of opposite directions share
-// their even part).  S holds D_a u_b + D_b u_a.
+// their even part).  S holds D_a u_b + D_b u_a.  Sums of two products name
+// their fused multiply-add, so the 2D kernels that inline this (one step,
+// step with map, batched) round alike.
 template <class R>
 __device__ __forceinline__ void feq9(R p, R ux, R uy, R Sxx, R Syy, R Sxy, R A, R* f) {
   using C = EqC<R>;
-  const R base = R(3) * p - R(1.5) * (ux * ux + uy * uy);
+  const R base = fma(R(-1.5), fma(uy, uy, ux * ux), R(3) * p);
   f[0] = C::w0_9 * base;
   auto pair = [&](int i, R w, R c3w, R cu, R cSc) {
     R com = w * (base + R(4.5) * cu * cu + A * cSc);
-    R od = c3w * cu;
-    f[i] = com + od;
-    f[i + 1] = com - od;
+    f[i] = fma(c3w, cu, com);
+    f[i + 1] = fma(-c3w, cu, com);
   };
   pair(1, C::wa, C::ca, ux, Sxx);
   pair(3, C::wa, C::ca, uy, Syy);
