@@ -61,17 +61,10 @@ constexpr int MAP_ZPL = 3;
 constexpr int KZ_PAD = 8;
 // 3D forward march with a body slot per step: steps mapped per launch.
 constexpr int MAP_BATCH = 8;
-// 3D map transpose: design levels per lane group (short chunks, and long
+// 3D map transpose: design levels per block (short chunks, and long
 // ones for FP32 when the design grid has at least 3 x 24 levels).
 constexpr int MAPADJ_LCH = 8;
 constexpr int MAPADJ_LCH_LONG = 24;
-// 3D map transpose: planes whose loads are in flight per lane group.
-constexpr int MAPADJ_PREFETCH = 2;
-// Map transposes: lanes per design column (3D: per level chunk), one per
-// row of the 4 x 4 xy taps.
-constexpr int MAPADJ_TPC = 4;
-// 2D map transpose: runs of 64 design points per block.
-constexpr int MAPADJ_PTS2 = 2;
 // 2D transfer: a block is a MAP2_TX x MAP2_TY patch of analysis nodes.
 constexpr int MAP2_TX = 64, MAP2_TY = 4;
 
@@ -118,10 +111,9 @@ __host__ __device__ inline long long inner_points(const Geo& g) {
   return M;
 }
 
-// Blocks of the 2D map transpose (MAPADJ_PTS2 runs of 64 points each).
+// Blocks of the 2D map transpose (a 16 x 16 patch of design points each).
 __host__ __device__ inline int mapadj_blocks_2d(const Geo& g) {
-  constexpr long long per = (long long)MAPADJ_PTS2 * (MAPADJ_THREADS / MAPADJ_TPC);
-  return (int)((g.Mtot + per - 1) / per);
+  return ((g.D[0] + 15) / 16) * ((g.D[1] + 15) / 16);
 }
 
 // Support box of the body at one step, in unwrapped analysis coordinates;

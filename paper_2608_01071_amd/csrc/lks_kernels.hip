@@ -612,6 +612,7 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
   }
   const int bvol = (int)a.box.vol, bplane = a.box.sx * a.box.sy;
   const bool body = a.bk && bvol > 0;
+  const bool wbody = __ballot(cbxy >= 0) != 0;  // some lane of the wave owns a box column
   const unsigned bb = (unsigned)bvol * es;  // bytes of one body field
   const __amdgpu_buffer_rsrc_t rbk = brsrc(a.bk, bb);
   const __amdgpu_buffer_rsrc_t rbu = brsrc(a.bu, 3u * bb);
@@ -651,9 +652,10 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
     fzw = fzw + 1 == nz ? 0 : fzw + 1;
     fr2 = fr2 + 1 == nz ? 0 : fr2 + 1;
     B.bin = false;
-    if (body) {
-      B.bin = cbxy >= 0 && r2 < a.box.ext[2] && zp - 2 >= z0 && zp - 2 < z1;
-      // (plane offsets past the box read 0; B.bin decides)
+    // wave-uniform skip: waves without an output column in the box (the halo
+    // waves among them) and planes outside the box load no body fields
+    if (body && wbody && r2 < a.box.ext[2]) {
+      B.bin = cbxy >= 0 && zp - 2 >= z0 && zp - 2 < z1;
       const unsigned so = (unsigned)(bplane * r2) * es;
       B.bk = bld<R>(rbk, cvo, so);
       B.bu[0] = bld<R>(rbu, cvo, so);
@@ -1771,28 +1773,6 @@ __global__ __launch_bounds__(256) void k_map3d(Geo g, const R* kt, int lz, Mot m
   }
 }
 
-// Sum over the 4 lanes of a quad (lanes 4q..4q+3), the same value in every
-// lane: two DPP quad permutations (xor 1, then xor 2), no LDS traffic.
-__device__ __forceinline__ float quad_sum(float v) {
-  float t = v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-  return t + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(t), 0x4E, 0xF, 0xF, false));
-}
-__device__ __forceinline__ double dpp_quad(double v, int ctrl) {
-  const long long b = __double_as_longlong(v);
-  int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
-  if (ctrl == 0xB1) {
-    lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);
-    hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
-  } else {
-    lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);
-    hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
-  }
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double quad_sum(double v) {
-  const double t = v + dpp_quad(v, 0xB1);
-  return t + dpp_quad(t, 0x4E);
-}
 
 // A value every lane of the wave holds, moved to a scalar register.
 __device__ __forceinline__ float uniform(float v) {
@@ -2059,106 +2039,119 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
     for (int q = 0; q < 8; ++q) mpart[(long long)blockIdx.x * 8 + q] = tot[q];
 }
 
-// 2D transpose of the transfer for one step: one DPP quad per design point,
-// lane r owning the r-th row of its 4 x 4 analysis taps (buffer loads, taps
-// outside the box read 0); lane 0 accumulates kappa_ref-bar and the point's
-// motion terms.  A block covers MAPADJ_PTS2 runs of 64 consecutive points and
-// writes one fixed-order set of motion partials.
+// 2D transpose of the transfer for one step.  A block takes a 16 x 16 patch
+// of design points, one thread each.  The 4 x 4 taps of the whole patch lie
+// in a 28 x 28 window of the analysis grid (the rotated patch spans at most
+// 15 sqrt(2) nodes, the taps 4 more), so the window's three body-adjoint
+// fields are staged in LDS with loads along x and every thread reads its
+// taps from there.  Each point's sums weighted by W, dW/dx and dW/dy give
+// dJ/dkappa_ref and its motion terms; the block writes one fixed-order set
+// of motion partials.
+constexpr int MA2_P = 16, MA2_W = 28;
 template <class R>
 __device__ __forceinline__ void mapadj_block(const Geo& g, const R* kref, Mot m, Box box,
                                              const StepInfo* si, const R* bkbar, const R* bubar,
                                              double* kref_bar, int overwrite, double* mpart,
                                              int bid) {
   apply_step(box, m, si);
-  static_assert(MAPADJ_TPC == 4, "a design point is one DPP quad");
-  constexpr int PPR = MAPADJ_THREADS / MAPADJ_TPC;  // points per run
-  constexpr unsigned BAD = 0x80000000u;  // byte offset past every buffer: loads return 0
+  static_assert(MAPADJ_THREADS == MA2_P * MA2_P, "one design point per thread");
+  constexpr int WN = MA2_W * MA2_W;
+  __shared__ R win[3][WN];
+  const int npx = (g.D[0] + MA2_P - 1) / MA2_P;
+  const int px = bid % npx, py = bid / npx;
+  const int e0 = px * MA2_P + (int)threadIdx.x % MA2_P, e1 = py * MA2_P + (int)threadIdx.x / MA2_P;
+  const bool active = e0 < g.D[0] && e1 < g.D[1];
+  const long long k = active ? e0 + (long long)g.D[0] * e1 : 0;
+  const double r0 = e0 - g.xiG[0], r1 = e1 - g.xiG[1];
+  const double X0 = m.c * r0 - m.s * r1 + m.xg[0];
+  const double X1 = m.s * r0 + m.c * r1 + m.xg[1];
+  // window origin: the rotated positions are linear in (e0, e1), so their
+  // least floor is at a corner; one node of margin covers rounding
+  int wx0, wy0;
+  {
+    double mx = 1e300, my = 1e300;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double q0 = px * MA2_P + (MA2_P - 1) * (c & 1) - g.xiG[0];
+      const double q1 = py * MA2_P + (MA2_P - 1) * (c >> 1) - g.xiG[1];
+      mx = fmin(mx, m.c * q0 - m.s * q1 + m.xg[0]);
+      my = fmin(my, m.s * q0 + m.c * q1 + m.xg[1]);
+    }
+    wx0 = (int)floor(mx) - 2;
+    wy0 = (int)floor(my) - 2;
+  }
+  // stage the window: nodes outside the box or on a wall read 0
   const int bvol = (int)box.vol;
-  const int nrec = bvol * (int)sizeof(R);
-  const __amdgpu_buffer_rsrc_t rk = __builtin_amdgcn_make_buffer_rsrc((void*)bkbar, 0, nrec, 0x00020000);
-  const __amdgpu_buffer_rsrc_t ru0 = __builtin_amdgcn_make_buffer_rsrc((void*)bubar, 0, nrec, 0x00020000);
-  const __amdgpu_buffer_rsrc_t ru1 =
-      __builtin_amdgcn_make_buffer_rsrc((void*)(bubar + bvol), 0, nrec, 0x00020000);
-  auto bload = [](__amdgpu_buffer_rsrc_t r, unsigned off) -> R {
-    if constexpr (sizeof(R) == 4)
-      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
-    else
-      return __builtin_bit_cast(R, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
-  };
-  const int row = threadIdx.x % MAPADJ_TPC;
+  for (int n = threadIdx.x; n < WN; n += MAPADJ_THREADS) {
+    int vx = wx0 + n % MA2_W, vy = wy0 + n / MA2_W;
+    R v0 = R(0), v1 = R(0), v2 = R(0);
+    if (wrap_axis(g, 0, vx) && wrap_axis(g, 1, vy) && !on_wall(g, 0, vx) && !on_wall(g, 1, vy)) {
+      int b0 = vx - box.lo[0], b1 = vy - box.lo[1];
+      if (g.bc[0] == 0) { b0 %= g.n[0]; if (b0 < 0) b0 += g.n[0]; }
+      if (g.bc[1] == 0) { b1 %= g.n[1]; if (b1 < 0) b1 += g.n[1]; }
+      if (b0 >= 0 && b0 < box.ext[0] && b1 >= 0 && b1 < box.ext[1]) {
+        const int bi = b0 + box.sx * b1;
+        v0 = bkbar[bi];
+        v1 = bubar[bi];
+        v2 = bubar[bvol + bi];
+      }
+    }
+    win[0][n] = v0;
+    win[1][n] = v1;
+    win[2][n] = v2;
+  }
+  __syncthreads();
+  R wx[4], dx[4], wy[4], dy[4];
+  const int lx = (int)floor(X0) - 1 - wx0, ly = (int)floor(X1) - 1 - wy0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const R rx = (R)((double)(lx + wx0 + q) - X0), ry = (R)((double)(ly + wy0 + q) - X1);
+    // points past the design grid weight their taps by 0
+    wx[q] = active ? wk(rx) : R(0);
+    dx[q] = active ? wkd(rx) : R(0);
+    wy[q] = wk(ry);
+    dy[q] = wkd(ry);
+  }
+  // (lx, ly) lie in [0, MA2_W - 4] by the choice of the window; clamped only
+  // so that no thread can address outside it
+  const int c0 = min(max(lx, 0), MA2_W - 4) + MA2_W * min(max(ly, 0), MA2_W - 4);
+  R P[9];  // (W, dW/dx, dW/dy) x (k-bar, u-bar_x, u-bar_y)
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    R S = R(0), Dx = R(0), Dy = R(0);
+#pragma unroll
+    for (int cy = 0; cy < 4; ++cy) {
+      R s = R(0), d = R(0);
+#pragma unroll
+      for (int cx = 0; cx < 4; ++cx) {
+        const R v = win[q][c0 + cy * MA2_W + cx];
+        s += wx[cx] * v;
+        d += dx[cx] * v;
+      }
+      S += wy[cy] * s;
+      Dx += wy[cy] * d;
+      Dy += dy[cy] * s;
+    }
+    P[q] = S;
+    P[3 + q] = Dx;
+    P[6 + q] = Dy;
+  }
   double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int run = 0; run < MAPADJ_PTS2; ++run) {
-    const long long k = ((long long)bid * MAPADJ_PTS2 + run) * PPR + threadIdx.x / MAPADJ_TPC;
-    const bool active = k < g.Mtot;
-    const long long kk = active ? k : 0;
-    const int e0 = (int)(kk % g.D[0]), e1 = (int)(kk / g.D[0]);
-    const double r0 = e0 - g.xiG[0], r1 = e1 - g.xiG[1];
-    const double X0 = m.c * r0 - m.s * r1 + m.xg[0];
-    const double X1 = m.s * r0 + m.c * r1 + m.xg[1];
-    R wx[4], dx[4];
-    unsigned ox[4];
-    const int lx = (int)floor(X0) - 1;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int vx = lx + q;
-      const R rx = (R)((double)vx - X0);
-      wx[q] = wk(rx);
-      dx[q] = wkd(rx);
-      unsigned o = BAD;
-      if (active && wrap_axis(g, 0, vx) && !on_wall(g, 0, vx)) {
-        int bb = vx - box.lo[0];
-        if (g.bc[0] == 0) { bb %= g.n[0]; if (bb < 0) bb += g.n[0]; }
-        if (bb >= 0 && bb < box.ext[0]) o = (unsigned)bb * sizeof(R);
-      }
-      ox[q] = o;
-    }
-    R wy, dy;
-    unsigned base = BAD;
-    {
-      int vy = (int)floor(X1) - 1 + row;
-      const R ry = (R)((double)vy - X1);
-      wy = wk(ry);
-      dy = wkd(ry);
-      if (active && wrap_axis(g, 1, vy) && !on_wall(g, 1, vy)) {
-        int bb = vy - box.lo[1];
-        if (g.bc[1] == 0) { bb %= g.n[1]; if (bb < 0) bb += g.n[1]; }
-        if (bb >= 0 && bb < box.ext[1]) base = (unsigned)(box.sx * bb) * sizeof(R);
-      }
-    }
-    R S[3] = {R(0), R(0), R(0)}, D[3] = {R(0), R(0), R(0)};
-#pragma unroll
-    for (int cx = 0; cx < 4; ++cx) {
-      const unsigned off = (base == BAD || ox[cx] == BAD) ? BAD : base + ox[cx];
-      const R v[3] = {bload(rk, off), bload(ru0, off), bload(ru1, off)};
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        S[q] += wx[cx] * v[q];
-        D[q] += dx[cx] * v[q];
-      }
-    }
-    R P[9];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      P[q] = quad_sum(wy * S[q]);      // W k-bar, W u-bar
-      P[3 + q] = quad_sum(wy * D[q]);  // dW/dx ...
-      P[6 + q] = quad_sum(dy * S[q]);  // dW/dy ...
-    }
-    if (active && row == 0) {
-      const double kr = (double)kref[k];
-      const double U0 = m.om * (-m.s * r0 - m.c * r1) + m.ug[0];
-      const double U1 = m.om * (m.c * r0 - m.s * r1) + m.ug[1];
-      const double Xb0 = -(kr * P[3] + U0 * P[4] + U1 * P[5]);
-      const double Xb1 = -(kr * P[6] + U0 * P[7] + U1 * P[8]);
-      kref_bar[k] = (overwrite ? 0.0 : kref_bar[k]) + (double)P[0];
-      const double dX0 = -m.s * r0 - m.c * r1, dX1 = m.c * r0 - m.s * r1;                      // R' r
-      const double dU0 = m.om * (-m.c * r0 + m.s * r1), dU1 = m.om * (-m.s * r0 - m.c * r1);  // om R'' r
-      part[0] += Xb0;
-      part[1] += Xb1;
-      part[3] += P[1];
-      part[4] += P[2];
-      part[6] += Xb0 * dX0 + Xb1 * dX1 + (double)P[1] * dU0 + (double)P[2] * dU1;
-      part[7] += (double)P[1] * dX0 + (double)P[2] * dX1;
-    }
+  if (active) {
+    const double kr = (double)kref[k];
+    const double U0 = m.om * (-m.s * r0 - m.c * r1) + m.ug[0];
+    const double U1 = m.om * (m.c * r0 - m.s * r1) + m.ug[1];
+    const double Xb0 = -(kr * P[3] + U0 * P[4] + U1 * P[5]);
+    const double Xb1 = -(kr * P[6] + U0 * P[7] + U1 * P[8]);
+    kref_bar[k] = (overwrite ? 0.0 : kref_bar[k]) + (double)P[0];
+    const double dX0 = -m.s * r0 - m.c * r1, dX1 = m.c * r0 - m.s * r1;                      // R' r
+    const double dU0 = m.om * (-m.c * r0 + m.s * r1), dU1 = m.om * (-m.s * r0 - m.c * r1);  // om R'' r
+    part[0] = Xb0;
+    part[1] = Xb1;
+    part[3] = P[1];
+    part[4] = P[2];
+    part[6] = Xb0 * dX0 + Xb1 * dX1 + (double)P[1] * dU0 + (double)P[2] * dU1;
+    part[7] = (double)P[1] * dX0 + (double)P[2] * dX1;
   }
   double tot[8];
   block_sum<8, MAPADJ_THREADS>(part, tot);
