@@ -155,7 +155,7 @@ struct lks_plan {
   int mrow;         // block slots per step of the motion partials: map transpose, then J2
   Box bmax;     // strides, volume and launch extents of the body buffers
   // workspace offsets (bytes)
-  size_t o_mot, o_tab, o_info, o_kref, o_flags, o_J3, o_seed, o_opart, o_ck, o_pp, o_tape,
+  size_t o_mot, o_tab, o_info, o_kref, o_flags, o_J3, o_seed, o_opart, o_ck, o_pp, o_tape, o_tape2,
       o_body, o_btape, o_badj, o_lam, o_xadj, o_acarry, o_inp, o_cmot, o_badjt, o_kpart, o_krefbar, o_mpart, o_mbar, o_den, o_kz, o_geo, o_j2acc, o_j2seed, total;
   int first_lazy = 1;
   void* fwd_ws = nullptr;
@@ -164,12 +164,21 @@ struct lks_plan {
   GraphCache gfwd, gadj, gbatch;
   std::vector<const void*> bkey;       // pointer tables the batch graph was captured for
   std::vector<hipStream_t> bstreams;   // capture branches of the batch graph
+  // 2D reverse sweep: the next segment's recompute on a side stream, into the
+  // second of two state tapes (tsel picks the tape tape_slot() addresses)
+  bool ovl = false;
+  int tsel = 0;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ~lks_plan() {
     gfwd.reset();
     gadj.reset();
     gbatch.reset();
     for (hipStream_t b : bstreams) (void)hipStreamDestroy(b);
     if (cap) (void)hipStreamDestroy(cap);
+    if (side) (void)hipStreamDestroy(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
   }
 };
 
@@ -300,7 +309,7 @@ const StepInfo* tab(lks_plan* P, void* ws, int n) {
 void* ck_slot(lks_plan* P, void* ws, int j) { return wsp(ws, P->o_ck) + (size_t)j * P->S * P->es; }
 void* pp_slot(lks_plan* P, void* ws, int j) { return wsp(ws, P->o_pp) + (size_t)j * P->S * P->es; }
 void* tape_slot(lks_plan* P, void* ws, int j) {
-  return wsp(ws, P->o_tape) + (size_t)j * P->S * P->es;
+  return wsp(ws, P->tsel ? P->o_tape2 : P->o_tape) + (size_t)j * P->S * P->es;
 }
 void* lam_slot(lks_plan* P, void* ws, int j) { return wsp(ws, P->o_lam) + (size_t)j * P->S * P->es; }
 void* xadj_slot(lks_plan* P, void* ws, int j) {
@@ -538,21 +547,54 @@ MapAdjArgs mapadj_args(lks_plan* P, void* ws, int n) {
   return m;
 }
 
-lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
+// fork_ok: the loop may fork a side stream from `s`.  Off where `s` is itself
+// a branch forked inside a capture (lks_batch_run): a second-level fork under
+// capture has crashed the HIP runtime on the host.
+lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s, bool fork_ok = true) {
   const int nt = P->g.nt, K = P->K;
   int cur = 0;
-  for (int sg = P->nck - 1; sg >= 0; --sg) {
+  const bool ovl = P->ovl && fork_ok;
+  P->tsel = 0;
+  // recompute segment sg into the tape: tape[n - nb] holds state n (with one
+  // segment the forward march has written it already)
+  auto recompute = [&](int sg, hipStream_t st) -> lks_status {
     const int nb = sg * K + 1, ne = std::min((sg + 1) * K, nt);
-    // recompute the segment into the tape: tape[n - nb] holds state n (with
-    // one segment the forward march has written it already)
-    for (int n = nb; n <= ne && !P->store_all; ++n) {
+    for (int n = nb; n <= ne; ++n) {
       const void* in = (n == nb) ? ck_slot(P, ws, sg) : tape_slot(P, ws, n - nb - 1);
       const int lazy = (n == 1) ? P->first_lazy : 1;
       void* body = rev_body(P, ws, n, sg);
       if (!P->full_btape)
-        if (lks_status e = map_step(P, ws, n, body, s)) return e;
-      if (lks_status e = fwd_step(P, ws, n, in, tape_slot(P, ws, n - nb), body, lazy, 0, s))
+        if (lks_status e = map_step(P, ws, n, body, st)) return e;
+      if (lks_status e = fwd_step(P, ws, n, in, tape_slot(P, ws, n - nb), body, lazy, 0, st))
         return e;
+    }
+    return LKS_OK;
+  };
+  // 2D launches are latency-bound and leave most of the GPU idle: the
+  // recompute of segment sg - 1 (into the other tape) then runs on a side
+  // stream beside the reverse steps of segment sg, forked from and joined to
+  // the loop's stream (graph branches under capture)
+  if (ovl) {
+    if (!P->side) HIPCHK(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
+    if (!P->ev_fork) HIPCHK(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
+    if (!P->ev_join) HIPCHK(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
+    P->tsel = (P->nck - 1) & 1;
+    if (lks_status e = recompute(P->nck - 1, s)) return e;
+  }
+  for (int sg = P->nck - 1; sg >= 0; --sg) {
+    const int nb = sg * K + 1, ne = std::min((sg + 1) * K, nt);
+    const bool fork = ovl && sg > 0;
+    if (ovl) {
+      if (fork) {
+        HIPCHK(hipEventRecord(P->ev_fork, s));
+        HIPCHK(hipStreamWaitEvent(P->side, P->ev_fork, 0));
+        P->tsel = (sg - 1) & 1;
+        if (lks_status e = recompute(sg - 1, P->side)) return e;
+        HIPCHK(hipEventRecord(P->ev_join, P->side));
+      }
+      P->tsel = sg & 1;
+    } else if (!P->store_all) {
+      if (lks_status e = recompute(sg, s)) return e;
     }
     // J2: the segment's seeds on the fluid velocity in one launch (they
     // depend on the motion and kappa_ref only)
@@ -606,7 +648,9 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s) {
       HIPCHK(launch_kref_accum(P->g.Mtot, cnt, kp, (double*)wsp(ws, P->o_krefbar), s));
      }
     }
+    if (fork) HIPCHK(hipStreamWaitEvent(s, P->ev_join, 0));
   }
+  P->tsel = 0;
   return LKS_OK;
 }
 
@@ -745,6 +789,10 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   P->o_ck = take((size_t)P->nck * Sb);
   P->o_pp = take(2 * Sb);
   P->o_tape = take((size_t)P->K * Sb);
+  // 2D (latency-bound launches) with a body slot per step and more than one
+  // segment: a second tape lets the next segment's recompute run beside the
+  // reverse steps (set below, once the body-tape mode is known)
+  P->o_tape2 = 0;
   const size_t full_tape = (size_t)g.nt * body_bytes(P);
   // one segment (K = nt): the march keeps every state in the tape, and the
   // segment's body tape is the full one
@@ -753,6 +801,8 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
                   (prob->body_tape == 0 && full_tape <= LKS_BODY_TAPE_AUTO_MAX);
   P->o_body = take(P->full_btape ? 0 : body_bytes(P));
   P->o_btape = take(P->full_btape ? full_tape : (size_t)P->K * body_bytes(P));
+  P->ovl = g.d == 2 && !P->store_all && P->full_btape && P->nck > 1;
+  if (P->ovl) P->o_tape2 = take((size_t)P->K * Sb);
   P->o_badj = take(body_bytes(P));
   // the reverse sweep keeps the body adjoint of each step of a chunk (at most
   // kmt steps) and transposes the chunk's maps in one launch, each step's
@@ -1280,7 +1330,7 @@ lks_status lks_batch_run(int32_t count, lks_plan* const* plans, const double* co
     if (lks_status e = forward_loop(P, ws, st)) return e;
     HIPCHK(hipMemcpyAsync(J_out[k], wsp(ws, P->o_J3), 3 * sizeof(double),
                           hipMemcpyDeviceToDevice, st));
-    if (lks_status e = adjoint_loop(P, ws, st)) return e;
+    if (lks_status e = adjoint_loop(P, ws, st, false)) return e;
     return sens(P, gamma[k], ws, dJ_dgamma[k], dJ_dchi[k], dJ_dpsi[k], st);
   };
   key.push_back((const void*)(intptr_t)(shared ? 1 : 0));
