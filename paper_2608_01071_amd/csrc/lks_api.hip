@@ -156,7 +156,8 @@ struct lks_plan {
   Box bmax;     // strides, volume and launch extents of the body buffers
   // workspace offsets (bytes)
   size_t o_mot, o_tab, o_info, o_kref, o_flags, o_J3, o_seed, o_opart, o_ck, o_pp, o_tape, o_tape2,
-      o_body, o_btape, o_badj, o_lam, o_xadj, o_acarry, o_inp, o_cmot, o_badjt, o_kpart, o_krefbar, o_mpart, o_mbar, o_den, o_kz, o_geo, o_j2acc, o_j2seed, total;
+      o_body, o_btape, o_badj, o_lam, o_xadj, o_acarry, o_inp, o_cmot, o_badjt, o_kpart, o_badjt2,
+      o_kpart2, o_krefbar, o_mpart, o_mbar, o_den, o_kz, o_geo, o_j2acc, o_j2seed, total;
   int first_lazy = 1;
   void* fwd_ws = nullptr;
   bool use_graphs = true;
@@ -170,6 +171,13 @@ struct lks_plan {
   int tsel = 0;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // 2D J1: each chunk's map transposes on a second side stream beside the
+  // next chunk's reverse steps, the body-adjoint and kappa_ref-partial
+  // buffers doubled (bsel picks the pair)
+  bool ovt = false;
+  int bsel = 0;
+  hipStream_t side2 = nullptr;
+  hipEvent_t ev_chunk = nullptr, ev_tr[2] = {nullptr, nullptr};
   ~lks_plan() {
     gfwd.reset();
     gadj.reset();
@@ -179,6 +187,10 @@ struct lks_plan {
     if (side) (void)hipStreamDestroy(side);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side2) (void)hipStreamDestroy(side2);
+    if (ev_chunk) (void)hipEventDestroy(ev_chunk);
+    for (hipEvent_t e : ev_tr)
+      if (e) (void)hipEventDestroy(e);
   }
 };
 
@@ -317,7 +329,12 @@ void* xadj_slot(lks_plan* P, void* ws, int j) {
 }
 size_t body_bytes(const lks_plan* P) { return (size_t)(1 + P->g.d) * P->bmax.vol * P->es; }
 // Body adjoint (dJ/dkappa, dJ/du_s on the box) of segment step j.
-void* badj_slot(lks_plan* P, void* ws, int j) { return wsp(ws, P->o_badjt) + (size_t)j * body_bytes(P); }
+void* badj_slot(lks_plan* P, void* ws, int j) {
+  return wsp(ws, P->bsel ? P->o_badjt2 : P->o_badjt) + (size_t)j * body_bytes(P);
+}
+double* kpart_buf(lks_plan* P, void* ws) {
+  return (double*)wsp(ws, P->bsel ? P->o_kpart2 : P->o_kpart);
+}
 void* btape_slot(lks_plan* P, void* ws, int j) {
   return wsp(ws, P->o_btape) + (size_t)j * body_bytes(P);
 }
@@ -554,7 +571,16 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s, bool fork_ok = tru
   const int nt = P->g.nt, K = P->K;
   int cur = 0;
   const bool ovl = P->ovl && fork_ok;
+  const bool ovt = P->ovt && fork_ok;
   P->tsel = 0;
+  P->bsel = 0;
+  int chunk = 0;  // chunks so far (their parity picks the transposes' buffers)
+  if (ovt) {
+    if (!P->side2) HIPCHK(hipStreamCreateWithFlags(&P->side2, hipStreamNonBlocking));
+    if (!P->ev_chunk) HIPCHK(hipEventCreateWithFlags(&P->ev_chunk, hipEventDisableTiming));
+    for (hipEvent_t& e : P->ev_tr)
+      if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
   // recompute segment sg into the tape: tape[n - nb] holds state n (with one
   // segment the forward march has written it already)
   auto recompute = [&](int sg, hipStream_t st) -> lks_status {
@@ -609,8 +635,13 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s, bool fork_ok = tru
     // adjoint in a slot of its own; then the chunk's map transposes in one
     // launch (one step alone fills the GPU poorly) and its kappa_ref
     // partials summed, latest step first, as a transpose per step would
-    for (int chi = ne; chi >= nb; chi -= P->kmt) {
+    for (int chi = ne; chi >= nb; chi -= P->kmt, ++chunk) {
      const int clo = std::max(nb, chi - P->kmt + 1);
+     if (ovt) {
+       // the buffers of two chunks back are free once their transposes ran
+       P->bsel = chunk & 1;
+       if (chunk >= 2) HIPCHK(hipStreamWaitEvent(s, P->ev_tr[chunk & 1], 0));
+     }
      for (int n = chi; n >= clo; --n) {
       AdjArgs a = adj_args(P, ws, n, sg, cur);
       a.bkbar = badj_slot(P, ws, n - clo);
@@ -627,30 +658,43 @@ lks_status adjoint_loop(lks_plan* P, void* ws, hipStream_t s, bool fork_ok = tru
       cur = 1 - cur;
      }
      {
+      // with ovt on the second side stream, in chunk order (the kappa_ref
+      // partials are summed in the same order either way)
+      hipStream_t ts = s;
+      if (ovt) {
+        HIPCHK(hipEventRecord(P->ev_chunk, s));
+        HIPCHK(hipStreamWaitEvent(P->side2, P->ev_chunk, 0));
+        ts = P->side2;
+      }
       const int cnt = chi - clo + 1;
       const MapAdjArgs m = mapadj_args(P, ws, clo);
-      double* kp = (double*)wsp(ws, P->o_kpart);
+      double* kp = kpart_buf(P, ws);
       void* b0 = badj_slot(P, ws, 0);
       const StepBatch sb{(long long)(body_bytes(P) / P->es), P->g.Mtot,
                          (long long)P->mrow * P->g.mw};
       {
-        Scope sc("map_adj", s, true);
+        Scope sc("map_adj", ts, true);
         HIPCHK(launch_map_adjoint(P->g, P->prec, m.kref, nullptr, m.si, m.box, b0,
-                                  (char*)b0 + P->bmax.vol * P->es, kp, 1, m.mpart, s, cnt, sb));
+                                  (char*)b0 + P->bmax.vol * P->es, kp, 1, m.mpart, ts, cnt, sb));
       }
       // J2's direct terms join the same rows, in their own block slots
       if (P->j2) {
-        Scope sc("j2_adj", s, true);
+        Scope sc("j2_adj", ts, true);
         HIPCHK(launch_j2_adjoint(P->g, P->prec, m.kref, m.si, tape_slot(P, ws, clo - nb), P->S,
                                  (const double*)wsp(ws, P->o_seed), kp, P->g.Mtot, m.mpart,
-                                 (long long)P->mrow * P->g.mw, P->nblk_map, cnt, s));
+                                 (long long)P->mrow * P->g.mw, P->nblk_map, cnt, ts));
       }
-      HIPCHK(launch_kref_accum(P->g.Mtot, cnt, kp, (double*)wsp(ws, P->o_krefbar), s));
+      HIPCHK(launch_kref_accum(P->g.Mtot, cnt, kp, (double*)wsp(ws, P->o_krefbar), ts));
+      if (ovt) HIPCHK(hipEventRecord(P->ev_tr[chunk & 1], P->side2));
      }
     }
     if (fork) HIPCHK(hipStreamWaitEvent(s, P->ev_join, 0));
   }
+  // the last transposes join the loop's stream (the side stream runs them in
+  // order, so the last event covers all)
+  if (ovt && chunk > 0) HIPCHK(hipStreamWaitEvent(s, P->ev_tr[(chunk - 1) & 1], 0));
   P->tsel = 0;
+  P->bsel = 0;
   return LKS_OK;
 }
 
@@ -809,6 +853,9 @@ lks_status lks_plan_create(const lks_problem* prob, lks_plan** out, size_t* work
   // kappa_ref partials apart
   P->o_badjt = take((size_t)P->kmt * body_bytes(P));
   P->o_kpart = take((size_t)P->kmt * g.Mtot * sizeof(double));
+  P->ovt = P->ovl && !P->j2;
+  P->o_badjt2 = P->ovt ? take((size_t)P->kmt * body_bytes(P)) : 0;
+  P->o_kpart2 = P->ovt ? take((size_t)P->kmt * g.Mtot * sizeof(double)) : 0;
   P->o_lam = take(2 * Sb);
   P->alks = prob->scheme == LKS_ADJ_ALKS;
   // ALKS: raw first-moment part of the adjoint velocity, two slots like lambda
