@@ -270,6 +270,10 @@ def d2q9_workload(name: str):
     out, (J32, g32) = pass_rate(p, g, c, s, seed)
     out["workload"] = (f"D2Q9 {p.n[0]}^2, {p.m[0]}^2 design, {p.nt} steps, K = {p.ckpt_k}, "
                        "FP32 state / FP64 sums")
+    # one segment (K = nt): every state kept in HBM, no recompute
+    o1, _ = pass_rate(p.replace(ckpt_k=p.nt), g, c, s, seed)
+    out["one_segment"] = {k: o1[k] for k in ("workspace_gib", "forward_mlups", "mlups",
+                                              "ms_per_pass")}
     # dominant kernel of one event-timed pass
     plan = lks.Plan(p)
     run_pass(plan, g, c, s, seed)
