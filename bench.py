@@ -175,11 +175,13 @@ def oar_j2(nt: int = 4000):
     for key, q in (("j2", p), ("j1_same_shape", p.replace(objective=0))):
         plan = lks.Plan(q)
         run_pass(plan, g, c, s, seed)  # warm-up (graph capture)
-        J3, _, tf, ta = run_pass(plan, g, c, s, seed)
+        J3, grads, tf, ta = run_pass(plan, g, c, s, seed)
         out[key] = {"mlups": round(p.N * nt / (tf + ta) / 1e6, 1),
                     "ms_per_pass": round((tf + ta) * 1e3, 2)}
         if key == "j2":
             out[key]["J_FL_FD"] = [float(v) for v in J3.cpu().numpy()]
+            J32 = J3.cpu().numpy().copy()
+            g32 = {k: grads[k].cpu().numpy().copy() for k in ("dgamma", "dchi", "dpsi")}
             lks.profile_enable(True)
             run_pass(plan, g, c, s, seed)
             torch.cuda.synchronize()
@@ -188,6 +190,20 @@ def oar_j2(nt: int = 4000):
             out["us_per_step"] = {k: round(v[0] * 1e3 / nt, 2) for k, v in prof.items()}
         del plan
         torch.cuda.empty_cache()
+    # FP32 state against the FP64 plain form over the whole horizon: J2 is a
+    # difference of forces about a thousand times its size, so the FP32
+    # rounding shows at the forces' scale
+    import numpy as np
+    plan = lks.Plan(p.replace(precision=1))
+    J64, g64, _, _ = run_pass(plan, g, c, s, seed)
+    J64 = J64.cpu().numpy()
+    rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    out["fp32_err"] = {"J2": float(abs(J32[0] - J64[0]) / abs(J64[0])),
+                       "F_L": float(abs(J32[1] - J64[1]) / abs(J64[1])),
+                       "F_D": float(abs(J32[2] - J64[2]) / abs(J64[2])),
+                       **{k: rel(g32[k], g64[k].cpu().numpy()) for k in ("dgamma", "dchi", "dpsi")}}
+    del plan
+    torch.cuda.empty_cache()
     return out
 
 
