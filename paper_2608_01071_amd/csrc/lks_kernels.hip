@@ -837,12 +837,18 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
   Buf bA, bB;
   // z0 - 1 >= -1, so z0 + 2 keeps the residues nonnegative
   const int r0 = (z0 + 2) % 3;  // slot of plane z0 - 1
-  fetch(z0 - 2, bA);
-  commit(r0 == 0 ? 2 : r0 - 1, bA);
-  fetch(z0 - 1, bA);
-  commit(r0, bA);
-  fetch(z0, bA);
-  fetch(z0 + 1, bB);
+  {
+    // the four planes of the prologue are requested together (one memory
+    // round trip before the march, not three); the body fields of t0 and t1
+    // feed no output and their loads are dropped
+    Buf t0, t1;
+    fetch(z0 - 2, t0);
+    fetch(z0 - 1, t1);
+    fetch(z0, bA);
+    fetch(z0 + 1, bB);
+    commit(r0 == 0 ? 2 : r0 - 1, t0);
+    commit(r0, t1);
+  }
   // iterations z0-1 .. z1, two per trip so each buffer stays in fixed
   // registers (and every trip ends with the loads of the other buffer)
   int zf = z0 - 1, rs = r0;

@@ -763,3 +763,46 @@ def test_gpu_gradient_against_central_differences(d):
             fd = (J(gamma, chi, pp) - J(gamma, chi, pm)) / (2 * h)
             ad = dp[t]
         assert abs(fd - ad) < 1e-6 * max(abs(fd), 1e-2 * cmax), (t, comp, fd, ad)
+
+
+def test_c1_gradient_against_central_differences():
+    """The paper's verification (Appendix A) on the 64x64 / 200-step workload
+    itself, FP64 on the GPU: central differences of J (h = 1e-6) on 8 random
+    design entries and 8 random motion entries (x, y, theta at random steps)
+    agree with lks_adjoint's gradient to 1e-6, with checkpoints every 50 steps."""
+    lks = lk()
+    p, gamma, chi, psi = W.c1(precision=1)
+    gamma = gamma.ravel().copy()
+    plan = lks.Plan(p.replace(ckpt_k=50))
+    plan.forward(gamma, chi, psi)
+    g = plan.adjoint(gamma, chi, psi)
+    dg, dc, dp = cpu(g["dgamma"]), cpu(g["dchi"]), cpu(g["dpsi"])
+    J = lambda ga, ch, ps: cpu(plan.forward(ga, ch, ps)[0])[0]
+    rng = np.random.default_rng(2026)
+    h = 1e-6
+    gmax = np.abs(dg).max()
+    assert gmax > 0
+    for j in rng.choice(p.M, 8, replace=False):
+        gp, gm = gamma.copy(), gamma.copy()
+        gp[j] += h
+        gm[j] -= h
+        fd = (J(gp, chi, psi) - J(gm, chi, psi)) / (2 * h)
+        assert abs(fd - dg[j]) < 1e-6 * max(abs(fd), 1e-2 * gmax), (j, fd, dg[j])
+    cmax = max(np.abs(dc).max(), np.abs(dp).max())
+    assert cmax > 0
+    for j in range(8):
+        t = int(rng.integers(p.nt))
+        comp = (0, 1, 3)[j % 3]
+        if comp < 3:
+            cp, cm = chi.copy(), chi.copy()
+            cp[t, comp] += h
+            cm[t, comp] -= h
+            fd = (J(gamma, cp, psi) - J(gamma, cm, psi)) / (2 * h)
+            ad = dc[t, comp]
+        else:
+            pp, pm = psi.copy(), psi.copy()
+            pp[t] += h
+            pm[t] -= h
+            fd = (J(gamma, chi, pp) - J(gamma, chi, pm)) / (2 * h)
+            ad = dp[t]
+        assert abs(fd - ad) < 1e-6 * max(abs(fd), 1e-2 * cmax), (t, comp, fd, ad)
