@@ -363,20 +363,26 @@ __device__ __forceinline__ void feq15(R p, R ux, R uy, R uz, R Sxx, R Syy, R Szz
   using C = EqC<R>;
   const R base = R(3) * p - R(1.5) * (ux * ux + uy * uy + uz * uz);
   f[0] = C::w0_15 * base;
-  auto pair = [&](int i, R w, R c3w, R cu, R cSc) {
-    R com = w * (base + R(4.5) * cu * cu + A * cSc);
-    R od = c3w * cu;
-    f[i] = com + od;
-    f[i + 1] = com - od;
+  // w (base + 4.5 (c.u)^2 + A cSc) +- 3 w c.u, with w base and w A formed
+  // once per weight class (4.5 w is 1/2 on the axes, 1/16 on the diagonals)
+  const R wab = C::wa * base, wdb = C::wd_15 * base;
+  const R waA = C::wa * A, wdA = C::wd_15 * A;
+  auto pair = [&](int i, R wb, R w45, R wA, R c3w, R cu, R cSc) {
+    const R com = fma(wA, cSc, fma(w45 * cu, cu, wb));
+    f[i] = fma(c3w, cu, com);
+    f[i + 1] = fma(-c3w, cu, com);
   };
+  pair(1, wab, R(0.5), waA, C::ca, ux, Sxx);
+  pair(3, wab, R(0.5), waA, C::ca, uy, Syy);
+  pair(5, wab, R(0.5), waA, C::ca, uz, Szz);
+  // the four diagonal pairs share partial sums of c.u and c S c
   const R tr = Sxx + Syy + Szz;
-  pair(1, C::wa, C::ca, ux, Sxx);
-  pair(3, C::wa, C::ca, uy, Syy);
-  pair(5, C::wa, C::ca, uz, Szz);
-  pair(7, C::wd_15, C::cd_15, ux + uy + uz, tr + (Txy + Txz + Tyz));
-  pair(9, C::wd_15, C::cd_15, -ux + uy + uz, tr + (-Txy - Txz + Tyz));
-  pair(11, C::wd_15, C::cd_15, ux - uy + uz, tr + (-Txy + Txz - Tyz));
-  pair(13, C::wd_15, C::cd_15, ux + uy - uz, tr + (Txy - Txz - Tyz));
+  const R a = uy + uz, b = uy - uz;
+  const R s1 = tr + Tyz, s2 = tr - Tyz, d1 = Txy + Txz, d2 = Txy - Txz;
+  pair(7, wdb, R(0.0625), wdA, C::cd_15, ux + a, s1 + d1);    // (1,1,1)
+  pair(9, wdb, R(0.0625), wdA, C::cd_15, a - ux, s1 - d1);    // (-1,1,1)
+  pair(11, wdb, R(0.0625), wdA, C::cd_15, ux - b, s2 - d2);   // (1,-1,1)
+  pair(13, wdb, R(0.0625), wdA, C::cd_15, ux + b, s2 + d2);   // (1,1,-1)
 }
 
 // Block-wide fixed-order sum of K doubles per thread into out[0..K) (thread 0).
@@ -1756,6 +1762,30 @@ __global__ __launch_bounds__(256) void k_map3d(Geo g, const R* kt, int lz, Mot m
       ost[3][zz][hw] = wall ? R(0) : zs * vz;
     }
     __syncthreads();
+    if (!full_grid) {
+      // thread: column c of the block (fixed), staging rows r + 32 t; eight
+      // lanes in a row store eight consecutive x of one z level
+      const int c = threadIdx.x & 7, r = threadIdx.x >> 3;
+      const int cid = blockIdx.x * 8 + c;
+      if (cid < ncol) {
+        const int ic = cid % box.ext[0], jc = cid / box.ext[0];
+        const unsigned vb = (unsigned)box.vol * sizeof(R);
+        const __amdgpu_buffer_rsrc_t rbk = brsrc(bk, vb), rbu = brsrc(bu, 3u * vb);
+        const unsigned plane = (unsigned)(box.sx * box.sy) * sizeof(R);
+        const unsigned cb = (unsigned)(ic + box.sx * jc) * sizeof(R);
+#pragma unroll
+        for (int t = 0; t < ZPL; ++t) {
+          const int zz = r + 32 * t, kk = zblk + zz;
+          if (kk < box.ext[2]) {
+            const unsigned vo = cb + plane * (unsigned)kk;
+            bst<R>(ost[0][zz][c], rbk, vo, 0u);
+            bst<R>(ost[1][zz][c], rbu, vo, 0u);
+            bst<R>(ost[2][zz][c], rbu, vo, vb);
+            bst<R>(ost[3][zz][c], rbu, vo, 2u * vb);
+          }
+        }
+      }
+    } else
     // element e: column e % 8 (fastest), z e / 8 % ZB, field e / (8 ZB)
     for (int e = threadIdx.x; e < 4 * ZB * 8; e += 256) {
       const int c = e & 7, zz = (e >> 3) % ZB, q = e / (8 * ZB);
