@@ -1859,11 +1859,11 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
   const int f = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // field of this wave
   const int lane = threadIdx.x & 63;
   const int npx = (g.D[0] + 7) >> 3, npy = (g.D[1] + 7) >> 3;
-  int bi = blockIdx.x;
-  const int px = bi % npx;
-  bi /= npx;
-  const int py = bi % npy;
-  const int ch = bi / npy;
+  const int nch = (g.D[2] + LCH - 1) / LCH;
+  // XCD-aware: each XCD takes a contiguous run of patches (x fastest), so
+  // the overlapping windows of neighbouring patches meet in the same L2
+  int px, py, ch;
+  const int bi = xcd_tile_of(blockIdx.x, g.nxcd, npx, npy, nch, px, py, ch);
   const int e0 = px * 8 + (lane & 7), e1 = py * 8 + (lane >> 3);
   const bool active = e0 < g.D[0] && e1 < g.D[1];
   const int cols = g.D[0] * g.D[1];
@@ -2072,7 +2072,7 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kre
   double tot[8];
   block_sum<8, MAPADJ_THREADS>(part, tot);
   if (threadIdx.x == 0)
-    for (int q = 0; q < 8; ++q) mpart[(long long)blockIdx.x * 8 + q] = tot[q];
+    for (int q = 0; q < 8; ++q) mpart[(long long)bi * 8 + q] = tot[q];
 }
 
 // 2D transpose of the transfer for one step.  A block takes a 16 x 16 patch
