@@ -8,6 +8,10 @@
   every gradient within 1e-3 relative L2), and the smallest instance's first
   200 steps against the oracle (J within 1e-5 FP32 and 1e-10 FP64; gradients
   1e-3 and 1e-9).
+- The D3Q15 128^3 workload over its whole 5000-step horizon in the
+  configuration the benchmark times (checkpoints every 100 steps), FP32
+  state with FP64 sums against the FP64 plain form: J within 1e-5 and every
+  gradient within 1e-3 relative L2.
 - The 2D oar with J2 over its whole 4000-step horizon, FP32 against FP64.
   J2 is a small difference of forces about a thousand times larger than
   itself, so the FP32 state's rounding shows at their scale: the bars are
@@ -16,6 +20,7 @@
 """
 import numpy as np
 import pytest
+import torch
 
 from paper_2608_01071_amd import workloads as W
 
@@ -117,5 +122,28 @@ def test_oar_j2_fp32_whole_horizon():
     print(f"oar J2 FP32 vs FP64 over 4000 steps: {errs}", flush=True)
     assert errs["J2"] <= 2e-3
     assert errs["F_L"] <= 1e-3 and errs["F_D"] <= 2e-3
+    for key in ("dgamma", "dchi", "dpsi"):
+        assert errs[key] <= 1e-3, key
+
+
+def test_c4_fp32_against_fp64_whole_horizon():
+    lks = lk()
+    out = {}
+    for prec in (0, 1):
+        p, g, c, s = W.c4(precision=prec)
+        pl = lks.Plan(p)
+        J3, _ = pl.forward(g, c, s)
+        gr = pl.adjoint(g, c, s)
+        out[prec] = (cpu(J3), {k: cpu(gr[k]) for k in ("dgamma", "dchi", "dpsi")})
+        print(f"c4: precision {prec} pass done, J {out[prec][0][0]:.9e}", flush=True)
+        del pl, gr, J3
+        torch.cuda.empty_cache()
+    (J32, g32), (J64, g64) = out[0], out[1]
+    errs = {"J": abs(J32[0] - J64[0]) / abs(J64[0])}
+    for key in ("dgamma", "dchi", "dpsi"):
+        errs[key] = l2err(g32[key], g64[key])
+        assert np.abs(g64[key]).max() > 0, key
+    print(f"c4 FP32 vs FP64 over 5000 steps: {errs}", flush=True)
+    assert errs["J"] <= 1e-5
     for key in ("dgamma", "dchi", "dpsi"):
         assert errs[key] <= 1e-3, key
