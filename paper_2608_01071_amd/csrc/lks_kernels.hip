@@ -726,11 +726,16 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
   // rs = zf mod 3: ring slots of planes zf, zf + 1, zf - 1
   auto iter = [&](int zf, int rs, Buf& X) {
     const int sc = rs, sp1 = rs == 2 ? 0 : rs + 1, sm = rs == 0 ? 2 : rs - 1;
+    // the commit and the next plane's loads go out at raised wave priority,
+    // so the loads enter the memory system ahead of the other block's
+    // arithmetic (a scheduling hint only)
+    __builtin_amdgcn_s_setprio(2);
     commit(sp1, X);
     const bool binb = X.bin;
     const R bkv = X.bk, bu0 = X.bu[0], bu1 = X.bu[1], bu2 = X.bu[2];
     __syncthreads();
     fetch(zf + 3, X);
+    __builtin_amdgcn_s_setprio(0);
     R f0 = R(0), fzp = R(0), fzm = R(0);
     if (fok) {
       const R* ux = ring[sc][1];
@@ -1357,10 +1362,13 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
   // registers.  With a 4-plane ring one barrier per plane suffices; a
   // 3-plane ring (less LDS) needs a second one before the next commit.
   auto iter = [&](int zs, Buf& X) {
+    // commit and loads at raised wave priority, as in the forward step
+    __builtin_amdgcn_s_setprio(2);
     commit(zs + 1, X);
     const R upx = X.up[0], upy = X.up[1], upz = X.up[2];
     __syncthreads();
     fetch(zs + 3, X);
+    __builtin_amdgcn_s_setprio(0);
     R M[10];
 #pragma unroll
     for (int q = 0; q < 10; ++q) M[q] = R(0);
