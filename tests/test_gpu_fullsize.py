@@ -12,6 +12,11 @@
   configuration the benchmark times (checkpoints every 100 steps), FP32
   state with FP64 sums against the FP64 plain form: J within 1e-5 and every
   gradient within 1e-3 relative L2.
+- The largest FP32 D3Q15 grid the library accepts, 640^3 (2.6e8 nodes, a
+  4.2 GB state whose per-field byte offsets approach 2^32): one step of a
+  z-invariant state and body in a periodic box gives bitwise identical
+  planes, equal to the same pattern stepped on a 640 x 640 x 2 grid, which
+  matches the oracle.
 - The 2D oar with J2 over its whole 4000-step horizon, FP32 against FP64.
   J2 is a small difference of forces about a thousand times larger than
   itself, so the FP32 state's rounding shows at their scale: the bars are
@@ -24,7 +29,7 @@ import torch
 
 from paper_2608_01071_amd import workloads as W
 
-from test_gpu_parity import cpu, l2err, lk
+from test_gpu_parity import THIRD, cpu, l2err, lk, relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -147,3 +152,53 @@ def test_c4_fp32_against_fp64_whole_horizon():
     assert errs["J"] <= 1e-5
     for key in ("dgamma", "dchi", "dpsi"):
         assert errs[key] <= 1e-3, key
+
+
+def test_maximum_grid_z_invariant_step(orc):
+    lks = lk()
+    nx = ny = 640
+    P = nx * ny
+
+    def problem(nz, prec):
+        c = (nx / 2, ny / 2, nz / 2)
+        return W.Problem(d=3, n=(nx, ny, nz), bc=(0, 0, 0), nu=0.08, kappa_max=40.0, q=0.1,
+                         m=(4, 4, 4), margin=2, xg_min=c, xg_max=c, th_min=0.0, th_max=0.0,
+                         nt=1, r_t=1, r_w=1, tgt_lo=(0, 0, 0), tgt_hi=(1, 1, 1),
+                         ndir=(0.0, 0.0, 1.0), phi=0.0, precision=prec, ckpt_k=1)
+
+    # one x-y pattern of (p, u) and (kappa, u_s), the same on every plane
+    rng = np.random.default_rng(640)
+    base = np.concatenate([THIRD + 0.01 * rng.standard_normal(P), 0.03 * rng.standard_normal(3 * P)])
+    kb = np.abs(rng.standard_normal(P))
+    ub = 0.01 * rng.standard_normal(3 * P)
+    tile = lambda a, f, nz: np.repeat(a.reshape(f, 1, P), nz, axis=1).ravel()
+    ps = problem(2, 0)
+    s_small = tile(base, 4, 2)
+    k_small, u_small = tile(kb, 1, 2), tile(ub, 3, 2)
+    g_small = s_small.copy()
+    g_small[: ps.N] -= THIRD
+    out_s = lks.Plan(ps).step(g_small, k_small, u_small)
+    ref = orc.step(problem(2, 1), s_small, k_small, u_small)
+    o = cpu(out_s)
+    assert relerr(o[: ps.N], ref[: ps.N] - THIRD) < 2e-5
+    assert relerr(o[ps.N:], ref[ps.N:]) < 2e-6
+    print("max grid: 640 x 640 x 2 step matches the oracle", flush=True)
+    # 640^3 built on the device from the same plane
+    nz = 640
+    pb = problem(nz, 0)
+    assert pb.N < 2 ** 28
+    dev = torch.device("cuda")
+    plane = torch.tensor(g_small.reshape(4, 2, P)[:, 0, :], dtype=torch.float32, device=dev)
+    state = plane[:, None, :].expand(4, nz, P).contiguous().view(-1)
+    kap = torch.tensor(kb, dtype=torch.float32, device=dev)[None, :].expand(nz, P).contiguous().view(-1)
+    us = torch.tensor(ub.reshape(3, P), dtype=torch.float32, device=dev)[:, None, :].expand(
+        3, nz, P).contiguous().view(-1)
+    plan_b = lks.Plan(pb)
+    out_b = plan_b.step(state, kap, us).view(4, nz, P)
+    torch.cuda.synchronize()
+    first = out_b[:, :1, :]
+    assert torch.equal(out_b, first.expand(4, nz, P)), "planes differ"
+    assert torch.equal(first[:, 0, :], out_s.view(4, 2, P)[:, 0, :]), "differs from the 2-plane grid"
+    print("max grid: 640^3 step z-invariant and equal to the 2-plane grid", flush=True)
+    del out_b, first, state, kap, us, plan_b
+    torch.cuda.empty_cache()

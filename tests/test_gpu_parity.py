@@ -342,6 +342,42 @@ def test_edge_cases(orc):
     assert l2err(cpu(g["dgamma"]), adj["dgamma"]) < 1e-10
 
 
+def test_edge_cases_3d(orc):
+    """D3Q15: an empty target (J = 0, zero gradients), no body (kappa_max = 0,
+    a moving start state: J as the oracle's, every gradient exactly zero), and
+    a single step from a given state with K = 1 and a scaled seed, against the
+    oracle."""
+    lks = lk()
+    p = prob3d(prec=1, tgt_lo=(0, 0, 0), tgt_hi=(0, 18, 1))
+    plan = lks.Plan(p)
+    gamma, chi, psi = rand_inputs(p, 23)
+    J3, _ = plan.forward(gamma, chi, psi)
+    g = plan.adjoint(gamma, chi, psi)
+    assert np.all(cpu(J3) == 0)
+    assert np.all(cpu(g["dgamma"]) == 0) and np.all(cpu(g["dpsi"]) == 0)
+    p = prob3d(prec=1, kappa_max=0.0)
+    plan = lks.Plan(p)
+    s0 = rand_state(p, 26)  # a moving start state: at rest nothing would drive the flow
+    J3, _ = plan.forward(gamma, chi, psi, state0=gpu_state(s0, p))
+    g = plan.adjoint(gamma, chi, psi)
+    ref = orc.forward(p, gamma, chi, psi, state0=s0, want_final=False)
+    assert abs(ref["J"]) > 1e-8
+    assert abs(cpu(J3)[0] - ref["J"]) <= 1e-10 * abs(ref["J"])
+    for k in ("dgamma", "dchi", "dpsi"):
+        assert np.all(cpu(g[k]) == 0), k
+    p = prob3d(prec=1, nt=1, ckpt_k=1)
+    plan = lks.Plan(p)
+    gamma, chi, psi = rand_inputs(p, 24)
+    s0 = rand_state(p, 25)
+    J3, _ = plan.forward(gamma, chi, psi, state0=gpu_state(s0, p))
+    g = plan.adjoint(gamma, chi, psi, dJ=[-3.0])
+    ref = orc.forward(p, gamma, chi, psi, state0=s0)
+    adj = orc.adjoint(p, gamma, chi, psi, state0=s0, dJ=-3.0)
+    assert abs(cpu(J3)[0] - ref["J"]) <= 1e-11 * abs(ref["J"])
+    for k in ("dgamma", "dchi", "dpsi"):
+        assert l2err(cpu(g[k]), adj[k]) < 1e-10, k
+
+
 def test_domain_error_before_march():
     """A body whose support reaches a wall node is rejected (LKS_EDOMAIN)."""
     lks = lk()
