@@ -818,10 +818,11 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 6 : 3) void k_fwd3d(
           u1 = am[2];
           u2 = am[3];
           if (binb) {
+            // named fused multiply-adds: both unrolled copies round alike
             const R inv = brinkman_inv(bkv);
-            u0 = (u0 + bkv * bu0) * inv;
-            u1 = (u1 + bkv * bu1) * inv;
-            u2 = (u2 + bkv * bu2) * inv;
+            u0 = fma(bkv, bu0, u0) * inv;
+            u1 = fma(bkv, bu1, u1) * inv;
+            u2 = fma(bkv, bu2, u2) * inv;
           }
           const R uu = u0 * u0 + u1 * u1 + u2 * u2;
           bad = bad || !(uu < R(0.25));  // non-finite or |u| >= 0.5
@@ -1284,17 +1285,17 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
         x2 = X2 + s2;
       }
       if (B.bown) {
-        const R kb = x0 * (B.bu[0] - B.un[0]) + x1 * (B.bu[1] - B.un[1]) +
-                     x2 * (B.bu[2] - B.un[2]);
+        const R kb = fma(x2, B.bu[2] - B.un[2],
+                         fma(x1, B.bu[1] - B.un[1], x0 * (B.bu[0] - B.un[0])));
         bkbar[B.bi] = kb * inv;
         bubar[B.bi] = kk * x0 * inv;
         bubar[B.bi + bvol] = kk * x1 * inv;
         bubar[B.bi + 2 * bvol] = kk * x2 * inv;
       }
       if constexpr (ALK) {
-        ub0 = x0 * inv + (ub0 - X0);
-        ub1 = x1 * inv + (ub1 - X1);
-        ub2 = x2 * inv + (ub2 - X2);
+        ub0 = fma(x0, inv, ub0 - X0);
+        ub1 = fma(x1, inv, ub1 - X1);
+        ub2 = fma(x2, inv, ub2 - X2);
       } else {
         ub0 *= inv;
         ub1 *= inv;
@@ -1393,14 +1394,14 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
         if (cz == 1) { cu_p += vp.z; cu_m += vm.z; }
         if (cz == -1) { cu_p -= vp.z; cu_m -= vm.z; }
         const R Fp = vp.p + cu_p, Fm = vm.p - cu_m;
-        const R wS = R(Lat<15>::w[i]) * (Fp + Fm), wD = R(Lat<15>::w[i]) * (Fp - Fm);
-        M[0] += wS;
-        if (cx != 0) { M[1] += cx > 0 ? wD : -wD; M[4] += wS; }
-        if (cy != 0) { M[2] += cy > 0 ? wD : -wD; M[5] += wS; }
-        if (cz != 0) { M[3] += cz > 0 ? wD : -wD; M[6] += wS; }
-        if (cx * cy != 0) M[7] += cx * cy > 0 ? wS : -wS;
-        if (cx * cz != 0) M[8] += cx * cz > 0 ? wS : -wS;
-        if (cy * cz != 0) M[9] += cy * cz > 0 ? wS : -wS;
+        const R w = R(Lat<15>::w[i]), S = Fp + Fm, D = Fp - Fm;
+        M[0] = fma(w, S, M[0]);
+        if (cx != 0) { M[1] = fma(cx > 0 ? w : -w, D, M[1]); M[4] = fma(w, S, M[4]); }
+        if (cy != 0) { M[2] = fma(cy > 0 ? w : -w, D, M[2]); M[5] = fma(w, S, M[5]); }
+        if (cz != 0) { M[3] = fma(cz > 0 ? w : -w, D, M[3]); M[6] = fma(w, S, M[6]); }
+        if (cx * cy != 0) M[7] = fma(cx * cy > 0 ? w : -w, S, M[7]);
+        if (cx * cz != 0) M[8] = fma(cx * cz > 0 ? w : -w, S, M[8]);
+        if (cy * cz != 0) M[9] = fma(cy * cz > 0 ? w : -w, S, M[9]);
       }
       R(*mo)[FP] = mb[zs & 1];
       mo[0][fpos] = M[4];
@@ -1417,9 +1418,16 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
       const R M0 = Mp[0];
       const R Mxx = Mp[4], Myy = Mp[5], Mzz = Mp[6];
       const R Mxy = Mp[7], Mxz = Mp[8], Myz = Mp[9];
-      R bx = R(3) * Mp[1] + R(9) * (Mxx * ux + Mxy * uy + Mxz * uz) - R(3) * ux * M0;
-      R by = R(3) * Mp[2] + R(9) * (Mxy * ux + Myy * uy + Myz * uz) - R(3) * uy * M0;
-      R bz = R(3) * Mp[3] + R(9) * (Mxz * ux + Myz * uy + Mzz * uz) - R(3) * uz * M0;
+      // the fused multiply-adds are named here and below, so that the two
+      // unrolled copies of the plane loop round alike (a plane's result must
+      // not depend on the parity of its place in the segment)
+      auto eqT = [&](R m1, R mx, R my, R mz, R uc) {
+        const R t = fma(mz, uz, fma(my, uy, mx * ux));
+        return fma(-R(3) * uc, M0, fma(R(9), t, R(3) * m1));
+      };
+      R bx = eqT(Mp[1], Mxx, Mxy, Mxz, ux);
+      R by = eqT(Mp[2], Mxy, Myy, Myz, uy);
+      R bz = eqT(Mp[3], Mxz, Myz, Mzz, uz);
       // velocity-gradient transpose: D_x^T, D_y^T in plane (central, then the
       // one-sided transposes next to walls); D_z^T (periodic) from zo -+ 1
       R tx0 = m0[0][oc - 1] - m0[0][oc + 1];
@@ -1436,9 +1444,9 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
           const int j = r0 + min(max(tx + 1 + q - 2, 0), FX - 1);
-          tx0 += kxw[q] * m0[0][j];
-          tx1 += kxw[q] * m0[2][j];
-          tx2 += kxw[q] * m0[3][j];
+          tx0 = fma(kxw[q], m0[0][j], tx0);
+          tx1 = fma(kxw[q], m0[2][j], tx1);
+          tx2 = fma(kxw[q], m0[3][j], tx2);
         }
       }
       if (owy) {
@@ -1446,14 +1454,14 @@ __global__ __launch_bounds__(Tile3<R>::NT, sizeof(R) == 4 ? 3 : 2) void k_adj3d(
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
           const int j = (tx + 1) + min(max(ty + 1 + q - 2, 0), FY - 1) * FX;
-          ty0 += kyw[q] * m0[2][j];
-          ty1 += kyw[q] * m0[1][j];
-          ty2 += kyw[q] * m0[4][j];
+          ty0 = fma(kyw[q], m0[2][j], ty0);
+          ty1 = fma(kyw[q], m0[1][j], ty1);
+          ty2 = fma(kyw[q], m0[4][j], ty2);
         }
       }
-      bx += A * (tx0 + ty0 + (zprev[0] - M[8]));
-      by += A * (tx1 + ty1 + (zprev[1] - M[9]));
-      bz += A * (tx2 + ty2 + (zprev[2] - M[6]));
+      bx = fma(A, tx0 + ty0 + (zprev[0] - M[8]), bx);
+      by = fma(A, tx1 + ty1 + (zprev[1] - M[9]), by);
+      bz = fma(A, tx2 + ty2 + (zprev[2] - M[6]), bz);
       bst<R>(R(3) * M0, rlp, ovo, so);
       bst<R>(bx, rlp, ovo, so + fb);
       bst<R>(by, rlp, ovo, so + 2u * fb);

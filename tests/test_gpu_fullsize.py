@@ -14,9 +14,9 @@
   gradient within 1e-3 relative L2.
 - The largest FP32 D3Q15 grid the library accepts, 640^3 (2.6e8 nodes, a
   4.2 GB state whose per-field byte offsets approach 2^32): one step of a
-  z-invariant state and body in a periodic box gives bitwise identical
-  planes, equal to the same pattern stepped on a 640 x 640 x 2 grid, which
-  matches the oracle.
+  z-invariant state and body in a periodic box, and one adjoint step of a
+  z-invariant adjoint state, give bitwise identical planes, equal to the same
+  patterns stepped on a 640 x 640 x 2 grid, which matches the oracle.
 - The 2D oar with J2 over its whole 4000-step horizon, FP32 against FP64.
   J2 is a small difference of forces about a thousand times larger than
   itself, so the FP32 state's rounding shows at their scale: the bars are
@@ -200,5 +200,29 @@ def test_maximum_grid_z_invariant_step(orc):
     assert torch.equal(out_b, first.expand(4, nz, P)), "planes differ"
     assert torch.equal(first[:, 0, :], out_s.view(4, 2, P)[:, 0, :]), "differs from the 2-plane grid"
     print("max grid: 640^3 step z-invariant and equal to the 2-plane grid", flush=True)
-    del out_b, first, state, kap, us, plan_b
+    # the adjoint step on both grids from a z-invariant adjoint state
+    lam_plane = 0.1 * rng.standard_normal(4 * P)
+    lam_small = tile(lam_plane, 4, 2)
+    ref_out = ref.copy()
+    ref_out_g = ref_out.copy()
+    ref_out_g[: ps.N] -= THIRD
+    lp_s, kb_s, ub_s = lks.Plan(ps).step_adjoint(g_small, ref_out_g, k_small, u_small, lam_small)
+    rlp, rkb, rub = orc.step_adjoint(problem(2, 1), s_small, ref_out, k_small, u_small, lam_small)
+    assert relerr(cpu(lp_s), rlp) < 2e-5
+    assert relerr(cpu(kb_s), rkb) < 2e-5
+    assert relerr(cpu(ub_s), rub) < 2e-5
+    print("max grid: 640 x 640 x 2 adjoint step matches the oracle", flush=True)
+    so_plane = torch.tensor(ref_out_g.reshape(4, 2, P)[:, 0, :], dtype=torch.float32, device=dev)
+    state_out = so_plane[:, None, :].expand(4, nz, P).contiguous().view(-1)
+    del out_b, first
+    lam = torch.tensor(lam_plane.reshape(4, P), dtype=torch.float32, device=dev)[:, None, :].expand(
+        4, nz, P).contiguous().view(-1)
+    lp_b, kb_b, ub_b = plan_b.step_adjoint(state, state_out, kap, us, lam)
+    torch.cuda.synchronize()
+    for big, small, f in ((lp_b, lp_s, 4), (kb_b, kb_s, 1), (ub_b, ub_s, 3)):
+        v = big.view(f, nz, P)
+        assert torch.equal(v, v[:, :1, :].expand(f, nz, P)), ("adjoint planes differ", f)
+        assert torch.equal(v[:, 0, :], small.view(f, 2, P)[:, 0, :]), ("adjoint differs", f)
+    print("max grid: 640^3 adjoint step z-invariant and equal to the 2-plane grid", flush=True)
+    del lp_b, kb_b, ub_b, lam, state_out, state, kap, us, plan_b
     torch.cuda.empty_cache()

@@ -378,6 +378,32 @@ def test_edge_cases_3d(orc):
         assert l2err(cpu(g[k]), adj[k]) < 1e-10, k
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_step_results_do_not_depend_on_the_plane(prec):
+    """D3Q15 in a periodic box: one forward step and one adjoint step of a
+    z-invariant state, body and adjoint state give bitwise identical planes.
+    (The plane loops are unrolled, so a plane's arithmetic must not depend on
+    the parity of its place in a segment.)"""
+    lks = lk()
+    n = (40, 24, 20)
+    p = prob3d(n=n, prec=prec, bc=(0, 0, 0), tgt_lo=(0, 0, 0), tgt_hi=(1, 1, 1))
+    plan = lks.Plan(p)
+    P = n[0] * n[1]
+    rng = np.random.default_rng(77)
+    tile = lambda a, f: np.repeat(a.reshape(f, 1, P), n[2], axis=1).ravel()
+    st = tile(np.concatenate([0.01 * rng.standard_normal(P), 0.03 * rng.standard_normal(3 * P)]), 4)
+    so = tile(np.concatenate([0.01 * rng.standard_normal(P), 0.03 * rng.standard_normal(3 * P)]), 4)
+    kap = tile(np.abs(rng.standard_normal(P)), 1)
+    us = tile(0.01 * rng.standard_normal(3 * P), 3)
+    lam = tile(0.1 * rng.standard_normal(4 * P), 4)
+    out = cpu(plan.step(st, kap, us)).reshape(4, n[2], P)
+    assert np.array_equal(out, np.broadcast_to(out[:, :1], out.shape))
+    lp, kb, ub = (cpu(t) for t in plan.step_adjoint(st, so, kap, us, lam))
+    for v, f in ((lp, 4), (kb, 1), (ub, 3)):
+        v = v.reshape(f, n[2], P)
+        assert np.array_equal(v, np.broadcast_to(v[:, :1], v.shape)), f
+
+
 def test_domain_error_before_march():
     """A body whose support reaches a wall node is rejected (LKS_EDOMAIN)."""
     lks = lk()
