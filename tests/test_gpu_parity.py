@@ -404,6 +404,30 @@ def test_step_results_do_not_depend_on_the_plane(prec):
         assert np.array_equal(v, np.broadcast_to(v[:, :1], v.shape)), f
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_zsegment_length_does_not_change_the_fields(prec):
+    """D3Q15: the z-segment length (how the column tiles cut the march) does
+    not change the final state or the gradients, bitwise (phi = 0, so the
+    adjoint seed does not depend on the summed mean); J differs only by the
+    grouping of its FP64 sums."""
+    lks = lk()
+    p = prob3d(prec=prec, phi=0.0)
+    gamma, chi, psi = rand_inputs(p, 31)
+    outs = []
+    for zseg in (0, 4, 7):
+        plan = lks.Plan(p)
+        if zseg:
+            plan.set_zseg(zseg)
+        J3, fin = plan.forward(gamma, chi, psi, want_final=True)
+        g = plan.adjoint(gamma, chi, psi)
+        outs.append((cpu(J3)[0], cpu(fin), [cpu(g[k]) for k in ("dgamma", "dchi", "dpsi")]))
+    for J, fin, gr in outs[1:]:
+        assert abs(J - outs[0][0]) <= 1e-13 * abs(outs[0][0])
+        assert np.array_equal(fin, outs[0][1])
+        for a, b in zip(gr, outs[0][2]):
+            assert np.array_equal(a, b)
+
+
 def test_domain_error_before_march():
     """A body whose support reaches a wall node is rejected (LKS_EDOMAIN)."""
     lks = lk()
