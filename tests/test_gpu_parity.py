@@ -428,6 +428,47 @@ def test_zsegment_length_does_not_change_the_fields(prec):
             assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_translation_moves_the_fields_bitwise(prec):
+    """D3Q15 in a periodic box: moving the body, the target and the start
+    state by whole nodes (3, 2, 2) puts every node at another place in its
+    tile and segment; in FP32 the final state moves with them bitwise and
+    the gradients are bitwise unchanged (phi = 0; J differs only by the
+    grouping of its FP64 sums); in FP64, whose transfer weights come from
+    absolute positions, they agree to rounding."""
+    lks = lk()
+    n = (34, 18, 20)
+    d = (3, 2, 2)  # the target box stays inside the grid (it is clipped, not wrapped)
+    base = prob3d(n=n, prec=prec, bc=(0, 0, 0), phi=0.0)
+    moved = base.replace(
+        xg_min=tuple(a + b for a, b in zip(base.xg_min, d)),
+        xg_max=tuple(a + b for a, b in zip(base.xg_max, d)),
+        tgt_lo=tuple(a + b for a, b in zip(base.tgt_lo, d)),
+        tgt_hi=tuple(a + b for a, b in zip(base.tgt_hi, d)))
+    gamma, chi, psi = rand_inputs(base, 41)
+    s0 = gpu_state(rand_state(base, 42), base)
+    roll = lambda v: np.roll(v.reshape(4, n[2], n[1], n[0]), shift=(d[2], d[1], d[0]),
+                             axis=(1, 2, 3)).ravel()
+    outs = []
+    for p, st in ((base, s0), (moved, roll(s0))):
+        plan = lks.Plan(p)
+        J3, fin = plan.forward(gamma, chi, psi, state0=st, want_final=True)
+        g = plan.adjoint(gamma, chi, psi)
+        outs.append((cpu(J3)[0], cpu(fin), [cpu(g[k]) for k in ("dgamma", "dchi", "dpsi")]))
+    (J0, f0, g0), (J1, f1, g1) = outs
+    assert abs(J1 - J0) <= 1e-12 * abs(J0)
+    if prec == 0:
+        assert np.array_equal(f1, roll(f0))
+        for a, b in zip(g1, g0):
+            assert np.array_equal(a, b)
+    else:
+        # FP64 forms the transfer weights from absolute positions, so the
+        # moved body's weights differ in their last bits
+        assert relerr(f1, roll(f0)) < 1e-13
+        for a, b in zip(g1, g0):
+            assert relerr(a, b) < 1e-12
+
+
 def test_domain_error_before_march():
     """A body whose support reaches a wall node is rejected (LKS_EDOMAIN)."""
     lks = lk()
