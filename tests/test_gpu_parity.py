@@ -469,6 +469,40 @@ def test_translation_moves_the_fields_bitwise(prec):
             assert relerr(a, b) < 1e-12
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_translation_moves_the_fields_bitwise_2d(prec):
+    """D2Q9 in a periodic box, moved by whole nodes (5, 3): as the 3D check,
+    every node sits elsewhere in its 32 x 8 (forward) and 32 x 16 (adjoint)
+    tile; FP32 bitwise, FP64 to rounding."""
+    lks = lk()
+    n = (45, 21)
+    d = (5, 3)
+    base = prob2d(n, prec, bc=(0, 0, 0), phi=0.0, tgt_lo=(20, 2, 0), tgt_hi=(24, 17, 1))
+    moved = base.replace(
+        xg_min=(base.xg_min[0] + d[0], base.xg_min[1] + d[1], 0.0),
+        xg_max=(base.xg_max[0] + d[0], base.xg_max[1] + d[1], 0.0),
+        tgt_lo=(20 + d[0], 2 + d[1], 0), tgt_hi=(24 + d[0], 17 + d[1], 1))
+    gamma, chi, psi = rand_inputs(base, 43)
+    s0 = gpu_state(rand_state(base, 44), base)
+    roll = lambda v: np.roll(v.reshape(3, n[1], n[0]), shift=(d[1], d[0]), axis=(1, 2)).ravel()
+    outs = []
+    for p, st in ((base, s0), (moved, roll(s0))):
+        plan = lks.Plan(p)
+        J3, fin = plan.forward(gamma, chi, psi, state0=st, want_final=True)
+        g = plan.adjoint(gamma, chi, psi)
+        outs.append((cpu(J3)[0], cpu(fin), [cpu(g[k]) for k in ("dgamma", "dchi", "dpsi")]))
+    (J0, f0, g0), (J1, f1, g1) = outs
+    assert abs(J1 - J0) <= 1e-12 * abs(J0)
+    if prec == 0:
+        assert np.array_equal(f1, roll(f0))
+        for a, b in zip(g1, g0):
+            assert np.array_equal(a, b)
+    else:
+        assert relerr(f1, roll(f0)) < 1e-13
+        for a, b in zip(g1, g0):
+            assert relerr(a, b) < 1e-12
+
+
 def test_domain_error_before_march():
     """A body whose support reaches a wall node is rejected (LKS_EDOMAIN)."""
     lks = lk()
