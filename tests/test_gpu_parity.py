@@ -428,18 +428,20 @@ def test_zsegment_length_does_not_change_the_fields(prec):
             assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("scheme", [0, 1])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_translation_moves_the_fields_bitwise(prec):
+def test_translation_moves_the_fields_bitwise(prec, scheme):
     """D3Q15 in a periodic box: moving the body, the target and the start
     state by whole nodes (3, 2, 2) puts every node at another place in its
     tile and segment; in FP32 the final state moves with them bitwise and
     the gradients are bitwise unchanged (phi = 0; J differs only by the
     grouping of its FP64 sums); in FP64, whose transfer weights come from
-    absolute positions, they agree to rounding."""
+    absolute positions, they agree to rounding.  Both reverse sweeps (the
+    exact adjoint and the ALKS)."""
     lks = lk()
     n = (34, 18, 20)
     d = (3, 2, 2)  # the target box stays inside the grid (it is clipped, not wrapped)
-    base = prob3d(n=n, prec=prec, bc=(0, 0, 0), phi=0.0)
+    base = prob3d(n=n, prec=prec, bc=(0, 0, 0), phi=0.0, scheme=scheme)
     moved = base.replace(
         xg_min=tuple(a + b for a, b in zip(base.xg_min, d)),
         xg_max=tuple(a + b for a, b in zip(base.xg_max, d)),
