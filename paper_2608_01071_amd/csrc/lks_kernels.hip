@@ -1638,7 +1638,7 @@ __global__ __launch_bounds__(256) void k_kref_t(Geo g, const R* kref, R* kt, int
 }
 
 template <class R>
-__global__ __launch_bounds__(256) void k_map3d(Geo g, const R* kt, int lz, Mot m, Box box,
+__global__ __launch_bounds__(256, sizeof(R) == 4 ? 8 : 4) void k_map3d(Geo g, const R* kt, int lz, Mot m, Box box,
                                                const StepInfo* si, R* bk, R* bu, int full_grid,
                                                long long bstride) {
   // blockIdx.y: step within a batch of consecutive steps (per-step table rows
@@ -1717,9 +1717,10 @@ __global__ __launch_bounds__(256) void k_map3d(Geo g, const R* kt, int lz, Mot m
 #pragma unroll
     for (int t = 0; t < ZPL + 3; ++t) G[t] = R(0);
     R m0 = R(0), m1 = R(0), m2 = R(0);
-    // candidates four at a time: all their loads are issued before the
-    // sums, which then run in slot order
-    constexpr int CG = 4;
+    // candidates two at a time: their loads are issued before the sums,
+    // which run in slot order (in FP32 this keeps the kernel within 64
+    // VGPRs, eight waves per SIMD, which pays more than larger groups)
+    constexpr int CG = 2;
     unsigned long long it = mk;
     while (it) {
       int sl[CG];
