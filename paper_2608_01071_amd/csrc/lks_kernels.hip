@@ -1853,7 +1853,7 @@ __device__ __forceinline__ double uniform(double v) {
 // over the levels and the block adds the four.
 constexpr int MAW = 16;  // staged window side (analysis nodes)
 template <class R, int LCH>
-__global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj3d(Geo g, const R* kref, Mot m, Box box,
+__global__ __launch_bounds__(MAPADJ_THREADS, sizeof(R) == 4 ? 5 : 2) void k_mapadj3d(Geo g, const R* kref, Mot m, Box box,
                                                              const StepInfo* si, const R* bkbar,
                                                              const R* bubar, double* kref_bar,
                                                              int overwrite, double* mpart,
@@ -2336,7 +2336,7 @@ __global__ __launch_bounds__(J2_THREADS) void k_j2_fwd(Geo g, const R* kref, con
 // With J2 (jst non-null) a third range of blocks adds the J2 step sums of
 // the step's input state (after step jsi), which the step only reads.
 template <class R>
-__global__ __launch_bounds__(STEP_THREADS) void k_fwd2d_map(Geo g, FwdArgs a, int nstep,
+__global__ __launch_bounds__(STEP_THREADS, sizeof(R) == 4 ? 8 : 4) void k_fwd2d_map(Geo g, FwdArgs a, int nstep,
                                                            const R* kref, Box box,
                                                            const StepInfo* msi, R* bk, R* bu,
                                                            int nbx, int nmap,
