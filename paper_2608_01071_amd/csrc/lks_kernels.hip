@@ -126,11 +126,11 @@ __device__ __forceinline__ void apply_step(Box& b, const StepInfo* si) {
 }
 
 // Cosine kernel w(r) = (1 + cos(pi r / 2)) / 4 and its derivative (Sec. 2.3),
-// for |r| <= 2.  In single precision w = cos^2(y) / 2 and
-// w' = -(pi / 4) sin(y) cos(y) with y = pi r / 4 in [-pi/2, pi/2], where the
-// Taylor series of cos through y^12 and of sin through y^13 are below 7e-9
-// from the functions; the coefficients absorb the powers of pi / 4 so the
-// polynomials run in r^2.
+// for |r| <= 2, as w = cos^2(y) / 2 and w' = -(pi / 4) sin(y) cos(y) with
+// y = pi r / 4 in [-pi/2, pi/2].  Single precision takes the Taylor series of
+// cos through y^12 and of sin through y^13 (below 7e-9 from the functions),
+// double precision those through y^20 and y^21 (below 2e-17); the
+// coefficients absorb the powers of pi / 4 so the polynomials run in r^2.
 namespace wpoly {
 constexpr double Q = 0.78539816339744830962;  // pi / 4
 constexpr double Q2 = Q * Q;
@@ -148,17 +148,49 @@ __device__ __forceinline__ float cosq(float z) {  // cos(pi r / 4), z = r^2
 __device__ __forceinline__ float sinq(float r, float z) {  // sin(pi r / 4)
   return r * fmaf(fmaf(fmaf(fmaf(fmaf(fmaf(s6, z, s5), z, s4), z, s3), z, s2), z, s1), z, s0);
 }
+// double precision: coefficient k of cos(pi r / 4) and of sin(pi r / 4) / r
+// as series in z = r^2
+constexpr double ccos(int k) {
+  double v = 1.0;
+  for (int i = 1; i <= k; ++i) v *= -Q2 / ((2.0 * i - 1.0) * (2.0 * i));
+  return v;
+}
+constexpr double csin(int k) {
+  double v = Q;
+  for (int i = 1; i <= k; ++i) v *= -Q2 / ((2.0 * i) * (2.0 * i + 1.0));
+  return v;
+}
+__device__ __forceinline__ double cosq(double z) {
+  constexpr double a0 = ccos(0), a1 = ccos(1), a2 = ccos(2), a3 = ccos(3), a4 = ccos(4),
+                   a5 = ccos(5), a6 = ccos(6), a7 = ccos(7), a8 = ccos(8), a9 = ccos(9),
+                   a10 = ccos(10);
+  double p = fma(fma(fma(fma(fma(a10, z, a9), z, a8), z, a7), z, a6), z, a5);
+  return fma(fma(fma(fma(fma(p, z, a4), z, a3), z, a2), z, a1), z, a0);
+}
+__device__ __forceinline__ double sinq(double r, double z) {
+  constexpr double b0 = csin(0), b1 = csin(1), b2 = csin(2), b3 = csin(3), b4 = csin(4),
+                   b5 = csin(5), b6 = csin(6), b7 = csin(7), b8 = csin(8), b9 = csin(9),
+                   b10 = csin(10);
+  double p = fma(fma(fma(fma(fma(b10, z, b9), z, b8), z, b7), z, b6), z, b5);
+  return r * fma(fma(fma(fma(fma(p, z, b4), z, b3), z, b2), z, b1), z, b0);
+}
 }  // namespace wpoly
 __device__ __forceinline__ float wk(float r) {
   const float c = wpoly::cosq(r * r);
   return 0.5f * c * c;
 }
-__device__ __forceinline__ double wk(double r) { return 0.25 * (1.0 + cospi(0.5 * r)); }
+__device__ __forceinline__ double wk(double r) {
+  const double c = wpoly::cosq(r * r);
+  return 0.5 * c * c;
+}
 __device__ __forceinline__ float wkd(float r) {
   const float z = r * r;
   return -0.78539816f * wpoly::sinq(r, z) * wpoly::cosq(z);
 }
-__device__ __forceinline__ double wkd(double r) { return -0.39269908169872414 * sinpi(0.5 * r); }
+__device__ __forceinline__ double wkd(double r) {
+  const double z = r * r;
+  return -0.78539816339744830962 * wpoly::sinq(r, z) * wpoly::cosq(z);
+}
 
 // Derivative along one axis from an LDS row (stride st): central, or
 // second-order one-sided on a wall node.  The one-sided forms name their
@@ -1542,13 +1574,65 @@ __device__ __forceinline__ void apply_step(Box& b, Mot& m, const StepInfo* si) {
 }
 
 // Cosine-kernel sums over the design points whose rotated position lies
-// within the kernel support of analysis position (bx, by):
-// W-weighted kappa_ref, sum W, sum W r1, sum W r2.  A block is a
-// MAP2_TX x MAP2_TY patch of the box.  The offset of design point e from the
-// analysis node is R (q - e), q being the node in design coordinates, so the
-// candidate loop works on q - e relative to the window corner (small numbers,
-// exact in the working precision) instead of on absolute positions.
-template <class R>
+// within the kernel support of analysis position (bx, by): the W-weighted
+// kappa_ref, and from sum W, sum W r1, sum W r2 the transferred rigid velocity,
+// in arithmetic type C (kappa_ref read in the state type R; the fused
+// multiply-adds are named so every kernel that inlines this rounds alike).  The offset of
+// design point e from the analysis node is R (q - e), q being the node in
+// design coordinates, so the candidate loop works on q - e relative to the
+// window corner (small numbers, exact in the working precision) instead of on
+// absolute positions.
+template <class R, class C>
+__device__ __forceinline__ void map2d_sums(const Geo& g, const R* kref, const Mot& m, int bx,
+                                           int by, C& k, C& usx, C& usy) {
+  C m0 = C(0), m1 = C(0), m2 = C(0);
+  k = C(0);
+  const C c = (C)m.c, s = (C)m.s;
+  const double rx = bx - m.xg[0], ry = by - m.xg[1];
+  const double q0 = m.c * rx + m.s * ry + g.xiG[0];
+  const double q1 = -m.s * rx + m.c * ry + g.xiG[1];
+  const double h = 2.0 * (fabs(m.c) + fabs(m.s));
+  const int i0 = max(0, (int)ceil(q0 - h)), i1 = min(g.D[0] - 1, (int)floor(q0 + h));
+  const int j0 = max(0, (int)ceil(q1 - h)), j1 = min(g.D[1] - 1, (int)floor(q1 + h));
+  const C f0 = (C)(q0 - i0), f1 = (C)(q1 - j0);  // q - (window corner)
+  const C a0 = (C)((double)i0 - g.xiG[0]), a1 = (C)((double)j0 - g.xiG[1]);
+  // a window row has at most 6 points (its width is below 2 h + 1 <= 6.7):
+  // the row's loads are issued together, clamped into the row
+  const int jn = (i0 <= i1) ? j1 : j0 - 1;
+  for (int e1 = j0; e1 <= jn; ++e1) {
+    const C t1 = f1 - (C)(e1 - j0);
+    const C r1 = a1 + (C)(e1 - j0);
+    const R* kr = kref + (long long)g.D[0] * e1;
+    R v[6];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) v[u] = kr[min(i0 + u, i1)];
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      const C t0 = f0 - (C)u;
+      const C d0 = fma(c, t0, -s * t1);
+      const C d1 = fma(s, t0, c * t1);
+      if (i0 + u <= i1 && fabs(d0) < C(2) && fabs(d1) < C(2)) {
+        const C W = wk(d0) * wk(d1);
+        m0 += W;
+        m1 = fma(W, a0 + (C)u, m1);
+        m2 = fma(W, r1, m2);
+        k = fma(W, (C)v[u], k);
+      }
+    }
+  }
+  const C om = (C)m.om;
+  usx = fma(om, fma(-s, m1, -c * m2), (C)m.ug[0] * m0);
+  usy = fma(om, fma(c, m1, -s * m2), (C)m.ug[1] * m0);
+}
+
+// The transfer of one box node; a block is a MAP2_TX x MAP2_TY patch of the
+// box.  J2F (kernels built for single-precision states under the objective J2):
+// plans with that objective take the sums in FP64 and round the outputs once.
+// J2's force density kappa_ref (u_ref - U) is a small difference of the fluid
+// velocity, which the Brinkman term drives to the transferred rigid velocity,
+// and U, so single-precision weights and sums would show in it at the scale of
+// U; the objective J1 does not need them, and its kernels are built without.
+template <class R, bool J2F = false>
 __device__ __forceinline__ void map2d_row(const Geo& g, const R* kref, Mot m, Box box,
                                           const StepInfo* si, R* bk, R* bu, int full_grid,
                                           int bx_blk, int by_blk) {
@@ -1560,45 +1644,18 @@ __device__ __forceinline__ void map2d_row(const Geo& g, const R* kref, Mot m, Bo
   int x = bx, y = by;
   const bool inside = wrap_axis(g, 0, x) && wrap_axis(g, 1, y);
   const bool wall = inside && is_wall(g, x, y, 0);
-  R k = R(0), m0 = R(0), m1 = R(0), m2 = R(0);
-  const R c = (R)m.c, s = (R)m.s;
+  R k = R(0), usx = R(0), usy = R(0);
   if (inside && !wall) {
-    const double rx = bx - m.xg[0], ry = by - m.xg[1];
-    const double q0 = m.c * rx + m.s * ry + g.xiG[0];
-    const double q1 = -m.s * rx + m.c * ry + g.xiG[1];
-    const double h = 2.0 * (fabs(m.c) + fabs(m.s));
-    const int i0 = max(0, (int)ceil(q0 - h)), i1 = min(g.D[0] - 1, (int)floor(q0 + h));
-    const int j0 = max(0, (int)ceil(q1 - h)), j1 = min(g.D[1] - 1, (int)floor(q1 + h));
-    const R f0 = (R)(q0 - i0), f1 = (R)(q1 - j0);  // q - (window corner)
-    const R a0 = (R)((double)i0 - g.xiG[0]), a1 = (R)((double)j0 - g.xiG[1]);
-    // a window row has at most 6 points (its width is below 2 h + 1 <= 6.7):
-    // the row's loads are issued together, clamped into the row
-    const int jn = (i0 <= i1) ? j1 : j0 - 1;
-    for (int e1 = j0; e1 <= jn; ++e1) {
-      const R t1 = f1 - (R)(e1 - j0);
-      const R r1 = a1 + (R)(e1 - j0);
-      const R* kr = kref + (long long)g.D[0] * e1;
-      R v[6];
-#pragma unroll
-      for (int u = 0; u < 6; ++u) v[u] = kr[min(i0 + u, i1)];
-#pragma unroll
-      for (int u = 0; u < 6; ++u) {
-        const R t0 = f0 - (R)u;
-        const R d0 = c * t0 - s * t1;
-        const R d1 = s * t0 + c * t1;
-        if (i0 + u <= i1 && fabs(d0) < R(2) && fabs(d1) < R(2)) {
-          const R W = wk(d0) * wk(d1);
-          m0 += W;
-          m1 += W * (a0 + (R)u);
-          m2 += W * r1;
-          k += W * v[u];
-        }
-      }
+    if (J2F && g.obj == 1) {
+      double kd, ud, vd;
+      map2d_sums<R, double>(g, kref, m, bx, by, kd, ud, vd);
+      k = (R)kd;
+      usx = (R)ud;
+      usy = (R)vd;
+    } else {
+      map2d_sums<R, R>(g, kref, m, bx, by, k, usx, usy);
     }
   }
-  const R om = (R)m.om;
-  const R usx = om * (-s * m1 - c * m2) + (R)m.ug[0] * m0;
-  const R usy = om * (c * m1 - s * m2) + (R)m.ug[1] * m0;
   if (full_grid) {
     if (!inside || wall) return;
     const long long n = nidx(g, x, y, 0);
@@ -1613,11 +1670,11 @@ __device__ __forceinline__ void map2d_row(const Geo& g, const R* kref, Mot m, Bo
   }
 }
 
-template <class R>
+template <class R, bool J2F>
 __global__ __launch_bounds__(MAP2_TX * MAP2_TY) void k_map2d(Geo g, const R* kref, Mot m,
                                                              Box box, const StepInfo* si, R* bk,
                                                              R* bu, int full_grid) {
-  map2d_row<R>(g, kref, m, box, si, bk, bu, full_grid, blockIdx.x, blockIdx.y);
+  map2d_row<R, J2F>(g, kref, m, box, si, bk, bu, full_grid, blockIdx.x, blockIdx.y);
 }
 
 // 3D transfer.  The z factor of the kernel is axis aligned and its 4 weights
@@ -2099,9 +2156,11 @@ __global__ __launch_bounds__(MAPADJ_THREADS, sizeof(R) == 4 ? 5 : 2) void k_mapa
 // fields are staged in LDS with loads along x and every thread reads its
 // taps from there.  Each point's sums weighted by W, dW/dx and dW/dy give
 // dJ/dkappa_ref and its motion terms; the block writes one fixed-order set
-// of motion partials.
+// of motion partials.  Weights and tap sums in arithmetic type C: FP64 where
+// the transfer itself takes FP64 sums (single-precision states under J2), so
+// the transpose stays the transpose of the transfer that ran.
 constexpr int MA2_P = 16, MA2_W = 28;
-template <class R>
+template <class R, class C>
 __device__ __forceinline__ void mapadj_block(const Geo& g, const R* kref, Mot m, Box box,
                                              const StepInfo* si, const R* bkbar, const R* bubar,
                                              double* kref_bar, int overwrite, double* mpart,
@@ -2154,30 +2213,30 @@ __device__ __forceinline__ void mapadj_block(const Geo& g, const R* kref, Mot m,
     win[2][n] = v2;
   }
   __syncthreads();
-  R wx[4], dx[4], wy[4], dy[4];
+  C wx[4], dx[4], wy[4], dy[4];
   const int lx = (int)floor(X0) - 1 - wx0, ly = (int)floor(X1) - 1 - wy0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const R rx = (R)((double)(lx + wx0 + q) - X0), ry = (R)((double)(ly + wy0 + q) - X1);
+    const C rx = (C)((double)(lx + wx0 + q) - X0), ry = (C)((double)(ly + wy0 + q) - X1);
     // points past the design grid weight their taps by 0
-    wx[q] = active ? wk(rx) : R(0);
-    dx[q] = active ? wkd(rx) : R(0);
+    wx[q] = active ? wk(rx) : C(0);
+    dx[q] = active ? wkd(rx) : C(0);
     wy[q] = wk(ry);
     dy[q] = wkd(ry);
   }
   // (lx, ly) lie in [0, MA2_W - 4] by the choice of the window; clamped only
   // so that no thread can address outside it
   const int c0 = min(max(lx, 0), MA2_W - 4) + MA2_W * min(max(ly, 0), MA2_W - 4);
-  R P[9];  // (W, dW/dx, dW/dy) x (k-bar, u-bar_x, u-bar_y)
+  C P[9];  // (W, dW/dx, dW/dy) x (k-bar, u-bar_x, u-bar_y)
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    R S = R(0), Dx = R(0), Dy = R(0);
+    C S = C(0), Dx = C(0), Dy = C(0);
 #pragma unroll
     for (int cy = 0; cy < 4; ++cy) {
-      R s = R(0), d = R(0);
+      C s = C(0), d = C(0);
 #pragma unroll
       for (int cx = 0; cx < 4; ++cx) {
-        const R v = win[q][c0 + cy * MA2_W + cx];
+        const C v = (C)win[q][c0 + cy * MA2_W + cx];
         s += wx[cx] * v;
         d += dx[cx] * v;
       }
@@ -2212,7 +2271,20 @@ __device__ __forceinline__ void mapadj_block(const Geo& g, const R* kref, Mot m,
     for (int q = 0; q < 8; ++q) mpart[(long long)bid * 8 + q] = tot[q];
 }
 
-template <class R>
+// J2F: kernels built for single-precision states under J2 (see map2d_row);
+// plans with that objective take the FP64 form.
+template <class R, bool J2F>
+__device__ __forceinline__ void mapadj_any(const Geo& g, const R* kref, Mot m, Box box,
+                                           const StepInfo* si, const R* bkbar, const R* bubar,
+                                           double* kref_bar, int overwrite, double* mpart,
+                                           int bid) {
+  if (J2F && g.obj == 1)
+    mapadj_block<R, double>(g, kref, m, box, si, bkbar, bubar, kref_bar, overwrite, mpart, bid);
+  else
+    mapadj_block<R, R>(g, kref, m, box, si, bkbar, bubar, kref_bar, overwrite, mpart, bid);
+}
+
+template <class R, bool J2F>
 __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj(Geo g, const R* kref, Mot m, Box box,
                                                            const StepInfo* si, const R* bkbar,
                                                            const R* bubar, double* kref_bar,
@@ -2220,8 +2292,8 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj(Geo g, const R* kref,
                                                            StepBatch sb) {
   const int st = blockIdx.y;  // step within a batch of consecutive steps
   if (si) si += st;
-  mapadj_block<R>(g, kref, m, box, si, bkbar + st * sb.body, bubar + st * sb.body,
-                  kref_bar + st * sb.kref, overwrite, mpart + st * sb.mpart, blockIdx.x);
+  mapadj_any<R, J2F>(g, kref, m, box, si, bkbar + st * sb.body, bubar + st * sb.body,
+                     kref_bar + st * sb.kref, overwrite, mpart + st * sb.mpart, blockIdx.x);
 }
 
 // ------------------------------------------------- objective J2 (Sec. 2.6)
@@ -2257,8 +2329,9 @@ __device__ __forceinline__ void j2_coef(const Geo& g, const StepInfo& S, double&
   b = g.j2w[1] * S.om * g.j2s[2];
 }
 // u_ref at X and (DER) its derivatives dur[a][q] = d u_ref_q / d X_a.  The
-// kernel factors are taken once per axis, in the state precision (the offsets
-// are small numbers, exact enough in it); the sums are FP64.
+// kernel factors are taken once per axis and, like the sums, in FP64 for
+// either state precision: inside the body u_ref - U is a small difference of
+// nearly equal velocities, and single-precision factors would show in it.
 template <class R, bool DER>
 __device__ __forceinline__ void j2_gather(const Geo& g, const R* st, double X0, double X1,
                                           double ur[2], double dur[2][2]) {
@@ -2271,11 +2344,11 @@ __device__ __forceinline__ void j2_gather(const Geo& g, const R* st, double X0, 
   for (int q = 0; q < 4; ++q) {
     xs[q] = lx + q;
     ys[q] = ly + q;
-    const R rx = (R)((double)xs[q] - X0), ry = (R)((double)ys[q] - X1);
-    wx[q] = (double)wk(rx);
-    wy[q] = (double)wk(ry);
-    dx[q] = DER ? (double)wkd(rx) : 0.0;
-    dy[q] = DER ? (double)wkd(ry) : 0.0;
+    const double rx = (double)xs[q] - X0, ry = (double)ys[q] - X1;
+    wx[q] = wk(rx);
+    wy[q] = wk(ry);
+    dx[q] = DER ? wkd(rx) : 0.0;
+    dy[q] = DER ? wkd(ry) : 0.0;
     okx[q] = wrap_axis(g, 0, xs[q]) && !on_wall(g, 0, xs[q]);
     oky[q] = wrap_axis(g, 1, ys[q]) && !on_wall(g, 1, ys[q]);
   }
@@ -2335,8 +2408,8 @@ __global__ __launch_bounds__(J2_THREADS) void k_j2_fwd(Geo g, const R* kref, con
 // depends on the other.  Blocks [0, nstep) step, the rest map.
 // With J2 (jst non-null) a third range of blocks adds the J2 step sums of
 // the step's input state (after step jsi), which the step only reads.
-template <class R>
-__global__ __launch_bounds__(STEP_THREADS, sizeof(R) == 4 ? 8 : 4) void k_fwd2d_map(Geo g, FwdArgs a, int nstep,
+template <class R, bool J2F>
+__global__ __launch_bounds__(STEP_THREADS, sizeof(R) == 4 && !J2F ? 8 : 4) void k_fwd2d_map(Geo g, FwdArgs a, int nstep,
                                                            const R* kref, Box box,
                                                            const StepInfo* msi, R* bk, R* bu,
                                                            int nbx, int nmap,
@@ -2351,7 +2424,7 @@ __global__ __launch_bounds__(STEP_THREADS, sizeof(R) == 4 ? 8 : 4) void k_fwd2d_
   }
   if (b < nstep + nmap) {
     Mot m{};  // taken from msi
-    map2d_row<R>(g, kref, m, box, msi, bk, bu, 0, (b - nstep) % nbx, (b - nstep) / nbx);
+    map2d_row<R, J2F>(g, kref, m, box, msi, bk, bu, 0, (b - nstep) % nbx, (b - nstep) / nbx);
     return;
   }
   j2_fwd_block<R>(g, kref, jsi, jst, jacc, b - nstep - nmap);
@@ -2360,7 +2433,7 @@ __global__ __launch_bounds__(STEP_THREADS, sizeof(R) == 4 ? 8 : 4) void k_fwd2d_
 // The transfer of step n and the J2 step sums of state n - 1 in one launch
 // (both are short, latency-bound kernels with no dependence on each other):
 // blocks [0, nmap) map, the rest sum.
-template <class R>
+template <class R, bool J2F>
 __global__ __launch_bounds__(J2_THREADS) void k_map2d_j2(Geo g, const R* kref, Box box,
                                                          const StepInfo* si, R* bk, R* bu, int nbx,
                                                          int nmap, const StepInfo* jsi,
@@ -2369,7 +2442,7 @@ __global__ __launch_bounds__(J2_THREADS) void k_map2d_j2(Geo g, const R* kref, B
   const int b = blockIdx.x;
   if (b < nmap) {
     Mot m{};  // taken from si
-    map2d_row<R>(g, kref, m, box, si, bk, bu, 0, b % nbx, b / nbx);
+    map2d_row<R, J2F>(g, kref, m, box, si, bk, bu, 0, b % nbx, b / nbx);
     return;
   }
   j2_fwd_block<R>(g, kref, jsi, jst, jacc, b - nmap);
@@ -3037,7 +3110,7 @@ __global__ __launch_bounds__(ADJ2D_THREADS, 2) void k_adj2d_batch(Batch<AdjArgs>
   adj2d_tile<R, ALK>(g, b.a[k], bid);
 }
 
-template <class R>
+template <class R, bool J2F>
 __global__ __launch_bounds__(MAP2_TX * MAP2_TY) void k_map2d_batch(Batch<MapArgs> b) {
   const int k = batch_instance(b.start, b.count, blockIdx.x);
   const int bid = blockIdx.x - b.start[k];
@@ -3045,11 +3118,11 @@ __global__ __launch_bounds__(MAP2_TX * MAP2_TY) void k_map2d_batch(Batch<MapArgs
   if (bid >= a.bxn * ((a.box.ext[1] + MAP2_TY - 1) / MAP2_TY)) return;
   Mot m;
   memset(&m, 0, sizeof m);
-  map2d_row<R>(*b.geo[k], (const R*)a.kref, m, a.box, a.si, (R*)a.bk, (R*)a.bu, 0, bid % a.bxn,
+  map2d_row<R, J2F>(*b.geo[k], (const R*)a.kref, m, a.box, a.si, (R*)a.bk, (R*)a.bu, 0, bid % a.bxn,
                bid / a.bxn);
 }
 
-template <class R>
+template <class R, bool J2F>
 __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj_batch(Batch<MapAdjArgs> b) {
   const int k = batch_instance(b.start, b.count, blockIdx.x);
   const int bid = blockIdx.x - b.start[k];
@@ -3059,9 +3132,9 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj_batch(Batch<MapAdjArg
   Mot m;
   memset(&m, 0, sizeof m);
   const int st = blockIdx.y;  // step within a batch of consecutive steps
-  mapadj_block<R>(g, (const R*)a.kref, m, a.box, a.si ? a.si + st : nullptr,
-                  (const R*)a.bkbar + st * a.sb.body, (const R*)a.bubar + st * a.sb.body,
-                  a.kref_bar + st * a.sb.kref, a.overwrite, a.mpart + st * a.sb.mpart, bid);
+  mapadj_any<R, J2F>(g, (const R*)a.kref, m, a.box, a.si ? a.si + st : nullptr,
+                     (const R*)a.bkbar + st * a.sb.body, (const R*)a.bubar + st * a.sb.body,
+                     a.kref_bar + st * a.sb.kref, a.overwrite, a.mpart + st * a.sb.mpart, bid);
 }
 
 LaunchEvents& launch_events() {
@@ -3367,12 +3440,15 @@ hipError_t launch_map(const Geo& g, int precision, const void* kref, void* kzbuf
     memset(&m, 0, sizeof m);
   if (g.d == 2) {
     dim3 grid((box.ext[0] + MAP2_TX - 1) / MAP2_TX, (box.ext[1] + MAP2_TY - 1) / MAP2_TY);
-    if (precision == 0)
-      LKS_LAUNCH(k_map2d<float>, grid, dim3(MAP2_TX * MAP2_TY), 0, s, g, (const float*)kref, m, box, si,
-                         (float*)bk, (float*)bu, full_grid);
-    else
-      LKS_LAUNCH(k_map2d<double>, grid, dim3(MAP2_TX * MAP2_TY), 0, s, g, (const double*)kref, m, box, si,
-                         (double*)bk, (double*)bu, full_grid);
+    if (precision == 0) {
+      auto k = g.obj == 1 ? &k_map2d<float, true> : &k_map2d<float, false>;
+      LKS_LAUNCH(k, grid, dim3(MAP2_TX * MAP2_TY), 0, s, g, (const float*)kref, m, box, si,
+                 (float*)bk, (float*)bu, full_grid);
+    } else {
+      auto k = &k_map2d<double, false>;
+      LKS_LAUNCH(k, grid, dim3(MAP2_TX * MAP2_TY), 0, s, g, (const double*)kref, m, box, si,
+                 (double*)bk, (double*)bu, full_grid);
+    }
   } else {
     const int lz = kz_levels(g);
     dim3 grid((unsigned)((box.ext[0] * box.ext[1] + 7) / 8), (unsigned)nsteps);
@@ -3450,14 +3526,15 @@ hipError_t launch_map_adjoint(const Geo& g, int precision, const void* kref,
     }
     return hipGetLastError();
   }
-  if (precision == 0)
-    LKS_LAUNCH(k_mapadj<float>, grid, dim3(MAPADJ_THREADS), 0, s, g, (const float*)kref,
-                       m, box, si, (const float*)bkbar, (const float*)bubar, kref_bar, overwrite,
-                       mpart, sb);
-  else
-    LKS_LAUNCH(k_mapadj<double>, grid, dim3(MAPADJ_THREADS), 0, s, g,
-                       (const double*)kref, m, box, si, (const double*)bkbar, (const double*)bubar,
-                       kref_bar, overwrite, mpart, sb);
+  if (precision == 0) {
+    auto k = g.obj == 1 ? &k_mapadj<float, true> : &k_mapadj<float, false>;
+    LKS_LAUNCH(k, grid, dim3(MAPADJ_THREADS), 0, s, g, (const float*)kref, m, box, si,
+               (const float*)bkbar, (const float*)bubar, kref_bar, overwrite, mpart, sb);
+  } else {
+    auto k = &k_mapadj<double, false>;
+    LKS_LAUNCH(k, grid, dim3(MAPADJ_THREADS), 0, s, g, (const double*)kref, m, box, si,
+               (const double*)bkbar, (const double*)bubar, kref_bar, overwrite, mpart, sb);
+  }
   return hipGetLastError();
 }
 
@@ -3500,14 +3577,16 @@ hipError_t launch_forward_step_map(const Geo& g, int precision, const FwdArgs& a
   const int nbx = msi ? (box.ext[0] + MAP2_TX - 1) / MAP2_TX : 0;
   const int nmap = msi ? nbx * ((box.ext[1] + MAP2_TY - 1) / MAP2_TY) : 0;
   const dim3 grid(nstep + nmap + (jst ? j2_blocks(g) : 0));
-  if (precision == 0)
-    LKS_LAUNCH(k_fwd2d_map<float>, grid, dim3(STEP_THREADS), 0, s, g, a, nstep,
-               (const float*)kref, box, msi, (float*)bk, (float*)bu, nbx, nmap, jsi,
-               (const float*)jst, jacc);
-  else
-    LKS_LAUNCH(k_fwd2d_map<double>, grid, dim3(STEP_THREADS), 0, s, g, a, nstep,
+  if (precision == 0) {
+    auto k = g.obj == 1 ? &k_fwd2d_map<float, true> : &k_fwd2d_map<float, false>;
+    LKS_LAUNCH(k, grid, dim3(STEP_THREADS), 0, s, g, a, nstep, (const float*)kref, box, msi,
+               (float*)bk, (float*)bu, nbx, nmap, jsi, (const float*)jst, jacc);
+  } else {
+    auto kd = &k_fwd2d_map<double, false>;
+    LKS_LAUNCH(kd, grid, dim3(STEP_THREADS), 0, s, g, a, nstep,
                (const double*)kref, box, msi, (double*)bk, (double*)bu, nbx, nmap, jsi,
                (const double*)jst, jacc);
+  }
   return hipGetLastError();
 }
 
@@ -3516,12 +3595,15 @@ hipError_t launch_map_j2(const Geo& g, int precision, const void* kref, const St
                          double* jacc, hipStream_t s) {
   const int nbx = (box.ext[0] + MAP2_TX - 1) / MAP2_TX, nby = (box.ext[1] + MAP2_TY - 1) / MAP2_TY;
   const dim3 grid(nbx * nby + j2_blocks(g));
-  if (precision == 0)
-    LKS_LAUNCH(k_map2d_j2<float>, grid, dim3(J2_THREADS), 0, s, g, (const float*)kref, box, si,
-               (float*)bk, (float*)bu, nbx, nbx * nby, jsi, (const float*)jst, jacc);
-  else
-    LKS_LAUNCH(k_map2d_j2<double>, grid, dim3(J2_THREADS), 0, s, g, (const double*)kref, box, si,
+  if (precision == 0) {
+    auto k = g.obj == 1 ? &k_map2d_j2<float, true> : &k_map2d_j2<float, false>;
+    LKS_LAUNCH(k, grid, dim3(J2_THREADS), 0, s, g, (const float*)kref, box, si, (float*)bk,
+               (float*)bu, nbx, nbx * nby, jsi, (const float*)jst, jacc);
+  } else {
+    auto kd = &k_map2d_j2<double, false>;
+    LKS_LAUNCH(kd, grid, dim3(J2_THREADS), 0, s, g, (const double*)kref, box, si,
                (double*)bk, (double*)bu, nbx, nbx * nby, jsi, (const double*)jst, jacc);
+  }
   return hipGetLastError();
 }
 
@@ -3781,22 +3863,28 @@ hipError_t launch_adjoint_step_batch(int precision, const Batch<AdjArgs>& b, hip
   return hipGetLastError();
 }
 
-hipError_t launch_map_batch(int precision, const Batch<MapArgs>& b, hipStream_t s) {
+hipError_t launch_map_batch(int precision, const Batch<MapArgs>& b, hipStream_t s, bool j2) {
   dim3 grid(b.start[b.count]);
-  if (precision == 0)
-    LKS_LAUNCH(k_map2d_batch<float>, grid, dim3(MAP2_TX * MAP2_TY), 0, s, b);
-  else
-    LKS_LAUNCH(k_map2d_batch<double>, grid, dim3(MAP2_TX * MAP2_TY), 0, s, b);
+  if (precision == 0) {
+    auto k = j2 ? &k_map2d_batch<float, true> : &k_map2d_batch<float, false>;
+    LKS_LAUNCH(k, grid, dim3(MAP2_TX * MAP2_TY), 0, s, b);
+  } else {
+    auto k = &k_map2d_batch<double, false>;
+    LKS_LAUNCH(k, grid, dim3(MAP2_TX * MAP2_TY), 0, s, b);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_map_adjoint_batch(int precision, const Batch<MapAdjArgs>& b, hipStream_t s,
-                                    int nsteps) {
+                                    int nsteps, bool j2) {
   dim3 grid(b.start[b.count], nsteps);
-  if (precision == 0)
-    LKS_LAUNCH(k_mapadj_batch<float>, grid, dim3(MAPADJ_THREADS), 0, s, b);
-  else
-    LKS_LAUNCH(k_mapadj_batch<double>, grid, dim3(MAPADJ_THREADS), 0, s, b);
+  if (precision == 0) {
+    auto k = j2 ? &k_mapadj_batch<float, true> : &k_mapadj_batch<float, false>;
+    LKS_LAUNCH(k, grid, dim3(MAPADJ_THREADS), 0, s, b);
+  } else {
+    auto k = &k_mapadj_batch<double, false>;
+    LKS_LAUNCH(k, grid, dim3(MAPADJ_THREADS), 0, s, b);
+  }
   return hipGetLastError();
 }
 

@@ -125,8 +125,10 @@ def test_oar_j2_fp32_whole_horizon():
     for key in ("dgamma", "dchi", "dpsi"):
         errs[key] = l2err(g32[key], g64[key])
     print(f"oar J2 FP32 vs FP64 over 4000 steps: {errs}", flush=True)
-    assert errs["J2"] <= 2e-3
-    assert errs["F_L"] <= 1e-3 and errs["F_D"] <= 2e-3
+    # J2 to the objective bar of 1e-5; its parts F_L (a near-cancelling sum
+    # here) and F_D to their measured levels with margin
+    assert errs["J2"] <= 1e-5
+    assert errs["F_L"] <= 2e-4 and errs["F_D"] <= 2e-5
     for key in ("dgamma", "dchi", "dpsi"):
         assert errs[key] <= 1e-3, key
 
