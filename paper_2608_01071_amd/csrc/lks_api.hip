@@ -1199,8 +1199,6 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
     qb.start[k + 1] = qb.start[k] + round8(mapadj_blocks(P->g));
   }
   const bool full = plans[0]->full_btape;
-  bool any_j2 = false;
-  for (int k = 0; k < count; ++k) any_j2 = any_j2 || plans[k]->g.obj == 1;
   auto map_all = [&](int n, int sg_body) -> lks_status {
     // sg_body < 0: the forward march's body buffer; else the tape slot of step n
     for (int k = 0; k < count; ++k) {
@@ -1212,7 +1210,7 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
     }
     {
       Scope sc("map", s, true);
-      HIPCHK(launch_map_batch(prec, mb, s, any_j2));
+      HIPCHK(launch_map_batch(prec, mb, s));
     }
     return LKS_OK;
   };
@@ -1294,7 +1292,7 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
         qb.a[k] = m;
       }
       Scope sc("map_adj", s, true);
-      HIPCHK(launch_map_adjoint_batch(prec, qb, s, cnt, any_j2));
+      HIPCHK(launch_map_adjoint_batch(prec, qb, s, cnt));
       for (int k = 0; k < count; ++k) {
         lks_plan* P = plans[k];
         HIPCHK(launch_kref_accum(P->g.Mtot, cnt, (const double*)wsp(ws[k], P->o_kpart),

@@ -418,11 +418,9 @@ int adj2d_blocks(const Geo& g);  // tiles of the 2D adjoint step  // tiles of th
 int map_blocks_2d(const Box& bmax, int* bxn);
 hipError_t launch_forward_step_batch(int precision, const Batch<FwdArgs>& b, hipStream_t s);
 hipError_t launch_adjoint_step_batch(int precision, const Batch<AdjArgs>& b, hipStream_t s);
-// j2: some instance has the objective J2 (its single-precision transfers take
-// their sums in FP64)
-hipError_t launch_map_batch(int precision, const Batch<MapArgs>& b, hipStream_t s, bool j2);
+hipError_t launch_map_batch(int precision, const Batch<MapArgs>& b, hipStream_t s);
 hipError_t launch_map_adjoint_batch(int precision, const Batch<MapAdjArgs>& b, hipStream_t s,
-                                    int nsteps, bool j2);
+                                    int nsteps = 1);
 __host__ __device__ void body_box(const Geo& g, const double* m8, int* out);
 // StepInfo of one motion row (box included).
 __host__ __device__ void step_info(const Geo& g, const double* mrow, StepInfo& si);

@@ -36,6 +36,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <type_traits>
 
 #include "lks_internal.h"
 
@@ -1626,8 +1627,8 @@ __device__ __forceinline__ void map2d_sums(const Geo& g, const R* kref, const Mo
 }
 
 // The transfer of one box node; a block is a MAP2_TX x MAP2_TY patch of the
-// box.  J2F (kernels built for single-precision states under the objective J2):
-// plans with that objective take the sums in FP64 and round the outputs once.
+// box.  J2F (kernels launched for single-precision plans with the objective
+// J2 only): the sums are taken in FP64 and the outputs rounded once.
 // J2's force density kappa_ref (u_ref - U) is a small difference of the fluid
 // velocity, which the Brinkman term drives to the transferred rigid velocity,
 // and U, so single-precision weights and sums would show in it at the scale of
@@ -1646,7 +1647,7 @@ __device__ __forceinline__ void map2d_row(const Geo& g, const R* kref, Mot m, Bo
   const bool wall = inside && is_wall(g, x, y, 0);
   R k = R(0), usx = R(0), usy = R(0);
   if (inside && !wall) {
-    if (J2F && g.obj == 1) {
+    if (J2F) {
       double kd, ud, vd;
       map2d_sums<R, double>(g, kref, m, bx, by, kd, ud, vd);
       k = (R)kd;
@@ -2271,19 +2272,8 @@ __device__ __forceinline__ void mapadj_block(const Geo& g, const R* kref, Mot m,
     for (int q = 0; q < 8; ++q) mpart[(long long)bid * 8 + q] = tot[q];
 }
 
-// J2F: kernels built for single-precision states under J2 (see map2d_row);
-// plans with that objective take the FP64 form.
-template <class R, bool J2F>
-__device__ __forceinline__ void mapadj_any(const Geo& g, const R* kref, Mot m, Box box,
-                                           const StepInfo* si, const R* bkbar, const R* bubar,
-                                           double* kref_bar, int overwrite, double* mpart,
-                                           int bid) {
-  if (J2F && g.obj == 1)
-    mapadj_block<R, double>(g, kref, m, box, si, bkbar, bubar, kref_bar, overwrite, mpart, bid);
-  else
-    mapadj_block<R, R>(g, kref, m, box, si, bkbar, bubar, kref_bar, overwrite, mpart, bid);
-}
-
+// J2F: built for single-precision states under J2 (launched for those plans
+// only; see map2d_row): weights and tap sums in FP64.
 template <class R, bool J2F>
 __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj(Geo g, const R* kref, Mot m, Box box,
                                                            const StepInfo* si, const R* bkbar,
@@ -2292,7 +2282,8 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj(Geo g, const R* kref,
                                                            StepBatch sb) {
   const int st = blockIdx.y;  // step within a batch of consecutive steps
   if (si) si += st;
-  mapadj_any<R, J2F>(g, kref, m, box, si, bkbar + st * sb.body, bubar + st * sb.body,
+  using C = typename std::conditional<J2F, double, R>::type;
+  mapadj_block<R, C>(g, kref, m, box, si, bkbar + st * sb.body, bubar + st * sb.body,
                      kref_bar + st * sb.kref, overwrite, mpart + st * sb.mpart, blockIdx.x);
 }
 
@@ -3110,7 +3101,9 @@ __global__ __launch_bounds__(ADJ2D_THREADS, 2) void k_adj2d_batch(Batch<AdjArgs>
   adj2d_tile<R, ALK>(g, b.a[k], bid);
 }
 
-template <class R, bool J2F>
+// J2 plans never join a batched launch (lks_batch_run runs them as graph
+// branches), so the batched transfers take the J1 form.
+template <class R>
 __global__ __launch_bounds__(MAP2_TX * MAP2_TY) void k_map2d_batch(Batch<MapArgs> b) {
   const int k = batch_instance(b.start, b.count, blockIdx.x);
   const int bid = blockIdx.x - b.start[k];
@@ -3118,11 +3111,11 @@ __global__ __launch_bounds__(MAP2_TX * MAP2_TY) void k_map2d_batch(Batch<MapArgs
   if (bid >= a.bxn * ((a.box.ext[1] + MAP2_TY - 1) / MAP2_TY)) return;
   Mot m;
   memset(&m, 0, sizeof m);
-  map2d_row<R, J2F>(*b.geo[k], (const R*)a.kref, m, a.box, a.si, (R*)a.bk, (R*)a.bu, 0, bid % a.bxn,
+  map2d_row<R>(*b.geo[k], (const R*)a.kref, m, a.box, a.si, (R*)a.bk, (R*)a.bu, 0, bid % a.bxn,
                bid / a.bxn);
 }
 
-template <class R, bool J2F>
+template <class R>
 __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj_batch(Batch<MapAdjArgs> b) {
   const int k = batch_instance(b.start, b.count, blockIdx.x);
   const int bid = blockIdx.x - b.start[k];
@@ -3132,7 +3125,7 @@ __global__ __launch_bounds__(MAPADJ_THREADS) void k_mapadj_batch(Batch<MapAdjArg
   Mot m;
   memset(&m, 0, sizeof m);
   const int st = blockIdx.y;  // step within a batch of consecutive steps
-  mapadj_any<R, J2F>(g, (const R*)a.kref, m, a.box, a.si ? a.si + st : nullptr,
+  mapadj_block<R, R>(g, (const R*)a.kref, m, a.box, a.si ? a.si + st : nullptr,
                      (const R*)a.bkbar + st * a.sb.body, (const R*)a.bubar + st * a.sb.body,
                      a.kref_bar + st * a.sb.kref, a.overwrite, a.mpart + st * a.sb.mpart, bid);
 }
@@ -3863,28 +3856,22 @@ hipError_t launch_adjoint_step_batch(int precision, const Batch<AdjArgs>& b, hip
   return hipGetLastError();
 }
 
-hipError_t launch_map_batch(int precision, const Batch<MapArgs>& b, hipStream_t s, bool j2) {
+hipError_t launch_map_batch(int precision, const Batch<MapArgs>& b, hipStream_t s) {
   dim3 grid(b.start[b.count]);
-  if (precision == 0) {
-    auto k = j2 ? &k_map2d_batch<float, true> : &k_map2d_batch<float, false>;
-    LKS_LAUNCH(k, grid, dim3(MAP2_TX * MAP2_TY), 0, s, b);
-  } else {
-    auto k = &k_map2d_batch<double, false>;
-    LKS_LAUNCH(k, grid, dim3(MAP2_TX * MAP2_TY), 0, s, b);
-  }
+  if (precision == 0)
+    LKS_LAUNCH(k_map2d_batch<float>, grid, dim3(MAP2_TX * MAP2_TY), 0, s, b);
+  else
+    LKS_LAUNCH(k_map2d_batch<double>, grid, dim3(MAP2_TX * MAP2_TY), 0, s, b);
   return hipGetLastError();
 }
 
 hipError_t launch_map_adjoint_batch(int precision, const Batch<MapAdjArgs>& b, hipStream_t s,
-                                    int nsteps, bool j2) {
+                                    int nsteps) {
   dim3 grid(b.start[b.count], nsteps);
-  if (precision == 0) {
-    auto k = j2 ? &k_mapadj_batch<float, true> : &k_mapadj_batch<float, false>;
-    LKS_LAUNCH(k, grid, dim3(MAPADJ_THREADS), 0, s, b);
-  } else {
-    auto k = &k_mapadj_batch<double, false>;
-    LKS_LAUNCH(k, grid, dim3(MAPADJ_THREADS), 0, s, b);
-  }
+  if (precision == 0)
+    LKS_LAUNCH(k_mapadj_batch<float>, grid, dim3(MAPADJ_THREADS), 0, s, b);
+  else
+    LKS_LAUNCH(k_mapadj_batch<double>, grid, dim3(MAPADJ_THREADS), 0, s, b);
   return hipGetLastError();
 }
 
