@@ -1576,13 +1576,13 @@ __device__ __forceinline__ void apply_step(Box& b, Mot& m, const StepInfo* si) {
 
 // Cosine-kernel sums over the design points whose rotated position lies
 // within the kernel support of analysis position (bx, by): the W-weighted
-// kappa_ref, and from sum W, sum W r1, sum W r2 the transferred rigid velocity,
-// in arithmetic type C (kappa_ref read in the state type R; the fused
-// multiply-adds are named so every kernel that inlines this rounds alike).  The offset of
-// design point e from the analysis node is R (q - e), q being the node in
-// design coordinates, so the candidate loop works on q - e relative to the
-// window corner (small numbers, exact in the working precision) instead of on
-// absolute positions.
+// kappa_ref, and from sum W, sum W r1, sum W r2 the transferred rigid
+// velocity, in arithmetic type C (kappa_ref read in the state type R; the
+// fused multiply-adds are named so every kernel that inlines this rounds
+// alike).  The offset of design point e from the analysis node is R (q - e),
+// q being the node in design coordinates, so the candidate loop works on
+// q - e relative to the window corner (small numbers, exact in the working
+// precision) instead of on absolute positions.
 template <class R, class C>
 __device__ __forceinline__ void map2d_sums(const Geo& g, const R* kref, const Mot& m, int bx,
                                            int by, C& k, C& usx, C& usy) {
