@@ -102,7 +102,12 @@ typedef struct lks_problem {
                               Eq. objective2 (2D only), the propulsive force F_L,
                               drag work F_D and torque work T of the force density
                               kappa_ref (u_ref - u_S_ref) on the design points,
-                              J2 = F_L + w_d F_D + w_t T */
+                              J2 = F_L + w_d F_D + w_t T.  Inside the body this
+                              density is a small difference of nearly equal
+                              velocities, so with an FP32 state the 2D transfer,
+                              its transpose and the pull-back u_ref take their
+                              weights and sums in FP64 (J2 then agrees with the
+                              FP64 state to about 2e-6 on the oar workload) */
   double w_d, w_t;         /* J2 weights of F_D and T */
   double l_m;              /* J2 moment arm in T's normalisation 2 pi l_m (> 0);
                               F_D is normalised by xg_max[1] - xg_min[1] (> 0) */
