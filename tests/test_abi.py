@@ -156,6 +156,33 @@ def test_bench_refuses_more_than_one_gpu():
     assert "one GPU" in r.stderr
 
 
+
+def test_bench_traffic_is_read_only_for_its_kernel_source(tmp_path, monkeypatch):
+    """The roofline's measured HBM traffic comes from the committed counter
+    summary only while the digest that summary names is the kernel source's;
+    after any change to the source (or without a summary) it is None, and the
+    bench line reports it as null."""
+    import hashlib
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    src = tmp_path / "kernels.hip"
+    src.write_bytes(b"kernel source, first form")
+    digest = hashlib.sha256(b"kernel source, first form").hexdigest()
+    summary = tmp_path / "traffic.txt"
+    summary.write_text("# counter summary\n"
+                       f"kernel_source_sha256 {digest}\n"
+                       "traffic k_fwd3d<float> 123\n"
+                       "traffic k_adj3d<float> 456\n")
+    monkeypatch.setattr(bench, "KERNEL_SOURCE", str(src))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(summary))
+    assert bench.measured_traffic("fwd_step") == 123.0
+    assert bench.measured_traffic("adj_step") == 456.0
+    src.write_bytes(b"kernel source, second form")
+    assert bench.measured_traffic("fwd_step") is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "absent.txt"))
+    assert bench.measured_traffic("fwd_step") is None
+
 def test_noalloc_entry_point_rejects_oversized_design_grid(L):
     """The allocation-free chain rule refuses, on the host and before any
     device call, a plan with more inner design points than its fixed
