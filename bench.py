@@ -190,9 +190,9 @@ def oar_j2(nt: int = 4000):
             out["us_per_step"] = {k: round(v[0] * 1e3 / nt, 2) for k, v in prof.items()}
         del plan
         torch.cuda.empty_cache()
-    # FP32 state against the FP64 plain form over the whole horizon: J2 is a
-    # difference of forces about a thousand times its size, so the FP32
-    # rounding shows at the forces' scale
+    # FP32 state against the FP64 plain form over the whole horizon (J2 is a
+    # difference of forces about a thousand times its size; the library's
+    # single-precision J2 plans take the 2D transfer's sums in FP64 for it)
     import numpy as np
     plan = lks.Plan(p.replace(precision=1))
     J64, g64, _, _ = run_pass(plan, g, c, s, seed)
