@@ -1199,7 +1199,7 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
     qb.start[k + 1] = qb.start[k] + round8(mapadj_blocks(P->g));
   }
   const bool full = plans[0]->full_btape;
-  auto map_all = [&](int n, int sg_body) -> lks_status {
+  auto set_map = [&](int n, int sg_body) {
     // sg_body < 0: the forward march's body buffer; else the tape slot of step n
     for (int k = 0; k < count; ++k) {
       lks_plan* P = plans[k];
@@ -1208,6 +1208,9 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
       mb.a[k].bk = body;
       mb.a[k].bu = (char*)body + P->bmax.vol * P->es;
     }
+  };
+  auto map_all = [&](int n, int sg_body) -> lks_status {
+    set_map(n, sg_body);
     {
       Scope sc("map", s, true);
       HIPCHK(launch_map_batch(prec, mb, s));
@@ -1222,8 +1225,13 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
     HIPCHK(launch_zero(wsp(ws[k], P->o_opart), (size_t)P->nblk_step * 2 * sizeof(double), s));
     in[k] = ck_slot(P, ws[k], 0);
   }
+  // with a body slot per step, step n and the map of step n + 1 share a
+  // launch (they touch different slots), as in a single plan's march
+  if (full)
+    if (lks_status e = map_all(1, -1)) return e;
   for (int n = 1; n <= nt; ++n) {
-    if (lks_status e = map_all(n, -1)) return e;
+    if (!full)
+      if (lks_status e = map_all(n, -1)) return e;
     for (int k = 0; k < count; ++k) {
       lks_plan* P = plans[k];
       void* out = fwd_out(P, ws[k], n);
@@ -1233,7 +1241,12 @@ lks_status batched_march(int count, lks_plan* const* plans, void* const* ws,
     }
     {
       Scope sc("fwd_step", s, true);
-      HIPCHK(launch_forward_step_batch(prec, fb, s));
+      if (full && n < nt) {
+        set_map(n + 1, -1);
+        HIPCHK(launch_forward_step_map_batch(prec, fb, mb, s));
+      } else {
+        HIPCHK(launch_forward_step_batch(prec, fb, s));
+      }
     }
   }
   for (int k = 0; k < count; ++k) {

@@ -411,12 +411,16 @@ struct Batch {
   int count;
 };
 static_assert(sizeof(Batch<AdjArgs>) < 4000 && sizeof(Batch<FwdArgs>) < 4000 &&
-                  sizeof(Batch<MapArgs>) < 4000 && sizeof(Batch<MapAdjArgs>) < 4000,
+                  sizeof(Batch<MapArgs>) < 4000 && sizeof(Batch<MapAdjArgs>) < 4000 &&
+                  sizeof(Batch<FwdArgs>) + sizeof(Batch<MapArgs>) < 4000,
               "batched launch arguments must fit the kernel argument buffer");
 int step_blocks_2d(const Geo& g);
 int adj2d_blocks(const Geo& g);  // tiles of the 2D adjoint step  // tiles of the 2D step kernels
 int map_blocks_2d(const Box& bmax, int* bxn);
 hipError_t launch_forward_step_batch(int precision, const Batch<FwdArgs>& b, hipStream_t s);
+// Step n of every instance and the transfer of step n + 1 (mb) in one launch.
+hipError_t launch_forward_step_map_batch(int precision, const Batch<FwdArgs>& fb,
+                                        const Batch<MapArgs>& mb, hipStream_t s);
 hipError_t launch_adjoint_step_batch(int precision, const Batch<AdjArgs>& b, hipStream_t s);
 hipError_t launch_map_batch(int precision, const Batch<MapArgs>& b, hipStream_t s);
 hipError_t launch_map_adjoint_batch(int precision, const Batch<MapAdjArgs>& b, hipStream_t s,

@@ -3096,6 +3096,34 @@ __global__ __launch_bounds__(STEP_THREADS) void k_fwd2d_batch(Batch<FwdArgs> b) 
   fwd2d_tile<R>(g, b.a[k], bid);
 }
 
+// Batched forward march with a body slot per step: step n of every instance
+// and the transfer of step n + 1 in one launch, as k_fwd2d_map does for one
+// plan (both parts are short and latency-bound, neither depends on the
+// other).  Blocks [0, fb.start[count]) step, the rest map.
+template <class R>
+__global__ __launch_bounds__(STEP_THREADS, sizeof(R) == 4 ? 8 : 4) void k_fwd2d_map_batch(
+    Batch<FwdArgs> fb, Batch<MapArgs> mb) {
+  static_assert(MAP2_TX * MAP2_TY == STEP_THREADS, "one block size for both parts");
+  const int nfwd = fb.start[fb.count];
+  if ((int)blockIdx.x < nfwd) {
+    const int k = batch_instance(fb.start, fb.count, blockIdx.x);
+    const int bid = blockIdx.x - fb.start[k];
+    const Geo& g = *fb.geo[k];
+    if (bid >= tiles_x(g) * tiles_y(g)) return;
+    fwd2d_tile<R>(g, fb.a[k], bid);
+    return;
+  }
+  const int b = (int)blockIdx.x - nfwd;
+  const int k = batch_instance(mb.start, mb.count, b);
+  const int bid = b - mb.start[k];
+  const MapArgs& a = mb.a[k];
+  if (bid >= a.bxn * ((a.box.ext[1] + MAP2_TY - 1) / MAP2_TY)) return;
+  Mot m;
+  memset(&m, 0, sizeof m);
+  map2d_row<R>(*mb.geo[k], (const R*)a.kref, m, a.box, a.si, (R*)a.bk, (R*)a.bu, 0, bid % a.bxn,
+               bid / a.bxn);
+}
+
 template <class R, bool ALK>
 __global__ __launch_bounds__(ADJ2D_THREADS, 2) void k_adj2d_batch(Batch<AdjArgs> b) {
   const int k = batch_instance(b.start, b.count, blockIdx.x);
@@ -3846,6 +3874,16 @@ hipError_t launch_forward_step_batch(int precision, const Batch<FwdArgs>& b, hip
     LKS_LAUNCH(k_fwd2d_batch<float>, grid, dim3(STEP_THREADS), 0, s, b);
   else
     LKS_LAUNCH(k_fwd2d_batch<double>, grid, dim3(STEP_THREADS), 0, s, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_step_map_batch(int precision, const Batch<FwdArgs>& fb,
+                                        const Batch<MapArgs>& mb, hipStream_t s) {
+  const dim3 grid(fb.start[fb.count] + mb.start[mb.count]);
+  if (precision == 0)
+    LKS_LAUNCH(k_fwd2d_map_batch<float>, grid, dim3(STEP_THREADS), 0, s, fb, mb);
+  else
+    LKS_LAUNCH(k_fwd2d_map_batch<double>, grid, dim3(STEP_THREADS), 0, s, fb, mb);
   return hipGetLastError();
 }
 
